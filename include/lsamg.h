@@ -1,0 +1,182 @@
+/*
+ * lsamg.h -- C-ABI of an MI355X (gfx950) implementation of the solve phase
+ * of least-squares AMG-DD for sparse SPD systems A = G^T G.
+ *
+ * Method: Southworth, Al Daas, Wimmer, Threlfall, "Algebraic Multigrid with
+ * Overlapping Schwarz Smoothers and Local Spectral Coarse Grids for Least
+ * Squares Problems".  Setup follows Algorithm 1 (sec. 3.2); solve is
+ * preconditioned CG (sec. 4.1, relative residual 1e-8) around a V-cycle with
+ * one restricted additive Schwarz pre-smoothing (eq:ras, sec. 2.2), the
+ * coarse-grid correction eq:cgc with the local-spectral interpolation
+ * eq:mg-p (sec. 3.1.1), and one RAS-transpose post-smoothing (eq:ras-t).
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: LSAMG_OK (0) or a negative LSAMG_E* code; the message of
+ *    the last error on the calling thread is lsamg_last_error().
+ *  - "device" pointers are HIP device (HBM) addresses on the handle's GPU;
+ *    "host" pointers are ordinary CPU memory.  The caller owns every buffer
+ *    it passes in; the library never frees them and keeps no reference to
+ *    them after the call returns.
+ *  - Vectors are FP64, indexed in the caller's numbering of the columns of G.
+ *  - stream is a hipStream_t passed as void* (NULL = default stream).  Every
+ *    entry point that takes a stream enqueues its work on it and returns
+ *    after that work completed.
+ */
+#ifndef LSAMG_H
+#define LSAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LSAMG_OK = 0,
+  LSAMG_EINVAL = -1,     /* bad sizes, pointers or parameters               */
+  LSAMG_EBADINPUT = -2,  /* non-finite entry in G or in a right-hand side   */
+  LSAMG_ENOTSPD = -3,    /* a local or coarsest Cholesky failed (A singular) */
+  LSAMG_ENOMEM = -4,     /* host or device allocation failed                */
+  LSAMG_EHIP = -5,       /* HIP runtime error                               */
+  LSAMG_ENOCONV = -6,    /* maxit reached: x and stats are still written    */
+  LSAMG_ENODEV = -7      /* handle has no device copy, or no GPU present    */
+};
+
+enum { LSAMG_FP64 = 0, LSAMG_MIXED = 1 };
+
+enum {                    /* operators for lsamg_apply_op (finest level)    */
+  LSAMG_OP_A = 0,         /* y = G^T (G x)                 (eq:Ax=b)        */
+  LSAMG_OP_RAS = 1,       /* y = sum_i R_i^T D_i A_i^{-1} R_i x   (eq:ras)  */
+  LSAMG_OP_RAST = 2,      /* y = sum_i R_i^T A_i^{-1} D_i R_i x   (eq:ras-t)*/
+  LSAMG_OP_VCYCLE = 3     /* y = B x, one V-cycle from zero (sec. 3.1.1)    */
+};
+
+/* Sparse G in CSR, host memory, FP64.  m rows, n columns; row r holds the
+ * entries rowptr[r] .. rowptr[r+1]-1.  Explicit zeros and empty rows are
+ * allowed (they are dropped).  Copied by lsamg_setup. */
+typedef struct lsamg_csr {
+  int64_t m, n, nnz;
+  const int64_t* rowptr;
+  const int32_t* col;
+  const double* val;
+} lsamg_csr;
+
+/* Setup parameters (Algorithm 1 inputs, sec. 3.2 and 3.4). */
+typedef struct lsamg_params {
+  int32_t max_levels;    /* L_max                                   (def 10) */
+  int64_t max_coarse;    /* n_coarse: stop once a level is this small (2000) */
+  int32_t ndim;          /* lattice dimension of G's columns (2 or 3)        */
+  int32_t grid[3];       /* lattice extent per axis, x fastest               */
+  int32_t block;         /* lattice block width per axis (4 in 2D, 3 in 3D)  */
+  int32_t omega_max;     /* coarse levels shrink the block until every
+                            aggregate has at most this many unknowns (400)   */
+  int32_t n_eig_fixed;   /* > 0: fixed eigenvector count per aggregate;
+                            0: threshold rule of sec. 3.4                    */
+  double kappa;          /* target condition number (50, sec. 3.4)           */
+  int32_t cmin[8];       /* minimum coarsening ratio per level, the last one
+                            repeats (LS_{a,b,...} of sec. 3.4)               */
+  int32_t ncmin;
+  double tie_rtol;       /* relative width of an eigenvalue cluster (1e-8)   */
+  double tie_atol;       /* absolute width of an eigenvalue cluster (1e-12)  */
+  double pinv_rtol;      /* pseudo-inverse cutoff in eq:gevp-S (1e-12)       */
+  double thresh_margin;  /* strict side of the threshold test (1e-10)        */
+  double stall_ratio;    /* stop coarsening if n_{l+1} > ratio * n_l (0.9)   */
+  int32_t precision;     /* LSAMG_FP64 or LSAMG_MIXED (FP32 V-cycle)         */
+  int32_t device;        /* HIP device ordinal; < 0 builds a host-only handle
+                            (setup data and lsamg_export_setup only)         */
+  int32_t nthreads;      /* host threads for setup (0 = all cores)           */
+} lsamg_params;
+
+/* Per-solve statistics (host memory, one entry per right-hand side). */
+typedef struct lsamg_stats {
+  int32_t iters;         /* PCG iterations (applications of A)               */
+  int32_t converged;     /* 1 if ||r_k|| <= tol ||b||                        */
+  double rel_res;        /* ||r_k|| / ||b||, recurrence residual             */
+  double true_rel_res;   /* ||b - A x|| / ||b||, recomputed in FP64          */
+  double rho;            /* average convergence factor (||r_k||/||r_0||)^(1/k)*/
+  double seconds;        /* wall time of the whole call                      */
+} lsamg_stats;
+
+typedef struct lsamg_level_info {
+  int64_t n;             /* unknowns                                         */
+  int64_t nagg;          /* aggregates (0 on the coarsest level)             */
+  int64_t g_rows;        /* stored rows of G_l (after exact row compression) */
+  int64_t g_nnz;         /* stored entries of G_l                            */
+  int64_t a_nnz;         /* entries of A_l = G_l^T G_l                       */
+  int64_t smoother_entries; /* sum_i |omega_i| |Omega_i|                     */
+  int64_t p_entries;     /* entries of P_l                                   */
+  int32_t block, n_color, n_mult, kmin, kmax;
+  double thresh;
+  int64_t hazards;       /* aggregates with an eigenvalue at the threshold   */
+} lsamg_level_info;
+
+typedef struct lsamg_info {
+  int32_t nlevels;
+  int64_t n0, m0;
+  double setup_seconds;
+  size_t device_bytes;
+  double op_complexity;      /* sum_l nnz(A_l) / nnz(A_0)                    */
+  double smoother_complexity;/* sum_l sum_i |omega_i||Omega_i| / nnz(A_0)    */
+  lsamg_level_info level[16];
+} lsamg_info;
+
+/* Integer setup of one level in the canonical numbering: finest-level
+ * unknowns are G's columns; a coarse unknown is numbered by (aggregate of the
+ * finer level, eigenvector index).  Arrays are owned by the handle and stay
+ * valid until the next lsamg_export_setup call or lsamg_destroy. */
+typedef struct lsamg_setup_view {
+  int64_t n, nagg;
+  const int32_t* agg;    /* [n] aggregate of each unknown                    */
+  const int64_t* optr;   /* [nagg+1]                                         */
+  const int64_t* oidx;   /* Omega_i: omega_i ascending, then Gamma_i ascending */
+  const int32_t* k;      /* [nagg] eigenvectors kept                         */
+  const int32_t* M;      /* finest level: multiplicity of each kept row of G;
+                            NULL on coarser levels                           */
+  const double* mu;      /* local eigenvalues mu = 1/lambda, ascending       */
+  const int64_t* muptr;  /* [nagg+1]                                         */
+  int32_t block, n_color, n_mult;
+  double thresh;
+} lsamg_setup_view;
+
+typedef struct lsamg_handle lsamg_handle;
+
+/* Fill p with the defaults listed above (ndim/grid left zero). */
+void lsamg_params_default(lsamg_params* p);
+
+/* Build the hierarchy of Algorithm 1 for A = G^T G on the host (FP64) and,
+ * if p->device >= 0, upload it to that GPU.  G is host CSR and is copied.
+ * On success *out owns all host and device memory of the hierarchy.
+ * Errors: EINVAL (sizes, lattice, params), EBADINPUT (non-finite G),
+ * ENOTSPD (singular A: a column of G without entries, or a failed local
+ * factorisation), ENOMEM, EHIP. */
+int lsamg_setup(const lsamg_csr* G, const lsamg_params* p, lsamg_handle** out);
+
+/* Solve A x = b for nrhs right-hand sides with PCG (x0 = 0) preconditioned
+ * by one V-cycle per iteration, until ||r_k|| <= tol ||b|| or maxit.
+ * b, x: device, FP64, column-major n x nrhs with leading dimension ld >= n.
+ * Each column is solved independently (its own CG scalars and stop test).
+ * stats: host array of nrhs entries, or NULL.
+ * Errors: EINVAL, ENODEV, EBADINPUT (non-finite b), EHIP, ENOCONV. */
+int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs,
+                int64_t ld, double tol, int32_t maxit, void* stream,
+                lsamg_stats* stats);
+
+/* y = op(x) on the finest level (see LSAMG_OP_*), one vector, in the
+ * precision selected for the V-cycle.  x, y: device, FP64, length n. */
+int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y,
+                   void* stream);
+
+/* Select the V-cycle precision (LSAMG_FP64 or LSAMG_MIXED) for later calls. */
+int lsamg_set_precision(lsamg_handle* h, int32_t precision);
+
+int lsamg_info_get(const lsamg_handle* h, lsamg_info* out);
+int lsamg_export_setup(lsamg_handle* h, int32_t level, lsamg_setup_view* out);
+size_t lsamg_device_bytes(const lsamg_handle* h);
+void lsamg_destroy(lsamg_handle* h);
+const char* lsamg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSAMG_H */

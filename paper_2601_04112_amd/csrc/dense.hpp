@@ -1,0 +1,231 @@
+// Small dense FP64 linear algebra for the host setup phase.
+//
+// All matrices are column-major with leading dimension equal to their row
+// count.  Written from the textbook algorithms (Golub & Van Loan, "Matrix
+// Computations", 4th ed.): right-looking Cholesky (sec. 4.2), Householder
+// tridiagonalisation (sec. 8.3.1) followed by the implicit symmetric QR step
+// with Wilkinson shift (sec. 8.3.3), and Householder QR (sec. 5.2.2).
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <numeric>
+#include <vector>
+
+namespace lsamg {
+
+// In-place lower Cholesky factor of the SPD matrix a (n x n).  Only the lower
+// triangle is read and written.  Returns false if a pivot is not positive.
+inline bool chol_lower(int n, double* a) {
+  for (int j = 0; j < n; ++j) {
+    double* cj = a + (size_t)j * n;
+    double d = cj[j];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    d = std::sqrt(d);
+    cj[j] = d;
+    const double inv = 1.0 / d;
+    for (int i = j + 1; i < n; ++i) cj[i] *= inv;
+    for (int k = j + 1; k < n; ++k) {
+      double* ck = a + (size_t)k * n;
+      const double f = cj[k];
+      if (f == 0.0) continue;
+      for (int i = k; i < n; ++i) ck[i] -= cj[i] * f;
+    }
+  }
+  return true;
+}
+
+// Solve L X = B in place (B is n x r), L lower triangular from chol_lower.
+inline void trsm_lower(int n, const double* l, int r, double* b) {
+  for (int c = 0; c < r; ++c) {
+    double* x = b + (size_t)c * n;
+    for (int j = 0; j < n; ++j) {
+      const double* lj = l + (size_t)j * n;
+      const double xj = x[j] / lj[j];
+      x[j] = xj;
+      if (xj == 0.0) continue;
+      for (int i = j + 1; i < n; ++i) x[i] -= lj[i] * xj;
+    }
+  }
+}
+
+// Solve L^T X = B in place (B is n x r).
+inline void trsm_lower_t(int n, const double* l, int r, double* b) {
+  for (int c = 0; c < r; ++c) {
+    double* x = b + (size_t)c * n;
+    for (int j = n - 1; j >= 0; --j) {
+      const double* lj = l + (size_t)j * n;
+      double s = x[j];
+      for (int i = j + 1; i < n; ++i) s -= lj[i] * x[i];
+      x[j] = s / lj[j];
+    }
+  }
+}
+
+// Householder vector of x (length m): on return x holds v with v[0] scaled
+// so that H = I - beta v v^T maps the input to alpha e_1.
+inline void householder(int m, double* x, double& beta, double& alpha) {
+  double sig = 0.0;
+  for (int i = 1; i < m; ++i) sig += x[i] * x[i];
+  const double x0 = x[0];
+  if (sig == 0.0) {
+    beta = 0.0;
+    alpha = x0;
+    return;
+  }
+  const double nrm = std::sqrt(x0 * x0 + sig);
+  alpha = (x0 >= 0.0) ? -nrm : nrm;
+  x[0] = x0 - alpha;
+  const double vtv = x[0] * x[0] + sig;
+  beta = 2.0 / vtv;
+}
+
+// Symmetric eigen-decomposition a = V diag(w) V^T of the n x n matrix a
+// (full storage, overwritten by V).  Eigenvalues ascending.  Returns false if
+// the QR iteration does not converge.
+inline bool sym_eig(int n, double* a, double* w) {
+  if (n == 0) return true;
+  if (n == 1) {
+    w[0] = a[0];
+    a[0] = 1.0;
+    return true;
+  }
+  std::vector<double> d(n), e(n, 0.0), betas(n, 0.0), p(n), q(n);
+  // 1. Householder tridiagonalisation: reflector k acts on rows/cols k+1..n-1
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double* v = a + (size_t)k * n + (k + 1);      // column k below diagonal
+    double beta, alpha;
+    householder(m, v, beta, alpha);
+    betas[k] = beta;
+    e[k] = alpha;
+    if (beta == 0.0) continue;
+    // p = beta * T v, T = trailing block a[k+1:, k+1:]
+    for (int i = 0; i < m; ++i) p[i] = 0.0;
+    for (int j = 0; j < m; ++j) {
+      const double* tj = a + (size_t)(k + 1 + j) * n + (k + 1);
+      const double vj = v[j];
+      for (int i = 0; i < m; ++i) p[i] += tj[i] * vj;
+    }
+    double ptv = 0.0;
+    for (int i = 0; i < m; ++i) {
+      p[i] *= beta;
+      ptv += p[i] * v[i];
+    }
+    const double kk = 0.5 * beta * ptv;
+    for (int i = 0; i < m; ++i) q[i] = p[i] - kk * v[i];      // w
+    for (int j = 0; j < m; ++j) {
+      double* tj = a + (size_t)(k + 1 + j) * n + (k + 1);
+      const double vj = v[j], wj = q[j];
+      for (int i = 0; i < m; ++i) tj[i] -= v[i] * wj + q[i] * vj;
+    }
+  }
+  for (int k = 0; k < n; ++k) d[k] = a[(size_t)k * n + k];
+  e[n - 2] = a[(size_t)(n - 2) * n + (n - 1)];
+  // 2. accumulate Q = H_0 H_1 ... backwards into a separate matrix
+  std::vector<double> Q((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) Q[(size_t)i * n + i] = 1.0;
+  for (int k = n - 3; k >= 0; --k) {
+    const double beta = betas[k];
+    if (beta == 0.0) continue;
+    const int m = n - k - 1;
+    const double* v = a + (size_t)k * n + (k + 1);
+    for (int j = k + 1; j < n; ++j) {
+      double* qj = Q.data() + (size_t)j * n + (k + 1);
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += v[i] * qj[i];
+      s *= beta;
+      if (s == 0.0) continue;
+      for (int i = 0; i < m; ++i) qj[i] -= s * v[i];
+    }
+  }
+  // 3. implicit symmetric QR with Wilkinson shift on (d, e)
+  const double eps = 2.220446049250313e-16;
+  int hi = n - 1;
+  int guard = 0;
+  const int max_steps = 60 * n;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 &&
+           std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo])))
+      --lo;
+    if (++guard > max_steps) return false;
+    const double dd = 0.5 * (d[hi - 1] - d[hi]);
+    const double eh = e[hi - 1];
+    const double den = dd + ((dd >= 0.0) ? 1.0 : -1.0) * std::hypot(dd, eh);
+    const double mu = d[hi] - eh * eh / den;
+    double x = d[lo] - mu, z = e[lo];
+    for (int k = lo; k < hi; ++k) {
+      const double r = std::hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = x / r;
+        s = -z / r;
+      }
+      if (k > lo) e[k - 1] = c * x - s * z;
+      const double ak = d[k], bk = d[k + 1], fk = e[k];
+      d[k] = c * c * ak - 2.0 * c * s * fk + s * s * bk;
+      d[k + 1] = s * s * ak + 2.0 * c * s * fk + c * c * bk;
+      e[k] = c * s * (ak - bk) + (c * c - s * s) * fk;
+      if (k + 1 < hi) {
+        const double h = e[k + 1];
+        z = -s * h;
+        e[k + 1] = c * h;
+        x = e[k];
+      }
+      double* qk = Q.data() + (size_t)k * n;
+      double* qk1 = Q.data() + (size_t)(k + 1) * n;
+      for (int i = 0; i < n; ++i) {
+        const double u = qk[i], t = qk1[i];
+        qk[i] = c * u - s * t;
+        qk1[i] = s * u + c * t;
+      }
+    }
+  }
+  // 4. sort ascending
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int i, int j) { return d[i] < d[j]; });
+  for (int j = 0; j < n; ++j) {
+    w[j] = d[ord[j]];
+    std::copy(Q.data() + (size_t)ord[j] * n, Q.data() + (size_t)(ord[j] + 1) * n,
+              a + (size_t)j * n);
+  }
+  return true;
+}
+
+// Householder QR of the r x c matrix a (column-major).  On return the first
+// min(r, c) rows of a hold R (upper trapezoidal; entries below the diagonal
+// are zeroed), so that R^T R = A^T A.
+inline void qr_r(int r, int c, double* a) {
+  const int kmax = std::min(r - 1, c);
+  std::vector<double> v(r);
+  for (int k = 0; k < kmax; ++k) {
+    const int m = r - k;
+    double* col = a + (size_t)k * r + k;
+    std::copy(col, col + m, v.begin());
+    double beta, alpha;
+    householder(m, v.data(), beta, alpha);
+    if (beta == 0.0) continue;
+    col[0] = alpha;
+    for (int i = 1; i < m; ++i) col[i] = 0.0;
+    for (int j = k + 1; j < c; ++j) {
+      double* cj = a + (size_t)j * r + k;
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += v[i] * cj[i];
+      s *= beta;
+      if (s == 0.0) continue;
+      for (int i = 0; i < m; ++i) cj[i] -= s * v[i];
+    }
+  }
+  for (int j = 0; j < c; ++j)
+    for (int i = j + 1; i < r; ++i) a[(size_t)j * r + i] = 0.0;
+}
+
+}  // namespace lsamg

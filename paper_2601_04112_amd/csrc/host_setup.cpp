@@ -1,0 +1,820 @@
+// Host (CPU, FP64) construction of the LS-AMG-DD hierarchy, Algorithm 1 of
+// the paper (sec. 3.2), for the library.  Independent of the test oracle.
+//
+// Per level: lattice aggregation with unknowns renumbered so that every
+// aggregate omega_i is a contiguous range; one-layer overlap Omega_i =
+// omega_i + Gamma_i from the rows of G touching omega_i (sec. 2.2, 3.1.1);
+// multiplicities M and the SPSD splitting A~_i (Lemma, sec. 3.1.1); the
+// reduced eigenproblem eq:gevp-S solved as S~ u = mu A_ww u; selection of
+// sec. 3.4; smoother rows Z_i = A_i^{-1}(omega_i, Omega_i); interpolation
+// eq:mg-p; G_{l+1} = G_l P_l (sec. 3.1.3) with exact row compression.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <mutex>
+#include <numeric>
+#include <stdexcept>
+
+#include "dense.hpp"
+#include "internal.hpp"
+
+namespace lsamg {
+
+namespace {
+
+struct SetupError {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw SetupError{code, msg}; }
+
+}  // namespace
+
+int default_threads() {
+  unsigned h = std::thread::hardware_concurrency();
+  if (h == 0) h = 1;
+  return (int)std::min<unsigned>(h, 32);
+}
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int)>& body, int nthreads) {
+  if (n <= 0) return;
+  if (nthreads <= 0) nthreads = default_threads();
+  nthreads = (int)std::min<int64_t>(nthreads, n);
+  if (nthreads <= 1) {
+    for (int64_t i = 0; i < n; ++i) body(i, 0);
+    return;
+  }
+  std::atomic<int64_t> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  std::vector<std::thread> th;
+  th.reserve(nthreads);
+  for (int t = 0; t < nthreads; ++t) {
+    th.emplace_back([&, t]() {
+      try {
+        for (;;) {
+          int64_t i = next.fetch_add(1);
+          if (i >= n) break;
+          body(i, t);
+        }
+      } catch (...) {
+        std::lock_guard<std::mutex> g(mu);
+        if (!err) err = std::current_exception();
+        next.store(n);
+      }
+    });
+  }
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
+
+namespace {
+
+// Block id of each lattice index for block width b: a remainder narrower than
+// b/2 joins the last block, otherwise it is a block of its own.
+void axis_blocks(int extent, int b, std::vector<int>& id, int& nb) {
+  id.assign(extent, 0);
+  const int q = extent / b, r = extent % b;
+  if (q == 0) {
+    nb = 1;
+    return;
+  }
+  if (r == 0 || 2 * r >= b) {
+    for (int x = 0; x < extent; ++x) id[x] = x / b;
+    nb = q + (r ? 1 : 0);
+  } else {
+    for (int x = 0; x < extent; ++x) id[x] = std::min(x / b, q - 1);
+    nb = q;
+  }
+}
+
+struct AggResult {
+  int b = 0;
+  int64_t nagg = 0;
+  int aext[3] = {1, 1, 1};
+  std::vector<int64_t> id;  // per point
+};
+
+// Aggregate lattice points (coordinates pc, weights w = unknowns per point):
+// largest block b <= b0 with every aggregate holding at most omega_max
+// unknowns.
+AggResult aggregate_points(const std::vector<int32_t>& pc, const std::vector<int64_t>& w,
+                           int ndim, const int ext[3], int b0, int omega_max) {
+  const int64_t np = (int64_t)w.size();
+  AggResult res;
+  for (int b = b0; b >= 1; --b) {
+    std::vector<int> ids[3];
+    int nb[3] = {1, 1, 1};
+    for (int d = 0; d < ndim; ++d) axis_blocks(ext[d], b, ids[d], nb[d]);
+    int64_t nagg = 1;
+    for (int d = 0; d < ndim; ++d) nagg *= nb[d];
+    std::vector<int64_t> id(np);
+    std::vector<int64_t> size(nagg, 0);
+    for (int64_t i = 0; i < np; ++i) {
+      int64_t a = 0, stride = 1;
+      for (int d = 0; d < ndim; ++d) {
+        a += (int64_t)ids[d][pc[(size_t)i * ndim + d]] * stride;
+        stride *= nb[d];
+      }
+      id[i] = a;
+      size[a] += w[i];
+    }
+    int64_t mx = *std::max_element(size.begin(), size.end());
+    if (mx <= omega_max || b == 1) {
+      res.b = b;
+      res.nagg = nagg;
+      for (int d = 0; d < 3; ++d) res.aext[d] = d < ndim ? nb[d] : 1;
+      res.id = std::move(id);
+      for (int64_t a = 0; a < nagg; ++a)
+        if (size[a] == 0) fail(LSAMG_EINVAL, "empty aggregate");
+      return res;
+    }
+  }
+  return res;
+}
+
+struct Csr {
+  std::vector<int64_t> ptr;
+  std::vector<int32_t> col;
+  std::vector<double> val;
+};
+
+// Everything a level needs transiently during setup.
+struct Work {
+  std::vector<int32_t> agg_of;                     // aggregate of each unknown
+  std::vector<int64_t> gtouch_ptr;                 // per group: aggregates touched
+  std::vector<int32_t> gtouch;
+  std::vector<int64_t> nz_ptr;                     // per aggregate: groups in nz_i
+  std::vector<int32_t> nz;
+  std::vector<int64_t> dg_ptr;                     // per unknown: groups containing it
+  std::vector<int32_t> dg;
+  Csr A;                                           // A_l, structural pattern
+};
+
+int cmin_at(const lsamg_params& p, int level) {
+  int nc = std::max(1, std::min(p.ncmin, 8));
+  return std::max(1, p.cmin[std::min(level, nc - 1)]);
+}
+
+// Groups containing each unknown, and the sparse A_l = sum_g R_g^T R_g.
+void build_A(Level& L, Work& W, int nthreads) {
+  const Groups& G = L.G;
+  const int64_t ng = G.ng(), n = L.n;
+  W.dg_ptr.assign(n + 1, 0);
+  for (int64_t g = 0; g < ng; ++g)
+    for (int64_t q = G.sptr[g]; q < G.sptr[g + 1]; ++q) W.dg_ptr[G.supp[q] + 1]++;
+  for (int64_t d = 0; d < n; ++d) W.dg_ptr[d + 1] += W.dg_ptr[d];
+  W.dg.assign(W.dg_ptr[n], 0);
+  {
+    std::vector<int64_t> fill(W.dg_ptr.begin(), W.dg_ptr.end() - 1);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int64_t q = G.sptr[g]; q < G.sptr[g + 1]; ++q) W.dg[fill[G.supp[q]]++] = (int32_t)g;
+  }
+  for (int64_t d = 0; d < n; ++d)
+    if (W.dg_ptr[d + 1] == W.dg_ptr[d])
+      fail(LSAMG_ENOTSPD, "an unknown is touched by no row of G (A is singular)");
+  // rows of A, computed in parallel chunks then concatenated
+  const int64_t chunk = 4096;
+  const int64_t nchunk = (n + chunk - 1) / chunk;
+  std::vector<std::vector<int32_t>> ccol(nchunk);
+  std::vector<std::vector<double>> cval(nchunk);
+  std::vector<std::vector<int64_t>> clen(nchunk);
+  int nt = nthreads > 0 ? nthreads : default_threads();
+  std::vector<std::vector<double>> acc(nt);
+  std::vector<std::vector<int32_t>> mark(nt);
+  parallel_for(nchunk, [&](int64_t c, int t) {
+    if (acc[t].empty()) {
+      acc[t].assign(n, 0.0);
+      mark[t].assign(n, -1);
+    }
+    auto& a = acc[t];
+    auto& mk = mark[t];
+    std::vector<int32_t> touched;
+    const int64_t d0 = c * chunk, d1 = std::min(n, d0 + chunk);
+    for (int64_t d = d0; d < d1; ++d) {
+      touched.clear();
+      for (int64_t e = W.dg_ptr[d]; e < W.dg_ptr[d + 1]; ++e) {
+        const int64_t g = W.dg[e];
+        const int64_t s0 = G.sptr[g], ns = G.sptr[g + 1] - s0;
+        const int32_t* sp = G.supp.data() + s0;
+        const int64_t pd = std::lower_bound(sp, sp + ns, (int32_t)d) - sp;
+        const double* R = G.val.data() + G.vptr[g];
+        for (int64_t q = 0; q < ns; ++q)
+          if (mk[sp[q]] != (int32_t)d) {
+            mk[sp[q]] = (int32_t)d;
+            touched.push_back(sp[q]);
+          }
+        for (int t2 = 0; t2 < G.nrows[g]; ++t2) {
+          const double cf = R[t2 * ns + pd];
+          if (cf == 0.0) continue;
+          const double* row = R + t2 * ns;
+          for (int64_t q = 0; q < ns; ++q) a[sp[q]] += cf * row[q];
+        }
+      }
+      std::sort(touched.begin(), touched.end());
+      for (int32_t e : touched) {
+        ccol[c].push_back(e);
+        cval[c].push_back(a[e]);
+        a[e] = 0.0;
+      }
+      clen[c].push_back((int64_t)touched.size());
+    }
+  }, nthreads);
+  W.A.ptr.assign(n + 1, 0);
+  int64_t d = 0;
+  for (int64_t c = 0; c < nchunk; ++c)
+    for (int64_t len : clen[c]) {
+      W.A.ptr[d + 1] = W.A.ptr[d] + len;
+      ++d;
+    }
+  W.A.col.resize(W.A.ptr[n]);
+  W.A.val.resize(W.A.ptr[n]);
+  int64_t off = 0;
+  for (int64_t c = 0; c < nchunk; ++c) {
+    std::copy(ccol[c].begin(), ccol[c].end(), W.A.col.begin() + off);
+    std::copy(cval[c].begin(), cval[c].end(), W.A.val.begin() + off);
+    off += (int64_t)ccol[c].size();
+  }
+}
+
+// nz_i, Gamma_i, Omega_i, M (Lemma of sec. 3.1.1), colouring, threshold.
+void overlap_and_colour(Level& L, Work& W, const lsamg_params& p, int nthreads) {
+  const Groups& G = L.G;
+  const int64_t ng = G.ng(), n = L.n, na = L.nagg;
+  W.agg_of.assign(n, 0);
+  for (int64_t a = 0; a < na; ++a)
+    for (int64_t d = L.astart[a]; d < L.astart[a + 1]; ++d) W.agg_of[d] = (int32_t)a;
+  // aggregates touched by each group: supports ascend and aggregates are
+  // contiguous ranges, so the touched list is the run of distinct values
+  W.gtouch_ptr.assign(ng + 1, 0);
+  W.gtouch.clear();
+  L.M.assign(ng, 0);
+  for (int64_t g = 0; g < ng; ++g) {
+    int32_t last = -1;
+    for (int64_t q = G.sptr[g]; q < G.sptr[g + 1]; ++q) {
+      int32_t a = W.agg_of[G.supp[q]];
+      if (a != last) {
+        W.gtouch.push_back(a);
+        last = a;
+      }
+    }
+    W.gtouch_ptr[g + 1] = (int64_t)W.gtouch.size();
+    L.M[g] = (int32_t)(W.gtouch_ptr[g + 1] - W.gtouch_ptr[g]);
+  }
+  W.nz_ptr.assign(na + 1, 0);
+  for (int32_t a : W.gtouch) W.nz_ptr[a + 1]++;
+  for (int64_t a = 0; a < na; ++a) W.nz_ptr[a + 1] += W.nz_ptr[a];
+  W.nz.assign(W.nz_ptr[na], 0);
+  {
+    std::vector<int64_t> fill(W.nz_ptr.begin(), W.nz_ptr.end() - 1);
+    for (int64_t g = 0; g < ng; ++g)
+      for (int64_t e = W.gtouch_ptr[g]; e < W.gtouch_ptr[g + 1]; ++e)
+        W.nz[fill[W.gtouch[e]]++] = (int32_t)g;
+  }
+  // Omega_i = omega_i then Gamma_i ascending
+  std::vector<std::vector<int32_t>> gam(na);
+  int nt = nthreads > 0 ? nthreads : default_threads();
+  std::vector<std::vector<int32_t>> mark(nt);
+  parallel_for(na, [&](int64_t a, int t) {
+    if (mark[t].empty()) mark[t].assign(n, -1);
+    auto& mk = mark[t];
+    const int64_t w0 = L.astart[a], w1 = L.astart[a + 1];
+    auto& out = gam[a];
+    for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) {
+      const int64_t g = W.nz[e];
+      for (int64_t q = G.sptr[g]; q < G.sptr[g + 1]; ++q) {
+        const int32_t d = G.supp[q];
+        if (d >= w0 && d < w1) continue;
+        if (mk[d] != (int32_t)a) {
+          mk[d] = (int32_t)a;
+          out.push_back(d);
+        }
+      }
+    }
+    std::sort(out.begin(), out.end());
+  }, nthreads);
+  L.optr.assign(na + 1, 0);
+  for (int64_t a = 0; a < na; ++a)
+    L.optr[a + 1] = L.optr[a] + (L.astart[a + 1] - L.astart[a]) + (int64_t)gam[a].size();
+  L.oidx.resize(L.optr[na]);
+  for (int64_t a = 0; a < na; ++a) {
+    int64_t o = L.optr[a];
+    for (int64_t d = L.astart[a]; d < L.astart[a + 1]; ++d) L.oidx[o++] = (int32_t)d;
+    for (int32_t d : gam[a]) L.oidx[o++] = d;
+  }
+  // cover lists: unknown -> aggregates whose Omega holds it
+  std::vector<int64_t> cptr(n + 1, 0);
+  for (int32_t d : L.oidx) cptr[d + 1]++;
+  for (int64_t d = 0; d < n; ++d) cptr[d + 1] += cptr[d];
+  std::vector<int32_t> cov(cptr[n]);
+  {
+    std::vector<int64_t> fill(cptr.begin(), cptr.end() - 1);
+    for (int64_t a = 0; a < na; ++a)
+      for (int64_t o = L.optr[a]; o < L.optr[a + 1]; ++o) cov[fill[L.oidx[o]]++] = (int32_t)a;
+  }
+  int64_t nmult = 0;
+  for (int64_t d = 0; d < n; ++d) nmult = std::max(nmult, cptr[d + 1] - cptr[d]);
+  L.n_mult = (int)nmult;
+  // aggregate graph: i ~ j iff A(Omega_i, Omega_j) != 0 (structural)
+  std::vector<std::vector<int32_t>> adj(na);
+  std::vector<std::vector<int32_t>> mark2(nt);
+  parallel_for(na, [&](int64_t a, int t) {
+    if (mark2[t].empty()) mark2[t].assign(na, -1);
+    auto& mk = mark2[t];
+    auto& out = adj[a];
+    mk[a] = (int32_t)a;
+    for (int64_t o = L.optr[a]; o < L.optr[a + 1]; ++o) {
+      const int32_t d = L.oidx[o];
+      for (int64_t e = W.A.ptr[d]; e < W.A.ptr[d + 1]; ++e) {
+        const int32_t f = W.A.col[e];
+        for (int64_t c = cptr[f]; c < cptr[f + 1]; ++c) {
+          const int32_t b = cov[c];
+          if (mk[b] != (int32_t)a) {
+            mk[b] = (int32_t)a;
+            out.push_back(b);
+          }
+        }
+      }
+    }
+  }, nthreads);
+  std::vector<int32_t> color(na, -1);
+  int ncol = 0;
+  std::vector<int32_t> seen;
+  for (int64_t a = 0; a < na; ++a) {
+    seen.assign(adj[a].size() + 1, 0);
+    for (int32_t b : adj[a])
+      if (color[b] >= 0 && color[b] < (int32_t)seen.size()) seen[color[b]] = 1;
+    int c = 0;
+    while (seen[c]) ++c;
+    color[a] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  L.n_color = ncol;
+  L.thresh = std::max(0.1, (p.kappa - ncol) / ((double)ncol * (double)std::max(1, L.n_mult)));
+}
+
+// Eigenvector count of one aggregate (sec. 3.4 and the cluster reading).
+int select_count(const double* mu, int nw, const lsamg_params& p, int level, double thresh,
+                 bool& hazard) {
+  int k;
+  hazard = false;
+  if (p.n_eig_fixed > 0) {
+    k = std::min(p.n_eig_fixed, nw);
+  } else {
+    const double cut = (1.0 / thresh) * (1.0 - p.thresh_margin);
+    int count = 0;
+    for (int j = 0; j < nw; ++j) {
+      if (mu[j] < cut) ++count;
+      if (std::fabs(mu[j] - 1.0 / thresh) <= 1e-8 / thresh) hazard = true;
+    }
+    k = std::min(count, nw / cmin_at(p, level));
+  }
+  k = std::max(k, 1);
+  auto tie = [&](int j) {
+    return std::fabs(mu[j] - mu[j - 1]) <= p.tie_rtol * std::fabs(mu[j]) + p.tie_atol;
+  };
+  const int k0 = k;
+  while (k > 0 && k < nw && tie(k)) --k;
+  if (k == 0) {
+    k = k0;
+    while (k < nw && tie(k)) ++k;
+  }
+  return k;
+}
+
+// Local eigenproblems (eq:gevp-S) and smoother rows, one aggregate at a time.
+void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, int nthreads) {
+  const Groups& G = L.G;
+  const int64_t na = L.nagg, n = L.n;
+  L.k.assign(na, 0);
+  std::vector<std::vector<double>> mus(na), zh(na), zs(na);
+  std::atomic<int64_t> hazards{0};
+  int nt = nthreads > 0 ? nthreads : default_threads();
+  std::vector<std::vector<int32_t>> locs(nt);
+  parallel_for(na, [&](int64_t a, int t) {
+    if (locs[t].empty()) locs[t].assign(n, -1);
+    auto& loc = locs[t];
+    const int nw = (int)(L.astart[a + 1] - L.astart[a]);
+    const int64_t o0 = L.optr[a];
+    const int nO = (int)(L.optr[a + 1] - o0);
+    const int ng = nO - nw;
+    for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = j;
+    // A~_i (weighted, nO x nO) and A_ww = G_{nz,w}^T G_{nz,w}
+    std::vector<double> At((size_t)nO * nO, 0.0), Aww((size_t)nw * nw, 0.0);
+    std::vector<int> lp;
+    for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) {
+      const int64_t g = W.nz[e];
+      const int64_t s0 = G.sptr[g];
+      const int ns = (int)(G.sptr[g + 1] - s0);
+      const double wg = 1.0 / (double)L.M[g];
+      lp.resize(ns);
+      for (int q = 0; q < ns; ++q) lp[q] = loc[G.supp[s0 + q]];
+      const double* R = G.val.data() + G.vptr[g];
+      for (int r = 0; r < G.nrows[g]; ++r) {
+        const double* row = R + (size_t)r * ns;
+        for (int qc = 0; qc < ns; ++qc) {
+          const double vc = row[qc];
+          if (vc == 0.0) continue;
+          double* col = At.data() + (size_t)lp[qc] * nO;
+          const bool cw = lp[qc] < nw;
+          double* colw = Aww.data() + (size_t)lp[qc] * nw;
+          for (int qr = 0; qr < ns; ++qr) {
+            const double pr = row[qr] * vc;
+            col[lp[qr]] += wg * pr;
+            if (cw && lp[qr] < nw) colw[lp[qr]] += pr;
+          }
+        }
+      }
+    }
+    // S~ = A~_ww - A~_wG (A~_GG)^+ A~_Gw
+    std::vector<double> S((size_t)nw * nw);
+    for (int j = 0; j < nw; ++j)
+      for (int i = 0; i < nw; ++i) S[(size_t)j * nw + i] = At[(size_t)j * nO + i];
+    if (ng > 0) {
+      std::vector<double> Agg((size_t)ng * ng), lam(ng);
+      for (int j = 0; j < ng; ++j)
+        for (int i = 0; i < ng; ++i) Agg[(size_t)j * ng + i] = At[(size_t)(nw + j) * nO + nw + i];
+      if (!sym_eig(ng, Agg.data(), lam.data())) fail(LSAMG_ENOTSPD, "eigensolver did not converge");
+      const double lmax = std::max(lam[ng - 1], 0.0);
+      // Y = V_keep^T A~_Gw, then S -= Y^T diag(1/lam) Y
+      for (int c = 0; c < ng; ++c) {
+        if (!(lam[c] > p.pinv_rtol * lmax)) continue;
+        const double* v = Agg.data() + (size_t)c * ng;
+        std::vector<double> y(nw, 0.0);
+        for (int j = 0; j < nw; ++j) {
+          const double* col = At.data() + (size_t)j * nO + nw;   // A~_Gw column j
+          double s = 0.0;
+          for (int i = 0; i < ng; ++i) s += v[i] * col[i];
+          y[j] = s;
+        }
+        const double il = 1.0 / lam[c];
+        for (int j = 0; j < nw; ++j) {
+          const double f = y[j] * il;
+          double* sj = S.data() + (size_t)j * nw;
+          for (int i = 0; i < nw; ++i) sj[i] -= y[i] * f;
+        }
+      }
+    }
+    // S~ u = mu A_ww u  ->  C = L^{-1} S~ L^{-T}
+    if (!chol_lower(nw, Aww.data())) fail(LSAMG_ENOTSPD, "A(omega,omega) is not SPD");
+    std::vector<double> X(S);
+    trsm_lower(nw, Aww.data(), nw, X.data());
+    std::vector<double> C((size_t)nw * nw);
+    for (int j = 0; j < nw; ++j)
+      for (int i = 0; i < nw; ++i) C[(size_t)j * nw + i] = X[(size_t)i * nw + j];
+    trsm_lower(nw, Aww.data(), nw, C.data());
+    for (int j = 0; j < nw; ++j)
+      for (int i = j + 1; i < nw; ++i) {
+        const double s = 0.5 * (C[(size_t)j * nw + i] + C[(size_t)i * nw + j]);
+        C[(size_t)j * nw + i] = s;
+        C[(size_t)i * nw + j] = s;
+      }
+    std::vector<double> mu(nw);
+    if (!sym_eig(nw, C.data(), mu.data())) fail(LSAMG_ENOTSPD, "eigensolver did not converge");
+    bool hz = false;
+    const int k = select_count(mu.data(), nw, p, level, L.thresh, hz);
+    if (hz) hazards++;
+    trsm_lower_t(nw, Aww.data(), k, C.data());          // U = L^{-T} Y
+    std::vector<double> Zh((size_t)nw * k);
+    for (int t2 = 0; t2 < k; ++t2) {
+      const double* u = C.data() + (size_t)t2 * nw;
+      int jm = 0;
+      for (int j = 1; j < nw; ++j)
+        if (std::fabs(u[j]) > std::fabs(u[jm])) jm = j;
+      const double sg = u[jm] < 0.0 ? -1.0 : 1.0;
+      for (int j = 0; j < nw; ++j) Zh[(size_t)j * k + t2] = sg * u[j];
+    }
+    L.k[a] = k;
+    mus[a] = std::move(mu);
+    zh[a] = std::move(Zh);
+    // smoother: A_i = A(Omega_i, Omega_i), Z_i = A_i^{-1}(omega_i, Omega_i)
+    std::vector<double> Ai((size_t)nO * nO, 0.0);
+    for (int r = 0; r < nO; ++r) {
+      const int32_t d = L.oidx[o0 + r];
+      for (int64_t e = W.A.ptr[d]; e < W.A.ptr[d + 1]; ++e) {
+        const int c = loc[W.A.col[e]];
+        if (c >= 0) Ai[(size_t)c * nO + r] = W.A.val[e];
+      }
+    }
+    for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = -1;
+    if (!chol_lower(nO, Ai.data())) fail(LSAMG_ENOTSPD, "local block A(Omega,Omega) is not SPD");
+    std::vector<double> Zc((size_t)nO * nw, 0.0);
+    for (int j = 0; j < nw; ++j) Zc[(size_t)j * nO + j] = 1.0;
+    trsm_lower(nO, Ai.data(), nw, Zc.data());
+    trsm_lower_t(nO, Ai.data(), nw, Zc.data());
+    zs[a] = std::move(Zc);          // column j = row j of A_i^{-1} restricted to omega
+  }, nthreads);
+  L.hazards = hazards.load();
+  L.muptr.assign(na + 1, 0);
+  L.zoff.assign(na + 1, 0);
+  L.poff.assign(na + 1, 0);
+  for (int64_t a = 0; a < na; ++a) {
+    L.muptr[a + 1] = L.muptr[a] + (int64_t)mus[a].size();
+    L.zoff[a + 1] = L.zoff[a] + (int64_t)zs[a].size();
+    L.poff[a + 1] = L.poff[a] + (int64_t)zh[a].size();
+  }
+  L.mu.resize(L.muptr[na]);
+  L.Z.resize(L.zoff[na]);
+  L.Zhat.resize(L.poff[na]);
+  parallel_for(na, [&](int64_t a, int) {
+    std::copy(mus[a].begin(), mus[a].end(), L.mu.begin() + L.muptr[a]);
+    std::copy(zs[a].begin(), zs[a].end(), L.Z.begin() + L.zoff[a]);
+    std::copy(zh[a].begin(), zh[a].end(), L.Zhat.begin() + L.poff[a]);
+  }, nthreads);
+}
+
+// Next level: numbering (aggregated or not), and G_{l+1} = G_l P_l grouped by
+// the set of parent aggregates each row touches, every group replaced by the
+// R factor of its QR factorisation.
+void next_level(Level& L, Work& W, Level& N, bool aggregate_next, const lsamg_params& p,
+                int nthreads) {
+  const int64_t na = L.nagg;
+  const int ndim = L.ndim;
+  std::vector<int32_t> pc((size_t)na * ndim);
+  for (int64_t a = 0; a < na; ++a) {
+    int64_t r = a;
+    for (int d = 0; d < ndim; ++d) {
+      pc[(size_t)a * ndim + d] = (int32_t)(r % L.aext[d]);
+      r /= L.aext[d];
+    }
+  }
+  std::vector<int64_t> wk(na);
+  for (int64_t a = 0; a < na; ++a) wk[a] = L.k[a];
+  std::vector<int64_t> cagg(na, 0);
+  N.ndim = ndim;
+  for (int d = 0; d < 3; ++d) N.ext[d] = L.aext[d];
+  if (aggregate_next) {
+    AggResult r = aggregate_points(pc, wk, ndim, N.ext, p.block, p.omega_max);
+    cagg = r.id;
+    N.block = r.b;
+    N.nagg = r.nagg;
+    for (int d = 0; d < 3; ++d) N.aext[d] = r.aext[d];
+  }
+  std::vector<int64_t> order(na);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t x, int64_t y) { return cagg[x] < cagg[y]; });
+  L.cstart.assign(na + 1, 0);
+  std::vector<int64_t> canon_off(na + 1, 0);
+  for (int64_t a = 0; a < na; ++a) canon_off[a + 1] = canon_off[a] + L.k[a];
+  int64_t off = 0;
+  N.n = canon_off[na];
+  N.coord.resize((size_t)N.n * ndim);
+  N.canon.resize(N.n);
+  if (aggregate_next) N.astart.assign(N.nagg + 1, 0);
+  for (int64_t t = 0; t < na; ++t) {
+    const int64_t a = order[t];
+    L.cstart[a] = off;
+    for (int s = 0; s < L.k[a]; ++s) {
+      for (int d = 0; d < ndim; ++d) N.coord[(size_t)(off + s) * ndim + d] = pc[(size_t)a * ndim + d];
+      N.canon[off + s] = canon_off[a] + s;
+    }
+    if (aggregate_next) N.astart[cagg[a] + 1] += L.k[a];
+    off += L.k[a];
+  }
+  L.cstart[na] = off;
+  if (aggregate_next)
+    for (int64_t c = 0; c < N.nagg; ++c) N.astart[c + 1] += N.astart[c];
+  // group the rows of G_l by touched-aggregate set
+  const Groups& G = L.G;
+  const int64_t ng = G.ng();
+  typedef std::array<int32_t, 8> Key;
+  std::vector<Key> keys(ng);
+  for (int64_t g = 0; g < ng; ++g) {
+    Key k;
+    k.fill(-1);
+    const int64_t t0 = W.gtouch_ptr[g], nt = W.gtouch_ptr[g + 1] - t0;
+    if (nt > 8) fail(LSAMG_EINVAL, "a row of G touches more than 8 aggregates");
+    for (int64_t e = 0; e < nt; ++e) k[e] = W.gtouch[t0 + e];
+    std::sort(k.begin(), k.begin() + nt);
+    keys[g] = k;
+  }
+  std::vector<int64_t> gord(ng);
+  std::iota(gord.begin(), gord.end(), 0);
+  std::sort(gord.begin(), gord.end(), [&](int64_t x, int64_t y) {
+    if (keys[x] != keys[y]) return keys[x] < keys[y];
+    return x < y;
+  });
+  std::vector<int64_t> gstart;
+  for (int64_t t = 0; t < ng; ++t)
+    if (t == 0 || keys[gord[t]] != keys[gord[t - 1]]) gstart.push_back(t);
+  gstart.push_back(ng);
+  const int64_t nng = (int64_t)gstart.size() - 1;
+  std::vector<std::vector<int32_t>> nsupp(nng);
+  std::vector<std::vector<double>> nval(nng);
+  std::vector<int32_t> nrows(nng);
+  parallel_for(nng, [&](int64_t h, int) {
+    const Key& key = keys[gord[gstart[h]]];
+    std::vector<int64_t> par;
+    for (int32_t a : key)
+      if (a >= 0) par.push_back(a);
+    std::sort(par.begin(), par.end(), [&](int64_t x, int64_t y) { return L.cstart[x] < L.cstart[y]; });
+    std::vector<int32_t> supp;
+    std::vector<int64_t> pos(par.size());
+    for (size_t e = 0; e < par.size(); ++e) {
+      pos[e] = (int64_t)supp.size();
+      for (int s = 0; s < L.k[par[e]]; ++s) supp.push_back((int32_t)(L.cstart[par[e]] + s));
+    }
+    const int c = (int)supp.size();
+    int64_t rows = 0;
+    for (int64_t t = gstart[h]; t < gstart[h + 1]; ++t) rows += G.nrows[gord[t]];
+    std::vector<double> B((size_t)rows * c, 0.0);     // column-major rows x c
+    int64_t r0 = 0;
+    for (int64_t t = gstart[h]; t < gstart[h + 1]; ++t) {
+      const int64_t g = gord[t];
+      const int64_t s0 = G.sptr[g];
+      const int ns = (int)(G.sptr[g + 1] - s0);
+      const double* R = G.val.data() + G.vptr[g];
+      for (int q = 0; q < ns; ++q) {
+        const int32_t d = G.supp[s0 + q];
+        const int32_t a = W.agg_of[d];
+        const int64_t e = std::find(par.begin(), par.end(), (int64_t)a) - par.begin();
+        const int kk = L.k[a];
+        const int pw = (int)(d - L.astart[a]);
+        const double* zrow = L.Zhat.data() + L.poff[a] + (size_t)pw * kk;
+        for (int r = 0; r < G.nrows[g]; ++r) {
+          const double v = R[(size_t)r * ns + q];
+          if (v == 0.0) continue;
+          for (int s = 0; s < kk; ++s) B[(size_t)(pos[e] + s) * rows + r0 + r] += v * zrow[s];
+        }
+      }
+      r0 += G.nrows[g];
+    }
+    qr_r((int)rows, c, B.data());
+    const int nr = (int)std::min<int64_t>(rows, c);
+    std::vector<double> out((size_t)nr * c);
+    for (int r = 0; r < nr; ++r)
+      for (int j = 0; j < c; ++j) out[(size_t)r * c + j] = B[(size_t)j * rows + r];
+    nsupp[h] = std::move(supp);
+    nval[h] = std::move(out);
+    nrows[h] = nr;
+  }, nthreads);
+  Groups& NG = N.G;
+  NG.sptr.assign(nng + 1, 0);
+  NG.vptr.assign(nng + 1, 0);
+  NG.nrows = nrows;
+  for (int64_t h = 0; h < nng; ++h) {
+    NG.sptr[h + 1] = NG.sptr[h] + (int64_t)nsupp[h].size();
+    NG.vptr[h + 1] = NG.vptr[h] + (int64_t)nval[h].size();
+  }
+  NG.supp.resize(NG.sptr[nng]);
+  NG.val.resize(NG.vptr[nng]);
+  for (int64_t h = 0; h < nng; ++h) {
+    std::copy(nsupp[h].begin(), nsupp[h].end(), NG.supp.begin() + NG.sptr[h]);
+    std::copy(nval[h].begin(), nval[h].end(), NG.val.begin() + NG.vptr[h]);
+  }
+}
+
+void coarsest_inverse(Level& L, Work& W, int nthreads) {
+  const int64_t n = L.n;
+  if (n > 40000) fail(LSAMG_EINVAL, "coarsest level too large for a dense solve");
+  std::vector<double> A((size_t)n * n, 0.0);
+  for (int64_t r = 0; r < n; ++r)
+    for (int64_t e = W.A.ptr[r]; e < W.A.ptr[r + 1]; ++e) A[(size_t)W.A.col[e] * n + r] = W.A.val[e];
+  if (!chol_lower((int)n, A.data())) fail(LSAMG_ENOTSPD, "coarsest matrix is not SPD");
+  L.Ainv.assign((size_t)n * n, 0.0);
+  parallel_for(n, [&](int64_t j, int) {
+    double* x = L.Ainv.data() + (size_t)j * n;
+    x[j] = 1.0;
+    trsm_lower((int)n, A.data(), 1, x);
+    trsm_lower_t((int)n, A.data(), 1, x);
+  }, nthreads);
+}
+
+}  // namespace
+
+int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, std::string& msg) {
+  auto t0 = std::chrono::steady_clock::now();
+  try {
+    H.params = p;
+    const int ndim = p.ndim;
+    if (ndim < 1 || ndim > 3) fail(LSAMG_EINVAL, "ndim must be 1, 2 or 3");
+    int64_t np = 1;
+    for (int d = 0; d < ndim; ++d) {
+      if (p.grid[d] <= 0) fail(LSAMG_EINVAL, "grid extents must be positive");
+      np *= p.grid[d];
+    }
+    if (Gin.n != np) fail(LSAMG_EINVAL, "G has n columns != product of grid extents");
+    if (Gin.m <= 0 || Gin.n <= 0 || !Gin.rowptr || (Gin.nnz > 0 && (!Gin.col || !Gin.val)))
+      fail(LSAMG_EINVAL, "bad G");
+    if (p.block < 1 || p.omega_max < 1 || p.max_levels < 1) fail(LSAMG_EINVAL, "bad params");
+    if (Gin.rowptr[0] != 0 || Gin.rowptr[Gin.m] != Gin.nnz) fail(LSAMG_EINVAL, "bad rowptr");
+    if (Gin.n > INT32_MAX) fail(LSAMG_EINVAL, "n too large");
+    const int nthreads = p.nthreads;
+    H.ndim = ndim;
+    const int64_t n = Gin.n;
+    // level-0 aggregation on the canonical lattice
+    std::vector<int32_t> pc((size_t)n * ndim);
+    for (int64_t c = 0; c < n; ++c) {
+      int64_t r = c;
+      for (int d = 0; d < ndim; ++d) {
+        pc[(size_t)c * ndim + d] = (int32_t)(r % p.grid[d]);
+        r /= p.grid[d];
+      }
+    }
+    H.levels.clear();
+    H.levels.emplace_back();
+    Level& L0 = H.levels[0];
+    L0.n = n;
+    L0.ndim = ndim;
+    for (int d = 0; d < 3; ++d) L0.ext[d] = d < ndim ? p.grid[d] : 1;
+    const bool agg0 = (p.max_levels > 1) && (n > p.max_coarse);
+    std::vector<int64_t> aid(n, 0);
+    if (agg0) {
+      std::vector<int64_t> w(n, 1);
+      AggResult r = aggregate_points(pc, w, ndim, L0.ext, p.block, p.omega_max);
+      aid = r.id;
+      L0.block = r.b;
+      L0.nagg = r.nagg;
+      for (int d = 0; d < 3; ++d) L0.aext[d] = r.aext[d];
+    }
+    std::vector<int64_t> perm(n);      // internal -> canonical
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int64_t x, int64_t y) { return aid[x] < aid[y]; });
+    std::vector<int32_t> inv(n);
+    for (int64_t i = 0; i < n; ++i) inv[perm[i]] = (int32_t)i;
+    L0.canon = perm;
+    L0.coord.resize((size_t)n * ndim);
+    for (int64_t i = 0; i < n; ++i)
+      for (int d = 0; d < ndim; ++d) L0.coord[(size_t)i * ndim + d] = pc[(size_t)perm[i] * ndim + d];
+    if (agg0) {
+      L0.astart.assign(L0.nagg + 1, 0);
+      for (int64_t c = 0; c < n; ++c) L0.astart[aid[c] + 1]++;
+      for (int64_t a = 0; a < L0.nagg; ++a) L0.astart[a + 1] += L0.astart[a];
+    }
+    // level-0 groups: every non-empty row of G (exact zeros dropped)
+    Groups& G0 = L0.G;
+    G0.sptr.assign(1, 0);
+    G0.vptr.assign(1, 0);
+    H.row_map.clear();
+    std::vector<std::pair<int32_t, double>> ent;
+    for (int64_t r = 0; r < Gin.m; ++r) {
+      ent.clear();
+      const int64_t e0 = Gin.rowptr[r], e1 = Gin.rowptr[r + 1];
+      if (e1 < e0) fail(LSAMG_EINVAL, "rowptr not monotone");
+      for (int64_t e = e0; e < e1; ++e) {
+        const int32_t c = Gin.col[e];
+        const double v = Gin.val[e];
+        if (c < 0 || c >= n) fail(LSAMG_EINVAL, "column index out of range");
+        if (!std::isfinite(v)) fail(LSAMG_EBADINPUT, "non-finite entry in G");
+        if (v != 0.0) ent.emplace_back(inv[c], v);
+      }
+      if (ent.empty()) continue;
+      std::sort(ent.begin(), ent.end());
+      for (size_t q = 1; q < ent.size(); ++q)
+        if (ent[q].first == ent[q - 1].first) fail(LSAMG_EINVAL, "duplicate column in a row of G");
+      H.row_map.push_back(r);
+      for (auto& pr : ent) {
+        G0.supp.push_back(pr.first);
+        G0.val.push_back(pr.second);
+      }
+      G0.sptr.push_back((int64_t)G0.supp.size());
+      G0.vptr.push_back((int64_t)G0.val.size());
+      G0.nrows.push_back(1);
+    }
+    H.m0 = (int64_t)H.row_map.size();
+    // Algorithm 1 main loop
+    int l = 0;
+    bool aggregated = agg0;
+    for (;;) {
+      Level& L = H.levels[l];
+      Work W;
+      build_A(L, W, nthreads);
+      L.a_nnz = W.A.ptr[L.n];
+      if (!aggregated) {
+        L.coarsest = true;
+        coarsest_inverse(L, W, nthreads);
+        break;
+      }
+      overlap_and_colour(L, W, p, nthreads);
+      spectral_and_smoother(L, W, p, l, nthreads);
+      int64_t nn = 0;
+      for (int32_t kk : L.k) nn += kk;
+      const bool stall = (double)nn > p.stall_ratio * (double)L.n;
+      const bool agg_next = (l + 1 < p.max_levels - 1) && (nn > p.max_coarse) && !stall;
+      Level N;
+      next_level(L, W, N, agg_next, p, nthreads);
+      H.levels.push_back(std::move(N));
+      aggregated = agg_next;
+      ++l;
+    }
+  } catch (const SetupError& e) {
+    msg = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    msg = "host allocation failed during setup";
+    return LSAMG_ENOMEM;
+  } catch (const std::exception& e) {
+    msg = e.what();
+    return LSAMG_EINVAL;
+  }
+  H.setup_seconds =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return LSAMG_OK;
+}
+
+}  // namespace lsamg

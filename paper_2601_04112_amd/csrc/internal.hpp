@@ -1,0 +1,86 @@
+// Internal host-side data of the LS-AMG-DD library (not part of the C-ABI).
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lsamg.h"
+
+namespace lsamg {
+
+// Rows of G_l, grouped.  On the finest level every row of the user's G is a
+// group of its own.  On coarser levels a group holds all rows of G_l = G_{l-1}
+// P_{l-1} that touch the same set of parent aggregates; they share one
+// symbolic support (every unknown of those parents), one multiplicity M and
+// one set of overlapping aggregates, and are replaced by the R factor of
+// their QR factorisation, which leaves every sum of w g^T g unchanged.
+struct Groups {
+  std::vector<int64_t> sptr;   // [ng+1] support pointer
+  std::vector<int32_t> supp;   // support columns, ascending (internal numbering)
+  std::vector<int32_t> nrows;  // [ng] rows stored for the group
+  std::vector<int64_t> vptr;   // [ng+1] value offset: nrows x |supp| row-major
+  std::vector<double> val;
+  int64_t ng() const { return (int64_t)nrows.size(); }
+  int64_t total_rows() const {
+    int64_t s = 0;
+    for (int32_t r : nrows) s += r;
+    return s;
+  }
+};
+
+struct Level {
+  int64_t n = 0;
+  int ndim = 0;
+  int ext[3] = {1, 1, 1};          // lattice extent of this level
+  std::vector<int32_t> coord;      // [n*ndim] lattice coordinate of each unknown
+  std::vector<int64_t> canon;      // canonical index of each internal unknown
+  Groups G;
+  bool coarsest = false;
+  int64_t a_nnz = 0;               // entries of A_l = G_l^T G_l
+  // aggregation (non-coarsest)
+  int block = 0;
+  int64_t nagg = 0;
+  int aext[3] = {1, 1, 1};
+  std::vector<int64_t> astart;     // [nagg+1] omega_i = [astart[i], astart[i+1])
+  std::vector<int64_t> optr;       // [nagg+1]
+  std::vector<int32_t> oidx;       // Omega_i = omega_i then Gamma_i (ascending)
+  std::vector<int32_t> M;          // multiplicity per group
+  int n_color = 0, n_mult = 0;
+  double thresh = 0.0;
+  std::vector<int32_t> k;          // eigenvectors kept per aggregate
+  std::vector<double> mu;          // all local eigenvalues, concatenated by aggregate
+  std::vector<int64_t> muptr;      // [nagg+1]
+  std::vector<int64_t> zoff;       // [nagg+1] offsets into Z
+  std::vector<double> Z;           // A_i^{-1}(omega_i, Omega_i), row-major
+  std::vector<int64_t> poff;       // [nagg+1] offsets into Zhat
+  std::vector<double> Zhat;        // |omega_i| x k_i row-major
+  std::vector<int64_t> cstart;     // [nagg+1] coarse unknowns of aggregate i
+  int64_t hazards = 0;
+  // coarsest
+  std::vector<double> Ainv;        // n x n dense inverse
+};
+
+struct Hierarchy {
+  lsamg_params params;
+  int ndim = 0;
+  int64_t m0 = 0;                  // rows of the user's G after dropping empty ones
+  std::vector<int64_t> row_map;    // kept user rows
+  std::vector<Level> levels;
+  double setup_seconds = 0.0;
+};
+
+// Build the whole hierarchy on the host.  Returns an LSAMG_* code and fills
+// msg on error.
+int build_hierarchy(const lsamg_csr& G, const lsamg_params& p, Hierarchy& H,
+                    std::string& msg);
+
+// Run body(i) for i in [0, n) on a pool of threads (dynamic schedule).
+void parallel_for(int64_t n, const std::function<void(int64_t, int)>& body,
+                  int nthreads = 0);
+int default_threads();
+
+}  // namespace lsamg

@@ -1,0 +1,713 @@
+// Device hierarchy, V-cycle, PCG and the C-ABI of the LS-AMG-DD library.
+//
+// Solve phase (all on the GPU): preconditioned CG in FP64 (sec. 4.1) whose
+// preconditioner is one V-cycle per iteration (sec. 3.1.1): RAS pre-smoothing
+// (eq:ras), residual b - G^T(G x), restriction with P^T (eq:mg-p), the next
+// level's V-cycle or the dense coarsest inverse, prolongation, residual and
+// RAS-T post-smoothing (eq:ras-t).  The V-cycle runs in FP64 or, in mixed
+// mode, in FP32 under the FP64 CG.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "kernels.hpp"
+
+using namespace lsamg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct DevError {
+  int code;
+  std::string msg;
+};
+
+#define HIP_OK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw DevError{e_ == hipErrorOutOfMemory ? LSAMG_ENOMEM : LSAMG_EHIP,           \
+                     std::string(#expr) + ": " + hipGetErrorString(e_)};              \
+  } while (0)
+
+#define LAUNCH_OK() HIP_OK(hipGetLastError())
+
+inline unsigned nblocks(int64_t work) {
+  return (unsigned)std::max<int64_t>(1, (work + dev::kBlock - 1) / dev::kBlock);
+}
+
+template <typename T>
+struct DPrec {            // arrays that exist in both V-cycle precisions
+  T* g_val = nullptr;     // G_l values (CSR)
+  T* gt_val = nullptr;    // G_l^T values (CSR by unknown)
+  T* Zc = nullptr;        // Z_i column-major (RAS)
+  T* Zr = nullptr;        // Z_i row-major (RAS-T)
+  T* Zh = nullptr;        // Zhat_i row-major (P)
+  T* Ainv = nullptr;      // coarsest inverse
+  T* x = nullptr;         // V-cycle output at this level
+  T* b = nullptr;         // V-cycle input at this level
+  T* r = nullptr;         // residual
+  T* y = nullptr;         // G x (length = rows of G_l)
+  T* tb = nullptr;        // RAS-T staging, sum |Omega_i|
+};
+
+struct DLevel {
+  int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
+  bool coarsest = false;
+  int lanes_g = 1, lanes_gt = 1;
+  int max_nO = 0, max_nw = 0, max_k = 0;
+  int64_t* g_ptr = nullptr;
+  int32_t* g_col = nullptr;
+  int64_t* gt_ptr = nullptr;
+  int32_t* gt_col = nullptr;
+  int64_t *astart = nullptr, *optr = nullptr, *zoff = nullptr, *poff = nullptr,
+          *cstart = nullptr, *cptr = nullptr, *cpos = nullptr;
+  int32_t* oidx = nullptr;
+  int32_t* kk = nullptr;
+  DPrec<double> d;
+  DPrec<float> f;
+};
+
+template <typename T>
+DPrec<T>& prec(DLevel& L);
+template <>
+DPrec<double>& prec<double>(DLevel& L) { return L.d; }
+template <>
+DPrec<float>& prec<float>(DLevel& L) { return L.f; }
+
+int lanes_for(double avg) {
+  int l = 1;
+  while (l < 64 && l < avg) l <<= 1;
+  return l;
+}
+
+}  // namespace
+
+struct lsamg_handle {
+  Hierarchy H;
+  int device = -1;
+  int precision = LSAMG_FP64;
+  std::vector<DLevel> L;
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  int64_t* perm = nullptr;          // internal -> user numbering (finest level)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
+         *bi = nullptr, *part = nullptr, *sc = nullptr;
+  int* flag = nullptr;
+  double* sc_host = nullptr;         // pinned
+  int nparts = 1024;
+  // export buffers
+  std::vector<int32_t> ex_agg, ex_k, ex_M;
+  std::vector<int64_t> ex_optr, ex_oidx, ex_muptr;
+  std::vector<double> ex_mu;
+
+  template <typename T>
+  T* alloc(size_t count) {
+    void* ptr = nullptr;
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    HIP_OK(hipMalloc(&ptr, b));
+    allocs.push_back(ptr);
+    bytes += b;
+    return (T*)ptr;
+  }
+  template <typename T>
+  T* upload(const std::vector<T>& v) {
+    T* ptr = alloc<T>(v.size());
+    if (!v.empty()) HIP_OK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return ptr;
+  }
+  template <typename T>
+  T* upload_f(const std::vector<double>& v) {   // FP64 host data in precision T
+    if (sizeof(T) == sizeof(double)) return (T*)upload(v);
+    std::vector<T> t(v.begin(), v.end());
+    return upload(t);
+  }
+  void free_all() {
+    for (void* ptr : allocs) (void)hipFree(ptr);
+    allocs.clear();
+    if (sc_host) (void)hipHostFree(sc_host);
+    sc_host = nullptr;
+    bytes = 0;
+  }
+};
+
+namespace {
+
+// Build the device image of one level from the host hierarchy.
+void upload_level(lsamg_handle* h, const Level& HL, DLevel& D) {
+  D.n = HL.n;
+  D.coarsest = HL.coarsest;
+  // CSR of G_l: finest rows as given; coarse groups store the upper
+  // trapezoid of their R factor (row t keeps support columns t..c-1)
+  std::vector<int64_t> gp(1, 0);
+  std::vector<int32_t> gc;
+  std::vector<double> gv;
+  const Groups& G = HL.G;
+  for (int64_t g = 0; g < G.ng(); ++g) {
+    const int64_t s0 = G.sptr[g];
+    const int c = (int)(G.sptr[g + 1] - s0);
+    const double* R = G.val.data() + G.vptr[g];
+    const bool tri = G.nrows[g] > 1;
+    for (int t = 0; t < G.nrows[g]; ++t) {
+      for (int j = tri ? t : 0; j < c; ++j) {
+        gc.push_back(G.supp[s0 + j]);
+        gv.push_back(R[(size_t)t * c + j]);
+      }
+      gp.push_back((int64_t)gc.size());
+    }
+  }
+  D.nrows = (int64_t)gp.size() - 1;
+  D.nnz = (int64_t)gc.size();
+  // transpose
+  std::vector<int64_t> tp(D.n + 1, 0);
+  for (int32_t c : gc) tp[c + 1]++;
+  for (int64_t j = 0; j < D.n; ++j) tp[j + 1] += tp[j];
+  std::vector<int32_t> tc(D.nnz);
+  std::vector<double> tv(D.nnz);
+  {
+    std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+    for (int64_t r = 0; r < D.nrows; ++r)
+      for (int64_t e = gp[r]; e < gp[r + 1]; ++e) {
+        const int64_t o = fill[gc[e]]++;
+        tc[o] = (int32_t)r;
+        tv[o] = gv[e];
+      }
+  }
+  D.lanes_g = lanes_for((double)D.nnz / std::max<int64_t>(1, D.nrows));
+  D.lanes_gt = lanes_for((double)D.nnz / std::max<int64_t>(1, D.n));
+  D.g_ptr = h->upload(gp);
+  D.g_col = h->upload(gc);
+  D.gt_ptr = h->upload(tp);
+  D.gt_col = h->upload(tc);
+  D.d.g_val = h->upload_f<double>(gv);
+  D.f.g_val = h->upload_f<float>(gv);
+  D.d.gt_val = h->upload_f<double>(tv);
+  D.f.gt_val = h->upload_f<float>(tv);
+  D.d.x = h->alloc<double>(D.n);
+  D.d.b = h->alloc<double>(D.n);
+  D.d.r = h->alloc<double>(D.n);
+  D.d.y = h->alloc<double>(D.nrows);
+  D.f.x = h->alloc<float>(D.n);
+  D.f.b = h->alloc<float>(D.n);
+  D.f.r = h->alloc<float>(D.n);
+  D.f.y = h->alloc<float>(D.nrows);
+  if (HL.coarsest) {
+    D.d.Ainv = h->upload_f<double>(HL.Ainv);
+    D.f.Ainv = h->upload_f<float>(HL.Ainv);
+    return;
+  }
+  D.nagg = HL.nagg;
+  D.ntb = HL.optr[HL.nagg];
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    D.max_nO = std::max<int>(D.max_nO, (int)(HL.optr[a + 1] - HL.optr[a]));
+    D.max_nw = std::max<int>(D.max_nw, (int)(HL.astart[a + 1] - HL.astart[a]));
+    D.max_k = std::max<int>(D.max_k, HL.k[a]);
+  }
+  // Z_i row-major (host layout) and its column-major copy
+  std::vector<double> Zc(HL.Z.size());
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    const int nw = (int)(HL.astart[a + 1] - HL.astart[a]);
+    const int nO = (int)(HL.optr[a + 1] - HL.optr[a]);
+    const double* zr = HL.Z.data() + HL.zoff[a];
+    double* zc = Zc.data() + HL.zoff[a];
+    for (int p = 0; p < nw; ++p)
+      for (int c = 0; c < nO; ++c) zc[(size_t)c * nw + p] = zr[(size_t)p * nO + c];
+  }
+  // cover lists for the RAS-T gather: for unknown j, staging positions
+  // optr[i] + (index of j in Omega_i), ascending i
+  std::vector<int64_t> cp(D.n + 1, 0);
+  for (int32_t j : HL.oidx) cp[j + 1]++;
+  for (int64_t j = 0; j < D.n; ++j) cp[j + 1] += cp[j];
+  std::vector<int64_t> cs(cp[D.n]);
+  {
+    std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+    for (int64_t a = 0; a < HL.nagg; ++a)
+      for (int64_t o = HL.optr[a]; o < HL.optr[a + 1]; ++o) cs[fill[HL.oidx[o]]++] = o;
+  }
+  D.astart = h->upload(HL.astart);
+  D.optr = h->upload(HL.optr);
+  D.oidx = h->upload(HL.oidx);
+  D.zoff = h->upload(HL.zoff);
+  D.poff = h->upload(HL.poff);
+  D.cstart = h->upload(HL.cstart);
+  D.kk = h->upload(HL.k);
+  D.cptr = h->upload(cp);
+  D.cpos = h->upload(cs);
+  D.d.Zr = h->upload_f<double>(HL.Z);
+  D.f.Zr = h->upload_f<float>(HL.Z);
+  D.d.Zc = h->upload_f<double>(Zc);
+  D.f.Zc = h->upload_f<float>(Zc);
+  D.d.Zh = h->upload_f<double>(HL.Zhat);
+  D.f.Zh = h->upload_f<float>(HL.Zhat);
+  D.d.tb = h->alloc<double>(D.ntb);
+  D.f.tb = h->alloc<float>(D.ntb);
+}
+
+void upload(lsamg_handle* h) {
+  HIP_OK(hipSetDevice(h->device));
+  h->L.resize(h->H.levels.size());
+  for (size_t l = 0; l < h->H.levels.size(); ++l) upload_level(h, h->H.levels[l], h->L[l]);
+  const Level& L0 = h->H.levels[0];
+  h->perm = h->upload(L0.canon);
+  const int64_t n = L0.n;
+  h->x = h->alloc<double>(n);
+  h->r = h->alloc<double>(n);
+  h->z = h->alloc<double>(n);
+  h->p = h->alloc<double>(n);
+  h->q = h->alloc<double>(n);
+  h->bi = h->alloc<double>(n);
+  h->part = h->alloc<double>(h->nparts);
+  h->sc = h->alloc<double>(8);
+  h->flag = h->alloc<int>(1);
+  HIP_OK(hipHostMalloc((void**)&h->sc_host, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+// --------------------------------------------------------------------------
+// kernel launch helpers
+// --------------------------------------------------------------------------
+template <typename T>
+void spmv_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, const T* val,
+              const T* x, T* y, hipStream_t s) {
+  const unsigned g = nblocks(rows * lanes);
+  switch (lanes) {
+#define CASE(L) \
+  case L: dev::k_spmv<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, x, y); break;
+    CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
+#undef CASE
+  }
+  LAUNCH_OK();
+}
+
+template <typename T>
+void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, const T* val,
+               const T* y, const T* b, T* r, hipStream_t s) {
+  const unsigned g = nblocks(rows * lanes);
+  switch (lanes) {
+#define CASE(L) \
+  case L: dev::k_resid_t<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, y, b, r); break;
+    CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
+#undef CASE
+  }
+  LAUNCH_OK();
+}
+
+// r = b - A x on level L (precision T)
+template <typename T>
+void residual(DLevel& L, const T* x, const T* b, T* r, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  spmv_csr<T>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, P.g_val, x, P.y, s);
+  resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, r, s);
+}
+
+template <typename T>
+void ras(DLevel& L, const T* b, T* x, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  dev::k_ras<T><<<(unsigned)L.nagg, dev::kBlock, (L.max_nO + dev::kBlock) * sizeof(T), s>>>(
+      L.astart, L.optr, L.oidx, L.zoff, P.Zc, b, x);
+  LAUNCH_OK();
+}
+
+// x += RAS-T(r)
+template <typename T>
+void ras_t_add(DLevel& L, const T* r, T* x, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  dev::k_rast<T><<<(unsigned)L.nagg, dev::kBlock, (L.max_nw + dev::kBlock) * sizeof(T), s>>>(
+      L.astart, L.optr, L.zoff, P.Zr, r, P.tb);
+  LAUNCH_OK();
+  dev::k_gather_add<T><<<nblocks(L.n), dev::kBlock, 0, s>>>(L.n, L.cptr, L.cpos, P.tb, x);
+  LAUNCH_OK();
+}
+
+// x = B b on level l, from a zero initial guess.
+template <typename T>
+void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s) {
+  DLevel& L = h->L[l];
+  DPrec<T>& P = prec<T>(L);
+  if (L.coarsest) {
+    dev::k_dense_gemv<T><<<nblocks(L.n * 64), dev::kBlock, 0, s>>>(L.n, P.Ainv, b, x);
+    LAUNCH_OK();
+    return;
+  }
+  DLevel& C = h->L[l + 1];
+  DPrec<T>& PC = prec<T>(C);
+  ras<T>(L, b, x, s);                                     // eq:ras, x0 = 0
+  residual<T>(L, x, b, P.r, s);
+  dev::k_restrict<T><<<(unsigned)L.nagg, dev::kBlock, L.max_nw * sizeof(T), s>>>(
+      L.astart, L.cstart, L.kk, L.poff, P.Zh, P.r, PC.b);         // P^T r
+  LAUNCH_OK();
+  vcycle<T>(h, l + 1, PC.b, PC.x, s);
+  dev::k_prolong<T><<<(unsigned)L.nagg, dev::kBlock, L.max_k * sizeof(T), s>>>(
+      L.astart, L.cstart, L.kk, L.poff, P.Zh, PC.x, x);           // x += P e
+  LAUNCH_OK();
+  residual<T>(L, x, b, P.r, s);
+  ras_t_add<T>(L, P.r, x, s);                             // eq:ras-t
+}
+
+// z = B r (FP64 in and out), in the handle's precision.
+void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
+  DLevel& L0 = h->L[0];
+  if (h->precision == LSAMG_MIXED) {
+    dev::k_convert<double, float><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, r, L0.f.b);
+    LAUNCH_OK();
+    vcycle<float>(h, 0, L0.f.b, L0.f.x, s);
+    dev::k_convert<float, double><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, L0.f.x, z);
+    LAUNCH_OK();
+  } else {
+    vcycle<double>(h, 0, r, z, s);
+  }
+}
+
+// y = A x = G^T (G x), FP64, finest level
+void apply_A(lsamg_handle* h, const double* x, double* y, hipStream_t s) {
+  DLevel& L = h->L[0];
+  spmv_csr<double>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, L.d.g_val, x, L.d.y, s);
+  spmv_csr<double>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, y, s);
+}
+
+// sc[slot] = a . b  (device)
+void dot(lsamg_handle* h, int64_t n, const double* a, const double* b, int slot, hipStream_t s) {
+  const int np = (int)std::min<int64_t>(h->nparts, std::max<int64_t>(1, (n + 2047) / 2048));
+  dev::k_dot_partial<<<np, dev::kBlock, 0, s>>>(n, a, b, h->part);
+  LAUNCH_OK();
+  dev::k_sum_final<<<1, dev::kBlock, 0, s>>>(np, h->part, h->sc + slot);
+  LAUNCH_OK();
+}
+
+double read_scalar(lsamg_handle* h, int slot, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(h->sc_host + slot, h->sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return h->sc_host[slot];
+}
+
+struct DeviceGuard {
+  int old = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&old) != hipSuccess) old = -1;
+    HIP_OK(hipSetDevice(dev));
+  }
+  ~DeviceGuard() {
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+};
+
+// One PCG solve of a single right-hand side (device vectors in user numbering).
+int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
+            lsamg_stats* st) {
+  auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = h->L[0].n;
+  const unsigned gb = nblocks(n);
+  HIP_OK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
+  dev::k_nonfinite<<<gb, dev::kBlock, 0, s>>>(n, b, h->flag);
+  LAUNCH_OK();
+  int bad = 0;
+  HIP_OK(hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (bad) throw DevError{LSAMG_EBADINPUT, "non-finite entry in the right-hand side"};
+  dev::k_perm_in<<<gb, dev::kBlock, 0, s>>>(n, h->perm, b, h->bi);
+  LAUNCH_OK();
+  dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->x);
+  dev::k_copy<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->r);
+  LAUNCH_OK();
+  dot(h, n, h->bi, h->bi, 4, s);
+  const double nb = std::sqrt(read_scalar(h, 4, s));
+  int its = 0;
+  double rn = nb;
+  bool conv = (nb == 0.0);
+  if (!conv) {
+    precondition(h, h->r, h->z, s);
+    dev::k_copy<<<gb, dev::kBlock, 0, s>>>(n, h->z, h->p);
+    LAUNCH_OK();
+    dot(h, n, h->r, h->z, 0, s);
+    while (its < maxit) {
+      apply_A(h, h->p, h->q, s);
+      dot(h, n, h->p, h->q, 1, s);
+      dev::k_cg_update<<<gb, dev::kBlock, 0, s>>>(n, h->sc, h->p, h->q, h->x, h->r);
+      LAUNCH_OK();
+      dot(h, n, h->r, h->r, 3, s);
+      ++its;
+      rn = std::sqrt(read_scalar(h, 3, s));
+      if (!std::isfinite(rn)) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
+      if (rn <= tol * nb) {
+        conv = true;
+        break;
+      }
+      precondition(h, h->r, h->z, s);
+      dot(h, n, h->r, h->z, 2, s);
+      dev::k_cg_dir<<<gb, dev::kBlock, 0, s>>>(n, h->sc, h->z, h->p);
+      LAUNCH_OK();
+      HIP_OK(hipMemcpyAsync(h->sc, h->sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+  }
+  // true residual in FP64
+  apply_A(h, h->x, h->q, s);
+  dev::k_sub<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->q, h->z);
+  LAUNCH_OK();
+  dot(h, n, h->z, h->z, 7, s);
+  const double tr = std::sqrt(read_scalar(h, 7, s));
+  dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->x, x);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  if (st) {
+    st->iters = its;
+    st->converged = conv ? 1 : 0;
+    st->rel_res = nb > 0 ? rn / nb : 0.0;
+    st->true_rel_res = nb > 0 ? tr / nb : 0.0;
+    st->rho = (its > 0 && nb > 0) ? std::pow(rn / nb, 1.0 / its) : 0.0;
+    st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return conv ? LSAMG_OK : LSAMG_ENOCONV;
+}
+
+int fail_with(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lsamg_params_default(lsamg_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->max_levels = 10;
+  p->max_coarse = 2000;
+  p->block = 4;
+  p->omega_max = 400;
+  p->n_eig_fixed = 0;
+  p->kappa = 50.0;
+  p->cmin[0] = 2;
+  p->ncmin = 1;
+  p->tie_rtol = 1e-8;
+  p->tie_atol = 1e-12;
+  p->pinv_rtol = 1e-12;
+  p->thresh_margin = 1e-10;
+  p->stall_ratio = 0.9;
+  p->precision = LSAMG_FP64;
+  p->device = 0;
+  p->nthreads = 0;
+}
+
+const char* lsamg_last_error(void) { return g_last_error.c_str(); }
+
+int lsamg_setup(const lsamg_csr* G, const lsamg_params* p, lsamg_handle** out) {
+  if (!G || !p || !out) return fail_with(LSAMG_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->precision != LSAMG_FP64 && p->precision != LSAMG_MIXED)
+    return fail_with(LSAMG_EINVAL, "bad precision");
+  lsamg_handle* h = new (std::nothrow) lsamg_handle();
+  if (!h) return fail_with(LSAMG_ENOMEM, "handle allocation failed");
+  std::string msg;
+  int rc = build_hierarchy(*G, *p, h->H, msg);
+  if (rc != LSAMG_OK) {
+    delete h;
+    return fail_with(rc, msg);
+  }
+  h->precision = p->precision;
+  h->device = p->device;
+  if (p->device >= 0) {
+    try {
+      int ndev = 0;
+      if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= p->device)
+        throw DevError{LSAMG_ENODEV, "no such HIP device"};
+      DeviceGuard g(p->device);
+      upload(h);
+      HIP_OK(hipDeviceSynchronize());
+    } catch (const DevError& e) {
+      h->free_all();
+      delete h;
+      return fail_with(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+      h->free_all();
+      delete h;
+      return fail_with(LSAMG_ENOMEM, "host allocation failed during upload");
+    }
+  }
+  *out = h;
+  return LSAMG_OK;
+}
+
+int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64_t ld, double tol,
+                int32_t maxit, void* stream, lsamg_stats* stats) {
+  if (!h || nrhs < 0 || maxit < 0 || !(tol >= 0.0)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (nrhs == 0) return LSAMG_OK;
+  if (!b || !x) return fail_with(LSAMG_EINVAL, "null vector");
+  if (h->device < 0 || h->L.empty()) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  const int64_t n = h->L[0].n;
+  if (ld < n) return fail_with(LSAMG_EINVAL, "ld < n");
+  try {
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = LSAMG_OK;
+    for (int32_t c = 0; c < nrhs; ++c) {
+      int r1 = pcg_one(h, b + (size_t)c * ld, x + (size_t)c * ld, tol, maxit, s,
+                       stats ? stats + c : nullptr);
+      if (r1 != LSAMG_OK) rc = r1;
+    }
+    if (rc == LSAMG_ENOCONV) g_last_error = "maximum iterations reached";
+    return rc;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void* stream) {
+  if (!h || !x || !y) return fail_with(LSAMG_EINVAL, "null argument");
+  if (h->device < 0 || h->L.empty()) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  if (op < LSAMG_OP_A || op > LSAMG_OP_VCYCLE) return fail_with(LSAMG_EINVAL, "bad op");
+  DLevel& L0 = h->L[0];
+  if ((op == LSAMG_OP_RAS || op == LSAMG_OP_RAST) && L0.coarsest)
+    return fail_with(LSAMG_EINVAL, "single-level hierarchy has no smoother");
+  try {
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = L0.n;
+    const unsigned gb = nblocks(n);
+    dev::k_perm_in<<<gb, dev::kBlock, 0, s>>>(n, h->perm, x, h->bi);
+    LAUNCH_OK();
+    const bool mixed = h->precision == LSAMG_MIXED;
+    if (op == LSAMG_OP_A) {
+      apply_A(h, h->bi, h->z, s);
+    } else if (op == LSAMG_OP_VCYCLE) {
+      precondition(h, h->bi, h->z, s);
+    } else if (mixed) {
+      dev::k_convert<double, float><<<gb, dev::kBlock, 0, s>>>(n, h->bi, L0.f.b);
+      LAUNCH_OK();
+      if (op == LSAMG_OP_RAS) {
+        ras<float>(L0, L0.f.b, L0.f.x, s);
+      } else {
+        HIP_OK(hipMemsetAsync(L0.f.x, 0, n * sizeof(float), s));
+        ras_t_add<float>(L0, L0.f.b, L0.f.x, s);
+      }
+      dev::k_convert<float, double><<<gb, dev::kBlock, 0, s>>>(n, L0.f.x, h->z);
+      LAUNCH_OK();
+    } else {
+      if (op == LSAMG_OP_RAS) {
+        ras<double>(L0, h->bi, h->z, s);
+      } else {
+        dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->z);
+        LAUNCH_OK();
+        ras_t_add<double>(L0, h->bi, h->z, s);
+      }
+    }
+    dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->z, y);
+    LAUNCH_OK();
+    HIP_OK(hipStreamSynchronize(s));
+    return LSAMG_OK;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_set_precision(lsamg_handle* h, int32_t precision) {
+  if (!h || (precision != LSAMG_FP64 && precision != LSAMG_MIXED))
+    return fail_with(LSAMG_EINVAL, "bad argument");
+  h->precision = precision;
+  return LSAMG_OK;
+}
+
+int lsamg_info_get(const lsamg_handle* h, lsamg_info* out) {
+  if (!h || !out) return fail_with(LSAMG_EINVAL, "null argument");
+  std::memset(out, 0, sizeof(*out));
+  const Hierarchy& H = h->H;
+  out->nlevels = (int32_t)std::min<size_t>(H.levels.size(), 16);
+  out->n0 = H.levels.empty() ? 0 : H.levels[0].n;
+  out->m0 = H.m0;
+  out->setup_seconds = H.setup_seconds;
+  out->device_bytes = h->bytes;
+  double a0 = H.levels.empty() ? 1.0 : (double)std::max<int64_t>(1, H.levels[0].a_nnz);
+  double oc = 0, sc = 0;
+  for (int l = 0; l < out->nlevels; ++l) {
+    const Level& L = H.levels[l];
+    lsamg_level_info& I = out->level[l];
+    I.n = L.n;
+    I.nagg = L.nagg;
+    for (int64_t g = 0; g < L.G.ng(); ++g) {
+      const int64_t c = L.G.sptr[g + 1] - L.G.sptr[g];
+      const int r = L.G.nrows[g];
+      I.g_rows += r;
+      I.g_nnz += (r > 1) ? (int64_t)r * c - (int64_t)r * (r - 1) / 2 : c;
+    }
+    I.a_nnz = L.a_nnz;
+    oc += (double)L.a_nnz / a0;
+    if (!L.coarsest) {
+      for (int64_t a = 0; a < L.nagg; ++a)
+        I.smoother_entries += (L.astart[a + 1] - L.astart[a]) * (L.optr[a + 1] - L.optr[a]);
+      I.p_entries = (int64_t)L.Zhat.size();
+      I.block = L.block;
+      I.n_color = L.n_color;
+      I.n_mult = L.n_mult;
+      I.kmin = L.k.empty() ? 0 : *std::min_element(L.k.begin(), L.k.end());
+      I.kmax = L.k.empty() ? 0 : *std::max_element(L.k.begin(), L.k.end());
+      I.thresh = L.thresh;
+      I.hazards = L.hazards;
+      sc += (double)I.smoother_entries / a0;
+    }
+  }
+  out->op_complexity = oc;
+  out->smoother_complexity = sc;
+  return LSAMG_OK;
+}
+
+int lsamg_export_setup(lsamg_handle* h, int32_t level, lsamg_setup_view* out) {
+  if (!h || !out) return fail_with(LSAMG_EINVAL, "null argument");
+  if (level < 0 || level >= (int32_t)h->H.levels.size())
+    return fail_with(LSAMG_EINVAL, "bad level");
+  const Level& L = h->H.levels[level];
+  std::memset(out, 0, sizeof(*out));
+  out->n = L.n;
+  if (L.coarsest) return LSAMG_OK;
+  out->nagg = L.nagg;
+  h->ex_agg.assign(L.n, -1);
+  for (int64_t a = 0; a < L.nagg; ++a)
+    for (int64_t d = L.astart[a]; d < L.astart[a + 1]; ++d) h->ex_agg[L.canon[d]] = (int32_t)a;
+  h->ex_optr = L.optr;
+  h->ex_oidx.resize(L.oidx.size());
+  for (int64_t a = 0; a < L.nagg; ++a) {
+    const int64_t o0 = L.optr[a], nw = L.astart[a + 1] - L.astart[a];
+    for (int64_t o = o0; o < L.optr[a + 1]; ++o) h->ex_oidx[o] = L.canon[L.oidx[o]];
+    std::sort(h->ex_oidx.begin() + o0, h->ex_oidx.begin() + o0 + nw);
+    std::sort(h->ex_oidx.begin() + o0 + nw, h->ex_oidx.begin() + L.optr[a + 1]);
+  }
+  h->ex_k = L.k;
+  h->ex_mu = L.mu;
+  h->ex_muptr = L.muptr;
+  out->agg = h->ex_agg.data();
+  out->optr = h->ex_optr.data();
+  out->oidx = h->ex_oidx.data();
+  out->k = h->ex_k.data();
+  out->mu = h->ex_mu.data();
+  out->muptr = h->ex_muptr.data();
+  if (level == 0) {
+    h->ex_M = L.M;
+    out->M = h->ex_M.data();
+  }
+  out->block = L.block;
+  out->n_color = L.n_color;
+  out->n_mult = L.n_mult;
+  out->thresh = L.thresh;
+  return LSAMG_OK;
+}
+
+size_t lsamg_device_bytes(const lsamg_handle* h) { return h ? h->bytes : 0; }
+
+void lsamg_destroy(lsamg_handle* h) {
+  if (!h) return;
+  if (h->device >= 0) {
+    int old = -1;
+    (void)hipGetDevice(&old);
+    (void)hipSetDevice(h->device);
+    h->free_all();
+    if (old >= 0) (void)hipSetDevice(old);
+  }
+  delete h;
+}
+
+}  // extern "C"

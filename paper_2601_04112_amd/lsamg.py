@@ -1,0 +1,286 @@
+"""ctypes binding of ``liblsamg.so`` (the C-ABI declared in ``include/lsamg.h``).
+
+Argument marshalling only: every step of setup and solve runs in the native
+library (host C++ setup, HIP kernels for the solve).  PyTorch is used for
+device memory and the current HIP stream; importing this module fails loudly
+if the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblsamg.so")
+
+LSAMG_OK, LSAMG_EINVAL, LSAMG_EBADINPUT, LSAMG_ENOTSPD = 0, -1, -2, -3
+LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
+FP64, MIXED = 0, 1
+OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
+
+ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
+               -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
+
+
+class LsamgError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"lsamg {ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Csr(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("rowptr", C.POINTER(C.c_int64)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class Params(C.Structure):
+    _fields_ = [("max_levels", C.c_int32), ("max_coarse", C.c_int64),
+                ("ndim", C.c_int32), ("grid", C.c_int32 * 3),
+                ("block", C.c_int32), ("omega_max", C.c_int32),
+                ("n_eig_fixed", C.c_int32), ("kappa", C.c_double),
+                ("cmin", C.c_int32 * 8), ("ncmin", C.c_int32),
+                ("tie_rtol", C.c_double), ("tie_atol", C.c_double),
+                ("pinv_rtol", C.c_double), ("thresh_margin", C.c_double),
+                ("stall_ratio", C.c_double), ("precision", C.c_int32),
+                ("device", C.c_int32), ("nthreads", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32),
+                ("rel_res", C.c_double), ("true_rel_res", C.c_double),
+                ("rho", C.c_double), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LevelInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nagg", C.c_int64), ("g_rows", C.c_int64),
+                ("g_nnz", C.c_int64), ("a_nnz", C.c_int64),
+                ("smoother_entries", C.c_int64), ("p_entries", C.c_int64),
+                ("block", C.c_int32), ("n_color", C.c_int32),
+                ("n_mult", C.c_int32), ("kmin", C.c_int32), ("kmax", C.c_int32),
+                ("thresh", C.c_double), ("hazards", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("nlevels", C.c_int32), ("n0", C.c_int64), ("m0", C.c_int64),
+                ("setup_seconds", C.c_double), ("device_bytes", C.c_size_t),
+                ("op_complexity", C.c_double),
+                ("smoother_complexity", C.c_double),
+                ("level", LevelInfo * 16)]
+
+
+class SetupView(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nagg", C.c_int64),
+                ("agg", C.POINTER(C.c_int32)), ("optr", C.POINTER(C.c_int64)),
+                ("oidx", C.POINTER(C.c_int64)), ("k", C.POINTER(C.c_int32)),
+                ("M", C.POINTER(C.c_int32)), ("mu", C.POINTER(C.c_double)),
+                ("muptr", C.POINTER(C.c_int64)), ("block", C.c_int32),
+                ("n_color", C.c_int32), ("n_mult", C.c_int32),
+                ("thresh", C.c_double)]
+
+
+# every symbol the header declares, with its ctypes signature
+_SIGS = {
+    "lsamg_params_default": (None, [C.POINTER(Params)]),
+    "lsamg_setup": (C.c_int, [C.POINTER(Csr), C.POINTER(Params),
+                              C.POINTER(C.c_void_p)]),
+    "lsamg_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                              C.c_int64, C.c_double, C.c_int32, C.c_void_p,
+                              C.POINTER(Stats)]),
+    "lsamg_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
+    "lsamg_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lsamg_info_get": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
+    "lsamg_export_setup": (C.c_int, [C.c_void_p, C.c_int32,
+                                     C.POINTER(SetupView)]),
+    "lsamg_device_bytes": (C.c_size_t, [C.c_void_p]),
+    "lsamg_destroy": (None, [C.c_void_p]),
+    "lsamg_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the built library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run "
+                          "python -m paper_2601_04112_amd.build")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, allow=()):
+    if rc != LSAMG_OK and rc not in allow:
+        msg = load().lsamg_last_error()
+        raise LsamgError(rc, msg.decode() if msg else "")
+    return rc
+
+
+def default_params() -> Params:
+    p = Params()
+    load().lsamg_params_default(C.byref(p))
+    return p
+
+
+def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
+                max_levels: int = 10, max_coarse: int = 2000,
+                omega_max: int = 400, n_eig_fixed: int = 0,
+                kappa: float = 50.0, cmin: Sequence[int] = (2,),
+                tie_rtol: float = 1e-8, tie_atol: float = 1e-12,
+                pinv_rtol: float = 1e-12, thresh_margin: float = 1e-10,
+                stall_ratio: float = 0.9, precision: int = FP64,
+                device: int = 0, nthreads: int = 0) -> Params:
+    p = default_params()
+    p.ndim = ndim
+    for d in range(3):
+        p.grid[d] = int(grid[d]) if d < len(grid) else 1
+    p.block, p.max_levels, p.max_coarse = block, max_levels, max_coarse
+    p.omega_max, p.n_eig_fixed, p.kappa = omega_max, n_eig_fixed, kappa
+    cm = list(cmin)[:8]
+    for i, c in enumerate(cm):
+        p.cmin[i] = int(c)
+    p.ncmin = len(cm)
+    p.tie_rtol, p.tie_atol, p.pinv_rtol = tie_rtol, tie_atol, pinv_rtol
+    p.thresh_margin, p.stall_ratio = thresh_margin, stall_ratio
+    p.precision, p.device, p.nthreads = precision, device, nthreads
+    return p
+
+
+class Solver:
+    """Handle over one hierarchy: ``setup(G, params)`` then ``solve(b, tol)``."""
+
+    def __init__(self, G, ndim: int, grid: Sequence[int], **params):
+        lib = load()
+        G = G.tocsr()
+        self._rowptr = np.ascontiguousarray(G.indptr, dtype=np.int64)
+        self._col = np.ascontiguousarray(G.indices, dtype=np.int32)
+        self._val = np.ascontiguousarray(G.data, dtype=np.float64)
+        csr = Csr(G.shape[0], G.shape[1], int(self._val.size),
+                  self._rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                  self._col.ctypes.data_as(C.POINTER(C.c_int32)),
+                  self._val.ctypes.data_as(C.POINTER(C.c_double)))
+        self.params = make_params(ndim, grid, **params)
+        h = C.c_void_p()
+        _check(lib.lsamg_setup(C.byref(csr), C.byref(self.params), C.byref(h)))
+        self._h = h
+        self.n = G.shape[1]
+        self.device = self.params.device
+        del self._rowptr, self._col, self._val
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lsamg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ----------------------------------------------------------
+    @staticmethod
+    def _stream(stream):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        return C.c_void_p(stream.cuda_stream)
+
+    def _dev_vec(self, t):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda
+                and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("expected a contiguous float64 CUDA/HIP tensor")
+        return t
+
+    # -- solve ------------------------------------------------------------
+    def solve(self, b, tol: float = 1e-8, maxit: int = 1000, out=None,
+              stream=None, raise_on_noconv: bool = False):
+        """Solve A x = b.  ``b``: device float64 tensor of shape (n,) or
+        (nrhs, n) (each row one right-hand side).  Returns (x, stats)."""
+        import torch
+        b = self._dev_vec(b)
+        nrhs = 1 if b.dim() == 1 else b.shape[0]
+        if b.shape[-1] != self.n:
+            raise ValueError("length mismatch")
+        x = torch.empty_like(b) if out is None else self._dev_vec(out)
+        st = (Stats * nrhs)()
+        rc = load().lsamg_solve(self._h, C.c_void_p(b.data_ptr()),
+                                C.c_void_p(x.data_ptr()), nrhs, self.n, tol,
+                                maxit, self._stream(stream), st)
+        _check(rc, allow=() if raise_on_noconv else (LSAMG_ENOCONV,))
+        return x, [s.as_dict() for s in st]
+
+    def apply(self, op: int, x, out=None, stream=None):
+        """y = op(x) on the finest level (OP_A, OP_RAS, OP_RAST, OP_VCYCLE)."""
+        import torch
+        x = self._dev_vec(x)
+        y = torch.empty_like(x) if out is None else self._dev_vec(out)
+        _check(load().lsamg_apply_op(self._h, op, C.c_void_p(x.data_ptr()),
+                                     C.c_void_p(y.data_ptr()),
+                                     self._stream(stream)))
+        return y
+
+    def set_precision(self, precision: int):
+        _check(load().lsamg_set_precision(self._h, precision))
+
+    # -- introspection ----------------------------------------------------
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().lsamg_info_get(self._h, C.byref(inf)))
+        levels = []
+        for l in range(inf.nlevels):
+            L = inf.level[l]
+            levels.append({k: getattr(L, k) for k, _ in LevelInfo._fields_})
+        return dict(nlevels=inf.nlevels, n0=inf.n0, m0=inf.m0,
+                    setup_seconds=inf.setup_seconds,
+                    device_bytes=inf.device_bytes,
+                    op_complexity=inf.op_complexity,
+                    smoother_complexity=inf.smoother_complexity,
+                    levels=levels)
+
+    def export_setup(self, level: int) -> dict:
+        v = SetupView()
+        _check(load().lsamg_export_setup(self._h, level, C.byref(v)))
+        out = dict(n=v.n, nagg=v.nagg, block=v.block, n_color=v.n_color,
+                   n_mult=v.n_mult, thresh=v.thresh)
+        if v.nagg == 0:
+            return out
+
+        def arr(ptr, count, dt):
+            return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt).copy()
+        out["agg"] = arr(v.agg, v.n, np.int64)
+        out["optr"] = arr(v.optr, v.nagg + 1, np.int64)
+        out["oidx"] = arr(v.oidx, int(out["optr"][-1]), np.int64)
+        out["k"] = arr(v.k, v.nagg, np.int64)
+        out["muptr"] = arr(v.muptr, v.nagg + 1, np.int64)
+        out["mu"] = arr(v.mu, int(out["muptr"][-1]), np.float64)
+        if bool(v.M):
+            out["M"] = arr(v.M, self._m0(), np.int64)
+        return out
+
+    def _m0(self) -> int:
+        inf = Info()
+        _check(load().lsamg_info_get(self._h, C.byref(inf)))
+        return inf.m0
+
+
+def symbols() -> list:
+    """Names of every C-ABI entry point (all must be exported)."""
+    return list(_SIGS)
