@@ -139,6 +139,14 @@ typedef struct lsamg_setup_view {
   double thresh;
 } lsamg_setup_view;
 
+/* Per-kernel timing record (see lsamg_profile). */
+typedef struct lsamg_kprof {
+  char name[80];         /* kernel symbol, e.g. "k_gemv_wide<float, 1, false, 16>" */
+  int64_t launches;      /* launches timed since profiling was enabled       */
+  double ms;             /* summed HIP-event durations of those launches     */
+  double bytes;          /* summed algorithmic bytes of those launches       */
+} lsamg_kprof;
+
 typedef struct lsamg_handle lsamg_handle;
 
 /* Fill p with the defaults listed above (ndim/grid left zero). */
@@ -169,6 +177,19 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y,
 
 /* Select the V-cycle precision (LSAMG_FP64 or LSAMG_MIXED) for later calls. */
 int lsamg_set_precision(lsamg_handle* h, int32_t precision);
+
+/* Kernel timing.  mode 1: bracket every kernel launch of later solve /
+ * apply calls with a pair of HIP events recorded on the launch stream; if
+ * only != NULL, only launches of that kernel symbol are bracketed (the others
+ * run undisturbed).  mode 0: stop.  Recording is bounded (65536 launches).
+ * Each record also carries the launch's algorithmic bytes: the bytes the
+ * kernel must move at least (matrix entries, index lists, every distinct
+ * vector entry read once, outputs). */
+int lsamg_profile(lsamg_handle* h, int32_t mode, const char* only);
+
+/* Synchronize the recorded events and write per-kernel totals (host array
+ * out of cap entries; *count = number written).  Resets the totals. */
+int lsamg_profile_read(lsamg_handle* h, lsamg_kprof* out, int32_t cap, int32_t* count);
 
 int lsamg_info_get(const lsamg_handle* h, lsamg_info* out);
 int lsamg_export_setup(lsamg_handle* h, int32_t level, lsamg_setup_view* out);

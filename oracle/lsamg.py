@@ -239,8 +239,9 @@ def local_splitting(G: sp.csr_matrix, nz: np.ndarray, Omega: np.ndarray,
                     M: np.ndarray) -> np.ndarray:
     """``A~_i = G_{nz,Omega}^T W(nz,nz) G_{nz,Omega}``, ``W = diag(1/M)``
     (eq:local_splitting)."""
-    Gs = G[nz][:, Omega].toarray()
-    return Gs.T @ (Gs / M[nz][:, None])
+    Gs = G[nz][:, Omega]
+    W = sp.diags(1.0 / M[nz])
+    return (Gs.T @ (W @ Gs)).toarray()
 
 
 def schur_pinv(At: np.ndarray, nw: int, pinv_rtol: float) -> np.ndarray:
@@ -359,8 +360,8 @@ def _build_level(L: Level, l: int, p: Params, basis_hook):
         w, Om = L.omega[i], L.Omega[i]
         nw = len(w)
         At = local_splitting(L.G, L.nz[i], Om, L.M)
-        Gw = L.G[L.nz[i]][:, w].toarray()
-        Aww = Gw.T @ Gw                                  # G_{nz,w}^T G_{nz,w}
+        Gw = L.G[L.nz[i]][:, w]
+        Aww = (Gw.T @ Gw).toarray()                      # G_{nz,w}^T G_{nz,w}
         St = schur_pinv(At, nw, p.pinv_rtol)
         mu, U = sla.eigh(St, Aww)                        # U^T Aww U = I
         k, hazard = select_count(mu, nw, p, l, L.thresh)

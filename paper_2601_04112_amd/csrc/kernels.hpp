@@ -30,17 +30,37 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nrows, const int64_t* _
                                                  const int32_t* __restrict__ col,
                                                  const T* __restrict__ val,
                                                  const T* __restrict__ x, T* __restrict__ y) {
+  // each group of LANES threads owns two rows, processed together so that
+  // their loads overlap
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t row = gid / LANES;
+  const int64_t r0 = (gid / LANES) * 2;
   const int lane = (int)(gid % LANES);
-  if (row >= nrows) return;  // LANES divides the block, so whole groups exit
-  T s = 0;
-  for (int64_t e = ptr[row] + lane; e < ptr[row + 1]; e += LANES) s += val[e] * x[col[e]];
-  if (LANES > 1) s = wave_sum(s, LANES);
-  if (lane == 0) y[row] = s;
+  if (r0 >= nrows) return;  // LANES divides the block, so whole groups exit
+  const bool two = r0 + 1 < nrows;
+  const int64_t b0 = ptr[r0], e0 = ptr[r0 + 1];
+  const int64_t e1 = two ? ptr[r0 + 2] : e0;
+  T s0 = 0, s1 = 0;
+  int64_t p = b0 + lane, q = e0 + lane;
+  for (; p < e0 && q < e1; p += LANES, q += LANES) {
+    const T v0 = val[p], v1 = val[q];
+    const int32_t c0 = col[p], c1 = col[q];
+    s0 += v0 * x[c0];
+    s1 += v1 * x[c1];
+  }
+  for (; p < e0; p += LANES) s0 += val[p] * x[col[p]];
+  for (; q < e1; q += LANES) s1 += val[q] * x[col[q]];
+  if (LANES > 1) {
+    s0 = wave_sum(s0, LANES);
+    s1 = wave_sum(s1, LANES);
+  }
+  if (lane == 0) {
+    y[r0] = s0;
+    if (two) y[r0 + 1] = s1;
+  }
 }
 
 // r = b - G^T y  (rows of G^T = unknowns); G^T stored as CSR by unknown.
+// b == nullptr gives r = G^T y (no subtraction, no sign change).
 template <typename T, int LANES>
 __global__ void __launch_bounds__(kBlock) k_resid_t(int64_t n, const int64_t* __restrict__ ptr,
                                                     const int32_t* __restrict__ col,
@@ -48,106 +68,176 @@ __global__ void __launch_bounds__(kBlock) k_resid_t(int64_t n, const int64_t* __
                                                     const T* __restrict__ y,
                                                     const T* __restrict__ b, T* __restrict__ r) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t row = gid / LANES;
+  const int64_t r0 = (gid / LANES) * 2;
   const int lane = (int)(gid % LANES);
-  if (row >= n) return;
-  T s = 0;
-  for (int64_t e = ptr[row] + lane; e < ptr[row + 1]; e += LANES) s += val[e] * y[col[e]];
-  if (LANES > 1) s = wave_sum(s, LANES);
-  if (lane == 0) r[row] = (b ? b[row] : T(0)) - s;
-}
-
-// ---------------------------------------------------------------------------
-// RAS (eq:ras) from a zero initial guess: x(omega_i) = Z_i b(Omega_i), with
-// Z_i = A_i^{-1}(omega_i, Omega_i) stored column-major (Omega-major) so that
-// consecutive threads read consecutive rows of one column.  One workgroup per
-// aggregate; b(Omega_i) is gathered into LDS first.  The Boolean partition
-// of unity makes every unknown written by exactly one workgroup.
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_ras(const int64_t* __restrict__ astart,
-                                                const int64_t* __restrict__ optr,
-                                                const int32_t* __restrict__ oidx,
-                                                const int64_t* __restrict__ zoff,
-                                                const T* __restrict__ Zc, const T* __restrict__ b,
-                                                T* __restrict__ x) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sb = reinterpret_cast<T*>(smem_raw);
-  const int64_t a = blockIdx.x;
-  const int64_t w0 = astart[a];
-  const int nw = (int)(astart[a + 1] - w0);
-  const int64_t o0 = optr[a];
-  const int nO = (int)(optr[a + 1] - o0);
-  T* part = sb + nO;  // kBlock partial sums
-  for (int c = threadIdx.x; c < nO; c += kBlock) sb[c] = b[oidx[o0 + c]];
-  __syncthreads();
-  const T* Z = Zc + zoff[a];
-  int nwp = 1;
-  while (nwp < nw) nwp <<= 1;
-  if (nwp <= kBlock) {
-    const int groups = kBlock / nwp;
-    const int p = threadIdx.x % nwp, g = threadIdx.x / nwp;
-    T s = 0;
-    if (p < nw)
-      for (int c = g; c < nO; c += groups) s += Z[(int64_t)c * nw + p] * sb[c];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < nw) {
-      T t = 0;
-      for (int gg = 0; gg < groups; ++gg) t += part[gg * nwp + threadIdx.x];
-      x[w0 + threadIdx.x] = t;
-    }
-  } else {
-    for (int p = threadIdx.x; p < nw; p += kBlock) {
-      T s = 0;
-      for (int c = 0; c < nO; ++c) s += Z[(int64_t)c * nw + p] * sb[c];
-      x[w0 + p] = s;
-    }
+  if (r0 >= n) return;
+  const bool two = r0 + 1 < n;
+  const int64_t b0 = ptr[r0], e0 = ptr[r0 + 1];
+  const int64_t e1 = two ? ptr[r0 + 2] : e0;
+  T s0 = 0, s1 = 0;
+  int64_t p = b0 + lane, q = e0 + lane;
+  for (; p < e0 && q < e1; p += LANES, q += LANES) {
+    const T v0 = val[p], v1 = val[q];
+    const int32_t c0 = col[p], c1 = col[q];
+    s0 += v0 * y[c0];
+    s1 += v1 * y[c1];
+  }
+  for (; p < e0; p += LANES) s0 += val[p] * y[col[p]];
+  for (; q < e1; q += LANES) s1 += val[q] * y[col[q]];
+  if (LANES > 1) {
+    s0 = wave_sum(s0, LANES);
+    s1 = wave_sum(s1, LANES);
+  }
+  if (lane == 0) {
+    r[r0] = b ? b[r0] - s0 : s0;
+    if (two) r[r0 + 1] = b ? b[r0 + 1] - s1 : s1;
   }
 }
 
-// RAS-T (eq:ras-t), first half: t_i = Z_i^T r(omega_i) = A_i^{-1}(Omega_i,
-// omega_i) r(omega_i), with Z_i stored row-major (omega-major).  The |Omega_i|
-// values are written to the staging buffer tb at optr[i]; k_gather_add then
-// adds them into x in a fixed order (deterministic, no atomics).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_rast(const int64_t* __restrict__ astart,
-                                                 const int64_t* __restrict__ optr,
-                                                 const int64_t* __restrict__ zoff,
-                                                 const T* __restrict__ Zr,
-                                                 const T* __restrict__ r, T* __restrict__ tb) {
+// ---------------------------------------------------------------------------
+// Batched small dense GEMV over aggregates: the smoothers and the transfer
+// operators of the V-cycle are all of the form
+//
+//     out[obase_a + j]  (=|+=)  sum_l  M_a[l][j] * in_a[l],   j < lj_a, l < ll_a
+//
+// with M_a stored so that j is contiguous (M_a[l][j] at moff_a + l*lj_a + j):
+//   RAS    (eq:ras):   M = A_i^{-1}(omega_i, Omega_i) column-major, j = row of
+//                      omega_i, l = Omega_i entry, in = b gathered via Omega_i
+//   RAS-T  (eq:ras-t): M = the same block row-major, j = Omega_i entry,
+//                      l = row of omega_i, in = r(omega_i), out = staging tb
+//   P^T    (eq:mg-p):  M = Zhat_i row-major, j = coarse unknown, l = row
+//   P      (eq:mg-p):  M = Zhat_i column-major, j = row, l = coarse unknown,
+//                      out += ; the input may add the coarse level's staged
+//                      RAS-T contributions on the fly (IN_TB)
+// Lanes run along j (coalesced loads), the loop runs along l, and every
+// output is reduced in a fixed order (deterministic, no atomics).
+// ---------------------------------------------------------------------------
+enum { IN_DIRECT = 0, IN_GATHER = 1, IN_TB = 2 };
+
+struct GemvOp {
+  const int64_t* moff;   // [nagg] offset of M_a
+  const int32_t* lj;     // [nagg] output length (contiguous dimension)
+  const int32_t* ll;     // [nagg] input length (loop dimension)
+  const int64_t* ibase;  // [nagg] input base (index-list base for IN_GATHER)
+  const int64_t* obase;  // [nagg] output base
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ T load_in(const T* __restrict__ in, int64_t i,
+                                     const int32_t* __restrict__ gidx,
+                                     const int64_t* __restrict__ cptr,
+                                     const int64_t* __restrict__ cpos,
+                                     const T* __restrict__ tb) {
+  if (MODE == IN_GATHER) return in[gidx[i]];
+  if (MODE == IN_TB) {
+    T v = in[i];
+    for (int64_t e = cptr[i]; e < cptr[i + 1]; ++e) v += tb[cpos[e]];
+    return v;
+  }
+  return in[i];
+}
+
+// Narrow form (every lj_a <= G <= 64): one wavefront per aggregate, the
+// wavefront split into 64/G lane groups that share the loop over l; four
+// aggregates per 256-thread workgroup.  LDS: 4 * lmax * sizeof(T).
+template <typename T, int MODE, bool ADD, int G>
+__global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op, int lmax,
+                                                        const int32_t* __restrict__ gidx,
+                                                        const int64_t* __restrict__ cptr,
+                                                        const int64_t* __restrict__ cpos,
+                                                        const T* __restrict__ tb,
+                                                        const T* __restrict__ M,
+                                                        const T* __restrict__ in,
+                                                        T* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
-  T* sr = reinterpret_cast<T*>(smem_raw);
-  const int64_t a = blockIdx.x;
-  const int64_t w0 = astart[a];
-  const int nw = (int)(astart[a + 1] - w0);
-  const int64_t o0 = optr[a];
-  const int nO = (int)(optr[a + 1] - o0);
-  T* part = sr + nw;
-  for (int p = threadIdx.x; p < nw; p += kBlock) sr[p] = r[w0 + p];
+  constexpr int S = 64 / G;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  const bool valid = a < nagg;
+  T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * lmax;
+  int nj = 0, nl = 0;
+  if (valid) {
+    nj = op.lj[a];
+    nl = op.ll[a];
+    const int64_t ib = op.ibase[a];
+    for (int l = lane; l < nl; l += 64) sv[l] = load_in<T, MODE>(in, ib + l, gidx, cptr, cpos, tb);
+  }
   __syncthreads();
-  const T* Z = Zr + zoff[a];
-  int nOp = 1;
-  while (nOp < nO) nOp <<= 1;
-  if (nOp <= kBlock) {
-    const int groups = kBlock / nOp;
-    const int c = threadIdx.x % nOp, g = threadIdx.x / nOp;
-    T s = 0;
-    if (c < nO)
-      for (int p = g; p < nw; p += groups) s += Z[(int64_t)p * nO + c] * sr[p];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    if (threadIdx.x < nO) {
-      T t = 0;
-      for (int gg = 0; gg < groups; ++gg) t += part[gg * nOp + threadIdx.x];
-      tb[o0 + threadIdx.x] = t;
+  if (!valid) return;
+  const int s = lane / G, j = lane % G;
+  T acc = 0;
+  if (j < nj) {
+    const T* m = M + op.moff[a] + j;
+    T a1 = 0, a2 = 0, a3 = 0;
+    int l = s;
+    for (; l + 3 * S < nl; l += 4 * S) {   // four independent loads in flight
+      const T m0 = m[(int64_t)l * nj], m1 = m[(int64_t)(l + S) * nj];
+      const T m2 = m[(int64_t)(l + 2 * S) * nj], m3 = m[(int64_t)(l + 3 * S) * nj];
+      acc += m0 * sv[l];
+      a1 += m1 * sv[l + S];
+      a2 += m2 * sv[l + 2 * S];
+      a3 += m3 * sv[l + 3 * S];
     }
-  } else {
-    for (int c = threadIdx.x; c < nO; c += kBlock) {
-      T s = 0;
-      for (int p = 0; p < nw; ++p) s += Z[(int64_t)p * nO + c] * sr[p];
-      tb[o0 + c] = s;
+    for (; l < nl; l += S) acc += m[(int64_t)l * nj] * sv[l];
+    acc = (acc + a1) + (a2 + a3);
+  }
+  for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  if (s == 0 && j < nj) {
+    T* dst = out + op.obase[a] + j;
+    *dst = ADD ? *dst + acc : acc;
+  }
+}
+
+// Wide form: one workgroup of NW wavefronts per task (aggregate a, 64-wide
+// slice j0 of its outputs); the waves split the loop over l and their
+// partial sums are added in wave order through LDS.
+// LDS: (lmax + NW*64) * sizeof(T).
+template <typename T, int MODE, bool ADD, int NW>
+__global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict__ task_a,
+                                                       const int32_t* __restrict__ task_j0,
+                                                       GemvOp op, int lmax,
+                                                       const int32_t* __restrict__ gidx,
+                                                       const int64_t* __restrict__ cptr,
+                                                       const int64_t* __restrict__ cpos,
+                                                       const T* __restrict__ tb,
+                                                       const T* __restrict__ M,
+                                                       const T* __restrict__ in,
+                                                       T* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sv = reinterpret_cast<T*>(smem_raw);
+  T* part = sv + lmax;
+  const int64_t a = task_a[blockIdx.x];
+  const int j0 = task_j0[blockIdx.x];
+  const int nj = op.lj[a], nl = op.ll[a];
+  const int64_t ib = op.ibase[a];
+  for (int l = threadIdx.x; l < nl; l += NW * 64)
+    sv[l] = load_in<T, MODE>(in, ib + l, gidx, cptr, cpos, tb);
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = j0 + lane;
+  T acc = 0;
+  if (j < nj) {
+    const T* m = M + op.moff[a] + j;
+    T a1 = 0, a2 = 0, a3 = 0;
+    int l = wave;
+    for (; l + 3 * NW < nl; l += 4 * NW) {  // four independent loads in flight
+      const T m0 = m[(int64_t)l * nj], m1 = m[(int64_t)(l + NW) * nj];
+      const T m2 = m[(int64_t)(l + 2 * NW) * nj], m3 = m[(int64_t)(l + 3 * NW) * nj];
+      acc += m0 * sv[l];
+      a1 += m1 * sv[l + NW];
+      a2 += m2 * sv[l + 2 * NW];
+      a3 += m3 * sv[l + 3 * NW];
     }
+    for (; l < nl; l += NW) acc += m[(int64_t)l * nj] * sv[l];
+    acc = (acc + a1) + (a2 + a3);
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  if (wave == 0 && j < nj) {
+    T t = part[lane];
+    for (int w = 1; w < NW; ++w) t += part[w * 64 + lane];
+    T* dst = out + op.obase[a] + j;
+    *dst = ADD ? *dst + t : t;
   }
 }
 
@@ -165,59 +255,6 @@ __global__ void __launch_bounds__(kBlock) k_gather_add(int64_t n, const int64_t*
   x[j] = s;
 }
 
-// ---------------------------------------------------------------------------
-// Restriction r_c = P^T r and prolongation x += P e (eq:mg-p, eq:cgc): P is
-// block diagonal, block i = Zhat_i (|omega_i| x k_i, row-major); the coarse
-// unknowns of aggregate i are [cstart[i], cstart[i] + k_i) (not ordered by i).
-// ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_restrict(const int64_t* __restrict__ astart,
-                                                     const int64_t* __restrict__ cstart,
-                                                     const int32_t* __restrict__ kk,
-                                                     const int64_t* __restrict__ poff,
-                                                     const T* __restrict__ Zh,
-                                                     const T* __restrict__ r, T* __restrict__ rc) {
-  extern __shared__ unsigned char smem_raw[];
-  T* sr = reinterpret_cast<T*>(smem_raw);
-  const int64_t a = blockIdx.x;
-  const int64_t w0 = astart[a];
-  const int nw = (int)(astart[a + 1] - w0);
-  const int64_t c0 = cstart[a];
-  const int k = kk[a];
-  for (int p = threadIdx.x; p < nw; p += kBlock) sr[p] = r[w0 + p];
-  __syncthreads();
-  const T* Z = Zh + poff[a];
-  for (int s = threadIdx.x; s < k; s += kBlock) {
-    T acc = 0;
-    for (int p = 0; p < nw; ++p) acc += Z[(int64_t)p * k + s] * sr[p];
-    rc[c0 + s] = acc;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_prolong(const int64_t* __restrict__ astart,
-                                                    const int64_t* __restrict__ cstart,
-                                                    const int32_t* __restrict__ kk,
-                                                    const int64_t* __restrict__ poff,
-                                                    const T* __restrict__ Zh,
-                                                    const T* __restrict__ e, T* __restrict__ x) {
-  extern __shared__ unsigned char smem_raw[];
-  T* se = reinterpret_cast<T*>(smem_raw);
-  const int64_t a = blockIdx.x;
-  const int64_t w0 = astart[a];
-  const int nw = (int)(astart[a + 1] - w0);
-  const int64_t c0 = cstart[a];
-  const int k = kk[a];
-  for (int s = threadIdx.x; s < k; s += kBlock) se[s] = e[c0 + s];
-  __syncthreads();
-  const T* Z = Zh + poff[a];
-  for (int p = threadIdx.x; p < nw; p += kBlock) {
-    T acc = 0;
-    for (int s = 0; s < k; ++s) acc += Z[(int64_t)p * k + s] * se[s];
-    x[w0 + p] += acc;
-  }
-}
-
 // Coarsest level: e = A_L^{-1} r with the dense inverse (row-major); one
 // wavefront per row.
 template <typename T>
@@ -232,6 +269,138 @@ __global__ void __launch_bounds__(kBlock) k_dense_gemv(int64_t n, const T* __res
   for (int64_t j = lane; j < n; j += 64) s += mr[j] * r[j];
   s = wave_sum(s, 64);
   if (lane == 0) e[row] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Fused FP64 CG kernels.  A dot product is produced as one partial sum per
+// workgroup (part[blockIdx.x]); the kernel that needs the scalar re-adds the
+// partials itself, every workgroup in the same fixed order, so the value is
+// identical everywhere and deterministic, with no atomics and no fences.
+// All CG kernels run on the same grid of np = gridDim.x <= 1024 workgroups.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double sm[kBlock / 64];
+  __shared__ double tot;
+  v = wave_sum(v, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0;
+    for (int w = 0; w < kBlock / 64; ++w) s += sm[w];
+    tot = s;
+  }
+  __syncthreads();
+  return tot;
+}
+
+// sum of np partials, same value in every workgroup and thread
+__device__ __forceinline__ double sum_parts(const double* __restrict__ part, int np) {
+  double s = 0;
+  for (int i = threadIdx.x; i < np; i += kBlock) s += part[i];
+  return block_sum(s);
+}
+
+__device__ __forceinline__ void write_part(double v, double* __restrict__ part) {
+  v = block_sum(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = v;
+}
+
+// partials of a . b
+__global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const double* __restrict__ a,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ part) {
+  double v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    v += a[i] * b[i];
+  write_part(v, part);
+}
+
+// q = G^T y (finest level, CSR of G^T, LANES threads per row) and partials
+// of p . q
+template <int LANES>
+__global__ void __launch_bounds__(kBlock) k_cg_apq(int64_t n, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const double* __restrict__ val,
+                                                   const double* __restrict__ y,
+                                                   const double* __restrict__ p,
+                                                   double* __restrict__ q,
+                                                   double* __restrict__ part) {
+  const int lane = threadIdx.x % LANES;
+  const int64_t groups = (int64_t)gridDim.x * (kBlock / LANES);
+  double v = 0;
+  for (int64_t row = (int64_t)blockIdx.x * (kBlock / LANES) + threadIdx.x / LANES; row < n;
+       row += groups) {
+    double s = 0;
+    for (int64_t e = ptr[row] + lane; e < ptr[row + 1]; e += LANES) s += val[e] * y[col[e]];
+    if (LANES > 1) s = wave_sum(s, LANES);
+    if (lane == 0) {
+      q[row] = s;
+      v += s * p[row];
+    }
+  }
+  write_part(v, part);
+}
+
+// alpha = rho / pq from the partials; x += alpha p; r -= alpha q;
+// r32 = (float) r (if given); partials of r . r
+__global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* __restrict__ rz_part,
+                                                      const double* __restrict__ pq_part,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      float* __restrict__ r32,
+                                                      double* __restrict__ rr_part) {
+  const int np = gridDim.x;
+  const double alpha = sum_parts(rz_part, np) / sum_parts(pq_part, np);
+  double v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    if (r32) r32[i] = (float)ri;
+    v += ri * ri;
+  }
+  write_part(v, rr_part);
+}
+
+// z = xv + staged RAS-T contributions (the finest level's V-cycle output in
+// the V-cycle precision T, widened to FP64); partials of r . z
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_cg_z(int64_t n, const T* __restrict__ xv,
+                                                 const int64_t* __restrict__ cptr,
+                                                 const int64_t* __restrict__ cpos,
+                                                 const T* __restrict__ tb,
+                                                 const double* __restrict__ r,
+                                                 double* __restrict__ z,
+                                                 double* __restrict__ rz_part) {
+  double v = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    T s = xv[i];
+    if (cptr)
+      for (int64_t e = cptr[i]; e < cptr[i + 1]; ++e) s += tb[cpos[e]];
+    const double zi = (double)s;
+    z[i] = zi;
+    v += r[i] * zi;
+  }
+  write_part(v, rz_part);
+}
+
+// p = z + beta p with beta = rho_new / rho_old (rho_old_part == nullptr: p = z)
+__global__ void __launch_bounds__(kBlock) k_cg_dir(int64_t n,
+                                                   const double* __restrict__ rz_new,
+                                                   const double* __restrict__ rz_old,
+                                                   const double* __restrict__ z,
+                                                   double* __restrict__ p) {
+  const int np = gridDim.x;
+  const double beta = rz_old ? sum_parts(rz_new, np) / sum_parts(rz_old, np) : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    p[i] = z[i] + beta * p[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -268,29 +437,6 @@ __global__ void __launch_bounds__(kBlock) k_sum_final(int nparts, const double* 
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = sm[0];
-}
-
-// x += alpha p ; r -= alpha q   with alpha = s[0] / s[1] read on the device
-__global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* __restrict__ sc,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ q,
-                                                      double* __restrict__ x,
-                                                      double* __restrict__ r) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double alpha = sc[0] / sc[1];
-  x[i] += alpha * p[i];
-  r[i] -= alpha * q[i];
-}
-
-// p = z + beta p   with beta = s[2] / s[0]
-__global__ void __launch_bounds__(kBlock) k_cg_dir(int64_t n, const double* __restrict__ sc,
-                                                   const double* __restrict__ z,
-                                                   double* __restrict__ p) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i >= n) return;
-  const double beta = sc[2] / sc[0];
-  p[i] = z[i] + beta * p[i];
 }
 
 template <typename Ti, typename To>
@@ -333,13 +479,6 @@ __global__ void __launch_bounds__(kBlock) k_sub(int64_t n, const double* __restr
 __global__ void __launch_bounds__(kBlock) k_fill(int64_t n, double v, double* __restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < n) b[i] = v;
-}
-
-// count of non-finite entries (for input validation)
-__global__ void __launch_bounds__(kBlock) k_nonfinite(int64_t n, const double* __restrict__ a,
-                                                      int* __restrict__ flag) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n && !isfinite(a[i])) atomicOr(flag, 1);
 }
 
 }  // namespace dev

@@ -49,7 +49,8 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* gt_val = nullptr;    // G_l^T values (CSR by unknown)
   T* Zc = nullptr;        // Z_i column-major (RAS)
   T* Zr = nullptr;        // Z_i row-major (RAS-T)
-  T* Zh = nullptr;        // Zhat_i row-major (P)
+  T* Zh = nullptr;        // Zhat_i row-major (restriction P^T)
+  T* ZhT = nullptr;       // Zhat_i column-major (prolongation P)
   T* Ainv = nullptr;      // coarsest inverse
   T* x = nullptr;         // V-cycle output at this level
   T* b = nullptr;         // V-cycle input at this level
@@ -58,7 +59,23 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* tb = nullptr;        // RAS-T staging, sum |Omega_i|
 };
 
+// Launch plan of one batched-GEMV operator on one level.
+struct GemvPlan {
+  dev::GemvOp op{};
+  int64_t nagg = 0;
+  int lmax = 0;        // largest input length
+  int G = 0;           // narrow form lane-group width (0: wide form)
+  int NW = 4;          // wide form: wavefronts per workgroup
+  int64_t ntask = 0;   // wide form: tasks (aggregate, 64-wide output slice)
+  // algorithmic size of one application: matrix entries, distinct input
+  // entries, gathered index entries, outputs
+  int64_t mat = 0, in_u = 0, idx = 0, out = 0;
+  int32_t* task_a = nullptr;
+  int32_t* task_j0 = nullptr;
+};
+
 struct DLevel {
+  GemvPlan ras, rast, rst, pro;
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
   int lanes_g = 1, lanes_gt = 1;
@@ -88,9 +105,63 @@ int lanes_for(double avg) {
   return l;
 }
 
+// Kernel timing with HIP events (lsamg_profile).
+struct Profiler {
+  bool on = false;
+  std::string only;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    std::string name;
+    double bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  bool want(const std::string& nm) const { return on && (only.empty() || nm == only); }
+};
+
+thread_local Profiler* g_prof = nullptr;
+
+inline Profiler* prof_active() { return (g_prof && g_prof->on) ? g_prof : nullptr; }
+
+struct ProfScope {
+  Profiler* p = nullptr;
+  size_t rec = 0;
+  hipStream_t s;
+  ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t st) : s(st) {
+    if (!pp || !pp->want(name) || pp->used + 2 > pp->pool.size()) return;
+    p = pp;
+    hipEvent_t a = pp->pool[pp->used++], b = pp->pool[pp->used++];
+    pp->recs.push_back(Profiler::Rec{name, bytes, a, b});
+    rec = pp->recs.size() - 1;
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (p) (void)hipEventRecord(p->recs[rec].b, s);
+  }
+};
+
+// PROF(name-expression, bytes-expression, stream): the expressions are only
+// evaluated while profiling is on.
+#define PROF(NAME, BYTES, S)          \
+  Profiler* pp_ = prof_active();      \
+  ProfScope ps_(pp_, pp_ ? std::string(NAME) : std::string(), pp_ ? (double)(BYTES) : 0.0, S)
+
+template <typename T>
+const char* tname();
+template <>
+const char* tname<double>() { return "double"; }
+template <>
+const char* tname<float>() { return "float"; }
+
+inline std::string kname(const char* base, const std::string& args) {
+  return std::string(base) + "<" + args + ">";
+}
+
 }  // namespace
 
 struct lsamg_handle {
+  Profiler prof;
   Hierarchy H;
   int device = -1;
   int precision = LSAMG_FP64;
@@ -100,9 +171,12 @@ struct lsamg_handle {
   int64_t* perm = nullptr;          // internal -> user numbering (finest level)
   double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr,
          *bi = nullptr, *part = nullptr, *sc = nullptr;
-  int* flag = nullptr;
+  // per-workgroup partial sums of the CG dot products (red_blocks(n) each)
+  double *p_pq = nullptr, *p_rr = nullptr, *p_rz[2] = {nullptr, nullptr}, *p_tmp = nullptr;
+  int red_np = 1;
   double* sc_host = nullptr;         // pinned
   int nparts = 1024;
+  hipEvent_t ev_rr[2] = {nullptr, nullptr};
   // export buffers
   std::vector<int32_t> ex_agg, ex_k, ex_M;
   std::vector<int64_t> ex_optr, ex_oidx, ex_muptr;
@@ -130,6 +204,11 @@ struct lsamg_handle {
     return upload(t);
   }
   void free_all() {
+    for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
+    for (auto& e : ev_rr)
+      if (e) (void)hipEventDestroy(e);
+    ev_rr[0] = ev_rr[1] = nullptr;
+    prof.pool.clear();
     for (void* ptr : allocs) (void)hipFree(ptr);
     allocs.clear();
     if (sc_host) (void)hipHostFree(sc_host);
@@ -141,7 +220,7 @@ struct lsamg_handle {
 namespace {
 
 // Build the device image of one level from the host hierarchy.
-void upload_level(lsamg_handle* h, const Level& HL, DLevel& D) {
+void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.n = HL.n;
   D.coarsest = HL.coarsest;
   // CSR of G_l: finest rows as given; coarse groups store the upper
@@ -182,14 +261,18 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D) {
   }
   D.lanes_g = lanes_for((double)D.nnz / std::max<int64_t>(1, D.nrows));
   D.lanes_gt = lanes_for((double)D.nnz / std::max<int64_t>(1, D.n));
-  D.g_ptr = h->upload(gp);
-  D.g_col = h->upload(gc);
-  D.gt_ptr = h->upload(tp);
-  D.gt_col = h->upload(tc);
-  D.d.g_val = h->upload_f<double>(gv);
-  D.f.g_val = h->upload_f<float>(gv);
-  D.d.gt_val = h->upload_f<double>(tv);
-  D.f.gt_val = h->upload_f<float>(tv);
+  // a coarse coarsest level is solved densely and needs no G; the finest
+  // level always keeps G (the outer CG applies A = G^T G there)
+  if (!HL.coarsest || finest) {
+    D.g_ptr = h->upload(gp);
+    D.g_col = h->upload(gc);
+    D.gt_ptr = h->upload(tp);
+    D.gt_col = h->upload(tc);
+    D.d.g_val = h->upload_f<double>(gv);
+    D.f.g_val = h->upload_f<float>(gv);
+    D.d.gt_val = h->upload_f<double>(tv);
+    D.f.gt_val = h->upload_f<float>(tv);
+  }
   D.d.x = h->alloc<double>(D.n);
   D.d.b = h->alloc<double>(D.n);
   D.d.r = h->alloc<double>(D.n);
@@ -246,6 +329,70 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D) {
   D.f.Zc = h->upload_f<float>(Zc);
   D.d.Zh = h->upload_f<double>(HL.Zhat);
   D.f.Zh = h->upload_f<float>(HL.Zhat);
+  std::vector<double> ZhT(HL.Zhat.size());
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    const int nw = (int)(HL.astart[a + 1] - HL.astart[a]), k = HL.k[a];
+    const double* zr = HL.Zhat.data() + HL.poff[a];
+    double* zc = ZhT.data() + HL.poff[a];
+    for (int p = 0; p < nw; ++p)
+      for (int t = 0; t < k; ++t) zc[(size_t)t * nw + p] = zr[(size_t)p * k + t];
+  }
+  D.d.ZhT = h->upload_f<double>(ZhT);
+  D.f.ZhT = h->upload_f<float>(ZhT);
+  std::vector<int32_t> nw(HL.nagg), nO(HL.nagg), kk(HL.k.begin(), HL.k.end());
+  std::vector<int64_t> w0(HL.astart.begin(), HL.astart.end() - 1),
+      o0(HL.optr.begin(), HL.optr.end() - 1), z0(HL.zoff.begin(), HL.zoff.end() - 1),
+      p0(HL.poff.begin(), HL.poff.end() - 1), c0(HL.cstart.begin(), HL.cstart.end() - 1);
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    nw[a] = (int32_t)(HL.astart[a + 1] - HL.astart[a]);
+    nO[a] = (int32_t)(HL.optr[a + 1] - HL.optr[a]);
+  }
+  int32_t* d_nw = h->upload(nw);
+  int32_t* d_nO = h->upload(nO);
+  int32_t* d_k = h->upload(kk);
+  int64_t* d_w0 = h->upload(w0);
+  int64_t* d_o0 = h->upload(o0);
+  int64_t* d_z0 = h->upload(z0);
+  int64_t* d_p0 = h->upload(p0);
+  int64_t* d_c0 = h->upload(c0);
+  auto plan = [&](GemvPlan& P, const std::vector<int32_t>& lj, const std::vector<int32_t>& ll,
+                  int32_t* dlj, int32_t* dll, int64_t* moff, int64_t* ib, int64_t* ob,
+                  int64_t in_unique, bool gathered) {
+    P.op = dev::GemvOp{moff, dlj, dll, ib, ob};
+    P.nagg = HL.nagg;
+    P.mat = P.out = 0;
+    for (int64_t a = 0; a < HL.nagg; ++a) {
+      P.mat += (int64_t)lj[a] * ll[a];
+      P.out += lj[a];
+      if (gathered) P.idx += ll[a];
+    }
+    P.in_u = in_unique;
+    P.lmax = *std::max_element(ll.begin(), ll.end());
+    const int ljmax = *std::max_element(lj.begin(), lj.end());
+    if (ljmax <= 64) {
+      int g = 1;
+      while (g < ljmax) g <<= 1;
+      P.G = g;
+      return;
+    }
+    std::vector<int32_t> ta, tj;
+    for (int64_t a = 0; a < HL.nagg; ++a)
+      for (int j = 0; j < lj[a]; j += 64) {
+        ta.push_back((int32_t)a);
+        tj.push_back(j);
+      }
+    P.G = 0;
+    P.ntask = (int64_t)ta.size();
+    P.NW = 4;
+    while (P.NW < 16 && P.ntask * P.NW < 4096) P.NW <<= 1;
+    P.task_a = h->upload(ta);
+    P.task_j0 = h->upload(tj);
+  };
+  const int64_t ncoarse = HL.cstart[HL.nagg];
+  plan(D.ras, nw, nO, d_nw, d_nO, d_z0, d_o0, d_w0, D.n, true);
+  plan(D.rast, nO, nw, d_nO, d_nw, d_z0, d_w0, d_o0, D.n, false);
+  plan(D.rst, kk, nw, d_k, d_nw, d_p0, d_w0, d_c0, D.n, false);
+  plan(D.pro, nw, kk, d_nw, d_k, d_p0, d_c0, d_w0, ncoarse, false);
   D.d.tb = h->alloc<double>(D.ntb);
   D.f.tb = h->alloc<float>(D.ntb);
 }
@@ -253,7 +400,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D) {
 void upload(lsamg_handle* h) {
   HIP_OK(hipSetDevice(h->device));
   h->L.resize(h->H.levels.size());
-  for (size_t l = 0; l < h->H.levels.size(); ++l) upload_level(h, h->H.levels[l], h->L[l]);
+  for (size_t l = 0; l < h->H.levels.size(); ++l) upload_level(h, h->H.levels[l], h->L[l], l == 0);
   const Level& L0 = h->H.levels[0];
   h->perm = h->upload(L0.canon);
   const int64_t n = L0.n;
@@ -265,8 +412,14 @@ void upload(lsamg_handle* h) {
   h->bi = h->alloc<double>(n);
   h->part = h->alloc<double>(h->nparts);
   h->sc = h->alloc<double>(8);
-  h->flag = h->alloc<int>(1);
-  HIP_OK(hipHostMalloc((void**)&h->sc_host, 8 * sizeof(double), hipHostMallocDefault));
+  h->red_np = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + dev::kBlock - 1) / dev::kBlock));
+  h->p_pq = h->alloc<double>(h->red_np);
+  h->p_rr = h->alloc<double>(h->red_np);
+  h->p_rz[0] = h->alloc<double>(h->red_np);
+  h->p_rz[1] = h->alloc<double>(h->red_np);
+  h->p_tmp = h->alloc<double>(h->red_np);
+  HIP_OK(hipHostMalloc((void**)&h->sc_host, 3 * 1024 * sizeof(double), hipHostMallocDefault));
+  for (auto& e : h->ev_rr) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
 // --------------------------------------------------------------------------
@@ -274,8 +427,10 @@ void upload(lsamg_handle* h) {
 // --------------------------------------------------------------------------
 template <typename T>
 void spmv_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, const T* val,
-              const T* x, T* y, hipStream_t s) {
-  const unsigned g = nblocks(rows * lanes);
+              const T* x, T* y, hipStream_t s, int64_t nnz, int64_t ncols) {
+  const unsigned g = nblocks((rows + 1) / 2 * lanes);
+  PROF(kname("k_spmv", std::string(tname<T>()) + ", " + std::to_string(lanes)),
+       nnz * (sizeof(T) + 4) + 8 * (rows + 1) + sizeof(T) * (ncols + rows), s);
   switch (lanes) {
 #define CASE(L) \
   case L: dev::k_spmv<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, x, y); break;
@@ -287,8 +442,10 @@ void spmv_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, c
 
 template <typename T>
 void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, const T* val,
-               const T* y, const T* b, T* r, hipStream_t s) {
-  const unsigned g = nblocks(rows * lanes);
+               const T* y, const T* b, T* r, hipStream_t s, int64_t nnz, int64_t ny) {
+  const unsigned g = nblocks((rows + 1) / 2 * lanes);
+  PROF(kname("k_resid_t", std::string(tname<T>()) + ", " + std::to_string(lanes)),
+       nnz * (sizeof(T) + 4) + 8 * (rows + 1) + sizeof(T) * (ny + 2 * rows), s);
   switch (lanes) {
 #define CASE(L) \
   case L: dev::k_resid_t<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, y, b, r); break;
@@ -302,89 +459,157 @@ void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, 
 template <typename T>
 void residual(DLevel& L, const T* x, const T* b, T* r, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  spmv_csr<T>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, P.g_val, x, P.y, s);
-  resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, r, s);
+  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
+  spmv_csr<T>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, P.g_val, x, P.y, s, L.nnz, L.n);
+  resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, r, s, L.nnz, L.nrows);
 }
 
+template <typename T, int MODE, bool ADD>
+void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int64_t* cpos,
+          const T* tb, const T* M, const T* in, T* out, hipStream_t s, int64_t tb_extra = 0) {
+  PROF(kname(P.G > 0 ? "k_gemv_narrow" : "k_gemv_wide",
+             std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
+                 (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : P.NW)),
+       sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + tb_extra,
+       s);
+  if (P.G > 0) {
+    const unsigned g = (unsigned)((P.nagg + 3) / 4);
+    const size_t lds = (size_t)4 * P.lmax * sizeof(T);
+    switch (P.G) {
+#define CASE(GG)                                                                            \
+  case GG:                                                                                  \
+    dev::k_gemv_narrow<T, MODE, ADD, GG><<<g, dev::kBlock, lds, s>>>(P.nagg, P.op, P.lmax,  \
+                                                                     gidx, cptr, cpos, tb,  \
+                                                                     M, in, out);           \
+    break;
+      CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
+#undef CASE
+    }
+  } else {
+    const size_t lds = ((size_t)P.lmax + (size_t)P.NW * 64) * sizeof(T);
+    switch (P.NW) {
+#define CASE(NW)                                                                               \
+  case NW:                                                                                     \
+    dev::k_gemv_wide<T, MODE, ADD, NW><<<(unsigned)P.ntask, NW * 64, lds, s>>>(                \
+        P.task_a, P.task_j0, P.op, P.lmax, gidx, cptr, cpos, tb, M, in, out);                  \
+    break;
+      CASE(4) CASE(8) CASE(16)
+#undef CASE
+    }
+  }
+  LAUNCH_OK();
+}
+
+// x = RAS(b) from a zero initial guess (eq:ras)
 template <typename T>
 void ras(DLevel& L, const T* b, T* x, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  dev::k_ras<T><<<(unsigned)L.nagg, dev::kBlock, (L.max_nO + dev::kBlock) * sizeof(T), s>>>(
-      L.astart, L.optr, L.oidx, L.zoff, P.Zc, b, x);
-  LAUNCH_OK();
+  gemv<T, dev::IN_GATHER, false>(L.ras, L.oidx, nullptr, nullptr, nullptr, P.Zc, b, x, s);
 }
 
-// x += RAS-T(r)
+// staged RAS-T(r) (eq:ras-t) into tb; gather_add folds it into x
 template <typename T>
-void ras_t_add(DLevel& L, const T* r, T* x, hipStream_t s) {
+void ras_t_stage(DLevel& L, const T* r, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  dev::k_rast<T><<<(unsigned)L.nagg, dev::kBlock, (L.max_nw + dev::kBlock) * sizeof(T), s>>>(
-      L.astart, L.optr, L.zoff, P.Zr, r, P.tb);
-  LAUNCH_OK();
+  gemv<T, dev::IN_DIRECT, false>(L.rast, nullptr, nullptr, nullptr, nullptr, P.Zr, r, P.tb, s);
+}
+
+template <typename T>
+void gather_add(DLevel& L, T* x, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  PROF(kname("k_gather_add", tname<T>()),
+       (sizeof(T) + 8) * L.ntb + 8 * (L.n + 1) + 2 * sizeof(T) * L.n, s);
   dev::k_gather_add<T><<<nblocks(L.n), dev::kBlock, 0, s>>>(L.n, L.cptr, L.cpos, P.tb, x);
   LAUNCH_OK();
 }
 
-// x = B b on level l, from a zero initial guess.
+// x = B b on level l from a zero initial guess.  With finalize = false the
+// RAS-T contributions of this level are left staged in tb: the caller (the
+// finer level's prolongation) adds them when it reads x.
 template <typename T>
-void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s) {
+void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool finalize) {
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
   if (L.coarsest) {
+    PROF(kname("k_dense_gemv", tname<T>()), sizeof(T) * (L.n * L.n + 2 * L.n), s);
     dev::k_dense_gemv<T><<<nblocks(L.n * 64), dev::kBlock, 0, s>>>(L.n, P.Ainv, b, x);
     LAUNCH_OK();
     return;
   }
   DLevel& C = h->L[l + 1];
   DPrec<T>& PC = prec<T>(C);
-  ras<T>(L, b, x, s);                                     // eq:ras, x0 = 0
+  ras<T>(L, b, x, s);                                                        // eq:ras
   residual<T>(L, x, b, P.r, s);
-  dev::k_restrict<T><<<(unsigned)L.nagg, dev::kBlock, L.max_nw * sizeof(T), s>>>(
-      L.astart, L.cstart, L.kk, L.poff, P.Zh, P.r, PC.b);         // P^T r
-  LAUNCH_OK();
-  vcycle<T>(h, l + 1, PC.b, PC.x, s);
-  dev::k_prolong<T><<<(unsigned)L.nagg, dev::kBlock, L.max_k * sizeof(T), s>>>(
-      L.astart, L.cstart, L.kk, L.poff, P.Zh, PC.x, x);           // x += P e
-  LAUNCH_OK();
+  gemv<T, dev::IN_DIRECT, false>(L.rst, nullptr, nullptr, nullptr, nullptr, P.Zh, P.r, PC.b,
+                                 s);                                         // P^T r
+  vcycle<T>(h, l + 1, PC.b, PC.x, s, false);
+  if (C.coarsest)
+    gemv<T, dev::IN_DIRECT, true>(L.pro, nullptr, nullptr, nullptr, nullptr, P.ZhT, PC.x, x, s);
+  else
+    gemv<T, dev::IN_TB, true>(L.pro, nullptr, C.cptr, C.cpos, PC.tb, P.ZhT, PC.x, x, s,
+                              (int64_t)(sizeof(T) + 8) * C.ntb + 8 * (C.n + 1));
   residual<T>(L, x, b, P.r, s);
-  ras_t_add<T>(L, P.r, x, s);                             // eq:ras-t
+  ras_t_stage<T>(L, P.r, s);                                                 // eq:ras-t
+  if (finalize) gather_add<T>(L, x, s);
 }
 
 // z = B r (FP64 in and out), in the handle's precision.
 void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
   DLevel& L0 = h->L[0];
   if (h->precision == LSAMG_MIXED) {
-    dev::k_convert<double, float><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, r, L0.f.b);
-    LAUNCH_OK();
-    vcycle<float>(h, 0, L0.f.b, L0.f.x, s);
-    dev::k_convert<float, double><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, L0.f.x, z);
-    LAUNCH_OK();
+    {
+      PROF("k_convert<double, float>", 12 * L0.n, s);
+      dev::k_convert<double, float><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, r, L0.f.b);
+      LAUNCH_OK();
+    }
+    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, true);
+    {
+      PROF("k_convert<float, double>", 12 * L0.n, s);
+      dev::k_convert<float, double><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, L0.f.x, z);
+      LAUNCH_OK();
+    }
   } else {
-    vcycle<double>(h, 0, r, z, s);
+    vcycle<double>(h, 0, r, z, s, true);
   }
 }
 
 // y = A x = G^T (G x), FP64, finest level
 void apply_A(lsamg_handle* h, const double* x, double* y, hipStream_t s) {
   DLevel& L = h->L[0];
-  spmv_csr<double>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, L.d.g_val, x, L.d.y, s);
-  spmv_csr<double>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, y, s);
+  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
+  spmv_csr<double>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, L.d.g_val, x, L.d.y, s, L.nnz, L.n);
+  spmv_csr<double>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, y, s, L.nnz,
+                   L.nrows);
 }
 
-// sc[slot] = a . b  (device)
-void dot(lsamg_handle* h, int64_t n, const double* a, const double* b, int slot, hipStream_t s) {
-  const int np = (int)std::min<int64_t>(h->nparts, std::max<int64_t>(1, (n + 2047) / 2048));
-  dev::k_dot_partial<<<np, dev::kBlock, 0, s>>>(n, a, b, h->part);
-  LAUNCH_OK();
-  dev::k_sum_final<<<1, dev::kBlock, 0, s>>>(np, h->part, h->sc + slot);
+inline unsigned red_blocks(int64_t n) {
+  return (unsigned)std::min<int64_t>(1024, std::max<int64_t>(1, (n + dev::kBlock - 1) / dev::kBlock));
+}
+
+// partials of a . b into part (red_np of them)
+void dot_parts(lsamg_handle* h, int64_t n, const double* a, const double* b, double* part,
+               hipStream_t s) {
+  PROF("k_dot", 16 * n + 8 * h->red_np, s);
+  dev::k_dot<<<h->red_np, dev::kBlock, 0, s>>>(n, a, b, part);
   LAUNCH_OK();
 }
 
-double read_scalar(lsamg_handle* h, int slot, hipStream_t s) {
-  HIP_OK(hipMemcpyAsync(h->sc_host + slot, h->sc + slot, sizeof(double), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  return h->sc_host[slot];
+// queue a copy of red_np partials into pinned host slot (1024 doubles each)
+void parts_to_host(lsamg_handle* h, const double* part, int slot, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(h->sc_host + (size_t)slot * 1024, part, h->red_np * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
 }
+
+double host_sum(const lsamg_handle* h, int slot) {
+  double t = 0;
+  for (int i = 0; i < h->red_np; ++i) t += h->sc_host[(size_t)slot * 1024 + i];
+  return t;
+}
+
+struct ProfGuard {
+  explicit ProfGuard(Profiler* p) { g_prof = p; }
+  ~ProfGuard() { g_prof = nullptr; }
+};
 
 struct DeviceGuard {
   int old = -1;
@@ -397,63 +622,129 @@ struct DeviceGuard {
   }
 };
 
-// One PCG solve of a single right-hand side (device vectors in user numbering).
+// q = A p (finest level, FP64) with sc[CG_PQ] = p . q fused into the G^T pass
+void cg_apply(lsamg_handle* h, hipStream_t s) {
+  DLevel& L = h->L[0];
+  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
+  const int64_t n = L.n;
+  spmv_csr<double>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, L.d.g_val, h->p, L.d.y, s, L.nnz, n);
+  const unsigned g = h->red_np;
+  PROF(kname("k_cg_apq", std::to_string(L.lanes_gt)),
+       12 * L.nnz + 8 * (n + 1) + 8 * L.nrows + 24 * n + 8 * g, s);
+  switch (L.lanes_gt) {
+#define CASE(LN)                                                                          \
+  case LN:                                                                                \
+    dev::k_cg_apq<LN><<<g, dev::kBlock, 0, s>>>(n, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, \
+                                                h->p, h->q, h->p_pq);                     \
+    break;
+    CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
+#undef CASE
+  }
+  LAUNCH_OK();
+}
+
+// z = B r from the residual h->r (and its FP32 copy in mixed mode), the
+// partials of r . z into p_rz[cur], and p = z + beta p (beta from p_rz[cur]
+// over p_rz[1-cur]; p = z when first).
+void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
+  DLevel& L0 = h->L[0];
+  const int64_t n = L0.n;
+  const unsigned g = h->red_np;
+  const bool stage = !L0.coarsest;
+  if (h->precision == LSAMG_MIXED) {
+    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, false);
+    PROF("k_cg_z<float>", 4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
+    dev::k_cg_z<float><<<g, dev::kBlock, 0, s>>>(n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
+                                                 L0.f.tb, h->r, h->z, h->p_rz[cur]);
+  } else {
+    vcycle<double>(h, 0, h->r, L0.d.x, s, false);
+    PROF("k_cg_z<double>", 8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
+    dev::k_cg_z<double><<<g, dev::kBlock, 0, s>>>(n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
+                                                  L0.d.tb, h->r, h->z, h->p_rz[cur]);
+  }
+  LAUNCH_OK();
+  PROF("k_cg_dir", 24 * n + 16 * g, s);
+  dev::k_cg_dir<<<g, dev::kBlock, 0, s>>>(n, h->p_rz[cur], first ? nullptr : h->p_rz[1 - cur],
+                                          h->z, h->p);
+  LAUNCH_OK();
+}
+
+// One PCG solve of a single right-hand side (device vectors in user
+// numbering).  The host learns ||r_k|| through a pinned copy recorded after
+// the update of iteration k; while it waits, the V-cycle of iteration k is
+// already queued, so the GPU never idles on the stop test.  Only when the
+// residual history predicts convergence within the next iteration does the
+// host wait before queueing the V-cycle (which would otherwise be wasted).
 int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
             lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
-  const int64_t n = h->L[0].n;
+  DLevel& L0 = h->L[0];
+  const int64_t n = L0.n;
   const unsigned gb = nblocks(n);
-  HIP_OK(hipMemsetAsync(h->flag, 0, sizeof(int), s));
-  dev::k_nonfinite<<<gb, dev::kBlock, 0, s>>>(n, b, h->flag);
-  LAUNCH_OK();
-  int bad = 0;
-  HIP_OK(hipMemcpyAsync(&bad, h->flag, sizeof(int), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if (bad) throw DevError{LSAMG_EBADINPUT, "non-finite entry in the right-hand side"};
   dev::k_perm_in<<<gb, dev::kBlock, 0, s>>>(n, h->perm, b, h->bi);
   LAUNCH_OK();
   dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->x);
+  LAUNCH_OK();
   dev::k_copy<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->r);
   LAUNCH_OK();
-  dot(h, n, h->bi, h->bi, 4, s);
-  const double nb = std::sqrt(read_scalar(h, 4, s));
+  dot_parts(h, n, h->bi, h->bi, h->p_tmp, s);
+  parts_to_host(h, h->p_tmp, 0, s);
+  HIP_OK(hipStreamSynchronize(s));
+  const double nb2 = host_sum(h, 0);
+  if (!std::isfinite(nb2)) throw DevError{LSAMG_EBADINPUT, "non-finite entry in the right-hand side"};
+  const double nb = std::sqrt(nb2);
+  const bool mixed = h->precision == LSAMG_MIXED;
   int its = 0;
-  double rn = nb;
+  double rn = nb, rprev = nb, fac = 0.5;
   bool conv = (nb == 0.0);
-  if (!conv) {
-    precondition(h, h->r, h->z, s);
-    dev::k_copy<<<gb, dev::kBlock, 0, s>>>(n, h->z, h->p);
-    LAUNCH_OK();
-    dot(h, n, h->r, h->z, 0, s);
-    while (its < maxit) {
-      apply_A(h, h->p, h->q, s);
-      dot(h, n, h->p, h->q, 1, s);
-      dev::k_cg_update<<<gb, dev::kBlock, 0, s>>>(n, h->sc, h->p, h->q, h->x, h->r);
+  if (!conv && maxit > 0) {
+    if (mixed) {
+      dev::k_convert<double, float><<<gb, dev::kBlock, 0, s>>>(n, h->r, L0.f.b);
       LAUNCH_OK();
-      dot(h, n, h->r, h->r, 3, s);
+    }
+    int cur = 0;                        // p_rz[cur] holds rho of the current direction
+    cg_precondition(h, s, true, cur);
+    const double target = tol * nb;
+    while (its < maxit) {
+      cg_apply(h, s);
+      {
+        PROF("k_cg_update", (mixed ? 60 : 56) * n + 24 * h->red_np, s);
+        dev::k_cg_update<<<h->red_np, dev::kBlock, 0, s>>>(n, h->p_rz[cur], h->p_pq, h->p, h->q,
+                                                          h->x, h->r, mixed ? L0.f.b : nullptr,
+                                                          h->p_rr);
+        LAUNCH_OK();
+      }
+      const int slot = 1 + (its & 1);
+      parts_to_host(h, h->p_rr, slot, s);
+      HIP_OK(hipEventRecord(h->ev_rr[its & 1], s));
       ++its;
-      rn = std::sqrt(read_scalar(h, 3, s));
+      // predicted residual after this update, from the average reduction so far
+      const bool near = rprev * fac <= 2.0 * target || its >= maxit;
+      if (!near) cg_precondition(h, s, false, 1 - cur);
+      HIP_OK(hipEventSynchronize(h->ev_rr[(its - 1) & 1]));
+      rn = std::sqrt(host_sum(h, slot));
       if (!std::isfinite(rn)) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
-      if (rn <= tol * nb) {
+      fac = std::pow(rn / nb, 1.0 / its);
+      rprev = rn;
+      if (rn <= target) {
         conv = true;
         break;
       }
-      precondition(h, h->r, h->z, s);
-      dot(h, n, h->r, h->z, 2, s);
-      dev::k_cg_dir<<<gb, dev::kBlock, 0, s>>>(n, h->sc, h->z, h->p);
-      LAUNCH_OK();
-      HIP_OK(hipMemcpyAsync(h->sc, h->sc + 2, sizeof(double), hipMemcpyDeviceToDevice, s));
+      if (its >= maxit) break;
+      if (near) cg_precondition(h, s, false, 1 - cur);
+      cur = 1 - cur;
     }
   }
   // true residual in FP64
   apply_A(h, h->x, h->q, s);
   dev::k_sub<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->q, h->z);
   LAUNCH_OK();
-  dot(h, n, h->z, h->z, 7, s);
-  const double tr = std::sqrt(read_scalar(h, 7, s));
+  dot_parts(h, n, h->z, h->z, h->p_tmp, s);
+  parts_to_host(h, h->p_tmp, 0, s);
   dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->x, x);
   LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
+  const double tr = std::sqrt(host_sum(h, 0));
   if (st) {
     st->iters = its;
     st->converged = conv ? 1 : 0;
@@ -544,6 +835,7 @@ int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64
   if (ld < n) return fail_with(LSAMG_EINVAL, "ld < n");
   try {
     DeviceGuard g(h->device);
+    ProfGuard pg(&h->prof);
     hipStream_t s = (hipStream_t)stream;
     int rc = LSAMG_OK;
     for (int32_t c = 0; c < nrhs; ++c) {
@@ -567,6 +859,7 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
     return fail_with(LSAMG_EINVAL, "single-level hierarchy has no smoother");
   try {
     DeviceGuard g(h->device);
+    ProfGuard pg(&h->prof);
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = L0.n;
     const unsigned gb = nblocks(n);
@@ -584,7 +877,8 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
         ras<float>(L0, L0.f.b, L0.f.x, s);
       } else {
         HIP_OK(hipMemsetAsync(L0.f.x, 0, n * sizeof(float), s));
-        ras_t_add<float>(L0, L0.f.b, L0.f.x, s);
+        ras_t_stage<float>(L0, L0.f.b, s);
+        gather_add<float>(L0, L0.f.x, s);
       }
       dev::k_convert<float, double><<<gb, dev::kBlock, 0, s>>>(n, L0.f.x, h->z);
       LAUNCH_OK();
@@ -594,12 +888,66 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
       } else {
         dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->z);
         LAUNCH_OK();
-        ras_t_add<double>(L0, h->bi, h->z, s);
+        ras_t_stage<double>(L0, h->bi, s);
+        gather_add<double>(L0, h->z, s);
       }
     }
     dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->z, y);
     LAUNCH_OK();
     HIP_OK(hipStreamSynchronize(s));
+    return LSAMG_OK;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_profile(lsamg_handle* h, int32_t mode, const char* only) {
+  if (!h || (mode != 0 && mode != 1)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (h->device < 0) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  try {
+    DeviceGuard g(h->device);
+    Profiler& P = h->prof;
+    if (mode == 1 && P.pool.empty()) {
+      P.pool.resize(2 * 32768);
+      for (auto& e : P.pool) HIP_OK(hipEventCreate(&e));
+    }
+    P.on = mode == 1;
+    P.only = only ? only : "";
+    return LSAMG_OK;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_profile_read(lsamg_handle* h, lsamg_kprof* out, int32_t cap, int32_t* count) {
+  if (!h || !count || cap < 0 || (cap > 0 && !out)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (h->device < 0) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  try {
+    DeviceGuard g(h->device);
+    Profiler& P = h->prof;
+    HIP_OK(hipDeviceSynchronize());
+    std::vector<std::string> names;
+    std::vector<lsamg_kprof> acc;
+    for (auto& r : P.recs) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, r.a, r.b));
+      size_t i = std::find(names.begin(), names.end(), r.name) - names.begin();
+      if (i == names.size()) {
+        names.push_back(r.name);
+        lsamg_kprof k;
+        std::memset(&k, 0, sizeof(k));
+        std::strncpy(k.name, r.name.c_str(), sizeof(k.name) - 1);
+        acc.push_back(k);
+      }
+      acc[i].launches += 1;
+      acc[i].ms += ms;
+      acc[i].bytes += r.bytes;
+    }
+    P.recs.clear();
+    P.used = 0;
+    const int32_t nw = (int32_t)std::min<size_t>(acc.size(), (size_t)cap);
+    for (int32_t i = 0; i < nw; ++i) out[i] = acc[i];
+    *count = nw;
     return LSAMG_OK;
   } catch (const DevError& e) {
     return fail_with(e.code, e.msg);

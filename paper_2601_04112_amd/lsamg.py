@@ -85,6 +85,11 @@ class SetupView(C.Structure):
                 ("thresh", C.c_double)]
 
 
+class KProf(C.Structure):
+    _fields_ = [("name", C.c_char * 80), ("launches", C.c_int64),
+                ("ms", C.c_double), ("bytes", C.c_double)]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
     "lsamg_params_default": (None, [C.POINTER(Params)]),
@@ -96,6 +101,9 @@ _SIGS = {
     "lsamg_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "lsamg_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lsamg_profile": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
+    "lsamg_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KProf), C.c_int32,
+                                     C.POINTER(C.c_int32)]),
     "lsamg_info_get": (C.c_int, [C.c_void_p, C.POINTER(Info)]),
     "lsamg_export_setup": (C.c_int, [C.c_void_p, C.c_int32,
                                      C.POINTER(SetupView)]),
@@ -239,6 +247,20 @@ class Solver:
 
     def set_precision(self, precision: int):
         _check(load().lsamg_set_precision(self._h, precision))
+
+    # -- kernel timing ----------------------------------------------------
+    def profile(self, on: bool = True, only: Optional[str] = None):
+        """Bracket kernel launches with HIP events (all, or one symbol)."""
+        _check(load().lsamg_profile(self._h, 1 if on else 0,
+                                    only.encode() if only else None))
+
+    def profile_read(self) -> list:
+        """Per-kernel totals since profiling was enabled (then reset)."""
+        buf = (KProf * 256)()
+        cnt = C.c_int32()
+        _check(load().lsamg_profile_read(self._h, buf, 256, C.byref(cnt)))
+        return [dict(name=buf[i].name.decode(), launches=buf[i].launches,
+                     ms=buf[i].ms, bytes=buf[i].bytes) for i in range(cnt.value)]
 
     # -- introspection ----------------------------------------------------
     def info(self) -> dict:
