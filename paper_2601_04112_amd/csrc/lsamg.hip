@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.hpp"
@@ -126,20 +127,41 @@ inline Profiler* prof_active() { return (g_prof && g_prof->on) ? g_prof : nullpt
 
 struct ProfScope {
   Profiler* p = nullptr;
-  size_t rec = 0;
-  hipStream_t s;
-  ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t st) : s(st) {
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope() = default;
+  ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t) {
     if (!pp || !pp->want(name) || pp->used + 2 > pp->pool.size()) return;
     p = pp;
-    hipEvent_t a = pp->pool[pp->used++], b = pp->pool[pp->used++];
+    a = pp->pool[pp->used++];
+    b = pp->pool[pp->used++];
     pp->recs.push_back(Profiler::Rec{name, bytes, a, b});
-    rec = pp->recs.size() - 1;
-    (void)hipEventRecord(a, s);
-  }
-  ~ProfScope() {
-    if (p) (void)hipEventRecord(p->recs[rec].b, s);
   }
 };
+
+// Launch kern on stream s; when the launch is being timed, the dispatch packet
+// itself stamps the start/stop events (hipExtLaunchKernel), so the recorded
+// interval is the kernel's own execution.
+template <typename... KArgs, typename... Args>
+void klaunch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const ProfScope& ps,
+             void (*kern)(KArgs...), Args&&... args) {
+  std::tuple<KArgs...> tup(std::forward<Args>(args)...);
+  void* argv[sizeof...(KArgs) > 0 ? sizeof...(KArgs) : 1];
+  std::apply([&](auto&... e) {
+    int i = 0;
+    ((argv[i++] = (void*)&e), ...);
+  }, tup);
+  hipError_t e = ps.p ? hipExtLaunchKernel((const void*)kern, grid, block, argv, lds, s, ps.a,
+                                           ps.b, 0)
+                      : hipLaunchKernel((const void*)kern, grid, block, argv, lds, s);
+  if (e != hipSuccess)
+    throw DevError{LSAMG_EHIP, std::string("kernel launch: ") + hipGetErrorString(e)};
+}
+
+const ProfScope kNoProf{};
+
+// KLAUNCH inside a PROF scope times the launch; KLAUNCH0 never does
+#define KLAUNCH(G, B, LDS, S, ...) klaunch(G, B, LDS, S, ps_, __VA_ARGS__)
+#define KLAUNCH0(G, B, LDS, S, ...) klaunch(G, B, LDS, S, kNoProf, __VA_ARGS__)
 
 // PROF(name-expression, bytes-expression, stream): the expressions are only
 // evaluated while profiling is on.
@@ -433,7 +455,7 @@ void spmv_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, c
        nnz * (sizeof(T) + 4) + 8 * (rows + 1) + sizeof(T) * (ncols + rows), s);
   switch (lanes) {
 #define CASE(L) \
-  case L: dev::k_spmv<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, x, y); break;
+  case L: KLAUNCH(g, dev::kBlock, 0, s, dev::k_spmv<T, L>, rows, ptr, col, val, x, y); break;
     CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
   }
@@ -448,7 +470,7 @@ void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, 
        nnz * (sizeof(T) + 4) + 8 * (rows + 1) + sizeof(T) * (ny + 2 * rows), s);
   switch (lanes) {
 #define CASE(L) \
-  case L: dev::k_resid_t<T, L><<<g, dev::kBlock, 0, s>>>(rows, ptr, col, val, y, b, r); break;
+  case L: KLAUNCH(g, dev::kBlock, 0, s, dev::k_resid_t<T, L>, rows, ptr, col, val, y, b, r); break;
     CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
   }
@@ -478,7 +500,7 @@ void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int
     switch (P.G) {
 #define CASE(GG)                                                                            \
   case GG:                                                                                  \
-    dev::k_gemv_narrow<T, MODE, ADD, GG><<<g, dev::kBlock, lds, s>>>(P.nagg, P.op, P.lmax,  \
+    KLAUNCH(g, dev::kBlock, lds, s, dev::k_gemv_narrow<T, MODE, ADD, GG>, P.nagg, P.op, P.lmax,  \
                                                                      gidx, cptr, cpos, tb,  \
                                                                      M, in, out);           \
     break;
@@ -490,7 +512,7 @@ void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int
     switch (P.NW) {
 #define CASE(NW)                                                                               \
   case NW:                                                                                     \
-    dev::k_gemv_wide<T, MODE, ADD, NW><<<(unsigned)P.ntask, NW * 64, lds, s>>>(                \
+    KLAUNCH((unsigned)P.ntask, NW * 64, lds, s, dev::k_gemv_wide<T, MODE, ADD, NW>,                 \
         P.task_a, P.task_j0, P.op, P.lmax, gidx, cptr, cpos, tb, M, in, out);                  \
     break;
       CASE(4) CASE(8) CASE(16)
@@ -519,7 +541,7 @@ void gather_add(DLevel& L, T* x, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
   PROF(kname("k_gather_add", tname<T>()),
        (sizeof(T) + 8) * L.ntb + 8 * (L.n + 1) + 2 * sizeof(T) * L.n, s);
-  dev::k_gather_add<T><<<nblocks(L.n), dev::kBlock, 0, s>>>(L.n, L.cptr, L.cpos, P.tb, x);
+  KLAUNCH(nblocks(L.n), dev::kBlock, 0, s, dev::k_gather_add<T>, L.n, L.cptr, L.cpos, P.tb, x);
   LAUNCH_OK();
 }
 
@@ -532,7 +554,7 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   DPrec<T>& P = prec<T>(L);
   if (L.coarsest) {
     PROF(kname("k_dense_gemv", tname<T>()), sizeof(T) * (L.n * L.n + 2 * L.n), s);
-    dev::k_dense_gemv<T><<<nblocks(L.n * 64), dev::kBlock, 0, s>>>(L.n, P.Ainv, b, x);
+    KLAUNCH(nblocks(L.n * 64), dev::kBlock, 0, s, dev::k_dense_gemv<T>, L.n, P.Ainv, b, x);
     LAUNCH_OK();
     return;
   }
@@ -559,13 +581,13 @@ void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
   if (h->precision == LSAMG_MIXED) {
     {
       PROF("k_convert<double, float>", 12 * L0.n, s);
-      dev::k_convert<double, float><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, r, L0.f.b);
+      KLAUNCH(nblocks(L0.n), dev::kBlock, 0, s, dev::k_convert<double, float>, L0.n, r, L0.f.b);
       LAUNCH_OK();
     }
     vcycle<float>(h, 0, L0.f.b, L0.f.x, s, true);
     {
       PROF("k_convert<float, double>", 12 * L0.n, s);
-      dev::k_convert<float, double><<<nblocks(L0.n), dev::kBlock, 0, s>>>(L0.n, L0.f.x, z);
+      KLAUNCH(nblocks(L0.n), dev::kBlock, 0, s, dev::k_convert<float, double>, L0.n, L0.f.x, z);
       LAUNCH_OK();
     }
   } else {
@@ -590,7 +612,7 @@ inline unsigned red_blocks(int64_t n) {
 void dot_parts(lsamg_handle* h, int64_t n, const double* a, const double* b, double* part,
                hipStream_t s) {
   PROF("k_dot", 16 * n + 8 * h->red_np, s);
-  dev::k_dot<<<h->red_np, dev::kBlock, 0, s>>>(n, a, b, part);
+  KLAUNCH(h->red_np, dev::kBlock, 0, s, dev::k_dot, n, a, b, part);
   LAUNCH_OK();
 }
 
@@ -634,7 +656,7 @@ void cg_apply(lsamg_handle* h, hipStream_t s) {
   switch (L.lanes_gt) {
 #define CASE(LN)                                                                          \
   case LN:                                                                                \
-    dev::k_cg_apq<LN><<<g, dev::kBlock, 0, s>>>(n, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, \
+    KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_apq<LN>, n, L.gt_ptr, L.gt_col, L.d.gt_val, L.d.y, \
                                                 h->p, h->q, h->p_pq);                     \
     break;
     CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
@@ -654,17 +676,17 @@ void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   if (h->precision == LSAMG_MIXED) {
     vcycle<float>(h, 0, L0.f.b, L0.f.x, s, false);
     PROF("k_cg_z<float>", 4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
-    dev::k_cg_z<float><<<g, dev::kBlock, 0, s>>>(n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
+    KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<float>, n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
                                                  L0.f.tb, h->r, h->z, h->p_rz[cur]);
   } else {
     vcycle<double>(h, 0, h->r, L0.d.x, s, false);
     PROF("k_cg_z<double>", 8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
-    dev::k_cg_z<double><<<g, dev::kBlock, 0, s>>>(n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
+    KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<double>, n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
                                                   L0.d.tb, h->r, h->z, h->p_rz[cur]);
   }
   LAUNCH_OK();
   PROF("k_cg_dir", 24 * n + 16 * g, s);
-  dev::k_cg_dir<<<g, dev::kBlock, 0, s>>>(n, h->p_rz[cur], first ? nullptr : h->p_rz[1 - cur],
+  KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_dir, n, h->p_rz[cur], first ? nullptr : h->p_rz[1 - cur],
                                           h->z, h->p);
   LAUNCH_OK();
 }
@@ -681,11 +703,11 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
   DLevel& L0 = h->L[0];
   const int64_t n = L0.n;
   const unsigned gb = nblocks(n);
-  dev::k_perm_in<<<gb, dev::kBlock, 0, s>>>(n, h->perm, b, h->bi);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_in, n, h->perm, b, h->bi);
   LAUNCH_OK();
-  dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->x);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_fill, n, 0.0, h->x);
   LAUNCH_OK();
-  dev::k_copy<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->r);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_copy, n, h->bi, h->r);
   LAUNCH_OK();
   dot_parts(h, n, h->bi, h->bi, h->p_tmp, s);
   parts_to_host(h, h->p_tmp, 0, s);
@@ -699,7 +721,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
   bool conv = (nb == 0.0);
   if (!conv && maxit > 0) {
     if (mixed) {
-      dev::k_convert<double, float><<<gb, dev::kBlock, 0, s>>>(n, h->r, L0.f.b);
+      KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<double, float>, n, h->r, L0.f.b);
       LAUNCH_OK();
     }
     int cur = 0;                        // p_rz[cur] holds rho of the current direction
@@ -709,7 +731,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
       cg_apply(h, s);
       {
         PROF("k_cg_update", (mixed ? 60 : 56) * n + 24 * h->red_np, s);
-        dev::k_cg_update<<<h->red_np, dev::kBlock, 0, s>>>(n, h->p_rz[cur], h->p_pq, h->p, h->q,
+        KLAUNCH(h->red_np, dev::kBlock, 0, s, dev::k_cg_update, n, h->p_rz[cur], h->p_pq, h->p, h->q,
                                                           h->x, h->r, mixed ? L0.f.b : nullptr,
                                                           h->p_rr);
         LAUNCH_OK();
@@ -737,11 +759,11 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
   }
   // true residual in FP64
   apply_A(h, h->x, h->q, s);
-  dev::k_sub<<<gb, dev::kBlock, 0, s>>>(n, h->bi, h->q, h->z);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_sub, n, h->bi, h->q, h->z);
   LAUNCH_OK();
   dot_parts(h, n, h->z, h->z, h->p_tmp, s);
   parts_to_host(h, h->p_tmp, 0, s);
-  dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->x, x);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_out, n, h->perm, h->x, x);
   LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
   const double tr = std::sqrt(host_sum(h, 0));
@@ -863,7 +885,7 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = L0.n;
     const unsigned gb = nblocks(n);
-    dev::k_perm_in<<<gb, dev::kBlock, 0, s>>>(n, h->perm, x, h->bi);
+    KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_in, n, h->perm, x, h->bi);
     LAUNCH_OK();
     const bool mixed = h->precision == LSAMG_MIXED;
     if (op == LSAMG_OP_A) {
@@ -871,7 +893,7 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
     } else if (op == LSAMG_OP_VCYCLE) {
       precondition(h, h->bi, h->z, s);
     } else if (mixed) {
-      dev::k_convert<double, float><<<gb, dev::kBlock, 0, s>>>(n, h->bi, L0.f.b);
+      KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<double, float>, n, h->bi, L0.f.b);
       LAUNCH_OK();
       if (op == LSAMG_OP_RAS) {
         ras<float>(L0, L0.f.b, L0.f.x, s);
@@ -880,19 +902,19 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
         ras_t_stage<float>(L0, L0.f.b, s);
         gather_add<float>(L0, L0.f.x, s);
       }
-      dev::k_convert<float, double><<<gb, dev::kBlock, 0, s>>>(n, L0.f.x, h->z);
+      KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<float, double>, n, L0.f.x, h->z);
       LAUNCH_OK();
     } else {
       if (op == LSAMG_OP_RAS) {
         ras<double>(L0, h->bi, h->z, s);
       } else {
-        dev::k_fill<<<gb, dev::kBlock, 0, s>>>(n, 0.0, h->z);
+        KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_fill, n, 0.0, h->z);
         LAUNCH_OK();
         ras_t_stage<double>(L0, h->bi, s);
         gather_add<double>(L0, h->z, s);
       }
     }
-    dev::k_perm_out<<<gb, dev::kBlock, 0, s>>>(n, h->perm, h->z, y);
+    KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_out, n, h->perm, h->z, y);
     LAUNCH_OK();
     HIP_OK(hipStreamSynchronize(s));
     return LSAMG_OK;
