@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(kBlock) k_cg_dir(int64_t n,
   const double beta = rz_old ? sum_parts(rz_new, np) / sum_parts(rz_old, np) : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock)
-    p[i] = z[i] + beta * p[i];
+    p[i] = rz_old ? z[i] + beta * p[i] : z[i];   // first direction: p = z
 }
 
 // ---------------------------------------------------------------------------

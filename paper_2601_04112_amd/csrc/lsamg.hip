@@ -18,6 +18,7 @@
 
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "kernels_batched.hpp"
 
 using namespace lsamg;
 
@@ -77,6 +78,7 @@ struct GemvPlan {
 
 struct DLevel {
   GemvPlan ras, rast, rst, pro;
+  GemvPlan dense;         // coarsest level: A_L^{-1} as one block (batched path)
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
   int lanes_g = 1, lanes_gt = 1;
@@ -187,6 +189,7 @@ struct lsamg_handle {
   Hierarchy H;
   int device = -1;
   int precision = LSAMG_FP64;
+  int batch_mode = 1;               // 1: nrhs > 1 solved as batches of <= 64
   std::vector<DLevel> L;
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -199,6 +202,20 @@ struct lsamg_handle {
   double* sc_host = nullptr;         // pinned
   int nparts = 1024;
   hipEvent_t ev_rr[2] = {nullptr, nullptr};
+  // multi-right-hand-side buffers (interleaved n x NB, allocated for NB = 64
+  // on the first batched solve; a narrower batch uses a prefix)
+  struct BLev {
+    double *x = nullptr, *b = nullptr, *r = nullptr, *y = nullptr, *tb = nullptr;
+    float *fx = nullptr, *fb = nullptr, *fr = nullptr, *fy = nullptr, *ftb = nullptr;
+  };
+  bool batched_ready = false;
+  std::vector<BLev> BL;
+  double *BX = nullptr, *BR = nullptr, *BZ = nullptr, *BP = nullptr, *BQ = nullptr,
+         *BBi = nullptr, *Bpq = nullptr, *Brr = nullptr, *Brz[2] = {nullptr, nullptr},
+         *Btmp = nullptr;
+  int* Bactive = nullptr;
+  int* Bactive_host = nullptr;       // pinned
+  double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
   // export buffers
   std::vector<int32_t> ex_agg, ex_k, ex_M;
   std::vector<int64_t> ex_optr, ex_oidx, ex_muptr;
@@ -235,6 +252,10 @@ struct lsamg_handle {
     allocs.clear();
     if (sc_host) (void)hipHostFree(sc_host);
     sc_host = nullptr;
+    if (Bactive_host) (void)hipHostFree(Bactive_host);
+    Bactive_host = nullptr;
+    if (Bparts_host) (void)hipHostFree(Bparts_host);
+    Bparts_host = nullptr;
     bytes = 0;
   }
 };
@@ -306,6 +327,25 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   if (HL.coarsest) {
     D.d.Ainv = h->upload_f<double>(HL.Ainv);
     D.f.Ainv = h->upload_f<float>(HL.Ainv);
+    // the dense inverse as a one-block operator for the batched GEMM
+    GemvPlan& P = D.dense;
+    std::vector<int64_t> z1(1, 0);
+    std::vector<int32_t> n1(1, (int32_t)D.n);
+    int32_t* dn = h->upload(n1);
+    int64_t* dz = h->upload(z1);
+    P.op = dev::GemvOp{dz, dn, dn, dz, dz};
+    P.nagg = 1;
+    P.lmax = (int)D.n;
+    P.mat = D.n * D.n;
+    P.in_u = P.out = D.n;
+    std::vector<int32_t> ta, tj;
+    for (int64_t j = 0; j < D.n; j += 64) {
+      ta.push_back(0);
+      tj.push_back((int32_t)j);
+    }
+    P.ntask = (int64_t)ta.size();
+    P.task_a = h->upload(ta);
+    P.task_j0 = h->upload(tj);
     return;
   }
   D.nagg = HL.nagg;
@@ -391,24 +431,26 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     P.in_u = in_unique;
     P.lmax = *std::max_element(ll.begin(), ll.end());
     const int ljmax = *std::max_element(lj.begin(), lj.end());
-    if (ljmax <= 64) {
-      int g = 1;
-      while (g < ljmax) g <<= 1;
-      P.G = g;
-      return;
-    }
+    // tasks (aggregate, 64-wide output slice): the wide single-vector form
+    // and the batched form both use them
     std::vector<int32_t> ta, tj;
     for (int64_t a = 0; a < HL.nagg; ++a)
       for (int j = 0; j < lj[a]; j += 64) {
         ta.push_back((int32_t)a);
         tj.push_back(j);
       }
-    P.G = 0;
     P.ntask = (int64_t)ta.size();
-    P.NW = 4;
-    while (P.NW < 16 && P.ntask * P.NW < 4096) P.NW <<= 1;
     P.task_a = h->upload(ta);
     P.task_j0 = h->upload(tj);
+    P.G = 0;
+    if (ljmax <= 64) {
+      int g = 1;
+      while (g < ljmax) g <<= 1;
+      P.G = g;
+      return;
+    }
+    P.NW = 4;
+    while (P.NW < 16 && P.ntask * P.NW < 4096) P.NW <<= 1;
   };
   const int64_t ncoarse = HL.cstart[HL.nagg];
   plan(D.ras, nw, nO, d_nw, d_nO, d_z0, d_o0, d_w0, D.n, true);
@@ -778,6 +820,320 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
   return conv ? LSAMG_OK : LSAMG_ENOCONV;
 }
 
+// ===========================================================================
+// Multi-right-hand-side path
+// ===========================================================================
+constexpr int kBNP = 256;      // workgroups (and partials per column) of the batched CG kernels
+constexpr int kBMax = 64;      // widest batch
+
+void ensure_batched(lsamg_handle* h) {
+  if (h->batched_ready) return;
+  h->BL.resize(h->L.size());
+  for (size_t l = 0; l < h->L.size(); ++l) {
+    DLevel& L = h->L[l];
+    auto& B = h->BL[l];
+    const size_t n = (size_t)L.n * kBMax, ny = (size_t)std::max<int64_t>(L.nrows, 1) * kBMax,
+                 nt = (size_t)std::max<int64_t>(L.ntb, 1) * kBMax;
+    B.x = h->alloc<double>(n);
+    B.b = h->alloc<double>(n);
+    B.r = h->alloc<double>(n);
+    B.y = h->alloc<double>(ny);
+    B.tb = h->alloc<double>(nt);
+    B.fx = h->alloc<float>(n);
+    B.fb = h->alloc<float>(n);
+    B.fr = h->alloc<float>(n);
+    B.fy = h->alloc<float>(ny);
+    B.ftb = h->alloc<float>(nt);
+  }
+  const size_t n0 = (size_t)h->L[0].n * kBMax;
+  h->BX = h->alloc<double>(n0);
+  h->BR = h->alloc<double>(n0);
+  h->BZ = h->alloc<double>(n0);
+  h->BP = h->alloc<double>(n0);
+  h->BQ = h->alloc<double>(n0);
+  h->BBi = h->alloc<double>(n0);
+  h->Bpq = h->alloc<double>(kBNP * kBMax);
+  h->Brr = h->alloc<double>(kBNP * kBMax);
+  h->Brz[0] = h->alloc<double>(kBNP * kBMax);
+  h->Brz[1] = h->alloc<double>(kBNP * kBMax);
+  h->Btmp = h->alloc<double>(kBNP * kBMax);
+  h->Bactive = h->alloc<int>(kBMax);
+  HIP_OK(hipHostMalloc((void**)&h->Bactive_host, kBMax * sizeof(int), hipHostMallocDefault));
+  HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * kBNP * kBMax * sizeof(double),
+                       hipHostMallocDefault));
+  h->batched_ready = true;
+}
+
+template <typename T>
+struct BVec {
+  T *x, *b, *r, *y, *tb;
+};
+template <typename T>
+BVec<T> bvec(lsamg_handle::BLev& B);
+template <>
+BVec<double> bvec<double>(lsamg_handle::BLev& B) { return {B.x, B.b, B.r, B.y, B.tb}; }
+template <>
+BVec<float> bvec<float>(lsamg_handle::BLev& B) { return {B.fx, B.fb, B.fr, B.fy, B.ftb}; }
+
+template <typename T, int MODE, bool ADD, int NB>
+void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int64_t* cpos,
+           const T* tb, const T* M, const T* in, T* out, hipStream_t s, int64_t tb_extra = 0) {
+  PROF(kname("k_bgemm", std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
+                            (ADD ? "true" : "false") + ", " + std::to_string(NB)),
+       sizeof(T) * (P.mat + (P.in_u + P.out * (ADD ? 2 : 1)) * NB) + 4 * P.idx + 32 * P.nagg +
+           tb_extra * NB,
+       s);
+  KLAUNCH((unsigned)P.ntask, dev::kBlock, 0, s, dev::k_bgemm<T, MODE, ADD, NB>, P.task_a,
+          P.task_j0, P.op, gidx, cptr, cpos, tb, M, in, out);
+  LAUNCH_OK();
+}
+
+template <typename T, int NB>
+void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
+  {
+    PROF(kname("k_bspmv", std::string(tname<T>()) + ", " + std::to_string(NB)),
+         L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
+    KLAUNCH(nblocks(L.nrows * NB), dev::kBlock, 0, s, dev::k_bspmv<T, NB>, L.nrows, L.g_ptr,
+            L.g_col, P.g_val, X, V.y);
+    LAUNCH_OK();
+  }
+  PROF(kname("k_bresid_t", std::string(tname<T>()) + ", " + std::to_string(NB)),
+       L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
+  KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bresid_t<T, NB>, L.n, L.gt_ptr, L.gt_col,
+          P.gt_val, (const T*)V.y, B, R);
+  LAUNCH_OK();
+}
+
+// X = B_l(B) for NB interleaved right-hand sides (see vcycle)
+template <typename T, int NB>
+void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool finalize) {
+  DLevel& L = h->L[l];
+  DPrec<T>& P = prec<T>(L);
+  BVec<T> V = bvec<T>(h->BL[l]);
+  if (L.coarsest) {
+    bgemm<T, dev::IN_DIRECT, false, NB>(L.dense, nullptr, nullptr, nullptr, nullptr, P.Ainv, B, X,
+                                        s);
+    return;
+  }
+  DLevel& C = h->L[l + 1];
+  BVec<T> VC = bvec<T>(h->BL[l + 1]);
+  bgemm<T, dev::IN_GATHER, false, NB>(L.ras, L.oidx, nullptr, nullptr, nullptr, P.Zc, B, X, s);
+  bresidual<T, NB>(L, V, X, B, V.r, s);
+  bgemm<T, dev::IN_DIRECT, false, NB>(L.rst, nullptr, nullptr, nullptr, nullptr, P.Zh, V.r, VC.b,
+                                      s);
+  bvcycle<T, NB>(h, l + 1, VC.b, VC.x, s, false);
+  if (C.coarsest)
+    bgemm<T, dev::IN_DIRECT, true, NB>(L.pro, nullptr, nullptr, nullptr, nullptr, P.ZhT, VC.x, X,
+                                       s);
+  else
+    bgemm<T, dev::IN_TB, true, NB>(L.pro, nullptr, C.cptr, C.cpos, VC.tb, P.ZhT, VC.x, X, s,
+                                   (int64_t)(sizeof(T)) * C.ntb + 8 * (C.ntb + C.n + 1) / NB);
+  bresidual<T, NB>(L, V, X, B, V.r, s);
+  bgemm<T, dev::IN_DIRECT, false, NB>(L.rast, nullptr, nullptr, nullptr, nullptr, P.Zr, V.r, V.tb,
+                                      s);
+  if (finalize) {
+    PROF(kname("k_bgather_add", std::string(tname<T>()) + ", " + std::to_string(NB)),
+         8 * (L.ntb + L.n + 1) + sizeof(T) * (L.ntb + 2 * L.n) * NB, s);
+    KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bgather_add<T, NB>, L.n, L.cptr, L.cpos,
+            (const T*)V.tb, X);
+    LAUNCH_OK();
+  }
+}
+
+template <int NB>
+void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, hipStream_t s) {
+  DLevel& L = h->L[0];
+  BVec<double> V = bvec<double>(h->BL[0]);
+  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
+  {
+    PROF(kname("k_bspmv", std::string("double, ") + std::to_string(NB)),
+         L.nnz * 12 + 8 * (L.nrows + 1) + 8 * (L.n + L.nrows) * NB, s);
+    KLAUNCH(nblocks(L.nrows * NB), dev::kBlock, 0, s, dev::k_bspmv<double, NB>, L.nrows, L.g_ptr,
+            L.g_col, L.d.g_val, Pv, V.y);
+    LAUNCH_OK();
+  }
+  PROF(kname("k_bcg_apq", std::to_string(NB)),
+       L.nnz * 12 + 8 * (L.n + 1) + 8 * (L.nrows + 2 * L.n) * NB, s);
+  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq<NB>, L.n, L.gt_ptr, L.gt_col, L.d.gt_val,
+          (const double*)V.y, Pv, Qv, pq_part);
+  LAUNCH_OK();
+}
+
+template <int NB>
+void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
+  DLevel& L0 = h->L[0];
+  const int64_t n = L0.n;
+  auto& B0 = h->BL[0];
+  const bool stage = !L0.coarsest;
+  if (h->precision == LSAMG_MIXED) {
+    bvcycle<float, NB>(h, 0, B0.fb, B0.fx, s, false);
+    PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), 20 * n * NB, s);
+    KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
+            stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
+            h->Brz[cur]);
+  } else {
+    bvcycle<double, NB>(h, 0, h->BR, B0.x, s, false);
+    PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), 24 * n * NB, s);
+    KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
+            stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
+            h->BZ, h->Brz[cur]);
+  }
+  LAUNCH_OK();
+  PROF(kname("k_bcg_dir", std::to_string(NB)), 24 * n * NB, s);
+  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, (const double*)h->Brz[cur],
+          first ? (const double*)nullptr : (const double*)h->Brz[1 - cur], (const double*)h->BZ,
+          h->BP);
+  LAUNCH_OK();
+}
+
+// per-column sums of kBNP x NB partials copied to pinned slot
+void bparts_to_host(lsamg_handle* h, const double* part, int NB, int slot, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(h->Bparts_host + (size_t)slot * kBNP * kBMax, part,
+                        (size_t)kBNP * NB * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+void bhost_sums(const lsamg_handle* h, int NB, int slot, double* out) {
+  const double* p = h->Bparts_host + (size_t)slot * kBNP * kBMax;
+  for (int j = 0; j < NB; ++j) {
+    double t = 0;
+    for (int b = 0; b < kBNP; ++b) t += p[(size_t)b * NB + j];
+    out[j] = t;
+  }
+}
+
+// PCG on nr <= NB right-hand sides at once: one FP64 CG per column (own
+// scalars and stop test), sharing every matrix read of the V-cycle and of A.
+template <int NB>
+int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
+                int maxit, hipStream_t s, lsamg_stats* st) {
+  auto t0 = std::chrono::steady_clock::now();
+  ensure_batched(h);
+  DLevel& L0 = h->L[0];
+  auto& B0 = h->BL[0];
+  const int64_t n = L0.n;
+  const unsigned ge = nblocks(n * NB);
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_in<NB>, n, nr, ld, (const int64_t*)h->perm, b,
+           h->BBi);
+  LAUNCH_OK();
+  HIP_OK(hipMemsetAsync(h->BX, 0, (size_t)n * NB * sizeof(double), s));
+  HIP_OK(hipMemcpyAsync(h->BR, h->BBi, (size_t)n * NB * sizeof(double), hipMemcpyDeviceToDevice,
+                        s));
+  KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BBi,
+           (const double*)h->BBi, h->Btmp);
+  LAUNCH_OK();
+  bparts_to_host(h, h->Btmp, NB, 0, s);
+  HIP_OK(hipStreamSynchronize(s));
+  double nb2[kBMax], rr[kBMax], nbv[kBMax], rn[kBMax];
+  int its_col[kBMax], conv_col[kBMax];
+  bhost_sums(h, NB, 0, nb2);
+  int nactive = 0;
+  for (int j = 0; j < NB; ++j) {
+    if (j < nr && !std::isfinite(nb2[j]))
+      throw DevError{LSAMG_EBADINPUT, "non-finite entry in a right-hand side"};
+    nbv[j] = std::sqrt(j < nr ? nb2[j] : 0.0);
+    rn[j] = nbv[j];
+    its_col[j] = 0;
+    conv_col[j] = (j < nr && nbv[j] == 0.0) ? 1 : 0;
+    h->Bactive_host[j] = (j < nr && nbv[j] > 0.0 && maxit > 0) ? 1 : 0;
+    nactive += h->Bactive_host[j];
+  }
+  HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, NB * sizeof(int), hipMemcpyHostToDevice, s));
+  const bool mixed = h->precision == LSAMG_MIXED;
+  int its = 0;
+  double fac = 0.5;
+  if (nactive > 0) {
+    if (mixed) {
+      KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_convert<double, float>, n * NB,
+               (const double*)h->BR, B0.fb);
+      LAUNCH_OK();
+    }
+    int cur = 0;
+    bcg_precondition<NB>(h, s, true, cur);
+    while (its < maxit && nactive > 0) {
+      bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, s);
+      {
+        PROF(kname("k_bcg_update", std::to_string(NB)), (mixed ? 60 : 56) * n * NB, s);
+        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_update<NB>, n, (const double*)h->Brz[cur],
+                (const double*)h->Bpq, (const int*)h->Bactive, (const double*)h->BP,
+                (const double*)h->BQ, h->BX, h->BR, mixed ? B0.fb : (float*)nullptr, h->Brr);
+        LAUNCH_OK();
+      }
+      const int slot = 1 + (its & 1);
+      bparts_to_host(h, h->Brr, NB, slot, s);
+      HIP_OK(hipEventRecord(h->ev_rr[its & 1], s));
+      ++its;
+      // the most advanced active column predicts whether this update converges
+      double best = 1e300;
+      for (int j = 0; j < NB; ++j)
+        if (h->Bactive_host[j]) best = std::min(best, rn[j] / nbv[j]);
+      const bool near = best * fac <= 2.0 * tol || its >= maxit;
+      if (!near) bcg_precondition<NB>(h, s, false, 1 - cur);
+      HIP_OK(hipEventSynchronize(h->ev_rr[(its - 1) & 1]));
+      bhost_sums(h, NB, slot, rr);
+      nactive = 0;
+      double worst = 0;
+      for (int j = 0; j < NB; ++j) {
+        if (!h->Bactive_host[j]) continue;
+        rn[j] = std::sqrt(rr[j]);
+        if (!std::isfinite(rn[j])) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
+        its_col[j] = its;
+        if (rn[j] <= tol * nbv[j]) {
+          conv_col[j] = 1;
+          h->Bactive_host[j] = 0;
+        } else {
+          ++nactive;
+          worst = std::max(worst, std::pow(rn[j] / nbv[j], 1.0 / its));
+        }
+      }
+      if (worst > 0) fac = worst;
+      if (nactive == 0 || its >= maxit) break;
+      HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, NB * sizeof(int), hipMemcpyHostToDevice,
+                            s));
+      if (near) bcg_precondition<NB>(h, s, false, 1 - cur);
+      cur = 1 - cur;
+    }
+  }
+  // true residuals in FP64
+  bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, s);
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_sub, n * NB, (const double*)h->BBi, (const double*)h->BQ,
+           h->BZ);
+  LAUNCH_OK();
+  KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BZ,
+           (const double*)h->BZ, h->Btmp);
+  LAUNCH_OK();
+  bparts_to_host(h, h->Btmp, NB, 0, s);
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
+           (const double*)h->BX, x);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  double tr2[kBMax];
+  bhost_sums(h, NB, 0, tr2);
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (int j = 0; j < nr; ++j) {
+    all = all && conv_col[j];
+    if (st) {
+      st[j].iters = its_col[j];
+      st[j].converged = conv_col[j];
+      st[j].rel_res = nbv[j] > 0 ? rn[j] / nbv[j] : 0.0;
+      st[j].true_rel_res = nbv[j] > 0 ? std::sqrt(tr2[j]) / nbv[j] : 0.0;
+      st[j].rho = (its_col[j] > 0 && nbv[j] > 0) ? std::pow(rn[j] / nbv[j], 1.0 / its_col[j]) : 0.0;
+      st[j].seconds = secs;
+    }
+  }
+  return all ? LSAMG_OK : LSAMG_ENOCONV;
+}
+
+int solve_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
+                  int maxit, hipStream_t s, lsamg_stats* st) {
+  if (nr <= 8) return pcg_batched<8>(h, b, x, nr, ld, tol, maxit, s, st);
+  if (nr <= 16) return pcg_batched<16>(h, b, x, nr, ld, tol, maxit, s, st);
+  if (nr <= 32) return pcg_batched<32>(h, b, x, nr, ld, tol, maxit, s, st);
+  return pcg_batched<64>(h, b, x, nr, ld, tol, maxit, s, st);
+}
+
 int fail_with(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
@@ -860,10 +1216,19 @@ int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64
     ProfGuard pg(&h->prof);
     hipStream_t s = (hipStream_t)stream;
     int rc = LSAMG_OK;
-    for (int32_t c = 0; c < nrhs; ++c) {
-      int r1 = pcg_one(h, b + (size_t)c * ld, x + (size_t)c * ld, tol, maxit, s,
-                       stats ? stats + c : nullptr);
-      if (r1 != LSAMG_OK) rc = r1;
+    if (nrhs == 1 || h->batch_mode == 0) {
+      for (int32_t c = 0; c < nrhs; ++c) {
+        int r1 = pcg_one(h, b + (size_t)c * ld, x + (size_t)c * ld, tol, maxit, s,
+                         stats ? stats + c : nullptr);
+        if (r1 != LSAMG_OK) rc = r1;
+      }
+    } else {
+      for (int32_t c0 = 0; c0 < nrhs; c0 += kBMax) {
+        const int nr = std::min<int32_t>(kBMax, nrhs - c0);
+        int r1 = solve_batched(h, b + (size_t)c0 * ld, x + (size_t)c0 * ld, nr, ld, tol, maxit, s,
+                               stats ? stats + c0 : nullptr);
+        if (r1 != LSAMG_OK) rc = r1;
+      }
     }
     if (rc == LSAMG_ENOCONV) g_last_error = "maximum iterations reached";
     return rc;

@@ -181,15 +181,63 @@ def test_pcg_mixed(which, request):
     assert st[0]["iters"] <= math.ceil(1.10 * info["iters"])
 
 
-def test_multi_rhs_equals_single(rot):
+@pytest.mark.parametrize("nrhs", [3, 8, 20])
+def test_batched_equals_single(rot, nrhs):
+    """A batch of right-hand sides (one FP64 CG per column, shared matrix
+    reads) gives each column's single-vector iterate at equal iteration count
+    to 1e-10, and the same stop iteration (+-1)."""
     p, H, s = rot
-    import torch
-    B = np.stack([P.rhs_uniform(p.n, 100 + j) for j in range(4)])
+    s.set_precision(L.FP64)
+    B = np.stack([P.rhs_uniform(p.n, 100 + j) for j in range(nrhs)])
+    k = 12
+    X, st = s.solve(dvec(B), tol=0.0, maxit=k)
+    for j in range(nrhs):
+        x1, st1 = s.solve(dvec(B[j]), tol=0.0, maxit=k)
+        assert st[j]["iters"] == k
+        assert rel(host(X[j]), host(x1)) <= 1e-10
     X, st = s.solve(dvec(B), tol=1e-8)
-    for j in range(4):
+    for j in range(nrhs):
         x1, st1 = s.solve(dvec(B[j]), tol=1e-8)
-        assert torch.equal(X[j], x1)            # deterministic kernels: bit-identical
-        assert st[j]["iters"] == st1[0]["iters"]
+        assert abs(st[j]["iters"] - st1[0]["iters"]) <= 1
+        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1.01e-8
+        r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
+        assert r <= 1.01e-8
+
+
+def test_batched_mixed(rot):
+    p, H, s = rot
+    B = np.stack([P.rhs_uniform(p.n, 200 + j) for j in range(5)])
+    _, info = O.pcg(H, B[0], tol=1e-8)
+    s.set_precision(L.MIXED)
+    try:
+        X, st = s.solve(dvec(B), tol=1e-8)
+    finally:
+        s.set_precision(L.FP64)
+    for j in range(5):
+        r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
+        assert st[j]["converged"] == 1 and r <= 1.05e-8
+        assert st[j]["iters"] <= math.ceil(1.10 * info["iters"]) + 1
+
+
+def test_batched_edge_columns(cfg1):
+    """A zero column converges at once without disturbing the others; a
+    single-level hierarchy works in the batched path."""
+    p, H, s = cfg1
+    B = np.stack([P.rhs_uniform(p.n, 1), np.zeros(p.n), P.rhs_uniform(p.n, 2)])
+    X, st = s.solve(dvec(B), tol=1e-8)
+    assert st[1]["iters"] == 0 and st[1]["converged"] == 1 and np.all(host(X[1]) == 0)
+    for j in (0, 2):
+        r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
+        assert r <= 1.01e-8
+    q = P.aniso2d(12, 0.2, 0.3)
+    s1 = L.Solver(q.G, 2, q.grid, device=0)
+    Bq = np.stack([P.rhs_uniform(q.n, 5 + j) for j in range(3)])
+    Xq, stq = s1.solve(dvec(Bq), tol=1e-10)
+    A = (q.G.T @ q.G).toarray()
+    for j in range(3):
+        assert stq[j]["iters"] == 1
+        assert rel(host(Xq[j]), np.linalg.solve(A, Bq[j])) <= 1e-10
+    s1.close()
 
 
 def test_edge_zero_and_bad_rhs(cfg1):
@@ -289,4 +337,13 @@ def test_config2_full_size(gpu_device):
     x, st = s.solve(dvec(b), tol=1e-8)
     assert st[0]["converged"] == 1 and st[0]["true_rel_res"] <= 1.05e-8
     assert st[0]["iters"] <= math.ceil(1.10 * K)
+    # 64 right-hand sides (seeds 100-163) in one batch, mixed precision
+    B = np.stack([P.rhs_uniform(p.n, 100 + j) for j in range(64)])
+    X, st = s.solve(dvec(B), tol=1e-8)
+    for j in range(64):
+        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1.05e-8
+        assert st[j]["iters"] <= math.ceil(1.10 * K) + 1
+    for j in (0, 31, 63):
+        r = np.linalg.norm(B[j] - p.G.T @ (p.G @ host(X[j]))) / np.linalg.norm(B[j])
+        assert r <= 1.05e-8
     s.close()
