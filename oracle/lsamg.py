@@ -208,11 +208,13 @@ def coloring(C: sp.csr_matrix, S: sp.csr_matrix):
     """Greedy colouring (aggregates in index order, smallest free colour) of
     the graph ``i ~ j iff A(Omega_i, Omega_j) != 0`` (structural); and the
     largest number of overlapping aggregates that share one unknown."""
-    As = (S.T @ S).tocsr()
-    As.data[:] = 1.0
     Cb = C.copy()
     Cb.data[:] = 1.0
-    adj = (Cb.T @ As @ Cb).tocsr()
+    # A(Omega_i, Omega_j) != 0 iff some row of G touches both Omega_i and
+    # Omega_j: the pattern of C^T (S^T S) C, computed as (S C)^T (S C)
+    SC = (S @ Cb).tocsr()
+    SC.data[:] = 1.0
+    adj = (SC.T @ SC).tocsr()
     n_agg = adj.shape[0]
     color = -np.ones(n_agg, dtype=np.int64)
     for i in range(n_agg):
@@ -360,8 +362,8 @@ def _build_level(L: Level, l: int, p: Params, basis_hook):
         w, Om = L.omega[i], L.Omega[i]
         nw = len(w)
         At = local_splitting(L.G, L.nz[i], Om, L.M)
-        Gw = L.G[L.nz[i]][:, w]
-        Aww = (Gw.T @ Gw).toarray()                      # G_{nz,w}^T G_{nz,w}
+        # G_{nz,w}^T G_{nz,w} = A(w, w): rows outside nz vanish on w
+        Aww = L.A[w][:, w].toarray()
         St = schur_pinv(At, nw, p.pinv_rtol)
         mu, U = sla.eigh(St, Aww)                        # U^T Aww U = I
         k, hazard = select_count(mu, nw, p, l, L.thresh)
