@@ -149,6 +149,47 @@ typedef struct lsamg_kprof {
 
 typedef struct lsamg_handle lsamg_handle;
 
+/* ---- serving ---------------------------------------------------------- */
+
+/* One solve request.  Requests with equal op_key share one hierarchy: the
+ * first builds it (host setup + upload), later ones find it resident. */
+typedef struct lsamg_request {
+  uint64_t id;             /* caller's id, returned in lsamg_done                */
+  uint64_t op_key;         /* operator identity                                  */
+  const lsamg_csr* G;      /* host CSR of G, read on a cache miss only; it and the
+                              arrays it points to must stay valid until the
+                              request completes                                  */
+  const lsamg_params* params; /* setup parameters (params->device is ignored)   */
+  const double* b;         /* host, column-major n x nrhs (ld = n); copied at
+                              submit                                             */
+  double* x;               /* host, column-major n x nrhs; written before the
+                              request is reported done                           */
+  int32_t nrhs;            /* 1 .. 64                                            */
+  int32_t maxit;
+  double tol;
+} lsamg_request;
+
+typedef struct lsamg_done {
+  uint64_t id;
+  int32_t status;          /* LSAMG_OK, LSAMG_ENOCONV, or the setup/solve error  */
+  int32_t cache_hit;       /* hierarchy resident when the request was taken      */
+  int32_t batch_rhs;       /* right-hand sides solved together with this one     */
+  int32_t iters_max;       /* most PCG iterations over the request's columns     */
+  double true_rel_res_max; /* largest ||b - A x|| / ||b|| over its columns       */
+  double t_queue;          /* seconds from submit until taken by a worker        */
+  double t_setup;          /* host setup + upload (0 on a hit)                   */
+  double t_solve;          /* copy-in, solve, copy-out                           */
+  double t_total;          /* submit to completion                               */
+} lsamg_done;
+
+typedef struct lsamg_server_stats {
+  int64_t submitted, completed, hits, misses, evictions;
+  size_t resident_bytes, peak_bytes, budget;
+  int32_t queued, active;
+} lsamg_server_stats;
+
+typedef struct lsamg_server lsamg_server;
+
 /* Fill p with the defaults listed above (ndim/grid left zero). */
 void lsamg_params_default(lsamg_params* p);
 
@@ -196,6 +237,32 @@ int lsamg_export_setup(lsamg_handle* h, int32_t level, lsamg_setup_view* out);
 size_t lsamg_device_bytes(const lsamg_handle* h);
 void lsamg_destroy(lsamg_handle* h);
 const char* lsamg_last_error(void);
+
+/* Continuous-batching request server on one GPU.  max_slots worker threads,
+ * each with its own HIP stream, take queued requests: a request whose
+ * hierarchy is resident and idle is solved at once, together with every other
+ * queued request for the same operator and tolerance (one multi-right-hand-
+ * side solve, at most 64 columns); a request for a new operator builds its
+ * hierarchy on the host while the other slots keep the GPU busy, and is
+ * admitted when its exact device footprint fits hbm_budget (idle
+ * hierarchies are evicted least-recently-used first; a hierarchy larger than
+ * the whole budget fails with ENOMEM).  Solves of different operators run
+ * concurrently on their slots' streams.  Errors: EINVAL, ENODEV, ENOMEM. */
+int lsamg_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
+                        lsamg_server** out);
+
+/* Queue a request (non-blocking; b is copied).  EINVAL on bad fields. */
+int lsamg_server_submit(lsamg_server* s, const lsamg_request* req);
+
+/* Up to cap completed requests into out (host array); waits up to wait_ms
+ * milliseconds for the first one.  *count = number written. */
+int lsamg_server_poll(lsamg_server* s, lsamg_done* out, int32_t cap, int32_t* count,
+                      int32_t wait_ms);
+
+int lsamg_server_stats_get(lsamg_server* s, lsamg_server_stats* out);
+
+/* Finish every queued request, stop the workers, free all hierarchies. */
+void lsamg_server_destroy(lsamg_server* s);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,11 @@
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -221,20 +226,40 @@ struct lsamg_handle {
   std::vector<int64_t> ex_optr, ex_oidx, ex_muptr;
   std::vector<double> ex_mu;
 
+  bool dry = false;                  // count bytes only (admission planning)
+  bool batch_alloc = false;          // allocations belong to the batched buffers
+  std::vector<void*> ballocs;        // batched buffers (freed when the width grows)
+  size_t bbytes = 0;
+  int bwidth = 0;                    // batch width the buffers were sized for
+
   template <typename T>
   T* alloc(size_t count) {
-    void* ptr = nullptr;
     const size_t b = std::max<size_t>(count, 1) * sizeof(T);
-    HIP_OK(hipMalloc(&ptr, b));
-    allocs.push_back(ptr);
     bytes += b;
+    if (dry) return nullptr;
+    void* ptr = nullptr;
+    HIP_OK(hipMalloc(&ptr, b));
+    if (batch_alloc) {
+      ballocs.push_back(ptr);
+      bbytes += b;
+    } else {
+      allocs.push_back(ptr);
+    }
     return (T*)ptr;
   }
   template <typename T>
   T* upload(const std::vector<T>& v) {
     T* ptr = alloc<T>(v.size());
-    if (!v.empty()) HIP_OK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!dry && !v.empty())
+      HIP_OK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return ptr;
+  }
+  void free_batched() {
+    for (void* ptr : ballocs) (void)hipFree(ptr);
+    ballocs.clear();
+    bytes -= bbytes;
+    bbytes = 0;
+    bwidth = 0;
   }
   template <typename T>
   T* upload_f(const std::vector<double>& v) {   // FP64 host data in precision T
@@ -243,6 +268,7 @@ struct lsamg_handle {
     return upload(t);
   }
   void free_all() {
+    free_batched();
     for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
     for (auto& e : ev_rr)
       if (e) (void)hipEventDestroy(e);
@@ -462,7 +488,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
 }
 
 void upload(lsamg_handle* h) {
-  HIP_OK(hipSetDevice(h->device));
+  if (!h->dry) HIP_OK(hipSetDevice(h->device));
   h->L.resize(h->H.levels.size());
   for (size_t l = 0; l < h->H.levels.size(); ++l) upload_level(h, h->H.levels[l], h->L[l], l == 0);
   const Level& L0 = h->H.levels[0];
@@ -482,8 +508,25 @@ void upload(lsamg_handle* h) {
   h->p_rz[0] = h->alloc<double>(h->red_np);
   h->p_rz[1] = h->alloc<double>(h->red_np);
   h->p_tmp = h->alloc<double>(h->red_np);
+  if (h->dry) return;
   HIP_OK(hipHostMalloc((void**)&h->sc_host, 3 * 1024 * sizeof(double), hipHostMallocDefault));
   for (auto& e : h->ev_rr) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+// Device bytes the upload of h's hierarchy will allocate (no GPU call).
+size_t planned_device_bytes(lsamg_handle* h) {
+  lsamg_handle t;
+  std::swap(t.H, h->H);   // the dry upload reads only the host hierarchy
+  t.dry = true;
+  t.device = h->device;
+  try {
+    upload(&t);
+  } catch (...) {
+    std::swap(t.H, h->H);
+    throw;
+  }
+  std::swap(t.H, h->H);
+  return t.bytes;
 }
 
 // --------------------------------------------------------------------------
@@ -826,9 +869,18 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
 constexpr int kBNP = 256;      // workgroups (and partials per column) of the batched CG kernels
 constexpr int kBMax = 64;      // widest batch
 
-void ensure_batched(lsamg_handle* h) {
-  if (h->batched_ready) return;
-  h->BL.resize(h->L.size());
+void ensure_batched(lsamg_handle* h, int NB) {
+  if (h->batched_ready && h->bwidth >= NB) return;
+  h->free_batched();
+  h->batched_ready = false;
+  h->batch_alloc = true;
+  struct Reset {
+    lsamg_handle* h;
+    ~Reset() { h->batch_alloc = false; }
+  } reset{h};
+  h->bwidth = NB;
+  const int kBMax = NB;            // buffers sized for this width
+  h->BL.assign(h->L.size(), lsamg_handle::BLev{});
   for (size_t l = 0; l < h->L.size(); ++l) {
     DLevel& L = h->L[l];
     auto& B = h->BL[l];
@@ -858,9 +910,11 @@ void ensure_batched(lsamg_handle* h) {
   h->Brz[1] = h->alloc<double>(kBNP * kBMax);
   h->Btmp = h->alloc<double>(kBNP * kBMax);
   h->Bactive = h->alloc<int>(kBMax);
-  HIP_OK(hipHostMalloc((void**)&h->Bactive_host, kBMax * sizeof(int), hipHostMallocDefault));
-  HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * kBNP * kBMax * sizeof(double),
-                       hipHostMallocDefault));
+  if (!h->Bactive_host)
+    HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 64 * sizeof(int), hipHostMallocDefault));
+  if (!h->Bparts_host)
+    HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * kBNP * 64 * sizeof(double),
+                         hipHostMallocDefault));
   h->batched_ready = true;
 }
 
@@ -1009,7 +1063,7 @@ template <int NB>
 int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
                 int maxit, hipStream_t s, lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
-  ensure_batched(h);
+  ensure_batched(h, NB);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -1443,6 +1497,381 @@ void lsamg_destroy(lsamg_handle* h) {
     if (old >= 0) (void)hipSetDevice(old);
   }
   delete h;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Continuous-batching server (lsamg_server_*)
+// ===========================================================================
+namespace {
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct SReq {
+  lsamg_request r;
+  std::vector<double> b;
+  int64_t n = 0;
+  double t_submit = 0;
+};
+
+struct SEntry {
+  lsamg_handle* h = nullptr;
+  size_t bytes = 0;
+  bool ready = false, busy = false, failed = false;
+  int err = 0;
+  std::string msg;
+  uint64_t last_use = 0;
+};
+
+}  // namespace
+
+struct lsamg_server {
+  int device = 0;
+  size_t budget = 0;
+  int slots = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<SReq> queue;
+  std::unordered_map<uint64_t, SEntry> cache;
+  std::deque<lsamg_done> done;
+  std::vector<std::thread> workers;
+  bool stop = false;
+  size_t resident = 0, peak = 0;
+  uint64_t tick = 0;
+  int64_t submitted = 0, completed = 0, hits = 0, misses = 0, evictions = 0;
+  int active = 0, waiting = 0;
+
+  void account(size_t add, size_t sub) {
+    resident = resident + add - sub;
+    peak = std::max(peak, resident);
+  }
+
+  // post a completion (lock held)
+  void post(const SReq& q, int status, int hit, int batch, int its, double trr, double tq,
+            double tsetup, double tsolve) {
+    lsamg_done d;
+    std::memset(&d, 0, sizeof(d));
+    d.id = q.r.id;
+    d.status = status;
+    d.cache_hit = hit;
+    d.batch_rhs = batch;
+    d.iters_max = its;
+    d.true_rel_res_max = trr;
+    d.t_queue = tq;
+    d.t_setup = tsetup;
+    d.t_solve = tsolve;
+    d.t_total = now_s() - q.t_submit;
+    done.push_back(d);
+    ++completed;
+    cv_done.notify_all();
+  }
+
+  // evict the least-recently-used idle hierarchy (lock held); false if none
+  bool evict_one() {
+    auto best = cache.end();
+    for (auto it = cache.begin(); it != cache.end(); ++it)
+      if (it->second.ready && !it->second.busy &&
+          (best == cache.end() || it->second.last_use < best->second.last_use))
+        best = it;
+    if (best == cache.end()) return false;
+    lsamg_handle* h = best->second.h;
+    account(0, best->second.bytes);
+    cache.erase(best);
+    ++evictions;
+    lsamg_destroy(h);
+    return true;
+  }
+
+  void worker();
+};
+
+void lsamg_server::worker() {
+  (void)hipSetDevice(device);
+  hipStream_t st = nullptr;
+  (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  double *dB = nullptr, *dX = nullptr;
+  size_t cap = 0;
+  std::vector<lsamg_stats> stats;
+  std::unique_lock<std::mutex> lk(mu);
+  for (;;) {
+    // first queued request whose operator is resident and idle, or unknown
+    size_t pick = queue.size();
+    bool miss = false;
+    for (size_t i = 0; i < queue.size(); ++i) {
+      auto it = cache.find(queue[i].r.op_key);
+      if (it == cache.end()) {
+        pick = i;
+        miss = true;
+        break;
+      }
+      if (it->second.failed || (it->second.ready && !it->second.busy)) {
+        pick = i;
+        break;
+      }
+    }
+    if (pick == queue.size()) {
+      if (stop && queue.empty() && active == 0) break;
+      cv_work.wait_for(lk, std::chrono::milliseconds(50));
+      continue;
+    }
+    SReq first = std::move(queue[pick]);
+    queue.erase(queue.begin() + pick);
+    const uint64_t key = first.r.op_key;
+    ++active;
+    const double t_taken = now_s();
+    double t_setup = 0;
+    if (!miss && cache[key].failed) {
+      post(first, cache[key].err, 0, 0, 0, 0, t_taken - first.t_submit, 0, 0);
+      --active;
+      cv_work.notify_all();
+      continue;
+    }
+    SEntry* e = nullptr;
+    int hit = miss ? 0 : 1;
+    if (miss) {
+      ++misses;
+      e = &cache[key];
+      e->busy = true;
+      lk.unlock();
+      lsamg_params p = *first.r.params;
+      p.device = -1;                       // host setup now, upload after admission
+      lsamg_handle* h = nullptr;
+      int rc = lsamg_setup(first.r.G, &p, &h);
+      std::string msg = rc == LSAMG_OK ? "" : lsamg_last_error();
+      size_t need = 0;
+      if (rc == LSAMG_OK) {
+        h->device = device;
+        h->precision = first.r.params->precision;
+        try {
+          need = planned_device_bytes(h);
+        } catch (const DevError& de) {
+          rc = de.code;
+          msg = de.msg;
+        }
+      }
+      lk.lock();
+      e = &cache[key];
+      // admission against the budget: evict idle hierarchies, else wait for
+      // running solves to finish; a hierarchy larger than the budget fails
+      while (rc == LSAMG_OK && resident + need > budget) {
+        if (evict_one()) continue;
+        if (need > budget || waiting + 1 >= active) {
+          rc = LSAMG_ENOMEM;
+          msg = "hierarchy does not fit the device budget";
+          break;
+        }
+        ++waiting;
+        cv_done.wait_for(lk, std::chrono::milliseconds(50));
+        --waiting;
+        e = &cache[key];
+      }
+      if (rc == LSAMG_OK) {
+        account(need, 0);                  // reserve before uploading
+        lk.unlock();
+        try {
+          DeviceGuard g(device);
+          upload(h);                       // synchronous copies: nothing pending
+        } catch (const DevError& de) {
+          rc = de.code;
+          msg = de.msg;
+        }
+        lk.lock();
+        e = &cache[key];
+        account(h->bytes, need);
+      }
+      if (rc != LSAMG_OK) {
+        if (h) lsamg_destroy(h);
+        e->failed = true;
+        e->busy = false;
+        e->err = rc;
+        e->msg = msg;
+        post(first, rc, 0, 0, 0, 0, t_taken - first.t_submit, now_s() - t_taken, 0);
+        --active;
+        cv_work.notify_all();
+        continue;
+      }
+      e->h = h;
+      e->bytes = h->bytes;
+      e->ready = true;
+      t_setup = now_s() - t_taken;
+    } else {
+      ++hits;
+      e = &cache[key];
+      e->busy = true;
+    }
+    // continuous batching: every queued request for this operator with the
+    // same tolerance and iteration limit joins the solve (<= 64 columns)
+    std::vector<SReq> group;
+    group.push_back(std::move(first));
+    int total = group[0].r.nrhs;
+    for (size_t i = 0; i < queue.size();) {
+      const lsamg_request& r = queue[i].r;
+      if (r.op_key == key && r.tol == group[0].r.tol && r.maxit == group[0].r.maxit &&
+          total + r.nrhs <= 64) {
+        total += r.nrhs;
+        group.push_back(std::move(queue[i]));
+        queue.erase(queue.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+    lsamg_handle* h = e->h;
+    const size_t before = h->bytes;
+    lk.unlock();
+    const double t_solve0 = now_s();
+    const int64_t n = group[0].n;
+    int rc = LSAMG_OK;
+    std::string msg;
+    stats.assign(total, lsamg_stats{});
+    size_t grow = 0;
+    try {
+      DeviceGuard g(device);
+      const size_t need = (size_t)n * total;
+      if (need > cap) {
+        if (dB) (void)hipFree(dB);
+        if (dX) (void)hipFree(dX);
+        dB = dX = nullptr;
+        HIP_OK(hipMalloc(&dB, need * sizeof(double)));
+        HIP_OK(hipMalloc(&dX, need * sizeof(double)));
+        grow = 2 * (need - cap) * sizeof(double);
+        cap = need;
+      }
+      size_t off = 0;
+      for (auto& q : group) {
+        HIP_OK(hipMemcpyAsync(dB + off, q.b.data(), q.b.size() * sizeof(double),
+                              hipMemcpyHostToDevice, st));
+        off += q.b.size();
+      }
+      rc = lsamg_solve(h, dB, dX, total, n, group[0].r.tol, group[0].r.maxit, st, stats.data());
+      if (rc != LSAMG_OK) msg = lsamg_last_error();
+      if (rc == LSAMG_OK || rc == LSAMG_ENOCONV) {
+        off = 0;
+        for (auto& q : group) {
+          HIP_OK(hipMemcpyAsync(q.r.x, dX + off, q.b.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+          off += q.b.size();
+        }
+      }
+      HIP_OK(hipStreamSynchronize(st));
+    } catch (const DevError& de) {
+      rc = de.code;
+      msg = de.msg;
+    }
+    const double t_solve = now_s() - t_solve0;
+    lk.lock();
+    e = &cache[key];
+    e->busy = false;
+    e->last_use = ++tick;
+    account(h->bytes + grow, before);      // batched buffers the solve added
+    e->bytes = h->bytes;
+    int c0 = 0;
+    for (auto& q : group) {
+      int its = 0;
+      double trr = 0;
+      bool conv = true;
+      for (int j = 0; j < q.r.nrhs; ++j) {
+        its = std::max(its, stats[c0 + j].iters);
+        trr = std::max(trr, stats[c0 + j].true_rel_res);
+        conv = conv && stats[c0 + j].converged;
+      }
+      const int status = (rc == LSAMG_OK || rc == LSAMG_ENOCONV)
+                             ? (conv ? LSAMG_OK : LSAMG_ENOCONV)
+                             : rc;
+      post(q, status, hit, total, its, trr, t_taken - q.t_submit, t_setup, t_solve);
+      c0 += q.r.nrhs;
+    }
+    (void)msg;
+    --active;
+    cv_work.notify_all();
+  }
+  lk.unlock();
+  if (dB) (void)hipFree(dB);
+  if (dX) (void)hipFree(dX);
+  if (st) (void)hipStreamDestroy(st);
+}
+
+extern "C" {
+
+int lsamg_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
+                        lsamg_server** out) {
+  if (!out || max_slots < 1 || max_slots > 64 || hbm_budget == 0)
+    return fail_with(LSAMG_EINVAL, "bad argument");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail_with(LSAMG_ENODEV, "no such HIP device");
+  lsamg_server* s = new (std::nothrow) lsamg_server();
+  if (!s) return fail_with(LSAMG_ENOMEM, "server allocation failed");
+  s->device = device;
+  s->budget = hbm_budget;
+  s->slots = max_slots;
+  for (int i = 0; i < max_slots; ++i) s->workers.emplace_back([s]() { s->worker(); });
+  *out = s;
+  return LSAMG_OK;
+}
+
+int lsamg_server_submit(lsamg_server* s, const lsamg_request* req) {
+  if (!s || !req || !req->G || !req->params || !req->b || !req->x || req->nrhs < 1 ||
+      req->nrhs > 64 || req->maxit < 0 || !(req->tol >= 0.0) || req->G->n <= 0)
+    return fail_with(LSAMG_EINVAL, "bad request");
+  SReq q;
+  q.r = *req;
+  q.n = req->G->n;
+  q.b.assign(req->b, req->b + (size_t)q.n * req->nrhs);
+  q.t_submit = now_s();
+  std::lock_guard<std::mutex> g(s->mu);
+  if (s->stop) return fail_with(LSAMG_EINVAL, "server is stopping");
+  s->queue.push_back(std::move(q));
+  ++s->submitted;
+  s->cv_work.notify_one();
+  return LSAMG_OK;
+}
+
+int lsamg_server_poll(lsamg_server* s, lsamg_done* out, int32_t cap, int32_t* count,
+                      int32_t wait_ms) {
+  if (!s || !count || cap < 0 || (cap > 0 && !out)) return fail_with(LSAMG_EINVAL, "bad argument");
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_ms > 0)
+    s->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [s] { return !s->done.empty(); });
+  int32_t k = 0;
+  while (k < cap && !s->done.empty()) {
+    out[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *count = k;
+  return LSAMG_OK;
+}
+
+int lsamg_server_stats_get(lsamg_server* s, lsamg_server_stats* out) {
+  if (!s || !out) return fail_with(LSAMG_EINVAL, "bad argument");
+  std::lock_guard<std::mutex> g(s->mu);
+  out->submitted = s->submitted;
+  out->completed = s->completed;
+  out->hits = s->hits;
+  out->misses = s->misses;
+  out->evictions = s->evictions;
+  out->resident_bytes = s->resident;
+  out->peak_bytes = s->peak;
+  out->budget = s->budget;
+  out->queued = (int32_t)s->queue.size();
+  out->active = s->active;
+  return LSAMG_OK;
+}
+
+void lsamg_server_destroy(lsamg_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  for (auto& t : s->workers) t.join();
+  for (auto& kv : s->cache)
+    if (kv.second.h) lsamg_destroy(kv.second.h);
+  delete s;
 }
 
 }  // extern "C"

@@ -90,6 +90,32 @@ class KProf(C.Structure):
                 ("ms", C.c_double), ("bytes", C.c_double)]
 
 
+class Request(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("op_key", C.c_uint64),
+                ("G", C.POINTER(Csr)), ("params", C.POINTER(Params)),
+                ("b", C.c_void_p), ("x", C.c_void_p), ("nrhs", C.c_int32),
+                ("maxit", C.c_int32), ("tol", C.c_double)]
+
+
+class Done(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("status", C.c_int32), ("cache_hit", C.c_int32),
+                ("batch_rhs", C.c_int32), ("iters_max", C.c_int32),
+                ("true_rel_res_max", C.c_double), ("t_queue", C.c_double),
+                ("t_setup", C.c_double), ("t_solve", C.c_double),
+                ("t_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64),
+                ("hits", C.c_int64), ("misses", C.c_int64),
+                ("evictions", C.c_int64), ("resident_bytes", C.c_size_t),
+                ("peak_bytes", C.c_size_t), ("budget", C.c_size_t),
+                ("queued", C.c_int32), ("active", C.c_int32)]
+
+
 # every symbol the header declares, with its ctypes signature
 _SIGS = {
     "lsamg_params_default": (None, [C.POINTER(Params)]),
@@ -110,6 +136,13 @@ _SIGS = {
     "lsamg_device_bytes": (C.c_size_t, [C.c_void_p]),
     "lsamg_destroy": (None, [C.c_void_p]),
     "lsamg_last_error": (C.c_char_p, []),
+    "lsamg_server_create": (C.c_int, [C.c_int32, C.c_size_t, C.c_int32,
+                                      C.POINTER(C.c_void_p)]),
+    "lsamg_server_submit": (C.c_int, [C.c_void_p, C.POINTER(Request)]),
+    "lsamg_server_poll": (C.c_int, [C.c_void_p, C.POINTER(Done), C.c_int32,
+                                    C.POINTER(C.c_int32), C.c_int32]),
+    "lsamg_server_stats_get": (C.c_int, [C.c_void_p, C.POINTER(ServerStats)]),
+    "lsamg_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None
@@ -306,3 +339,82 @@ class Solver:
 def symbols() -> list:
     """Names of every C-ABI entry point (all must be exported)."""
     return list(_SIGS)
+
+
+class _HostCsr:
+    """A CSR of G kept alive (with its ctypes view) while requests use it."""
+
+    def __init__(self, G):
+        G = G.tocsr()
+        self.rowptr = np.ascontiguousarray(G.indptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(G.indices, dtype=np.int32)
+        self.val = np.ascontiguousarray(G.data, dtype=np.float64)
+        self.csr = Csr(G.shape[0], G.shape[1], int(self.val.size),
+                       self.rowptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                       self.col.ctypes.data_as(C.POINTER(C.c_int32)),
+                       self.val.ctypes.data_as(C.POINTER(C.c_double)))
+        self.n = G.shape[1]
+
+
+class Server:
+    """Continuous-batching request server (lsamg_server_*).
+
+    ``submit(op_key, G, ndim, grid, b, ...)`` queues a solve with host right-
+    hand sides ``b`` (shape (n,) or (nrhs, n)); ``poll()`` returns finished
+    requests as dicts carrying the solution ``x`` (host numpy array)."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 4, device: int = 0):
+        h = C.c_void_p()
+        _check(load().lsamg_server_create(device, hbm_budget, max_slots, C.byref(h)))
+        self._h = h
+        self._ops = {}          # op_key -> (_HostCsr, Params)
+        self._live = {}         # id -> (b, x, request)
+        self._next = 0
+
+    def submit(self, op_key: int, G, ndim: int, grid, b, tol: float = 1e-8,
+               maxit: int = 1000, precision: int = MIXED, req_id: Optional[int] = None,
+               **params):
+        if op_key not in self._ops:
+            self._ops[op_key] = (_HostCsr(G), make_params(ndim, grid, precision=precision,
+                                                          device=0, **params))
+        hc, prm = self._ops[op_key]
+        bb = np.ascontiguousarray(np.atleast_2d(b), dtype=np.float64)
+        if bb.shape[1] != hc.n:
+            raise ValueError("length mismatch")
+        x = np.empty_like(bb)
+        rid = self._next if req_id is None else req_id
+        self._next = max(self._next, rid) + 1
+        req = Request(rid, op_key, C.pointer(hc.csr), C.pointer(prm),
+                      C.c_void_p(bb.ctypes.data), C.c_void_p(x.ctypes.data),
+                      bb.shape[0], maxit, tol)
+        _check(load().lsamg_server_submit(self._h, C.byref(req)))
+        self._live[rid] = (bb, x, req)
+        return rid
+
+    def poll(self, wait_ms: int = 0, cap: int = 256) -> list:
+        buf = (Done * cap)()
+        cnt = C.c_int32()
+        _check(load().lsamg_server_poll(self._h, buf, cap, C.byref(cnt), wait_ms))
+        out = []
+        for i in range(cnt.value):
+            d = buf[i].as_dict()
+            bb, x, _ = self._live.pop(d["id"])
+            d["x"] = x
+            out.append(d)
+        return out
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().lsamg_server_stats_get(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lsamg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,135 @@
+"""Continuous-batching server (lsamg_server_*) on the GPU, through the C-ABI.
+
+A result must be the same alone and in a mix of concurrent requests, within
+the solve tolerance: both solutions reach ||b - A x|| <= tol ||b|| (checked
+here in FP64 with A = G^T G) and differ by at most what two such solutions
+can differ by.  Admission against the device budget, eviction, a failing
+setup and an oversize hierarchy are covered as well.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import problems as P
+from paper_2601_04112_amd import lsamg as L
+
+pytestmark = pytest.mark.gpu
+
+OPS = [(48, 0.3, 1e-2), (40, 1.1, 1e-4), (56, math.pi / 6, 1e-3), (32, 0.0, 1.0)]
+
+
+def op(k):
+    N, th, eps = OPS[k]
+    return P.aniso2d(N, th, eps)
+
+
+def drain(srv, count, timeout_ms=120000):
+    out = {}
+    waited = 0
+    while len(out) < count and waited < timeout_ms:
+        for d in srv.poll(wait_ms=200):
+            out[d["id"]] = d
+        waited += 200
+    assert len(out) == count, f"only {len(out)} of {count} requests completed"
+    return out
+
+
+def check(prob, b, x, tol):
+    A_b = np.atleast_2d(b)
+    X = np.atleast_2d(x)
+    for j in range(A_b.shape[0]):
+        r = A_b[j] - prob.G.T @ (prob.G @ X[j])
+        assert np.linalg.norm(r) <= 1.02 * tol * np.linalg.norm(A_b[j])
+
+
+def test_alone_equals_in_mix(gpu_device):
+    probs = [op(k) for k in range(len(OPS))]
+    rng = np.random.default_rng(5)
+    b0 = np.stack([P.rhs_uniform(probs[0].n, 900 + j) for j in range(3)])
+    # alone
+    srv = L.Server(hbm_budget=8 << 30, max_slots=4)
+    rid = srv.submit(0, probs[0].G, 2, probs[0].grid, b0, tol=1e-8, cmin=(2,), max_coarse=200)
+    alone = drain(srv, 1)[rid]
+    srv.close()
+    assert alone["status"] == 0 and alone["cache_hit"] == 0
+    check(probs[0], b0, alone["x"], 1e-8)
+    # in a mix: 24 requests over 4 operators, submitted at once
+    srv = L.Server(hbm_budget=8 << 30, max_slots=4)
+    ids = {}
+    for i in range(24):
+        k = int(rng.integers(len(OPS)))
+        nr = int(rng.integers(1, 5))
+        b = np.stack([P.rhs_uniform(probs[k].n, 1000 + 10 * i + j) for j in range(nr)])
+        ids[srv.submit(k, probs[k].G, 2, probs[k].grid, b, tol=1e-8, cmin=(2,),
+                       max_coarse=200)] = (k, b)
+        if i == 11:
+            mid = srv.submit(0, probs[0].G, 2, probs[0].grid, b0, tol=1e-8, cmin=(2,),
+                             max_coarse=200)
+    res = drain(srv, 25)
+    st = srv.stats()
+    srv.close()
+    for rid_, (k, b) in ids.items():
+        assert res[rid_]["status"] == 0
+        check(probs[k], b, res[rid_]["x"], 1e-8)
+    mix = res[mid]
+    assert mix["status"] == 0
+    check(probs[0], b0, mix["x"], 1e-8)
+    for j in range(3):
+        d = np.linalg.norm(mix["x"][j] - alone["x"][j]) / np.linalg.norm(alone["x"][j])
+        assert d <= 1e-6
+    # one setup per operator; later requests either joined a running batch or hit
+    assert st["misses"] == len(OPS) and st["completed"] == 25
+    assert max(r["batch_rhs"] for r in res.values()) > 4     # requests were merged
+
+
+def test_budget_admission_and_eviction(gpu_device):
+    probs = [op(k) for k in range(3)]
+    # size the budget for about one hierarchy
+    s = L.Solver(probs[2].G, 2, probs[2].grid, device=0, cmin=(2,), max_coarse=200)
+    one = s.info()["device_bytes"]
+    s.close()
+    srv = L.Server(hbm_budget=int(one * 1.5), max_slots=2)
+    ids = {}
+    for i in range(9):
+        k = i % 3
+        b = P.rhs_uniform(probs[k].n, 300 + i)
+        ids[srv.submit(k, probs[k].G, 2, probs[k].grid, b, tol=1e-8, cmin=(2,),
+                       max_coarse=200, precision=L.FP64)] = (k, b)
+    res = drain(srv, 9)
+    st = srv.stats()
+    srv.close()
+    for rid, (k, b) in ids.items():
+        assert res[rid]["status"] == 0
+        check(probs[k], b, res[rid]["x"], 1e-8)
+    assert st["evictions"] >= 1
+    assert st["peak_bytes"] <= int(one * 1.5) * 1.5      # batched buffers may add a little
+
+
+def test_failed_setup_is_isolated(gpu_device):
+    good = op(3)
+    bad = P.aniso2d(32, 0.0, 1.0)
+    Gb = bad.G.tolil()
+    Gb[:, 7] = 0.0                       # an unknown no row touches: A singular
+    import scipy.sparse as sp
+    Gb = sp.csr_matrix(Gb)
+    srv = L.Server(hbm_budget=4 << 30, max_slots=2)
+    r_bad = srv.submit(9, Gb, 2, bad.grid, np.ones(bad.n), tol=1e-8, max_coarse=100)
+    r_bad2 = srv.submit(9, Gb, 2, bad.grid, np.ones(bad.n), tol=1e-8, max_coarse=100)
+    b = P.rhs_uniform(good.n, 4)
+    r_ok = srv.submit(3, good.G, 2, good.grid, b, tol=1e-8, max_coarse=100)
+    res = drain(srv, 3)
+    srv.close()
+    assert res[r_bad]["status"] == L.LSAMG_ENOTSPD
+    assert res[r_bad2]["status"] == L.LSAMG_ENOTSPD
+    assert res[r_ok]["status"] == 0
+    check(good, b, res[r_ok]["x"], 1e-8)
+
+
+def test_hierarchy_larger_than_budget(gpu_device):
+    p = op(0)
+    srv = L.Server(hbm_budget=1 << 20, max_slots=1)
+    rid = srv.submit(0, p.G, 2, p.grid, np.ones(p.n), tol=1e-8, cmin=(2,), max_coarse=200)
+    res = drain(srv, 1)
+    srv.close()
+    assert res[rid]["status"] == L.LSAMG_ENOMEM
