@@ -61,6 +61,82 @@ def percentile(v, q):
     return v[lo] + (v[hi] - v[lo]) * (k - lo)
 
 
+def run_serving(args):
+    """Request stream: Poisson arrivals at args.qps, operators drawn from a
+    seeded pool of args.pool distinct 2D problems (N in {64,...,1024}, theta
+    ~ U[0, pi), log10 eps ~ U[-6, 0]), 1-8 right-hand sides each, FP32
+    V-cycle under FP64 CG to 1e-8.  Hierarchies stay resident (HBM budget
+    args.budget_gb) and requests for a busy or resident operator are merged."""
+    import numpy as np
+    import problems as P
+    from paper_2601_04112_amd import lsamg as L
+
+    rng = np.random.default_rng(5)
+    sizes = [64, 128, 256, 512, 1024]
+    pool = []
+    for k in range(args.pool):
+        N = int(rng.choice(sizes))
+        pool.append((N, float(rng.uniform(0, math.pi)), float(10 ** rng.uniform(-6, 0))))
+    reqs = []
+    t = 0.0
+    for i in range(args.requests):
+        t += float(rng.exponential(1.0 / args.qps))
+        reqs.append((t, int(rng.integers(args.pool)), int(rng.integers(1, 9)), 10000 + 8 * i))
+    probs = {}
+    srv = L.Server(hbm_budget=int(args.budget_gb * (1 << 30)), max_slots=args.slots)
+    done = {}
+    t0 = time.perf_counter()
+    t_report = t0
+    i = 0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while i < len(reqs) and reqs[i][0] <= now:
+            _, k, nr, seed = reqs[i]
+            if k not in probs:
+                probs[k] = P.aniso2d(*pool[k])
+            p = probs[k]
+            b = np.stack([P.rhs_uniform(p.n, seed + j) for j in range(nr)])
+            srv.submit(k, p.G, 2, p.grid, b, tol=1e-8, precision=L.MIXED, req_id=i,
+                       cmin=(2,))
+            i += 1
+        wait = 5 if i >= len(reqs) else max(0, int((reqs[i][0] - now) * 1e3))
+        for d in srv.poll(wait_ms=min(wait, 20)):
+            d.pop("x")
+            done[d["id"]] = d
+        if time.perf_counter() - t_report > 5.0:
+            t_report = time.perf_counter()
+            print(f"[serve] t={t_report - t0:.0f}s submitted {i}/{len(reqs)} "
+                  f"done {len(done)}", file=sys.stderr, flush=True)
+    makespan = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = [d["t_total"] * 1e3 for d in done.values()]
+    hit_lat = [d["t_total"] * 1e3 for d in done.values() if d["cache_hit"]]
+    solve_lat = [(d["t_queue"] + d["t_solve"]) * 1e3 for d in done.values()]
+    nrhs_total = sum(r[2] for r in reqs)
+    ok = sum(1 for d in done.values() if d["status"] == 0)
+    line = {
+        "metric": "serving: solves/s and p50/p99 latency, 1e-8 rel. residual",
+        "value": round(nrhs_total / makespan, 2), "unit": "solves/s",
+        "requests": len(reqs), "rhs_total": nrhs_total, "qps": args.qps,
+        "makespan_s": round(makespan, 2), "ok": ok,
+        "p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
+        "p50_ms_hit": round(percentile(hit_lat, 0.5), 2) if hit_lat else None,
+        "p99_ms_hit": round(percentile(hit_lat, 0.99), 2) if hit_lat else None,
+        "p50_ms_excl_setup": round(percentile(solve_lat, 0.5), 2),
+        "p99_ms_excl_setup": round(percentile(solve_lat, 0.99), 2),
+        "max_true_rel_res": max(d["true_rel_res_max"] for d in done.values()),
+        "max_batch_rhs": max(d["batch_rhs"] for d in done.values()),
+        "setup_s_total": round(sum(d["t_setup"] for d in done.values()), 1),
+        "server": st, "pool": args.pool, "slots": args.slots,
+        "dtype": "f32 V-cycle / f64 CG", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} Poisson requests at {args.qps}/s over a pool of "
+                               f"{args.pool} aniso2d operators, N in {sizes}, theta~U[0,pi), "
+                               f"log10 eps~U[-6,0], 1-8 rhs"},
+    }
+    print(json.dumps(line))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,7 +146,21 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=2,
                     help="PCG iterations of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="right-hand sides of the batched workload (0: skip)")
+    ap.add_argument("--serve", action="store_true",
+                    help="run the request-stream serving benchmark instead")
+    ap.add_argument("--qps", type=float, default=50.0)
+    ap.add_argument("--requests", type=int, default=1024)
+    ap.add_argument("--pool", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--budget-gb", type=float, default=160.0)
     args = ap.parse_args()
+    if args.serve:
+        if args.gpus != 1:
+            sys.exit(2)
+        run_serving(args)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the per-GPU shard would be a block of aggregates; see the "
@@ -136,6 +226,37 @@ def main():
 
     mixed, kp = timed(L.MIXED, args.steps, args.warmup, only=dominant)
     fp64, _ = timed(L.FP64, args.steps, args.warmup)
+
+    # batched workload: the same operator with 64 right-hand sides (seeds
+    # 100-163) solved together, one FP64 CG per column, FP32 V-cycle
+    batched = None
+    if args.batch > 0:
+        B = torch.tensor([P.rhs_uniform(prob.n, 100 + j) for j in range(args.batch)],
+                         dtype=torch.float64, device="cuda:0")
+        XB = torch.empty_like(B)
+        s.set_precision(L.MIXED)
+        s.solve(B, tol=1e-8, out=XB)
+        s.profile(True)
+        s.solve(B, tol=1e-8, out=XB)
+        bk = sorted(s.profile_read(), key=lambda r: -r["ms"])
+        s.profile(False)
+        nb_steps = max(2, args.steps // 4)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(nb_steps):
+            _, bst = s.solve(B, tol=1e-8, out=XB)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t1
+        its = [r["iters"] for r in bst]
+        batched = dict(nrhs=args.batch, solves_per_s=round(args.batch * nb_steps / el, 2),
+                       ms_per_batch=round(el * 1e3 / nb_steps, 3), steps=nb_steps,
+                       iters_min=min(its), iters_max=max(its),
+                       all_converged=all(r["converged"] for r in bst),
+                       max_true_rel_res=max(r["true_rel_res"] for r in bst),
+                       top_kernels=[dict(name=r["name"], ms_per_batch=round(r["ms"], 3),
+                                         launches=r["launches"],
+                                         gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1))
+                                    for r in bk[:5]])
     dom = next((r for r in kp if r["name"] == dominant), None)
     roofline = None
     if dom and dom["launches"] > 0 and dom["ms"] > 0:
@@ -199,7 +320,9 @@ def main():
         "iters": mixed["iters"],
         "true_rel_res": mixed["true_rel_res"],
         "vcycles_per_s": round(mixed["solves_per_s"] * (mixed["iters"] + 1), 1),
-        "fp64": {k: (round(v, 4) if isinstance(v, float) else v) for k, v in fp64.items()},
+        "fp64": {k: (round(v, 4) if isinstance(v, float) and k != "true_rel_res" else v)
+                 for k, v in fp64.items()},
+        "batched_mixed": batched,
         "mixed_vs_fp64_speedup": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
         "top_kernels": [dict(name=r["name"], ms_per_solve=round(r["ms"], 3),
                              launches=r["launches"],
