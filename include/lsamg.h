@@ -222,7 +222,8 @@ int lsamg_set_precision(lsamg_handle* h, int32_t precision);
 /* Kernel timing.  mode 1: bracket every kernel launch of later solve /
  * apply calls with a pair of HIP events recorded on the launch stream; if
  * only != NULL, only launches of that kernel symbol are bracketed (the others
- * run undisturbed).  mode 0: stop.  Recording is bounded (65536 launches).
+ * run undisturbed).  mode 2: as mode 1, with the V-cycle kernels reported per
+ * hierarchy level (name suffix " @L<level>").  mode 0: stop.  Recording is bounded (65536 launches).
  * Each record also carries the launch's algorithmic bytes: the bytes the
  * kernel must move at least (matrix entries, index lists, every distinct
  * vector entry read once, outputs). */

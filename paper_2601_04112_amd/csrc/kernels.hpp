@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_t(int64_t n, const int64_t* __
 // Lanes run along j (coalesced loads), the loop runs along l, and every
 // output is reduced in a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
-enum { IN_DIRECT = 0, IN_GATHER = 1, IN_TB = 2 };
+enum { IN_DIRECT = 0, IN_GATHER = 1, IN_TB = 2, IN_RESG = 3 };
 
 struct GemvOp {
   const int64_t* moff;   // [nagg] offset of M_a
@@ -122,19 +122,35 @@ struct GemvOp {
   const int64_t* obase;  // [nagg] output base
 };
 
+// Where the input vector entries come from (MODE):
+//   IN_DIRECT  in[i]
+//   IN_GATHER  in[idx[i]]
+//   IN_TB      in[i] + sum_{e in [ptr[i], ptr[i+1])} v1[pos[e]]       (staged RAS-T)
+//   IN_RESG    in[i] - sum_{e in [ptr[i], ptr[i+1])} v1[e] * v2[idx[e]] (row i of G^T
+//              applied to v2 = G x): the residual b - A x formed on the fly, so
+//              the residual vector of the level is never written to memory
+template <typename T>
+struct InSpec {
+  const int32_t* idx;
+  const int64_t* ptr;
+  const int64_t* pos;
+  const T* v1;
+  const T* v2;
+};
+
 template <typename T, int MODE>
-__device__ __forceinline__ T load_in(const T* __restrict__ in, int64_t i,
-                                     const int32_t* __restrict__ gidx,
-                                     const int64_t* __restrict__ cptr,
-                                     const int64_t* __restrict__ cpos,
-                                     const T* __restrict__ tb) {
-  if (MODE == IN_GATHER) return in[gidx[i]];
+__device__ __forceinline__ T load_in(const T* __restrict__ in, int64_t i, const InSpec<T>& sp) {
+  if (MODE == IN_GATHER) return in[sp.idx[i]];
+  if (MODE == IN_DIRECT) return in[i];
+  const int64_t e0 = sp.ptr[i], e1 = sp.ptr[i + 1];
+  T v = in[i];
   if (MODE == IN_TB) {
-    T v = in[i];
-    for (int64_t e = cptr[i]; e < cptr[i + 1]; ++e) v += tb[cpos[e]];
+    for (int64_t e = e0; e < e1; ++e) v += sp.v1[sp.pos[e]];
     return v;
   }
-  return in[i];
+  T t = 0;
+  for (int64_t e = e0; e < e1; ++e) t += sp.v1[e] * sp.v2[sp.idx[e]];
+  return v - t;
 }
 
 // Narrow form (every lj_a <= G <= 64): one wavefront per aggregate, the
@@ -142,10 +158,7 @@ __device__ __forceinline__ T load_in(const T* __restrict__ in, int64_t i,
 // aggregates per 256-thread workgroup.  LDS: 4 * lmax * sizeof(T).
 template <typename T, int MODE, bool ADD, int G>
 __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op, int lmax,
-                                                        const int32_t* __restrict__ gidx,
-                                                        const int64_t* __restrict__ cptr,
-                                                        const int64_t* __restrict__ cpos,
-                                                        const T* __restrict__ tb,
+                                                        InSpec<T> spec,
                                                         const T* __restrict__ M,
                                                         const T* __restrict__ in,
                                                         T* __restrict__ out) {
@@ -160,7 +173,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
     nj = op.lj[a];
     nl = op.ll[a];
     const int64_t ib = op.ibase[a];
-    for (int l = lane; l < nl; l += 64) sv[l] = load_in<T, MODE>(in, ib + l, gidx, cptr, cpos, tb);
+    for (int l = lane; l < nl; l += 64) sv[l] = load_in<T, MODE>(in, ib + l, spec);
   }
   __syncthreads();
   if (!valid) return;
@@ -195,11 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
 template <typename T, int MODE, bool ADD, int NW>
 __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict__ task_a,
                                                        const int32_t* __restrict__ task_j0,
-                                                       GemvOp op, int lmax,
-                                                       const int32_t* __restrict__ gidx,
-                                                       const int64_t* __restrict__ cptr,
-                                                       const int64_t* __restrict__ cpos,
-                                                       const T* __restrict__ tb,
+                                                       GemvOp op, int lmax, InSpec<T> spec,
                                                        const T* __restrict__ M,
                                                        const T* __restrict__ in,
                                                        T* __restrict__ out) {
@@ -211,7 +220,7 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
   const int nj = op.lj[a], nl = op.ll[a];
   const int64_t ib = op.ibase[a];
   for (int l = threadIdx.x; l < nl; l += NW * 64)
-    sv[l] = load_in<T, MODE>(in, ib + l, gidx, cptr, cpos, tb);
+    sv[l] = load_in<T, MODE>(in, ib + l, spec);
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = j0 + lane;
@@ -253,6 +262,183 @@ __global__ void __launch_bounds__(kBlock) k_gather_add(int64_t n, const int64_t*
   T s = x[j];
   for (int64_t e = cptr[j]; e < cptr[j + 1]; ++e) s += tb[cpos[e]];
   x[j] = s;
+}
+
+// ---------------------------------------------------------------------------
+// A = G^T G on a coarse level in one pass over the stored rows.  A coarse
+// G_l is stored as row groups; group g covers the support columns supp_g
+// (c of them) with an upper-trapezoidal block R_g (row t holds columns
+// t..c-1), so A_l = sum_g R_g^T R_g.  A task is a range of rows [t0, t0+nr)
+// of one group; it forms y_t = R_g[t, :] x(supp_g) for its rows and stages
+// its contribution sum_t R_g[t, j] y_t to unknown supp_g[j] (t0 <= j < c) at
+// stg[soff + j - t0].  Each matrix entry is read once and used for both
+// products from registers; the consumer sums the staged values of an unknown
+// in a fixed order.  Row t0+i of a task starts at
+// vstart + i*(c - t0) - i*(i-1)/2, so the loop has no pointer loads.
+// ---------------------------------------------------------------------------
+struct GrpTasks {
+  const int64_t* vstart;   // value offset of the task's first row
+  const int32_t* nrow;     // rows in the task
+  const int32_t* t0;       // index of the first row within its group
+  const int32_t* c;        // support size of the group
+  const int64_t* s0;       // offset of the group's support list
+  const int64_t* soff;     // staging offset of the task
+};
+
+// Small groups: LW lanes per task of at most RW rows, lane chunk k covers
+// j = t0 + lane + k*LW.  Every row of the task is loaded before any product
+// is formed, so a task costs one memory round trip for its matrix entries.
+template <typename T, int LW, int KC, int RW>
+__global__ void __launch_bounds__(kBlock) k_grp_ata(int64_t ntask, GrpTasks tk,
+                                                    const T* __restrict__ val,
+                                                    const int32_t* __restrict__ supp,
+                                                    const T* __restrict__ x,
+                                                    T* __restrict__ stg) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t task = gid / LW;
+  const int lane = (int)(gid % LW);
+  if (task >= ntask) return;    // LW divides the wavefront: whole lane groups exit
+  const int nr = tk.nrow[task], t0 = tk.t0[task], c = tk.c[task];
+  const int w = c - t0;
+  const int64_t v0 = tk.vstart[task];
+  // support indices first: the x gather waits only for them, not for the
+  // matrix entries issued after them
+  const int32_t* sp = supp + tk.s0[task] + t0;
+  int32_t col[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int q = lane + k * LW;
+    col[k] = sp[q < w ? q : 0];
+  }
+  // local row i holds local columns q = i..w-1 at v0 + i*w - i*(i-1)/2 + (q - i);
+  // out-of-range lanes load the task's first entry and discard it (no branches)
+  T rv[RW][KC];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    const int64_t o = v0 + (int64_t)i * w - (int64_t)i * (i - 1) / 2 - i;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int q = lane + k * LW;
+      const bool ok = i < nr && q >= i && q < w;
+      const T v = val[ok ? o + q : v0];
+      rv[i][k] = ok ? v : T(0);
+    }
+  }
+  T xv[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int q = lane + k * LW;
+    const T v = x[col[k]];
+    xv[k] = q < w ? v : T(0);
+  }
+  T y[RW];
+#pragma unroll
+  for (int i = 0; i < RW; ++i) {
+    T p = 0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) p += rv[i][k] * xv[k];
+    y[i] = p;
+  }
+#pragma unroll
+  for (int i = 0; i < RW; ++i) y[i] = wave_sum(y[i], LW);
+  T* dst = stg + tk.soff[task];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < RW; ++i) acc += y[i] * rv[i][k];
+    const int q = lane + k * LW;
+    if (q < w) dst[q] = acc;
+  }
+}
+
+// Large groups (c - t0 <= 64*KC): one workgroup of NW wavefronts per task of
+// at most NW*RW rows; wave v takes local rows v, v+NW, ..., loads them all,
+// then forms its products; the waves' partial sums are added in wave
+// order through LDS.  LDS: NW*KC*64*sizeof(T).
+template <typename T, int KC, int NW, int RW>
+__global__ void __launch_bounds__(NW * 64) k_grp_ata_wg(GrpTasks tk, const T* __restrict__ val,
+                                                        const int32_t* __restrict__ supp,
+                                                        const T* __restrict__ x,
+                                                        T* __restrict__ stg) {
+  extern __shared__ unsigned char smem_raw[];
+  T* red = reinterpret_cast<T*>(smem_raw);     // NW*KC*64
+  const int64_t task = blockIdx.x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nr = tk.nrow[task], t0 = tk.t0[task], c = tk.c[task];
+  const int w = c - t0;
+  const int64_t v0 = tk.vstart[task];
+  const int32_t* sp = supp + tk.s0[task] + t0;
+  int32_t col[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int q = lane + 64 * k;
+    col[k] = sp[q < w ? q : 0];
+  }
+  T rv[RW][KC];
+#pragma unroll
+  for (int u = 0; u < RW; ++u) {
+    const int i = wave + NW * u;      // rows dealt round-robin over the waves
+    const int64_t o = v0 + (int64_t)i * w - (int64_t)i * (i - 1) / 2 - i;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+      const int q = lane + 64 * k;
+      const bool ok = i < nr && q >= i && q < w;
+      const T v = val[ok ? o + q : v0];
+      rv[u][k] = ok ? v : T(0);
+    }
+  }
+  T xv[KC];
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    const int q = lane + 64 * k;
+    const T v = x[col[k]];
+    xv[k] = q < w ? v : T(0);
+  }
+  T y[RW];
+#pragma unroll
+  for (int u = 0; u < RW; ++u) {
+    T p = 0;
+#pragma unroll
+    for (int k = 0; k < KC; ++k) p += rv[u][k] * xv[k];
+    y[u] = p;
+  }
+#pragma unroll
+  for (int u = 0; u < RW; ++u) y[u] = wave_sum(y[u], 64);
+#pragma unroll
+  for (int k = 0; k < KC; ++k) {
+    T acc = 0;
+#pragma unroll
+    for (int u = 0; u < RW; ++u) acc += y[u] * rv[u][k];
+    red[(wave * KC + k) * 64 + lane] = acc;
+  }
+  __syncthreads();
+  T* dst = stg + tk.soff[task];
+  for (int q = threadIdx.x; q < w; q += NW * 64) {
+    const int k = q >> 6, ln = q & 63;
+    T t = 0;
+    for (int v = 0; v < NW; ++v) t += red[(v * KC + k) * 64 + ln];
+    dst[q] = t;
+  }
+}
+
+// r = b - (sum of the staged values of each unknown).  8 lanes per unknown
+// split its list (lane l takes entries l, l+8, ...) and are added in a fixed
+// tree order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_resid_stg(int64_t n, const int64_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ pos,
+                                                      const T* __restrict__ stg,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ r) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t i = gid >> 3;
+  const int lane = (int)(gid & 7);
+  if (i >= n) return;          // whole groups of 8 lanes exit together
+  T t = 0;
+  for (int64_t e = ptr[i] + lane; e < ptr[i + 1]; e += 8) t += stg[pos[e]];
+  t = wave_sum(t, 8);
+  if (lane == 0) r[i] = b[i] - t;
 }
 
 // Coarsest level: e = A_L^{-1} r with the dense inverse (row-major); one

@@ -64,6 +64,7 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* r = nullptr;         // residual
   T* y = nullptr;         // G x (length = rows of G_l)
   T* tb = nullptr;        // RAS-T staging, sum |Omega_i|
+  T* stg = nullptr;       // staged G^T G x of the row-group pass (coarse levels)
 };
 
 // Launch plan of one batched-GEMV operator on one level.
@@ -96,6 +97,15 @@ struct DLevel {
           *cstart = nullptr, *cptr = nullptr, *cpos = nullptr;
   int32_t* oidx = nullptr;
   int32_t* kk = nullptr;
+  // coarse levels: A = G^T G applied by row-group tasks (k_grp_ata) whose
+  // staged output the residual's consumer gathers through rc_ptr / rc_pos
+  bool grp = false;
+  int grp_lw = 0, grp_kc = 0, grp_nw = 0, grp_rw = 0;   // grp_nw > 0: workgroup per task
+  int64_t grp_ntask = 0, grp_nstg = 0;
+  dev::GrpTasks gtask{};
+  int32_t* grp_supp = nullptr;
+  int64_t* rc_ptr = nullptr;
+  int32_t* rc_pos = nullptr;
   DPrec<double> d;
   DPrec<float> f;
 };
@@ -116,6 +126,7 @@ int lanes_for(double avg) {
 // Kernel timing with HIP events (lsamg_profile).
 struct Profiler {
   bool on = false;
+  bool by_level = false;  // append " @L<level>" to V-cycle kernel names
   std::string only;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
@@ -129,6 +140,13 @@ struct Profiler {
 };
 
 thread_local Profiler* g_prof = nullptr;
+thread_local int g_level = -1;   // hierarchy level whose kernels are being launched
+
+struct LevelTag {   // sets g_level for the kernels of one V-cycle level
+  int old;
+  explicit LevelTag(int l) : old(g_level) { g_level = l; }
+  ~LevelTag() { g_level = old; }
+};
 
 inline Profiler* prof_active() { return (g_prof && g_prof->on) ? g_prof : nullptr; }
 
@@ -141,7 +159,8 @@ struct ProfScope {
     p = pp;
     a = pp->pool[pp->used++];
     b = pp->pool[pp->used++];
-    pp->recs.push_back(Profiler::Rec{name, bytes, a, b});
+    pp->recs.push_back(Profiler::Rec{
+        pp->by_level && g_level >= 0 ? name + " @L" + std::to_string(g_level) : name, bytes, a, b});
   }
 };
 
@@ -288,6 +307,76 @@ struct lsamg_handle {
 
 namespace {
 
+// Row-group tasks of a coarse level (k_grp_ata) and the cover lists of the
+// staged output.  gp: CSR row pointer of the stored rows of G_l.
+void build_group_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
+                       const std::vector<int64_t>& gp) {
+  const Groups& G = HL.G;
+  int cmax = 0;
+  for (int64_t g = 0; g < G.ng(); ++g) cmax = std::max<int>(cmax, (int)(G.sptr[g + 1] - G.sptr[g]));
+  if (cmax == 0 || cmax > 64 * 16) return;        // keep the two-pass CSR form
+  // small supports (c <= 128): a lane group of lw lanes (4 chunks) per task
+  // of <= rw rows, rw from the mean rows per group; large supports: a
+  // workgroup of nw wavefronts per task of nw * rw rows
+  int lw = 64, kc = 1, nw = 0, rw = 4;
+  if (cmax <= 128) {
+    lw = 4;
+    while (lw * 4 < cmax) lw <<= 1;
+    while (kc * lw < cmax) kc <<= 1;
+    const double mean_rows = (double)G.total_rows() / (double)std::max<int64_t>(1, G.ng());
+    while (rw < 16 && rw < mean_rows) rw <<= 1;
+  } else {
+    while (kc * 64 < cmax) kc <<= 1;
+    nw = kc >= 16 ? 4 : 8;       // LDS stays below 64 KiB in FP64
+    rw = kc >= 8 ? 4 : 8;
+  }
+  const int rpt = nw > 0 ? nw * rw : rw;
+  std::vector<int64_t> vs, s0v, so;
+  std::vector<int32_t> nr, t0v, cv;
+  std::vector<std::pair<int32_t, int64_t>> cover;   // (unknown, staging position)
+  int64_t row = 0, nstg = 0;
+  for (int64_t g = 0; g < G.ng(); ++g) {
+    const int c = (int)(G.sptr[g + 1] - G.sptr[g]);
+    // split the group's rows evenly into tasks of at most rpt rows
+    const int ntk = (G.nrows[g] + rpt - 1) / rpt;
+    const int chunk = (G.nrows[g] + ntk - 1) / ntk;
+    for (int t0 = 0; t0 < G.nrows[g]; t0 += chunk) {
+      vs.push_back(gp[row + t0]);
+      nr.push_back(std::min(chunk, G.nrows[g] - t0));
+      t0v.push_back(t0);
+      cv.push_back(c);
+      s0v.push_back(G.sptr[g]);
+      so.push_back(nstg);
+      for (int j = t0; j < c; ++j) cover.emplace_back(G.supp[G.sptr[g] + j], nstg + (j - t0));
+      nstg += c - t0;
+    }
+    row += G.nrows[g];
+  }
+  if (nstg >= ((int64_t)1 << 31)) return;         // positions are 32-bit
+  std::vector<int64_t> cp(D.n + 1, 0);
+  std::vector<int32_t> cs(cover.size());
+  for (auto& e : cover) cp[e.first + 1]++;
+  for (int64_t j = 0; j < D.n; ++j) cp[j + 1] += cp[j];
+  {
+    std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+    for (auto& e : cover) cs[fill[e.first]++] = (int32_t)e.second;   // ascending position
+  }
+  D.grp = true;
+  D.grp_lw = lw;
+  D.grp_kc = kc;
+  D.grp_nw = nw;
+  D.grp_rw = rw;
+  D.grp_ntask = (int64_t)vs.size();
+  D.grp_nstg = nstg;
+  D.gtask = dev::GrpTasks{h->upload(vs), h->upload(nr), h->upload(t0v), h->upload(cv),
+                          h->upload(s0v), h->upload(so)};
+  D.grp_supp = h->upload(G.supp);
+  D.rc_ptr = h->upload(cp);
+  D.rc_pos = h->upload(cs);
+  D.d.stg = h->alloc<double>(nstg);
+  D.f.stg = h->alloc<float>(nstg);
+}
+
 // Build the device image of one level from the host hierarchy.
 void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.n = HL.n;
@@ -342,6 +431,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     D.d.gt_val = h->upload_f<double>(tv);
     D.f.gt_val = h->upload_f<float>(tv);
   }
+  if (!finest && !HL.coarsest) build_group_tasks(h, HL, D, gp);
   D.d.x = h->alloc<double>(D.n);
   D.d.b = h->alloc<double>(D.n);
   D.d.r = h->alloc<double>(D.n);
@@ -562,22 +652,13 @@ void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, 
   LAUNCH_OK();
 }
 
-// r = b - A x on level L (precision T)
-template <typename T>
-void residual(DLevel& L, const T* x, const T* b, T* r, hipStream_t s) {
-  DPrec<T>& P = prec<T>(L);
-  if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
-  spmv_csr<T>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, P.g_val, x, P.y, s, L.nnz, L.n);
-  resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, r, s, L.nnz, L.nrows);
-}
-
 template <typename T, int MODE, bool ADD>
-void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int64_t* cpos,
-          const T* tb, const T* M, const T* in, T* out, hipStream_t s, int64_t tb_extra = 0) {
+void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, T* out,
+          hipStream_t s, int64_t extra_bytes = 0) {
   PROF(kname(P.G > 0 ? "k_gemv_narrow" : "k_gemv_wide",
              std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
                  (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : P.NW)),
-       sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + tb_extra,
+       sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
        s);
   if (P.G > 0) {
     const unsigned g = (unsigned)((P.nagg + 3) / 4);
@@ -586,8 +667,7 @@ void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int
 #define CASE(GG)                                                                            \
   case GG:                                                                                  \
     KLAUNCH(g, dev::kBlock, lds, s, dev::k_gemv_narrow<T, MODE, ADD, GG>, P.nagg, P.op, P.lmax,  \
-                                                                     gidx, cptr, cpos, tb,  \
-                                                                     M, in, out);           \
+            sp, M, in, out);                                                                \
     break;
       CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
@@ -598,7 +678,7 @@ void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int
 #define CASE(NW)                                                                               \
   case NW:                                                                                     \
     KLAUNCH((unsigned)P.ntask, NW * 64, lds, s, dev::k_gemv_wide<T, MODE, ADD, NW>,                 \
-        P.task_a, P.task_j0, P.op, P.lmax, gidx, cptr, cpos, tb, M, in, out);                  \
+        P.task_a, P.task_j0, P.op, P.lmax, sp, M, in, out);                                    \
     break;
       CASE(4) CASE(8) CASE(16)
 #undef CASE
@@ -607,18 +687,25 @@ void gemv(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int
   LAUNCH_OK();
 }
 
+template <typename T>
+dev::InSpec<T> no_spec() {
+  return dev::InSpec<T>{nullptr, nullptr, nullptr, nullptr, nullptr};
+}
+
 // x = RAS(b) from a zero initial guess (eq:ras)
 template <typename T>
 void ras(DLevel& L, const T* b, T* x, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  gemv<T, dev::IN_GATHER, false>(L.ras, L.oidx, nullptr, nullptr, nullptr, P.Zc, b, x, s);
+  dev::InSpec<T> sp = no_spec<T>();
+  sp.idx = L.oidx;
+  gemv<T, dev::IN_GATHER, false>(L.ras, sp, P.Zc, b, x, s);
 }
 
 // staged RAS-T(r) (eq:ras-t) into tb; gather_add folds it into x
 template <typename T>
 void ras_t_stage(DLevel& L, const T* r, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  gemv<T, dev::IN_DIRECT, false>(L.rast, nullptr, nullptr, nullptr, nullptr, P.Zr, r, P.tb, s);
+  gemv<T, dev::IN_DIRECT, false>(L.rast, no_spec<T>(), P.Zr, r, P.tb, s);
 }
 
 template <typename T>
@@ -630,11 +717,90 @@ void gather_add(DLevel& L, T* x, hipStream_t s) {
   LAUNCH_OK();
 }
 
+// First pass of the residual b - A x of level L for a consumer that forms
+// r(omega_i) on the fly: the row-group pass (coarse levels, staged output) or
+// y = G x (finest level, G^T applied by the consumer).
+template <typename T>
+void resid_first(DLevel& L, const T* x, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  if (!L.grp) {
+    if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
+    spmv_csr<T>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, P.g_val, x, P.y, s, L.nnz, L.n);
+    return;
+  }
+  const int lw = L.grp_lw, kc = L.grp_kc, nw = L.grp_nw, rw = L.grp_rw;
+  const double bytes = sizeof(T) * (L.nnz + L.n + L.grp_nstg) + 4 * L.grp_nstg + 36 * L.grp_ntask;
+  if (nw > 0) {
+    PROF(kname("k_grp_ata_wg", std::string(tname<T>()) + ", " + std::to_string(kc) + ", " +
+                                   std::to_string(nw) + ", " + std::to_string(rw)),
+         bytes, s);
+    const size_t lds = (size_t)(nw * kc * 64) * sizeof(T);
+    switch (kc * 10000 + nw * 100 + rw) {
+#define CASE(KC, NW, RW)                                                                   \
+  case KC * 10000 + NW * 100 + RW:                                                         \
+    KLAUNCH((unsigned)L.grp_ntask, NW * 64, lds, s, dev::k_grp_ata_wg<T, KC, NW, RW>,      \
+            L.gtask, P.g_val, L.grp_supp, x, P.stg);                                       \
+    break;
+      CASE(2, 8, 8) CASE(4, 8, 8) CASE(8, 8, 4) CASE(16, 4, 4)
+#undef CASE
+      default:
+        throw DevError{LSAMG_EINVAL, "row-group pass: unsupported shape"};
+    }
+  } else {
+    PROF(kname("k_grp_ata", std::string(tname<T>()) + ", " + std::to_string(lw) + ", " +
+                                std::to_string(kc) + ", " + std::to_string(rw)),
+         bytes, s);
+    const unsigned g = nblocks(L.grp_ntask * lw);
+    switch (lw * 10000 + kc * 100 + rw) {
+#define CASE(LW, KC, RW)                                                                   \
+  case LW * 10000 + KC * 100 + RW:                                                         \
+    KLAUNCH(g, dev::kBlock, 0, s, dev::k_grp_ata<T, LW, KC, RW>, L.grp_ntask, L.gtask,     \
+            P.g_val, L.grp_supp, x, P.stg);                                                \
+    break;
+#define CASES(LW, KC) CASE(LW, KC, 4) CASE(LW, KC, 8) CASE(LW, KC, 16)
+      CASES(4, 1) CASES(4, 2) CASES(4, 4) CASES(8, 4) CASES(16, 4) CASES(32, 4)
+#undef CASES
+#undef CASE
+      default:
+        throw DevError{LSAMG_EINVAL, "row-group pass: unsupported shape"};
+    }
+  }
+  LAUNCH_OK();
+}
+
+// out (=|+=) op(r) where r = b - A x is formed by the consumer from the first
+// pass of resid_first
+template <typename T, bool ADD>
+void gemv_resid(DLevel& L, const GemvPlan& Pl, const T* M, const T* b, T* out, hipStream_t s) {
+  DPrec<T>& P = prec<T>(L);
+  dev::InSpec<T> sp = no_spec<T>();
+  if (L.grp) {
+    // r = b - (staged row-group output), formed once for the level
+    {
+      PROF(kname("k_resid_stg", tname<T>()),
+           (sizeof(T) + 4) * L.grp_nstg + 8 * (L.n + 1) + 2 * sizeof(T) * L.n, s);
+      KLAUNCH(nblocks(L.n * 8), dev::kBlock, 0, s, dev::k_resid_stg<T>, L.n, L.rc_ptr, L.rc_pos,
+              P.stg, b, P.r);
+      LAUNCH_OK();
+    }
+    gemv<T, dev::IN_DIRECT, ADD>(Pl, sp, M, P.r, out, s);
+  } else {
+    sp.idx = L.gt_col;
+    sp.ptr = L.gt_ptr;
+    sp.v1 = P.gt_val;
+    sp.v2 = P.y;
+    gemv<T, dev::IN_RESG, ADD>(Pl, sp, M, b, out, s,
+                               (int64_t)(sizeof(T) + 4) * L.nnz + 8 * (L.n + 1) +
+                                   sizeof(T) * L.nrows);
+  }
+}
+
 // x = B b on level l from a zero initial guess.  With finalize = false the
 // RAS-T contributions of this level are left staged in tb: the caller (the
 // finer level's prolongation) adds them when it reads x.
 template <typename T>
 void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool finalize) {
+  LevelTag tag_((int)l);
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
   if (L.coarsest) {
@@ -646,17 +812,21 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   DLevel& C = h->L[l + 1];
   DPrec<T>& PC = prec<T>(C);
   ras<T>(L, b, x, s);                                                        // eq:ras
-  residual<T>(L, x, b, P.r, s);
-  gemv<T, dev::IN_DIRECT, false>(L.rst, nullptr, nullptr, nullptr, nullptr, P.Zh, P.r, PC.b,
-                                 s);                                         // P^T r
+  resid_first<T>(L, x, s);
+  gemv_resid<T, false>(L, L.rst, P.Zh, b, PC.b, s);                          // P^T (b - A x)
   vcycle<T>(h, l + 1, PC.b, PC.x, s, false);
-  if (C.coarsest)
-    gemv<T, dev::IN_DIRECT, true>(L.pro, nullptr, nullptr, nullptr, nullptr, P.ZhT, PC.x, x, s);
-  else
-    gemv<T, dev::IN_TB, true>(L.pro, nullptr, C.cptr, C.cpos, PC.tb, P.ZhT, PC.x, x, s,
+  if (C.coarsest) {
+    gemv<T, dev::IN_DIRECT, true>(L.pro, no_spec<T>(), P.ZhT, PC.x, x, s);
+  } else {
+    dev::InSpec<T> sp = no_spec<T>();
+    sp.ptr = C.cptr;
+    sp.pos = C.cpos;
+    sp.v1 = PC.tb;
+    gemv<T, dev::IN_TB, true>(L.pro, sp, P.ZhT, PC.x, x, s,
                               (int64_t)(sizeof(T) + 8) * C.ntb + 8 * (C.n + 1));
-  residual<T>(L, x, b, P.r, s);
-  ras_t_stage<T>(L, P.r, s);                                                 // eq:ras-t
+  }
+  resid_first<T>(L, x, s);
+  gemv_resid<T, false>(L, L.rast, P.Zr, b, P.tb, s);                         // eq:ras-t
   if (finalize) gather_add<T>(L, x, s);
 }
 
@@ -963,6 +1133,7 @@ void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t 
 // X = B_l(B) for NB interleaved right-hand sides (see vcycle)
 template <typename T, int NB>
 void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool finalize) {
+  LevelTag tag_((int)l);
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
   BVec<T> V = bvec<T>(h->BL[l]);
@@ -1343,16 +1514,17 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
 }
 
 int lsamg_profile(lsamg_handle* h, int32_t mode, const char* only) {
-  if (!h || (mode != 0 && mode != 1)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (!h || mode < 0 || mode > 2) return fail_with(LSAMG_EINVAL, "bad argument");
   if (h->device < 0) return fail_with(LSAMG_ENODEV, "handle has no device copy");
   try {
     DeviceGuard g(h->device);
     Profiler& P = h->prof;
-    if (mode == 1 && P.pool.empty()) {
+    if (mode != 0 && P.pool.empty()) {
       P.pool.resize(2 * 32768);
       for (auto& e : P.pool) HIP_OK(hipEventCreate(&e));
     }
-    P.on = mode == 1;
+    P.on = mode != 0;
+    P.by_level = mode == 2;
     P.only = only ? only : "";
     return LSAMG_OK;
   } catch (const DevError& e) {

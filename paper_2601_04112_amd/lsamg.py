@@ -282,10 +282,12 @@ class Solver:
         _check(load().lsamg_set_precision(self._h, precision))
 
     # -- kernel timing ----------------------------------------------------
-    def profile(self, on: bool = True, only: Optional[str] = None):
-        """Bracket kernel launches with HIP events (all, or one symbol)."""
-        _check(load().lsamg_profile(self._h, 1 if on else 0,
-                                    only.encode() if only else None))
+    def profile(self, on: bool = True, only: Optional[str] = None,
+                by_level: bool = False):
+        """Bracket kernel launches with HIP events (all, or one symbol);
+        by_level reports the V-cycle kernels per hierarchy level."""
+        mode = (2 if by_level else 1) if on else 0
+        _check(load().lsamg_profile(self._h, mode, only.encode() if only else None))
 
     def profile_read(self) -> list:
         """Per-kernel totals since profiling was enabled (then reset)."""
