@@ -142,7 +142,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--workload", choices=("aniso2d", "ls3d"), default="aniso2d",
+                    help="aniso2d: 2D rotated anisotropy (default); ls3d: 3D "
+                         "A = D1 + B^T D2^-1 B on a 128^3 grid")
+    ap.add_argument("--N", type=int, default=0,
+                    help="cells per side (default 512 for aniso2d, 128 for ls3d)")
     ap.add_argument("--cpu-iters", type=int, default=2,
                     help="PCG iterations of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -161,6 +165,14 @@ def main():
             sys.exit(2)
         run_serving(args)
         return
+    three_d = args.workload == "ls3d"
+    if args.N == 0:
+        args.N = 128 if three_d else 512
+    if three_d:
+        # the oracle's Python setup of a 2M-unknown hierarchy takes hours, and
+        # the multi-right-hand-side section is defined on the 2D operator
+        args.no_cpu_baseline = True
+        args.batch = 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(the per-GPU shard would be a block of aggregates; see the "
@@ -181,13 +193,21 @@ def main():
     import problems as P
     from paper_2601_04112_amd import lsamg as L
 
-    prob = P.config2(args.N)
     t0 = time.time()
-    s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=(2,))
+    if three_d:
+        prob = P.config3(args.N)
+        print(f"ls3d N={args.N}: n={prob.n}, m={prob.m}, nnz={prob.G.nnz}; setup ...",
+              file=sys.stderr, flush=True)
+        s = L.Solver(prob.G, 3, prob.grid, device=0, block=3, cmin=(3, 4), verbose=True)
+        seed = P.CONFIG_RHS_SEED[3]
+    else:
+        prob = P.config2(args.N)
+        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=(2,))
+        seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
+    print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
     inf = s.info()
-    b = torch.tensor(P.rhs_uniform(prob.n, P.CONFIG_RHS_SEED[2]), dtype=torch.float64,
-                     device="cuda:0")
+    b = torch.tensor(P.rhs_uniform(prob.n, seed), dtype=torch.float64, device="cuda:0")
     x = torch.empty_like(b)
     stream = torch.cuda.current_stream()
 
@@ -225,7 +245,9 @@ def main():
     ktotal = sum(r["ms"] for r in allk)
 
     mixed, kp = timed(L.MIXED, args.steps, args.warmup, only=dominant)
+    print(f"mixed {mixed['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     fp64, _ = timed(L.FP64, args.steps, args.warmup)
+    print(f"fp64 {fp64['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
 
     # batched workload: the same operator with 64 right-hand sides (seeds
     # 100-163) solved together, one FP64 CG per column, FP32 V-cycle
@@ -304,8 +326,12 @@ def main():
         "dtype": "f32 V-cycle / f64 CG",
         "data": "synthetic",
         "config": {
-            "workload": (f"aniso2d N={args.N} theta=pi/6 eps=1e-4 (n={prob.n}, "
-                         f"m={prob.m}), rhs uniform[-1,1] seed 1, tol 1e-8, "
+            "workload": (f"ls3d N={args.N} A=D1+B^T D2^-1 B, K=Q diag(1,1e-3,1e-3) Q^T, "
+                         f"lognormal coefficient (n={prob.n}, m={prob.m}), rhs "
+                         f"uniform[-1,1] seed {seed}, tol 1e-8, 3x3x3 aggregates, "
+                         f"c_min=3,4, coarsest<2000" if three_d else
+                         f"aniso2d N={args.N} theta=pi/6 eps=1e-4 (n={prob.n}, "
+                         f"m={prob.m}), rhs uniform[-1,1] seed {seed}, tol 1e-8, "
                          f"4x4 aggregates, c_min=2, coarsest<2000"),
             "levels": inf["nlevels"],
             "n_per_level": [l["n"] for l in inf["levels"]],
@@ -313,6 +339,7 @@ def main():
             "smoother_complexity": round(inf["smoother_complexity"], 3),
             "smoother_entries": smoother_entries,
             "setup_s": round(t_setup, 2),
+            "device_gb": round(inf["device_bytes"] / 1e9, 2),
             "parallelism": "single GPU",
         },
         "p50_ms": round(mixed["p50_ms"], 3),

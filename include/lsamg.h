@@ -86,6 +86,13 @@ typedef struct lsamg_params {
   int32_t device;        /* HIP device ordinal; < 0 builds a host-only handle
                             (setup data and lsamg_export_setup only)         */
   int32_t nthreads;      /* host threads for setup (0 = all cores)           */
+  int32_t verbose;       /* 1: one progress line per setup phase on stderr   */
+  int64_t dense_tail;    /* > 0: the V-cycle from the first level l >= 1 with
+                            at most this many unknowns down to the coarsest
+                            (a fixed symmetric linear map) is formed once on
+                            the GPU and applied as one dense matrix (n_l^2
+                            entries per precision); 0: always recurse.
+                            Default 16384.                                   */
 } lsamg_params;
 
 /* Per-solve statistics (host memory, one entry per right-hand side). */
@@ -119,6 +126,8 @@ typedef struct lsamg_info {
   double op_complexity;      /* sum_l nnz(A_l) / nnz(A_0)                    */
   double smoother_complexity;/* sum_l sum_i |omega_i||Omega_i| / nnz(A_0)    */
   lsamg_level_info level[16];
+  int32_t tail_level;        /* level applied as one dense matrix (see
+                                dense_tail), -1 if none                      */
 } lsamg_info;
 
 /* Integer setup of one level in the canonical numbering: finest-level

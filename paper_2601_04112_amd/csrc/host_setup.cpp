@@ -9,6 +9,7 @@
 // sec. 3.4; smoother rows Z_i = A_i^{-1}(omega_i, Omega_i); interpolation
 // eq:mg-p; G_{l+1} = G_l P_l (sec. 3.1.3) with exact row compression.
 #include <algorithm>
+#include <cstdio>
 #include <array>
 #include <chrono>
 #include <cmath>
@@ -780,6 +781,14 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     // Algorithm 1 main loop
     int l = 0;
     bool aggregated = agg0;
+    auto progress = [&](int lev, const char* what) {
+      if (!p.verbose) return;
+      const double t =
+          std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      std::fprintf(stderr, "lsamg setup: level %d (n=%lld) %s, %.1f s\n", lev,
+                   (long long)H.levels[lev].n, what, t);
+      std::fflush(stderr);
+    };
     for (;;) {
       Level& L = H.levels[l];
       Work W;
@@ -788,10 +797,13 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
       if (!aggregated) {
         L.coarsest = true;
         coarsest_inverse(L, W, nthreads);
+        progress(l, "coarsest inverse done");
         break;
       }
       overlap_and_colour(L, W, p, nthreads);
+      progress(l, "overlap and colouring done");
       spectral_and_smoother(L, W, p, l, nthreads);
+      progress(l, "local eigenproblems and smoother done");
       int64_t nn = 0;
       for (int32_t kk : L.k) nn += kk;
       const bool stall = (double)nn > p.stall_ratio * (double)L.n;

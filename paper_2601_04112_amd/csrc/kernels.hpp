@@ -441,20 +441,83 @@ __global__ void __launch_bounds__(kBlock) k_resid_stg(int64_t n, const int64_t* 
   if (lane == 0) r[i] = b[i] - t;
 }
 
-// Coarsest level: e = A_L^{-1} r with the dense inverse (row-major); one
-// wavefront per row.
+// Dense level operator (the coarsest inverse, or the precomputed V-cycle of a
+// dense tail): e = M r, M row-major n x n.  A wavefront takes four rows, so
+// each loaded r entry serves four rows; lanes stride the row with eight
+// independent loads per row in flight.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_dense_gemv(int64_t n, const T* __restrict__ M,
                                                        const T* __restrict__ r,
                                                        T* __restrict__ e) {
-  const int64_t row = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64;
+  constexpr int R = 4, U = 8;
+  const int64_t row0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64 * R;
   const int lane = threadIdx.x % 64;
-  if (row >= n) return;
-  const T* mr = M + row * n;
-  T s = 0;
-  for (int64_t j = lane; j < n; j += 64) s += mr[j] * r[j];
-  s = wave_sum(s, 64);
-  if (lane == 0) e[row] = s;
+  if (row0 >= n) return;
+  const T* mr[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) mr[q] = M + (row0 + q < n ? row0 + q : row0) * n;
+  T acc[R][2] = {};
+  int64_t j = lane;
+  for (; j + (U - 1) * 64 < n; j += U * 64) {
+    T rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rv[u] = r[j + u * 64];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      T mv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) mv[u] = mr[q][j + u * 64];
+#pragma unroll
+      for (int u = 0; u < U; ++u) acc[q][u & 1] += mv[u] * rv[u];
+    }
+  }
+  for (; j < n; j += 64) {
+    const T rv = r[j];
+#pragma unroll
+    for (int q = 0; q < R; ++q) acc[q][0] += mr[q][j] * rv;
+  }
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    const T t = wave_sum(acc[q][0] + acc[q][1], 64);
+    if (lane == 0 && row0 + q < n) e[row0 + q] = t;
+  }
+}
+
+// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the
+// interleaved n x NB layout of the multi-right-hand-side path.
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_unit_block(int64_t n, int64_t j0,
+                                                       double* __restrict__ E) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= n * NB) return;
+  const int64_t i = gid / NB;
+  const int c = (int)(gid % NB);
+  E[gid] = (i == j0 + c) ? 1.0 : 0.0;
+}
+
+// M[:, j0 + c] = X[:, c] for the columns that exist (M column-major n x n)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_scatter_cols(int64_t n, int64_t j0,
+                                                         const double* __restrict__ X,
+                                                         double* __restrict__ M) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= n * NB) return;
+  const int64_t i = gid / NB;
+  const int c = (int)(gid % NB);
+  if (j0 + c < n) M[(j0 + c) * n + i] = X[gid];
+}
+
+// M = (M + M^T) / 2 in place (the tail operator is symmetric in exact
+// arithmetic; this removes the rounding asymmetry, so row- and column-major
+// reads agree)
+__global__ void __launch_bounds__(kBlock) k_symmetrize(int64_t n, double* __restrict__ M) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (gid >= n * n) return;
+  const int64_t i = gid / n, j = gid % n;
+  if (i >= j) return;
+  const double v = 0.5 * (M[i * n + j] + M[j * n + i]);
+  M[i * n + j] = v;
+  M[j * n + i] = v;
 }
 
 // ---------------------------------------------------------------------------

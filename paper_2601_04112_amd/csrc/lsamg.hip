@@ -58,7 +58,7 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* Zr = nullptr;        // Z_i row-major (RAS-T)
   T* Zh = nullptr;        // Zhat_i row-major (restriction P^T)
   T* ZhT = nullptr;       // Zhat_i column-major (prolongation P)
-  T* Ainv = nullptr;      // coarsest inverse
+  T* Ainv = nullptr;      // coarsest inverse, or the dense tail operator
   T* x = nullptr;         // V-cycle output at this level
   T* b = nullptr;         // V-cycle input at this level
   T* r = nullptr;         // residual
@@ -87,6 +87,7 @@ struct DLevel {
   GemvPlan dense;         // coarsest level: A_L^{-1} as one block (batched path)
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
+  bool tail = false;      // V-cycle from here down applied as the dense matrix Ainv
   int lanes_g = 1, lanes_gt = 1;
   int max_nO = 0, max_nw = 0, max_k = 0;
   int64_t* g_ptr = nullptr;
@@ -377,6 +378,29 @@ void build_group_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
   D.f.stg = h->alloc<float>(nstg);
 }
 
+// The dense level operator Ainv (n x n) as a one-block operator of the
+// multi-right-hand-side GEMM.
+void make_dense_plan(lsamg_handle* h, DLevel& D) {
+  GemvPlan& P = D.dense;
+  std::vector<int64_t> z1(1, 0);
+  std::vector<int32_t> n1(1, (int32_t)D.n);
+  int32_t* dn = h->upload(n1);
+  int64_t* dz = h->upload(z1);
+  P.op = dev::GemvOp{dz, dn, dn, dz, dz};
+  P.nagg = 1;
+  P.lmax = (int)D.n;
+  P.mat = D.n * D.n;
+  P.in_u = P.out = D.n;
+  std::vector<int32_t> ta, tj;
+  for (int64_t j = 0; j < D.n; j += 64) {
+    ta.push_back(0);
+    tj.push_back((int32_t)j);
+  }
+  P.ntask = (int64_t)ta.size();
+  P.task_a = h->upload(ta);
+  P.task_j0 = h->upload(tj);
+}
+
 // Build the device image of one level from the host hierarchy.
 void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.n = HL.n;
@@ -443,25 +467,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   if (HL.coarsest) {
     D.d.Ainv = h->upload_f<double>(HL.Ainv);
     D.f.Ainv = h->upload_f<float>(HL.Ainv);
-    // the dense inverse as a one-block operator for the batched GEMM
-    GemvPlan& P = D.dense;
-    std::vector<int64_t> z1(1, 0);
-    std::vector<int32_t> n1(1, (int32_t)D.n);
-    int32_t* dn = h->upload(n1);
-    int64_t* dz = h->upload(z1);
-    P.op = dev::GemvOp{dz, dn, dn, dz, dz};
-    P.nagg = 1;
-    P.lmax = (int)D.n;
-    P.mat = D.n * D.n;
-    P.in_u = P.out = D.n;
-    std::vector<int32_t> ta, tj;
-    for (int64_t j = 0; j < D.n; j += 64) {
-      ta.push_back(0);
-      tj.push_back((int32_t)j);
-    }
-    P.ntask = (int64_t)ta.size();
-    P.task_a = h->upload(ta);
-    P.task_j0 = h->upload(tj);
+    make_dense_plan(h, D);
     return;
   }
   D.nagg = HL.nagg;
@@ -577,6 +583,8 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.f.tb = h->alloc<float>(D.ntb);
 }
 
+void build_tail(lsamg_handle* h, size_t lc);
+
 void upload(lsamg_handle* h) {
   if (!h->dry) HIP_OK(hipSetDevice(h->device));
   h->L.resize(h->H.levels.size());
@@ -598,6 +606,15 @@ void upload(lsamg_handle* h) {
   h->p_rz[0] = h->alloc<double>(h->red_np);
   h->p_rz[1] = h->alloc<double>(h->red_np);
   h->p_tmp = h->alloc<double>(h->red_np);
+  // dense tail: the first level below the finest that is small enough
+  size_t lc = 0;
+  if (h->H.params.dense_tail > 0)
+    for (size_t l = 1; l < h->L.size() && !h->L[l].coarsest; ++l)
+      if (h->L[l].n <= h->H.params.dense_tail) {
+        lc = l;
+        break;
+      }
+  if (lc > 0) build_tail(h, lc);
   if (h->dry) return;
   HIP_OK(hipHostMalloc((void**)&h->sc_host, 3 * 1024 * sizeof(double), hipHostMallocDefault));
   for (auto& e : h->ev_rr) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -784,6 +801,11 @@ void gemv_resid(DLevel& L, const GemvPlan& Pl, const T* M, const T* b, T* out, h
       LAUNCH_OK();
     }
     gemv<T, dev::IN_DIRECT, ADD>(Pl, sp, M, P.r, out, s);
+  } else if (Pl.G == 0) {
+    // the wide form has several output slices per aggregate, each of which
+    // would re-form r(omega_i): form r once
+    resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, P.r, s, L.nnz, L.nrows);
+    gemv<T, dev::IN_DIRECT, ADD>(Pl, sp, M, P.r, out, s);
   } else {
     sp.idx = L.gt_col;
     sp.ptr = L.gt_ptr;
@@ -803,9 +825,10 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   LevelTag tag_((int)l);
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
-  if (L.coarsest) {
+  if (L.coarsest || L.tail) {
     PROF(kname("k_dense_gemv", tname<T>()), sizeof(T) * (L.n * L.n + 2 * L.n), s);
-    KLAUNCH(nblocks(L.n * 64), dev::kBlock, 0, s, dev::k_dense_gemv<T>, L.n, P.Ainv, b, x);
+    KLAUNCH(nblocks((L.n + 3) / 4 * 64), dev::kBlock, 0, s, dev::k_dense_gemv<T>, L.n, P.Ainv, b,
+            x);
     LAUNCH_OK();
     return;
   }
@@ -815,7 +838,7 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   resid_first<T>(L, x, s);
   gemv_resid<T, false>(L, L.rst, P.Zh, b, PC.b, s);                          // P^T (b - A x)
   vcycle<T>(h, l + 1, PC.b, PC.x, s, false);
-  if (C.coarsest) {
+  if (C.coarsest || C.tail) {
     gemv<T, dev::IN_DIRECT, true>(L.pro, no_spec<T>(), P.ZhT, PC.x, x, s);
   } else {
     dev::InSpec<T> sp = no_spec<T>();
@@ -1137,7 +1160,7 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
   BVec<T> V = bvec<T>(h->BL[l]);
-  if (L.coarsest) {
+  if (L.coarsest || L.tail) {
     bgemm<T, dev::IN_DIRECT, false, NB>(L.dense, nullptr, nullptr, nullptr, nullptr, P.Ainv, B, X,
                                         s);
     return;
@@ -1149,7 +1172,7 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
   bgemm<T, dev::IN_DIRECT, false, NB>(L.rst, nullptr, nullptr, nullptr, nullptr, P.Zh, V.r, VC.b,
                                       s);
   bvcycle<T, NB>(h, l + 1, VC.b, VC.x, s, false);
-  if (C.coarsest)
+  if (C.coarsest || C.tail)
     bgemm<T, dev::IN_DIRECT, true, NB>(L.pro, nullptr, nullptr, nullptr, nullptr, P.ZhT, VC.x, X,
                                        s);
   else
@@ -1165,6 +1188,69 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
             (const T*)V.tb, X);
     LAUNCH_OK();
   }
+}
+
+// Dense tail: the V-cycle of levels >= lc is a fixed symmetric linear map
+// B_lc.  It is formed once, in FP64, by applying the multi-right-hand-side
+// V-cycle to the columns of the identity (64 at a time), symmetrized, and
+// stored in both precisions as the level's dense operator; later V-cycles
+// apply it with one dense GEMV (or GEMM) instead of recursing.  Temporary
+// multi-right-hand-side buffers for levels >= lc are freed afterwards.
+void build_tail(lsamg_handle* h, size_t lc) {
+  DLevel& T = h->L[lc];
+  const int64_t n = T.n;
+  T.d.Ainv = h->alloc<double>((size_t)n * n);
+  T.f.Ainv = h->alloc<float>((size_t)n * n);
+  make_dense_plan(h, T);
+  if (h->dry) {
+    T.tail = true;
+    return;
+  }
+  constexpr int NB = 64;
+  struct Tmp {
+    std::vector<void*> v;
+    lsamg_handle* h;
+    ~Tmp() {
+      for (void* p : v) (void)hipFree(p);
+      h->BL.clear();
+    }
+    double* get(size_t count) {
+      void* p = nullptr;
+      HIP_OK(hipMalloc(&p, std::max<size_t>(count, 1) * sizeof(double)));
+      v.push_back(p);
+      return (double*)p;
+    }
+  } tmp{{}, h};
+  h->BL.assign(h->L.size(), lsamg_handle::BLev{});
+  for (size_t l = lc; l < h->L.size(); ++l) {
+    DLevel& L = h->L[l];
+    auto& B = h->BL[l];
+    const size_t nn = (size_t)L.n * NB, ny = (size_t)std::max<int64_t>(L.nrows, 1) * NB,
+                 nt = (size_t)std::max<int64_t>(L.ntb, 1) * NB;
+    B.x = tmp.get(nn);
+    B.b = tmp.get(nn);
+    B.r = tmp.get(nn);
+    B.y = tmp.get(ny);
+    B.tb = tmp.get(nt);
+  }
+  double* E = tmp.get((size_t)n * NB);
+  double* X = tmp.get((size_t)n * NB);
+  hipStream_t s = nullptr;
+  const unsigned g = nblocks(n * NB);
+  for (int64_t j0 = 0; j0 < n; j0 += NB) {
+    KLAUNCH0(g, dev::kBlock, 0, s, dev::k_unit_block<NB>, n, j0, E);
+    LAUNCH_OK();
+    bvcycle<double, NB>(h, lc, E, X, s, true);
+    KLAUNCH0(g, dev::kBlock, 0, s, dev::k_scatter_cols<NB>, n, j0, (const double*)X, T.d.Ainv);
+    LAUNCH_OK();
+  }
+  KLAUNCH0(nblocks(n * n), dev::kBlock, 0, s, dev::k_symmetrize, n, T.d.Ainv);
+  LAUNCH_OK();
+  KLAUNCH0(nblocks(n * n), dev::kBlock, 0, s, dev::k_convert<double, float>, n * n,
+           (const double*)T.d.Ainv, T.f.Ainv);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  T.tail = true;
 }
 
 template <int NB>
@@ -1387,6 +1473,8 @@ void lsamg_params_default(lsamg_params* p) {
   p->precision = LSAMG_FP64;
   p->device = 0;
   p->nthreads = 0;
+  p->verbose = 0;
+  p->dense_tail = 16384;
 }
 
 const char* lsamg_last_error(void) { return g_last_error.c_str(); }
@@ -1614,6 +1702,9 @@ int lsamg_info_get(const lsamg_handle* h, lsamg_info* out) {
   }
   out->op_complexity = oc;
   out->smoother_complexity = sc;
+  out->tail_level = -1;
+  for (size_t l = 0; l < h->L.size(); ++l)
+    if (h->L[l].tail) out->tail_level = (int32_t)l;
   return LSAMG_OK;
 }
 

@@ -46,7 +46,8 @@ class Params(C.Structure):
                 ("tie_rtol", C.c_double), ("tie_atol", C.c_double),
                 ("pinv_rtol", C.c_double), ("thresh_margin", C.c_double),
                 ("stall_ratio", C.c_double), ("precision", C.c_int32),
-                ("device", C.c_int32), ("nthreads", C.c_int32)]
+                ("device", C.c_int32), ("nthreads", C.c_int32),
+                ("verbose", C.c_int32), ("dense_tail", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -72,7 +73,7 @@ class Info(C.Structure):
                 ("setup_seconds", C.c_double), ("device_bytes", C.c_size_t),
                 ("op_complexity", C.c_double),
                 ("smoother_complexity", C.c_double),
-                ("level", LevelInfo * 16)]
+                ("level", LevelInfo * 16), ("tail_level", C.c_int32)]
 
 
 class SetupView(C.Structure):
@@ -185,7 +186,8 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 tie_rtol: float = 1e-8, tie_atol: float = 1e-12,
                 pinv_rtol: float = 1e-12, thresh_margin: float = 1e-10,
                 stall_ratio: float = 0.9, precision: int = FP64,
-                device: int = 0, nthreads: int = 0) -> Params:
+                device: int = 0, nthreads: int = 0, verbose: bool = False,
+                dense_tail: int = 16384) -> Params:
     p = default_params()
     p.ndim = ndim
     for d in range(3):
@@ -199,6 +201,8 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
     p.tie_rtol, p.tie_atol, p.pinv_rtol = tie_rtol, tie_atol, pinv_rtol
     p.thresh_margin, p.stall_ratio = thresh_margin, stall_ratio
     p.precision, p.device, p.nthreads = precision, device, nthreads
+    p.verbose = 1 if verbose else 0
+    p.dense_tail = int(dense_tail)
     return p
 
 
@@ -310,7 +314,7 @@ class Solver:
                     device_bytes=inf.device_bytes,
                     op_complexity=inf.op_complexity,
                     smoother_complexity=inf.smoother_complexity,
-                    levels=levels)
+                    levels=levels, tail_level=inf.tail_level)
 
     def export_setup(self, level: int) -> dict:
         v = SetupView()

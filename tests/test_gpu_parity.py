@@ -63,8 +63,20 @@ def cfg1(gpu_device):
 @pytest.fixture(scope="module")
 def rot(gpu_device):
     p = P.aniso2d(64, math.pi / 6, 1e-4)
-    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150)
-    assert len(H.levels) >= 3
+    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150,
+                 dense_tail=0)
+    assert len(H.levels) >= 3 and s.info()["tail_level"] == -1
+    yield p, H, s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def rot_tail(gpu_device):
+    """As rot, with the V-cycle below level 1 applied as one dense matrix."""
+    p = P.aniso2d(64, math.pi / 6, 1e-4)
+    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150,
+                 dense_tail=2000)
+    assert len(H.levels) >= 4 and s.info()["tail_level"] == 1
     yield p, H, s
     s.close()
 
@@ -73,7 +85,8 @@ def rot(gpu_device):
 def ragged(gpu_device):
     # 46 interior nodes per axis = 11 blocks of 4 plus one of 2
     p = P.aniso2d(47, math.pi / 6, 1e-4)
-    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150)
+    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150,
+                 dense_tail=0)
     yield p, H, s
     s.close()
 
@@ -98,13 +111,14 @@ def min_kept_gamma_ratio(H):
 def illcond(gpu_device):
     # ragged lattice, LS_{3,4} caps, theta=0.5, eps=1e-2
     p = P.aniso2d(47, 0.5, 1e-2)
-    H, s = build(p, 2, O.Params(cmin=(3, 4), max_coarse=150), cmin=(3, 4), max_coarse=150)
+    H, s = build(p, 2, O.Params(cmin=(3, 4), max_coarse=150), cmin=(3, 4), max_coarse=150,
+                 dense_tail=0)
     assert min_kept_gamma_ratio(H) < 1e-11
     yield p, H, s
     s.close()
 
 
-CASES = ["cfg1", "rot", "ragged", "illcond"]
+CASES = ["cfg1", "rot", "rot_tail", "ragged", "illcond"]
 U = 2.220446049250313e-16
 
 
@@ -204,8 +218,9 @@ def test_batched_equals_single(rot, nrhs):
         assert r <= 1.01e-8
 
 
-def test_batched_mixed(rot):
-    p, H, s = rot
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_batched_mixed(which, request):
+    p, H, s = request.getfixturevalue(which)
     B = np.stack([P.rhs_uniform(p.n, 200 + j) for j in range(5)])
     _, info = O.pcg(H, B[0], tol=1e-8)
     s.set_precision(L.MIXED)
@@ -283,10 +298,12 @@ def test_full_coarse_space_is_direct(gpu_device):
     s.close()
 
 
-def test_3d_small(gpu_device):
+@pytest.mark.parametrize("tail", [0, 16384])
+def test_3d_small(gpu_device, tail):
     p = P.ls3d(12)
     H, s = build(p, 3, O.Params(block=3, cmin=(2,), max_coarse=100),
-                 block=3, cmin=(2,), max_coarse=100)
+                 block=3, cmin=(2,), max_coarse=100, dense_tail=tail)
+    assert (s.info()["tail_level"] > 0) == (tail > 0 and len(H.levels) > 2)
     v = np.random.default_rng(9).standard_normal(p.n)
     assert rel(host(s.apply(L.OP_VCYCLE, dvec(v))), O.vcycle(H, v)) <= vtol(H)
     b = P.rhs_uniform(p.n, 3)
@@ -316,6 +333,8 @@ def test_config2_full_size(gpu_device):
     s = L.Solver(p.G, 2, p.grid, device=0, cmin=(2,))
     inf = s.info()
     assert inf["nlevels"] == len(fx["levels"])
+    # levels 3.. (9,021 unknowns and below) run as one dense operator
+    assert inf["tail_level"] == 3
     for l, lv in enumerate(fx["levels"]):
         assert inf["levels"][l]["n"] == lv["n"]
         if lv["coarsest"]:
