@@ -159,6 +159,12 @@ def main():
     ap.add_argument("--pool", type=int, default=16)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=160.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the solves, negate a float32 buffer of this many MiB "
+                         "into another (a plain streaming kernel of known bytes, the "
+                         "reference for hardware byte counters)")
+    ap.add_argument("--maxit", type=int, default=0,
+                    help="PCG iteration cap (default 1000; 200 for ls3d)")
     args = ap.parse_args()
     if args.serve:
         if args.gpus != 1:
@@ -168,6 +174,8 @@ def main():
     three_d = args.workload == "ls3d"
     if args.N == 0:
         args.N = 128 if three_d else 512
+    if args.maxit == 0:
+        args.maxit = 200 if three_d else 1000
     if three_d:
         # the oracle's Python setup of a 2M-unknown hierarchy takes hours, and
         # the multi-right-hand-side section is defined on the 2D operator
@@ -207,6 +215,12 @@ def main():
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
     inf = s.info()
+    if args.copy_calibration > 0:
+        src = torch.rand(args.copy_calibration << 18, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     b = torch.tensor(P.rhs_uniform(prob.n, seed), dtype=torch.float64, device="cuda:0")
     x = torch.empty_like(b)
     stream = torch.cuda.current_stream()
@@ -214,7 +228,7 @@ def main():
     def timed(prec, steps, warmup, only=None):
         s.set_precision(prec)
         for _ in range(warmup):
-            s.solve(b, tol=1e-8, out=x)
+            s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
         if only is not None:
             s.profile(True, only)
         torch.cuda.synchronize()
@@ -222,7 +236,7 @@ def main():
         t_start = time.perf_counter()
         for _ in range(steps):
             t1 = time.perf_counter()
-            _, st = s.solve(b, tol=1e-8, out=x)
+            _, st = s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
             lat.append((time.perf_counter() - t1) * 1e3)
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t_start
@@ -232,20 +246,26 @@ def main():
         return dict(solves_per_s=steps / elapsed, ms_per_step=elapsed * 1e3 / steps,
                     p50_ms=percentile(lat, 0.5), p99_ms=percentile(lat, 0.99),
                     iters=st[0]["iters"], true_rel_res=st[0]["true_rel_res"],
-                    converged=bool(st[0]["converged"])), kp
+                    converged=bool(st[0]["converged"]),
+                    ms_per_iteration=elapsed * 1e3 / steps / max(1, st[0]["iters"])), kp
 
     # untimed pass over every kernel: find the dominant kernel of the mixed path
     s.set_precision(L.MIXED)
-    s.solve(b, tol=1e-8, out=x)
+    s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
     s.profile(True)
-    s.solve(b, tol=1e-8, out=x)
+    s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
     allk = sorted(s.profile_read(), key=lambda r: -r["ms"])
     s.profile(False)
     dominant = allk[0]["name"]
     ktotal = sum(r["ms"] for r in allk)
 
+    # timed region: the dominant kernel's launches carry HIP events (so the
+    # V-cycle is launched kernel by kernel); the same solve replaying its
+    # V-cycle from a HIP graph is timed next, without events
     mixed, kp = timed(L.MIXED, args.steps, args.warmup, only=dominant)
     print(f"mixed {mixed['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
+    mixed_graph, _ = timed(L.MIXED, args.steps, args.warmup)
+    print(f"mixed (graph) {mixed_graph['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     fp64, _ = timed(L.FP64, args.steps, args.warmup)
     print(f"fp64 {fp64['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
 
@@ -253,15 +273,35 @@ def main():
     # 100-163) solved together, one FP64 CG per column, FP32 V-cycle
     batched = None
     if args.batch > 0:
-        B = torch.tensor([P.rhs_uniform(prob.n, 100 + j) for j in range(args.batch)],
+        import numpy as np
+        B = torch.tensor(np.stack([P.rhs_uniform(prob.n, 100 + j) for j in range(args.batch)]),
                          dtype=torch.float64, device="cuda:0")
         XB = torch.empty_like(B)
         s.set_precision(L.MIXED)
+        s.solve(B, tol=1e-8, out=XB)     # first batched solve: autotunes the MFMA tiles
+        s.profile(True, by_level=True)
         s.solve(B, tol=1e-8, out=XB)
-        s.profile(True)
-        s.solve(B, tol=1e-8, out=XB)
-        bk = sorted(s.profile_read(), key=lambda r: -r["ms"])
+        bkl = s.profile_read()
         s.profile(False)
+        merged = {}
+        for r in bkl:
+            nm = r["name"].split(" @L")[0]
+            m = merged.setdefault(nm, dict(name=nm, ms=0.0, launches=0, bytes=0.0))
+            m["ms"] += r["ms"]
+            m["launches"] += r["launches"]
+            m["bytes"] += r["bytes"]
+        bk = sorted(merged.values(), key=lambda r: -r["ms"])
+        # matrix-core utilisation of the dense level's GEMM (2 n^2 NB flops)
+        mfma = None
+        lt = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
+        nt = inf["levels"][lt]["n"]
+        for r in bkl:
+            if r["name"].startswith("k_bmm<") and r["name"].endswith(f"@L{lt}") and r["launches"]:
+                us = r["ms"] / r["launches"] * 1e3
+                tf = 2.0 * nt * nt * args.batch / (us * 1e-6) / 1e12
+                mfma = dict(kernel=r["name"], n=nt, nrhs=args.batch, avg_launch_us=round(us, 2),
+                            achieved=round(tf, 2), peak=157.3, unit="TFLOP/s",
+                            frac=round(tf / 157.3, 4))
         nb_steps = max(2, args.steps // 4)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -275,10 +315,11 @@ def main():
                        iters_min=min(its), iters_max=max(its),
                        all_converged=all(r["converged"] for r in bst),
                        max_true_rel_res=max(r["true_rel_res"] for r in bst),
+                       mfma_dense=mfma,
                        top_kernels=[dict(name=r["name"], ms_per_batch=round(r["ms"], 3),
                                          launches=r["launches"],
                                          gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1))
-                                    for r in bk[:5]])
+                                    for r in bk[:6]])
     dom = next((r for r in kp if r["name"] == dominant), None)
     roofline = None
     if dom and dom["launches"] > 0 and dom["ms"] > 0:
@@ -339,14 +380,19 @@ def main():
             "smoother_complexity": round(inf["smoother_complexity"], 3),
             "smoother_entries": smoother_entries,
             "setup_s": round(t_setup, 2),
+            "dense_tail_level": inf["tail_level"],
             "device_gb": round(inf["device_bytes"] / 1e9, 2),
             "parallelism": "single GPU",
         },
         "p50_ms": round(mixed["p50_ms"], 3),
         "p99_ms": round(mixed["p99_ms"], 3),
         "iters": mixed["iters"],
+        "converged": mixed["converged"],
         "true_rel_res": mixed["true_rel_res"],
+        "ms_per_iteration": round(mixed["ms_per_iteration"], 4),
         "vcycles_per_s": round(mixed["solves_per_s"] * (mixed["iters"] + 1), 1),
+        "mixed_graph": {k: (round(v, 4) if isinstance(v, float) and k != "true_rel_res" else v)
+                        for k, v in mixed_graph.items()},
         "fp64": {k: (round(v, 4) if isinstance(v, float) and k != "true_rel_res" else v)
                  for k, v in fp64.items()},
         "batched_mixed": batched,

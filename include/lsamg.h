@@ -228,6 +228,32 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y,
 /* Select the V-cycle precision (LSAMG_FP64 or LSAMG_MIXED) for later calls. */
 int lsamg_set_precision(lsamg_handle* h, int32_t precision);
 
+enum {
+  LSAMG_OPT_BATCHED = 0,  /* 1 (default): nrhs > 1 is solved in batches of up to
+                             64 interleaved columns that share every matrix read;
+                             0: one column after another                        */
+  LSAMG_OPT_MFMA = 1,     /* 1 (default): the FP32 V-cycle of a batch of >= 16
+                             columns runs its local solves, transfers and dense
+                             coarse operator as matrix-core (MFMA) tiles whose
+                             shapes are autotuned on the first such solve;
+                             0: plain FMA kernels                               */
+  LSAMG_OPT_GRAPH = 2     /* 1 (default): each V-cycle of a solve is replayed
+                             from a HIP graph of kernel nodes built on first use (one per
+                             precision and batch width; not while kernel timing
+                             is on); 0: kernels launched one by one             */
+};
+
+/* Set a solve-path option (LSAMG_OPT_*) for later calls.  EINVAL on an
+ * unknown option or value. */
+int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
+
+/* Y = B X: one V-cycle from zero (the preconditioner of lsamg_solve, sec.
+ * 3.1.1) applied to nrhs <= 64 columns at once by the multi-right-hand-side
+ * path, in the selected precision.  X, Y: device, FP64, column-major
+ * n x nrhs with leading dimension ld >= n.  Errors: EINVAL, ENODEV, EHIP. */
+int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y,
+                             int32_t nrhs, int64_t ld, void* stream);
+
 /* Kernel timing.  mode 1: bracket every kernel launch of later solve /
  * apply calls with a pair of HIP events recorded on the launch stream; if
  * only != NULL, only launches of that kernel symbol are bracketed (the others

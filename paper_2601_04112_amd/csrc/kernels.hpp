@@ -227,18 +227,20 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
   T acc = 0;
   if (j < nj) {
     const T* m = M + op.moff[a] + j;
-    T a1 = 0, a2 = 0, a3 = 0;
+    constexpr int U = 8;                    // independent loads in flight per lane
+    T av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) av[u] = 0;
     int l = wave;
-    for (; l + 3 * NW < nl; l += 4 * NW) {  // four independent loads in flight
-      const T m0 = m[(int64_t)l * nj], m1 = m[(int64_t)(l + NW) * nj];
-      const T m2 = m[(int64_t)(l + 2 * NW) * nj], m3 = m[(int64_t)(l + 3 * NW) * nj];
-      acc += m0 * sv[l];
-      a1 += m1 * sv[l + NW];
-      a2 += m2 * sv[l + 2 * NW];
-      a3 += m3 * sv[l + 3 * NW];
+    for (; l + (U - 1) * NW < nl; l += U * NW) {
+      T mv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * NW) * nj];
+#pragma unroll
+      for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
     }
-    for (; l < nl; l += NW) acc += m[(int64_t)l * nj] * sv[l];
-    acc = (acc + a1) + (a2 + a3);
+    for (; l < nl; l += NW) av[0] += m[(int64_t)l * nj] * sv[l];
+    acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
   }
   part[threadIdx.x] = acc;
   __syncthreads();
@@ -441,49 +443,141 @@ __global__ void __launch_bounds__(kBlock) k_resid_stg(int64_t n, const int64_t* 
   if (lane == 0) r[i] = b[i] - t;
 }
 
-// Dense level operator (the coarsest inverse, or the precomputed V-cycle of a
-// dense tail): e = M r, M row-major n x n.  A wavefront takes four rows, so
-// each loaded r entry serves four rows; lanes stride the row with eight
-// independent loads per row in flight.
+// ---------------------------------------------------------------------------
+// Symmetric dense level operator S (the coarsest inverse or the dense tail)
+// in packed 64x64 tiles: only the tiles (I, J) with J <= I are stored (S
+// zero-padded to nT = ceil(n/64) tiles per side), each row-major and
+// contiguous, tile (I, J) at (I(I+1)/2 + J) * 4096.  y = S x reads every
+// stored tile once: the workgroup of tile (I, J) adds S_IJ x_J to row block I
+// and, off the diagonal, S_IJ^T x_I to row block J, each into its own slot of
+// part (slot J of block I, slot I of block J), so that every slot of every
+// row block is written exactly once; k_sym_reduce then adds the nT slots of
+// each row in slot order (deterministic, no atomics).  Half the bytes of the
+// full matrix, and 16-byte aligned loads.
+// ---------------------------------------------------------------------------
+constexpr int kTile = 64;
+
+__device__ __forceinline__ void tile_ij(int64_t t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((int64_t)(i + 1) * (i + 2) / 2 <= t) ++i;
+  while ((int64_t)i * (i + 1) / 2 > t) --i;
+  I = i;
+  J = (int)(t - (int64_t)i * (i + 1) / 2);
+}
+
+// one workgroup per stored tile: S_packed(I, J) = A(I, J) (A row-major n x n)
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dense_gemv(int64_t n, const T* __restrict__ M,
-                                                       const T* __restrict__ r,
-                                                       T* __restrict__ e) {
-  constexpr int R = 4, U = 8;
-  const int64_t row0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / 64 * R;
-  const int lane = threadIdx.x % 64;
-  if (row0 >= n) return;
-  const T* mr[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q) mr[q] = M + (row0 + q < n ? row0 + q : row0) * n;
-  T acc[R][2] = {};
-  int64_t j = lane;
-  for (; j + (U - 1) * 64 < n; j += U * 64) {
-    T rv[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) rv[u] = r[j + u * 64];
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      T mv[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = mr[q][j + u * 64];
-#pragma unroll
-      for (int u = 0; u < U; ++u) acc[q][u & 1] += mv[u] * rv[u];
-    }
-  }
-  for (; j < n; j += 64) {
-    const T rv = r[j];
-#pragma unroll
-    for (int q = 0; q < R; ++q) acc[q][0] += mr[q][j] * rv;
-  }
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const T t = wave_sum(acc[q][0] + acc[q][1], 64);
-    if (lane == 0 && row0 + q < n) e[row0 + q] = t;
+__global__ void __launch_bounds__(kBlock) k_sym_pack(int64_t n, const double* __restrict__ A,
+                                                     T* __restrict__ S) {
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  T* dst = S + (int64_t)blockIdx.x * kTile * kTile;
+  for (int e = threadIdx.x; e < kTile * kTile; e += kBlock) {
+    const int64_t r = (int64_t)I * kTile + e / kTile, c = (int64_t)J * kTile + e % kTile;
+    dst[e] = (r < n && c < n) ? (T)A[r * n + c] : T(0);
   }
 }
 
-// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the
+template <typename T>
+__device__ __forceinline__ void load4(const T* __restrict__ p, T (&m)[4]);
+template <>
+__device__ __forceinline__ void load4<float>(const float* __restrict__ p, float (&m)[4]) {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  const v4 t = *(const v4*)p;
+  m[0] = t[0];
+  m[1] = t[1];
+  m[2] = t[2];
+  m[3] = t[3];
+}
+template <>
+__device__ __forceinline__ void load4<double>(const double* __restrict__ p, double (&m)[4]) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 t0 = *(const v2*)p, t1 = *(const v2*)(p + 2);
+  m[0] = t0[0];
+  m[1] = t0[1];
+  m[2] = t1[0];
+  m[3] = t1[1];
+}
+
+// part: nT slots of nT*64 values.  Lane l of wave w holds the 4x4 block of
+// the tile at rows 4*rb .. 4*rb+3, columns 4*cb .. 4*cb+3 with cb = l % 16 and
+// rb = 4*w + l / 16: the sixteen lanes of a row group read 256 contiguous
+// bytes per row.  Row sums (S_IJ x_J) reduce over cb inside the wave;
+// column sums (S_IJ^T x_I) reduce over rb across lanes, then over the four
+// wavefronts through LDS; every sum is taken in a fixed order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sym_gemv(int64_t n, int nT, const T* __restrict__ S,
+                                                     const T* __restrict__ x,
+                                                     T* __restrict__ part) {
+  __shared__ T sm[4][kTile];
+  int I, J;
+  tile_ij(blockIdx.x, I, J);
+  const int64_t npad = (int64_t)nT * kTile;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cb = lane & 15, rb = 4 * w + (lane >> 4);
+  const T* src = S + (int64_t)blockIdx.x * kTile * kTile + (4 * rb) * kTile + 4 * cb;
+  T m[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) load4<T>(src + i * kTile, m[i]);
+  const int64_t r0 = (int64_t)I * kTile + 4 * rb, c0 = (int64_t)J * kTile + 4 * cb;
+  T xc[4], xr[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    xc[k] = c0 + k < n ? x[c0 + k] : T(0);
+    xr[k] = r0 + k < n ? x[r0 + k] : T(0);
+  }
+  // S_IJ x_J: rows 4rb + i, summed over the 16 lanes of the row group
+  T d[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    d[i] = (m[i][0] * xc[0] + m[i][1] * xc[1]) + (m[i][2] * xc[2] + m[i][3] * xc[3]);
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) d[i] += __shfl_xor(d[i], o);
+  }
+  if (cb < 4) part[(int64_t)J * npad + r0 + cb] = cb == 0 ? d[0] : cb == 1 ? d[1] : cb == 2 ? d[2] : d[3];
+  if (I != J) {                    // uniform over the workgroup
+    // S_IJ^T x_I: columns 4cb + k, summed over the rows of the lane, the four
+    // row groups of the wave, then the four waves
+    T t[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      t[k] = (m[0][k] * xr[0] + m[1][k] * xr[1]) + (m[2][k] * xr[2] + m[3][k] * xr[3]);
+      t[k] += __shfl_xor(t[k], 16);
+      t[k] += __shfl_xor(t[k], 32);
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) sm[w][4 * cb + k] = t[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kTile)
+      part[(int64_t)I * npad + (int64_t)J * kTile + threadIdx.x] =
+          (sm[0][threadIdx.x] + sm[1][threadIdx.x]) + (sm[2][threadIdx.x] + sm[3][threadIdx.x]);
+  }
+}
+
+// y[i] = sum over the nT slots s of part[s*npad + i] in a fixed order: a
+// workgroup takes 16 rows; thread (g, i) adds slots g, g + 16, ...; the 16
+// partial sums of a row are then added in g order.  Grid: ceil(npad / 16).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_sym_reduce(int64_t n, int nT, const T* __restrict__ part,
+                                                       T* __restrict__ y) {
+  __shared__ T sm[16][16];
+  const int il = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + il;
+  const int64_t npad = (int64_t)nT * kTile;
+  T t = 0;
+  for (int s = g; s < nT; s += 16) t += part[(int64_t)s * npad + i];
+  sm[g][il] = t;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    T u = 0;
+    for (int q = 0; q < 16; ++q) u += sm[q][il];
+    y[i] = u;
+  }
+}
+
+// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the
 // interleaved n x NB layout of the multi-right-hand-side path.
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_unit_block(int64_t n, int64_t j0,

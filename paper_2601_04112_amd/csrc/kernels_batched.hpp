@@ -13,6 +13,52 @@
 namespace lsamg {
 namespace dev {
 
+// With NB = 64 a wavefront works on one row (or unknown) at a time; the
+// index is then made explicitly wave-uniform, so that the row's CSR
+// pointers, column indices and values are fetched by scalar loads once per
+// wavefront and only the gathers of the NB vector values use vector loads.
+// Callers keep row counts below 2^31.
+template <int NB>
+__device__ __forceinline__ int64_t wave_row(int64_t r) {
+  if constexpr (NB == 64)
+    return (int64_t)__builtin_amdgcn_readfirstlane((int)r);
+  else
+    return r;
+}
+
+// sum over e in [e0, e1) of val[e] * X[col[e]][j]: eight entries at a time,
+// all their indices and values loaded before the gathers are issued, so a
+// wavefront keeps eight gathers in flight
+template <typename T, int NB>
+__device__ __forceinline__ T row_dot(int64_t e0, int64_t e1, const int32_t* __restrict__ col,
+                                     const T* __restrict__ val, const T* __restrict__ X, int j) {
+  constexpr int U = 8;
+  T acc[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) acc[u] = 0;
+  int64_t e = e0;
+  for (; e + U <= e1; e += U) {
+    int32_t c[U];
+    T v[U], x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      c[u] = col[e + u];
+      v[u] = val[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) x[u] = X[(int64_t)c[u] * NB + j];
+#pragma unroll
+    for (int u = 0; u < U; ++u) acc[u] += v[u] * x[u];
+  }
+  for (int u = 0; u < U - 1; ++u) {        // remainder: at most U - 1 entries
+    const bool ok = e + u < e1;
+    const int32_t c = ok ? col[e + u] : 0;
+    const T v = ok ? val[e + u] : T(0);
+    acc[u] += v * X[(int64_t)c * NB + j];
+  }
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 // Y = G X: one group of NB lanes per row, lanes along the right-hand sides.
 template <typename T, int NB>
 __global__ void __launch_bounds__(kBlock) k_bspmv(int64_t nrows, const int64_t* __restrict__ ptr,
@@ -20,20 +66,10 @@ __global__ void __launch_bounds__(kBlock) k_bspmv(int64_t nrows, const int64_t* 
                                                   const T* __restrict__ val,
                                                   const T* __restrict__ X, T* __restrict__ Y) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t row = gid / NB;
+  const int64_t row = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (row >= nrows) return;
-  const int64_t e0 = ptr[row], e1 = ptr[row + 1];
-  T s0 = 0, s1 = 0;
-  int64_t e = e0;
-  for (; e + 1 < e1; e += 2) {
-    const int32_t c0 = col[e], c1 = col[e + 1];
-    const T v0 = val[e], v1 = val[e + 1];
-    s0 += v0 * X[(int64_t)c0 * NB + j];
-    s1 += v1 * X[(int64_t)c1 * NB + j];
-  }
-  if (e < e1) s0 += val[e] * X[(int64_t)col[e] * NB + j];
-  Y[row * NB + j] = s0 + s1;
+  Y[row * NB + j] = row_dot<T, NB>(ptr[row], ptr[row + 1], col, val, X, j);
 }
 
 // R = B - G^T Y (B == nullptr: R = G^T Y)
@@ -45,24 +81,82 @@ __global__ void __launch_bounds__(kBlock) k_bresid_t(int64_t n, const int64_t* _
                                                      const T* __restrict__ B,
                                                      T* __restrict__ R) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t d = gid / NB;
+  const int64_t d = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (d >= n) return;
-  const int64_t e0 = ptr[d], e1 = ptr[d + 1];
-  T s0 = 0, s1 = 0;
-  int64_t e = e0;
-  for (; e + 1 < e1; e += 2) {
-    const int32_t c0 = col[e], c1 = col[e + 1];
-    const T v0 = val[e], v1 = val[e + 1];
-    s0 += v0 * Y[(int64_t)c0 * NB + j];
-    s1 += v1 * Y[(int64_t)c1 * NB + j];
-  }
-  if (e < e1) s0 += val[e] * Y[(int64_t)col[e] * NB + j];
-  const T s = s0 + s1;
+  const T s = row_dot<T, NB>(ptr[d], ptr[d + 1], col, val, Y, j);
   R[d * NB + j] = B ? B[d * NB + j] - s : s;
 }
 
-// Batched form of the aggregate GEMV family (see k_gemv_*):
+// R = B - G^T (G X) in one pass, for a G whose rows are short (the finest
+// level): the work item of unknown d takes the (at most ME) rows of G that
+// touch d (its row of G^T) and recomputes each y_r = g_r . X (rows of at most
+// MF entries) from cached entries, so G X is never written to memory.  All
+// indices of one level of the chain (G^T entries, row pointers, row entries)
+// are loaded before the next level, so the gathers of every row are in
+// flight together.  B == nullptr gives R = G^T G X.
+template <typename T, int NB, int ME, int MF>
+__device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_ptr,
+                                     const int32_t* __restrict__ gt_col,
+                                     const T* __restrict__ gt_val,
+                                     const int64_t* __restrict__ g_ptr,
+                                     const int32_t* __restrict__ g_col,
+                                     const T* __restrict__ g_val, const T* __restrict__ X, int j) {
+  const int64_t e0 = gt_ptr[d];
+  const int ne = (int)(gt_ptr[d + 1] - e0);
+  int64_t r[ME], f0[ME];
+  int nf[ME];
+  T w[ME];
+#pragma unroll
+  for (int k = 0; k < ME; ++k) {
+    const bool ok = k < ne;
+    r[k] = ok ? (int64_t)gt_col[e0 + k] : 0;
+    w[k] = ok ? gt_val[e0 + k] : T(0);
+  }
+#pragma unroll
+  for (int k = 0; k < ME; ++k) {
+    f0[k] = g_ptr[r[k]];
+    nf[k] = k < ne ? (int)(g_ptr[r[k] + 1] - f0[k]) : 0;
+  }
+  int32_t c[ME][MF];
+  T v[ME][MF];
+#pragma unroll
+  for (int k = 0; k < ME; ++k)
+#pragma unroll
+    for (int q = 0; q < MF; ++q) {
+      const bool ok = q < nf[k];
+      c[k][q] = ok ? g_col[f0[k] + q] : 0;
+      v[k][q] = ok ? g_val[f0[k] + q] : T(0);
+    }
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < ME; ++k) {
+    T y = 0;
+#pragma unroll
+    for (int q = 0; q < MF; ++q) y += v[k][q] * X[(int64_t)c[k][q] * NB + j];
+    acc += w[k] * y;
+  }
+  return acc;
+}
+
+template <typename T, int NB, int ME, int MF>
+__global__ void __launch_bounds__(kBlock) k_bata(int64_t n, const int64_t* __restrict__ gt_ptr,
+                                                 const int32_t* __restrict__ gt_col,
+                                                 const T* __restrict__ gt_val,
+                                                 const int64_t* __restrict__ g_ptr,
+                                                 const int32_t* __restrict__ g_col,
+                                                 const T* __restrict__ g_val,
+                                                 const T* __restrict__ X, const T* __restrict__ B,
+                                                 T* __restrict__ R) {
+  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t d = wave_row<NB>(gid / NB);
+  const int j = (int)(gid % NB);
+  if (d >= n) return;
+  const T acc = ata_row<T, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
+  R[d * NB + j] = B ? B[d * NB + j] - acc : acc;
+}
+
+// Batched form of the aggregate GEMV family (see k_gemv_*):// Batched form of the aggregate GEMV family (see k_gemv_*):
 //   OUT[obase_a + jj][:] (=|+=) sum_l M_a[l][jj] * IN_a[l][:]
 // Task = (aggregate a, 64-wide slice j0 of its outputs) x all NB columns.
 // Thread t: output row jj = j0 + (t % 64) (lanes along the contiguous matrix
@@ -127,6 +221,167 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
   }
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core form of k_bgemm for the FP32 V-cycle and NB >= 16 right-hand
+// sides: every per-aggregate product OUT_a = M_a^T IN_a is tiled into
+// v_mfma_f32_16x16x4f32 operations (FP32 operands, FP32 accumulation).
+//
+// One wavefront runs one task at a time: aggregate a, output rows
+// [j0, j0 + 16*RT) (RT row tiles), loop indices [k0, k1), all NB columns
+// (CT = NB/16 column tiles).  The launch is persistent: its waves stride over
+// the task list, which the host orders longest-first (size buckets), so one
+// launch covers every aggregate of a level.
+//
+// v_mfma_f32_16x16x4f32 computes D(16x16) += A(16x4) B(4x16); lane L = i +
+// 16 g supplies A[i][g] and B[g][i] and receives D[4g + v][i] in acc[v].
+// Here A[i][g] = M_a[l][j0 + 16 r + i] and B[g][i] = IN_a[l][CT i + q] with
+// l = k + g (row tile r, column tile q): the sixteen lanes of a group read
+// 64 contiguous bytes of M_a and 64*CT contiguous bytes of one input row, so
+// the input is fetched with one CT-wide vector load per lane, and each
+// output row is written back the same way.
+//
+// Tasks with slot >= 0 (a loop split across waves) store their partial sums
+// to part[slot][row][:] for k_bmm_reduce; the others write (or add to) out.
+// ---------------------------------------------------------------------------
+struct MmTasks {
+  const int32_t* a;     // aggregate
+  const int32_t* j0;    // first output row
+  const int32_t* k0;    // loop range [k0, k1)
+  const int32_t* k1;
+  const int32_t* slot;  // partial-sum slot, or -1
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+template <int CT>
+__device__ __forceinline__ void vload(const float* __restrict__ p, float (&v)[CT]) {
+  if constexpr (CT == 4) {
+    const f32x4 t = *(const f32x4*)p;
+    v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
+  } else if constexpr (CT == 2) {
+    const f32x2 t = *(const f32x2*)p;
+    v[0] = t[0]; v[1] = t[1];
+  } else {
+    v[0] = *p;
+  }
+}
+
+template <int CT>
+__device__ __forceinline__ void vstore(float* __restrict__ p, const float (&v)[CT]) {
+  if constexpr (CT == 4) {
+    f32x4 t;
+    t[0] = v[0]; t[1] = v[1]; t[2] = v[2]; t[3] = v[3];
+    *(f32x4*)p = t;
+  } else if constexpr (CT == 2) {
+    f32x2 t;
+    t[0] = v[0]; t[1] = v[1];
+    *(f32x2*)p = t;
+  } else {
+    *p = v[0];
+  }
+}
+
+template <int MODE, bool ADD, int RT, int NB>
+__global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op,
+                                                const int32_t* __restrict__ gidx,
+                                                const int64_t* __restrict__ cptr,
+                                                const int64_t* __restrict__ cpos,
+                                                const float* __restrict__ tb,
+                                                const float* __restrict__ M,
+                                                const float* __restrict__ in,
+                                                float* __restrict__ out,
+                                                float* __restrict__ part, int64_t part_rows) {
+  static_assert(NB % 16 == 0 && NB <= 64, "column tiles of 16");
+  constexpr int CT = NB / 16;
+  constexpr int U = 2;                       // loop steps whose loads are issued together
+  constexpr int WPB = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, g = lane >> 4;
+  for (int t = __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + (threadIdx.x >> 6)); t < ntask;
+       t += gridDim.x * WPB) {
+    const int a = tk.a[t], j0 = tk.j0[t], k0 = tk.k0[t], k1 = tk.k1[t];
+    const int nj = op.lj[a];
+    const int64_t ib = op.ibase[a];
+    const float* __restrict__ m = M + op.moff[a];
+    f32x4 acc[RT][CT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int q = 0; q < CT; ++q) acc[r][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int k = k0; k < k1; k += 4 * U) {
+      float av[U][RT], bv[U][CT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = k + 4 * u + g;
+        const bool lv = l < k1;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const int jj = j0 + 16 * r + i;
+          av[u][r] = (lv && jj < nj) ? m[(int64_t)l * nj + jj] : 0.f;
+        }
+#pragma unroll
+        for (int q = 0; q < CT; ++q) bv[u][q] = 0.f;
+        if (lv) {
+          const int64_t e = ib + l;
+          const int64_t row = MODE == IN_GATHER ? (int64_t)gidx[e] : e;
+          vload<CT>(in + row * NB + CT * i, bv[u]);
+          if (MODE == IN_TB) {
+            for (int64_t p = cptr[e]; p < cptr[e + 1]; ++p) {
+              float w[CT];
+              vload<CT>(tb + cpos[p] * NB + CT * i, w);
+#pragma unroll
+              for (int q = 0; q < CT; ++q) bv[u][q] += w[q];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int q = 0; q < CT; ++q)
+            acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u][r], bv[u][q], acc[r][q], 0, 0, 0);
+    }
+    const int slot = tk.slot[t];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = j0 + 16 * r + 4 * g + v;
+        if (jj >= nj) continue;
+        float o[CT];
+#pragma unroll
+        for (int q = 0; q < CT; ++q) o[q] = acc[r][q][v];
+        if (slot >= 0) {
+          vstore<CT>(part + ((int64_t)slot * part_rows + jj) * NB + CT * i, o);
+        } else {
+          float* d = out + (op.obase[a] + jj) * NB + CT * i;
+          if (ADD) {
+            float w[CT];
+            vload<CT>(d, w);
+#pragma unroll
+            for (int q = 0; q < CT; ++q) o[q] += w[q];
+          }
+          vstore<CT>(d, o);
+        }
+      }
+  }
+}
+
+// out[r][:] (=|+=) sum over the S slots of part[s][r][:], in slot order
+template <bool ADD, int NB>
+__global__ void __launch_bounds__(kBlock) k_bmm_reduce(int64_t rows, int S,
+                                                       const float* __restrict__ part,
+                                                       float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= rows * NB) return;
+  float s = 0.f;
+  for (int k = 0; k < S; ++k) s += part[(int64_t)k * rows * NB + e];
+  out[e] = ADD ? out[e] + s : s;
+}
+
 // X[j][:] += staged RAS-T contributions (batched k_gather_add)
 template <typename T, int NB>
 __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t* __restrict__ cptr,
@@ -134,7 +389,7 @@ __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t
                                                         const T* __restrict__ tb,
                                                         T* __restrict__ X) {
   const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t d = gid / NB;
+  const int64_t d = wave_row<NB>(gid / NB);
   const int c = (int)(gid % NB);
   if (d >= n) return;
   T s = X[d * NB + c];
@@ -143,9 +398,11 @@ __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t
 }
 
 // ---------------------------------------------------------------------------
-// Batched FP64 CG.  Column j has its own scalars; partial sums are stored per
-// workgroup and column (part[blockIdx.x * NB + j]) and re-summed in fixed
-// order by the consuming kernel.  active[j] = 0 freezes a converged column.
+// Batched FP64 CG.  Column j has its own scalars.  A kernel that produces a
+// dot product stores one partial per workgroup and column
+// (part[blockIdx.x * NB + j]); k_bsum adds them in a fixed order into one
+// scalar per column, which the consuming kernels read.  active[j] = 0
+// freezes a converged column.
 // ---------------------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void bwrite_parts(double v, double* __restrict__ part) {
@@ -161,11 +418,22 @@ __device__ __forceinline__ void bwrite_parts(double v, double* __restrict__ part
   __syncthreads();
 }
 
-// value of column j summed over np workgroups (same order everywhere)
-__device__ __forceinline__ double bsum(const double* __restrict__ part, int np, int NB, int j) {
+// out[j] = sum over np workgroup partials of column j (one workgroup per
+// column; strided partial sums, then a fixed-order tree)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bsum(int np, const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  __shared__ double sm[kBlock];
+  const int j = blockIdx.x;
   double s = 0;
-  for (int b = 0; b < np; ++b) s += part[(int64_t)b * NB + j];
-  return s;
+  for (int b = threadIdx.x; b < np; b += kBlock) s += part[(int64_t)b * NB + j];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = sm[0];
 }
 
 template <int NB>
@@ -192,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq(int64_t n, const int64_t* __
                                                     double* __restrict__ part) {
   const int j = threadIdx.x % NB;
   double v = 0;
-  for (int64_t d = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / NB; d < n;
+  for (int64_t d = wave_row<NB>(((int64_t)blockIdx.x * kBlock + threadIdx.x) / NB); d < n;
        d += (int64_t)gridDim.x * (kBlock / NB)) {
     double s = 0;
     for (int64_t e = ptr[d]; e < ptr[d + 1]; ++e) s += val[e] * Y[(int64_t)col[e] * NB + j];
@@ -202,11 +470,34 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq(int64_t n, const int64_t* __
   bwrite_parts<NB>(v, part);
 }
 
-// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
+// Q = G^T (G P) in one pass (as k_bata) and partials of P . Q per column
+template <int NB, int ME, int MF>
+__global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* __restrict__ gt_ptr,
+                                                     const int32_t* __restrict__ gt_col,
+                                                     const double* __restrict__ gt_val,
+                                                     const int64_t* __restrict__ g_ptr,
+                                                     const int32_t* __restrict__ g_col,
+                                                     const double* __restrict__ g_val,
+                                                     const double* __restrict__ P,
+                                                     double* __restrict__ Q,
+                                                     double* __restrict__ part) {
+  const int j = threadIdx.x % NB;
+  double v = 0;
+  for (int64_t d = wave_row<NB>(((int64_t)blockIdx.x * kBlock + threadIdx.x) / NB); d < n;
+       d += (int64_t)gridDim.x * (kBlock / NB)) {
+    const double acc =
+        ata_row<double, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, P, j);
+    Q[d * NB + j] = acc;
+    v += acc * P[d * NB + j];
+  }
+  bwrite_parts<NB>(v, part);
+}
+
+// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
 // R32 = (float) R (if given); partials of R . R
 template <int NB>
-__global__ void __launch_bounds__(kBlock) k_bcg_update(int64_t n, const double* __restrict__ rz_part,
-                                                       const double* __restrict__ pq_part,
+__global__ void __launch_bounds__(kBlock) k_bcg_update(int64_t n, const double* __restrict__ rz,
+                                                       const double* __restrict__ pqs,
                                                        const int* __restrict__ active,
                                                        const double* __restrict__ P,
                                                        const double* __restrict__ Q,
@@ -214,12 +505,11 @@ __global__ void __launch_bounds__(kBlock) k_bcg_update(int64_t n, const double* 
                                                        double* __restrict__ R,
                                                        float* __restrict__ R32,
                                                        double* __restrict__ rr_part) {
-  const int np = gridDim.x;
   const int j = threadIdx.x % NB;
   bool act = active[j] != 0;
-  const double pq = act ? bsum(pq_part, np, NB, j) : 0.0;
+  const double pq = act ? pqs[j] : 0.0;
   act = act && pq != 0.0;
-  const double alpha = act ? bsum(rz_part, np, NB, j) / pq : 0.0;
+  const double alpha = act ? rz[j] / pq : 0.0;
   double v = 0;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
        e += (int64_t)gridDim.x * kBlock) {
@@ -246,7 +536,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
   double v = 0;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
        e += (int64_t)gridDim.x * kBlock) {
-    const int64_t d = e / NB;
+    const int64_t d = wave_row<NB>(e / NB);
     T s = XV[e];
     if (cptr)
       for (int64_t q = cptr[d]; q < cptr[d + 1]; ++q) s += tb[cpos[q] * NB + c];
@@ -257,18 +547,18 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
   bwrite_parts<NB>(v, rz_part);
 }
 
-// P = Z + beta P, beta_j = rz_new_j / rz_old_j (rz_old == nullptr: P = Z)
+// P = Z + beta P, beta_j = rz_new_j / rz_old_j (rz_old == nullptr: P = Z);
+// rz_new, rz_old: per-column scalars
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_bcg_dir(int64_t n, const double* __restrict__ rz_new,
                                                     const double* __restrict__ rz_old,
                                                     const double* __restrict__ Z,
                                                     double* __restrict__ P) {
-  const int np = gridDim.x;
   const int j = threadIdx.x % NB;
   double beta = 0.0;
   if (rz_old) {
-    const double o = bsum(rz_old, np, NB, j);
-    beta = o != 0.0 ? bsum(rz_new, np, NB, j) / o : 0.0;   // an all-zero column stays zero
+    const double o = rz_old[j];
+    beta = o != 0.0 ? rz_new[j] / o : 0.0;   // an all-zero column stays zero
   }
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
        e += (int64_t)gridDim.x * kBlock)

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -59,6 +60,8 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* Zh = nullptr;        // Zhat_i row-major (restriction P^T)
   T* ZhT = nullptr;       // Zhat_i column-major (prolongation P)
   T* Ainv = nullptr;      // coarsest inverse, or the dense tail operator
+  T* Spk = nullptr;       // the same operator as packed lower 64x64 tiles (k_sym_gemv)
+  T* spart = nullptr;     // k_sym_gemv slots, nT * nT * 64
   T* x = nullptr;         // V-cycle output at this level
   T* b = nullptr;         // V-cycle input at this level
   T* r = nullptr;         // residual
@@ -80,6 +83,18 @@ struct GemvPlan {
   int64_t mat = 0, in_u = 0, idx = 0, out = 0;
   int32_t* task_a = nullptr;
   int32_t* task_j0 = nullptr;
+  // per-aggregate output and loop lengths, kept on the host for the task
+  // lists of the matrix-core batched form (k_bmm)
+  std::vector<int32_t> hlj, hll;
+  // tile shape of k_bmm chosen by the autotuner, and its task list
+  struct Mm {
+    int rt = 0;              // row tiles of 16 per task (0: not tuned, use k_bgemm)
+    int split = 1;           // loop split of a single-aggregate operator
+    int64_t ntask = 0;
+    unsigned grid = 0;       // workgroups of the persistent launch
+    dev::MmTasks tk{};
+    float* part = nullptr;   // partial sums of a split loop (split > 1)
+  } mm;
 };
 
 struct DLevel {
@@ -88,6 +103,9 @@ struct DLevel {
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
   bool tail = false;      // V-cycle from here down applied as the dense matrix Ainv
+  bool fuse_ata = false;  // rows of G short enough for the one-pass batched G^T G (k_bata)
+  int nT = 0;             // 64-row tiles per side of the packed dense operator
+  int ata_me = 8;         // k_bata: most rows of G per unknown (8 or 16; rows <= 4 entries)
   int lanes_g = 1, lanes_gt = 1;
   int max_nO = 0, max_nw = 0, max_k = 0;
   int64_t* g_ptr = nullptr;
@@ -168,6 +186,15 @@ struct ProfScope {
 // Launch kern on stream s; when the launch is being timed, the dispatch packet
 // itself stamps the start/stop events (hipExtLaunchKernel), so the recorded
 // interval is the kernel's own execution.
+// While a GraphRec is active on the calling thread, launches are appended to
+// its graph as kernel nodes (each depending on the previous one) instead of
+// being enqueued.
+struct GraphRec {
+  hipGraph_t g = nullptr;
+  hipGraphNode_t last = nullptr;
+};
+thread_local GraphRec* g_rec = nullptr;
+
 template <typename... KArgs, typename... Args>
 void klaunch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const ProfScope& ps,
              void (*kern)(KArgs...), Args&&... args) {
@@ -177,6 +204,22 @@ void klaunch(dim3 grid, dim3 block, size_t lds, hipStream_t s, const ProfScope& 
     int i = 0;
     ((argv[i++] = (void*)&e), ...);
   }, tup);
+  if (g_rec) {
+    hipKernelNodeParams kp{};
+    kp.func = (void*)kern;
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = (unsigned)lds;
+    kp.kernelParams = argv;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    const hipError_t e = hipGraphAddKernelNode(&node, g_rec->g, g_rec->last ? &g_rec->last : nullptr,
+                                               g_rec->last ? 1 : 0, &kp);
+    if (e != hipSuccess)
+      throw DevError{LSAMG_EHIP, std::string("graph kernel node: ") + hipGetErrorString(e)};
+    g_rec->last = node;
+    return;
+  }
   hipError_t e = ps.p ? hipExtLaunchKernel((const void*)kern, grid, block, argv, lds, s, ps.a,
                                            ps.b, 0)
                       : hipLaunchKernel((const void*)kern, grid, block, argv, lds, s);
@@ -215,6 +258,20 @@ struct lsamg_handle {
   int device = -1;
   int precision = LSAMG_FP64;
   int batch_mode = 1;               // 1: nrhs > 1 solved as batches of <= 64
+  bool use_mfma = true;             // FP32 batched V-cycle on the matrix cores (k_bmm)
+  // V-cycles replayed from HIP graphs, one per (precision, batch width)
+  bool use_graphs = true;
+  std::unordered_map<int, hipGraphExec_t> graphs;
+  void drop_graphs(bool batched_only) {
+    for (auto it = graphs.begin(); it != graphs.end();) {
+      if (!batched_only || (it->first & 127) > 1) {
+        (void)hipGraphExecDestroy(it->second);
+        it = graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
   std::vector<DLevel> L;
   std::vector<void*> allocs;
   size_t bytes = 0;
@@ -238,6 +295,8 @@ struct lsamg_handle {
   double *BX = nullptr, *BR = nullptr, *BZ = nullptr, *BP = nullptr, *BQ = nullptr,
          *BBi = nullptr, *Bpq = nullptr, *Brr = nullptr, *Brz[2] = {nullptr, nullptr},
          *Btmp = nullptr;
+  // per-column scalars summed from those partials (k_bsum)
+  double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr;
   int* Bactive = nullptr;
   int* Bactive_host = nullptr;       // pinned
   double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
@@ -274,7 +333,12 @@ struct lsamg_handle {
       HIP_OK(hipMemcpy(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     return ptr;
   }
+  bool mm_tuned = false;             // k_bmm tile shapes chosen for the batched buffers
   void free_batched() {
+    for (auto& D : L)
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
+    mm_tuned = false;
+    drop_graphs(true);
     for (void* ptr : ballocs) (void)hipFree(ptr);
     ballocs.clear();
     bytes -= bbytes;
@@ -289,6 +353,7 @@ struct lsamg_handle {
   }
   void free_all() {
     free_batched();
+    drop_graphs(false);
     for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
     for (auto& e : ev_rr)
       if (e) (void)hipEventDestroy(e);
@@ -378,6 +443,27 @@ void build_group_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
   D.f.stg = h->alloc<float>(nstg);
 }
 
+// Packed symmetric copy (k_sym_gemv) of the dense level operator, from the
+// FP64 matrix in D.d.Ainv (fill = false: allocate only).
+void make_packed(lsamg_handle* h, DLevel& D, bool fill) {
+  const int64_t n = D.n;
+  D.nT = (int)((n + dev::kTile - 1) / dev::kTile);
+  const int64_t nt = (int64_t)D.nT * (D.nT + 1) / 2;
+  const size_t tile = (size_t)dev::kTile * dev::kTile;
+  D.d.Spk = h->alloc<double>((size_t)nt * tile);
+  D.f.Spk = h->alloc<float>((size_t)nt * tile);
+  D.d.spart = h->alloc<double>((size_t)D.nT * D.nT * dev::kTile);
+  D.f.spart = h->alloc<float>((size_t)D.nT * D.nT * dev::kTile);
+  if (h->dry || !fill) return;
+  KLAUNCH0((unsigned)nt, dev::kBlock, 0, nullptr, dev::k_sym_pack<double>, n,
+           (const double*)D.d.Ainv, D.d.Spk);
+  LAUNCH_OK();
+  KLAUNCH0((unsigned)nt, dev::kBlock, 0, nullptr, dev::k_sym_pack<float>, n,
+           (const double*)D.d.Ainv, D.f.Spk);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(nullptr));
+}
+
 // The dense level operator Ainv (n x n) as a one-block operator of the
 // multi-right-hand-side GEMM.
 void make_dense_plan(lsamg_handle* h, DLevel& D) {
@@ -388,6 +474,8 @@ void make_dense_plan(lsamg_handle* h, DLevel& D) {
   int64_t* dz = h->upload(z1);
   P.op = dev::GemvOp{dz, dn, dn, dz, dz};
   P.nagg = 1;
+  P.hlj = n1;
+  P.hll = n1;
   P.lmax = (int)D.n;
   P.mat = D.n * D.n;
   P.in_u = P.out = D.n;
@@ -441,6 +529,15 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
         tv[o] = gv[e];
       }
   }
+  {
+    int64_t rmax = 0, tmax = 0;
+    for (int64_t r = 0; r < D.nrows; ++r) rmax = std::max(rmax, gp[r + 1] - gp[r]);
+    for (int64_t j = 0; j < D.n; ++j) tmax = std::max(tmax, tp[j + 1] - tp[j]);
+    // recomputing each row of G per touching unknown costs sum_r len(r)^2
+    // gathers: worth it only for short rows (finite-difference G)
+    D.fuse_ata = finest && rmax <= 4 && tmax <= 16;
+    D.ata_me = tmax <= 8 ? 8 : 16;
+  }
   D.lanes_g = lanes_for((double)D.nnz / std::max<int64_t>(1, D.nrows));
   D.lanes_gt = lanes_for((double)D.nnz / std::max<int64_t>(1, D.n));
   // a coarse coarsest level is solved densely and needs no G; the finest
@@ -467,6 +564,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   if (HL.coarsest) {
     D.d.Ainv = h->upload_f<double>(HL.Ainv);
     D.f.Ainv = h->upload_f<float>(HL.Ainv);
+    make_packed(h, D, true);
     make_dense_plan(h, D);
     return;
   }
@@ -544,6 +642,8 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
                   int64_t in_unique, bool gathered) {
     P.op = dev::GemvOp{moff, dlj, dll, ib, ob};
     P.nagg = HL.nagg;
+    P.hlj = lj;
+    P.hll = ll;
     P.mat = P.out = 0;
     for (int64_t a = 0; a < HL.nagg; ++a) {
       P.mat += (int64_t)lj[a] * ll[a];
@@ -826,9 +926,17 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   DLevel& L = h->L[l];
   DPrec<T>& P = prec<T>(L);
   if (L.coarsest || L.tail) {
-    PROF(kname("k_dense_gemv", tname<T>()), sizeof(T) * (L.n * L.n + 2 * L.n), s);
-    KLAUNCH(nblocks((L.n + 3) / 4 * 64), dev::kBlock, 0, s, dev::k_dense_gemv<T>, L.n, P.Ainv, b,
-            x);
+    {
+      // algorithmic: the stored half of the symmetric operator, x and y once
+      PROF(kname("k_sym_gemv", tname<T>()), sizeof(T) * (L.n * (L.n + 1) / 2 + 2 * L.n), s);
+      KLAUNCH((unsigned)((int64_t)L.nT * (L.nT + 1) / 2), dev::kBlock, 0, s, dev::k_sym_gemv<T>,
+              L.n, L.nT, (const T*)P.Spk, b, P.spart);
+      LAUNCH_OK();
+    }
+    PROF(kname("k_sym_reduce", tname<T>()),
+         sizeof(T) * ((int64_t)L.nT * L.nT * dev::kTile + L.n), s);
+    KLAUNCH((unsigned)L.nT * (dev::kTile / 16), dev::kBlock, 0, s, dev::k_sym_reduce<T>, L.n, L.nT,
+            (const T*)P.spart, x);
     LAUNCH_OK();
     return;
   }
@@ -854,6 +962,40 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
 }
 
 // z = B r (FP64 in and out), in the handle's precision.
+// Run fn (which launches a fixed sequence of kernels on a stream: one
+// V-cycle) on s.  With graphs on and no kernel timing active, the sequence is
+// recorded once per key as a chain of kernel nodes of a HIP graph (no stream
+// capture, so other threads' allocations and copies are unaffected) and
+// replayed on s.  The launches' arguments are device addresses that stay
+// fixed while the graph lives (batched graphs are dropped with the batched
+// buffers); only kernels are recorded, no memset or copy.
+template <typename F>
+void run_graph(lsamg_handle* h, int key, hipStream_t s, F&& fn) {
+  if (!h->use_graphs || prof_active()) {
+    fn(s);
+    return;
+  }
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    GraphRec rec;
+    HIP_OK(hipGraphCreate(&rec.g, 0));
+    struct Stop {
+      GraphRec* r;
+      ~Stop() {
+        g_rec = nullptr;
+        if (r->g) (void)hipGraphDestroy(r->g);
+      }
+    } stop{&rec};
+    g_rec = &rec;
+    fn(s);
+    g_rec = nullptr;
+    hipGraphExec_t ex = nullptr;
+    HIP_OK(hipGraphInstantiate(&ex, rec.g, nullptr, nullptr, 0));
+    it = h->graphs.emplace(key, ex).first;
+  }
+  HIP_OK(hipGraphLaunch(it->second, s));
+}
+
 void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
   DLevel& L0 = h->L[0];
   if (h->precision == LSAMG_MIXED) {
@@ -952,12 +1094,12 @@ void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   const unsigned g = h->red_np;
   const bool stage = !L0.coarsest;
   if (h->precision == LSAMG_MIXED) {
-    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, false);
+    run_graph(h, 128 + 1, s, [&](hipStream_t gs) { vcycle<float>(h, 0, L0.f.b, L0.f.x, gs, false); });
     PROF("k_cg_z<float>", 4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<float>, n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
                                                  L0.f.tb, h->r, h->z, h->p_rz[cur]);
   } else {
-    vcycle<double>(h, 0, h->r, L0.d.x, s, false);
+    run_graph(h, 1, s, [&](hipStream_t gs) { vcycle<double>(h, 0, h->r, L0.d.x, gs, false); });
     PROF("k_cg_z<double>", 8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<double>, n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
                                                   L0.d.tb, h->r, h->z, h->p_rz[cur]);
@@ -1059,7 +1201,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
 // ===========================================================================
 // Multi-right-hand-side path
 // ===========================================================================
-constexpr int kBNP = 256;      // workgroups (and partials per column) of the batched CG kernels
+constexpr int kBNP = 2048;     // workgroups (and partials per column) of the batched CG kernels
 constexpr int kBMax = 64;      // widest batch
 
 void ensure_batched(lsamg_handle* h, int NB) {
@@ -1071,6 +1213,9 @@ void ensure_batched(lsamg_handle* h, int NB) {
     lsamg_handle* h;
     ~Reset() { h->batch_alloc = false; }
   } reset{h};
+  for (auto& L : h->L)            // the batched kernels index rows with 32-bit wave-uniform values
+    if (L.n >= ((int64_t)1 << 31) || L.nrows >= ((int64_t)1 << 31))
+      throw DevError{LSAMG_EINVAL, "level too large for the multi-right-hand-side path"};
   h->bwidth = NB;
   const int kBMax = NB;            // buffers sized for this width
   h->BL.assign(h->L.size(), lsamg_handle::BLev{});
@@ -1102,11 +1247,16 @@ void ensure_batched(lsamg_handle* h, int NB) {
   h->Brz[0] = h->alloc<double>(kBNP * kBMax);
   h->Brz[1] = h->alloc<double>(kBNP * kBMax);
   h->Btmp = h->alloc<double>(kBNP * kBMax);
+  h->Bpq_s = h->alloc<double>(kBMax);
+  h->Brr_s = h->alloc<double>(kBMax);
+  h->Brz_s[0] = h->alloc<double>(kBMax);
+  h->Brz_s[1] = h->alloc<double>(kBMax);
+  h->Btmp_s = h->alloc<double>(kBMax);
   h->Bactive = h->alloc<int>(kBMax);
   if (!h->Bactive_host)
     HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 64 * sizeof(int), hipHostMallocDefault));
   if (!h->Bparts_host)
-    HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * kBNP * 64 * sizeof(double),
+    HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * 64 * sizeof(double),
                          hipHostMallocDefault));
   h->batched_ready = true;
 }
@@ -1122,23 +1272,188 @@ BVec<double> bvec<double>(lsamg_handle::BLev& B) { return {B.x, B.b, B.r, B.y, B
 template <>
 BVec<float> bvec<float>(lsamg_handle::BLev& B) { return {B.fx, B.fb, B.fr, B.fy, B.ftb}; }
 
+// Task list of k_bmm for RT row tiles per task and a loop split S (single-
+// aggregate operators only).  Tasks are ordered by loop length, longest
+// first, in power-of-two size buckets (aggregate order inside a bucket), so
+// the persistent launch starts the longest tasks first.  tmp: allocate with
+// hipMalloc (a tuning candidate, freed by mm_free) instead of the handle.
+GemvPlan::Mm mm_build(lsamg_handle* h, const GemvPlan& P, int RT, int S, bool tmp) {
+  struct Task {
+    int32_t a, j0, k0, k1, slot, bucket;
+  };
+  std::vector<Task> ts;
+  const int sn = P.nagg == 1 ? std::max(1, S) : 1;
+  int used_split = 1;
+  for (int64_t a = 0; a < P.nagg; ++a) {
+    const int nj = P.hlj[a], K = P.hll[a];
+    int kc = (K + sn - 1) / sn;
+    kc = std::max(8, (kc + 7) / 8 * 8);
+    const int ns = sn > 1 ? std::max(1, (K + kc - 1) / kc) : 1;
+    if (sn > 1) used_split = ns;
+    for (int j0 = 0; j0 < nj; j0 += 16 * RT)
+      for (int q = 0; q < ns; ++q) {
+        const int k0 = sn > 1 ? q * kc : 0, k1 = sn > 1 ? std::min(K, (q + 1) * kc) : K;
+        int b = 0;
+        while ((1 << b) < k1 - k0) ++b;
+        ts.push_back(Task{(int32_t)a, j0, k0, k1, ns > 1 ? q : -1, b});
+      }
+  }
+  std::stable_sort(ts.begin(), ts.end(),
+                   [](const Task& x, const Task& y) { return x.bucket > y.bucket; });
+  std::vector<int32_t> v[5];
+  for (auto& t : ts) {
+    v[0].push_back(t.a);
+    v[1].push_back(t.j0);
+    v[2].push_back(t.k0);
+    v[3].push_back(t.k1);
+    v[4].push_back(t.slot);
+  }
+  GemvPlan::Mm mm;
+  mm.rt = RT;
+  mm.split = used_split;
+  mm.ntask = (int64_t)ts.size();
+  // persistent launch: at most 8 workgroups of 4 wavefronts per compute unit
+  mm.grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((mm.ntask + 3) / 4, 256 * 8));
+  int32_t* d[5];
+  for (int c = 0; c < 5; ++c) {
+    if (tmp) {
+      HIP_OK(hipMalloc((void**)&d[c], std::max<size_t>(1, v[c].size()) * sizeof(int32_t)));
+      if (!v[c].empty())
+        HIP_OK(hipMemcpy(d[c], v[c].data(), v[c].size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    } else {
+      d[c] = h->upload(v[c]);
+    }
+  }
+  mm.tk = dev::MmTasks{d[0], d[1], d[2], d[3], d[4]};
+  return mm;
+}
+
+void mm_free(GemvPlan::Mm& mm) {
+  for (const int32_t* p : {mm.tk.a, mm.tk.j0, mm.tk.k0, mm.tk.k1, mm.tk.slot})
+    if (p) (void)hipFree((void*)p);
+  mm.tk = dev::MmTasks{};
+}
+
+template <int MODE, bool ADD, int NB>
+void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
+                const int64_t* cptr, const int64_t* cpos, const float* tb, const float* M,
+                const float* in, float* out, hipStream_t s, double bytes) {
+  const bool split = mm.split > 1;
+  {
+    PROF(kname("k_bmm", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
+                            std::to_string(mm.rt) + ", " + std::to_string(NB)),
+         split ? bytes - sizeof(float) * (double)P.out * NB : bytes, s);
+    auto launch = [&](auto kern) {
+      KLAUNCH(mm.grid, dev::kBlock, 0, s, kern, mm.tk, (int)mm.ntask, P.op, gidx, cptr, cpos, tb, M,
+              in, split ? mm.part : out, mm.part, (int64_t)P.out);
+    };
+    if (mm.rt == 1)
+      launch(dev::k_bmm<MODE, ADD, 1, NB>);
+    else if (mm.rt == 2)
+      launch(dev::k_bmm<MODE, ADD, 2, NB>);
+    else
+      launch(dev::k_bmm<MODE, ADD, 4, NB>);
+    LAUNCH_OK();
+  }
+  if (split) {
+    PROF(kname("k_bmm_reduce", std::string(ADD ? "true" : "false") + ", " + std::to_string(NB)),
+         sizeof(float) * (double)P.out * NB * (mm.split + (ADD ? 2 : 1)), s);
+    KLAUNCH(nblocks(P.out * NB), dev::kBlock, 0, s, dev::k_bmm_reduce<ADD, NB>, (int64_t)P.out,
+            mm.split, (const float*)mm.part, out);
+    LAUNCH_OK();
+  }
+}
+
 template <typename T, int MODE, bool ADD, int NB>
 void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const int64_t* cpos,
            const T* tb, const T* M, const T* in, T* out, hipStream_t s, int64_t tb_extra = 0) {
+  const double bytes = sizeof(T) * (P.mat + (P.in_u + P.out * (ADD ? 2 : 1)) * NB) + 4 * P.idx +
+                       32 * P.nagg + tb_extra * NB;
+  if constexpr (std::is_same<T, float>::value && NB >= 16) {
+    if (P.mm.rt > 0) {
+      bmm_launch<MODE, ADD, NB>(P, P.mm, gidx, cptr, cpos, tb, M, in, out, s, bytes);
+      return;
+    }
+  }
   PROF(kname("k_bgemm", std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
                             (ADD ? "true" : "false") + ", " + std::to_string(NB)),
-       sizeof(T) * (P.mat + (P.in_u + P.out * (ADD ? 2 : 1)) * NB) + 4 * P.idx + 32 * P.nagg +
-           tb_extra * NB,
-       s);
+       bytes, s);
   KLAUNCH((unsigned)P.ntask, dev::kBlock, 0, s, dev::k_bgemm<T, MODE, ADD, NB>, P.task_a,
           P.task_j0, P.op, gidx, cptr, cpos, tb, M, in, out);
   LAUNCH_OK();
+}
+
+// Autotuner of the matrix-core batched GEMM: every candidate tile shape (row
+// tiles per task, and the loop split of a single-aggregate operator) is timed
+// on the operator's own matrices and buffers (one warm-up and three timed
+// launches), and the fastest is kept.
+template <int MODE, bool ADD, int NB>
+void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
+             const int64_t* cpos, const float* tb, const float* M, const float* in, float* out,
+             float* part, int64_t part_cap, hipStream_t s) {
+  if (P.nagg == 0 || P.hlj.empty()) return;
+  const int ljmax = *std::max_element(P.hlj.begin(), P.hlj.end());
+  const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
+  std::vector<std::pair<int, int>> cand;
+  for (int rt : {1, 2, 4}) {
+    if (rt > 1 && 16 * (rt / 2) >= ljmax) continue;      // the tile would be mostly empty
+    for (int sp : {1, 2, 4, 8, 16}) {
+      if (sp > 1 && (P.nagg != 1 || llmax / sp < 256)) continue;
+      if ((int64_t)sp * P.out * NB > part_cap) continue;
+      cand.emplace_back(rt, sp);
+    }
+  }
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, int> pick{1, 1};
+  for (auto c : cand) {
+    GemvPlan::Mm mm = mm_build(h, P, c.first, c.second, true);
+    mm.part = part;
+    float ms = 0.f;
+    try {
+      bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
+      HIP_OK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r)
+        bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+    } catch (...) {
+      mm_free(mm);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    mm_free(mm);
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P.mm = mm_build(h, P, pick.first, pick.second, false);
+  P.mm.part = part;
 }
 
 template <typename T, int NB>
 void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
+  if (L.fuse_ata) {
+    PROF(kname("k_bata", std::string(tname<T>()) + ", " + std::to_string(NB)),
+         2 * L.nnz * (sizeof(T) + 4) + 8 * (L.n + L.nrows + 2) + sizeof(T) * 3 * L.n * NB, s);
+    if (L.ata_me == 8)
+      KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bata<T, NB, 8, 4>, L.n, L.gt_ptr,
+              L.gt_col, P.gt_val, L.g_ptr, L.g_col, P.g_val, X, B, R);
+    else
+      KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bata<T, NB, 16, 4>, L.n, L.gt_ptr,
+              L.gt_col, P.gt_val, L.g_ptr, L.g_col, P.g_val, X, B, R);
+    LAUNCH_OK();
+    return;
+  }
   {
     PROF(kname("k_bspmv", std::string(tname<T>()) + ", " + std::to_string(NB)),
          L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
@@ -1190,6 +1505,57 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
   }
 }
 
+// Choose the k_bmm tile shapes of every operator the FP32 multi-right-hand-
+// side V-cycle applies (once per allocation of the batched buffers).
+template <int NB>
+void mm_tune_all(lsamg_handle* h, hipStream_t s) {
+  if constexpr (NB >= 16) {
+    if (h->mm_tuned || h->dry) return;
+    struct Quiet {                       // tuning launches are not profiled
+      Profiler* p;
+      lsamg_handle* h;
+      ~Quiet() {
+        g_prof = p;
+        h->batch_alloc = false;
+      }
+    } quiet{g_prof, h};
+    g_prof = nullptr;
+    h->batch_alloc = true;               // task lists live with the batched buffers
+    int64_t cap = 0;
+    for (auto& L : h->L)
+      if (L.coarsest || L.tail) {
+        cap = std::max<int64_t>(cap, 16 * L.n * NB);
+        break;
+      }
+    float* part = cap > 0 ? h->alloc<float>((size_t)cap) : nullptr;
+    for (size_t l = 0; l < h->L.size(); ++l) {
+      DLevel& L = h->L[l];
+      auto& B = h->BL[l];
+      if (L.coarsest || L.tail) {
+        mm_tune<dev::IN_DIRECT, false, NB>(h, L.dense, nullptr, nullptr, nullptr, nullptr,
+                                           L.f.Ainv, B.fb, B.fx, part, cap, s);
+        break;
+      }
+      DLevel& C = h->L[l + 1];
+      auto& BC = h->BL[l + 1];
+      mm_tune<dev::IN_GATHER, false, NB>(h, L.ras, L.oidx, nullptr, nullptr, nullptr, L.f.Zc,
+                                         B.fb, B.fx, part, cap, s);
+      mm_tune<dev::IN_DIRECT, false, NB>(h, L.rst, nullptr, nullptr, nullptr, nullptr, L.f.Zh,
+                                         B.fr, BC.fb, part, cap, s);
+      if (C.coarsest || C.tail)
+        mm_tune<dev::IN_DIRECT, true, NB>(h, L.pro, nullptr, nullptr, nullptr, nullptr, L.f.ZhT,
+                                          BC.fx, B.fx, part, cap, s);
+      else
+        mm_tune<dev::IN_TB, true, NB>(h, L.pro, nullptr, C.cptr, C.cpos, BC.ftb, L.f.ZhT, BC.fx,
+                                      B.fx, part, cap, s);
+      mm_tune<dev::IN_DIRECT, false, NB>(h, L.rast, nullptr, nullptr, nullptr, nullptr, L.f.Zr,
+                                         B.fr, B.ftb, part, cap, s);
+    }
+    HIP_OK(hipStreamSynchronize(s));
+    h->mm_tuned = true;
+  }
+}
+
 // Dense tail: the V-cycle of levels >= lc is a fixed symmetric linear map
 // B_lc.  It is formed once, in FP64, by applying the multi-right-hand-side
 // V-cycle to the columns of the identity (64 at a time), symmetrized, and
@@ -1203,6 +1569,7 @@ void build_tail(lsamg_handle* h, size_t lc) {
   T.f.Ainv = h->alloc<float>((size_t)n * n);
   make_dense_plan(h, T);
   if (h->dry) {
+    make_packed(h, T, false);
     T.tail = true;
     return;
   }
@@ -1250,14 +1617,34 @@ void build_tail(lsamg_handle* h, size_t lc) {
            (const double*)T.d.Ainv, T.f.Ainv);
   LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
+  make_packed(h, T, true);
   T.tail = true;
 }
 
 template <int NB>
-void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, hipStream_t s) {
+void bsum(const double* part, double* out, hipStream_t s);
+
+template <int NB>
+void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, double* pq,
+               hipStream_t s) {
   DLevel& L = h->L[0];
   BVec<double> V = bvec<double>(h->BL[0]);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
+  if (L.fuse_ata) {
+    {
+      PROF(kname("k_bcg_apq1", std::to_string(NB)),
+           2 * L.nnz * 12 + 8 * (L.n + L.nrows + 2) + 8 * 3 * L.n * NB, s);
+      if (L.ata_me == 8)
+        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq1<NB, 8, 4>, L.n, L.gt_ptr, L.gt_col,
+                L.d.gt_val, L.g_ptr, L.g_col, L.d.g_val, Pv, Qv, pq_part);
+      else
+        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq1<NB, 16, 4>, L.n, L.gt_ptr, L.gt_col,
+                L.d.gt_val, L.g_ptr, L.g_col, L.d.g_val, Pv, Qv, pq_part);
+      LAUNCH_OK();
+    }
+    bsum<NB>(pq_part, pq, s);
+    return;
+  }
   {
     PROF(kname("k_bspmv", std::string("double, ") + std::to_string(NB)),
          L.nnz * 12 + 8 * (L.nrows + 1) + 8 * (L.n + L.nrows) * NB, s);
@@ -1270,6 +1657,7 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, h
   KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq<NB>, L.n, L.gt_ptr, L.gt_col, L.d.gt_val,
           (const double*)V.y, Pv, Qv, pq_part);
   LAUNCH_OK();
+  bsum<NB>(pq_part, pq, s);
 }
 
 template <int NB>
@@ -1279,39 +1667,44 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   auto& B0 = h->BL[0];
   const bool stage = !L0.coarsest;
   if (h->precision == LSAMG_MIXED) {
-    bvcycle<float, NB>(h, 0, B0.fb, B0.fx, s, false);
+    run_graph(h, 128 + NB, s,
+              [&](hipStream_t gs) { bvcycle<float, NB>(h, 0, B0.fb, B0.fx, gs, false); });
     PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), 20 * n * NB, s);
     KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
             stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
             h->Brz[cur]);
   } else {
-    bvcycle<double, NB>(h, 0, h->BR, B0.x, s, false);
+    run_graph(h, NB, s, [&](hipStream_t gs) { bvcycle<double, NB>(h, 0, h->BR, B0.x, gs, false); });
     PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), 24 * n * NB, s);
     KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
             stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
             h->BZ, h->Brz[cur]);
   }
   LAUNCH_OK();
+  bsum<NB>(h->Brz[cur], h->Brz_s[cur], s);
   PROF(kname("k_bcg_dir", std::to_string(NB)), 24 * n * NB, s);
-  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, (const double*)h->Brz[cur],
-          first ? (const double*)nullptr : (const double*)h->Brz[1 - cur], (const double*)h->BZ,
+  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, (const double*)h->Brz_s[cur],
+          first ? (const double*)nullptr : (const double*)h->Brz_s[1 - cur], (const double*)h->BZ,
           h->BP);
   LAUNCH_OK();
 }
 
-// per-column sums of kBNP x NB partials copied to pinned slot
-void bparts_to_host(lsamg_handle* h, const double* part, int NB, int slot, hipStream_t s) {
-  HIP_OK(hipMemcpyAsync(h->Bparts_host + (size_t)slot * kBNP * kBMax, part,
-                        (size_t)kBNP * NB * sizeof(double), hipMemcpyDeviceToHost, s));
+// per-column scalars out[j] = sum of the kBNP partials of column j
+template <int NB>
+void bsum(const double* part, double* out, hipStream_t s) {
+  PROF(kname("k_bsum", std::to_string(NB)), 8.0 * (kBNP + 1) * NB, s);
+  KLAUNCH(NB, dev::kBlock, 0, s, dev::k_bsum<NB>, kBNP, part, out);
+  LAUNCH_OK();
+}
+
+// NB per-column scalars copied to pinned slot
+void bparts_to_host(lsamg_handle* h, const double* scal, int NB, int slot, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(h->Bparts_host + (size_t)slot * 64, scal, (size_t)NB * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
 }
 
 void bhost_sums(const lsamg_handle* h, int NB, int slot, double* out) {
-  const double* p = h->Bparts_host + (size_t)slot * kBNP * kBMax;
-  for (int j = 0; j < NB; ++j) {
-    double t = 0;
-    for (int b = 0; b < kBNP; ++b) t += p[(size_t)b * NB + j];
-    out[j] = t;
-  }
+  for (int j = 0; j < NB; ++j) out[j] = h->Bparts_host[(size_t)slot * 64 + j];
 }
 
 // PCG on nr <= NB right-hand sides at once: one FP64 CG per column (own
@@ -1321,6 +1714,7 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
                 int maxit, hipStream_t s, lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
   ensure_batched(h, NB);
+  if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -1334,7 +1728,8 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
   KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BBi,
            (const double*)h->BBi, h->Btmp);
   LAUNCH_OK();
-  bparts_to_host(h, h->Btmp, NB, 0, s);
+  bsum<NB>(h->Btmp, h->Btmp_s, s);
+  bparts_to_host(h, h->Btmp_s, NB, 0, s);
   HIP_OK(hipStreamSynchronize(s));
   double nb2[kBMax], rr[kBMax], nbv[kBMax], rn[kBMax];
   int its_col[kBMax], conv_col[kBMax];
@@ -1363,16 +1758,17 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
     int cur = 0;
     bcg_precondition<NB>(h, s, true, cur);
     while (its < maxit && nactive > 0) {
-      bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, s);
+      bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, h->Bpq_s, s);
       {
         PROF(kname("k_bcg_update", std::to_string(NB)), (mixed ? 60 : 56) * n * NB, s);
-        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_update<NB>, n, (const double*)h->Brz[cur],
-                (const double*)h->Bpq, (const int*)h->Bactive, (const double*)h->BP,
+        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_update<NB>, n, (const double*)h->Brz_s[cur],
+                (const double*)h->Bpq_s, (const int*)h->Bactive, (const double*)h->BP,
                 (const double*)h->BQ, h->BX, h->BR, mixed ? B0.fb : (float*)nullptr, h->Brr);
         LAUNCH_OK();
       }
+      bsum<NB>(h->Brr, h->Brr_s, s);
       const int slot = 1 + (its & 1);
-      bparts_to_host(h, h->Brr, NB, slot, s);
+      bparts_to_host(h, h->Brr_s, NB, slot, s);
       HIP_OK(hipEventRecord(h->ev_rr[its & 1], s));
       ++its;
       // the most advanced active column predicts whether this update converges
@@ -1407,14 +1803,15 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
     }
   }
   // true residuals in FP64
-  bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, s);
+  bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
   KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_sub, n * NB, (const double*)h->BBi, (const double*)h->BQ,
            h->BZ);
   LAUNCH_OK();
   KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BZ,
            (const double*)h->BZ, h->Btmp);
   LAUNCH_OK();
-  bparts_to_host(h, h->Btmp, NB, 0, s);
+  bsum<NB>(h->Btmp, h->Btmp_s, s);
+  bparts_to_host(h, h->Btmp_s, NB, 0, s);
   KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
            (const double*)h->BX, x);
   LAUNCH_OK();
@@ -1435,6 +1832,42 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
     }
   }
   return all ? LSAMG_OK : LSAMG_ENOCONV;
+}
+
+// Y = B X for nr <= NB columns through the multi-right-hand-side V-cycle
+// (the preconditioner step of pcg_batched), user numbering in and out.
+template <int NB>
+void bapply_vcycle(lsamg_handle* h, const double* X, double* Y, int nr, int64_t ld,
+                   hipStream_t s) {
+  ensure_batched(h, NB);
+  if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
+  DLevel& L0 = h->L[0];
+  auto& B0 = h->BL[0];
+  const int64_t n = L0.n;
+  const unsigned ge = nblocks(n * NB);
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_in<NB>, n, nr, ld, (const int64_t*)h->perm, X,
+           h->BR);
+  LAUNCH_OK();
+  const bool stage = !L0.coarsest;
+  if (h->precision == LSAMG_MIXED) {
+    KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_convert<double, float>, n * NB, (const double*)h->BR,
+             B0.fb);
+    LAUNCH_OK();
+    bvcycle<float, NB>(h, 0, B0.fb, B0.fx, s, false);
+    KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
+             stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
+             h->Btmp);
+  } else {
+    bvcycle<double, NB>(h, 0, h->BR, B0.x, s, false);
+    KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
+             stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
+             h->BZ, h->Btmp);
+  }
+  LAUNCH_OK();
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
+           (const double*)h->BZ, Y);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
 }
 
 int solve_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
@@ -1599,6 +2032,49 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
   } catch (const DevError& e) {
     return fail_with(e.code, e.msg);
   }
+}
+
+int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_t nrhs,
+                             int64_t ld, void* stream) {
+  if (!h || !X || !Y || nrhs < 1 || nrhs > kBMax) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (h->device < 0 || h->L.empty()) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  if (ld < h->L[0].n) return fail_with(LSAMG_EINVAL, "ld < n");
+  try {
+    DeviceGuard g(h->device);
+    ProfGuard pg(&h->prof);
+    hipStream_t s = (hipStream_t)stream;
+    if (nrhs <= 8)
+      bapply_vcycle<8>(h, X, Y, nrhs, ld, s);
+    else if (nrhs <= 16)
+      bapply_vcycle<16>(h, X, Y, nrhs, ld, s);
+    else if (nrhs <= 32)
+      bapply_vcycle<32>(h, X, Y, nrhs, ld, s);
+    else
+      bapply_vcycle<64>(h, X, Y, nrhs, ld, s);
+    return LSAMG_OK;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
+  if (!h || (value != 0 && value != 1)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (opt == LSAMG_OPT_BATCHED) {
+    h->batch_mode = (int)value;
+  } else if (opt == LSAMG_OPT_MFMA) {
+    h->use_mfma = value != 0;
+    if (!h->use_mfma) {                 // back to k_bgemm; task lists stay until the buffers go
+      for (auto& D : h->L)
+        for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      h->mm_tuned = false;
+    }
+    h->drop_graphs(true);               // captured batched V-cycles name the old kernels
+  } else if (opt == LSAMG_OPT_GRAPH) {
+    h->use_graphs = value != 0;
+  } else {
+    return fail_with(LSAMG_EINVAL, "unknown option");
+  }
+  return LSAMG_OK;
 }
 
 int lsamg_profile(lsamg_handle* h, int32_t mode, const char* only) {

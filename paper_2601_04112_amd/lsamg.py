@@ -20,6 +20,7 @@ LSAMG_OK, LSAMG_EINVAL, LSAMG_EBADINPUT, LSAMG_ENOTSPD = 0, -1, -2, -3
 LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
 FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
+OPT_BATCHED, OPT_MFMA, OPT_GRAPH = 0, 1, 2
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
                -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
@@ -128,6 +129,9 @@ _SIGS = {
     "lsamg_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "lsamg_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
+    "lsamg_set_option": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
+    "lsamg_apply_vcycle_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_int32, C.c_int64, C.c_void_p]),
     "lsamg_profile": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
     "lsamg_profile_read": (C.c_int, [C.c_void_p, C.POINTER(KProf), C.c_int32,
                                      C.POINTER(C.c_int32)]),
@@ -282,8 +286,25 @@ class Solver:
                                      self._stream(stream)))
         return y
 
+    def apply_vcycle_batch(self, X, out=None, stream=None):
+        """Y = B X for the rows of X (shape (nrhs, n), nrhs <= 64) through
+        the multi-right-hand-side V-cycle."""
+        import torch
+        X = self._dev_vec(X)
+        if X.dim() != 2 or X.shape[1] != self.n:
+            raise ValueError("expected shape (nrhs, n)")
+        Y = torch.empty_like(X) if out is None else self._dev_vec(out)
+        _check(load().lsamg_apply_vcycle_batch(
+            self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()),
+            X.shape[0], self.n, self._stream(stream)))
+        return Y
+
     def set_precision(self, precision: int):
         _check(load().lsamg_set_precision(self._h, precision))
+
+    def set_option(self, opt: int, value: int):
+        """OPT_BATCHED, OPT_MFMA or OPT_GRAPH, value 0 or 1."""
+        _check(load().lsamg_set_option(self._h, opt, int(value)))
 
     # -- kernel timing ----------------------------------------------------
     def profile(self, on: bool = True, only: Optional[str] = None,

@@ -120,20 +120,21 @@ def rotation_from_seed(seed: int, rng: np.random.Generator | None = None):
 
 
 def ls3d(N: int, eps_perp: float = 1e-3, d1: float = 1e-6,
-         seed: int = 2) -> Problem:
+         seed: int = 2, sigma: float = 1.0) -> Problem:
     """3D ``D1 + B^T D2^{-1} B`` with ``D2^{-1} = a_c Q diag(1,e,e) Q^T``.
 
     ``G = [sqrt(d1) I ; sqrt(a_c) K^{1/2} grad+]``: the ``n`` rows of
     ``sqrt(D1)`` come first, then three rows per cell.  The rotation ``Q``
-    and the per-cell lognormal(0, 1) coefficients are drawn, in that order,
-    from ``numpy.random.default_rng(seed)``; cells are x-fastest.
+    and the per-cell lognormal(0, sigma) coefficients (sigma = 1 in the
+    workload) are drawn, in that order, from
+    ``numpy.random.default_rng(seed)``; cells are x-fastest.
     """
     h = 1.0 / N
     rng = np.random.default_rng(seed)
     Q = rotation_from_seed(seed, rng)
     Kh = Q @ np.diag([1.0, math.sqrt(eps_perp), math.sqrt(eps_perp)]) @ Q.T
     ncell = N ** 3
-    acoef = rng.lognormal(0.0, 1.0, ncell)
+    acoef = rng.lognormal(0.0, sigma, ncell)
     sa = np.sqrt(acoef)
     ci, cj, ck = np.meshgrid(np.arange(N), np.arange(N), np.arange(N),
                              indexing="ij")

@@ -234,6 +234,59 @@ def test_batched_mixed(which, request):
         assert st[j]["iters"] <= math.ceil(1.10 * info["iters"]) + 1
 
 
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+@pytest.mark.parametrize("nrhs", [64, 20, 16, 5])
+def test_batched_vcycle_matches_single(which, nrhs, request):
+    """One multi-right-hand-side V-cycle equals the single-vector V-cycle on
+    every column: to 1e-12 in FP64; in FP32 (matrix-core tiles for >= 16
+    columns, FMA kernels otherwise or with the matrix cores switched off) to
+    2e-5, the spread of two FP32 summation orders over the levels."""
+    p, H, s = request.getfixturevalue(which)
+    X = np.stack([P.rhs_uniform(p.n, 300 + j) for j in range(nrhs)])
+    dX = dvec(X)
+    try:
+        for prec, mfma, tol in ((L.FP64, 1, 1e-12), (L.MIXED, 1, 2e-5), (L.MIXED, 0, 2e-5)):
+            s.set_precision(prec)
+            s.set_option(L.OPT_MFMA, mfma)
+            Y = host(s.apply_vcycle_batch(dX))
+            for j in range(nrhs):
+                y1 = host(s.apply(L.OP_VCYCLE, dX[j]))
+                assert rel(Y[j], y1) <= tol, (prec, mfma, j, rel(Y[j], y1))
+    finally:
+        s.set_precision(L.FP64)
+        s.set_option(L.OPT_MFMA, 1)
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_graph_replay_equals_eager(rot_tail, prec):
+    """Solves whose V-cycles replay a captured HIP graph are bit-identical to
+    solves with the kernels launched one by one, on every replay, with eager
+    work and synchronisations between the replays; single and batched (the
+    batched FP32 V-cycle on matrix-core tiles)."""
+    import torch
+    p, H, s = rot_tail
+    b = dvec(P.rhs_uniform(p.n, 7))
+    B = dvec(np.stack([P.rhs_uniform(p.n, 400 + j) for j in range(16)]))
+    s.set_precision(prec)
+    try:
+        s.set_option(L.OPT_GRAPH, 0)
+        x_e, st_e = s.solve(b, tol=1e-8)
+        X_e, St_e = s.solve(B, tol=1e-8)
+        s.set_option(L.OPT_GRAPH, 1)
+        for rep in range(3):
+            x_g, st_g = s.solve(b, tol=1e-8)
+            X_g, St_g = s.solve(B, tol=1e-8)
+            assert st_g[0]["iters"] == st_e[0]["iters"]
+            assert np.array_equal(host(x_g), host(x_e)), rep
+            assert [t["iters"] for t in St_g] == [t["iters"] for t in St_e]
+            assert np.array_equal(host(X_g), host(X_e)), rep
+            s.apply(L.OP_A, b)                  # eager work between replays
+            torch.cuda.synchronize()
+    finally:
+        s.set_option(L.OPT_GRAPH, 1)
+        s.set_precision(L.FP64)
+
+
 def test_batched_edge_columns(cfg1):
     """A zero column converges at once without disturbing the others; a
     single-level hierarchy works in the batched path."""
