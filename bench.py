@@ -52,6 +52,36 @@ print(json.dumps(dict(t_setup=t_setup, t_sample=t, iters={iters})))
     return [sys.executable, "-c", code]
 
 
+KERNEL_SOURCES = ("paper_2601_04112_amd/csrc/kernels.hpp",
+                  "paper_2601_04112_amd/csrc/kernels_batched.hpp")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (profiles/*_traffic.md: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+    the counters' reading for a plain streaming kernel of known size), or
+    None when no summary covers this kernel or the kernel sources changed
+    since the counters were taken."""
+    import glob
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
+        txt = open(f).read()
+        if "```json" not in txt:
+            continue
+        rec = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        if rec.get("kernel") == kernel and rec.get("source_sha256") == kernel_source_hash():
+            return rec["traffic_bytes_per_launch"]
+    return None
+
+
 def percentile(v, q):
     v = sorted(v)
     if not v:
@@ -328,7 +358,7 @@ def main():
         achieved = bytes_per_launch / avg_s / 1e9
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
                         unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                        traffic=None, kernel=dominant,
+                        traffic=measured_traffic(dominant), kernel=dominant,
                         avg_launch_us=round(avg_s * 1e6, 3),
                         algorithmic_bytes_per_launch=int(bytes_per_launch),
                         launches=dom["launches"],

@@ -15,6 +15,18 @@ namespace dev {
 
 constexpr int kBlock = 256;
 
+// XCD-aware block order.  The command processor deals consecutive workgroups
+// of a launch to the 8 XCDs in turn, and each XCD has its own L2; this
+// bijection of [0, nb) gives XCD x = b % 8 the contiguous range of logical
+// blocks [x*q + min(x, r), ...) (q = nb / 8, r = nb % 8), so workgroups that
+// touch neighbouring rows (and gather the same vector entries) share an L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) {
+  constexpr int64_t X = 8;
+  const int64_t q = nb / X, r = nb % X;
+  const int64_t x = b % X, k = b / X;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v, int width) {
   for (int o = width >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, width);
@@ -164,35 +176,48 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
                                                         T* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
   constexpr int S = 64 / G;
+  constexpr int U = 8;                       // independent loads in flight per lane
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + wave;
   const bool valid = a < nagg;
   T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * lmax;
+  const int s = lane / G, j = lane % G;
   int nj = 0, nl = 0;
+  const T* m = M;
+  T mv[U];
   if (valid) {
     nj = op.lj[a];
     nl = op.ll[a];
+    m = M + op.moff[a] + (j < nj ? j : 0);
+    // the first U matrix entries of the lane do not depend on the staged
+    // input: their loads are issued before the staging gather and barrier
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = s + u * S;
+      mv[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
+    }
     const int64_t ib = op.ibase[a];
     for (int l = lane; l < nl; l += 64) sv[l] = load_in<T, MODE>(in, ib + l, spec);
   }
   __syncthreads();
   if (!valid) return;
-  const int s = lane / G, j = lane % G;
   T acc = 0;
   if (j < nj) {
-    const T* m = M + op.moff[a] + j;
-    T a1 = 0, a2 = 0, a3 = 0;
-    int l = s;
-    for (; l + 3 * S < nl; l += 4 * S) {   // four independent loads in flight
-      const T m0 = m[(int64_t)l * nj], m1 = m[(int64_t)(l + S) * nj];
-      const T m2 = m[(int64_t)(l + 2 * S) * nj], m3 = m[(int64_t)(l + 3 * S) * nj];
-      acc += m0 * sv[l];
-      a1 += m1 * sv[l + S];
-      a2 += m2 * sv[l + 2 * S];
-      a3 += m3 * sv[l + 3 * S];
+    T av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = s + u * S;
+      av[u] = l < nl ? mv[u] * sv[l] : T(0);
     }
-    for (; l < nl; l += S) acc += m[(int64_t)l * nj] * sv[l];
-    acc = (acc + a1) + (a2 + a3);
+    int l = s + U * S;
+    for (; l + (U - 1) * S < nl; l += U * S) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * S) * nj];
+#pragma unroll
+      for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * S];
+    }
+    for (; l < nl; l += S) av[0] += m[(int64_t)l * nj] * sv[l];
+    acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
   }
   for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
   if (s == 0 && j < nj) {
@@ -219,19 +244,30 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
   const int j0 = task_j0[blockIdx.x];
   const int nj = op.lj[a], nl = op.ll[a];
   const int64_t ib = op.ibase[a];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = j0 + lane;
+  constexpr int U = 8;                      // independent loads in flight per lane
+  const T* m = M + op.moff[a] + (j < nj ? j : 0);
+  // the first U matrix entries of the lane do not depend on the staged input:
+  // their loads are issued before the staging gather and barrier
+  T mv0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int l = wave + u * NW;
+    mv0[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
+  }
   for (int l = threadIdx.x; l < nl; l += NW * 64)
     sv[l] = load_in<T, MODE>(in, ib + l, spec);
   __syncthreads();
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int j = j0 + lane;
   T acc = 0;
   if (j < nj) {
-    const T* m = M + op.moff[a] + j;
-    constexpr int U = 8;                    // independent loads in flight per lane
     T av[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) av[u] = 0;
-    int l = wave;
+    for (int u = 0; u < U; ++u) {
+      const int l = wave + u * NW;
+      av[u] = l < nl ? mv0[u] * sv[l] : T(0);
+    }
+    int l = wave + U * NW;
     for (; l + (U - 1) * NW < nl; l += U * NW) {
       T mv[U];
 #pragma unroll

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(kBlock) k_bspmv(int64_t nrows, const int64_t* 
                                                   const int32_t* __restrict__ col,
                                                   const T* __restrict__ val,
                                                   const T* __restrict__ X, T* __restrict__ Y) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t row = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (row >= nrows) return;
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(kBlock) k_bresid_t(int64_t n, const int64_t* _
                                                      const T* __restrict__ Y,
                                                      const T* __restrict__ B,
                                                      T* __restrict__ R) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t d = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (d >= n) return;
@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(kBlock) k_bata(int64_t n, const int64_t* __res
                                                  const T* __restrict__ g_val,
                                                  const T* __restrict__ X, const T* __restrict__ B,
                                                  T* __restrict__ R) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t d = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (d >= n) return;
@@ -228,7 +228,8 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
 //
 // One wavefront runs one task at a time: aggregate a, output rows
 // [j0, j0 + 16*RT) (RT row tiles), loop indices [k0, k1), all NB columns
-// (CT = NB/16 column tiles).  The launch is persistent: its waves stride over
+// (CT = NB/16 column tiles); the loads of U loop steps are issued before
+// their matrix operations.  The launch is persistent: its waves stride over
 // the task list, which the host orders longest-first (size buckets), so one
 // launch covers every aggregate of a level.
 //
@@ -282,7 +283,7 @@ __device__ __forceinline__ void vstore(float* __restrict__ p, const float (&v)[C
   }
 }
 
-template <int MODE, bool ADD, int RT, int NB>
+template <int MODE, bool ADD, int RT, int U, int NB>
 __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op,
                                                 const int32_t* __restrict__ gidx,
                                                 const int64_t* __restrict__ cptr,
@@ -294,7 +295,6 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
                                                 float* __restrict__ part, int64_t part_rows) {
   static_assert(NB % 16 == 0 && NB <= 64, "column tiles of 16");
   constexpr int CT = NB / 16;
-  constexpr int U = 2;                       // loop steps whose loads are issued together
   constexpr int WPB = kBlock / 64;
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, g = lane >> 4;
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t
                                                         const int64_t* __restrict__ cpos,
                                                         const T* __restrict__ tb,
                                                         T* __restrict__ X) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t d = wave_row<NB>(gid / NB);
   const int c = (int)(gid % NB);
   if (d >= n) return;
@@ -460,7 +460,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq(int64_t n, const int64_t* __
                                                     double* __restrict__ part) {
   const int j = threadIdx.x % NB;
   double v = 0;
-  for (int64_t d = wave_row<NB>(((int64_t)blockIdx.x * kBlock + threadIdx.x) / NB); d < n;
+  for (int64_t d = wave_row<NB>((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / NB); d < n;
        d += (int64_t)gridDim.x * (kBlock / NB)) {
     double s = 0;
     for (int64_t e = ptr[d]; e < ptr[d + 1]; ++e) s += val[e] * Y[(int64_t)col[e] * NB + j];
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* _
                                                      double* __restrict__ part) {
   const int j = threadIdx.x % NB;
   double v = 0;
-  for (int64_t d = wave_row<NB>(((int64_t)blockIdx.x * kBlock + threadIdx.x) / NB); d < n;
+  for (int64_t d = wave_row<NB>((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / NB); d < n;
        d += (int64_t)gridDim.x * (kBlock / NB)) {
     const double acc =
         ata_row<double, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, P, j);

@@ -89,6 +89,7 @@ struct GemvPlan {
   // tile shape of k_bmm chosen by the autotuner, and its task list
   struct Mm {
     int rt = 0;              // row tiles of 16 per task (0: not tuned, use k_bgemm)
+    int u = 2;               // loop steps whose loads are issued together (2 or 8)
     int split = 1;           // loop split of a single-aggregate operator
     int64_t ntask = 0;
     unsigned grid = 0;       // workgroups of the persistent launch
@@ -1341,18 +1342,28 @@ void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
   const bool split = mm.split > 1;
   {
     PROF(kname("k_bmm", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
-                            std::to_string(mm.rt) + ", " + std::to_string(NB)),
+                            std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
+                            std::to_string(NB)),
          split ? bytes - sizeof(float) * (double)P.out * NB : bytes, s);
     auto launch = [&](auto kern) {
       KLAUNCH(mm.grid, dev::kBlock, 0, s, kern, mm.tk, (int)mm.ntask, P.op, gidx, cptr, cpos, tb, M,
               in, split ? mm.part : out, mm.part, (int64_t)P.out);
     };
-    if (mm.rt == 1)
-      launch(dev::k_bmm<MODE, ADD, 1, NB>);
-    else if (mm.rt == 2)
-      launch(dev::k_bmm<MODE, ADD, 2, NB>);
-    else
-      launch(dev::k_bmm<MODE, ADD, 4, NB>);
+    if (mm.u == 2) {
+      if (mm.rt == 1)
+        launch(dev::k_bmm<MODE, ADD, 1, 2, NB>);
+      else if (mm.rt == 2)
+        launch(dev::k_bmm<MODE, ADD, 2, 2, NB>);
+      else
+        launch(dev::k_bmm<MODE, ADD, 4, 2, NB>);
+    } else {
+      if (mm.rt == 1)
+        launch(dev::k_bmm<MODE, ADD, 1, 8, NB>);
+      else if (mm.rt == 2)
+        launch(dev::k_bmm<MODE, ADD, 2, 8, NB>);
+      else
+        launch(dev::k_bmm<MODE, ADD, 4, 8, NB>);
+    }
     LAUNCH_OK();
   }
   if (split) {
@@ -1394,22 +1405,29 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
   if (P.nagg == 0 || P.hlj.empty()) return;
   const int ljmax = *std::max_element(P.hlj.begin(), P.hlj.end());
   const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
-  std::vector<std::pair<int, int>> cand;
+  struct Cand {
+    int rt, u, sp;
+  };
+  std::vector<Cand> cand;
   for (int rt : {1, 2, 4}) {
     if (rt > 1 && 16 * (rt / 2) >= ljmax) continue;      // the tile would be mostly empty
-    for (int sp : {1, 2, 4, 8, 16}) {
-      if (sp > 1 && (P.nagg != 1 || llmax / sp < 256)) continue;
-      if ((int64_t)sp * P.out * NB > part_cap) continue;
-      cand.emplace_back(rt, sp);
+    for (int u : {2, 8}) {
+      if (u == 8 && llmax <= 8) continue;                 // one step covers the loop
+      for (int sp : {1, 2, 4, 8, 16}) {
+        if (sp > 1 && (P.nagg != 1 || llmax / sp < 256)) continue;
+        if ((int64_t)sp * P.out * NB > part_cap) continue;
+        cand.push_back(Cand{rt, u, sp});
+      }
     }
   }
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   float best = 1e30f;
-  std::pair<int, int> pick{1, 1};
+  Cand pick{1, 2, 1};
   for (auto c : cand) {
-    GemvPlan::Mm mm = mm_build(h, P, c.first, c.second, true);
+    GemvPlan::Mm mm = mm_build(h, P, c.rt, c.sp, true);
+    mm.u = c.u;
     mm.part = part;
     float ms = 0.f;
     try {
@@ -1434,7 +1452,8 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  P.mm = mm_build(h, P, pick.first, pick.second, false);
+  P.mm = mm_build(h, P, pick.rt, pick.sp, false);
+  P.mm.u = pick.u;
   P.mm.part = part;
 }
 
