@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(int64_t nrows, const int64_t* _
                                                  const T* __restrict__ x, T* __restrict__ y) {
   // each group of LANES threads owns two rows, processed together so that
   // their loads overlap
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t r0 = (gid / LANES) * 2;
   const int lane = (int)(gid % LANES);
   if (r0 >= nrows) return;  // LANES divides the block, so whole groups exit
@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_t(int64_t n, const int64_t* __
                                                     const T* __restrict__ val,
                                                     const T* __restrict__ y,
                                                     const T* __restrict__ b, T* __restrict__ r) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t r0 = (gid / LANES) * 2;
   const int lane = (int)(gid % LANES);
   if (r0 >= n) return;
@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
   constexpr int S = 64 / G;
   constexpr int U = 8;                       // independent loads in flight per lane
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t a = (int64_t)blockIdx.x * (kBlock / 64) + wave;
+  const int64_t a = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
   const bool valid = a < nagg;
   T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * lmax;
   const int s = lane / G, j = lane % G;
@@ -240,8 +240,9 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
   extern __shared__ unsigned char smem_raw[];
   T* sv = reinterpret_cast<T*>(smem_raw);
   T* part = sv + lmax;
-  const int64_t a = task_a[blockIdx.x];
-  const int j0 = task_j0[blockIdx.x];
+  const int64_t task = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t a = task_a[task];
+  const int j0 = task_j0[task];
   const int nj = op.lj[a], nl = op.ll[a];
   const int64_t ib = op.ibase[a];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -332,7 +333,7 @@ __global__ void __launch_bounds__(kBlock) k_grp_ata(int64_t ntask, GrpTasks tk,
                                                     const int32_t* __restrict__ supp,
                                                     const T* __restrict__ x,
                                                     T* __restrict__ stg) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t task = gid / LW;
   const int lane = (int)(gid % LW);
   if (task >= ntask) return;    // LW divides the wavefront: whole lane groups exit
@@ -401,7 +402,7 @@ __global__ void __launch_bounds__(NW * 64) k_grp_ata_wg(GrpTasks tk, const T* __
                                                         T* __restrict__ stg) {
   extern __shared__ unsigned char smem_raw[];
   T* red = reinterpret_cast<T*>(smem_raw);     // NW*KC*64
-  const int64_t task = blockIdx.x;
+  const int64_t task = xcd_block(blockIdx.x, gridDim.x);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nr = tk.nrow[task], t0 = tk.t0[task], c = tk.c[task];
   const int w = c - t0;
@@ -469,7 +470,7 @@ __global__ void __launch_bounds__(kBlock) k_resid_stg(int64_t n, const int64_t* 
                                                       const T* __restrict__ stg,
                                                       const T* __restrict__ b,
                                                       T* __restrict__ r) {
-  const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
   const int64_t i = gid >> 3;
   const int lane = (int)(gid & 7);
   if (i >= n) return;          // whole groups of 8 lanes exit together

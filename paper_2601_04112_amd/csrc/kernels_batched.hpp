@@ -26,6 +26,67 @@ __device__ __forceinline__ int64_t wave_row(int64_t r) {
     return r;
 }
 
+// Value of v held by lane L (L wave-uniform): a scalar register.
+__device__ __forceinline__ int32_t lane_val(int32_t v, int L) {
+  return __builtin_amdgcn_readlane(v, L);
+}
+__device__ __forceinline__ float lane_val(float v, int L) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), L));
+}
+__device__ __forceinline__ double lane_val(double v, int L) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), L);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), L);
+  return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum of the staged values tb[pos[e]][lane] for e in [e0, e1) (NB = 64, e0
+// and e1 wave-uniform), in e order: lane k loads pos[e0 + k], and the
+// wavefront walks the positions, each broadcast from its lane.
+template <typename T>
+__device__ __forceinline__ T staged_sum64(int64_t e0, int64_t e1, const int64_t* __restrict__ pos,
+                                          const T* __restrict__ tb, int lane) {
+  T s = 0;
+  for (int64_t b = e0; b < e1; b += 64) {
+    const int cnt = (int)(e1 - b < 64 ? e1 - b : 64);
+    const int64_t p = pos[b + (lane < cnt ? lane : cnt - 1)];
+    const int plo = (int)(p & 0xffffffff), phi = (int)(p >> 32);
+    for (int L = 0; L < cnt; ++L) {
+      const int64_t q = ((int64_t)__builtin_amdgcn_readlane(phi, L) << 32) |
+                        (uint32_t)__builtin_amdgcn_readlane(plo, L);
+      s += tb[q * 64 + lane];
+    }
+  }
+  return s;
+}
+
+// NB = 64, one row per wavefront (e0, e1 wave-uniform): the lanes load 64
+// entries of the row (indices and values) with one vector load each, and the
+// wavefront then walks them, each entry's index and value broadcast from its
+// lane, gathering one 64-wide row of X per entry.
+template <typename T>
+__device__ __forceinline__ T row_dot64(int64_t e0, int64_t e1, const int32_t* __restrict__ col,
+                                       const T* __restrict__ val, const T* __restrict__ X,
+                                       int lane) {
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int64_t b = e0; b < e1; b += 64) {
+    const int cnt = (int)(e1 - b < 64 ? e1 - b : 64);
+    const int64_t f = b + (lane < cnt ? lane : cnt - 1);
+    const int32_t c = col[f];
+    const T v = val[f];
+    int L = 0;
+    for (; L + 4 <= cnt; L += 4) {
+      T x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)lane_val(c, L + u) * 64 + lane];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += lane_val(v, L + u) * x[u];
+    }
+    for (; L < cnt; ++L) acc[0] += lane_val(v, L) * X[(int64_t)lane_val(c, L) * 64 + lane];
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
+
 // sum over e in [e0, e1) of val[e] * X[col[e]][j]: eight entries at a time,
 // all their indices and values loaded before the gathers are issued, so a
 // wavefront keeps eight gathers in flight
@@ -50,11 +111,14 @@ __device__ __forceinline__ T row_dot(int64_t e0, int64_t e1, const int32_t* __re
 #pragma unroll
     for (int u = 0; u < U; ++u) acc[u] += v[u] * x[u];
   }
-  for (int u = 0; u < U - 1; ++u) {        // remainder: at most U - 1 entries
-    const bool ok = e + u < e1;
-    const int32_t c = ok ? col[e + u] : 0;
-    const T v = ok ? val[e + u] : T(0);
-    acc[u] += v * X[(int64_t)c * NB + j];
+  if (e < e1) {                             // remainder: 1 .. U-1 entries, loads clamped
+#pragma unroll
+    for (int u = 0; u < U - 1; ++u) {
+      const int64_t f = e + u < e1 ? e + u : e1 - 1;
+      const int32_t c = col[f];
+      const T v = val[f];
+      acc[u] += (e + u < e1 ? v : T(0)) * X[(int64_t)c * NB + j];
+    }
   }
   return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
 }
@@ -69,7 +133,10 @@ __global__ void __launch_bounds__(kBlock) k_bspmv(int64_t nrows, const int64_t* 
   const int64_t row = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (row >= nrows) return;
-  Y[row * NB + j] = row_dot<T, NB>(ptr[row], ptr[row + 1], col, val, X, j);
+  if constexpr (NB == 64)
+    Y[row * NB + j] = row_dot64<T>(ptr[row], ptr[row + 1], col, val, X, j);
+  else
+    Y[row * NB + j] = row_dot<T, NB>(ptr[row], ptr[row + 1], col, val, X, j);
 }
 
 // R = B - G^T Y (B == nullptr: R = G^T Y)
@@ -84,7 +151,11 @@ __global__ void __launch_bounds__(kBlock) k_bresid_t(int64_t n, const int64_t* _
   const int64_t d = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (d >= n) return;
-  const T s = row_dot<T, NB>(ptr[d], ptr[d + 1], col, val, Y, j);
+  T s;
+  if constexpr (NB == 64)
+    s = row_dot64<T>(ptr[d], ptr[d + 1], col, val, Y, j);
+  else
+    s = row_dot<T, NB>(ptr[d], ptr[d + 1], col, val, Y, j);
   R[d * NB + j] = B ? B[d * NB + j] - s : s;
 }
 
@@ -102,6 +173,9 @@ __device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_p
                                      const int64_t* __restrict__ g_ptr,
                                      const int32_t* __restrict__ g_col,
                                      const T* __restrict__ g_val, const T* __restrict__ X, int j) {
+  // every load is unconditional, from an index clamped into the row (rows
+  // and columns of G are never empty), and masked afterwards: no branch
+  // separates the loads of one level, so they are issued together
   const int64_t e0 = gt_ptr[d];
   const int ne = (int)(gt_ptr[d + 1] - e0);
   int64_t r[ME], f0[ME];
@@ -109,14 +183,15 @@ __device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_p
   T w[ME];
 #pragma unroll
   for (int k = 0; k < ME; ++k) {
-    const bool ok = k < ne;
-    r[k] = ok ? (int64_t)gt_col[e0 + k] : 0;
-    w[k] = ok ? gt_val[e0 + k] : T(0);
+    const int64_t e = e0 + (k < ne ? k : ne - 1);
+    r[k] = gt_col[e];
+    const T wv = gt_val[e];
+    w[k] = k < ne ? wv : T(0);
   }
 #pragma unroll
   for (int k = 0; k < ME; ++k) {
     f0[k] = g_ptr[r[k]];
-    nf[k] = k < ne ? (int)(g_ptr[r[k] + 1] - f0[k]) : 0;
+    nf[k] = (int)(g_ptr[r[k] + 1] - f0[k]);
   }
   int32_t c[ME][MF];
   T v[ME][MF];
@@ -124,9 +199,10 @@ __device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_p
   for (int k = 0; k < ME; ++k)
 #pragma unroll
     for (int q = 0; q < MF; ++q) {
-      const bool ok = q < nf[k];
-      c[k][q] = ok ? g_col[f0[k] + q] : 0;
-      v[k][q] = ok ? g_val[f0[k] + q] : T(0);
+      const int64_t f = f0[k] + (q < nf[k] ? q : nf[k] - 1);
+      c[k][q] = g_col[f];
+      const T vv = g_val[f];
+      v[k][q] = q < nf[k] ? vv : T(0);
     }
   T acc = 0;
 #pragma unroll
@@ -135,6 +211,48 @@ __device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_p
 #pragma unroll
     for (int q = 0; q < MF; ++q) y += v[k][q] * X[(int64_t)c[k][q] * NB + j];
     acc += w[k] * y;
+  }
+  return acc;
+}
+
+// NB = 64 form of ata_row (d wave-uniform): lane k loads G^T entry k and
+// the row pointers of its row r_k; lane k*MF + q loads entry q of row r_k;
+// the wavefront then walks the ME*MF entries, each index and value broadcast
+// from its lane, gathering X rows: three vector loads of indices in sequence
+// instead of a chain of scalar loads per row.
+template <typename T, int ME, int MF>
+__device__ __forceinline__ T ata_row64(int64_t d, const int64_t* __restrict__ gt_ptr,
+                                       const int32_t* __restrict__ gt_col,
+                                       const T* __restrict__ gt_val,
+                                       const int64_t* __restrict__ g_ptr,
+                                       const int32_t* __restrict__ g_col,
+                                       const T* __restrict__ g_val, const T* __restrict__ X,
+                                       int lane) {
+  static_assert(ME * MF <= 64, "one entry per lane");
+  const int64_t e0 = gt_ptr[d];
+  const int ne = (int)(gt_ptr[d + 1] - e0);
+  const int k1 = lane < ne ? lane : ne - 1;                 // columns of G are never empty
+  const int32_t r = gt_col[e0 + k1];
+  const T wv = gt_val[e0 + k1];
+  const T w = lane < ne ? wv : T(0);
+  const int64_t f0 = g_ptr[r];
+  const int nf = (int)(g_ptr[(int64_t)r + 1] - f0);          // rows of G are never empty
+  const int k3 = lane / MF, q3 = lane % MF;
+  const int64_t f0k = __shfl(f0, k3);
+  const int nfk = __shfl(nf, k3);
+  const int32_t c = g_col[f0k + (q3 < nfk ? q3 : nfk - 1)];
+  const T vv = g_val[f0k + (q3 < nfk ? q3 : nfk - 1)];
+  const T v = (q3 < nfk && k3 < ne) ? vv : T(0);
+  T acc = 0;
+#pragma unroll
+  for (int k = 0; k < ME; ++k) {
+    T x[MF];
+#pragma unroll
+    for (int q = 0; q < MF; ++q) x[q] = X[(int64_t)lane_val(c, k * MF + q) * 64 + lane];
+    T y = 0;
+#pragma unroll
+    for (int q = 0; q < MF; ++q) y += lane_val(v, k * MF + q) * x[q];
+    acc += lane_val(w, k) * y;
   }
   return acc;
 }
@@ -152,7 +270,11 @@ __global__ void __launch_bounds__(kBlock) k_bata(int64_t n, const int64_t* __res
   const int64_t d = wave_row<NB>(gid / NB);
   const int j = (int)(gid % NB);
   if (d >= n) return;
-  const T acc = ata_row<T, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
+  T acc;
+  if constexpr (NB == 64)
+    acc = ata_row64<T, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
+  else
+    acc = ata_row<T, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
   R[d * NB + j] = B ? B[d * NB + j] - acc : acc;
 }
 
@@ -176,8 +298,9 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
   constexpr int LC = 32;            // loop indices staged per chunk
   constexpr int RW = NB / 4;        // right-hand sides per thread
   __shared__ T sv[LC * NB];
-  const int64_t a = task_a[blockIdx.x];
-  const int j0 = task_j0[blockIdx.x];
+  const int64_t task = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t a = task_a[task];
+  const int j0 = task_j0[task];
   const int nj = op.lj[a], nl = op.ll[a];
   const int64_t ib = op.ibase[a];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -298,7 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
   constexpr int WPB = kBlock / 64;
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, g = lane >> 4;
-  for (int t = __builtin_amdgcn_readfirstlane(blockIdx.x * WPB + (threadIdx.x >> 6)); t < ntask;
+  for (int t = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6)); t < ntask;
        t += gridDim.x * WPB) {
     const int a = tk.a[t], j0 = tk.j0[t], k0 = tk.k0[t], k1 = tk.k1[t];
     const int nj = op.lj[a];
@@ -393,7 +516,10 @@ __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t
   const int c = (int)(gid % NB);
   if (d >= n) return;
   T s = X[d * NB + c];
-  for (int64_t e = cptr[d]; e < cptr[d + 1]; ++e) s += tb[cpos[e] * NB + c];
+  if constexpr (NB == 64)
+    s += staged_sum64<T>(cptr[d], cptr[d + 1], cpos, tb, c);
+  else
+    for (int64_t e = cptr[d]; e < cptr[d + 1]; ++e) s += tb[cpos[e] * NB + c];
   X[d * NB + c] = s;
 }
 
@@ -485,8 +611,11 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* _
   double v = 0;
   for (int64_t d = wave_row<NB>((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / NB); d < n;
        d += (int64_t)gridDim.x * (kBlock / NB)) {
-    const double acc =
-        ata_row<double, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, P, j);
+    double acc;
+    if constexpr (NB == 64)
+      acc = ata_row64<double, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, P, j);
+    else
+      acc = ata_row<double, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, P, j);
     Q[d * NB + j] = acc;
     v += acc * P[d * NB + j];
   }
@@ -538,8 +667,12 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
        e += (int64_t)gridDim.x * kBlock) {
     const int64_t d = wave_row<NB>(e / NB);
     T s = XV[e];
-    if (cptr)
-      for (int64_t q = cptr[d]; q < cptr[d + 1]; ++q) s += tb[cpos[q] * NB + c];
+    if (cptr) {
+      if constexpr (NB == 64)
+        s += staged_sum64<T>(cptr[d], cptr[d + 1], cpos, tb, c);
+      else
+        for (int64_t q = cptr[d]; q < cptr[d + 1]; ++q) s += tb[cpos[q] * NB + c];
+    }
     const double zi = (double)s;
     Z[e] = zi;
     v += R[e] * zi;
