@@ -237,14 +237,20 @@ enum {
                              coarse operator as matrix-core (MFMA) tiles whose
                              shapes are autotuned on the first such solve;
                              0: plain FMA kernels                               */
-  LSAMG_OPT_GRAPH = 2     /* 1 (default): each V-cycle of a solve is replayed
+  LSAMG_OPT_GRAPH = 2,    /* 1 (default): each V-cycle of a solve is replayed
                              from a HIP graph of kernel nodes built on first use (one per
                              precision and batch width; not while kernel timing
                              is on); 0: kernels launched one by one             */
+  LSAMG_OPT_MFMA_TILE = 3 /* 0 (default): the matrix-core tile shapes are
+                             autotuned; 100*rt + 10*u + split fixes them for every
+                             operator instead: rt in {1,2,4} row tiles of 16 per
+                             task, u in {2,8} loop steps loaded together, split in
+                             {1,2,4,8} loop ranges per task (reduced to 1 where
+                             the partial-sum buffer is too small)               */
 };
 
-/* Set a solve-path option (LSAMG_OPT_*) for later calls.  EINVAL on an
- * unknown option or value. */
+/* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
+ * except for LSAMG_OPT_MFMA_TILE.  EINVAL on an unknown option or value. */
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
 
 /* Y = B X: one V-cycle from zero (the preconditioner of lsamg_solve, sec.

@@ -365,7 +365,10 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
 // output row is written back the same way.
 //
 // Tasks with slot >= 0 (a loop split across waves) store their partial sums
-// to part[slot][row][:] for k_bmm_reduce; the others write (or add to) out.
+// to part[slot][row][:] (row = obase_a + output index) for k_bmm_reduce; the
+// others write (or add to) out.  With a split, every aggregate has one task
+// per slot (an empty loop range writes zeros), so every slot of every output
+// row is written.
 // ---------------------------------------------------------------------------
 struct MmTasks {
   const int32_t* a;     // aggregate
@@ -478,7 +481,7 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
 #pragma unroll
         for (int q = 0; q < CT; ++q) o[q] = acc[r][q][v];
         if (slot >= 0) {
-          vstore<CT>(part + ((int64_t)slot * part_rows + jj) * NB + CT * i, o);
+          vstore<CT>(part + ((int64_t)slot * part_rows + op.obase[a] + jj) * NB + CT * i, o);
         } else {
           float* d = out + (op.obase[a] + jj) * NB + CT * i;
           if (ADD) {

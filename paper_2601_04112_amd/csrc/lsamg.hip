@@ -76,7 +76,8 @@ struct GemvPlan {
   int64_t nagg = 0;
   int lmax = 0;        // largest input length
   int G = 0;           // narrow form lane-group width (0: wide form)
-  int NW = 4;          // wide form: wavefronts per workgroup
+  int NW = 4;          // wide form: wavefronts per workgroup (default from the task count)
+  mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
   int64_t ntask = 0;   // wide form: tasks (aggregate, 64-wide output slice)
   // algorithmic size of one application: matrix entries, distinct input
   // entries, gathered index entries, outputs
@@ -260,6 +261,8 @@ struct lsamg_handle {
   int precision = LSAMG_FP64;
   int batch_mode = 1;               // 1: nrhs > 1 solved as batches of <= 64
   bool use_mfma = true;             // FP32 batched V-cycle on the matrix cores (k_bmm)
+  int mm_fixed = 0;                 // k_bmm tile shape 100*rt + 10*u + split, 0: autotune
+  bool gv_tuned[2] = {false, false}; // single-vector wide GEMV shapes tuned (double, float)
   // V-cycles replayed from HIP graphs, one per (precision, batch width)
   bool use_graphs = true;
   std::unordered_map<int, hipGraphExec_t> graphs;
@@ -770,12 +773,67 @@ void resid_csr(int64_t rows, int lanes, const int64_t* ptr, const int32_t* col, 
   LAUNCH_OK();
 }
 
+// Autotuning of the single-vector wide GEMV (wavefronts per task): while a
+// GvTune is active on the calling thread (one eager V-cycle on the first
+// solve of each precision), every wide GEMV whose shape is not tuned yet times
+// each candidate on its real inputs, writing to a scratch output (so that
+// accumulating operators are not applied twice), and keeps the fastest.
+struct GvTune {
+  void* scratch = nullptr;      // >= the longest GEMV output, in doubles
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+thread_local GvTune* g_gvtune = nullptr;
+
+template <typename T, int MODE, bool ADD, int NW>
+void gemv_wide_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
+                      T* out, hipStream_t s, const ProfScope& ps_) {
+  const size_t lds = ((size_t)P.lmax + (size_t)NW * 64) * sizeof(T);
+  KLAUNCH((unsigned)P.ntask, NW * 64, lds, s, dev::k_gemv_wide<T, MODE, ADD, NW>, P.task_a,
+          P.task_j0, P.op, P.lmax, sp, M, in, out);
+}
+
+template <typename T, int MODE, bool ADD>
+void gemv_wide_nw(int nw, const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
+                  T* out, hipStream_t s, const ProfScope& ps) {
+  if (nw == 4)
+    gemv_wide_launch<T, MODE, ADD, 4>(P, sp, M, in, out, s, ps);
+  else if (nw == 8)
+    gemv_wide_launch<T, MODE, ADD, 8>(P, sp, M, in, out, s, ps);
+  else
+    gemv_wide_launch<T, MODE, ADD, 16>(P, sp, M, in, out, s, ps);
+}
+
 template <typename T, int MODE, bool ADD>
 void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, T* out,
           hipStream_t s, int64_t extra_bytes = 0) {
+  const int pi = sizeof(T) == sizeof(float) ? 1 : 0;
+  if (P.G == 0 && P.nw_t[pi] == 0 && g_gvtune && !g_rec) {
+    float best = 1e30f;
+    int pick = P.NW;
+    for (int nw : {4, 8, 16}) {
+      gemv_wide_nw<T, MODE, ADD>(nw, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+      float ms = 1e30f;
+      for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
+        HIP_OK(hipEventRecord(g_gvtune->e0, s));
+        for (int r = 0; r < 3; ++r)
+          gemv_wide_nw<T, MODE, ADD>(nw, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+        HIP_OK(hipEventRecord(g_gvtune->e1, s));
+        HIP_OK(hipEventSynchronize(g_gvtune->e1));
+        float t = 0.f;
+        HIP_OK(hipEventElapsedTime(&t, g_gvtune->e0, g_gvtune->e1));
+        ms = std::min(ms, t);
+      }
+      if (ms < best) {
+        best = ms;
+        pick = nw;
+      }
+    }
+    P.nw_t[pi] = pick;
+  }
+  const int NWsel = P.nw_t[pi] ? P.nw_t[pi] : P.NW;
   PROF(kname(P.G > 0 ? "k_gemv_narrow" : "k_gemv_wide",
              std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
-                 (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : P.NW)),
+                 (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : NWsel)),
        sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
        s);
   if (P.G > 0) {
@@ -791,16 +849,7 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
 #undef CASE
     }
   } else {
-    const size_t lds = ((size_t)P.lmax + (size_t)P.NW * 64) * sizeof(T);
-    switch (P.NW) {
-#define CASE(NW)                                                                               \
-  case NW:                                                                                     \
-    KLAUNCH((unsigned)P.ntask, NW * 64, lds, s, dev::k_gemv_wide<T, MODE, ADD, NW>,                 \
-        P.task_a, P.task_j0, P.op, P.lmax, sp, M, in, out);                                    \
-    break;
-      CASE(4) CASE(8) CASE(16)
-#undef CASE
-    }
+    gemv_wide_nw<T, MODE, ADD>(NWsel, P, sp, M, in, out, s, ps_);
   }
   LAUNCH_OK();
 }
@@ -1118,6 +1167,40 @@ void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
 // already queued, so the GPU never idles on the stop test.  Only when the
 // residual history predicts convergence within the next iteration does the
 // host wait before queueing the V-cycle (which would otherwise be wasted).
+// One eager V-cycle on the current level-0 input with GEMV autotuning on
+// (first solve of each precision); its output is overwritten by the solve.
+void gv_tune(lsamg_handle* h, hipStream_t s) {
+  const bool mixed = h->precision == LSAMG_MIXED;
+  const int pi = mixed ? 1 : 0;
+  if (h->gv_tuned[pi] || h->L.empty()) return;
+  int64_t mx = 1;
+  for (auto& D : h->L)
+    for (const GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro}) mx = std::max(mx, P->out);
+  struct Ctx {
+    GvTune t;
+    Profiler* saved = g_prof;
+    ~Ctx() {
+      g_gvtune = nullptr;
+      g_prof = saved;
+      if (t.scratch) (void)hipFree(t.scratch);
+      if (t.e0) (void)hipEventDestroy(t.e0);
+      if (t.e1) (void)hipEventDestroy(t.e1);
+    }
+  } c;
+  HIP_OK(hipMalloc(&c.t.scratch, (size_t)mx * sizeof(double)));
+  HIP_OK(hipEventCreate(&c.t.e0));
+  HIP_OK(hipEventCreate(&c.t.e1));
+  g_prof = nullptr;                     // tuning launches are not profiled
+  g_gvtune = &c.t;
+  DLevel& L0 = h->L[0];
+  if (mixed)
+    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, false);
+  else
+    vcycle<double>(h, 0, h->r, L0.d.x, s, false);
+  HIP_OK(hipStreamSynchronize(s));
+  h->gv_tuned[pi] = true;
+}
+
 int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
             lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1145,6 +1228,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
       KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<double, float>, n, h->r, L0.f.b);
       LAUNCH_OK();
     }
+    gv_tune(h, s);
     int cur = 0;                        // p_rz[cur] holds rho of the current direction
     cg_precondition(h, s, true, cur);
     const double target = tol * nb;
@@ -1202,7 +1286,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
 // ===========================================================================
 // Multi-right-hand-side path
 // ===========================================================================
-constexpr int kBNP = 2048;     // workgroups (and partials per column) of the batched CG kernels
+constexpr int kBNP = 8192;     // workgroups (and partials per column) of the batched CG kernels
 constexpr int kBMax = 64;      // widest batch
 
 void ensure_batched(lsamg_handle* h, int NB) {
@@ -1283,17 +1367,25 @@ GemvPlan::Mm mm_build(lsamg_handle* h, const GemvPlan& P, int RT, int S, bool tm
     int32_t a, j0, k0, k1, slot, bucket;
   };
   std::vector<Task> ts;
-  const int sn = P.nagg == 1 ? std::max(1, S) : 1;
+  // a split cuts every aggregate's loop into S ranges of a multiple of 8
+  // (trailing ranges may be empty): slot q of every output row is written by
+  // exactly one task
+  const int sn = std::max(1, S);
   int used_split = 1;
+  if (sn > 1 && P.nagg == 1) {        // a single aggregate: no empty ranges
+    const int K = P.hll[0];
+    const int kc = std::max(8, ((K + sn - 1) / sn + 7) / 8 * 8);
+    used_split = std::max(1, (K + kc - 1) / kc);
+  } else if (sn > 1) {
+    used_split = sn;
+  }
   for (int64_t a = 0; a < P.nagg; ++a) {
     const int nj = P.hlj[a], K = P.hll[a];
-    int kc = (K + sn - 1) / sn;
-    kc = std::max(8, (kc + 7) / 8 * 8);
-    const int ns = sn > 1 ? std::max(1, (K + kc - 1) / kc) : 1;
-    if (sn > 1) used_split = ns;
+    const int kc = std::max(8, ((K + used_split - 1) / used_split + 7) / 8 * 8);
+    const int ns = used_split;
     for (int j0 = 0; j0 < nj; j0 += 16 * RT)
       for (int q = 0; q < ns; ++q) {
-        const int k0 = sn > 1 ? q * kc : 0, k1 = sn > 1 ? std::min(K, (q + 1) * kc) : K;
+        const int k0 = ns > 1 ? std::min(K, q * kc) : 0, k1 = ns > 1 ? std::min(K, (q + 1) * kc) : K;
         int b = 0;
         while ((1 << b) < k1 - k0) ++b;
         ts.push_back(Task{(int32_t)a, j0, k0, k1, ns > 1 ? q : -1, b});
@@ -1409,12 +1501,19 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
     int rt, u, sp;
   };
   std::vector<Cand> cand;
+  if (h->mm_fixed > 0) {               // a fixed tile shape (LSAMG_OPT_MFMA_TILE)
+    const int rt = h->mm_fixed / 100, u = (h->mm_fixed / 10) % 10;
+    int sp = h->mm_fixed % 10;
+    if ((int64_t)sp * P.out * NB > part_cap) sp = 1;
+    cand.push_back(Cand{rt, u, sp});
+  }
   for (int rt : {1, 2, 4}) {
+    if (!cand.empty()) break;
     if (rt > 1 && 16 * (rt / 2) >= ljmax) continue;      // the tile would be mostly empty
     for (int u : {2, 8}) {
       if (u == 8 && llmax <= 8) continue;                 // one step covers the loop
       for (int sp : {1, 2, 4, 8, 16}) {
-        if (sp > 1 && (P.nagg != 1 || llmax / sp < 256)) continue;
+        if (sp > 1 && (llmax / sp < (P.nagg == 1 ? 256 : 64) || (P.nagg > 1 && sp > 4))) continue;
         if ((int64_t)sp * P.out * NB > part_cap) continue;
         cand.push_back(Cand{rt, u, sp});
       }
@@ -1429,15 +1528,19 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
     GemvPlan::Mm mm = mm_build(h, P, c.rt, c.sp, true);
     mm.u = c.u;
     mm.part = part;
-    float ms = 0.f;
+    float ms = 1e30f;
     try {
       bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
-      HIP_OK(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r)
-        bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
-      HIP_OK(hipEventRecord(e1, s));
-      HIP_OK(hipEventSynchronize(e1));
-      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
+        HIP_OK(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r)
+          bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
+        HIP_OK(hipEventRecord(e1, s));
+        HIP_OK(hipEventSynchronize(e1));
+        float t = 0.f;
+        HIP_OK(hipEventElapsedTime(&t, e0, e1));
+        ms = std::min(ms, t);
+      }
     } catch (...) {
       mm_free(mm);
       (void)hipEventDestroy(e0);
@@ -1540,12 +1643,17 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
     } quiet{g_prof, h};
     g_prof = nullptr;
     h->batch_alloc = true;               // task lists live with the batched buffers
+    // partial sums of split loops: 16 slots of the dense level, or 4 slots
+    // of a coarse level's output (RAS/P^T/P: n unknowns; RAS-T: staging)
     int64_t cap = 0;
-    for (auto& L : h->L)
+    for (size_t l = 0; l < h->L.size(); ++l) {
+      DLevel& L = h->L[l];
       if (L.coarsest || L.tail) {
         cap = std::max<int64_t>(cap, 16 * L.n * NB);
         break;
       }
+      if (l > 0) cap = std::max<int64_t>(cap, 4 * std::max(L.n, L.ntb) * NB);
+    }
     float* part = cap > 0 ? h->alloc<float>((size_t)cap) : nullptr;
     for (size_t l = 0; l < h->L.size(); ++l) {
       DLevel& L = h->L[l];
@@ -2077,7 +2185,8 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
 }
 
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
-  if (!h || (value != 0 && value != 1)) return fail_with(LSAMG_EINVAL, "bad argument");
+  if (!h || value < 0 || (opt != LSAMG_OPT_MFMA_TILE && value > 1))
+    return fail_with(LSAMG_EINVAL, "bad argument");
   if (opt == LSAMG_OPT_BATCHED) {
     h->batch_mode = (int)value;
   } else if (opt == LSAMG_OPT_MFMA) {
@@ -2090,6 +2199,16 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
   } else if (opt == LSAMG_OPT_GRAPH) {
     h->use_graphs = value != 0;
+  } else if (opt == LSAMG_OPT_MFMA_TILE) {
+    const int64_t rt = value / 100, u = (value / 10) % 10, sp = value % 10;
+    if (value != 0 && (value >= 1000 || (rt != 1 && rt != 2 && rt != 4) || (u != 2 && u != 8) ||
+                       (sp != 1 && sp != 2 && sp != 4 && sp != 8)))
+      return fail_with(LSAMG_EINVAL, "bad tile shape");
+    h->mm_fixed = (int)value;
+    for (auto& D : h->L)
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+    h->mm_tuned = false;                // retuned (or fixed) on the next batched solve
+    h->drop_graphs(true);
   } else {
     return fail_with(LSAMG_EINVAL, "unknown option");
   }

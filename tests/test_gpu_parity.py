@@ -257,6 +257,29 @@ def test_batched_vcycle_matches_single(which, nrhs, request):
         s.set_option(L.OPT_MFMA, 1)
 
 
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_batched_vcycle_every_tile_shape(which, request):
+    """Every fixed matrix-core tile shape (row tiles, loads in flight, loop
+    split, the split also on multi-aggregate operators) gives the single-
+    vector FP32 V-cycle on each of 64 columns to 2e-5."""
+    p, H, s = request.getfixturevalue(which)
+    X = np.stack([P.rhs_uniform(p.n, 500 + j) for j in range(64)])
+    dX = dvec(X)
+    s.set_precision(L.MIXED)
+    try:
+        Y1 = [host(s.apply(L.OP_VCYCLE, dX[j])) for j in range(0, 64, 7)]
+        for rt in (1, 2, 4):
+            for u in (2, 8):
+                for sp in (1, 2, 4, 8):
+                    s.set_option(L.OPT_MFMA_TILE, 100 * rt + 10 * u + sp)
+                    Y = host(s.apply_vcycle_batch(dX))
+                    for k, j in enumerate(range(0, 64, 7)):
+                        assert rel(Y[j], Y1[k]) <= 2e-5, (rt, u, sp, j, rel(Y[j], Y1[k]))
+    finally:
+        s.set_option(L.OPT_MFMA_TILE, 0)
+        s.set_precision(L.FP64)
+
+
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
 def test_graph_replay_equals_eager(rot_tail, prec):
     """Solves whose V-cycles replay a captured HIP graph are bit-identical to
