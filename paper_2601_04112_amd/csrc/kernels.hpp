@@ -165,12 +165,42 @@ __device__ __forceinline__ T load_in(const T* __restrict__ in, int64_t i, const 
   return v - t;
 }
 
+// IN_RESG staging in two steps.  The G^T rows of the consecutive inputs
+// ib .. ib+nl-1 form one contiguous range of entries, so the threads first
+// form every product v1[e] * v2[idx[e]] of that range with coalesced loads
+// into pr (LDS); after a barrier each input adds its own products in entry
+// order (the same order as load_in).
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_products(T* pr, int64_t ib, int nl, const InSpec<T>& sp,
+                                               int tid, int nt) {
+  if (MODE != IN_RESG) return;
+  const int64_t eb = sp.ptr[ib], ee = sp.ptr[ib + nl];
+  for (int64_t e = eb + tid; e < ee; e += nt) pr[e - eb] = sp.v1[e] * sp.v2[sp.idx[e]];
+}
+
+template <typename T, int MODE>
+__device__ __forceinline__ void stage_inputs(T* sv, const T* pr, const T* __restrict__ in,
+                                             int64_t ib, int nl, const InSpec<T>& sp, int tid,
+                                             int nt) {
+  for (int l = tid; l < nl; l += nt) {
+    if (MODE == IN_RESG) {
+      const int64_t eb = sp.ptr[ib];
+      T t = 0;
+      for (int64_t e = sp.ptr[ib + l]; e < sp.ptr[ib + l + 1]; ++e) t += pr[e - eb];
+      sv[l] = in[ib + l] - t;
+    } else {
+      sv[l] = load_in<T, MODE>(in, ib + l, sp);
+    }
+  }
+}
+
 // Narrow form (every lj_a <= G <= 64): one wavefront per aggregate, the
 // wavefront split into 64/G lane groups that share the loop over l; four
-// aggregates per 256-thread workgroup.  LDS: 4 * lmax * sizeof(T).
+// aggregates per 256-thread workgroup.  LDS: 4 * (lmax + emax) * sizeof(T)
+// (emax: the most G^T entries of one aggregate's inputs, IN_RESG only).
 template <typename T, int MODE, bool ADD, int G>
 __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op, int lmax,
-                                                        InSpec<T> spec,
+                                                        int emax, InSpec<T> spec,
                                                         const T* __restrict__ M,
                                                         const T* __restrict__ in,
                                                         T* __restrict__ out) {
@@ -180,9 +210,11 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t a = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
   const bool valid = a < nagg;
-  T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * lmax;
+  T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * (lmax + emax);
+  T* pr = sv + lmax;
   const int s = lane / G, j = lane % G;
   int nj = 0, nl = 0;
+  int64_t ib = 0;
   const T* m = M;
   T mv[U];
   if (valid) {
@@ -196,8 +228,15 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
       const int l = s + u * S;
       mv[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
     }
-    const int64_t ib = op.ibase[a];
-    for (int l = lane; l < nl; l += 64) sv[l] = load_in<T, MODE>(in, ib + l, spec);
+    ib = op.ibase[a];
+    if (MODE == IN_RESG)
+      stage_products<T, MODE>(pr, ib, nl, spec, lane, 64);
+    else
+      stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, lane, 64);
+  }
+  if (MODE == IN_RESG) {
+    __syncthreads();
+    if (valid) stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, lane, 64);
   }
   __syncthreads();
   if (!valid) return;
@@ -229,17 +268,19 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
 // Wide form: one workgroup of NW wavefronts per task (aggregate a, 64-wide
 // slice j0 of its outputs); the waves split the loop over l and their
 // partial sums are added in wave order through LDS.
-// LDS: (lmax + NW*64) * sizeof(T).
+// LDS: (lmax + emax + NW*64) * sizeof(T).
 template <typename T, int MODE, bool ADD, int NW>
 __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict__ task_a,
                                                        const int32_t* __restrict__ task_j0,
-                                                       GemvOp op, int lmax, InSpec<T> spec,
+                                                       GemvOp op, int lmax, int emax,
+                                                       InSpec<T> spec,
                                                        const T* __restrict__ M,
                                                        const T* __restrict__ in,
                                                        T* __restrict__ out) {
   extern __shared__ unsigned char smem_raw[];
   T* sv = reinterpret_cast<T*>(smem_raw);
-  T* part = sv + lmax;
+  T* pr = sv + lmax;
+  T* part = pr + emax;
   const int64_t task = xcd_block(blockIdx.x, gridDim.x);
   const int64_t a = task_a[task];
   const int j0 = task_j0[task];
@@ -257,8 +298,11 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
     const int l = wave + u * NW;
     mv0[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
   }
-  for (int l = threadIdx.x; l < nl; l += NW * 64)
-    sv[l] = load_in<T, MODE>(in, ib + l, spec);
+  if (MODE == IN_RESG) {
+    stage_products<T, MODE>(pr, ib, nl, spec, threadIdx.x, NW * 64);
+    __syncthreads();
+  }
+  stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, threadIdx.x, NW * 64);
   __syncthreads();
   T acc = 0;
   if (j < nj) {
@@ -277,7 +321,11 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
     }
     for (; l < nl; l += NW) av[0] += m[(int64_t)l * nj] * sv[l];
-    acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
+#pragma unroll
+    for (int w = U / 2; w > 0; w >>= 1)     // fixed pairwise tree over the U partial sums
+#pragma unroll
+      for (int u = 0; u < w; ++u) av[u] += av[u + w];
+    acc = av[0];
   }
   part[threadIdx.x] = acc;
   __syncthreads();

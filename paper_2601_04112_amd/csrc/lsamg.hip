@@ -75,6 +75,7 @@ struct GemvPlan {
   dev::GemvOp op{};
   int64_t nagg = 0;
   int lmax = 0;        // largest input length
+  int emax = 0;        // finest level: most G^T entries of one aggregate's inputs (IN_RESG)
   int G = 0;           // narrow form lane-group width (0: wide form)
   int NW = 4;          // wide form: wavefronts per workgroup (default from the task count)
   mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
@@ -683,6 +684,11 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   plan(D.rast, nO, nw, d_nO, d_nw, d_z0, d_w0, d_o0, D.n, false);
   plan(D.rst, kk, nw, d_k, d_nw, d_p0, d_w0, d_c0, D.n, false);
   plan(D.pro, nw, kk, d_nw, d_k, d_p0, d_c0, d_w0, ncoarse, false);
+  if (finest) {      // inputs of P^T and RAS-T are residual rows omega_a formed on the fly
+    int64_t em = 0;
+    for (int64_t a = 0; a < HL.nagg; ++a) em = std::max(em, tp[HL.astart[a + 1]] - tp[HL.astart[a]]);
+    D.rst.emax = D.rast.emax = (int)em;
+  }
   D.d.tb = h->alloc<double>(D.ntb);
   D.f.tb = h->alloc<float>(D.ntb);
 }
@@ -787,9 +793,10 @@ thread_local GvTune* g_gvtune = nullptr;
 template <typename T, int MODE, bool ADD, int NW>
 void gemv_wide_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
                       T* out, hipStream_t s, const ProfScope& ps_) {
-  const size_t lds = ((size_t)P.lmax + (size_t)NW * 64) * sizeof(T);
+  const int emax = MODE == dev::IN_RESG ? P.emax : 0;
+  const size_t lds = ((size_t)P.lmax + emax + (size_t)NW * 64) * sizeof(T);
   KLAUNCH((unsigned)P.ntask, NW * 64, lds, s, dev::k_gemv_wide<T, MODE, ADD, NW>, P.task_a,
-          P.task_j0, P.op, P.lmax, sp, M, in, out);
+          P.task_j0, P.op, P.lmax, emax, sp, M, in, out);
 }
 
 template <typename T, int MODE, bool ADD>
@@ -838,12 +845,13 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
        s);
   if (P.G > 0) {
     const unsigned g = (unsigned)((P.nagg + 3) / 4);
-    const size_t lds = (size_t)4 * P.lmax * sizeof(T);
+    const int emax = MODE == dev::IN_RESG ? P.emax : 0;
+    const size_t lds = (size_t)4 * (P.lmax + emax) * sizeof(T);
     switch (P.G) {
 #define CASE(GG)                                                                            \
   case GG:                                                                                  \
     KLAUNCH(g, dev::kBlock, lds, s, dev::k_gemv_narrow<T, MODE, ADD, GG>, P.nagg, P.op, P.lmax,  \
-            sp, M, in, out);                                                                \
+            emax, sp, M, in, out);                                                          \
     break;
       CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32) CASE(64)
 #undef CASE
