@@ -1019,7 +1019,6 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   if (finalize) gather_add<T>(L, x, s);
 }
 
-// z = B r (FP64 in and out), in the handle's precision.
 // Run fn (which launches a fixed sequence of kernels on a stream: one
 // V-cycle) on s.  With graphs on and no kernel timing active, the sequence is
 // recorded once per key as a chain of kernel nodes of a HIP graph (no stream
@@ -1054,6 +1053,7 @@ void run_graph(lsamg_handle* h, int key, hipStream_t s, F&& fn) {
   HIP_OK(hipGraphLaunch(it->second, s));
 }
 
+// z = B r (FP64 in and out), in the handle's precision.
 void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
   DLevel& L0 = h->L[0];
   if (h->precision == LSAMG_MIXED) {
