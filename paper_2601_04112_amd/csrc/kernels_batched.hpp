@@ -68,21 +68,25 @@ template <typename T>
 __device__ __forceinline__ T row_dot64(int64_t e0, int64_t e1, const int32_t* __restrict__ col,
                                        const T* __restrict__ val, const T* __restrict__ X,
                                        int lane) {
+  // 16 gathers in flight per round; entries past the row end repeat its last
+  // index (an L1 hit) with a zero weight
+  constexpr int U = 16;
   T acc[4] = {T(0), T(0), T(0), T(0)};
   for (int64_t b = e0; b < e1; b += 64) {
     const int cnt = (int)(e1 - b < 64 ? e1 - b : 64);
     const int64_t f = b + (lane < cnt ? lane : cnt - 1);
     const int32_t c = col[f];
-    const T v = val[f];
-    int L = 0;
-    for (; L + 4 <= cnt; L += 4) {
-      T x[4];
+    const T v = lane < cnt ? val[f] : T(0);
+    for (int L = 0; L < cnt; L += U) {
+      T x[U];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = X[(int64_t)lane_val(c, L + u) * 64 + lane];
+      for (int u = 0; u < U; ++u) {
+        const int k = L + u < cnt ? L + u : cnt - 1;
+        x[u] = X[(int64_t)lane_val(c, k) * 64 + lane];
+      }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc[u] += lane_val(v, L + u) * x[u];
+      for (int u = 0; u < U; ++u) acc[u & 3] += lane_val(v, (L + u) & 63) * x[u];
     }
-    for (; L < cnt; ++L) acc[0] += lane_val(v, L) * X[(int64_t)lane_val(c, L) * 64 + lane];
   }
   return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
