@@ -15,6 +15,9 @@ namespace dev {
 
 constexpr int kBlock = 256;
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 // XCD-aware block order.  The command processor deals consecutive workgroups
 // of a launch to the 8 XCDs in turn, and each XCD has its own L2; this
 // bijection of [0, nb) gives XCD x = b % 8 the contiguous range of logical
@@ -132,7 +135,14 @@ struct GemvOp {
   const int32_t* ll;     // [nagg] input length (loop dimension)
   const int64_t* ibase;  // [nagg] input base (index-list base for IN_GATHER)
   const int64_t* obase;  // [nagg] output base
+  int pad;               // != 0: rows of M_a padded to a multiple of 4 entries
 };
+
+// Row stride of M_a: lj, or lj rounded up to a multiple of 4 (padded
+// layout: every row starts 16-byte aligned for FP32, and the padding is zero).
+__device__ __forceinline__ int64_t mrow(int nj, int pad) {
+  return pad ? (int64_t)((nj + 3) & ~3) : (int64_t)nj;
+}
 
 // Where the input vector entries come from (MODE):
 //   IN_DIRECT  in[i]
@@ -214,19 +224,20 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
   T* pr = sv + lmax;
   const int s = lane / G, j = lane % G;
   int nj = 0, nl = 0;
-  int64_t ib = 0;
+  int64_t ib = 0, ld = 0;
   const T* m = M;
   T mv[U];
   if (valid) {
     nj = op.lj[a];
     nl = op.ll[a];
     m = M + op.moff[a] + (j < nj ? j : 0);
+    ld = mrow(nj, op.pad);
     // the first U matrix entries of the lane do not depend on the staged
     // input: their loads are issued before the staging gather and barrier
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int l = s + u * S;
-      mv[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
+      mv[u] = (j < nj && l < nl) ? m[(int64_t)l * ld] : T(0);
     }
     ib = op.ibase[a];
     if (MODE == IN_RESG)
@@ -251,11 +262,11 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
     int l = s + U * S;
     for (; l + (U - 1) * S < nl; l += U * S) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * S) * nj];
+      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * S) * ld];
 #pragma unroll
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * S];
     }
-    for (; l < nl; l += S) av[0] += m[(int64_t)l * nj] * sv[l];
+    for (; l < nl; l += S) av[0] += m[(int64_t)l * ld] * sv[l];
     acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
   }
   for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
@@ -290,13 +301,14 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
   const int j = j0 + lane;
   constexpr int U = 8;                      // independent loads in flight per lane
   const T* m = M + op.moff[a] + (j < nj ? j : 0);
+  const int64_t ld = mrow(nj, op.pad);
   // the first U matrix entries of the lane do not depend on the staged input:
   // their loads are issued before the staging gather and barrier
   T mv0[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int l = wave + u * NW;
-    mv0[u] = (j < nj && l < nl) ? m[(int64_t)l * nj] : T(0);
+    mv0[u] = (j < nj && l < nl) ? m[(int64_t)l * ld] : T(0);
   }
   if (MODE == IN_RESG) {
     stage_products<T, MODE>(pr, ib, nl, spec, threadIdx.x, NW * 64);
@@ -316,11 +328,11 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
     for (; l + (U - 1) * NW < nl; l += U * NW) {
       T mv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * NW) * nj];
+      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * NW) * ld];
 #pragma unroll
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
     }
-    for (; l < nl; l += NW) av[0] += m[(int64_t)l * nj] * sv[l];
+    for (; l < nl; l += NW) av[0] += m[(int64_t)l * ld] * sv[l];
 #pragma unroll
     for (int w = U / 2; w > 0; w >>= 1)     // fixed pairwise tree over the U partial sums
 #pragma unroll
@@ -334,6 +346,83 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
     for (int w = 1; w < NW; ++w) t += part[w * 64 + lane];
     T* dst = out + op.obase[a] + j;
     *dst = ADD ? *dst + t : t;
+  }
+}
+
+// Wide form with four outputs per lane (FP32, padded rows): a task covers up
+// to 256 consecutive outputs, lane L taking outputs j0 + 4L .. j0 + 4L + 3
+// with one 16-byte load per matrix row (rows are padded to a multiple of 4
+// entries and start 16-byte aligned, so the load never leaves the block); the
+// NW waves split the loop over l and their partial sums are added in wave
+// order through LDS.  LDS: (round_up(lmax + emax, 4) + NW*256) * 4 bytes.
+template <int MODE, bool ADD, int NW>
+__global__ void __launch_bounds__(NW * 64) k_gemv_wide4(const int32_t* __restrict__ task_a,
+                                                        const int32_t* __restrict__ task_j0,
+                                                        GemvOp op, int lmax, int emax,
+                                                        InSpec<float> spec,
+                                                        const float* __restrict__ M,
+                                                        const float* __restrict__ in,
+                                                        float* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  float* sv = reinterpret_cast<float*>(smem_raw);
+  float* pr = sv + lmax;
+  float* part = sv + ((lmax + emax + 3) & ~3);      // 16-byte aligned
+  const int64_t task = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t a = task_a[task];
+  const int j0 = task_j0[task];
+  const int nj = op.lj[a], nl = op.ll[a];
+  const int64_t ib = op.ibase[a];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = j0 + 4 * lane;
+  const bool jv = j < nj;
+  const int64_t ld = mrow(nj, 1);
+  const float* m = M + op.moff[a] + (jv ? j : 0);
+  constexpr int U = 8;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 mv0[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int l = wave + u * NW;
+    mv0[u] = (jv && l < nl) ? *(const f32x4*)(m + (int64_t)l * ld) : zero;
+  }
+  if (MODE == IN_RESG) {
+    stage_products<float, MODE>(pr, ib, nl, spec, threadIdx.x, NW * 64);
+    __syncthreads();
+  }
+  stage_inputs<float, MODE>(sv, pr, in, ib, nl, spec, threadIdx.x, NW * 64);
+  __syncthreads();
+  f32x4 acc = zero;
+  if (jv) {
+    f32x4 av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = wave + u * NW;
+      av[u] = l < nl ? mv0[u] * sv[l] : zero;
+    }
+    int l = wave + U * NW;
+    for (; l + (U - 1) * NW < nl; l += U * NW) {
+      f32x4 mv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) mv[u] = *(const f32x4*)(m + (int64_t)(l + u * NW) * ld);
+#pragma unroll
+      for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
+    }
+    for (; l < nl; l += NW) av[0] += *(const f32x4*)(m + (int64_t)l * ld) * sv[l];
+#pragma unroll
+    for (int w = U / 2; w > 0; w >>= 1)     // fixed pairwise tree over the U partial sums
+#pragma unroll
+      for (int u = 0; u < w; ++u) av[u] += av[u + w];
+    acc = av[0];
+  }
+  *(f32x4*)(part + (wave * 64 + lane) * 4) = acc;
+  __syncthreads();
+  if (wave == 0 && jv) {
+    f32x4 t = *(const f32x4*)(part + lane * 4);
+    for (int w = 1; w < NW; ++w) t += *(const f32x4*)(part + (w * 64 + lane) * 4);
+    float* dst = out + op.obase[a] + j;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (j + k < nj) dst[k] = ADD ? dst[k] + t[k] : t[k];
   }
 }
 

@@ -311,6 +311,7 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
   const int jj = j0 + lane;
   const bool jv = jj < nj;
   const T* m = M + op.moff[a] + (jv ? jj : 0);
+  const int64_t ld = mrow(nj, op.pad);
   T acc[RW];
 #pragma unroll
   for (int r = 0; r < RW; ++r) acc[r] = 0;
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_bgemm(const int32_t* __restrict__ ta
     __syncthreads();
     if (jv) {
       for (int l = 0; l < lc; ++l) {
-        const T mv = m[(int64_t)(l0 + l) * nj];
+        const T mv = m[(int64_t)(l0 + l) * ld];
         const T* s = sv + l * NB + wave * RW;
 #pragma unroll
         for (int r = 0; r < RW; ++r) acc[r] += mv * s[r];
@@ -382,8 +383,6 @@ struct MmTasks {
   const int32_t* slot;  // partial-sum slot, or -1
 };
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <int CT>
 __device__ __forceinline__ void vload(const float* __restrict__ p, float (&v)[CT]) {
@@ -434,6 +433,7 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
     const int nj = op.lj[a];
     const int64_t ib = op.ibase[a];
     const float* __restrict__ m = M + op.moff[a];
+    const int64_t ld = mrow(nj, op.pad);
     f32x4 acc[RT][CT];
 #pragma unroll
     for (int r = 0; r < RT; ++r)
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
           const int jj = j0 + 16 * r + i;
-          av[u][r] = (lv && jj < nj) ? m[(int64_t)l * nj + jj] : 0.f;
+          av[u][r] = (lv && jj < nj) ? m[(int64_t)l * ld + jj] : 0.f;
         }
 #pragma unroll
         for (int q = 0; q < CT; ++q) bv[u][q] = 0.f;

@@ -79,6 +79,10 @@ struct GemvPlan {
   int G = 0;           // narrow form lane-group width (0: wide form)
   int NW = 4;          // wide form: wavefronts per workgroup (default from the task count)
   mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
+  mutable int form_t = 0;         // FP32 wide form: 0 one output per lane, 1 four (k_gemv_wide4)
+  int64_t ntask4 = 0;             // tasks (aggregate, 256-wide output slice) of k_gemv_wide4
+  int32_t* task4_a = nullptr;
+  int32_t* task4_j0 = nullptr;
   int64_t ntask = 0;   // wide form: tasks (aggregate, 64-wide output slice)
   // algorithmic size of one application: matrix entries, distinct input
   // entries, gathered index entries, outputs
@@ -115,7 +119,7 @@ struct DLevel {
   int32_t* g_col = nullptr;
   int64_t* gt_ptr = nullptr;
   int32_t* gt_col = nullptr;
-  int64_t *astart = nullptr, *optr = nullptr, *zoff = nullptr, *poff = nullptr,
+  int64_t *astart = nullptr, *optr = nullptr,
           *cstart = nullptr, *cptr = nullptr, *cpos = nullptr;
   int32_t* oidx = nullptr;
   int32_t* kk = nullptr;
@@ -477,7 +481,7 @@ void make_dense_plan(lsamg_handle* h, DLevel& D) {
   std::vector<int32_t> n1(1, (int32_t)D.n);
   int32_t* dn = h->upload(n1);
   int64_t* dz = h->upload(z1);
-  P.op = dev::GemvOp{dz, dn, dn, dz, dz};
+  P.op = dev::GemvOp{dz, dn, dn, dz, dz, 0};
   P.nagg = 1;
   P.hlj = n1;
   P.hll = n1;
@@ -580,15 +584,41 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     D.max_nw = std::max<int>(D.max_nw, (int)(HL.astart[a + 1] - HL.astart[a]));
     D.max_k = std::max<int>(D.max_k, HL.k[a]);
   }
-  // Z_i row-major (host layout) and its column-major copy
-  std::vector<double> Zc(HL.Z.size());
+  // device layouts of Z_i (row-major for RAS-T, column-major for RAS) and of
+  // Zhat_i (row-major for P^T, column-major for P): every row padded to a
+  // multiple of 4 entries with zeros and every block starting at a multiple
+  // of 4 entries, so each row starts 16-byte aligned (FP32)
+  auto pad4 = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
+  std::vector<int64_t> offr(HL.nagg), offc(HL.nagg), offh(HL.nagg), offt(HL.nagg);
+  int64_t totr = 0, totc = 0, toth = 0, tott = 0;
   for (int64_t a = 0; a < HL.nagg; ++a) {
-    const int nw = (int)(HL.astart[a + 1] - HL.astart[a]);
-    const int nO = (int)(HL.optr[a + 1] - HL.optr[a]);
-    const double* zr = HL.Z.data() + HL.zoff[a];
-    double* zc = Zc.data() + HL.zoff[a];
-    for (int p = 0; p < nw; ++p)
-      for (int c = 0; c < nO; ++c) zc[(size_t)c * nw + p] = zr[(size_t)p * nO + c];
+    const int64_t nw = HL.astart[a + 1] - HL.astart[a], nO = HL.optr[a + 1] - HL.optr[a],
+                  k = HL.k[a];
+    offr[a] = totr;
+    totr += nw * pad4(nO);
+    offc[a] = totc;
+    totc += nO * pad4(nw);
+    offh[a] = toth;
+    toth += nw * pad4(k);
+    offt[a] = tott;
+    tott += k * pad4(nw);
+  }
+  std::vector<double> Zr(totr, 0.0), Zc(totc, 0.0), Zh(toth, 0.0), ZhT(tott, 0.0);
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    const int64_t nw = HL.astart[a + 1] - HL.astart[a], nO = HL.optr[a + 1] - HL.optr[a],
+                  k = HL.k[a];
+    const double* z = HL.Z.data() + HL.zoff[a];        // host: |omega| x |Omega| row-major
+    const double* zh = HL.Zhat.data() + HL.poff[a];    // host: |omega| x k row-major
+    for (int64_t p = 0; p < nw; ++p) {
+      for (int64_t c = 0; c < nO; ++c) {
+        Zr[offr[a] + p * pad4(nO) + c] = z[p * nO + c];
+        Zc[offc[a] + c * pad4(nw) + p] = z[p * nO + c];
+      }
+      for (int64_t t = 0; t < k; ++t) {
+        Zh[offh[a] + p * pad4(k) + t] = zh[p * k + t];
+        ZhT[offt[a] + t * pad4(nw) + p] = zh[p * k + t];
+      }
+    }
   }
   // cover lists for the RAS-T gather: for unknown j, staging positions
   // optr[i] + (index of j in Omega_i), ascending i
@@ -604,32 +634,21 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.astart = h->upload(HL.astart);
   D.optr = h->upload(HL.optr);
   D.oidx = h->upload(HL.oidx);
-  D.zoff = h->upload(HL.zoff);
-  D.poff = h->upload(HL.poff);
   D.cstart = h->upload(HL.cstart);
   D.kk = h->upload(HL.k);
   D.cptr = h->upload(cp);
   D.cpos = h->upload(cs);
-  D.d.Zr = h->upload_f<double>(HL.Z);
-  D.f.Zr = h->upload_f<float>(HL.Z);
+  D.d.Zr = h->upload_f<double>(Zr);
+  D.f.Zr = h->upload_f<float>(Zr);
   D.d.Zc = h->upload_f<double>(Zc);
   D.f.Zc = h->upload_f<float>(Zc);
-  D.d.Zh = h->upload_f<double>(HL.Zhat);
-  D.f.Zh = h->upload_f<float>(HL.Zhat);
-  std::vector<double> ZhT(HL.Zhat.size());
-  for (int64_t a = 0; a < HL.nagg; ++a) {
-    const int nw = (int)(HL.astart[a + 1] - HL.astart[a]), k = HL.k[a];
-    const double* zr = HL.Zhat.data() + HL.poff[a];
-    double* zc = ZhT.data() + HL.poff[a];
-    for (int p = 0; p < nw; ++p)
-      for (int t = 0; t < k; ++t) zc[(size_t)t * nw + p] = zr[(size_t)p * k + t];
-  }
+  D.d.Zh = h->upload_f<double>(Zh);
+  D.f.Zh = h->upload_f<float>(Zh);
   D.d.ZhT = h->upload_f<double>(ZhT);
   D.f.ZhT = h->upload_f<float>(ZhT);
   std::vector<int32_t> nw(HL.nagg), nO(HL.nagg), kk(HL.k.begin(), HL.k.end());
   std::vector<int64_t> w0(HL.astart.begin(), HL.astart.end() - 1),
-      o0(HL.optr.begin(), HL.optr.end() - 1), z0(HL.zoff.begin(), HL.zoff.end() - 1),
-      p0(HL.poff.begin(), HL.poff.end() - 1), c0(HL.cstart.begin(), HL.cstart.end() - 1);
+      o0(HL.optr.begin(), HL.optr.end() - 1), c0(HL.cstart.begin(), HL.cstart.end() - 1);
   for (int64_t a = 0; a < HL.nagg; ++a) {
     nw[a] = (int32_t)(HL.astart[a + 1] - HL.astart[a]);
     nO[a] = (int32_t)(HL.optr[a + 1] - HL.optr[a]);
@@ -639,13 +658,15 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   int32_t* d_k = h->upload(kk);
   int64_t* d_w0 = h->upload(w0);
   int64_t* d_o0 = h->upload(o0);
-  int64_t* d_z0 = h->upload(z0);
-  int64_t* d_p0 = h->upload(p0);
+  int64_t* d_offr = h->upload(offr);
+  int64_t* d_offc = h->upload(offc);
+  int64_t* d_offh = h->upload(offh);
+  int64_t* d_offt = h->upload(offt);
   int64_t* d_c0 = h->upload(c0);
   auto plan = [&](GemvPlan& P, const std::vector<int32_t>& lj, const std::vector<int32_t>& ll,
                   int32_t* dlj, int32_t* dll, int64_t* moff, int64_t* ib, int64_t* ob,
                   int64_t in_unique, bool gathered) {
-    P.op = dev::GemvOp{moff, dlj, dll, ib, ob};
+    P.op = dev::GemvOp{moff, dlj, dll, ib, ob, 1};
     P.nagg = HL.nagg;
     P.hlj = lj;
     P.hll = ll;
@@ -670,6 +691,17 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     P.task_a = h->upload(ta);
     P.task_j0 = h->upload(tj);
     P.G = 0;
+    if (ljmax > 64) {
+      std::vector<int32_t> ta4, tj4;
+      for (int64_t a = 0; a < HL.nagg; ++a)
+        for (int j = 0; j < lj[a]; j += 256) {
+          ta4.push_back((int32_t)a);
+          tj4.push_back(j);
+        }
+      P.ntask4 = (int64_t)ta4.size();
+      P.task4_a = h->upload(ta4);
+      P.task4_j0 = h->upload(tj4);
+    }
     if (ljmax <= 64) {
       int g = 1;
       while (g < ljmax) g <<= 1;
@@ -680,10 +712,10 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     while (P.NW < 16 && P.ntask * P.NW < 4096) P.NW <<= 1;
   };
   const int64_t ncoarse = HL.cstart[HL.nagg];
-  plan(D.ras, nw, nO, d_nw, d_nO, d_z0, d_o0, d_w0, D.n, true);
-  plan(D.rast, nO, nw, d_nO, d_nw, d_z0, d_w0, d_o0, D.n, false);
-  plan(D.rst, kk, nw, d_k, d_nw, d_p0, d_w0, d_c0, D.n, false);
-  plan(D.pro, nw, kk, d_nw, d_k, d_p0, d_c0, d_w0, ncoarse, false);
+  plan(D.ras, nw, nO, d_nw, d_nO, d_offc, d_o0, d_w0, D.n, true);
+  plan(D.rast, nO, nw, d_nO, d_nw, d_offr, d_w0, d_o0, D.n, false);
+  plan(D.rst, kk, nw, d_k, d_nw, d_offh, d_w0, d_c0, D.n, false);
+  plan(D.pro, nw, kk, d_nw, d_k, d_offt, d_c0, d_w0, ncoarse, false);
   if (finest) {      // inputs of P^T and RAS-T are residual rows omega_a formed on the fly
     int64_t em = 0;
     for (int64_t a = 0; a < HL.nagg; ++a) em = std::max(em, tp[HL.astart[a + 1]] - tp[HL.astart[a]]);
@@ -799,9 +831,30 @@ void gemv_wide_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, c
           P.task_j0, P.op, P.lmax, emax, sp, M, in, out);
 }
 
+template <int MODE, bool ADD, int NW>
+void gemv_wide4_launch(const GemvPlan& P, const dev::InSpec<float>& sp, const float* M,
+                       const float* in, float* out, hipStream_t s, const ProfScope& ps_) {
+  const int emax = MODE == dev::IN_RESG ? P.emax : 0;
+  const size_t lds = ((((size_t)P.lmax + emax + 3) & ~(size_t)3) + (size_t)NW * 256) * sizeof(float);
+  KLAUNCH((unsigned)P.ntask4, NW * 64, lds, s, dev::k_gemv_wide4<MODE, ADD, NW>, P.task4_a,
+          P.task4_j0, P.op, P.lmax, emax, sp, M, in, out);
+}
+
+// wide GEMV with nw wavefronts per task; form 1 (FP32 only): four outputs per lane
 template <typename T, int MODE, bool ADD>
-void gemv_wide_nw(int nw, const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
-                  T* out, hipStream_t s, const ProfScope& ps) {
+void gemv_wide_nw(int nw, int form, const GemvPlan& P, const dev::InSpec<T>& sp, const T* M,
+                  const T* in, T* out, hipStream_t s, const ProfScope& ps) {
+  if constexpr (std::is_same<T, float>::value) {
+    if (form == 1) {
+      if (nw == 4)
+        gemv_wide4_launch<MODE, ADD, 4>(P, sp, M, in, out, s, ps);
+      else if (nw == 8)
+        gemv_wide4_launch<MODE, ADD, 8>(P, sp, M, in, out, s, ps);
+      else
+        gemv_wide4_launch<MODE, ADD, 16>(P, sp, M, in, out, s, ps);
+      return;
+    }
+  }
   if (nw == 4)
     gemv_wide_launch<T, MODE, ADD, 4>(P, sp, M, in, out, s, ps);
   else if (nw == 8)
@@ -816,29 +869,35 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
   const int pi = sizeof(T) == sizeof(float) ? 1 : 0;
   if (P.G == 0 && P.nw_t[pi] == 0 && g_gvtune && !g_rec) {
     float best = 1e30f;
-    int pick = P.NW;
-    for (int nw : {4, 8, 16}) {
-      gemv_wide_nw<T, MODE, ADD>(nw, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
-      float ms = 1e30f;
-      for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
-        HIP_OK(hipEventRecord(g_gvtune->e0, s));
-        for (int r = 0; r < 3; ++r)
-          gemv_wide_nw<T, MODE, ADD>(nw, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
-        HIP_OK(hipEventRecord(g_gvtune->e1, s));
-        HIP_OK(hipEventSynchronize(g_gvtune->e1));
-        float t = 0.f;
-        HIP_OK(hipEventElapsedTime(&t, g_gvtune->e0, g_gvtune->e1));
-        ms = std::min(ms, t);
-      }
-      if (ms < best) {
-        best = ms;
-        pick = nw;
+    int pick = P.NW, pick_form = 0;
+    for (int form : {0, 1}) {
+      if (form == 1 && pi == 0) continue;          // four outputs per lane: FP32 only
+      for (int nw : {4, 8, 16}) {
+        gemv_wide_nw<T, MODE, ADD>(nw, form, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+        float ms = 1e30f;
+        for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
+          HIP_OK(hipEventRecord(g_gvtune->e0, s));
+          for (int r = 0; r < 3; ++r)
+            gemv_wide_nw<T, MODE, ADD>(nw, form, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+          HIP_OK(hipEventRecord(g_gvtune->e1, s));
+          HIP_OK(hipEventSynchronize(g_gvtune->e1));
+          float t = 0.f;
+          HIP_OK(hipEventElapsedTime(&t, g_gvtune->e0, g_gvtune->e1));
+          ms = std::min(ms, t);
+        }
+        if (ms < best) {
+          best = ms;
+          pick = nw;
+          pick_form = form;
+        }
       }
     }
     P.nw_t[pi] = pick;
+    if (pi == 1) P.form_t = pick_form;
   }
   const int NWsel = P.nw_t[pi] ? P.nw_t[pi] : P.NW;
-  PROF(kname(P.G > 0 ? "k_gemv_narrow" : "k_gemv_wide",
+  const int form = pi == 1 ? P.form_t : 0;
+  PROF(kname(P.G > 0 ? "k_gemv_narrow" : (form == 1 ? "k_gemv_wide4" : "k_gemv_wide"),
              std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
                  (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : NWsel)),
        sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
@@ -857,7 +916,7 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
 #undef CASE
     }
   } else {
-    gemv_wide_nw<T, MODE, ADD>(NWsel, P, sp, M, in, out, s, ps_);
+    gemv_wide_nw<T, MODE, ADD>(NWsel, form, P, sp, M, in, out, s, ps_);
   }
   LAUNCH_OK();
 }
