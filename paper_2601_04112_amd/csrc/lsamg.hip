@@ -897,9 +897,10 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
   }
   const int NWsel = P.nw_t[pi] ? P.nw_t[pi] : P.NW;
   const int form = pi == 1 ? P.form_t : 0;
+  // the names are those of the kernel symbols (k_gemv_wide4 has no type parameter)
   PROF(kname(P.G > 0 ? "k_gemv_narrow" : (form == 1 ? "k_gemv_wide4" : "k_gemv_wide"),
-             std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
-                 (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : NWsel)),
+             (form == 1 ? std::string() : std::string(tname<T>()) + ", ") + std::to_string(MODE) +
+                 ", " + (ADD ? "true" : "false") + ", " + std::to_string(P.G > 0 ? P.G : NWsel)),
        sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
        s);
   if (P.G > 0) {
@@ -1632,7 +1633,8 @@ void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t 
   DPrec<T>& P = prec<T>(L);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
   if (L.fuse_ata) {
-    PROF(kname("k_bata", std::string(tname<T>()) + ", " + std::to_string(NB)),
+    PROF(kname("k_bata", std::string(tname<T>()) + ", " + std::to_string(NB) + ", " +
+                             std::to_string(L.ata_me) + ", 4"),
          2 * L.nnz * (sizeof(T) + 4) + 8 * (L.n + L.nrows + 2) + sizeof(T) * 3 * L.n * NB, s);
     if (L.ata_me == 8)
       KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bata<T, NB, 8, 4>, L.n, L.gt_ptr,
@@ -1826,7 +1828,7 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
   if (L.fuse_ata) {
     {
-      PROF(kname("k_bcg_apq1", std::to_string(NB)),
+      PROF(kname("k_bcg_apq1", std::to_string(NB) + ", " + std::to_string(L.ata_me) + ", 4"),
            2 * L.nnz * 12 + 8 * (L.n + L.nrows + 2) + 8 * 3 * L.n * NB, s);
       if (L.ata_me == 8)
         KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq1<NB, 8, 4>, L.n, L.gt_ptr, L.gt_col,

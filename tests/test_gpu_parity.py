@@ -310,6 +310,30 @@ def test_graph_replay_equals_eager(rot_tail, prec):
         s.set_precision(L.FP64)
 
 
+def test_more_than_one_batch(rot):
+    """70 right-hand sides are solved as a block of 64 and a block of 6 (both
+    precisions); every column reaches the tolerance, and in FP64 equals its
+    single-vector solve at a fixed iteration count."""
+    p, H, s = rot
+    B = np.stack([P.rhs_uniform(p.n, 700 + j) for j in range(70)])
+    dB = dvec(B)
+    try:
+        for prec in (L.FP64, L.MIXED):
+            s.set_precision(prec)
+            X, st = s.solve(dB, tol=1e-8)
+            Xh = host(X)
+            for j in (0, 31, 63, 64, 69):
+                r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
+                assert st[j]["converged"] == 1 and r <= 1.05e-8, (prec, j, r)
+        s.set_precision(L.FP64)
+        X, _ = s.solve(dB, tol=0.0, maxit=6)
+        for j in (0, 63, 64, 69):
+            x1, _ = s.solve(dB[j], tol=0.0, maxit=6)
+            assert rel(host(X[j]), host(x1)) <= 1e-10, j
+    finally:
+        s.set_precision(L.FP64)
+
+
 def test_batched_edge_columns(cfg1):
     """A zero column converges at once without disturbing the others; a
     single-level hierarchy works in the batched path."""
