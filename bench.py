@@ -52,32 +52,27 @@ print(json.dumps(dict(t_setup=t_setup, t_sample=t, iters={iters})))
     return [sys.executable, "-c", code]
 
 
-KERNEL_SOURCES = ("paper_2601_04112_amd/csrc/kernels.hpp",
-                  "paper_2601_04112_amd/csrc/kernels_batched.hpp")
-
-
-def kernel_source_hash() -> str:
+def source_hash(rel_path: str) -> str:
+    """First 16 hex digits of the SHA-256 of a repository file."""
     import hashlib
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    with open(os.path.join(ROOT, rel_path), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
 def measured_traffic(kernel: str):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (profiles/*_traffic.md: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
     the counters' reading for a plain streaming kernel of known size), or
-    None when no summary covers this kernel or the kernel sources changed
-    since the counters were taken."""
+    None when no summary covers this kernel or the source file that defines
+    it changed since the counters were taken."""
     import glob
     for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.md"))):
         txt = open(f).read()
         if "```json" not in txt:
             continue
         rec = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
-        if rec.get("kernel") == kernel and rec.get("source_sha256") == kernel_source_hash():
+        if (rec.get("kernel") == kernel and rec.get("source_file")
+                and rec.get("source_sha256") == source_hash(rec["source_file"])):
             return rec["traffic_bytes_per_launch"]
     return None
 

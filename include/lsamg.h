@@ -241,12 +241,17 @@ enum {
                              from a HIP graph of kernel nodes built on first use (one per
                              precision and batch width; not while kernel timing
                              is on); 0: kernels launched one by one             */
-  LSAMG_OPT_MFMA_TILE = 3 /* 0 (default): the matrix-core tile shapes are
+  LSAMG_OPT_MFMA_TILE = 3, /* 0 (default): the matrix-core tile shapes are
                              autotuned; 100*rt + 10*u + split fixes them for every
                              operator instead: rt in {1,2,4} row tiles of 16 per
                              task, u in {2,8} loop steps loaded together, split in
                              {1,2,4,8} loop ranges per task (reduced to 1 where
                              the partial-sum buffer is too small)               */
+  LSAMG_OPT_ONEPASS_ATA = 4 /* 1 (default): where the rows of G are short (the
+                             finest level of a finite-difference G), the
+                             multi-right-hand-side G^T (G X) recomputes each row
+                             of G per unknown instead of storing G X; 0: two
+                             passes through G X                                 */
 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1

@@ -595,8 +595,13 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq(int64_t n, const int64_t* __
   double v = 0;
   for (int64_t d = wave_row<NB>((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / NB); d < n;
        d += (int64_t)gridDim.x * (kBlock / NB)) {
-    double s = 0;
-    for (int64_t e = ptr[d]; e < ptr[d + 1]; ++e) s += val[e] * Y[(int64_t)col[e] * NB + j];
+    double s;
+    if constexpr (NB == 64) {
+      s = row_dot64<double>(ptr[d], ptr[d + 1], col, val, Y, j);
+    } else {
+      s = 0;
+      for (int64_t e = ptr[d]; e < ptr[d + 1]; ++e) s += val[e] * Y[(int64_t)col[e] * NB + j];
+    }
     Q[d * NB + j] = s;
     v += s * P[d * NB + j];
   }

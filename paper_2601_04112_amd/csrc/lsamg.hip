@@ -110,7 +110,8 @@ struct DLevel {
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
   bool tail = false;      // V-cycle from here down applied as the dense matrix Ainv
-  bool fuse_ata = false;  // rows of G short enough for the one-pass batched G^T G (k_bata)
+  bool fuse_ata = false;  // one-pass batched G^T G (k_bata, k_bcg_apq1) in use
+  bool fuse_ok = false;   // rows of G short enough for it
   int nT = 0;             // 64-row tiles per side of the packed dense operator
   int ata_me = 8;         // k_bata: most rows of G per unknown (8 or 16; rows <= 4 entries)
   int lanes_g = 1, lanes_gt = 1;
@@ -544,7 +545,8 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     for (int64_t j = 0; j < D.n; ++j) tmax = std::max(tmax, tp[j + 1] - tp[j]);
     // recomputing each row of G per touching unknown costs sum_r len(r)^2
     // gathers: worth it only for short rows (finite-difference G)
-    D.fuse_ata = finest && rmax <= 4 && tmax <= 16;
+    D.fuse_ok = finest && rmax <= 4 && tmax <= 16;
+    D.fuse_ata = D.fuse_ok;
     D.ata_me = tmax <= 8 ? 8 : 16;
   }
   D.lanes_g = lanes_for((double)D.nnz / std::max<int64_t>(1, D.nrows));
@@ -1561,7 +1563,7 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
 template <int MODE, bool ADD, int NB>
 void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
              const int64_t* cpos, const float* tb, const float* M, const float* in, float* out,
-             float* part, int64_t part_cap, hipStream_t s) {
+             float* part, int64_t part_cap, hipStream_t s, double* flush, int64_t flush_n) {
   if (P.nagg == 0 || P.hlj.empty()) return;
   const int ljmax = *std::max_element(P.hlj.begin(), P.hlj.end());
   const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
@@ -1600,14 +1602,21 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
     try {
       bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
       for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
-        HIP_OK(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r)
+        float tot = 0.f;
+        for (int r = 0; r < 3; ++r) {
+          // in a V-cycle the operator's matrix arrives from HBM, not from the
+          // last-level cache: evict it first when a flush buffer is given
+          if (flush)
+            KLAUNCH0(nblocks(flush_n), dev::kBlock, 0, s, dev::k_fill, flush_n, 0.0, flush);
+          HIP_OK(hipEventRecord(e0, s));
           bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
-        HIP_OK(hipEventRecord(e1, s));
-        HIP_OK(hipEventSynchronize(e1));
-        float t = 0.f;
-        HIP_OK(hipEventElapsedTime(&t, e0, e1));
-        ms = std::min(ms, t);
+          HIP_OK(hipEventRecord(e1, s));
+          HIP_OK(hipEventSynchronize(e1));
+          float t = 0.f;
+          HIP_OK(hipEventElapsedTime(&t, e0, e1));
+          tot += t;
+        }
+        ms = std::min(ms, tot);
       }
     } catch (...) {
       mm_free(mm);
@@ -1724,28 +1733,40 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
       if (l > 0) cap = std::max<int64_t>(cap, 4 * std::max(L.n, L.ntb) * NB);
     }
     float* part = cap > 0 ? h->alloc<float>((size_t)cap) : nullptr;
+    // 512 MiB written between timed launches evicts the 256 MiB last-level cache
+    struct Flush {
+      double* p = nullptr;
+      ~Flush() {
+        if (p) (void)hipFree(p);
+      }
+    } fl;
+    const int64_t flush_n = (int64_t)64 << 20;
+    if (hipMalloc((void**)&fl.p, (size_t)flush_n * sizeof(double)) != hipSuccess) {
+      fl.p = nullptr;                      // no room: time without evicting
+      (void)hipGetLastError();
+    }
     for (size_t l = 0; l < h->L.size(); ++l) {
       DLevel& L = h->L[l];
       auto& B = h->BL[l];
       if (L.coarsest || L.tail) {
         mm_tune<dev::IN_DIRECT, false, NB>(h, L.dense, nullptr, nullptr, nullptr, nullptr,
-                                           L.f.Ainv, B.fb, B.fx, part, cap, s);
+                                           L.f.Ainv, B.fb, B.fx, part, cap, s, fl.p, flush_n);
         break;
       }
       DLevel& C = h->L[l + 1];
       auto& BC = h->BL[l + 1];
       mm_tune<dev::IN_GATHER, false, NB>(h, L.ras, L.oidx, nullptr, nullptr, nullptr, L.f.Zc,
-                                         B.fb, B.fx, part, cap, s);
+                                         B.fb, B.fx, part, cap, s, fl.p, flush_n);
       mm_tune<dev::IN_DIRECT, false, NB>(h, L.rst, nullptr, nullptr, nullptr, nullptr, L.f.Zh,
-                                         B.fr, BC.fb, part, cap, s);
+                                         B.fr, BC.fb, part, cap, s, fl.p, flush_n);
       if (C.coarsest || C.tail)
         mm_tune<dev::IN_DIRECT, true, NB>(h, L.pro, nullptr, nullptr, nullptr, nullptr, L.f.ZhT,
-                                          BC.fx, B.fx, part, cap, s);
+                                          BC.fx, B.fx, part, cap, s, fl.p, flush_n);
       else
         mm_tune<dev::IN_TB, true, NB>(h, L.pro, nullptr, C.cptr, C.cpos, BC.ftb, L.f.ZhT, BC.fx,
-                                      B.fx, part, cap, s);
+                                      B.fx, part, cap, s, fl.p, flush_n);
       mm_tune<dev::IN_DIRECT, false, NB>(h, L.rast, nullptr, nullptr, nullptr, nullptr, L.f.Zr,
-                                         B.fr, B.ftb, part, cap, s);
+                                         B.fr, B.ftb, part, cap, s, fl.p, flush_n);
     }
     HIP_OK(hipStreamSynchronize(s));
     h->mm_tuned = true;
@@ -2268,6 +2289,9 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
   } else if (opt == LSAMG_OPT_GRAPH) {
     h->use_graphs = value != 0;
+  } else if (opt == LSAMG_OPT_ONEPASS_ATA) {
+    for (auto& D : h->L) D.fuse_ata = value != 0 && D.fuse_ok;
+    h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_MFMA_TILE) {
     const int64_t rt = value / 100, u = (value / 10) % 10, sp = value % 10;
     if (value != 0 && (value >= 1000 || (rt != 1 && rt != 2 && rt != 4) || (u != 2 && u != 8) ||

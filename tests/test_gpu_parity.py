@@ -310,6 +310,31 @@ def test_graph_replay_equals_eager(rot_tail, prec):
         s.set_precision(L.FP64)
 
 
+def test_batched_two_pass_apply(rot):
+    """With the one-pass finest-level G^T (G X) switched off (two passes
+    through G X), a 64-column FP64 batch still equals the single-vector
+    solves at a fixed iteration count, and the mixed batch converges."""
+    p, H, s = rot
+    B = np.stack([P.rhs_uniform(p.n, 800 + j) for j in range(64)])
+    dB = dvec(B)
+    try:
+        s.set_option(L.OPT_ONEPASS_ATA, 0)
+        s.set_precision(L.FP64)
+        X, _ = s.solve(dB, tol=0.0, maxit=8)
+        for j in (0, 17, 63):
+            x1, _ = s.solve(dB[j], tol=0.0, maxit=8)
+            assert rel(host(X[j]), host(x1)) <= 1e-10, j
+        s.set_precision(L.MIXED)
+        X, st = s.solve(dB, tol=1e-8)
+        Xh = host(X)
+        for j in (0, 31, 63):
+            r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
+            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+    finally:
+        s.set_option(L.OPT_ONEPASS_ATA, 1)
+        s.set_precision(L.FP64)
+
+
 def test_more_than_one_batch(rot):
     """70 right-hand sides are solved as a block of 64 and a block of 6 (both
     precisions); every column reaches the tolerance, and in FP64 equals its
