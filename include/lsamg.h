@@ -247,11 +247,10 @@ enum {
                              task, u in {2,8} loop steps loaded together, split in
                              {1,2,4,8} loop ranges per task (reduced to 1 where
                              the partial-sum buffer is too small)               */
-  LSAMG_OPT_ONEPASS_ATA = 4 /* 1 (default): where the rows of G are short (the
-                             finest level of a finite-difference G), the
-                             multi-right-hand-side G^T (G X) recomputes each row
-                             of G per unknown instead of storing G X; 0: two
-                             passes through G X                                 */
+  LSAMG_OPT_ONEPASS_ATA = 4 /* 1 (default): where the rows of G are short (a
+                             finite-difference G), the FP64 A-apply G^T (G P) of
+                             the multi-right-hand-side CG recomputes each row of G
+                             per unknown instead of storing G P; 0: two passes   */
 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1

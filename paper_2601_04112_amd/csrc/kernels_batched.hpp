@@ -163,13 +163,79 @@ __global__ void __launch_bounds__(kBlock) k_bresid_t(int64_t n, const int64_t* _
   R[d * NB + j] = B ? B[d * NB + j] - s : s;
 }
 
-// R = B - G^T (G X) in one pass, for a G whose rows are short (the finest
-// level): the work item of unknown d takes the (at most ME) rows of G that
-// touch d (its row of G^T) and recomputes each y_r = g_r . X (rows of at most
-// MF entries) from cached entries, so G X is never written to memory.  All
-// indices of one level of the chain (G^T entries, row pointers, row entries)
-// are loaded before the next level, so the gathers of every row are in
-// flight together.  B == nullptr gives R = G^T G X.
+// Y[r] = B[r] - sum_e val[e] X[col[e]] (B == nullptr: Y[r] = the sum) for
+// NB = 64 and rows of a few entries: a wavefront takes rpw consecutive rows,
+// whose entries are one contiguous CSR range; the lanes load 64 entries of it
+// at a time (indices and values, one vector load each) and the row pointers
+// of the wave's rows, the wavefront issues 16 gathers, then walks the
+// entries in order, writing each row as soon as its last entry is added
+// (row boundaries are wave-uniform, so the walk has no divergence).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bspmm64(int64_t nrows, int rpw,
+                                                    const int64_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ col,
+                                                    const T* __restrict__ val,
+                                                    const T* __restrict__ X,
+                                                    const T* __restrict__ B,
+                                                    T* __restrict__ Y) {
+  constexpr int U = 16;
+  const int lane = threadIdx.x & 63;
+  const int64_t w = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)__builtin_amdgcn_readfirstlane((int)(w * rpw));
+  if (r0 >= nrows) return;
+  const int nr = (int)(nrows - r0 < rpw ? nrows - r0 : rpw);       // 1 .. rpw <= 63
+  // lane k (k <= nr) holds ptr[r0 + k]
+  const int64_t pk = ptr[r0 + (lane <= nr ? lane : nr)];
+  const int plo = (int)(pk & 0xffffffff), phi = (int)(pk >> 32);
+  auto rowptr = [&](int k) -> int64_t {
+    return ((int64_t)__builtin_amdgcn_readlane(phi, k) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane(plo, k);
+  };
+  const int64_t eb = rowptr(0), ee = rowptr(nr);
+  int k = 0;                          // current row r0 + k
+  int64_t rend = rowptr(1);
+  T acc = 0;
+  for (int64_t b = eb; b < ee; b += 64) {
+    const int cnt = (int)(ee - b < 64 ? ee - b : 64);
+    const int64_t f = b + (lane < cnt ? lane : cnt - 1);
+    const int32_t c = col[f];
+    const T v = lane < cnt ? val[f] : T(0);
+    for (int L = 0; L < cnt; L += U) {
+      T x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int q = L + u < cnt ? L + u : cnt - 1;
+        x[u] = X[(int64_t)lane_val(c, q) * 64 + lane];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (L + u >= cnt) break;
+        const int64_t e = b + L + u;
+        while (e >= rend) {           // finished rows (empty rows included)
+          const int64_t r = r0 + k;
+          Y[r * 64 + lane] = B ? B[r * 64 + lane] - acc : acc;
+          acc = 0;
+          ++k;
+          rend = rowptr(k + 1);
+        }
+        acc += lane_val(v, L + u) * x[u];
+      }
+    }
+  }
+  for (; k < nr; ++k) {               // the last row, and trailing empty rows
+    const int64_t r = r0 + k;
+    Y[r * 64 + lane] = B ? B[r * 64 + lane] - acc : acc;
+    acc = 0;
+  }
+}
+
+// One row of A = G^T G applied to NB interleaved columns (column j) at
+// unknown d, for a G whose rows are short (the finest level): the (at most
+// ME) rows of G that touch d (its row of G^T) are recomputed, y_r = g_r . X
+// (at most MF entries each) from cached entries, so G X is never written to
+// memory.  All indices of one level of the chain (G^T entries, row
+// pointers, row entries) are loaded before the next level, so the gathers of
+// every row are in flight together.
 template <typename T, int NB, int ME, int MF>
 __device__ __forceinline__ T ata_row(int64_t d, const int64_t* __restrict__ gt_ptr,
                                      const int32_t* __restrict__ gt_col,
@@ -261,26 +327,6 @@ __device__ __forceinline__ T ata_row64(int64_t d, const int64_t* __restrict__ gt
   return acc;
 }
 
-template <typename T, int NB, int ME, int MF>
-__global__ void __launch_bounds__(kBlock) k_bata(int64_t n, const int64_t* __restrict__ gt_ptr,
-                                                 const int32_t* __restrict__ gt_col,
-                                                 const T* __restrict__ gt_val,
-                                                 const int64_t* __restrict__ g_ptr,
-                                                 const int32_t* __restrict__ g_col,
-                                                 const T* __restrict__ g_val,
-                                                 const T* __restrict__ X, const T* __restrict__ B,
-                                                 T* __restrict__ R) {
-  const int64_t gid = xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x;
-  const int64_t d = wave_row<NB>(gid / NB);
-  const int j = (int)(gid % NB);
-  if (d >= n) return;
-  T acc;
-  if constexpr (NB == 64)
-    acc = ata_row64<T, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
-  else
-    acc = ata_row<T, NB, ME, MF>(d, gt_ptr, gt_col, gt_val, g_ptr, g_col, g_val, X, j);
-  R[d * NB + j] = B ? B[d * NB + j] - acc : acc;
-}
 
 // Batched form of the aggregate GEMV family (see k_gemv_*):// Batched form of the aggregate GEMV family (see k_gemv_*):
 //   OUT[obase_a + jj][:] (=|+=) sum_l M_a[l][jj] * IN_a[l][:]
@@ -608,7 +654,8 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq(int64_t n, const int64_t* __
   bwrite_parts<NB>(v, part);
 }
 
-// Q = G^T (G P) in one pass (as k_bata) and partials of P . Q per column
+// Q = G^T (G P) in one pass (rows of G recomputed, ata_row) and partials of
+// P . Q per column
 template <int NB, int ME, int MF>
 __global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* __restrict__ gt_ptr,
                                                      const int32_t* __restrict__ gt_col,

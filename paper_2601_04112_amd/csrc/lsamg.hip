@@ -110,10 +110,10 @@ struct DLevel {
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
   bool tail = false;      // V-cycle from here down applied as the dense matrix Ainv
-  bool fuse_ata = false;  // one-pass batched G^T G (k_bata, k_bcg_apq1) in use
+  bool fuse_ata = false;  // one-pass FP64 G^T G of the multi-right-hand-side CG (k_bcg_apq1) in use
   bool fuse_ok = false;   // rows of G short enough for it
   int nT = 0;             // 64-row tiles per side of the packed dense operator
-  int ata_me = 8;         // k_bata: most rows of G per unknown (8 or 16; rows <= 4 entries)
+  int ata_me = 8;         // k_bcg_apq1: most rows of G per unknown (8 or 16; rows <= 4 entries)
   int lanes_g = 1, lanes_gt = 1;
   int max_nO = 0, max_nw = 0, max_k = 0;
   int64_t* g_ptr = nullptr;
@@ -1637,35 +1637,49 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
   P.mm.part = part;
 }
 
+// Rows per wavefront of k_bspmm64: about 48 entries per wave; 0 when the
+// rows are long enough for one row per wave (k_bspmv / k_bresid_t).
+int rows_per_wave(int64_t nnz, int64_t rows) {
+  const int64_t avg = std::max<int64_t>(1, nnz / std::max<int64_t>(1, rows));
+  const int rpw = (int)std::min<int64_t>(16, std::max<int64_t>(1, 48 / avg));
+  return rpw >= 2 ? rpw : 0;
+}
+
 template <typename T, int NB>
 void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
-  if (L.fuse_ata) {
-    PROF(kname("k_bata", std::string(tname<T>()) + ", " + std::to_string(NB) + ", " +
-                             std::to_string(L.ata_me) + ", 4"),
-         2 * L.nnz * (sizeof(T) + 4) + 8 * (L.n + L.nrows + 2) + sizeof(T) * 3 * L.n * NB, s);
-    if (L.ata_me == 8)
-      KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bata<T, NB, 8, 4>, L.n, L.gt_ptr,
-              L.gt_col, P.gt_val, L.g_ptr, L.g_col, P.g_val, X, B, R);
-    else
-      KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bata<T, NB, 16, 4>, L.n, L.gt_ptr,
-              L.gt_col, P.gt_val, L.g_ptr, L.g_col, P.g_val, X, B, R);
+  // each pass: several short rows per wavefront (k_bspmm64), or one row per
+  // wavefront for long rows
+  const int rpw_g = NB == 64 ? rows_per_wave(L.nnz, L.nrows) : 0;
+  const int rpw_t = NB == 64 ? rows_per_wave(L.nnz, L.n) : 0;
+  if (rpw_g > 0) {
+    PROF(kname("k_bspmm64", tname<T>()),
+         L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
+    KLAUNCH((unsigned)((L.nrows + 4 * rpw_g - 1) / (4 * rpw_g)), dev::kBlock, 0, s,
+            dev::k_bspmm64<T>, L.nrows, rpw_g, L.g_ptr, L.g_col, P.g_val, X, (const T*)nullptr,
+            V.y);
     LAUNCH_OK();
-    return;
-  }
-  {
+  } else {
     PROF(kname("k_bspmv", std::string(tname<T>()) + ", " + std::to_string(NB)),
          L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
     KLAUNCH(nblocks(L.nrows * NB), dev::kBlock, 0, s, dev::k_bspmv<T, NB>, L.nrows, L.g_ptr,
             L.g_col, P.g_val, X, V.y);
     LAUNCH_OK();
   }
-  PROF(kname("k_bresid_t", std::string(tname<T>()) + ", " + std::to_string(NB)),
-       L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
-  KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bresid_t<T, NB>, L.n, L.gt_ptr, L.gt_col,
-          P.gt_val, (const T*)V.y, B, R);
-  LAUNCH_OK();
+  if (rpw_t > 0) {
+    PROF(kname("k_bspmm64", tname<T>()),
+         L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
+    KLAUNCH((unsigned)((L.n + 4 * rpw_t - 1) / (4 * rpw_t)), dev::kBlock, 0, s,
+            dev::k_bspmm64<T>, L.n, rpw_t, L.gt_ptr, L.gt_col, P.gt_val, (const T*)V.y, B, R);
+    LAUNCH_OK();
+  } else {
+    PROF(kname("k_bresid_t", std::string(tname<T>()) + ", " + std::to_string(NB)),
+         L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
+    KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bresid_t<T, NB>, L.n, L.gt_ptr,
+            L.gt_col, P.gt_val, (const T*)V.y, B, R);
+    LAUNCH_OK();
+  }
 }
 
 // X = B_l(B) for NB interleaved right-hand sides (see vcycle)
@@ -1862,7 +1876,15 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
     bsum<NB>(pq_part, pq, s);
     return;
   }
-  {
+  const int rpw_g = NB == 64 ? rows_per_wave(L.nnz, L.nrows) : 0;
+  if (rpw_g > 0) {
+    PROF(kname("k_bspmm64", "double"), L.nnz * 12 + 8 * (L.nrows + 1) + 8 * (L.n + L.nrows) * NB,
+         s);
+    KLAUNCH((unsigned)((L.nrows + 4 * rpw_g - 1) / (4 * rpw_g)), dev::kBlock, 0, s,
+            dev::k_bspmm64<double>, L.nrows, rpw_g, L.g_ptr, L.g_col, L.d.g_val, Pv,
+            (const double*)nullptr, V.y);
+    LAUNCH_OK();
+  } else {
     PROF(kname("k_bspmv", std::string("double, ") + std::to_string(NB)),
          L.nnz * 12 + 8 * (L.nrows + 1) + 8 * (L.n + L.nrows) * NB, s);
     KLAUNCH(nblocks(L.nrows * NB), dev::kBlock, 0, s, dev::k_bspmv<double, NB>, L.nrows, L.g_ptr,

@@ -311,9 +311,9 @@ def test_graph_replay_equals_eager(rot_tail, prec):
 
 
 def test_batched_two_pass_apply(rot):
-    """With the one-pass finest-level G^T (G X) switched off (two passes
-    through G X), a 64-column FP64 batch still equals the single-vector
-    solves at a fixed iteration count, and the mixed batch converges."""
+    """With the one-pass FP64 G^T (G P) of the batched CG switched off (two
+    passes through G P), a 64-column FP64 batch still equals the single-
+    vector solves at a fixed iteration count, and the mixed batch converges."""
     p, H, s = rot
     B = np.stack([P.rhs_uniform(p.n, 800 + j) for j in range(64)])
     dB = dvec(B)
