@@ -247,14 +247,23 @@ enum {
                              task, u in {2,8} loop steps loaded together, split in
                              {1,2,4,8} loop ranges per task (reduced to 1 where
                              the partial-sum buffer is too small)               */
-  LSAMG_OPT_ONEPASS_ATA = 4 /* 1 (default): where the rows of G are short (a
+  LSAMG_OPT_ONEPASS_ATA = 4, /* 1 (default): where the rows of G are short (a
                              finite-difference G), the FP64 A-apply G^T (G P) of
                              the multi-right-hand-side CG recomputes each row of G
                              per unknown instead of storing G P; 0: two passes   */
+  LSAMG_OPT_DENSE_SPLIT = 5 /* 0 (default): the FP32 dense level operator of a
+                             batch of 64 columns runs as the LDS-staged matrix-core
+                             GEMM or as the per-task tiles of the other operators,
+                             whichever the autotuner times faster (the latter only
+                             while LSAMG_OPT_MFMA_TILE fixes the tiles); 1..16: the
+                             LDS-staged GEMM with that many loop ranges (fewer
+                             where the partial-sum buffer is too small); 17: never
+                             the LDS-staged GEMM                                 */
 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
- * except for LSAMG_OPT_MFMA_TILE.  EINVAL on an unknown option or value. */
+ * except for LSAMG_OPT_MFMA_TILE and LSAMG_OPT_DENSE_SPLIT.  EINVAL on an
+ * unknown option or value. */
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
 
 /* Y = B X: one V-cycle from zero (the preconditioner of lsamg_solve, sec.

@@ -546,6 +546,103 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
   }
 }
 
+// Dense level operator on 64 right-hand sides (FP32 MFMA): OUT = M IN with M
+// n x n stored row-major with a padded row stride ld (a multiple of 4,
+// padding zero; k_pad_rows makes it), and IN, OUT interleaved n x 64.  A workgroup computes
+// a 64-row x 64-column output tile over the loop range [k0, k1) of its split
+// (blockIdx.y); its four waves take 16 rows each.  The loop runs in chunks of
+// KC: the KC input rows of a chunk are staged once in LDS for all four waves,
+// and each lane reads KC/4 entries of its own matrix row with 16-byte loads:
+// load v of lane group g takes loop indices kb + 16 v + 4 g + e (e < 4), so
+// the four lane groups of a row read 64 contiguous bytes per load and a
+// wave streams whole row segments of M.  MFMA step 4 v + e takes those four
+// loop indices (one per lane group).  The next chunk's loads are
+// issued before the current chunk's MFMAs.  Columns 4i+q of a 16-column tile
+// q sit in lane i, as in k_bmm.  Splits > 1 write partial sums to
+// part[split][row][:] for k_bmm_reduce (an empty loop range writes zeros).
+template <int KC>
+__global__ void __launch_bounds__(kBlock) k_dense_mm64(int64_t n, int64_t ld, int kchunk,
+                                                       const float* __restrict__ M,
+                                                       const float* __restrict__ in,
+                                                       float* __restrict__ out,
+                                                       float* __restrict__ part) {
+  static_assert(KC % 32 == 0, "chunks of 32 rows");
+  constexpr int SB = 64 + 4;                 // LDS row stride (words)
+  constexpr int KL = KC / 4;                 // loop indices per lane group and chunk
+  constexpr int SV = KC / 16;                // 16-byte staging loads per thread
+  __shared__ __attribute__((aligned(16))) float sB[2][KC * SB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int split = blockIdx.y;
+  const int64_t k0 = (int64_t)split * kchunk;
+  const int64_t k1 = k0 + kchunk < n ? k0 + kchunk : n;
+  const int64_t jr = row0 + i;               // this lane's matrix row (A operand row)
+  const float* __restrict__ mrow_p = M + (jr < n ? jr : 0) * ld;
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[4] = {zero, zero, zero, zero};
+  // staging: thread t moves input row kb + (t / 16) + 16 v, columns 4 (t % 16) .. +3
+  const int sr = threadIdx.x >> 4, sc = 4 * (threadIdx.x & 15);
+  f32x4 bst[SV], am[KL / 4];
+  auto load_chunk = [&](int64_t kb) {
+#pragma unroll
+    for (int v = 0; v < SV; ++v) {
+      const int64_t r = kb + sr + 16 * v;
+      bst[v] = r < k1 ? *(const f32x4*)(in + r * 64 + sc) : zero;
+    }
+#pragma unroll
+    for (int v = 0; v < KL / 4; ++v) {
+      // 4 entries from column c; c < ld covers them all (ld % 4 == 0), and
+      // columns >= n inside the row are the zero padding
+      const int64_t c = kb + 16 * v + 4 * g;
+      am[v] = (jr < n && c < k1) ? *(const f32x4*)(mrow_p + c) : zero;
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) load_chunk(k0);
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+    for (int v = 0; v < SV; ++v) *(f32x4*)(sB[buf] + (sr + 16 * v) * SB + sc) = bst[v];
+    f32x4 a[KL / 4];
+#pragma unroll
+    for (int v = 0; v < KL / 4; ++v) a[v] = am[v];
+    __syncthreads();
+    if (kb + KC < k1) load_chunk(kb + KC);    // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int st = 0; st < KL; ++st) {
+      const f32x4 b = *(const f32x4*)(sB[buf] + (16 * (st / 4) + 4 * g + st % 4) * SB + 4 * i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st / 4][st % 4], b[q], acc[q], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t jj = row0 + 4 * g + v;
+    if (jj >= n) continue;
+    f32x4 o;
+    o[0] = acc[0][v];
+    o[1] = acc[1][v];
+    o[2] = acc[2][v];
+    o[3] = acc[3][v];
+    float* dst = (gridDim.y > 1 ? part + (int64_t)split * n * 64 : out) + jj * 64 + 4 * i;
+    *(f32x4*)dst = o;
+  }
+}
+
+// dst[j][l] = src[l][j] (j, l < n) with row stride ld >= n, padding zero: the
+// row-major copy for k_dense_mm64 of an operator stored as the dense GEMV's
+// M (output j = sum over l of M[l][j] times input l).  Set-up only.
+__global__ void __launch_bounds__(kBlock) k_pad_rows(int64_t n, int64_t ld,
+                                                     const float* __restrict__ src,
+                                                     float* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * ld) return;
+  const int64_t j = e / ld, l = e - j * ld;
+  dst[e] = l < n ? src[l * n + j] : 0.f;
+}
+
 // out[r][:] (=|+=) sum over the S slots of part[s][r][:], in slot order
 template <bool ADD, int NB>
 __global__ void __launch_bounds__(kBlock) k_bmm_reduce(int64_t rows, int S,
@@ -681,7 +778,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* _
   bwrite_parts<NB>(v, part);
 }
 
-// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
+// alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
 // R32 = (float) R (if given); partials of R . R
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_bcg_update(int64_t n, const double* __restrict__ rz,

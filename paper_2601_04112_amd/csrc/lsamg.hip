@@ -114,6 +114,11 @@ struct DLevel {
   bool fuse_ok = false;   // rows of G short enough for it
   int nT = 0;             // 64-row tiles per side of the packed dense operator
   int ata_me = 8;         // k_bcg_apq1: most rows of G per unknown (8 or 16; rows <= 4 entries)
+  int dmm_split = 0;      // dense level, 64 columns: k_dense_mm64 loop ranges (0: bgemm)
+  int dmm_kchunk = 0;     // rows per loop range of k_dense_mm64
+  int dmm_kc = 64;        // its chunk length (32 or 64)
+  float* dmm_M = nullptr; // its padded row-major copy of the FP32 operator (batched buffers)
+  int64_t dmm_ld = 0;     // row stride of dmm_M
   int lanes_g = 1, lanes_gt = 1;
   int max_nO = 0, max_nw = 0, max_k = 0;
   int64_t* g_ptr = nullptr;
@@ -268,6 +273,7 @@ struct lsamg_handle {
   int batch_mode = 1;               // 1: nrhs > 1 solved as batches of <= 64
   bool use_mfma = true;             // FP32 batched V-cycle on the matrix cores (k_bmm)
   int mm_fixed = 0;                 // k_bmm tile shape 100*rt + 10*u + split, 0: autotune
+  int dense_split = 0;              // k_dense_mm64 loop ranges: 0 autotune, 1..16 fixed, 17 never
   bool gv_tuned[2] = {false, false}; // single-vector wide GEMV shapes tuned (double, float)
   // V-cycles replayed from HIP graphs, one per (precision, batch width)
   bool use_graphs = true;
@@ -345,8 +351,11 @@ struct lsamg_handle {
   }
   bool mm_tuned = false;             // k_bmm tile shapes chosen for the batched buffers
   void free_batched() {
-    for (auto& D : L)
+    for (auto& D : L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
+      D.dmm_split = 0;
+      D.dmm_M = nullptr;                // freed with the batched buffers below
+    }
     mm_tuned = false;
     drop_graphs(true);
     for (void* ptr : ballocs) (void)hipFree(ptr);
@@ -1561,10 +1570,10 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
 // on the operator's own matrices and buffers (one warm-up and three timed
 // launches), and the fastest is kept.
 template <int MODE, bool ADD, int NB>
-void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
+float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
              const int64_t* cpos, const float* tb, const float* M, const float* in, float* out,
              float* part, int64_t part_cap, hipStream_t s, double* flush, int64_t flush_n) {
-  if (P.nagg == 0 || P.hlj.empty()) return;
+  if (P.nagg == 0 || P.hlj.empty()) return 0.f;
   const int ljmax = *std::max_element(P.hlj.begin(), P.hlj.end());
   const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
   struct Cand {
@@ -1635,6 +1644,110 @@ void mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* c
   P.mm = mm_build(h, P, pick.rt, pick.sp, false);
   P.mm.u = pick.u;
   P.mm.part = part;
+  return best;
+}
+
+// The dense level operator on 64 columns as the LDS-staged GEMM
+// k_dense_mm64<KC> on the padded row-major copy L.dmm_M, with S loop ranges
+// of kchunk rows (S > 1: partial sums in part, then k_bmm_reduce in slot
+// order).
+void dense_mm_launch(const DLevel& L, int S, int kchunk, int KC, const float* in, float* out,
+                     float* part, hipStream_t s) {
+  const int64_t n = L.n;
+  {
+    PROF("k_dense_mm64", sizeof(float) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))),
+         s);
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)S);
+    if (KC == 64)
+      KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64<64>, n, L.dmm_ld, kchunk,
+              (const float*)L.dmm_M, in, out, part);
+    else
+      KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64<32>, n, L.dmm_ld, kchunk,
+              (const float*)L.dmm_M, in, out, part);
+    LAUNCH_OK();
+  }
+  if (S > 1) {
+    PROF(kname("k_bmm_reduce", "false, 64"), sizeof(float) * (double)n * 64 * (S + 1), s);
+    KLAUNCH(nblocks(n * 64), dev::kBlock, 0, s, dev::k_bmm_reduce<false, 64>, n, S,
+            (const float*)part, out);
+    LAUNCH_OK();
+  }
+}
+
+// Loop ranges of k_dense_mm64: kchunk rows (a multiple of its KC-row chunk)
+// per range, and the number of ranges that covers n rows.
+void dense_split_shape(int64_t n, int want, int KC, int* S, int* kchunk) {
+  int64_t kc = (n + want - 1) / want;
+  kc = (kc + KC - 1) / KC * KC;
+  *kchunk = (int)std::max<int64_t>(KC, kc);
+  *S = (int)((n + *kchunk - 1) / *kchunk);
+}
+
+// Autotuner of the dense level on 64 columns: k_dense_mm64 for both chunk
+// lengths and each loop split that fits the partial-sum buffer, timed as
+// mm_tune times k_bmm; kept if faster than the k_bmm tile shape already
+// chosen (time bmm_ms), or always when the split is fixed.  Makes the padded
+// row-major copy of the operator (with the multi-right-hand-side buffers).
+void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, float* out,
+                float* part, int64_t part_cap, hipStream_t s, double* flush, int64_t flush_n,
+                float bmm_ms) {
+  L.dmm_split = 0;
+  if (h->dense_split > 16 || (h->dense_split == 0 && h->mm_fixed > 0)) return;
+  const int64_t n = L.n;
+  if (!L.dmm_M) {
+    L.dmm_ld = (n + 3) / 4 * 4;
+    L.dmm_M = h->alloc<float>((size_t)(n * L.dmm_ld));
+    KLAUNCH0(nblocks(n * L.dmm_ld), dev::kBlock, 0, s, dev::k_pad_rows, n, L.dmm_ld, M, L.dmm_M);
+    LAUNCH_OK();
+  }
+  std::vector<int> want;
+  if (h->dense_split > 0)
+    want.push_back(h->dense_split);
+  else
+    want = {1, 2, 3, 4, 6, 8, 9, 12, 16};
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float best = h->dense_split > 0 ? 1e30f : bmm_ms;
+  try {
+    for (int KC : {32, 64}) {
+      for (int w : want) {
+        int S = 1, kc = 0;
+        dense_split_shape(n, w, KC, &S, &kc);
+        while (S > 1 && (int64_t)S * n * 64 > part_cap) dense_split_shape(n, S - 1, KC, &S, &kc);
+        if (S > 1 && !part) dense_split_shape(n, 1, KC, &S, &kc);
+        dense_mm_launch(L, S, kc, KC, in, out, part, s);
+        float ms = 1e30f;
+        for (int round = 0; round < 2; ++round) {
+          float tot = 0.f;
+          for (int r = 0; r < 3; ++r) {
+            if (flush)
+              KLAUNCH0(nblocks(flush_n), dev::kBlock, 0, s, dev::k_fill, flush_n, 0.0, flush);
+            HIP_OK(hipEventRecord(e0, s));
+            dense_mm_launch(L, S, kc, KC, in, out, part, s);
+            HIP_OK(hipEventRecord(e1, s));
+            HIP_OK(hipEventSynchronize(e1));
+            float t = 0.f;
+            HIP_OK(hipEventElapsedTime(&t, e0, e1));
+            tot += t;
+          }
+          ms = std::min(ms, tot);
+        }
+        if (ms < best) {
+          best = ms;
+          L.dmm_split = S;
+          L.dmm_kchunk = kc;
+          L.dmm_kc = KC;
+        }
+      }
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 // Rows per wavefront of k_bspmm64: about 48 entries per wave; 0 when the
@@ -1690,6 +1803,12 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
   DPrec<T>& P = prec<T>(L);
   BVec<T> V = bvec<T>(h->BL[l]);
   if (L.coarsest || L.tail) {
+    if constexpr (std::is_same<T, float>::value && NB == 64) {
+      if (L.dmm_split > 0) {
+        dense_mm_launch(L, L.dmm_split, L.dmm_kchunk, L.dmm_kc, B, X, L.dense.mm.part, s);
+        return;
+      }
+    }
     bgemm<T, dev::IN_DIRECT, false, NB>(L.dense, nullptr, nullptr, nullptr, nullptr, P.Ainv, B, X,
                                         s);
     return;
@@ -1763,8 +1882,11 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
       DLevel& L = h->L[l];
       auto& B = h->BL[l];
       if (L.coarsest || L.tail) {
-        mm_tune<dev::IN_DIRECT, false, NB>(h, L.dense, nullptr, nullptr, nullptr, nullptr,
-                                           L.f.Ainv, B.fb, B.fx, part, cap, s, fl.p, flush_n);
+        const float bmm_ms =
+            mm_tune<dev::IN_DIRECT, false, NB>(h, L.dense, nullptr, nullptr, nullptr, nullptr,
+                                               L.f.Ainv, B.fb, B.fx, part, cap, s, fl.p, flush_n);
+        if (NB == 64)
+          dense_tune(h, L, L.f.Ainv, B.fb, B.fx, part, cap, s, fl.p, flush_n, bmm_ms);
         break;
       }
       DLevel& C = h->L[l + 1];
@@ -2297,15 +2419,18 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
 }
 
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
-  if (!h || value < 0 || (opt != LSAMG_OPT_MFMA_TILE && value > 1))
+  if (!h || value < 0 || (opt == LSAMG_OPT_DENSE_SPLIT && value > 17) ||
+      (opt != LSAMG_OPT_MFMA_TILE && opt != LSAMG_OPT_DENSE_SPLIT && value > 1))
     return fail_with(LSAMG_EINVAL, "bad argument");
   if (opt == LSAMG_OPT_BATCHED) {
     h->batch_mode = (int)value;
   } else if (opt == LSAMG_OPT_MFMA) {
     h->use_mfma = value != 0;
     if (!h->use_mfma) {                 // back to k_bgemm; task lists stay until the buffers go
-      for (auto& D : h->L)
+      for (auto& D : h->L) {
         for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+        D.dmm_split = 0;
+      }
       h->mm_tuned = false;
     }
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
@@ -2320,9 +2445,19 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
                        (sp != 1 && sp != 2 && sp != 4 && sp != 8)))
       return fail_with(LSAMG_EINVAL, "bad tile shape");
     h->mm_fixed = (int)value;
-    for (auto& D : h->L)
+    for (auto& D : h->L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      D.dmm_split = 0;
+    }
     h->mm_tuned = false;                // retuned (or fixed) on the next batched solve
+    h->drop_graphs(true);
+  } else if (opt == LSAMG_OPT_DENSE_SPLIT) {
+    h->dense_split = (int)value;
+    for (auto& D : h->L) {
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      D.dmm_split = 0;
+    }
+    h->mm_tuned = false;
     h->drop_graphs(true);
   } else {
     return fail_with(LSAMG_EINVAL, "unknown option");
