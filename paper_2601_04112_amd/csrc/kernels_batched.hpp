@@ -328,7 +328,7 @@ __device__ __forceinline__ T ata_row64(int64_t d, const int64_t* __restrict__ gt
 }
 
 
-// Batched form of the aggregate GEMV family (see k_gemv_*):// Batched form of the aggregate GEMV family (see k_gemv_*):
+// Batched form of the aggregate GEMV family (see k_gemv_*):
 //   OUT[obase_a + jj][:] (=|+=) sum_l M_a[l][jj] * IN_a[l][:]
 // Task = (aggregate a, 64-wide slice j0 of its outputs) x all NB columns.
 // Thread t: output row jj = j0 + (t % 64) (lanes along the contiguous matrix

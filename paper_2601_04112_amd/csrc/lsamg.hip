@@ -113,7 +113,8 @@ struct DLevel {
   bool fuse_ata = false;  // one-pass FP64 G^T G of the multi-right-hand-side CG (k_bcg_apq1) in use
   bool fuse_ok = false;   // rows of G short enough for it
   int nT = 0;             // 64-row tiles per side of the packed dense operator
-  int ata_me = 8;         // k_bcg_apq1: most rows of G per unknown (8 or 16; rows <= 4 entries)
+  int ata_me = 8;         // k_bcg_apq1: most rows of G per unknown (6, 8 or 16)
+  int ata_mf = 4;         // k_bcg_apq1: most entries per row of G (3 or 4)
   int dmm_split = 0;      // dense level, 64 columns: k_dense_mm64 loop ranges (0: bgemm)
   int dmm_kchunk = 0;     // rows per loop range of k_dense_mm64
   int dmm_kc = 64;        // its chunk length (32 or 64)
@@ -556,7 +557,9 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     // gathers: worth it only for short rows (finite-difference G)
     D.fuse_ok = finest && rmax <= 4 && tmax <= 16;
     D.fuse_ata = D.fuse_ok;
-    D.ata_me = tmax <= 8 ? 8 : 16;
+    // the tightest compiled bounds: every gather beyond them is a wasted load
+    D.ata_me = tmax <= 6 ? 6 : tmax <= 8 ? 8 : 16;
+    D.ata_mf = rmax <= 3 ? 3 : 4;
   }
   D.lanes_g = lanes_for((double)D.nnz / std::max<int64_t>(1, D.nrows));
   D.lanes_gt = lanes_for((double)D.nnz / std::max<int64_t>(1, D.n));
@@ -1985,14 +1988,26 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
   if (L.fuse_ata) {
     {
-      PROF(kname("k_bcg_apq1", std::to_string(NB) + ", " + std::to_string(L.ata_me) + ", 4"),
+      PROF(kname("k_bcg_apq1", std::to_string(NB) + ", " + std::to_string(L.ata_me) + ", " +
+                                   std::to_string(L.ata_mf)),
            2 * L.nnz * 12 + 8 * (L.n + L.nrows + 2) + 8 * 3 * L.n * NB, s);
-      if (L.ata_me == 8)
-        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq1<NB, 8, 4>, L.n, L.gt_ptr, L.gt_col,
-                L.d.gt_val, L.g_ptr, L.g_col, L.d.g_val, Pv, Qv, pq_part);
+      auto launch = [&](auto kern) {
+        KLAUNCH(kBNP, dev::kBlock, 0, s, kern, L.n, L.gt_ptr, L.gt_col, L.d.gt_val, L.g_ptr,
+                L.g_col, L.d.g_val, Pv, Qv, pq_part);
+      };
+      const int me = L.ata_me, mf = L.ata_mf;
+      if (me == 6 && mf == 3)
+        launch(dev::k_bcg_apq1<NB, 6, 3>);
+      else if (me == 6)
+        launch(dev::k_bcg_apq1<NB, 6, 4>);
+      else if (me == 8 && mf == 3)
+        launch(dev::k_bcg_apq1<NB, 8, 3>);
+      else if (me == 8)
+        launch(dev::k_bcg_apq1<NB, 8, 4>);
+      else if (mf == 3)
+        launch(dev::k_bcg_apq1<NB, 16, 3>);
       else
-        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_apq1<NB, 16, 4>, L.n, L.gt_ptr, L.gt_col,
-                L.d.gt_val, L.g_ptr, L.g_col, L.d.g_val, Pv, Qv, pq_part);
+        launch(dev::k_bcg_apq1<NB, 16, 4>);
       LAUNCH_OK();
     }
     bsum<NB>(pq_part, pq, s);
