@@ -251,7 +251,7 @@ enum {
                              finite-difference G), the FP64 A-apply G^T (G P) of
                              the multi-right-hand-side CG recomputes each row of G
                              per unknown instead of storing G P; 0: two passes   */
-  LSAMG_OPT_DENSE_SPLIT = 5 /* 0 (default): the FP32 dense level operator of a
+  LSAMG_OPT_DENSE_SPLIT = 5, /* 0 (default): the FP32 dense level operator of a
                              batch of 64 columns runs as the LDS-staged matrix-core
                              GEMM or as the per-task tiles of the other operators,
                              whichever the autotuner times faster (the latter only
@@ -259,6 +259,11 @@ enum {
                              LDS-staged GEMM with that many loop ranges (fewer
                              where the partial-sum buffer is too small); 17: never
                              the LDS-staged GEMM                                 */
+  LSAMG_OPT_ATA_TILES = 6 /* 1 (default): on 64 columns, the finest level's
+                             G^T (G X) of the V-cycle residual and of the CG (with
+                             LSAMG_OPT_ONEPASS_ATA) runs in one pass over tiles of
+                             16 unknowns whose input rows are staged once in LDS,
+                             where G's rows are short enough; 0: the untiled forms */
 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1

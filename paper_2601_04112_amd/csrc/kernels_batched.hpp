@@ -778,6 +778,120 @@ __global__ void __launch_bounds__(kBlock) k_bcg_apq1(int64_t n, const int64_t* _
   bwrite_parts<NB>(v, part);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled one-pass G^T (G X) on 64 columns (finest level, short rows of G).
+// The unknowns are cut into tiles of TS consecutive unknowns.  For tile t the
+// host lists U_t, the unknowns that the rows of G touching the tile reach
+// (ascending), and R_t, those rows (ascending); the entries of each row of R_t
+// carry the position in U_t of their column (rli) and their value, padded to
+// MF entries with value 0, and each unknown of the tile carries the position
+// in R_t of its rows of G (drl) in the order of G^T's row and their values
+// (dw), padded to ME with value 0.  A workgroup stages the rows of X listed in
+// U_t in LDS, forms y_r = sum_q G[r][c_q] X[c_q] for the rows of R_t into
+// LDS (entries in row order), and then sum_k G[r_k][d] y_{r_k} for each
+// unknown d (rows in G^T order): the arithmetic of ata_row64, with every X
+// row read once per tile instead of once per entry that reaches it.  Each
+// wavefront loads the metadata of up to 64 entries with one vector load and
+// walks them by lane broadcast; the loads that need no tile list (the
+// unknowns' entries, B) are issued first.  The host keeps the rows of a tile
+// per wavefront within one metadata load (ceil(|R_t| / 4) * MF <= 64).
+//   EPI 0: R = B - G^T G X   (V-cycle residual)
+//   EPI 1: R = G^T G X, and partials of B . R per column (B = the CG's P)
+// LDS: (umax + rmax) * 64 * sizeof(T) bytes (dynamic).
+// ---------------------------------------------------------------------------
+struct AtaTiles {
+  const int32_t* uptr;    // [ntile + 1] offsets into ucol
+  const int32_t* ucol;    // U_t lists
+  const int32_t* rptr;    // [ntile + 1] offsets of R_t (rows of the tile order)
+  const uint16_t* rli;    // [rows * MF] position in U_t of each row entry's column
+  const uint16_t* drl;    // [n * ME] position in R_t of each unknown's rows
+  int64_t ntile;
+  int umax;               // largest |U_t| (LDS stride of the second buffer)
+};
+
+template <typename T, int TS, int ME, int MF, int EPI>
+__global__ void __launch_bounds__(kBlock) k_bata_tile(int64_t n, AtaTiles tl,
+                                                      const T* __restrict__ rv,
+                                                      const T* __restrict__ dw,
+                                                      const T* __restrict__ X,
+                                                      const T* __restrict__ B,
+                                                      T* __restrict__ R,
+                                                      double* __restrict__ part) {
+  constexpr int WPB = kBlock / 64;
+  constexpr int DPW = TS / WPB;                    // unknowns per wavefront
+  static_assert(TS % WPB == 0 && DPW * ME <= 64 && ME * MF <= 64, "one entry per lane");
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  T* sX = (T*)lds_raw;
+  T* sY = sX + (int64_t)tl.umax * 64;
+  constexpr int VPR = 64 * (int)sizeof(T) / 16;   // 16-byte pieces per row of X
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double v = 0;
+  for (int64_t t = xcd_block(blockIdx.x, gridDim.x); t < tl.ntile; t += gridDim.x) {
+    // loads that need no tile list first: this wavefront's unknowns (their
+    // G^T entries, and B)
+    const int64_t d0 = t * TS;
+    const int nd = (int)(n - d0 < TS ? n - d0 : TS);
+    const int db = w * DPW, nwd = nd - db < DPW ? (nd - db > 0 ? nd - db : 0) : DPW;
+    int lid = 0;
+    T ww = 0;
+    T bv[DPW];
+    if (nwd > 0) {
+      const int cnt = nwd * ME;
+      const int64_t e = (d0 + db) * ME + (lane < cnt ? lane : cnt - 1);
+      lid = tl.drl[e];
+      ww = dw[e];
+#pragma unroll
+      for (int u = 0; u < DPW; ++u) bv[u] = u < nwd ? B[(d0 + db + u) * 64 + lane] : T(0);
+    }
+    // the tile's lists, this wavefront's rows of R_t, and the staging of X
+    const int u0 = tl.uptr[t], nu = tl.uptr[t + 1] - u0;
+    const int r0 = tl.rptr[t], nr = tl.rptr[t + 1] - r0;
+    const int per = (nr + WPB - 1) / WPB;            // <= 64 / MF (checked by the host)
+    const int rb = w * per, nwr = nr - rb < per ? (nr - rb > 0 ? nr - rb : 0) : per;
+    int lir = 0;
+    T vv = 0;
+    if (nwr > 0) {
+      const int cnt = nwr * MF;
+      const int64_t e = (int64_t)(r0 + rb) * MF + (lane < cnt ? lane : cnt - 1);
+      lir = tl.rli[e];
+      vv = rv[e];
+    }
+    for (int e = threadIdx.x; e < nu * VPR; e += kBlock) {
+      const int row = e / VPR, pc = e - row * VPR;
+      const int64_t c = tl.ucol[u0 + row];
+      *(f32x4*)((char*)(sX + (int64_t)row * 64) + 16 * pc) =
+          *(const f32x4*)((const char*)(X + c * 64) + 16 * pc);
+    }
+    __syncthreads();
+    for (int r = 0; r < nwr; ++r) {
+      T y = 0;
+#pragma unroll
+      for (int q = 0; q < MF; ++q)
+        y += lane_val(vv, r * MF + q) * sX[(int64_t)lane_val(lir, r * MF + q) * 64 + lane];
+      sY[(int64_t)(rb + r) * 64 + lane] = y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < DPW; ++u) {
+      if (u >= nwd) break;
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < ME; ++k)
+        acc += lane_val(ww, u * ME + k) * sY[(int64_t)lane_val(lid, u * ME + k) * 64 + lane];
+      const int64_t o = (d0 + db + u) * 64 + lane;
+      if constexpr (EPI == 0) {
+        R[o] = bv[u] - acc;
+      } else {
+        R[o] = acc;
+        v += (double)acc * (double)bv[u];
+      }
+    }
+    __syncthreads();                  // LDS is refilled by the next tile
+  }
+  if constexpr (EPI == 1) bwrite_parts<64>(v, part);
+}
+
 // alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
 // R32 = (float) R (if given); partials of R . R
 template <int NB>

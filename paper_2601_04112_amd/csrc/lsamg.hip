@@ -47,6 +47,8 @@ struct DevError {
 
 #define LAUNCH_OK() HIP_OK(hipGetLastError())
 
+constexpr int kAtaTile = 16;       // unknowns per tile of k_bata_tile
+
 inline unsigned nblocks(int64_t work) {
   return (unsigned)std::max<int64_t>(1, (work + dev::kBlock - 1) / dev::kBlock);
 }
@@ -68,6 +70,8 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* y = nullptr;         // G x (length = rows of G_l)
   T* tb = nullptr;        // RAS-T staging, sum |Omega_i|
   T* stg = nullptr;       // staged G^T G x of the row-group pass (coarse levels)
+  T* trv = nullptr;       // tiled one-pass G^T G: row entry values of each tile
+  T* tdw = nullptr;       // tiled one-pass G^T G: G^T entry values per unknown
 };
 
 // Launch plan of one batched-GEMV operator on one level.
@@ -115,6 +119,10 @@ struct DLevel {
   int nT = 0;             // 64-row tiles per side of the packed dense operator
   int ata_me = 8;         // k_bcg_apq1: most rows of G per unknown (6, 8 or 16)
   int ata_mf = 4;         // k_bcg_apq1: most entries per row of G (3 or 4)
+  dev::AtaTiles at{};     // tiles of the one-pass G^T G on 64 columns (k_bata_tile)
+  int at_rmax = 0;        // largest row list of a tile
+  bool at_ok = false;     // tiles built
+  bool at_on = false;     // ... and in use (LSAMG_OPT_ATA_TILES)
   int dmm_split = 0;      // dense level, 64 columns: k_dense_mm64 loop ranges (0: bgemm)
   int dmm_kchunk = 0;     // rows per loop range of k_dense_mm64
   int dmm_kc = 64;        // its chunk length (32 or 64)
@@ -509,6 +517,72 @@ void make_dense_plan(lsamg_handle* h, DLevel& D) {
   P.task_j0 = h->upload(tj);
 }
 
+// Tiles of the one-pass G^T (G X) on 64 columns (k_bata_tile): ts = 16
+// consecutive unknowns per tile; for each tile the unknowns its rows of G
+// reach (U_t) and those rows (R_t), both ascending; per row of R_t its
+// entries in row order as (position in U_t, value), per unknown its rows in
+// G^T order as (position in R_t, value), padded with zero values to the
+// compiled bounds MF and ME.  Not built when a tile's two LDS buffers would
+// exceed 64 KB in FP64.
+void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
+                     const std::vector<int32_t>& gc, const std::vector<double>& gv,
+                     const std::vector<int64_t>& tp, const std::vector<int32_t>& tc,
+                     const std::vector<double>& tv) {
+  constexpr int TS = kAtaTile;
+  const int ME = D.ata_me, MF = D.ata_mf;
+  const int64_t n = D.n, nt = (n + TS - 1) / TS;
+  std::vector<int32_t> uptr(1, 0), ucol, rptr(1, 0);
+  std::vector<uint16_t> rli, drl((size_t)n * ME, 0);
+  std::vector<double> rvv, dwv((size_t)n * ME, 0.0);
+  std::vector<int32_t> rows, cols;
+  int umax = 0, rmax = 0;
+  auto pos = [](const std::vector<int32_t>& v, int32_t x) {
+    return (uint16_t)(std::lower_bound(v.begin(), v.end(), x) - v.begin());
+  };
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t d0 = t * TS, d1 = std::min<int64_t>(n, d0 + TS);
+    rows.clear();
+    for (int64_t d = d0; d < d1; ++d) rows.insert(rows.end(), tc.begin() + tp[d], tc.begin() + tp[d + 1]);
+    std::sort(rows.begin(), rows.end());
+    rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+    cols.clear();
+    for (int32_t r : rows) cols.insert(cols.end(), gc.begin() + gp[r], gc.begin() + gp[r + 1]);
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    umax = std::max(umax, (int)cols.size());
+    rmax = std::max(rmax, (int)rows.size());
+    // two LDS buffers within 64 KB in FP64; a wavefront's rows within one
+    // metadata load
+    if ((int64_t)(umax + rmax) * 64 * 8 > 65536 || (rmax + 3) / 4 * MF > 64) return;
+    for (int32_t r : rows)
+      for (int q = 0; q < MF; ++q) {
+        const int64_t f = gp[r] + q;
+        const bool ok = f < gp[r + 1];
+        rli.push_back(ok ? pos(cols, gc[f]) : 0);
+        rvv.push_back(ok ? gv[f] : 0.0);
+      }
+    for (int64_t d = d0; d < d1; ++d)
+      for (int k = 0; k < ME; ++k) {
+        const int64_t e = tp[d] + k;
+        if (e >= tp[d + 1]) continue;
+        drl[(size_t)d * ME + k] = pos(rows, tc[e]);
+        dwv[(size_t)d * ME + k] = tv[e];
+      }
+    ucol.insert(ucol.end(), cols.begin(), cols.end());
+    uptr.push_back((int32_t)ucol.size());
+    rptr.push_back(rptr.back() + (int32_t)rows.size());
+  }
+  D.at = dev::AtaTiles{h->upload(uptr), h->upload(ucol), h->upload(rptr), h->upload(rli),
+                       h->upload(drl), nt, umax};
+  D.at_rmax = rmax;
+  D.d.trv = h->upload_f<double>(rvv);
+  D.f.trv = h->upload_f<float>(rvv);
+  D.d.tdw = h->upload_f<double>(dwv);
+  D.f.tdw = h->upload_f<float>(dwv);
+  D.at_ok = true;
+  D.at_on = true;
+}
+
 // Build the device image of one level from the host hierarchy.
 void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   D.n = HL.n;
@@ -575,6 +649,7 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     D.d.gt_val = h->upload_f<double>(tv);
     D.f.gt_val = h->upload_f<float>(tv);
   }
+  if (finest && D.fuse_ok && !HL.coarsest) build_ata_tiles(h, D, gp, gc, gv, tp, tc, tv);
   if (!finest && !HL.coarsest) build_group_tasks(h, HL, D, gp);
   D.d.x = h->alloc<double>(D.n);
   D.d.b = h->alloc<double>(D.n);
@@ -1761,10 +1836,47 @@ int rows_per_wave(int64_t nnz, int64_t rows) {
   return rpw >= 2 ? rpw : 0;
 }
 
+// k_bata_tile on 64 columns: EPI 0 R = B - G^T G X; EPI 1 R = G^T G X and
+// partials of B . R (kBNP workgroups, as k_bsum expects)
+template <typename T, int EPI>
+void bata_tile(const DLevel& L, const T* X, const T* B, T* R, double* part, hipStream_t s) {
+  const DPrec<T>& P = prec<T>(const_cast<DLevel&>(L));
+  const size_t lds = (size_t)(L.at.umax + L.at_rmax) * 64 * sizeof(T);
+  const unsigned grid = EPI == 1 ? (unsigned)kBNP : (unsigned)L.at.ntile;
+  PROF(kname("k_bata_tile", std::string(tname<T>()) + ", " + std::to_string(L.ata_me) + ", " +
+                                std::to_string(L.ata_mf) + ", " + std::to_string(EPI)),
+       (double)sizeof(T) * L.n * 64 * 3 + (double)L.nnz * (sizeof(T) + 4) + 8.0 * (L.n + L.nrows),
+       s);
+  auto launch = [&](auto kern) {
+    KLAUNCH(grid, dev::kBlock, lds, s, kern, L.n, L.at, (const T*)P.trv, (const T*)P.tdw, X, B, R,
+            part);
+  };
+  const int me = L.ata_me, mf = L.ata_mf;
+  if (me == 6 && mf == 3)
+    launch(dev::k_bata_tile<T, kAtaTile, 6, 3, EPI>);
+  else if (me == 6)
+    launch(dev::k_bata_tile<T, kAtaTile, 6, 4, EPI>);
+  else if (me == 8 && mf == 3)
+    launch(dev::k_bata_tile<T, kAtaTile, 8, 3, EPI>);
+  else if (me == 8)
+    launch(dev::k_bata_tile<T, kAtaTile, 8, 4, EPI>);
+  else if (mf == 3)
+    launch(dev::k_bata_tile<T, kAtaTile, 16, 3, EPI>);
+  else
+    launch(dev::k_bata_tile<T, kAtaTile, 16, 4, EPI>);
+  LAUNCH_OK();
+}
+
 template <typename T, int NB>
 void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "G missing on the device"};
+  if constexpr (NB == 64) {
+    if (L.at_on) {                      // one pass, X rows staged per tile
+      bata_tile<T, 0>(L, X, B, R, nullptr, s);
+      return;
+    }
+  }
   // each pass: several short rows per wavefront (k_bspmm64), or one row per
   // wavefront for long rows
   const int rpw_g = NB == 64 ? rows_per_wave(L.nnz, L.nrows) : 0;
@@ -1986,6 +2098,13 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
   DLevel& L = h->L[0];
   BVec<double> V = bvec<double>(h->BL[0]);
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
+  if constexpr (NB == 64) {
+    if (L.fuse_ata && L.at_on) {
+      bata_tile<double, 1>(L, Pv, Pv, Qv, pq_part, s);
+      bsum<NB>(pq_part, pq, s);
+      return;
+    }
+  }
   if (L.fuse_ata) {
     {
       PROF(kname("k_bcg_apq1", std::to_string(NB) + ", " + std::to_string(L.ata_me) + ", " +
@@ -2453,6 +2572,9 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->use_graphs = value != 0;
   } else if (opt == LSAMG_OPT_ONEPASS_ATA) {
     for (auto& D : h->L) D.fuse_ata = value != 0 && D.fuse_ok;
+    h->drop_graphs(true);
+  } else if (opt == LSAMG_OPT_ATA_TILES) {
+    for (auto& D : h->L) D.at_on = value != 0 && D.at_ok;
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_MFMA_TILE) {
     const int64_t rt = value / 100, u = (value / 10) % 10, sp = value % 10;

@@ -21,6 +21,7 @@ LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
 FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
+OPT_ATA_TILES = 6
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
                -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
@@ -303,7 +304,7 @@ class Solver:
         _check(load().lsamg_set_precision(self._h, precision))
 
     def set_option(self, opt: int, value: int):
-        """OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_ONEPASS_ATA (value 0 or 1), OPT_MFMA_TILE
+        """OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_ONEPASS_ATA, OPT_ATA_TILES (value 0 or 1), OPT_MFMA_TILE
         (0: autotune, else 100*rt + 10*u + split) or OPT_DENSE_SPLIT (0: autotune,
         1..16: LDS-staged dense GEMM with that many loop ranges, 17: never)."""
         _check(load().lsamg_set_option(self._h, opt, int(value)))

@@ -363,6 +363,48 @@ def test_batched_two_pass_apply(rot):
         s.set_precision(L.FP64)
 
 
+def test_batched_tiled_ata(rot):
+    """The tiled one-pass G^T (G X) on 64 columns (k_bata_tile: residual of
+    the batched V-cycle, A-apply of the batched CG) against the untiled forms:
+    V-cycles agree to 1e-12 (FP64) and 2e-5 (FP32), FP64 solves at a fixed
+    iteration count to 1e-10, and the mixed solve reaches the tolerance; the
+    tiled kernel runs exactly when switched on."""
+    p, H, s = rot
+    B = np.stack([P.rhs_uniform(p.n, 1100 + j) for j in range(64)])
+    dB = dvec(B)
+    try:
+        for prec, tol in ((L.FP64, 1e-12), (L.MIXED, 2e-5)):
+            s.set_precision(prec)
+            out = {}
+            for on in (1, 0):
+                s.set_option(L.OPT_ATA_TILES, on)
+                s.profile(True)
+                out[on] = host(s.apply_vcycle_batch(dB))
+                names = {k["name"].split("<")[0] for k in s.profile_read()}
+                s.profile(False)
+                assert ("k_bata_tile" in names) == bool(on), (prec, on, sorted(names))
+            for j in (0, 21, 63):
+                assert rel(out[1][j], out[0][j]) <= tol, (prec, j, rel(out[1][j], out[0][j]))
+        s.set_precision(L.FP64)
+        X = {}
+        for on in (1, 0):
+            s.set_option(L.OPT_ATA_TILES, on)
+            X[on], _ = s.solve(dB, tol=0.0, maxit=8)
+        for j in (0, 40, 63):
+            assert rel(host(X[1][j]), host(X[0][j])) <= 1e-10, j
+        s.set_option(L.OPT_ATA_TILES, 1)
+        s.set_precision(L.MIXED)
+        Xm, st = s.solve(dB, tol=1e-8)
+        Xh = host(Xm)
+        for j in (0, 31, 63):
+            r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
+            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+    finally:
+        s.profile(False)
+        s.set_option(L.OPT_ATA_TILES, 1)
+        s.set_precision(L.FP64)
+
+
 def test_more_than_one_batch(rot):
     """70 right-hand sides are solved as a block of 64 and a block of 6 (both
     precisions); every column reaches the tolerance, and in FP64 equals its
