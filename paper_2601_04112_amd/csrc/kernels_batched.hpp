@@ -892,6 +892,76 @@ __global__ void __launch_bounds__(kBlock) k_bata_tile(int64_t n, AtaTiles tl,
   if constexpr (EPI == 1) bwrite_parts<64>(v, part);
 }
 
+// Single right-hand side, one pass: the CG's new direction and its A-apply.
+// Over tiles of TS consecutive unknowns (tiles and entry order as for
+// k_bata_tile): Pn = Z + beta Po (beta = rz_new / rz_old from the partials
+// of the preceding kernels, gridDim.x of them; Pn = Z when rz_old is null) is
+// formed for the tile's U_t into LDS, y_r for its rows R_t into LDS, and
+// Q[d] = sum_k G[r_k][d] y_{r_k} for its own unknowns, which also store Pn[d];
+// partials of Pn . Q per workgroup.  Pn must not alias Po (other tiles still
+// read Po for their halos).  One unknown per thread (TS = kBlock).
+// LDS: (umax + rmax) doubles (dynamic).
+template <int ME, int MF>
+__global__ void __launch_bounds__(kBlock) k_cg_tile(int64_t n, AtaTiles tl,
+                                                    const double* __restrict__ rv,
+                                                    const double* __restrict__ dw,
+                                                    const double* __restrict__ rz_new,
+                                                    const double* __restrict__ rz_old,
+                                                    const double* __restrict__ Z,
+                                                    const double* __restrict__ Po,
+                                                    double* __restrict__ Pn,
+                                                    double* __restrict__ Q,
+                                                    double* __restrict__ part) {
+  constexpr int TS = kBlock;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  double* sX = (double*)lds_raw;
+  double* sY = sX + tl.umax;
+  const int np = gridDim.x;
+  const bool first = rz_old == nullptr;
+  const double beta = first ? 0.0 : sum_parts(rz_new, np) / sum_parts(rz_old, np);
+  double v = 0;
+  for (int64_t t = xcd_block(blockIdx.x, gridDim.x); t < tl.ntile; t += gridDim.x) {
+    const int64_t d = t * TS + threadIdx.x;
+    // this thread's unknown: its entries and its new direction first
+    int li[ME];
+    double w[ME];
+    double pd = 0;
+    if (d < n) {
+#pragma unroll
+      for (int k = 0; k < ME; ++k) {
+        li[k] = tl.drl[d * ME + k];
+        w[k] = dw[d * ME + k];
+      }
+      pd = first ? Z[d] : Z[d] + beta * Po[d];
+    }
+    const int u0 = tl.uptr[t], nu = tl.uptr[t + 1] - u0;
+    const int r0 = tl.rptr[t], nr = tl.rptr[t + 1] - r0;
+    for (int e = threadIdx.x; e < nu; e += kBlock) {
+      const int64_t c = tl.ucol[u0 + e];
+      sX[e] = first ? Z[c] : Z[c] + beta * Po[c];
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nr; r += kBlock) {
+      const int64_t e0 = (int64_t)(r0 + r) * MF;
+      double y = 0;
+#pragma unroll
+      for (int q = 0; q < MF; ++q) y += rv[e0 + q] * sX[tl.rli[e0 + q]];
+      sY[r] = y;
+    }
+    __syncthreads();
+    if (d < n) {
+      double acc = 0;
+#pragma unroll
+      for (int k = 0; k < ME; ++k) acc += w[k] * sY[li[k]];
+      Q[d] = acc;
+      Pn[d] = pd;
+      v += pd * acc;
+    }
+    __syncthreads();                  // LDS is refilled by the next tile
+  }
+  write_part(v, part);
+}
+
 // alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
 // R32 = (float) R (if given); partials of R . R
 template <int NB>

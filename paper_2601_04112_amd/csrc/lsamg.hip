@@ -123,6 +123,10 @@ struct DLevel {
   int at_rmax = 0;        // largest row list of a tile
   bool at_ok = false;     // tiles built
   bool at_on = false;     // ... and in use (LSAMG_OPT_ATA_TILES)
+  dev::AtaTiles at1{};    // tiles of the single-vector CG's k_cg_tile (FP64)
+  int at1_rmax = 0;
+  double *trv1 = nullptr, *tdw1 = nullptr;
+  bool at1_ok = false, at1_on = false;
   int dmm_split = 0;      // dense level, 64 columns: k_dense_mm64 loop ranges (0: bgemm)
   int dmm_kchunk = 0;     // rows per loop range of k_dense_mm64
   int dmm_kc = 64;        // its chunk length (32 or 64)
@@ -306,6 +310,10 @@ struct lsamg_handle {
   // per-workgroup partial sums of the CG dot products (red_blocks(n) each)
   double *p_pq = nullptr, *p_rr = nullptr, *p_rz[2] = {nullptr, nullptr}, *p_tmp = nullptr;
   int red_np = 1;
+  // k_cg_tile: the direction update p = z + beta p is applied by the next
+  // A-apply, into p2 (then swapped with p); 0 none pending, 1 p = z, 2 p = z + beta p
+  double* p2 = nullptr;
+  int dir_pending = 0, dir_cur = 0;
   double* sc_host = nullptr;         // pinned
   int nparts = 1024;
   hipEvent_t ev_rr[2] = {nullptr, nullptr};
@@ -517,29 +525,37 @@ void make_dense_plan(lsamg_handle* h, DLevel& D) {
   P.task_j0 = h->upload(tj);
 }
 
-// Tiles of the one-pass G^T (G X) on 64 columns (k_bata_tile): ts = 16
-// consecutive unknowns per tile; for each tile the unknowns its rows of G
-// reach (U_t) and those rows (R_t), both ascending; per row of R_t its
-// entries in row order as (position in U_t, value), per unknown its rows in
-// G^T order as (position in R_t, value), padded with zero values to the
-// compiled bounds MF and ME.  Not built when a tile's two LDS buffers would
-// exceed 64 KB in FP64.
-void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
-                     const std::vector<int32_t>& gc, const std::vector<double>& gv,
-                     const std::vector<int64_t>& tp, const std::vector<int32_t>& tc,
-                     const std::vector<double>& tv) {
-  constexpr int TS = kAtaTile;
-  const int ME = D.ata_me, MF = D.ata_mf;
-  const int64_t n = D.n, nt = (n + TS - 1) / TS;
-  std::vector<int32_t> uptr(1, 0), ucol, rptr(1, 0);
-  std::vector<uint16_t> rli, drl((size_t)n * ME, 0);
-  std::vector<double> rvv, dwv((size_t)n * ME, 0.0);
-  std::vector<int32_t> rows, cols;
+// Tiles of the one-pass G^T (G X) (k_bata_tile on 64 columns: TS = 16; the
+// single-vector CG's k_cg_tile: TS = 256): TS consecutive unknowns per tile;
+// for each tile the unknowns its rows of G reach (U_t) and those rows (R_t),
+// both ascending; per row of R_t its entries in row order as (position in
+// U_t, value), per unknown its rows in G^T order as (position in R_t, value),
+// padded with zero values to the compiled bounds MF and ME.  Fails (false)
+// when a tile's two LDS buffers (row_bytes per staged row in FP64) would
+// exceed 64 KB, or, with wave_rows, when a wavefront's share of R_t would
+// not fit one metadata load.
+struct TileHost {
+  std::vector<int32_t> uptr{0}, ucol, rptr{0};
+  std::vector<uint16_t> rli, drl;
+  std::vector<double> rv, dw;
   int umax = 0, rmax = 0;
+  int64_t ntile = 0;
+};
+
+bool make_tiles(const DLevel& D, const std::vector<int64_t>& gp, const std::vector<int32_t>& gc,
+                const std::vector<double>& gv, const std::vector<int64_t>& tp,
+                const std::vector<int32_t>& tc, const std::vector<double>& tv, int TS,
+                int64_t row_bytes, bool wave_rows, TileHost& T) {
+  const int ME = D.ata_me, MF = D.ata_mf;
+  const int64_t n = D.n;
+  T.ntile = (n + TS - 1) / TS;
+  T.drl.assign((size_t)n * ME, 0);
+  T.dw.assign((size_t)n * ME, 0.0);
+  std::vector<int32_t> rows, cols;
   auto pos = [](const std::vector<int32_t>& v, int32_t x) {
     return (uint16_t)(std::lower_bound(v.begin(), v.end(), x) - v.begin());
   };
-  for (int64_t t = 0; t < nt; ++t) {
+  for (int64_t t = 0; t < T.ntile; ++t) {
     const int64_t d0 = t * TS, d1 = std::min<int64_t>(n, d0 + TS);
     rows.clear();
     for (int64_t d = d0; d < d1; ++d) rows.insert(rows.end(), tc.begin() + tp[d], tc.begin() + tp[d + 1]);
@@ -549,38 +565,62 @@ void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
     for (int32_t r : rows) cols.insert(cols.end(), gc.begin() + gp[r], gc.begin() + gp[r + 1]);
     std::sort(cols.begin(), cols.end());
     cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-    umax = std::max(umax, (int)cols.size());
-    rmax = std::max(rmax, (int)rows.size());
-    // two LDS buffers within 64 KB in FP64; a wavefront's rows within one
-    // metadata load
-    if ((int64_t)(umax + rmax) * 64 * 8 > 65536 || (rmax + 3) / 4 * MF > 64) return;
+    T.umax = std::max(T.umax, (int)cols.size());
+    T.rmax = std::max(T.rmax, (int)rows.size());
+    if ((int64_t)(T.umax + T.rmax) * row_bytes > 65536) return false;
+    if (wave_rows && (T.rmax + 3) / 4 * MF > 64) return false;
     for (int32_t r : rows)
       for (int q = 0; q < MF; ++q) {
         const int64_t f = gp[r] + q;
         const bool ok = f < gp[r + 1];
-        rli.push_back(ok ? pos(cols, gc[f]) : 0);
-        rvv.push_back(ok ? gv[f] : 0.0);
+        T.rli.push_back(ok ? pos(cols, gc[f]) : 0);
+        T.rv.push_back(ok ? gv[f] : 0.0);
       }
     for (int64_t d = d0; d < d1; ++d)
       for (int k = 0; k < ME; ++k) {
         const int64_t e = tp[d] + k;
         if (e >= tp[d + 1]) continue;
-        drl[(size_t)d * ME + k] = pos(rows, tc[e]);
-        dwv[(size_t)d * ME + k] = tv[e];
+        T.drl[(size_t)d * ME + k] = pos(rows, tc[e]);
+        T.dw[(size_t)d * ME + k] = tv[e];
       }
-    ucol.insert(ucol.end(), cols.begin(), cols.end());
-    uptr.push_back((int32_t)ucol.size());
-    rptr.push_back(rptr.back() + (int32_t)rows.size());
+    T.ucol.insert(T.ucol.end(), cols.begin(), cols.end());
+    T.uptr.push_back((int32_t)T.ucol.size());
+    T.rptr.push_back(T.rptr.back() + (int32_t)rows.size());
   }
-  D.at = dev::AtaTiles{h->upload(uptr), h->upload(ucol), h->upload(rptr), h->upload(rli),
-                       h->upload(drl), nt, umax};
-  D.at_rmax = rmax;
-  D.d.trv = h->upload_f<double>(rvv);
-  D.f.trv = h->upload_f<float>(rvv);
-  D.d.tdw = h->upload_f<double>(dwv);
-  D.f.tdw = h->upload_f<float>(dwv);
-  D.at_ok = true;
-  D.at_on = true;
+  return true;
+}
+
+dev::AtaTiles upload_tiles(lsamg_handle* h, const TileHost& T) {
+  return dev::AtaTiles{h->upload(T.uptr), h->upload(T.ucol), h->upload(T.rptr), h->upload(T.rli),
+                       h->upload(T.drl), T.ntile, T.umax};
+}
+
+void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
+                     const std::vector<int32_t>& gc, const std::vector<double>& gv,
+                     const std::vector<int64_t>& tp, const std::vector<int32_t>& tc,
+                     const std::vector<double>& tv) {
+  {
+    TileHost T;
+    if (make_tiles(D, gp, gc, gv, tp, tc, tv, kAtaTile, 64 * 8, true, T)) {
+      D.at = upload_tiles(h, T);
+      D.at_rmax = T.rmax;
+      D.d.trv = h->upload_f<double>(T.rv);
+      D.f.trv = h->upload_f<float>(T.rv);
+      D.d.tdw = h->upload_f<double>(T.dw);
+      D.f.tdw = h->upload_f<float>(T.dw);
+      D.at_ok = D.at_on = true;
+    }
+  }
+  {
+    TileHost T;
+    if (make_tiles(D, gp, gc, gv, tp, tc, tv, dev::kBlock, 8, false, T)) {
+      D.at1 = upload_tiles(h, T);
+      D.at1_rmax = T.rmax;
+      D.trv1 = h->upload_f<double>(T.rv);
+      D.tdw1 = h->upload_f<double>(T.dw);
+      D.at1_ok = D.at1_on = true;
+    }
+  }
 }
 
 // Build the device image of one level from the host hierarchy.
@@ -827,6 +867,7 @@ void upload(lsamg_handle* h) {
   h->r = h->alloc<double>(n);
   h->z = h->alloc<double>(n);
   h->p = h->alloc<double>(n);
+  h->p2 = h->alloc<double>(n);
   h->q = h->alloc<double>(n);
   h->bi = h->alloc<double>(n);
   h->part = h->alloc<double>(h->nparts);
@@ -1276,6 +1317,36 @@ void cg_apply(lsamg_handle* h, hipStream_t s) {
   DLevel& L = h->L[0];
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
   const int64_t n = L.n;
+  if (h->dir_pending) {                 // p = z (+ beta p) and q = A p in one pass
+    const int c = h->dir_cur;
+    const double* rz_old = h->dir_pending == 2 ? h->p_rz[1 - c] : nullptr;
+    PROF(kname("k_cg_tile", std::to_string(L.ata_me) + ", " + std::to_string(L.ata_mf)),
+         8.0 * (3 * n + (h->dir_pending == 2 ? n : 0)) + 12.0 * L.nnz + 8.0 * L.nrows + 16 * h->red_np,
+         s);
+    const size_t lds = (size_t)(L.at1.umax + L.at1_rmax) * sizeof(double);
+    auto launch = [&](auto kern) {
+      KLAUNCH(h->red_np, dev::kBlock, lds, s, kern, n, L.at1, (const double*)L.trv1,
+              (const double*)L.tdw1, (const double*)h->p_rz[c], rz_old, (const double*)h->z,
+              (const double*)h->p, h->p2, h->q, h->p_pq);
+    };
+    const int me = L.ata_me, mf = L.ata_mf;
+    if (me == 6 && mf == 3)
+      launch(dev::k_cg_tile<6, 3>);
+    else if (me == 6)
+      launch(dev::k_cg_tile<6, 4>);
+    else if (me == 8 && mf == 3)
+      launch(dev::k_cg_tile<8, 3>);
+    else if (me == 8)
+      launch(dev::k_cg_tile<8, 4>);
+    else if (mf == 3)
+      launch(dev::k_cg_tile<16, 3>);
+    else
+      launch(dev::k_cg_tile<16, 4>);
+    LAUNCH_OK();
+    std::swap(h->p, h->p2);
+    h->dir_pending = 0;
+    return;
+  }
   spmv_csr<double>(L.nrows, L.lanes_g, L.g_ptr, L.g_col, L.d.g_val, h->p, L.d.y, s, L.nnz, n);
   const unsigned g = h->red_np;
   PROF(kname("k_cg_apq", std::to_string(L.lanes_gt)),
@@ -1312,6 +1383,11 @@ void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
                                                   L0.d.tb, h->r, h->z, h->p_rz[cur]);
   }
   LAUNCH_OK();
+  if (L0.at1_on) {                      // applied by the next cg_apply (k_cg_tile)
+    h->dir_pending = first ? 1 : 2;
+    h->dir_cur = cur;
+    return;
+  }
   PROF("k_cg_dir", 24 * n + 16 * g, s);
   KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_dir, n, h->p_rz[cur], first ? nullptr : h->p_rz[1 - cur],
                                           h->z, h->p);
@@ -1386,6 +1462,7 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
       LAUNCH_OK();
     }
     gv_tune(h, s);
+    h->dir_pending = 0;
     int cur = 0;                        // p_rz[cur] holds rho of the current direction
     cg_precondition(h, s, true, cur);
     const double target = tol * nb;
@@ -2574,7 +2651,10 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     for (auto& D : h->L) D.fuse_ata = value != 0 && D.fuse_ok;
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_ATA_TILES) {
-    for (auto& D : h->L) D.at_on = value != 0 && D.at_ok;
+    for (auto& D : h->L) {
+      D.at_on = value != 0 && D.at_ok;
+      D.at1_on = value != 0 && D.at1_ok;
+    }
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_MFMA_TILE) {
     const int64_t rt = value / 100, u = (value / 10) % 10, sp = value % 10;

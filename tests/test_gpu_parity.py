@@ -405,6 +405,43 @@ def test_batched_tiled_ata(rot):
         s.set_precision(L.FP64)
 
 
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_single_cg_tile(rot, prec):
+    """The single-vector CG with its direction update fused into a tiled
+    one-pass A-apply (k_cg_tile) against the unfused kernels: equal iterates
+    to 1e-10 at a fixed iteration count (FP64 V-cycle), equal iteration
+    counts to 1e-8 with the true residual at the tolerance (both precisions),
+    and the fused kernel runs exactly when switched on."""
+    p, H, s = rot
+    b = P.rhs_uniform(p.n, 77)
+    db = dvec(b)
+    s.set_precision(prec)
+    try:
+        out, its = {}, {}
+        for on in (1, 0):
+            s.set_option(L.OPT_ATA_TILES, on)
+            s.profile(True)
+            x, st = s.solve(db, tol=1e-8)
+            names = {k["name"].split("<")[0] for k in s.profile_read()}
+            s.profile(False)
+            assert ("k_cg_tile" in names) == bool(on), (on, sorted(names))
+            assert ("k_cg_dir" in names) == (not on), (on, sorted(names))
+            out[on], its[on] = host(x), st[0]["iters"]
+            r = np.linalg.norm(b - H.levels[0].A @ out[on]) / np.linalg.norm(b)
+            assert st[0]["converged"] == 1 and r <= 1.05e-8, (on, r)
+        assert its[1] == its[0]
+        if prec == L.FP64:
+            x8 = {}
+            for on in (1, 0):
+                s.set_option(L.OPT_ATA_TILES, on)
+                x8[on], _ = s.solve(db, tol=0.0, maxit=8)
+            assert rel(host(x8[1]), host(x8[0])) <= 1e-10
+    finally:
+        s.profile(False)
+        s.set_option(L.OPT_ATA_TILES, 1)
+        s.set_precision(L.FP64)
+
+
 def test_more_than_one_batch(rot):
     """70 right-hand sides are solved as a block of 64 and a block of 6 (both
     precisions); every column reaches the tolerance, and in FP64 equals its
