@@ -276,6 +276,65 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
   }
 }
 
+// Narrow form with one aggregate per lane group (every lj_a <= G < 64): a
+// wavefront takes 64/G aggregates, lane group s owning the s-th; each lane
+// runs the whole loop over l for its output (U loads in flight), so a
+// wavefront carries 64/G aggregates' loads through each memory round trip.
+// LDS: 4 * (64/G) * (lmax + emax) * sizeof(T).
+template <typename T, int MODE, bool ADD, int G>
+__global__ void __launch_bounds__(kBlock) k_gemv_narrow_m(int64_t nagg, GemvOp op, int lmax,
+                                                          int emax, InSpec<T> spec,
+                                                          const T* __restrict__ M,
+                                                          const T* __restrict__ in,
+                                                          T* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  constexpr int S = 64 / G;
+  constexpr int U = 8;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int s = lane / G, j = lane % G;
+  const int64_t a = (xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave) * S + s;
+  const bool valid = a < nagg;
+  T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)(wave * S + s) * (lmax + emax);
+  T* pr = sv + lmax;
+  int nj = 0, nl = 0;
+  int64_t ib = 0, ld = 0;
+  const T* m = M;
+  T mv[U];
+  if (valid) {
+    nj = op.lj[a];
+    nl = op.ll[a];
+    m = M + op.moff[a] + (j < nj ? j : 0);
+    ld = mrow(nj, op.pad);
+#pragma unroll
+    for (int u = 0; u < U; ++u) mv[u] = (j < nj && u < nl) ? m[(int64_t)u * ld] : T(0);
+    ib = op.ibase[a];
+    if (MODE == IN_RESG)
+      stage_products<T, MODE>(pr, ib, nl, spec, j, G);
+    else
+      stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, j, G);
+  }
+  if (MODE == IN_RESG) {
+    __syncthreads();
+    if (valid) stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, j, G);
+  }
+  __syncthreads();
+  if (!valid || j >= nj) return;
+  T av[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) av[u] = u < nl ? mv[u] * sv[u] : T(0);
+  int l = U;
+  for (; l + U - 1 < nl; l += U) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u) * ld];
+#pragma unroll
+    for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u];
+  }
+  for (; l < nl; ++l) av[0] += m[(int64_t)l * ld] * sv[l];
+  const T acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
+  T* dst = out + op.obase[a] + j;
+  *dst = ADD ? *dst + acc : acc;
+}
+
 // Wide form: one workgroup of NW wavefronts per task (aggregate a, 64-wide
 // slice j0 of its outputs); the waves split the loop over l and their
 // partial sums are added in wave order through LDS.

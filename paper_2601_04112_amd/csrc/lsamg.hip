@@ -84,7 +84,8 @@ struct GemvPlan {
   int NW = 4;          // wide form: wavefronts per workgroup (default from the task count)
   mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
   mutable int form_t = 0;         // FP32 wide form: 0 one output per lane, 1 four (k_gemv_wide4)
-  mutable int narrow_t[2] = {1, 1};  // G > 0: narrow form kept (1) or the wide form timed faster (0)
+  mutable int narrow_t[2] = {1, 1};  // G > 0: the form timed fastest: 0 wide, 1 narrow
+                                     // (a wavefront per aggregate), 2 an aggregate per lane group
   int64_t ntask4 = 0;             // tasks (aggregate, 256-wide output slice) of k_gemv_wide4
   int32_t* task4_a = nullptr;
   int32_t* task4_j0 = nullptr;
@@ -1012,34 +1013,61 @@ void gemv_narrow_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M,
   }
 }
 
+// narrow form, an aggregate per lane group of G < 64 lanes
+template <typename T, int MODE, bool ADD>
+void gemv_narrow_m_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
+                          T* out, hipStream_t s, const ProfScope& ps_) {
+  const int S = 64 / P.G;
+  const unsigned g = (unsigned)((P.nagg + 4 * S - 1) / (4 * S));
+  const int emax = MODE == dev::IN_RESG ? P.emax : 0;
+  const size_t lds = (size_t)4 * S * (P.lmax + emax) * sizeof(T);
+  switch (P.G) {
+#define CASE(GG)                                                                              \
+  case GG:                                                                                    \
+    KLAUNCH(g, dev::kBlock, lds, s, dev::k_gemv_narrow_m<T, MODE, ADD, GG>, P.nagg, P.op, P.lmax, \
+            emax, sp, M, in, out);                                                            \
+    break;
+    CASE(1) CASE(2) CASE(4) CASE(8) CASE(16) CASE(32)
+#undef CASE
+  }
+}
+
 template <typename T, int MODE, bool ADD>
 void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, T* out,
           hipStream_t s, int64_t extra_bytes = 0) {
   const int pi = sizeof(T) == sizeof(float) ? 1 : 0;
-  // an operator with few aggregates of <= 64 outputs may run faster in the
-  // wide form (the loop split over waves) than one wavefront per four
-  // aggregates: the tuner times both
+  // operators of <= 64 outputs per aggregate: the tuner times the narrow
+  // form (a wavefront per aggregate), the narrow form with an aggregate per
+  // lane group, and, when aggregates are few, the wide form (the loop split
+  // over waves)
   const bool try_wide = P.G == 0 || P.nagg < 4096;
-  if (try_wide && P.nw_t[pi] == 0 && g_gvtune && !g_rec) {
+  if (P.nw_t[pi] == 0 && g_gvtune && !g_rec && (try_wide || P.G < 64)) {
     float best = 1e30f;
     int pick = P.NW, pick_form = 0, pick_narrow = 0;
-    if (P.G > 0) {
-      gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+    for (int nf = 1; nf <= 2 && P.G > 0; ++nf) {
+      if (nf == 2 && P.G >= 64) continue;
+      auto run = [&]() {
+        if (nf == 1)
+          gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+        else
+          gemv_narrow_m_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+      };
+      run();
       for (int round = 0; round < 2; ++round) {
         HIP_OK(hipEventRecord(g_gvtune->e0, s));
-        for (int r = 0; r < 3; ++r)
-          gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+        for (int r = 0; r < 3; ++r) run();
         HIP_OK(hipEventRecord(g_gvtune->e1, s));
         HIP_OK(hipEventSynchronize(g_gvtune->e1));
         float t = 0.f;
         HIP_OK(hipEventElapsedTime(&t, g_gvtune->e0, g_gvtune->e1));
         if (t < best) {
           best = t;
-          pick_narrow = 1;
+          pick_narrow = nf;
         }
       }
     }
     for (int form : {0, 1}) {
+      if (!try_wide) break;
       if (form == 1 && (pi == 0 || P.ntask4 == 0)) continue;   // four outputs per lane: FP32, > 64 outputs
       for (int nw : {4, 8, 16}) {
         gemv_wide_nw<T, MODE, ADD>(nw, form, P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
@@ -1066,16 +1094,20 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
     P.narrow_t[pi] = pick_narrow;
     if (pi == 1) P.form_t = pick_form;
   }
-  const bool narrow = P.G > 0 && (P.nw_t[pi] == 0 || P.narrow_t[pi]);
+  const int nform = P.G == 0 ? 0 : P.nw_t[pi] == 0 ? 1 : P.narrow_t[pi];
+  const bool narrow = nform > 0;
   const int NWsel = P.nw_t[pi] ? P.nw_t[pi] : P.NW;
   const int form = pi == 1 ? P.form_t : 0;
   // the names are those of the kernel symbols (k_gemv_wide4 has no type parameter)
-  PROF(kname(narrow ? "k_gemv_narrow" : (form == 1 ? "k_gemv_wide4" : "k_gemv_wide"),
+  PROF(kname(narrow ? (nform == 2 ? "k_gemv_narrow_m" : "k_gemv_narrow")
+                    : (form == 1 ? "k_gemv_wide4" : "k_gemv_wide"),
              (form == 1 ? std::string() : std::string(tname<T>()) + ", ") + std::to_string(MODE) +
                  ", " + (ADD ? "true" : "false") + ", " + std::to_string(narrow ? P.G : NWsel)),
        sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
        s);
-  if (narrow) {
+  if (nform == 2) {
+    gemv_narrow_m_launch<T, MODE, ADD>(P, sp, M, in, out, s, ps_);
+  } else if (narrow) {
     gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, out, s, ps_);
   } else {
     gemv_wide_nw<T, MODE, ADD>(NWsel, form, P, sp, M, in, out, s, ps_);
