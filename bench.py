@@ -340,7 +340,8 @@ def main():
         lt = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
         nt = inf["levels"][lt]["n"]
         for r in bkl:
-            if r["name"].startswith("k_bmm<") and r["name"].endswith(f"@L{lt}") and r["launches"]:
+            if (r["name"].startswith("k_bmm<") or r["name"].startswith("k_dense_mm64")) \
+                    and r["name"].endswith(f"@L{lt}") and r["launches"]:
                 us = r["ms"] / r["launches"] * 1e3
                 tf = 2.0 * nt * nt * args.batch / (us * 1e-6) / 1e12
                 mfma = dict(kernel=r["name"], n=nt, nrhs=args.batch, avg_launch_us=round(us, 2),
