@@ -259,16 +259,21 @@ enum {
                              LDS-staged GEMM with that many loop ranges (fewer
                              where the partial-sum buffer is too small); 17: never
                              the LDS-staged GEMM                                 */
-  LSAMG_OPT_ATA_TILES = 6 /* 1 (default): on 64 columns, the finest level's
+  LSAMG_OPT_ATA_TILES = 6, /* 1 (default): on 64 columns, the finest level's
                              G^T (G X) of the V-cycle residual and of the CG (with
                              LSAMG_OPT_ONEPASS_ATA) runs in one pass over tiles of
                              16 unknowns whose input rows are staged once in LDS,
                              where G's rows are short enough; 0: the untiled forms */
+  LSAMG_OPT_BGROUP = 7    /* 0 (default): on 64 columns in FP32, each coarse
+                             level's residual runs as the row-group pass (R_g^T R_g
+                             per group, staged) or as two CSR passes, whichever the
+                             autotuner times faster; 1: the row-group pass where
+                             built; 2: the CSR passes                           */
 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
- * except for LSAMG_OPT_MFMA_TILE and LSAMG_OPT_DENSE_SPLIT.  EINVAL on an
- * unknown option or value. */
+ * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT and LSAMG_OPT_BGROUP.
+ * EINVAL on an unknown option or value. */
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
 
 /* Y = B X: one V-cycle from zero (the preconditioner of lsamg_solve, sec.

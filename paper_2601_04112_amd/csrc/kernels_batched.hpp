@@ -962,6 +962,104 @@ __global__ void __launch_bounds__(kBlock) k_cg_tile(int64_t n, AtaTiles tl,
   write_part(v, part);
 }
 
+// Row-group pass of a coarse level on 64 columns (see k_grp_ata), FP32 on
+// the matrix cores: for a task (rows t0 .. t0+nr-1 of group g, nr <= 32;
+// support columns t0 .. c-1, w <= wmax of them)
+//   Y = R X_S     (nr x 64: y_i = sum_{q >= i} R_g[t0+i][t0+q] X[supp_g[t0+q]])
+//   STG[soff + q] = (R^T Y)[q]   (w x 64)
+// with R the task's upper-trapezoidal block (local column q of row i at
+// val[vstart + i*w - i*(i-1)/2 - i + q], zero for q < i).  One workgroup per
+// task; wavefront v owns output columns 16v .. 16v+15 of both products.  X_S
+// and the block (dense 32 x w, zero outside the trapezoid, odd row stride so
+// that the 16 rows one A operand reads fall in distinct banks) are staged in
+// LDS with coalesced loads; Y goes through LDS (32 rows, zero beyond nr)
+// between the two products.  v_mfma_f32_16x16x4f32 operand layout as in
+// k_bmm: lane i + 16g feeds A[i][g] and B[g][i] and holds D[4g+v][i].
+// LDS: ((wmax + 32) * 64 + 32 * (wmax + 1)) * 4 bytes (dynamic).
+__global__ void __launch_bounds__(kBlock) k_bgrp_ata64(GrpTasks tk, int wmax,
+                                                       const float* __restrict__ val,
+                                                       const int32_t* __restrict__ supp,
+                                                       const float* __restrict__ X,
+                                                       float* __restrict__ stg) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  float* sX = (float*)lds_raw;
+  float* sY = sX + (int64_t)wmax * 64;
+  float* sR = sY + 32 * 64;
+  constexpr int VPR = 16;                   // 16-byte pieces per row of X
+  const int64_t task = xcd_block(blockIdx.x, gridDim.x);
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, g = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int col = 16 * wv + i16;
+  const int nr = tk.nrow[task], t0 = tk.t0[task], c = tk.c[task];
+  const int w = c - t0;
+  const int64_t v0 = tk.vstart[task];
+  const int32_t* sp = supp + tk.s0[task] + t0;
+  const int W1 = w | 1;                     // odd LDS row stride of the block
+  for (int e = threadIdx.x; e < 32 * w; e += kBlock) {
+    const int i = e / w, q = e - i * w;
+    sR[i * W1 + q] = (i < nr && q >= i)
+                         ? val[v0 + (int64_t)i * w - (int64_t)i * (i - 1) / 2 - i + q]
+                         : 0.f;
+  }
+  // entry (i, q) of the task's block (i < 32), zero outside the trapezoid
+  auto rval = [&](int i, int q) -> float { return q < w ? sR[i * W1 + q] : 0.f; };
+  for (int e = threadIdx.x; e < w * VPR; e += kBlock) {
+    const int row = e / VPR, pc = e - row * VPR;
+    const int64_t cx = sp[row];
+    *(f32x4*)((char*)(sX + (int64_t)row * 64) + 16 * pc) =
+        *(const f32x4*)((const char*)(X + cx * 64) + 16 * pc);
+  }
+  __syncthreads();
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  {
+    f32x4 acc[2] = {zero, zero};
+#pragma unroll 4
+    for (int k = 0; k < w; k += 4) {
+      const int q = k + g;
+      const float bx = q < w ? sX[q * 64 + col] : 0.f;
+      acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(rval(i16, q), bx, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(rval(16 + i16, q), bx, acc[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sY[(16 * rt + 4 * g + v) * 64 + col] = acc[rt][v];
+  }
+  __syncthreads();
+  float* dst = stg + tk.soff[task] * 64;
+  for (int qt = 0; qt < w; qt += 16) {
+    f32x4 acc = zero;
+#pragma unroll
+    for (int k = 0; k < 32; k += 4) {
+      if (k >= nr) break;
+      const int i = k + g;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(rval(i, qt + i16), sY[i * 64 + col], acc, 0, 0,
+                                                 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int q = qt + 4 * g + v;
+      if (q < w) dst[(int64_t)q * 64 + col] = acc[v];
+    }
+  }
+}
+
+// R = B - (sum of the staged rows of each unknown, in position order), 64
+// columns, a wavefront per unknown.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bresid_stg64(int64_t n, const int64_t* __restrict__ cptr,
+                                                         const int64_t* __restrict__ cpos,
+                                                         const T* __restrict__ stg,
+                                                         const T* __restrict__ B,
+                                                         T* __restrict__ R) {
+  const int lane = threadIdx.x & 63;
+  const int64_t d = wave_row<64>((xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) / 64);
+  if (d >= n) return;
+  const T t = staged_sum64<T>(cptr[d], cptr[d + 1], cpos, stg, lane);
+  R[d * 64 + lane] = B[d * 64 + lane] - t;
+}
+
 // alpha_j = rho_j / pq_j (0 for inactive columns); X += alpha P; R -= alpha Q;
 // R32 = (float) R (if given); partials of R . R
 template <int NB>

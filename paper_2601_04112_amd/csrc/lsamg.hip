@@ -153,6 +153,15 @@ struct DLevel {
   int32_t* grp_supp = nullptr;
   int64_t* rc_ptr = nullptr;
   int32_t* rc_pos = nullptr;
+  // the same pass on 64 columns (k_bgrp_ata64): one task per group of at
+  // most 32 rows, staged rows of 64 values; tuned against the CSR passes
+  dev::GrpTasks bgtask{};
+  int64_t bg_ntask = 0, bg_nstg = 0;
+  int bg_wmax = 0, bg_rmax = 0;
+  int64_t* bg_cptr = nullptr;
+  int64_t* bg_cpos = nullptr;
+  bool bg_ok = false;     // tasks built
+  bool bg_on = false;     // chosen by the autotuner (FP32, 64 columns)
   DPrec<double> d;
   DPrec<float> f;
 };
@@ -289,6 +298,7 @@ struct lsamg_handle {
   bool use_mfma = true;             // FP32 batched V-cycle on the matrix cores (k_bmm)
   int mm_fixed = 0;                 // k_bmm tile shape 100*rt + 10*u + split, 0: autotune
   int dense_split = 0;              // k_dense_mm64 loop ranges: 0 autotune, 1..16 fixed, 17 never
+  int bgroup = 0;                   // coarse residual on 64 columns: 0 autotune, 1 row groups, 2 CSR
   bool gv_tuned[2] = {false, false}; // single-vector wide GEMV shapes tuned (double, float)
   // V-cycles replayed from HIP graphs, one per (precision, batch width)
   bool use_graphs = true;
@@ -324,6 +334,7 @@ struct lsamg_handle {
   struct BLev {
     double *x = nullptr, *b = nullptr, *r = nullptr, *y = nullptr, *tb = nullptr;
     float *fx = nullptr, *fb = nullptr, *fr = nullptr, *fy = nullptr, *ftb = nullptr;
+    float* fstg = nullptr;          // k_bgrp_ata64 staging, bg_nstg x 64
   };
   bool batched_ready = false;
   std::vector<BLev> BL;
@@ -374,6 +385,7 @@ struct lsamg_handle {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
       D.dmm_split = 0;
       D.dmm_M = nullptr;                // freed with the batched buffers below
+      D.bg_on = false;                  // its staging goes with them too
     }
     mm_tuned = false;
     drop_graphs(true);
@@ -413,6 +425,58 @@ namespace {
 
 // Row-group tasks of a coarse level (k_grp_ata) and the cover lists of the
 // staged output.  gp: CSR row pointer of the stored rows of G_l.
+// Tasks of the row-group pass on 64 columns (k_bgrp_ata64): a workgroup per
+// task of at most 32 rows of one group, covering support columns t0..c-1 (at
+// most 128 of them: the staged input rows and the rows' products fit 64 KB
+// of LDS in FP32); the staged output of each task and the cover lists of the
+// unknowns follow the single-vector layout, with positions in rows of 64.
+void build_bgroup_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
+                        const std::vector<int64_t>& gp) {
+  constexpr int RPT = 32, WMAX = 128;
+  const Groups& G = HL.G;
+  std::vector<int64_t> vs, s0v, so;
+  std::vector<int32_t> nr, t0v, cv;
+  std::vector<std::pair<int32_t, int64_t>> cover;
+  int64_t row = 0, nstg = 0;
+  int wmax = 0, rmax = 0;
+  for (int64_t g = 0; g < G.ng(); ++g) {
+    const int c = (int)(G.sptr[g + 1] - G.sptr[g]);
+    const int ntk = (G.nrows[g] + RPT - 1) / RPT;
+    const int chunk = (G.nrows[g] + ntk - 1) / ntk;
+    for (int t0 = 0; t0 < G.nrows[g]; t0 += chunk) {
+      const int w = c - t0, k = std::min(chunk, G.nrows[g] - t0);
+      if (w > WMAX) return;
+      wmax = std::max(wmax, w);
+      rmax = std::max(rmax, k);
+      vs.push_back(gp[row + t0]);
+      nr.push_back(k);
+      t0v.push_back(t0);
+      cv.push_back(c);
+      s0v.push_back(G.sptr[g]);
+      so.push_back(nstg);
+      for (int j = t0; j < c; ++j) cover.emplace_back(G.supp[G.sptr[g] + j], nstg + (j - t0));
+      nstg += w;
+    }
+    row += G.nrows[g];
+  }
+  std::vector<int64_t> cp(D.n + 1, 0), cs(cover.size());
+  for (auto& e : cover) cp[e.first + 1]++;
+  for (int64_t j = 0; j < D.n; ++j) cp[j + 1] += cp[j];
+  {
+    std::vector<int64_t> fill(cp.begin(), cp.end() - 1);
+    for (auto& e : cover) cs[fill[e.first]++] = e.second;   // ascending position
+  }
+  D.bgtask = dev::GrpTasks{h->upload(vs), h->upload(nr), h->upload(t0v), h->upload(cv),
+                           h->upload(s0v), h->upload(so)};
+  D.bg_ntask = (int64_t)vs.size();
+  D.bg_nstg = nstg;
+  D.bg_wmax = wmax;
+  D.bg_rmax = rmax;
+  D.bg_cptr = h->upload(cp);
+  D.bg_cpos = h->upload(cs);
+  D.bg_ok = true;
+}
+
 void build_group_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
                        const std::vector<int64_t>& gp) {
   const Groups& G = HL.G;
@@ -477,6 +541,7 @@ void build_group_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
   D.grp_supp = h->upload(G.supp);
   D.rc_ptr = h->upload(cp);
   D.rc_pos = h->upload(cs);
+  build_bgroup_tasks(h, HL, D, gp);
   D.d.stg = h->alloc<double>(nstg);
   D.f.stg = h->alloc<float>(nstg);
 }
@@ -1616,6 +1681,7 @@ void ensure_batched(lsamg_handle* h, int NB) {
     B.fr = h->alloc<float>(n);
     B.fy = h->alloc<float>(ny);
     B.ftb = h->alloc<float>(nt);
+    if (L.bg_ok) B.fstg = h->alloc<float>((size_t)L.bg_nstg * kBMax);
   }
   const size_t n0 = (size_t)h->L[0].n * kBMax;
   h->BX = h->alloc<double>(n0);
@@ -1646,13 +1712,14 @@ void ensure_batched(lsamg_handle* h, int NB) {
 template <typename T>
 struct BVec {
   T *x, *b, *r, *y, *tb;
+  T* stg;                 // k_bgrp_ata64 staging (FP32 only)
 };
 template <typename T>
 BVec<T> bvec(lsamg_handle::BLev& B);
 template <>
-BVec<double> bvec<double>(lsamg_handle::BLev& B) { return {B.x, B.b, B.r, B.y, B.tb}; }
+BVec<double> bvec<double>(lsamg_handle::BLev& B) { return {B.x, B.b, B.r, B.y, B.tb, nullptr}; }
 template <>
-BVec<float> bvec<float>(lsamg_handle::BLev& B) { return {B.fx, B.fb, B.fr, B.fy, B.ftb}; }
+BVec<float> bvec<float>(lsamg_handle::BLev& B) { return {B.fx, B.fb, B.fr, B.fy, B.ftb, B.fstg}; }
 
 // Task list of k_bmm for RT row tiles per task and a loop split S (single-
 // aggregate operators only).  Tasks are ordered by loop length, longest
@@ -2007,6 +2074,24 @@ void bata_tile(const DLevel& L, const T* X, const T* B, T* R, double* part, hipS
   LAUNCH_OK();
 }
 
+// coarse-level residual on 64 columns by row groups: k_bgrp_ata64 stages
+// R_g^T R_g X(supp_g) per task, k_bresid_stg64 gathers R = B - staged
+void bgrp_resid(const DLevel& L, const float* X, const float* B, float* R, float* stg,
+                hipStream_t s) {
+  {
+    PROF("k_bgrp_ata64",
+         4.0 * (L.nnz + 2.0 * L.bg_nstg * 64) + 36.0 * L.bg_ntask, s);
+    const size_t lds = ((size_t)(L.bg_wmax + 32) * 64 + 32 * (size_t)(L.bg_wmax + 1)) * sizeof(float);
+    KLAUNCH((unsigned)L.bg_ntask, dev::kBlock, lds, s, dev::k_bgrp_ata64, L.bgtask,
+            L.bg_wmax, (const float*)L.f.g_val, L.grp_supp, X, stg);
+    LAUNCH_OK();
+  }
+  PROF("k_bresid_stg64<float>", 4.0 * (L.bg_nstg + 2.0 * L.n) * 64 + 8.0 * (L.bg_nstg + L.n), s);
+  KLAUNCH(nblocks(L.n * 64), dev::kBlock, 0, s, dev::k_bresid_stg64<float>, L.n, L.bg_cptr,
+          L.bg_cpos, (const float*)stg, B, R);
+  LAUNCH_OK();
+}
+
 template <typename T, int NB>
 void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
@@ -2015,6 +2100,12 @@ void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t 
     if (L.at_on) {                      // one pass, X rows staged per tile
       bata_tile<T, 0>(L, X, B, R, nullptr, s);
       return;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+      if (L.bg_on) {                    // row groups, staged
+        bgrp_resid(L, X, B, R, V.stg, s);
+        return;
+      }
     }
   }
   // each pass: several short rows per wavefront (k_bspmm64), or one row per
@@ -2095,6 +2186,8 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
 
 // Choose the k_bmm tile shapes of every operator the FP32 multi-right-hand-
 // side V-cycle applies (once per allocation of the batched buffers).
+void bgroup_tune(lsamg_handle* h, hipStream_t s);
+
 template <int NB>
 void mm_tune_all(lsamg_handle* h, hipStream_t s) {
   if constexpr (NB >= 16) {
@@ -2159,9 +2252,53 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
       mm_tune<dev::IN_DIRECT, false, NB>(h, L.rast, nullptr, nullptr, nullptr, nullptr, L.f.Zr,
                                          B.fr, B.ftb, part, cap, s, fl.p, flush_n);
     }
+    if (NB == 64) bgroup_tune(h, s);
     HIP_OK(hipStreamSynchronize(s));
     h->mm_tuned = true;
   }
+}
+
+// Coarse-level residual on 64 columns, FP32: the row-group pass against the
+// two CSR passes, each timed on the level's own buffers (one warm-up, best of
+// two rounds of three), unless LSAMG_OPT_BGROUP fixes the form.
+void bgroup_tune(lsamg_handle* h, hipStream_t s) {
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  try {
+    for (size_t l = 1; l < h->L.size(); ++l) {
+      DLevel& L = h->L[l];
+      if (L.coarsest || L.tail) break;
+      L.bg_on = false;
+      if (!L.bg_ok || h->bgroup == 2) continue;
+      if (h->bgroup == 1) {
+        L.bg_on = true;
+        continue;
+      }
+      BVec<float> V = bvec<float>(h->BL[l]);
+      float t[2] = {1e30f, 1e30f};
+      for (int form = 0; form < 2; ++form) {
+        L.bg_on = form == 1;
+        bresidual<float, 64>(L, V, V.x, V.b, V.r, s);
+        for (int round = 0; round < 2; ++round) {
+          HIP_OK(hipEventRecord(e0, s));
+          for (int r = 0; r < 3; ++r) bresidual<float, 64>(L, V, V.x, V.b, V.r, s);
+          HIP_OK(hipEventRecord(e1, s));
+          HIP_OK(hipEventSynchronize(e1));
+          float ms = 0.f;
+          HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+          t[form] = std::min(t[form], ms);
+        }
+      }
+      L.bg_on = t[1] < t[0];
+    }
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
 }
 
 // Dense tail: the V-cycle of levels >= lc is a fixed symmetric linear map
@@ -2694,7 +2831,9 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
 
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
   if (!h || value < 0 || (opt == LSAMG_OPT_DENSE_SPLIT && value > 17) ||
-      (opt != LSAMG_OPT_MFMA_TILE && opt != LSAMG_OPT_DENSE_SPLIT && value > 1))
+      (opt == LSAMG_OPT_BGROUP && value > 2) ||
+      (opt != LSAMG_OPT_MFMA_TILE && opt != LSAMG_OPT_DENSE_SPLIT && opt != LSAMG_OPT_BGROUP &&
+       value > 1))
     return fail_with(LSAMG_EINVAL, "bad argument");
   if (opt == LSAMG_OPT_BATCHED) {
     h->batch_mode = (int)value;
@@ -2704,6 +2843,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
       for (auto& D : h->L) {
         for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
         D.dmm_split = 0;
+        D.bg_on = false;
       }
       h->mm_tuned = false;
     }
@@ -2712,6 +2852,15 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->use_graphs = value != 0;
   } else if (opt == LSAMG_OPT_ONEPASS_ATA) {
     for (auto& D : h->L) D.fuse_ata = value != 0 && D.fuse_ok;
+    h->drop_graphs(true);
+  } else if (opt == LSAMG_OPT_BGROUP) {
+    h->bgroup = (int)value;
+    for (auto& D : h->L) D.bg_on = false;
+    h->mm_tuned = false;                // decided again with the tiles on the next batched solve
+    for (auto& D : h->L) {
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      D.dmm_split = 0;
+    }
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_ATA_TILES) {
     for (auto& D : h->L) {

@@ -21,7 +21,7 @@ LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
 FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
-OPT_ATA_TILES = 6
+OPT_ATA_TILES, OPT_BGROUP = 6, 7
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
                -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
@@ -306,7 +306,8 @@ class Solver:
     def set_option(self, opt: int, value: int):
         """OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_ONEPASS_ATA, OPT_ATA_TILES (value 0 or 1), OPT_MFMA_TILE
         (0: autotune, else 100*rt + 10*u + split) or OPT_DENSE_SPLIT (0: autotune,
-        1..16: LDS-staged dense GEMM with that many loop ranges, 17: never)."""
+        1..16: LDS-staged dense GEMM with that many loop ranges, 17: never) or OPT_BGROUP
+        (0: autotune, 1: row-group pass, 2: CSR passes)."""
         _check(load().lsamg_set_option(self._h, opt, int(value)))
 
     # -- kernel timing ----------------------------------------------------

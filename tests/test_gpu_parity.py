@@ -442,6 +442,49 @@ def test_single_cg_tile(rot, prec):
         s.set_precision(L.FP64)
 
 
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_batched_group_pass(which, request):
+    """The coarse-level residual of the FP32 batched V-cycle as the row-group
+    pass on 64 columns (k_bgrp_ata64 + k_bresid_stg64) and as the two CSR
+    passes both give the single-vector V-cycle on each column to 2e-5; the
+    forced form is the one that runs, and the batched mixed solve with the
+    row-group pass reaches the tolerance."""
+    p, H, s = request.getfixturevalue(which)
+    B = np.stack([P.rhs_uniform(p.n, 1300 + j) for j in range(64)])
+    dB = dvec(B)
+    # levels with a residual between the finest and the dense tail (or coarsest)
+    inf = s.info()
+    last = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
+    coarse = last > 1
+    s.set_precision(L.MIXED)
+    try:
+        Y1 = [host(s.apply(L.OP_VCYCLE, dB[j])) for j in range(0, 64, 13)]
+        for bg in (1, 2, 0):
+            s.set_option(L.OPT_BGROUP, bg)
+            s.apply_vcycle_batch(dB)            # tunes
+            s.profile(True)
+            Y = host(s.apply_vcycle_batch(dB))
+            names = {k["name"].split("<")[0] for k in s.profile_read()}
+            s.profile(False)
+            if bg == 1:
+                assert ("k_bgrp_ata64" in names and "k_bresid_stg64" in names) == coarse, \
+                    (coarse, sorted(names))
+            if bg == 2:
+                assert "k_bgrp_ata64" not in names, sorted(names)
+            for k, j in enumerate(range(0, 64, 13)):
+                assert rel(Y[j], Y1[k]) <= 2e-5, (bg, j, rel(Y[j], Y1[k]))
+        s.set_option(L.OPT_BGROUP, 1)
+        X, st = s.solve(dB, tol=1e-8)
+        Xh = host(X)
+        for j in (0, 32, 63):
+            r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
+            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+    finally:
+        s.profile(False)
+        s.set_option(L.OPT_BGROUP, 0)
+        s.set_precision(L.FP64)
+
+
 def test_more_than_one_batch(rot):
     """70 right-hand sides are solved as a block of 64 and a block of 6 (both
     precisions); every column reaches the tolerance, and in FP64 equals its
