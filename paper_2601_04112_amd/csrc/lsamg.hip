@@ -2050,8 +2050,9 @@ void bata_tile(const DLevel& L, const T* X, const T* B, T* R, double* part, hipS
   const DPrec<T>& P = prec<T>(const_cast<DLevel&>(L));
   const size_t lds = (size_t)(L.at.umax + L.at_rmax) * 64 * sizeof(T);
   const unsigned grid = EPI == 1 ? (unsigned)kBNP : (unsigned)L.at.ntile;
-  PROF(kname("k_bata_tile", std::string(tname<T>()) + ", " + std::to_string(L.ata_me) + ", " +
-                                std::to_string(L.ata_mf) + ", " + std::to_string(EPI)),
+  PROF(kname("k_bata_tile", std::string(tname<T>()) + ", " + std::to_string(kAtaTile) + ", " +
+                                std::to_string(L.ata_me) + ", " + std::to_string(L.ata_mf) + ", " +
+                                std::to_string(EPI)),
        (double)sizeof(T) * L.n * 64 * 3 + (double)L.nnz * (sizeof(T) + 4) + 8.0 * (L.n + L.nrows),
        s);
   auto launch = [&](auto kern) {
