@@ -152,3 +152,22 @@ def test_single_level_when_small():
     p = P.aniso2d(8, 0.0, 1.0)           # 49 unknowns < max_coarse
     s = L.Solver(p.G, 2, p.grid, device=-1)
     assert s.info()["nlevels"] == 1
+
+
+def test_set_option_values():
+    """lsamg_set_option accepts each option's documented range and refuses
+    the rest with EINVAL (no GPU needed)."""
+    p = P.aniso2d(16, 0.3, 1e-2)
+    s = L.Solver(p.G, 2, p.grid, device=-1)
+    lib = L.load()
+    ok = [(L.OPT_BATCHED, 0), (L.OPT_BATCHED, 1), (L.OPT_MFMA, 0), (L.OPT_MFMA, 1),
+          (L.OPT_GRAPH, 0), (L.OPT_ONEPASS_ATA, 1), (L.OPT_MFMA_TILE, 0),
+          (L.OPT_MFMA_TILE, 428), (L.OPT_DENSE_SPLIT, 16), (L.OPT_DENSE_SPLIT, 17),
+          (L.OPT_ATA_TILES, 0), (L.OPT_BGROUP, 2), (L.OPT_BGROUP, 0)]
+    for opt, v in ok:
+        assert lib.lsamg_set_option(s._h, opt, v) == L.LSAMG_OK, (opt, v)
+    bad = [(L.OPT_BATCHED, 2), (L.OPT_GRAPH, -1), (L.OPT_MFMA_TILE, 123),
+           (L.OPT_MFMA_TILE, 1000), (L.OPT_DENSE_SPLIT, 18), (L.OPT_ATA_TILES, 2),
+           (L.OPT_BGROUP, 3), (99, 0)]
+    for opt, v in bad:
+        assert lib.lsamg_set_option(s._h, opt, v) == L.LSAMG_EINVAL, (opt, v)
