@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int l = s + u * S;
-      mv[u] = (j < nj && l < nl) ? m[(int64_t)l * ld] : T(0);
+      mv[u] = (j < nj && l < nl) ? __builtin_nontemporal_load(&m[(int64_t)l * ld]) : T(0);
     }
     ib = op.ibase[a];
     if (MODE == IN_RESG)
@@ -262,11 +262,11 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow(int64_t nagg, GemvOp op,
     int l = s + U * S;
     for (; l + (U - 1) * S < nl; l += U * S) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * S) * ld];
+      for (int u = 0; u < U; ++u) mv[u] = __builtin_nontemporal_load(&m[(int64_t)(l + u * S) * ld]);
 #pragma unroll
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * S];
     }
-    for (; l < nl; l += S) av[0] += m[(int64_t)l * ld] * sv[l];
+    for (; l < nl; l += S) av[0] += __builtin_nontemporal_load(&m[(int64_t)l * ld]) * sv[l];
     acc = ((av[0] + av[1]) + (av[2] + av[3])) + ((av[4] + av[5]) + (av[6] + av[7]));
   }
   for (int o = G; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
@@ -367,7 +367,7 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int l = wave + u * NW;
-    mv0[u] = (j < nj && l < nl) ? m[(int64_t)l * ld] : T(0);
+    mv0[u] = (j < nj && l < nl) ? __builtin_nontemporal_load(&m[(int64_t)l * ld]) : T(0);
   }
   if (MODE == IN_RESG) {
     stage_products<T, MODE>(pr, ib, nl, spec, threadIdx.x, NW * 64);
@@ -387,11 +387,11 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide(const int32_t* __restrict
     for (; l + (U - 1) * NW < nl; l += U * NW) {
       T mv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = m[(int64_t)(l + u * NW) * ld];
+      for (int u = 0; u < U; ++u) mv[u] = __builtin_nontemporal_load(&m[(int64_t)(l + u * NW) * ld]);
 #pragma unroll
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
     }
-    for (; l < nl; l += NW) av[0] += m[(int64_t)l * ld] * sv[l];
+    for (; l < nl; l += NW) av[0] += __builtin_nontemporal_load(&m[(int64_t)l * ld]) * sv[l];
 #pragma unroll
     for (int w = U / 2; w > 0; w >>= 1)     // fixed pairwise tree over the U partial sums
 #pragma unroll
@@ -442,7 +442,7 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide4(const int32_t* __restric
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int l = wave + u * NW;
-    mv0[u] = (jv && l < nl) ? *(const f32x4*)(m + (int64_t)l * ld) : zero;
+    mv0[u] = (jv && l < nl) ? __builtin_nontemporal_load((const f32x4*)(m + (int64_t)l * ld)) : zero;
   }
   if (MODE == IN_RESG) {
     stage_products<float, MODE>(pr, ib, nl, spec, threadIdx.x, NW * 64);
@@ -462,11 +462,11 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide4(const int32_t* __restric
     for (; l + (U - 1) * NW < nl; l += U * NW) {
       f32x4 mv[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) mv[u] = *(const f32x4*)(m + (int64_t)(l + u * NW) * ld);
+      for (int u = 0; u < U; ++u) mv[u] = __builtin_nontemporal_load((const f32x4*)(m + (int64_t)(l + u * NW) * ld));
 #pragma unroll
       for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * NW];
     }
-    for (; l < nl; l += NW) av[0] += *(const f32x4*)(m + (int64_t)l * ld) * sv[l];
+    for (; l < nl; l += NW) av[0] += __builtin_nontemporal_load((const f32x4*)(m + (int64_t)l * ld)) * sv[l];
 #pragma unroll
     for (int w = U / 2; w > 0; w >>= 1)     // fixed pairwise tree over the U partial sums
 #pragma unroll
