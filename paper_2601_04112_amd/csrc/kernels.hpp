@@ -810,7 +810,7 @@ __global__ void __launch_bounds__(kBlock) k_sym_reduce(int64_t n, int nT, const 
   }
 }
 
-// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the
+// Dense tail construction: E = columns j0..j0+NB-1 of the identity in the
 // interleaved n x NB layout of the multi-right-hand-side path.
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_unit_block(int64_t n, int64_t j0,
