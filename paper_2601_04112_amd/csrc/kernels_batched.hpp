@@ -1118,6 +1118,58 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
   bwrite_parts<NB>(v, rz_part);
 }
 
+// k_bcg_z on 64 columns with four columns per thread: a group of 16 lanes
+// takes one unknown (16-byte loads of XV and of each staged row, two of R
+// and Z in FP64), so a wavefront carries four unknowns through each memory
+// round trip.  Z = (double)(XV + staged sum), the staged rows added in
+// position order as in k_bcg_z; partials of R . Z per column and workgroup
+// (part[blockIdx.x * 64 + j]) summed over the 16 unknown slots in a fixed
+// order.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restrict__ XV,
+                                                    const int64_t* __restrict__ cptr,
+                                                    const int64_t* __restrict__ cpos,
+                                                    const T* __restrict__ tb,
+                                                    const double* __restrict__ R,
+                                                    double* __restrict__ Z,
+                                                    double* __restrict__ rz_part) {
+  constexpr int SL = kBlock / 16;          // unknown slots per workgroup
+  __shared__ double sm[SL][64];
+  const int slot = threadIdx.x >> 4, c4 = 4 * (threadIdx.x & 15);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t d = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SL + slot; d < n;
+       d += (int64_t)gridDim.x * SL) {
+    const int64_t o = d * 64 + c4;
+    T s[4];
+    load4<T>(XV + o, s);
+    if (cptr) {
+      const int64_t e1 = cptr[d + 1];
+      for (int64_t e = cptr[d]; e < e1; ++e) {
+        T t[4];
+        load4<T>(tb + cpos[e] * 64 + c4, t);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) s[k] += t[k];
+      }
+    }
+    double r[4];
+    load4<double>(R + o, r);
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const d2 z01 = {(double)s[0], (double)s[1]}, z23 = {(double)s[2], (double)s[3]};
+    *(d2*)(Z + o) = z01;
+    *(d2*)(Z + o + 2) = z23;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] += r[k] * (double)s[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sm[slot][c4 + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double t = 0;
+    for (int q = 0; q < SL; ++q) t += sm[q][threadIdx.x];
+    rz_part[(int64_t)blockIdx.x * 64 + threadIdx.x] = t;
+  }
+}
+
 // P = Z + beta P, beta_j = rz_new_j / rz_old_j (rz_old == nullptr: P = Z);
 // rz_new, rz_old: per-column scalars
 template <int NB>

@@ -2442,16 +2442,30 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   if (h->precision == LSAMG_MIXED) {
     run_graph(h, 128 + NB, s,
               [&](hipStream_t gs) { bvcycle<float, NB>(h, 0, B0.fb, B0.fx, gs, false); });
-    PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), 20 * n * NB, s);
-    KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
-            stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
-            h->Brz[cur]);
+    if (NB == 64) {
+      PROF("k_bcg_z64<float>", 20 * n * NB, s);
+      KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z64<float>, n, (const float*)B0.fx,
+              stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR,
+              h->BZ, h->Brz[cur]);
+    } else {
+      PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), 20 * n * NB, s);
+      KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
+              stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
+              h->Brz[cur]);
+    }
   } else {
     run_graph(h, NB, s, [&](hipStream_t gs) { bvcycle<double, NB>(h, 0, h->BR, B0.x, gs, false); });
-    PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), 24 * n * NB, s);
-    KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
-            stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
-            h->BZ, h->Brz[cur]);
+    if (NB == 64) {
+      PROF("k_bcg_z64<double>", 24 * n * NB, s);
+      KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z64<double>, n, (const double*)B0.x,
+              stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
+              h->BZ, h->Brz[cur]);
+    } else {
+      PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), 24 * n * NB, s);
+      KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
+              stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
+              h->BZ, h->Brz[cur]);
+    }
   }
   LAUNCH_OK();
   bsum<NB>(h->Brz[cur], h->Brz_s[cur], s);
