@@ -1170,6 +1170,79 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restri
   }
 }
 
+template <typename T>
+__device__ __forceinline__ void store4(T* __restrict__ p, const T (&m)[4]);
+template <>
+__device__ __forceinline__ void store4<float>(float* __restrict__ p, const float (&m)[4]) {
+  const f32x4 t = {m[0], m[1], m[2], m[3]};
+  *(f32x4*)p = t;
+}
+template <>
+__device__ __forceinline__ void store4<double>(double* __restrict__ p, const double (&m)[4]) {
+  typedef double v2 __attribute__((ext_vector_type(2)));
+  const v2 t0 = {m[0], m[1]}, t1 = {m[2], m[3]};
+  *(v2*)p = t0;
+  *(v2*)(p + 2) = t1;
+}
+
+// CSR rows on 64 columns with four columns per thread: a group of 16 lanes
+// takes one row, so a wavefront works on four rows at once.  The group loads
+// 16 entries (index, value) with one load per lane and walks them by lane
+// shuffle, four 16-byte row gathers in flight per lane; entries are added in
+// row order.  RES: Y = B - A X; else Y = A X.
+template <typename T, bool RES>
+__global__ void __launch_bounds__(kBlock) k_bspmv4(int64_t nrows, const int64_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ col,
+                                                   const T* __restrict__ val,
+                                                   const T* __restrict__ X,
+                                                   const T* __restrict__ B, T* __restrict__ Y) {
+  const int64_t row = (xcd_block(blockIdx.x, gridDim.x) * kBlock + threadIdx.x) >> 4;
+  const int j = threadIdx.x & 15, c4 = 4 * j;
+  if (row >= nrows) return;            // whole 16-lane groups exit together
+  const int64_t e0 = ptr[row], e1 = ptr[row + 1];
+  T acc[4] = {T(0), T(0), T(0), T(0)};
+  for (int64_t b = e0; b < e1; b += 16) {
+    const int cnt = (int)(e1 - b < 16 ? e1 - b : 16);
+    const int64_t e = b + (j < cnt ? j : cnt - 1);
+    const int cj = col[e];
+    const T vj = val[e];
+    int k = 0;
+    for (; k + 4 <= cnt; k += 4) {
+      T y[4][4];
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = __shfl(cj, k + u, 16);
+        v[u] = __shfl(vj, k + u, 16);
+        load4<T>(X + (int64_t)c * 64 + c4, y[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += v[u] * y[u][q];
+    }
+    for (; k < cnt; ++k) {
+      const int c = __shfl(cj, k, 16);
+      const T v = __shfl(vj, k, 16);
+      T y[4];
+      load4<T>(X + (int64_t)c * 64 + c4, y);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] += v * y[q];
+    }
+  }
+  T out[4];
+  if (RES) {
+    T bb[4];
+    load4<T>(B + row * 64 + c4, bb);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = bb[q] - acc[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[q] = acc[q];
+  }
+  store4<T>(Y + row * 64 + c4, out);
+}
+
 // P = Z + beta P, beta_j = rz_new_j / rz_old_j (rz_old == nullptr: P = Z);
 // rz_new, rz_old: per-column scalars
 template <int NB>

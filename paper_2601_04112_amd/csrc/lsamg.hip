@@ -2109,37 +2109,35 @@ void bresidual(DLevel& L, BVec<T>& V, const T* X, const T* B, T* R, hipStream_t 
       }
     }
   }
-  // each pass: several short rows per wavefront (k_bspmm64), or one row per
-  // wavefront for long rows
-  const int rpw_g = NB == 64 ? rows_per_wave(L.nnz, L.nrows) : 0;
-  const int rpw_t = NB == 64 ? rows_per_wave(L.nnz, L.n) : 0;
-  if (rpw_g > 0) {
-    PROF(kname("k_bspmm64", tname<T>()),
-         L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
-    KLAUNCH((unsigned)((L.nrows + 4 * rpw_g - 1) / (4 * rpw_g)), dev::kBlock, 0, s,
-            dev::k_bspmm64<T>, L.nrows, rpw_g, L.g_ptr, L.g_col, P.g_val, X, (const T*)nullptr,
-            V.y);
+  // two CSR passes: on 64 columns a 16-lane group per row, four columns per
+  // lane (k_bspmv4); narrower batches one row per wavefront slice
+  if (NB == 64) {
+    {
+      PROF(kname("k_bspmv4", std::string(tname<T>()) + ", false"),
+           L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
+      KLAUNCH(nblocks(L.nrows * 16), dev::kBlock, 0, s, dev::k_bspmv4<T, false>, L.nrows,
+              L.g_ptr, L.g_col, P.g_val, X, (const T*)nullptr, V.y);
+      LAUNCH_OK();
+    }
+    PROF(kname("k_bspmv4", std::string(tname<T>()) + ", true"),
+         L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
+    KLAUNCH(nblocks(L.n * 16), dev::kBlock, 0, s, dev::k_bspmv4<T, true>, L.n, L.gt_ptr,
+            L.gt_col, P.gt_val, (const T*)V.y, B, R);
     LAUNCH_OK();
-  } else {
+    return;
+  }
+  {
     PROF(kname("k_bspmv", std::string(tname<T>()) + ", " + std::to_string(NB)),
          L.nnz * (sizeof(T) + 4) + 8 * (L.nrows + 1) + sizeof(T) * (L.n + L.nrows) * NB, s);
     KLAUNCH(nblocks(L.nrows * NB), dev::kBlock, 0, s, dev::k_bspmv<T, NB>, L.nrows, L.g_ptr,
             L.g_col, P.g_val, X, V.y);
     LAUNCH_OK();
   }
-  if (rpw_t > 0) {
-    PROF(kname("k_bspmm64", tname<T>()),
-         L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
-    KLAUNCH((unsigned)((L.n + 4 * rpw_t - 1) / (4 * rpw_t)), dev::kBlock, 0, s,
-            dev::k_bspmm64<T>, L.n, rpw_t, L.gt_ptr, L.gt_col, P.gt_val, (const T*)V.y, B, R);
-    LAUNCH_OK();
-  } else {
-    PROF(kname("k_bresid_t", std::string(tname<T>()) + ", " + std::to_string(NB)),
-         L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
-    KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bresid_t<T, NB>, L.n, L.gt_ptr,
-            L.gt_col, P.gt_val, (const T*)V.y, B, R);
-    LAUNCH_OK();
-  }
+  PROF(kname("k_bresid_t", std::string(tname<T>()) + ", " + std::to_string(NB)),
+       L.nnz * (sizeof(T) + 4) + 8 * (L.n + 1) + sizeof(T) * (L.nrows + 2 * L.n) * NB, s);
+  KLAUNCH(nblocks(L.n * NB), dev::kBlock, 0, s, dev::k_bresid_t<T, NB>, L.n, L.gt_ptr, L.gt_col,
+          P.gt_val, (const T*)V.y, B, R);
+  LAUNCH_OK();
 }
 
 // X = B_l(B) for NB interleaved right-hand sides (see vcycle)
