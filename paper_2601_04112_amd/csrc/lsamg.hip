@@ -380,6 +380,9 @@ struct lsamg_handle {
     return ptr;
   }
   bool mm_tuned = false;             // k_bmm tile shapes chosen for the batched buffers
+  bool mm_tuned64 = false;           // and the 64-column forms (dense GEMM split, coarse residual)
+  float* mm_part = nullptr;          // partial sums of split loops, sized for the buffers' width
+  int64_t mm_part_cap = 0;
   void free_batched() {
     for (auto& D : L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
@@ -388,6 +391,9 @@ struct lsamg_handle {
       D.bg_on = false;                  // its staging goes with them too
     }
     mm_tuned = false;
+    mm_tuned64 = false;
+    mm_part = nullptr;                 // freed with the batched buffers below
+    mm_part_cap = 0;
     drop_graphs(true);
     for (void* ptr : ballocs) (void)hipFree(ptr);
     ballocs.clear();
@@ -1868,7 +1874,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   if (h->mm_fixed > 0) {               // a fixed tile shape (LSAMG_OPT_MFMA_TILE)
     const int rt = h->mm_fixed / 100, u = (h->mm_fixed / 10) % 10;
     int sp = h->mm_fixed % 10;
-    if ((int64_t)sp * P.out * NB > part_cap) sp = 1;
+    if ((int64_t)sp * P.out * std::max<int64_t>(NB, h->bwidth) > part_cap) sp = 1;
     cand.push_back(Cand{rt, u, sp});
   }
   for (int rt : {1, 2, 4}) {
@@ -1878,7 +1884,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
       if (u == 8 && llmax <= 8) continue;                 // one step covers the loop
       for (int sp : {1, 2, 4, 8, 16}) {
         if (sp > 1 && (llmax / sp < (P.nagg == 1 ? 256 : 64) || (P.nagg > 1 && sp > 4))) continue;
-        if ((int64_t)sp * P.out * NB > part_cap) continue;
+        if ((int64_t)sp * P.out * std::max<int64_t>(NB, h->bwidth) > part_cap) continue;
         cand.push_back(Cand{rt, u, sp});
       }
     }
@@ -2190,7 +2196,11 @@ void bgroup_tune(lsamg_handle* h, hipStream_t s);
 template <int NB>
 void mm_tune_all(lsamg_handle* h, hipStream_t s) {
   if constexpr (NB >= 16) {
-    if (h->mm_tuned || h->dry) return;
+    // the k_bmm shapes are chosen by the first batch (of any width >= 16);
+    // the 64-column forms (dense-level GEMM, coarse residual) by the first
+    // batch of 64, which also re-times the dense level's k_bmm shape at 64
+    const bool need_mm = !h->mm_tuned, need64 = NB == 64 && !h->mm_tuned64;
+    if ((!need_mm && !need64) || h->dry) return;
     struct Quiet {                       // tuning launches are not profiled
       Profiler* p;
       lsamg_handle* h;
@@ -2202,17 +2212,25 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
     g_prof = nullptr;
     h->batch_alloc = true;               // task lists live with the batched buffers
     // partial sums of split loops: 16 slots of the dense level, or 4 slots
-    // of a coarse level's output (RAS/P^T/P: n unknowns; RAS-T: staging)
+    // of a coarse level's output (RAS/P^T/P: n unknowns; RAS-T: staging).
+    // The shapes chosen now serve every later batch up to the buffers' width
+    // (bwidth >= NB), so the buffer and the split limits are sized for it.
+    const int64_t W = std::max<int64_t>(NB, h->bwidth);
     int64_t cap = 0;
     for (size_t l = 0; l < h->L.size(); ++l) {
       DLevel& L = h->L[l];
       if (L.coarsest || L.tail) {
-        cap = std::max<int64_t>(cap, 16 * L.n * NB);
+        cap = std::max<int64_t>(cap, 16 * L.n * W);
         break;
       }
-      if (l > 0) cap = std::max<int64_t>(cap, 4 * std::max(L.n, L.ntb) * NB);
+      if (l > 0) cap = std::max<int64_t>(cap, 4 * std::max(L.n, L.ntb) * W);
     }
-    float* part = cap > 0 ? h->alloc<float>((size_t)cap) : nullptr;
+    if (!h->mm_part && cap > 0) {
+      h->mm_part = h->alloc<float>((size_t)cap);
+      h->mm_part_cap = cap;
+    }
+    float* part = h->mm_part;
+    cap = h->mm_part_cap;
     // 512 MiB written between timed launches evicts the 256 MiB last-level cache
     struct Flush {
       double* p = nullptr;
@@ -2236,6 +2254,7 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
           dense_tune(h, L, L.f.Ainv, B.fb, B.fx, part, cap, s, fl.p, flush_n, bmm_ms);
         break;
       }
+      if (!need_mm) continue;
       DLevel& C = h->L[l + 1];
       auto& BC = h->BL[l + 1];
       mm_tune<dev::IN_GATHER, false, NB>(h, L.ras, L.oidx, nullptr, nullptr, nullptr, L.f.Zc,
@@ -2254,6 +2273,7 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
     if (NB == 64) bgroup_tune(h, s);
     HIP_OK(hipStreamSynchronize(s));
     h->mm_tuned = true;
+    if (NB == 64) h->mm_tuned64 = true;
   }
 }
 
@@ -2859,6 +2879,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
         D.bg_on = false;
       }
       h->mm_tuned = false;
+      h->mm_tuned64 = false;
     }
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
   } else if (opt == LSAMG_OPT_GRAPH) {
@@ -2870,6 +2891,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->bgroup = (int)value;
     for (auto& D : h->L) D.bg_on = false;
     h->mm_tuned = false;                // decided again with the tiles on the next batched solve
+    h->mm_tuned64 = false;
     for (auto& D : h->L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
       D.dmm_split = 0;
@@ -2892,6 +2914,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
       D.dmm_split = 0;
     }
     h->mm_tuned = false;                // retuned (or fixed) on the next batched solve
+    h->mm_tuned64 = false;
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_DENSE_SPLIT) {
     h->dense_split = (int)value;
@@ -2900,6 +2923,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
       D.dmm_split = 0;
     }
     h->mm_tuned = false;
+    h->mm_tuned64 = false;
     h->drop_graphs(true);
   } else {
     return fail_with(LSAMG_EINVAL, "unknown option");

@@ -308,33 +308,39 @@ def test_batched_dense_level_every_split(which, request):
         s.set_precision(L.FP64)
 
 
+@pytest.mark.parametrize("which,bgroup", [("rot_tail", 0), ("rot", 1)])
 @pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
-def test_graph_replay_equals_eager(rot_tail, prec):
+def test_graph_replay_equals_eager(which, bgroup, prec, request):
     """Solves whose V-cycles replay a captured HIP graph are bit-identical to
     solves with the kernels launched one by one, on every replay, with eager
-    work and synchronisations between the replays; single and batched (the
-    batched FP32 V-cycle on matrix-core tiles)."""
+    work and synchronisations between the replays; single vector, 16 columns
+    and 64 columns (the batched FP32 V-cycle on matrix-core tiles, the dense
+    level's LDS-staged GEMM, the tiled finest-level G^T G, and on "rot" the
+    coarse levels' row-group pass)."""
     import torch
-    p, H, s = rot_tail
+    p, H, s = request.getfixturevalue(which)
     b = dvec(P.rhs_uniform(p.n, 7))
-    B = dvec(np.stack([P.rhs_uniform(p.n, 400 + j) for j in range(16)]))
+    Bs = [dvec(np.stack([P.rhs_uniform(p.n, 400 + j) for j in range(nc)])) for nc in (16, 64)]
     s.set_precision(prec)
     try:
+        s.set_option(L.OPT_BGROUP, bgroup)
         s.set_option(L.OPT_GRAPH, 0)
         x_e, st_e = s.solve(b, tol=1e-8)
-        X_e, St_e = s.solve(B, tol=1e-8)
+        out_e = [s.solve(B, tol=1e-8) for B in Bs]
         s.set_option(L.OPT_GRAPH, 1)
         for rep in range(3):
             x_g, st_g = s.solve(b, tol=1e-8)
-            X_g, St_g = s.solve(B, tol=1e-8)
             assert st_g[0]["iters"] == st_e[0]["iters"]
             assert np.array_equal(host(x_g), host(x_e)), rep
-            assert [t["iters"] for t in St_g] == [t["iters"] for t in St_e]
-            assert np.array_equal(host(X_g), host(X_e)), rep
+            for B, (X_e, St_e) in zip(Bs, out_e):
+                X_g, St_g = s.solve(B, tol=1e-8)
+                assert [t["iters"] for t in St_g] == [t["iters"] for t in St_e]
+                assert np.array_equal(host(X_g), host(X_e)), (rep, B.shape)
             s.apply(L.OP_A, b)                  # eager work between replays
             torch.cuda.synchronize()
     finally:
         s.set_option(L.OPT_GRAPH, 1)
+        s.set_option(L.OPT_BGROUP, 0)
         s.set_precision(L.FP64)
 
 
