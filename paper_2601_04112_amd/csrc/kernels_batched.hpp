@@ -675,9 +675,10 @@ __global__ void __launch_bounds__(kBlock) k_bgather_add(int64_t n, const int64_t
 
 // ---------------------------------------------------------------------------
 // Batched FP64 CG.  Column j has its own scalars.  A kernel that produces a
-// dot product stores one partial per workgroup and column
-// (part[blockIdx.x * NB + j]); k_bsum adds them in a fixed order into one
-// scalar per column, which the consuming kernels read.  active[j] = 0
+// dot product stores one partial per workgroup and column, column-major
+// (part[j * gridDim.x + blockIdx.x], so that a column's partials are
+// contiguous); k_bsum adds them in a fixed order into one scalar per column,
+// which the consuming kernels read.  active[j] = 0
 // freezes a converged column.
 // ---------------------------------------------------------------------------
 template <int NB>
@@ -689,20 +690,28 @@ __device__ __forceinline__ void bwrite_parts(double v, double* __restrict__ part
   if (threadIdx.x < NB) {
     double s = 0;
     for (int t = threadIdx.x; t < kBlock; t += NB) s += sm[t];
-    part[(int64_t)blockIdx.x * NB + threadIdx.x] = s;
+    part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = s;
   }
   __syncthreads();
 }
 
-// out[j] = sum over np workgroup partials of column j (one workgroup per
-// column; strided partial sums, then a fixed-order tree)
+// out[j] = sum over the np workgroup partials of column j (one workgroup per
+// column, coalesced reads; strided partial sums, then a fixed-order tree)
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_bsum(int np, const double* __restrict__ part,
                                                  double* __restrict__ out) {
   __shared__ double sm[kBlock];
   const int j = blockIdx.x;
-  double s = 0;
-  for (int b = threadIdx.x; b < np; b += kBlock) s += part[(int64_t)b * NB + j];
+  const double* __restrict__ p = part + (int64_t)j * np;
+  // eight independent partial sums per thread, so eight loads are in flight
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int b = threadIdx.x;
+  for (; b + 7 * kBlock < np; b += 8 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[b + u * kBlock];
+  }
+  for (; b < np; b += kBlock) a[0] += p[b];
+  const double s = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
   sm[threadIdx.x] = s;
   __syncthreads();
   for (int o = kBlock / 2; o > 0; o >>= 1) {
@@ -1123,8 +1132,8 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
 // and Z in FP64), so a wavefront carries four unknowns through each memory
 // round trip.  Z = (double)(XV + staged sum), the staged rows added in
 // position order as in k_bcg_z; partials of R . Z per column and workgroup
-// (part[blockIdx.x * 64 + j]) summed over the 16 unknown slots in a fixed
-// order.
+// (column-major, as bwrite_parts) summed over the 16 unknown slots in a
+// fixed order.
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restrict__ XV,
                                                     const int64_t* __restrict__ cptr,
@@ -1166,7 +1175,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restri
   if (threadIdx.x < 64) {
     double t = 0;
     for (int q = 0; q < SL; ++q) t += sm[q][threadIdx.x];
-    rz_part[(int64_t)blockIdx.x * 64 + threadIdx.x] = t;
+    rz_part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
   }
 }
 
