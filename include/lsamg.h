@@ -244,7 +244,9 @@ enum {
   LSAMG_OPT_MFMA_TILE = 3, /* 0 (default): the matrix-core tile shapes are
                              autotuned; 100*rt + 10*u + split fixes them for every
                              operator instead: rt in {1,2,4} row tiles of 16 per
-                             task, u in {2,8} loop steps loaded together, split in
+                             task, u in {2,8} loop steps loaded together (u = 0
+                             with rt = 4: on 64 columns the form that stages the
+                             input rows in LDS per 64-row task), split in
                              {1,2,4,8} loop ranges per task (reduced to 1 where
                              the partial-sum buffer is too small)               */
   LSAMG_OPT_ONEPASS_ATA = 4, /* 1 (default): where the rows of G are short (a

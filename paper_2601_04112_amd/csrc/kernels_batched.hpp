@@ -546,6 +546,97 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
   }
 }
 
+// k_bmm on 64 columns with the input rows staged in LDS: a workgroup per
+// task (aggregate a, 64 output rows j0 .. j0+63, loop range [k0, k1), slot),
+// its four waves 16 rows each.  The loop runs in chunks of 32 input rows
+// (formed per MODE as in k_bmm: direct, gathered, or plus the staged RAS-T
+// rows), staged once per workgroup instead of once per wave and double-
+// buffered, the next chunk's loads issued before the current chunk's MFMAs;
+// each wave reads its 16 matrix columns from global memory as k_bmm does.
+// Output as k_bmm (columns 4i .. 4i+3 in lane i; slot >= 0: partial sums).
+template <int MODE, bool ADD>
+__global__ void __launch_bounds__(kBlock) k_bmm_lds(MmTasks tk, GemvOp op,
+                                                    const int32_t* __restrict__ gidx,
+                                                    const int64_t* __restrict__ cptr,
+                                                    const int64_t* __restrict__ cpos,
+                                                    const float* __restrict__ tb,
+                                                    const float* __restrict__ M,
+                                                    const float* __restrict__ in,
+                                                    float* __restrict__ out,
+                                                    float* __restrict__ part, int64_t part_rows) {
+  constexpr int KC = 32, SB = 64 + 4, KS = KC / 4;
+  __shared__ __attribute__((aligned(16))) float sB[2][KC * SB];
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+  const int a = tk.a[t], j0 = tk.j0[t], k0 = tk.k0[t], k1 = tk.k1[t], slot = tk.slot[t];
+  const int nj = op.lj[a];
+  const int64_t ib = op.ibase[a];
+  const float* __restrict__ m = M + op.moff[a];
+  const int64_t ld = mrow(nj, op.pad);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int jr = j0 + 16 * w + i;            // this lane's output row (A operand row)
+  const bool jv = jr < nj;
+  const int sr = threadIdx.x >> 3, sc = 8 * (threadIdx.x & 7);
+  const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[4] = {zero, zero, zero, zero};
+  f32x4 bst[2];
+  float am[KS];
+  auto load_chunk = [&](int kb) {
+    const int l = kb + sr;
+    bst[0] = zero;
+    bst[1] = zero;
+    if (l < k1) {
+      const int64_t e = ib + l;
+      const int64_t row = MODE == IN_GATHER ? (int64_t)gidx[e] : e;
+      bst[0] = *(const f32x4*)(in + row * 64 + sc);
+      bst[1] = *(const f32x4*)(in + row * 64 + sc + 4);
+      if (MODE == IN_TB) {
+        for (int64_t p = cptr[e]; p < cptr[e + 1]; ++p) {
+          bst[0] += *(const f32x4*)(tb + cpos[p] * 64 + sc);
+          bst[1] += *(const f32x4*)(tb + cpos[p] * 64 + sc + 4);
+        }
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const int lk = kb + 4 * st + g;
+      am[st] = (jv && lk < k1) ? m[(int64_t)lk * ld + jr] : 0.f;
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) load_chunk(k0);
+  for (int kb = k0; kb < k1; kb += KC) {
+    *(f32x4*)(sB[buf] + sr * SB + sc) = bst[0];
+    *(f32x4*)(sB[buf] + sr * SB + sc + 4) = bst[1];
+    float av[KS];
+#pragma unroll
+    for (int st = 0; st < KS; ++st) av[st] = am[st];
+    __syncthreads();
+    if (kb + KC < k1) load_chunk(kb + KC);    // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const f32x4 b = *(const f32x4*)(sB[buf] + (4 * st + g) * SB + 4 * i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[st], b[q], acc[q], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int jj = j0 + 16 * w + 4 * g + v;
+    if (jj >= nj) continue;
+    f32x4 o = {acc[0][v], acc[1][v], acc[2][v], acc[3][v]};
+    if (slot >= 0) {
+      *(f32x4*)(part + ((int64_t)slot * part_rows + op.obase[a] + jj) * 64 + 4 * i) = o;
+    } else {
+      float* d = out + (op.obase[a] + jj) * 64 + 4 * i;
+      if (ADD) o += *(const f32x4*)d;
+      *(f32x4*)d = o;
+    }
+  }
+}
+
 // Dense level operator on 64 right-hand sides (FP32 MFMA): OUT = M IN with M
 // n x n stored row-major with a padded row stride ld (a multiple of 4,
 // padding zero; k_pad_rows makes it), and IN, OUT interleaved n x 64.  A workgroup computes

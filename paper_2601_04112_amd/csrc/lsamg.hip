@@ -103,6 +103,7 @@ struct GemvPlan {
     int rt = 0;              // row tiles of 16 per task (0: not tuned, use k_bgemm)
     int u = 2;               // loop steps whose loads are issued together (2 or 8)
     int split = 1;           // loop split of a single-aggregate operator
+    bool lds = false;        // 64 columns: the LDS-staged form (k_bmm_lds, 64-row tasks)
     int64_t ntask = 0;
     unsigned grid = 0;       // workgroups of the persistent launch
     dev::MmTasks tk{};
@@ -1802,7 +1803,18 @@ void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
                 const int64_t* cptr, const int64_t* cpos, const float* tb, const float* M,
                 const float* in, float* out, hipStream_t s, double bytes) {
   const bool split = mm.split > 1;
-  {
+  bool done = false;
+  if constexpr (NB == 64) {
+    if (mm.lds) {
+      PROF(kname("k_bmm_lds", std::to_string(MODE) + ", " + (ADD ? "true" : "false")),
+           split ? bytes - sizeof(float) * (double)P.out * NB : bytes, s);
+      KLAUNCH((unsigned)mm.ntask, dev::kBlock, 0, s, dev::k_bmm_lds<MODE, ADD>, mm.tk, P.op, gidx,
+              cptr, cpos, tb, M, in, split ? mm.part : out, mm.part, (int64_t)P.out);
+      LAUNCH_OK();
+      done = true;
+    }
+  }
+  if (!done) {
     PROF(kname("k_bmm", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
                             std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
                             std::to_string(NB)),
@@ -1869,23 +1881,30 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
   struct Cand {
     int rt, u, sp;
+    bool lds;
   };
   std::vector<Cand> cand;
   if (h->mm_fixed > 0) {               // a fixed tile shape (LSAMG_OPT_MFMA_TILE)
-    const int rt = h->mm_fixed / 100, u = (h->mm_fixed / 10) % 10;
+    const int rt = h->mm_fixed / 100;
+    int u = (h->mm_fixed / 10) % 10;
     int sp = h->mm_fixed % 10;
     if ((int64_t)sp * P.out * std::max<int64_t>(NB, h->bwidth) > part_cap) sp = 1;
-    cand.push_back(Cand{rt, u, sp});
+    const bool lds = u == 0 && NB == 64;  // u = 0: the LDS-staged form (64 columns)
+    if (u == 0) u = 2;
+    cand.push_back(Cand{rt, u, sp, lds});
   }
+  const bool fixed = !cand.empty();
   for (int rt : {1, 2, 4}) {
-    if (!cand.empty()) break;
+    if (fixed) break;                                     // the shape is given
     if (rt > 1 && 16 * (rt / 2) >= ljmax) continue;      // the tile would be mostly empty
     for (int u : {2, 8}) {
       if (u == 8 && llmax <= 8) continue;                 // one step covers the loop
       for (int sp : {1, 2, 4, 8, 16}) {
         if (sp > 1 && (llmax / sp < (P.nagg == 1 ? 256 : 64) || (P.nagg > 1 && sp > 4))) continue;
         if ((int64_t)sp * P.out * std::max<int64_t>(NB, h->bwidth) > part_cap) continue;
-        cand.push_back(Cand{rt, u, sp});
+        cand.push_back(Cand{rt, u, sp, false});
+        // the LDS-staged form on 64 columns: 64-row tasks, same loop splits
+        if (NB == 64 && rt == 4 && u == 2) cand.push_back(Cand{4, 2, sp, true});
       }
     }
   }
@@ -1893,10 +1912,11 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   HIP_OK(hipEventCreate(&e0));
   HIP_OK(hipEventCreate(&e1));
   float best = 1e30f;
-  Cand pick{1, 2, 1};
+  Cand pick{1, 2, 1, false};
   for (auto c : cand) {
     GemvPlan::Mm mm = mm_build(h, P, c.rt, c.sp, true);
     mm.u = c.u;
+    mm.lds = c.lds;
     mm.part = part;
     float ms = 1e30f;
     try {
@@ -1934,6 +1954,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   (void)hipEventDestroy(e1);
   P.mm = mm_build(h, P, pick.rt, pick.sp, false);
   P.mm.u = pick.u;
+  P.mm.lds = pick.lds;
   P.mm.part = part;
   return best;
 }
@@ -2905,7 +2926,8 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_MFMA_TILE) {
     const int64_t rt = value / 100, u = (value / 10) % 10, sp = value % 10;
-    if (value != 0 && (value >= 1000 || (rt != 1 && rt != 2 && rt != 4) || (u != 2 && u != 8) ||
+    if (value != 0 && (value >= 1000 || (rt != 1 && rt != 2 && rt != 4) ||
+                       (u != 2 && u != 8 && !(u == 0 && rt == 4)) ||
                        (sp != 1 && sp != 2 && sp != 4 && sp != 8)))
       return fail_with(LSAMG_EINVAL, "bad tile shape");
     h->mm_fixed = (int)value;

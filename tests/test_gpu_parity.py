@@ -268,14 +268,19 @@ def test_batched_vcycle_every_tile_shape(which, request):
     s.set_precision(L.MIXED)
     try:
         Y1 = [host(s.apply(L.OP_VCYCLE, dX[j])) for j in range(0, 64, 7)]
-        for rt in (1, 2, 4):
-            for u in (2, 8):
-                for sp in (1, 2, 4, 8):
-                    s.set_option(L.OPT_MFMA_TILE, 100 * rt + 10 * u + sp)
-                    Y = host(s.apply_vcycle_batch(dX))
-                    for k, j in enumerate(range(0, 64, 7)):
-                        assert rel(Y[j], Y1[k]) <= 2e-5, (rt, u, sp, j, rel(Y[j], Y1[k]))
+        # u = 0: the form that stages the input rows in LDS (64-row tasks)
+        for rt, u in ((1, 2), (1, 8), (2, 2), (2, 8), (4, 2), (4, 8), (4, 0)):
+            for sp in (1, 2, 4, 8):
+                s.set_option(L.OPT_MFMA_TILE, 100 * rt + 10 * u + sp)
+                s.profile(True)
+                Y = host(s.apply_vcycle_batch(dX))
+                names = {k["name"].split("<")[0] for k in s.profile_read()}
+                s.profile(False)
+                assert ("k_bmm_lds" in names) == (u == 0), (rt, u, sp, sorted(names))
+                for k, j in enumerate(range(0, 64, 7)):
+                    assert rel(Y[j], Y1[k]) <= 2e-5, (rt, u, sp, j, rel(Y[j], Y1[k]))
     finally:
+        s.profile(False)
         s.set_option(L.OPT_MFMA_TILE, 0)
         s.set_precision(L.FP64)
 
