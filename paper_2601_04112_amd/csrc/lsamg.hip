@@ -1869,9 +1869,10 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
 }
 
 // Autotuner of the matrix-core batched GEMM: every candidate tile shape (row
-// tiles per task, and the loop split of a single-aggregate operator) is timed
-// on the operator's own matrices and buffers (one warm-up and three timed
-// launches), and the fastest is kept.
+// tiles per task, loads in flight, loop split, and on 64 columns the
+// LDS-staged form) is timed on the operator's own matrices and buffers (one
+// warm-up and three timed launches, each after evicting the last-level
+// cache), and the fastest is kept.
 template <int MODE, bool ADD, int NB>
 float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
              const int64_t* cpos, const float* tb, const float* M, const float* in, float* out,
@@ -1898,7 +1899,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
     if (fixed) break;                                     // the shape is given
     if (rt > 1 && 16 * (rt / 2) >= ljmax) continue;      // the tile would be mostly empty
     for (int u : {2, 8}) {
-      if (u == 8 && llmax <= 8) continue;                 // one step covers the loop
+      if (u == 8 && llmax <= 32) continue;                // a few steps cover the loop
       for (int sp : {1, 2, 4, 8, 16}) {
         if (sp > 1 && (llmax / sp < (P.nagg == 1 ? 256 : 64) || (P.nagg > 1 && sp > 4))) continue;
         if ((int64_t)sp * P.out * std::max<int64_t>(NB, h->bwidth) > part_cap) continue;
@@ -1921,7 +1922,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
     float ms = 1e30f;
     try {
       bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
-      for (int round = 0; round < 2; ++round) {   // best of two rounds of three launches
+      for (int round = 0; round < 1; ++round) {   // three launches after the warm-up
         float tot = 0.f;
         for (int r = 0; r < 3; ++r) {
           // in a V-cycle the operator's matrix arrives from HBM, not from the
@@ -2030,7 +2031,7 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
         if (S > 1 && !part) dense_split_shape(n, 1, KC, &S, &kc);
         dense_mm_launch(L, S, kc, KC, in, out, part, s);
         float ms = 1e30f;
-        for (int round = 0; round < 2; ++round) {
+        for (int round = 0; round < 1; ++round) {   // three launches after the warm-up
           float tot = 0.f;
           for (int r = 0; r < 3; ++r) {
             if (flush)
@@ -2299,8 +2300,8 @@ void mm_tune_all(lsamg_handle* h, hipStream_t s) {
 }
 
 // Coarse-level residual on 64 columns, FP32: the row-group pass against the
-// two CSR passes, each timed on the level's own buffers (one warm-up, best of
-// two rounds of three), unless LSAMG_OPT_BGROUP fixes the form.
+// two CSR passes, each timed on the level's own buffers (one warm-up and
+// three timed applications), unless LSAMG_OPT_BGROUP fixes the form.
 void bgroup_tune(lsamg_handle* h, hipStream_t s) {
   hipEvent_t e0, e1;
   HIP_OK(hipEventCreate(&e0));
@@ -2320,7 +2321,7 @@ void bgroup_tune(lsamg_handle* h, hipStream_t s) {
       for (int form = 0; form < 2; ++form) {
         L.bg_on = form == 1;
         bresidual<float, 64>(L, V, V.x, V.b, V.r, s);
-        for (int round = 0; round < 2; ++round) {
+        for (int round = 0; round < 1; ++round) {   // three launches after the warm-up
           HIP_OK(hipEventRecord(e0, s));
           for (int r = 0; r < 3; ++r) bresidual<float, 64>(L, V, V.x, V.b, V.r, s);
           HIP_OK(hipEventRecord(e1, s));
