@@ -158,7 +158,7 @@ struct DLevel {
   // most 32 rows, staged rows of 64 values; tuned against the CSR passes
   dev::GrpTasks bgtask{};
   int64_t bg_ntask = 0, bg_nstg = 0;
-  int bg_wmax = 0, bg_rmax = 0;
+  int bg_wmax = 0;        // most support columns of a task
   int64_t* bg_cptr = nullptr;
   int64_t* bg_cpos = nullptr;
   bool bg_ok = false;     // tasks built
@@ -445,7 +445,7 @@ void build_bgroup_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
   std::vector<int32_t> nr, t0v, cv;
   std::vector<std::pair<int32_t, int64_t>> cover;
   int64_t row = 0, nstg = 0;
-  int wmax = 0, rmax = 0;
+  int wmax = 0;
   for (int64_t g = 0; g < G.ng(); ++g) {
     const int c = (int)(G.sptr[g + 1] - G.sptr[g]);
     const int ntk = (G.nrows[g] + RPT - 1) / RPT;
@@ -454,7 +454,6 @@ void build_bgroup_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
       const int w = c - t0, k = std::min(chunk, G.nrows[g] - t0);
       if (w > WMAX) return;
       wmax = std::max(wmax, w);
-      rmax = std::max(rmax, k);
       vs.push_back(gp[row + t0]);
       nr.push_back(k);
       t0v.push_back(t0);
@@ -478,7 +477,6 @@ void build_bgroup_tasks(lsamg_handle* h, const Level& HL, DLevel& D,
   D.bg_ntask = (int64_t)vs.size();
   D.bg_nstg = nstg;
   D.bg_wmax = wmax;
-  D.bg_rmax = rmax;
   D.bg_cptr = h->upload(cp);
   D.bg_cpos = h->upload(cs);
   D.bg_ok = true;
