@@ -265,7 +265,11 @@ enum {
                              G^T (G X) of the V-cycle residual and of the CG (with
                              LSAMG_OPT_ONEPASS_ATA) runs in one pass over tiles of
                              16 unknowns whose input rows are staged once in LDS,
-                             where G's rows are short enough; 0: the untiled forms */
+                             where G's rows are short enough (FP32 forming the
+                             tile's rows of G X first, FP64 from each unknown's
+                             expanded stencil); 2 or 3: the row form or the
+                             expanded form in both precisions; 0: the untiled
+                             forms                                              */
   LSAMG_OPT_BGROUP = 7    /* 0 (default): on 64 columns in FP32, each coarse
                              level's residual runs as the row-group pass (R_g^T R_g
                              per group, staged) or as two CSR passes, whichever the

@@ -905,6 +905,8 @@ struct AtaTiles {
   const int32_t* rptr;    // [ntile + 1] offsets of R_t (rows of the tile order)
   const uint16_t* rli;    // [rows * MF] position in U_t of each row entry's column
   const uint16_t* drl;    // [n * ME] position in R_t of each unknown's rows
+  const uint16_t* eli;    // [n * ME * MF] expanded form: position in U_t of entry q of
+                          // row k of each unknown (values in ev, row weights in dw)
   int64_t ntile;
   int umax;               // largest |U_t| (LDS stride of the second buffer)
 };
@@ -979,6 +981,83 @@ __global__ void __launch_bounds__(kBlock) k_bata_tile(int64_t n, AtaTiles tl,
 #pragma unroll
       for (int k = 0; k < ME; ++k)
         acc += lane_val(ww, u * ME + k) * sY[(int64_t)lane_val(lid, u * ME + k) * 64 + lane];
+      const int64_t o = (d0 + db + u) * 64 + lane;
+      if constexpr (EPI == 0) {
+        R[o] = bv[u] - acc;
+      } else {
+        R[o] = acc;
+        v += (double)acc * (double)bv[u];
+      }
+    }
+    __syncthreads();                  // LDS is refilled by the next tile
+  }
+  if constexpr (EPI == 1) bwrite_parts<64>(v, part);
+}
+
+// The same one-pass G^T (G X) on 64 columns without the row phase: each
+// unknown carries its whole expanded stencil (for each of its rows k of G in
+// G^T order, the row's entries q in row order as (position in U_t, value)),
+// so a wavefront forms sum_k G[r_k][d] (sum_q G[r_k][c_q] X[c_q]) straight
+// from the staged X rows, in the order and arithmetic of ata_row64.  One LDS
+// buffer (umax * 64 * sizeof(T)) and one barrier per tile.  EPI as
+// k_bata_tile.
+template <typename T, int TS, int ME, int MF, int EPI>
+__global__ void __launch_bounds__(kBlock) k_bata_tilex(int64_t n, AtaTiles tl,
+                                                       const T* __restrict__ ev,
+                                                       const T* __restrict__ dw,
+                                                       const T* __restrict__ X,
+                                                       const T* __restrict__ B,
+                                                       T* __restrict__ R,
+                                                       double* __restrict__ part) {
+  constexpr int WPB = kBlock / 64;
+  constexpr int DPW = TS / WPB;                    // unknowns per wavefront
+  constexpr int EN = ME * MF;                      // stencil entries per unknown
+  static_assert(TS % WPB == 0 && EN <= 64, "one entry per lane");
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  T* sX = (T*)lds_raw;
+  constexpr int VPR = 64 * (int)sizeof(T) / 16;   // 16-byte pieces per row of X
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  double v = 0;
+  for (int64_t t = xcd_block(blockIdx.x, gridDim.x); t < tl.ntile; t += gridDim.x) {
+    const int64_t d0 = t * TS;
+    const int nd = (int)(n - d0 < TS ? n - d0 : TS);
+    const int db = w * DPW, nwd = nd - db < DPW ? (nd - db > 0 ? nd - db : 0) : DPW;
+    // this wavefront's unknowns first: stencils, row weights, B
+    int li[DPW];
+    T vv[DPW], ww[DPW], bv[DPW];
+#pragma unroll
+    for (int u = 0; u < DPW; ++u) {
+      li[u] = 0;
+      vv[u] = ww[u] = bv[u] = T(0);
+      if (u < nwd) {
+        const int64_t d = d0 + db + u;
+        li[u] = tl.eli[d * EN + (lane < EN ? lane : 0)];
+        vv[u] = lane < EN ? ev[d * EN + lane] : T(0);
+        ww[u] = lane < ME ? dw[d * ME + lane] : T(0);
+        bv[u] = B[d * 64 + lane];
+      }
+    }
+    const int u0 = tl.uptr[t], nu = tl.uptr[t + 1] - u0;
+    for (int e = threadIdx.x; e < nu * VPR; e += kBlock) {
+      const int row = e / VPR, pc = e - row * VPR;
+      const int64_t c = tl.ucol[u0 + row];
+      *(f32x4*)((char*)(sX + (int64_t)row * 64) + 16 * pc) =
+          *(const f32x4*)((const char*)(X + c * 64) + 16 * pc);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < DPW; ++u) {
+      if (u >= nwd) break;
+      T acc = 0;
+#pragma unroll
+      for (int k = 0; k < ME; ++k) {
+        T y = 0;
+#pragma unroll
+        for (int q = 0; q < MF; ++q)
+          y += lane_val(vv[u], k * MF + q) * sX[(int64_t)lane_val(li[u], k * MF + q) * 64 + lane];
+        acc += lane_val(ww[u], k) * y;
+      }
       const int64_t o = (d0 + db + u) * 64 + lane;
       if constexpr (EPI == 0) {
         R[o] = bv[u] - acc;

@@ -72,6 +72,7 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* stg = nullptr;       // staged G^T G x of the row-group pass (coarse levels)
   T* trv = nullptr;       // tiled one-pass G^T G: row entry values of each tile
   T* tdw = nullptr;       // tiled one-pass G^T G: G^T entry values per unknown
+  T* tev = nullptr;       // tiled one-pass G^T G, expanded form: stencil entry values
 };
 
 // Launch plan of one batched-GEMV operator on one level.
@@ -126,6 +127,9 @@ struct DLevel {
   int at_rmax = 0;        // largest row list of a tile
   bool at_ok = false;     // tiles built
   bool at_on = false;     // ... and in use (LSAMG_OPT_ATA_TILES)
+  int at_form = 0;        // 0: per precision (FP32 with the row phase, FP64 expanded
+                          // stencils, the faster of each on the benchmark); 2: row phase;
+                          // 3: expanded stencils
   dev::AtaTiles at1{};    // tiles of the single-vector CG's k_cg_tile (FP64)
   int at1_rmax = 0;
   double *trv1 = nullptr, *tdw1 = nullptr;
@@ -608,8 +612,8 @@ void make_dense_plan(lsamg_handle* h, DLevel& D) {
 // not fit one metadata load.
 struct TileHost {
   std::vector<int32_t> uptr{0}, ucol, rptr{0};
-  std::vector<uint16_t> rli, drl;
-  std::vector<double> rv, dw;
+  std::vector<uint16_t> rli, drl, eli;
+  std::vector<double> rv, dw, ev;
   int umax = 0, rmax = 0;
   int64_t ntile = 0;
 };
@@ -617,12 +621,16 @@ struct TileHost {
 bool make_tiles(const DLevel& D, const std::vector<int64_t>& gp, const std::vector<int32_t>& gc,
                 const std::vector<double>& gv, const std::vector<int64_t>& tp,
                 const std::vector<int32_t>& tc, const std::vector<double>& tv, int TS,
-                int64_t row_bytes, bool wave_rows, TileHost& T) {
+                int64_t row_bytes, bool wave_rows, bool expand, TileHost& T) {
   const int ME = D.ata_me, MF = D.ata_mf;
   const int64_t n = D.n;
   T.ntile = (n + TS - 1) / TS;
   T.drl.assign((size_t)n * ME, 0);
   T.dw.assign((size_t)n * ME, 0.0);
+  if (expand) {
+    T.eli.assign((size_t)n * ME * MF, 0);
+    T.ev.assign((size_t)n * ME * MF, 0.0);
+  }
   std::vector<int32_t> rows, cols;
   auto pos = [](const std::vector<int32_t>& v, int32_t x) {
     return (uint16_t)(std::lower_bound(v.begin(), v.end(), x) - v.begin());
@@ -654,6 +662,13 @@ bool make_tiles(const DLevel& D, const std::vector<int64_t>& gp, const std::vect
         if (e >= tp[d + 1]) continue;
         T.drl[(size_t)d * ME + k] = pos(rows, tc[e]);
         T.dw[(size_t)d * ME + k] = tv[e];
+        // expanded form: the row's entries, in row order
+        const int32_t r = tc[e];
+        for (int q = 0; expand && q < MF && gp[r] + q < gp[r + 1]; ++q) {
+          const size_t x = ((size_t)d * ME + k) * MF + q;
+          T.eli[x] = pos(cols, gc[gp[r] + q]);
+          T.ev[x] = gv[gp[r] + q];
+        }
       }
     T.ucol.insert(T.ucol.end(), cols.begin(), cols.end());
     T.uptr.push_back((int32_t)T.ucol.size());
@@ -664,7 +679,7 @@ bool make_tiles(const DLevel& D, const std::vector<int64_t>& gp, const std::vect
 
 dev::AtaTiles upload_tiles(lsamg_handle* h, const TileHost& T) {
   return dev::AtaTiles{h->upload(T.uptr), h->upload(T.ucol), h->upload(T.rptr), h->upload(T.rli),
-                       h->upload(T.drl), T.ntile, T.umax};
+                       h->upload(T.drl), h->upload(T.eli), T.ntile, T.umax};
 }
 
 void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
@@ -673,19 +688,21 @@ void build_ata_tiles(lsamg_handle* h, DLevel& D, const std::vector<int64_t>& gp,
                      const std::vector<double>& tv) {
   {
     TileHost T;
-    if (make_tiles(D, gp, gc, gv, tp, tc, tv, kAtaTile, 64 * 8, true, T)) {
+    if (make_tiles(D, gp, gc, gv, tp, tc, tv, kAtaTile, 64 * 8, true, true, T)) {
       D.at = upload_tiles(h, T);
       D.at_rmax = T.rmax;
       D.d.trv = h->upload_f<double>(T.rv);
       D.f.trv = h->upload_f<float>(T.rv);
       D.d.tdw = h->upload_f<double>(T.dw);
       D.f.tdw = h->upload_f<float>(T.dw);
+      D.d.tev = h->upload_f<double>(T.ev);
+      D.f.tev = h->upload_f<float>(T.ev);
       D.at_ok = D.at_on = true;
     }
   }
   {
     TileHost T;
-    if (make_tiles(D, gp, gc, gv, tp, tc, tv, dev::kBlock, 8, false, T)) {
+    if (make_tiles(D, gp, gc, gv, tp, tc, tv, dev::kBlock, 8, false, false, T)) {
       D.at1 = upload_tiles(h, T);
       D.at1_rmax = T.rmax;
       D.trv1 = h->upload_f<double>(T.rv);
@@ -2076,11 +2093,34 @@ void bata_tile(const DLevel& L, const T* X, const T* B, T* R, double* part, hipS
   const DPrec<T>& P = prec<T>(const_cast<DLevel&>(L));
   const size_t lds = (size_t)(L.at.umax + L.at_rmax) * 64 * sizeof(T);
   const unsigned grid = EPI == 1 ? (unsigned)kBNP : (unsigned)L.at.ntile;
-  PROF(kname("k_bata_tile", std::string(tname<T>()) + ", " + std::to_string(kAtaTile) + ", " +
+  const bool rows = L.at_form == 2 || (L.at_form == 0 && sizeof(T) == sizeof(float));
+  PROF(kname(rows ? "k_bata_tile" : "k_bata_tilex",
+             std::string(tname<T>()) + ", " + std::to_string(kAtaTile) + ", " +
                                 std::to_string(L.ata_me) + ", " + std::to_string(L.ata_mf) + ", " +
                                 std::to_string(EPI)),
        (double)sizeof(T) * L.n * 64 * 3 + (double)L.nnz * (sizeof(T) + 4) + 8.0 * (L.n + L.nrows),
        s);
+  if (!rows) {
+    auto launchx = [&](auto kern) {
+      KLAUNCH(grid, dev::kBlock, (size_t)L.at.umax * 64 * sizeof(T), s, kern, L.n, L.at,
+              (const T*)P.tev, (const T*)P.tdw, X, B, R, part);
+    };
+    const int me = L.ata_me, mf = L.ata_mf;
+    if (me == 6 && mf == 3)
+      launchx(dev::k_bata_tilex<T, kAtaTile, 6, 3, EPI>);
+    else if (me == 6)
+      launchx(dev::k_bata_tilex<T, kAtaTile, 6, 4, EPI>);
+    else if (me == 8 && mf == 3)
+      launchx(dev::k_bata_tilex<T, kAtaTile, 8, 3, EPI>);
+    else if (me == 8)
+      launchx(dev::k_bata_tilex<T, kAtaTile, 8, 4, EPI>);
+    else if (mf == 3)
+      launchx(dev::k_bata_tilex<T, kAtaTile, 16, 3, EPI>);
+    else
+      launchx(dev::k_bata_tilex<T, kAtaTile, 16, 4, EPI>);
+    LAUNCH_OK();
+    return;
+  }
   auto launch = [&](auto kern) {
     KLAUNCH(grid, dev::kBlock, lds, s, kern, L.n, L.at, (const T*)P.trv, (const T*)P.tdw, X, B, R,
             part);
@@ -2884,9 +2924,9 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
 
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
   if (!h || value < 0 || (opt == LSAMG_OPT_DENSE_SPLIT && value > 17) ||
-      (opt == LSAMG_OPT_BGROUP && value > 2) ||
+      (opt == LSAMG_OPT_BGROUP && value > 2) || (opt == LSAMG_OPT_ATA_TILES && value > 3) ||
       (opt != LSAMG_OPT_MFMA_TILE && opt != LSAMG_OPT_DENSE_SPLIT && opt != LSAMG_OPT_BGROUP &&
-       value > 1))
+       opt != LSAMG_OPT_ATA_TILES && value > 1))
     return fail_with(LSAMG_EINVAL, "bad argument");
   if (opt == LSAMG_OPT_BATCHED) {
     h->batch_mode = (int)value;
@@ -2920,6 +2960,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
   } else if (opt == LSAMG_OPT_ATA_TILES) {
     for (auto& D : h->L) {
       D.at_on = value != 0 && D.at_ok;
+      D.at_form = value >= 2 ? (int)value : 0;
       D.at1_on = value != 0 && D.at1_ok;
     }
     h->drop_graphs(true);

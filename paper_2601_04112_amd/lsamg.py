@@ -304,7 +304,8 @@ class Solver:
         _check(load().lsamg_set_precision(self._h, precision))
 
     def set_option(self, opt: int, value: int):
-        """OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_ONEPASS_ATA, OPT_ATA_TILES (value 0 or 1), OPT_MFMA_TILE
+        """OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_ONEPASS_ATA (value 0 or 1), OPT_ATA_TILES
+        (0 off, 1 per precision, 2 row form, 3 expanded form), OPT_MFMA_TILE
         (0: autotune, else 100*rt + 10*u + split) or OPT_DENSE_SPLIT (0: autotune,
         1..16: LDS-staged dense GEMM with that many loop ranges, 17: never) or OPT_BGROUP
         (0: autotune, 1: row-group pass, 2: CSR passes)."""

@@ -387,22 +387,28 @@ def test_batched_tiled_ata(rot):
         for prec, tol in ((L.FP64, 1e-12), (L.MIXED, 2e-5)):
             s.set_precision(prec)
             out = {}
-            for on in (1, 0):
+            # 2: with the row phase (k_bata_tile); 3: expanded stencils
+            # (k_bata_tilex); 1: the row form in FP32, the expanded one in FP64
+            for on in (1, 2, 3, 0):
                 s.set_option(L.OPT_ATA_TILES, on)
                 s.profile(True)
                 out[on] = host(s.apply_vcycle_batch(dB))
                 names = {k["name"].split("<")[0] for k in s.profile_read()}
                 s.profile(False)
-                assert ("k_bata_tile" in names) == bool(on), (prec, on, sorted(names))
-            for j in (0, 21, 63):
-                assert rel(out[1][j], out[0][j]) <= tol, (prec, j, rel(out[1][j], out[0][j]))
+                x = on == 3 or (on == 1 and prec == L.FP64)
+                assert ("k_bata_tilex" in names) == x, (prec, on, sorted(names))
+                assert ("k_bata_tile" in names) == (on != 0 and not x), (prec, on, sorted(names))
+            for on in (1, 2, 3):
+                for j in (0, 21, 63):
+                    assert rel(out[on][j], out[0][j]) <= tol, (prec, on, j, rel(out[on][j], out[0][j]))
         s.set_precision(L.FP64)
         X = {}
-        for on in (1, 0):
+        for on in (1, 2, 3, 0):
             s.set_option(L.OPT_ATA_TILES, on)
             X[on], _ = s.solve(dB, tol=0.0, maxit=8)
-        for j in (0, 40, 63):
-            assert rel(host(X[1][j]), host(X[0][j])) <= 1e-10, j
+        for on in (1, 2, 3):
+            for j in (0, 40, 63):
+                assert rel(host(X[on][j]), host(X[0][j])) <= 1e-10, (on, j)
         s.set_option(L.OPT_ATA_TILES, 1)
         s.set_precision(L.MIXED)
         Xm, st = s.solve(dB, tol=1e-8)

@@ -163,11 +163,11 @@ def test_set_option_values():
     ok = [(L.OPT_BATCHED, 0), (L.OPT_BATCHED, 1), (L.OPT_MFMA, 0), (L.OPT_MFMA, 1),
           (L.OPT_GRAPH, 0), (L.OPT_ONEPASS_ATA, 1), (L.OPT_MFMA_TILE, 0),
           (L.OPT_MFMA_TILE, 428), (L.OPT_MFMA_TILE, 404), (L.OPT_DENSE_SPLIT, 16), (L.OPT_DENSE_SPLIT, 17),
-          (L.OPT_ATA_TILES, 0), (L.OPT_BGROUP, 2), (L.OPT_BGROUP, 0)]
+          (L.OPT_ATA_TILES, 0), (L.OPT_ATA_TILES, 3), (L.OPT_BGROUP, 2), (L.OPT_BGROUP, 0)]
     for opt, v in ok:
         assert lib.lsamg_set_option(s._h, opt, v) == L.LSAMG_OK, (opt, v)
     bad = [(L.OPT_BATCHED, 2), (L.OPT_GRAPH, -1), (L.OPT_MFMA_TILE, 123),
-           (L.OPT_MFMA_TILE, 1000), (L.OPT_MFMA_TILE, 104), (L.OPT_DENSE_SPLIT, 18), (L.OPT_ATA_TILES, 2),
+           (L.OPT_MFMA_TILE, 1000), (L.OPT_MFMA_TILE, 104), (L.OPT_DENSE_SPLIT, 18), (L.OPT_ATA_TILES, 4),
            (L.OPT_BGROUP, 3), (99, 0)]
     for opt, v in bad:
         assert lib.lsamg_set_option(s._h, opt, v) == L.LSAMG_EINVAL, (opt, v)
