@@ -314,14 +314,14 @@ def main():
     print(f"fp64 {fp64['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
 
     # batched workload: the same operator with 64 right-hand sides (seeds
-    # 100-163) solved together, one FP64 CG per column, FP32 V-cycle
-    batched = None
-    if args.batch > 0:
+    # 100-163) solved together, one FP64 CG per column, with the FP32
+    # V-cycle and again with the FP64 one
+    def run_batched(prec, peak, steps):
         import numpy as np
         B = torch.tensor(np.stack([P.rhs_uniform(prob.n, 100 + j) for j in range(args.batch)]),
                          dtype=torch.float64, device="cuda:0")
         XB = torch.empty_like(B)
-        s.set_precision(L.MIXED)
+        s.set_precision(prec)
         s.solve(B, tol=1e-8, out=XB)     # first batched solve: autotunes the MFMA tiles
         s.profile(True, by_level=True)
         s.solve(B, tol=1e-8, out=XB)
@@ -340,31 +340,40 @@ def main():
         lt = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
         nt = inf["levels"][lt]["n"]
         for r in bkl:
-            if (r["name"].startswith("k_bmm<") or r["name"].startswith("k_dense_mm64")) \
+            if (r["name"].startswith("k_bmm<") or r["name"].startswith("k_dense_mm64")
+                    or r["name"].startswith("k_bgemm<")) \
                     and r["name"].endswith(f"@L{lt}") and r["launches"]:
                 us = r["ms"] / r["launches"] * 1e3
                 tf = 2.0 * nt * nt * args.batch / (us * 1e-6) / 1e12
                 mfma = dict(kernel=r["name"], n=nt, nrhs=args.batch, avg_launch_us=round(us, 2),
-                            achieved=round(tf, 2), peak=157.3, unit="TFLOP/s",
-                            frac=round(tf / 157.3, 4))
-        nb_steps = max(2, args.steps // 4)
+                            achieved=round(tf, 2), peak=peak, unit="TFLOP/s",
+                            frac=round(tf / peak, 4))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        for _ in range(nb_steps):
+        for _ in range(steps):
             _, bst = s.solve(B, tol=1e-8, out=XB)
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         its = [r["iters"] for r in bst]
-        batched = dict(nrhs=args.batch, solves_per_s=round(args.batch * nb_steps / el, 2),
-                       ms_per_batch=round(el * 1e3 / nb_steps, 3), steps=nb_steps,
-                       iters_min=min(its), iters_max=max(its),
-                       all_converged=all(r["converged"] for r in bst),
-                       max_true_rel_res=max(r["true_rel_res"] for r in bst),
-                       mfma_dense=mfma,
-                       top_kernels=[dict(name=r["name"], ms_per_batch=round(r["ms"], 3),
-                                         launches=r["launches"],
-                                         gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1))
-                                    for r in bk[:6]])
+        return dict(nrhs=args.batch, solves_per_s=round(args.batch * steps / el, 2),
+                    ms_per_batch=round(el * 1e3 / steps, 3), steps=steps,
+                    iters_min=min(its), iters_max=max(its),
+                    all_converged=all(r["converged"] for r in bst),
+                    max_true_rel_res=max(r["true_rel_res"] for r in bst),
+                    mfma_dense=mfma,
+                    top_kernels=[dict(name=r["name"], ms_per_batch=round(r["ms"], 3),
+                                      launches=r["launches"],
+                                      gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1))
+                                 for r in bk[:6]])
+
+    batched = batched64 = None
+    if args.batch > 0:
+        batched = run_batched(L.MIXED, 157.3, max(2, args.steps // 4))
+        print(f"batched mixed {batched['solves_per_s']:.2f} solves/s", file=sys.stderr,
+              flush=True)
+        batched64 = run_batched(L.FP64, 78.6, 2)
+        print(f"batched fp64 {batched64['solves_per_s']:.2f} solves/s", file=sys.stderr,
+              flush=True)
     dom = next((r for r in kp if r["name"] == dominant), None)
     roofline = None
     if dom and dom["launches"] > 0 and dom["ms"] > 0:
@@ -441,6 +450,7 @@ def main():
         "fp64": {k: (round(v, 4) if isinstance(v, float) and k != "true_rel_res" else v)
                  for k, v in fp64.items()},
         "batched_mixed": batched,
+        "batched_fp64": batched64,
         "mixed_vs_fp64_speedup": round(mixed["solves_per_s"] / fp64["solves_per_s"], 3),
         "top_kernels": [dict(name=r["name"], ms_per_solve=round(r["ms"], 3),
                              launches=r["launches"],

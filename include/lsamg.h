@@ -257,7 +257,9 @@ enum {
                              batch of 64 columns runs as the LDS-staged matrix-core
                              GEMM or as the per-task tiles of the other operators,
                              whichever the autotuner times faster (the latter only
-                             while LSAMG_OPT_MFMA_TILE fixes the tiles); 1..16: the
+                             while LSAMG_OPT_MFMA_TILE fixes the tiles), and the
+                             FP64 one as the FP64 LDS-staged matrix-core GEMM or
+                             the FMA kernel, whichever is faster; 1..16: the
                              LDS-staged GEMM with that many loop ranges (fewer
                              where the partial-sum buffer is too small); 17: never
                              the LDS-staged GEMM                                 */

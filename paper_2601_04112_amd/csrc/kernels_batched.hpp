@@ -722,16 +722,118 @@ __global__ void __launch_bounds__(kBlock) k_dense_mm64(int64_t n, int64_t ld, in
   }
 }
 
+// The same dense level operator in FP64 on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: operands as in the FP32 16x16x4 form, lane i + 16 g
+// holding A[i][g] and B[g][i]; result register v of lane i + 16 g holds
+// D[g + 4 v][i], not D[4 g + v][i] as in the FP32 form): OUT = M IN, M n x n row-major with padded stride ld (a
+// multiple of 4, padding zero), IN and OUT interleaved n x 64.  A workgroup
+// takes a 64-row x 64-column output tile over the loop range of its split
+// (blockIdx.y), 16 rows per wave; the loop runs in chunks of KC input rows
+// staged once in LDS (double-buffered), and each lane reads its own matrix
+// row in 32-byte pieces: piece v of lane group g holds loop indices
+// kb + 16 v + 4 g + e (e < 4), so a row's four lane groups read 128
+// contiguous bytes.  The next chunk's loads are in flight during the
+// current chunk's MFMAs.  Splits > 1 write partial sums to part[split][row][:]
+// for k_dense_reduce64d (an empty loop range writes zeros).
+template <int KC>
+__global__ void __launch_bounds__(kBlock) k_dense_mm64d(int64_t n, int64_t ld, int kchunk,
+                                                        const double* __restrict__ M,
+                                                        const double* __restrict__ in,
+                                                        double* __restrict__ out,
+                                                        double* __restrict__ part) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  static_assert(KC % 16 == 0, "chunks of 16 rows");
+  constexpr int SB = 64 + 4;                 // LDS row stride (doubles)
+  constexpr int KL = KC / 4;                 // loop indices per lane group and chunk
+  constexpr int SV = KC / 8;                 // 16-byte staging loads per thread
+  __shared__ __attribute__((aligned(16))) double sB[2][KC * SB];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int64_t row0 = (int64_t)blockIdx.x * 64 + 16 * w;
+  const int split = blockIdx.y;
+  const int64_t k0 = (int64_t)split * kchunk;
+  const int64_t k1 = k0 + kchunk < n ? k0 + kchunk : n;
+  const int64_t jr = row0 + i;               // this lane's matrix row (A operand row)
+  const double* __restrict__ mrow_p = M + (jr < n ? jr : 0) * ld;
+  const f64x4 zero4 = {0.0, 0.0, 0.0, 0.0};
+  const f64x2 zero2 = {0.0, 0.0};
+  f64x4 acc[4] = {zero4, zero4, zero4, zero4};
+  // staging: thread t moves input row kb + (t / 32) + 8 v, columns 2 (t % 32) .. +1
+  const int sr = threadIdx.x >> 5, sc = 2 * (threadIdx.x & 31);
+  f64x2 bst[SV];
+  f64x4 am[KL / 4];
+  auto load_chunk = [&](int64_t kb) {
+#pragma unroll
+    for (int v = 0; v < SV; ++v) {
+      const int64_t r = kb + sr + 8 * v;
+      bst[v] = r < k1 ? *(const f64x2*)(in + r * 64 + sc) : zero2;
+    }
+#pragma unroll
+    for (int v = 0; v < KL / 4; ++v) {
+      // 4 entries from column c; c < ld covers them all (ld % 4 == 0, and a
+      // split's range is a multiple of 4 long), columns >= n are padding
+      const int64_t c = kb + 16 * v + 4 * g;
+      am[v] = (jr < n && c < k1) ? *(const f64x4*)(mrow_p + c) : zero4;
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) load_chunk(k0);
+  for (int64_t kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+    for (int v = 0; v < SV; ++v) *(f64x2*)(sB[buf] + (sr + 8 * v) * SB + sc) = bst[v];
+    f64x4 a[KL / 4];
+#pragma unroll
+    for (int v = 0; v < KL / 4; ++v) a[v] = am[v];
+    __syncthreads();
+    if (kb + KC < k1) load_chunk(kb + KC);    // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int st = 0; st < KL; ++st) {
+      const f64x4 b = *(const f64x4*)(sB[buf] + (16 * (st / 4) + 4 * g + st % 4) * SB + 4 * i);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[st / 4][st % 4], b[q], acc[q], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t jj = row0 + g + 4 * v;
+    if (jj >= n) continue;
+    f64x4 o;
+    o[0] = acc[0][v];
+    o[1] = acc[1][v];
+    o[2] = acc[2][v];
+    o[3] = acc[3][v];
+    double* dst = (gridDim.y > 1 ? part + (int64_t)split * n * 64 : out) + jj * 64 + 4 * i;
+    *(f64x4*)dst = o;
+  }
+}
+
+// out[r][:] = sum over the S slots of part[s][r][:] (64 columns, FP64), in
+// slot order
+__global__ void __launch_bounds__(kBlock) k_dense_reduce64d(int64_t rows, int S,
+                                                            const double* __restrict__ part,
+                                                            double* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= rows * 64) return;
+  double s = 0.0;
+  for (int k = 0; k < S; ++k) s += part[(int64_t)k * rows * 64 + e];
+  out[e] = s;
+}
+
 // dst[j][l] = src[l][j] (j, l < n) with row stride ld >= n, padding zero: the
-// row-major copy for k_dense_mm64 of an operator stored as the dense GEMV's
-// M (output j = sum over l of M[l][j] times input l).  Set-up only.
+// row-major copy for k_dense_mm64 / k_dense_mm64d of an operator stored as
+// the dense GEMV's M (output j = sum over l of M[l][j] times input l).
+// Set-up only.
+template <typename T>
 __global__ void __launch_bounds__(kBlock) k_pad_rows(int64_t n, int64_t ld,
-                                                     const float* __restrict__ src,
-                                                     float* __restrict__ dst) {
+                                                     const T* __restrict__ src,
+                                                     T* __restrict__ dst) {
   const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (e >= n * ld) return;
   const int64_t j = e / ld, l = e - j * ld;
-  dst[e] = l < n ? src[l * n + j] : 0.f;
+  dst[e] = l < n ? src[l * n + j] : T(0);
 }
 
 // out[r][:] (=|+=) sum over the S slots of part[s][r][:], in slot order

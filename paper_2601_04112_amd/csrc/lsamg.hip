@@ -139,6 +139,10 @@ struct DLevel {
   int dmm_kc = 64;        // its chunk length (32 or 64)
   float* dmm_M = nullptr; // its padded row-major copy of the FP32 operator (batched buffers)
   int64_t dmm_ld = 0;     // row stride of dmm_M
+  double* dmmd_M = nullptr;    // the padded row-major copy of the FP64 operator (batched buffers)
+  double* dmmd_part = nullptr; // its partial sums of split loops (batched buffers)
+  int dmmd_split = 0;     // dense level, 64 columns, FP64: k_dense_mm64d loop ranges (0: bgemm)
+  int dmmd_kchunk = 0, dmmd_kc = 0;
   int lanes_g = 1, lanes_gt = 1;
   int max_nO = 0, max_nw = 0, max_k = 0;
   int64_t* g_ptr = nullptr;
@@ -386,17 +390,21 @@ struct lsamg_handle {
   }
   bool mm_tuned = false;             // k_bmm tile shapes chosen for the batched buffers
   bool mm_tuned64 = false;           // and the 64-column forms (dense GEMM split, coarse residual)
+  bool dmmd_tuned = false;           // the FP64 dense level's form on 64 columns chosen
   float* mm_part = nullptr;          // partial sums of split loops, sized for the buffers' width
   int64_t mm_part_cap = 0;
   void free_batched() {
     for (auto& D : L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
-      D.dmm_split = 0;
+      D.dmm_split = D.dmmd_split = 0;
       D.dmm_M = nullptr;                // freed with the batched buffers below
+      D.dmmd_M = nullptr;
+      D.dmmd_part = nullptr;
       D.bg_on = false;                  // its staging goes with them too
     }
     mm_tuned = false;
     mm_tuned64 = false;
+    dmmd_tuned = false;
     mm_part = nullptr;                 // freed with the batched buffers below
     mm_part_cap = 0;
     drop_graphs(true);
@@ -2025,7 +2033,7 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
   if (!L.dmm_M) {
     L.dmm_ld = (n + 3) / 4 * 4;
     L.dmm_M = h->alloc<float>((size_t)(n * L.dmm_ld));
-    KLAUNCH0(nblocks(n * L.dmm_ld), dev::kBlock, 0, s, dev::k_pad_rows, n, L.dmm_ld, M, L.dmm_M);
+    KLAUNCH0(nblocks(n * L.dmm_ld), dev::kBlock, 0, s, dev::k_pad_rows<float>, n, L.dmm_ld, M, L.dmm_M);
     LAUNCH_OK();
   }
   std::vector<int> want;
@@ -2076,6 +2084,118 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+}
+
+// The FP64 dense level operator on 64 columns as k_dense_mm64d<KC> on the
+// padded row-major copy L.dmmd_M, with S loop ranges of kchunk rows (S > 1:
+// partial sums in L.dmmd_part, then k_dense_reduce64d in slot order).
+void dense_mm_launch_d(const DLevel& L, int S, int kchunk, int KC, const double* in, double* out,
+                       hipStream_t s) {
+  const int64_t n = L.n;
+  {
+    PROF("k_dense_mm64d",
+         sizeof(double) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))), s);
+    const dim3 grid((unsigned)((n + 63) / 64), (unsigned)S);
+    if (KC == 32)
+      KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64d<32>, n, L.dmm_ld, kchunk,
+              (const double*)L.dmmd_M, in, out, L.dmmd_part);
+    else
+      KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64d<16>, n, L.dmm_ld, kchunk,
+              (const double*)L.dmmd_M, in, out, L.dmmd_part);
+    LAUNCH_OK();
+  }
+  if (S > 1) {
+    PROF("k_dense_reduce64d", sizeof(double) * (double)n * 64 * (S + 1), s);
+    KLAUNCH(nblocks(n * 64), dev::kBlock, 0, s, dev::k_dense_reduce64d, n, S,
+            (const double*)L.dmmd_part, out);
+    LAUNCH_OK();
+  }
+}
+
+// Autotuner of the FP64 dense level on 64 columns, run by the first FP64
+// batch of 64: the FMA k_bgemm against k_dense_mm64d for both chunk lengths
+// and loop splits 1..16 (or the split LSAMG_OPT_DENSE_SPLIT fixes), each
+// timed on the level's own buffers (one warm-up and three timed launches;
+// the FP64 matrix exceeds the last-level cache, so nothing is evicted
+// between them); the fastest is kept.  Makes the padded row-major FP64 copy
+// and the partial-sum buffer with the batched buffers.
+void dense_tune_d(lsamg_handle* h, hipStream_t s) {
+  if (h->dmmd_tuned || h->dry) return;
+  struct Quiet {                       // tuning launches are not profiled
+    Profiler* p;
+    lsamg_handle* h;
+    ~Quiet() {
+      g_prof = p;
+      h->batch_alloc = false;
+    }
+  } quiet{g_prof, h};
+  g_prof = nullptr;
+  h->batch_alloc = true;
+  for (size_t l = 0; l < h->L.size(); ++l) {
+    DLevel& L = h->L[l];
+    if (!(L.coarsest || L.tail)) continue;
+    L.dmmd_split = 0;
+    if (h->dense_split > 16) break;
+    const int64_t n = L.n;
+    auto& B = h->BL[l];
+    const double* in = B.b;
+    double* out = B.x;
+    if (!L.dmmd_M) {
+      L.dmm_ld = (n + 3) / 4 * 4;
+      L.dmmd_M = h->alloc<double>((size_t)(n * L.dmm_ld));
+      KLAUNCH0(nblocks(n * L.dmm_ld), dev::kBlock, 0, s, dev::k_pad_rows<double>, n, L.dmm_ld,
+               L.d.Ainv, L.dmmd_M);
+      LAUNCH_OK();
+      L.dmmd_part = h->alloc<double>((size_t)(16 * n * 64));
+    }
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    auto time3 = [&](auto&& run) {
+      run();                                   // warm-up
+      HIP_OK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) run();
+      HIP_OK(hipEventRecord(e1, s));
+      HIP_OK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIP_OK(hipEventElapsedTime(&t, e0, e1));
+      return t;
+    };
+    try {
+      float best = 1e30f;
+      if (h->dense_split == 0)
+        best = time3([&] {
+          bgemm<double, dev::IN_DIRECT, false, 64>(L.dense, nullptr, nullptr, nullptr, nullptr,
+                                                   L.d.Ainv, in, out, s);
+        });
+      std::vector<int> want;
+      if (h->dense_split > 0)
+        want.push_back(h->dense_split);
+      else
+        want = {1, 2, 3, 4, 6, 8, 12, 16};
+      for (int KC : {16, 32})
+        for (int w : want) {
+          int S = 1, kc = 0;
+          dense_split_shape(n, w, KC, &S, &kc);
+          const float ms = time3([&] { dense_mm_launch_d(L, S, kc, KC, in, out, s); });
+          if (ms < best) {
+            best = ms;
+            L.dmmd_split = S;
+            L.dmmd_kchunk = kc;
+            L.dmmd_kc = KC;
+          }
+        }
+    } catch (...) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    break;
+  }
+  HIP_OK(hipStreamSynchronize(s));
+  h->dmmd_tuned = true;
 }
 
 // Rows per wavefront of k_bspmm64: about 48 entries per wave; 0 when the
@@ -2217,6 +2337,12 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
     if constexpr (std::is_same<T, float>::value && NB == 64) {
       if (L.dmm_split > 0) {
         dense_mm_launch(L, L.dmm_split, L.dmm_kchunk, L.dmm_kc, B, X, L.dense.mm.part, s);
+        return;
+      }
+    }
+    if constexpr (std::is_same<T, double>::value && NB == 64) {
+      if (L.dmmd_split > 0) {
+        dense_mm_launch_d(L, L.dmmd_split, L.dmmd_kchunk, L.dmmd_kc, B, X, s);
         return;
       }
     }
@@ -2580,6 +2706,7 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
   auto t0 = std::chrono::steady_clock::now();
   ensure_batched(h, NB);
   if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
+  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) dense_tune_d(h, s);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -2706,6 +2833,7 @@ void bapply_vcycle(lsamg_handle* h, const double* X, double* Y, int nr, int64_t 
                    hipStream_t s) {
   ensure_batched(h, NB);
   if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
+  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) dense_tune_d(h, s);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -2935,11 +3063,11 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     if (!h->use_mfma) {                 // back to k_bgemm; task lists stay until the buffers go
       for (auto& D : h->L) {
         for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
-        D.dmm_split = 0;
+        D.dmm_split = D.dmmd_split = 0;
         D.bg_on = false;
       }
       h->mm_tuned = false;
-      h->mm_tuned64 = false;
+      h->mm_tuned64 = h->dmmd_tuned = false;
     }
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
   } else if (opt == LSAMG_OPT_GRAPH) {
@@ -2951,10 +3079,10 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->bgroup = (int)value;
     for (auto& D : h->L) D.bg_on = false;
     h->mm_tuned = false;                // decided again with the tiles on the next batched solve
-    h->mm_tuned64 = false;
+    h->mm_tuned64 = h->dmmd_tuned = false;
     for (auto& D : h->L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
-      D.dmm_split = 0;
+      D.dmm_split = D.dmmd_split = 0;
     }
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_ATA_TILES) {
@@ -2973,19 +3101,19 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->mm_fixed = (int)value;
     for (auto& D : h->L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
-      D.dmm_split = 0;
+      D.dmm_split = D.dmmd_split = 0;
     }
     h->mm_tuned = false;                // retuned (or fixed) on the next batched solve
-    h->mm_tuned64 = false;
+    h->mm_tuned64 = h->dmmd_tuned = false;
     h->drop_graphs(true);
   } else if (opt == LSAMG_OPT_DENSE_SPLIT) {
     h->dense_split = (int)value;
     for (auto& D : h->L) {
       for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
-      D.dmm_split = 0;
+      D.dmm_split = D.dmmd_split = 0;
     }
     h->mm_tuned = false;
-    h->mm_tuned64 = false;
+    h->mm_tuned64 = h->dmmd_tuned = false;
     h->drop_graphs(true);
   } else {
     return fail_with(LSAMG_EINVAL, "unknown option");

@@ -286,27 +286,32 @@ def test_batched_vcycle_every_tile_shape(which, request):
 
 
 @pytest.mark.parametrize("which", ["rot", "rot_tail"])
-def test_batched_dense_level_every_split(which, request):
-    """The LDS-staged matrix-core GEMM of the dense level (k_dense_mm64), for
-    loop splits from one range to more ranges than 32-row chunks, and with it
-    switched off, gives the single-vector FP32 V-cycle on each of 64 columns
-    to 2e-5; the forced form is the one that runs."""
+@pytest.mark.parametrize("prec", [L.MIXED, L.FP64])
+def test_batched_dense_level_every_split(which, prec, request):
+    """The LDS-staged matrix-core GEMM of the dense level (k_dense_mm64 in
+    FP32, k_dense_mm64d in FP64), for loop splits from one range to more
+    ranges than 32-row chunks, with it switched off, and as the tuner picks,
+    gives the single-vector V-cycle of the same precision on each of 64
+    columns to 2e-5 (FP32) or 1e-12 (FP64); the forced form is the one that
+    runs."""
     p, H, s = request.getfixturevalue(which)
     X = np.stack([P.rhs_uniform(p.n, 900 + j) for j in range(64)])
     dX = dvec(X)
-    s.set_precision(L.MIXED)
+    s.set_precision(prec)
+    kern, tol = ("k_dense_mm64", 2e-5) if prec == L.MIXED else ("k_dense_mm64d", 1e-12)
     try:
         Y1 = [host(s.apply(L.OP_VCYCLE, dX[j])) for j in range(0, 64, 9)]
-        for split in (1, 2, 3, 7, 16, 17):
+        for split in (1, 2, 3, 7, 16, 17, 0):
             s.set_option(L.OPT_DENSE_SPLIT, split)
             s.apply_vcycle_batch(dX)            # tunes (or fixes) the tile shapes
             s.profile(True)
             Y = host(s.apply_vcycle_batch(dX))
             names = {k["name"] for k in s.profile_read()}
             s.profile(False)
-            assert ("k_dense_mm64" in names) == (split <= 16), (split, sorted(names))
+            if split:
+                assert (kern in names) == (split <= 16), (split, sorted(names))
             for k, j in enumerate(range(0, 64, 9)):
-                assert rel(Y[j], Y1[k]) <= 2e-5, (split, j, rel(Y[j], Y1[k]))
+                assert rel(Y[j], Y1[k]) <= tol, (split, j, rel(Y[j], Y1[k]))
     finally:
         s.profile(False)
         s.set_option(L.OPT_DENSE_SPLIT, 0)
