@@ -248,7 +248,12 @@ enum {
                              with rt = 4: on 64 columns the form that stages the
                              input rows in LDS per 64-row task), split in
                              {1,2,4,8} loop ranges per task (reduced to 1 where
-                             the partial-sum buffer is too small)               */
+                             the partial-sum buffer is too small).  In FP64 the
+                             aggregate-block operators of a batch run on the
+                             FP64 matrix cores or on FMA, whichever the
+                             autotuner times faster; a fixed shape makes them all
+                             FP64 matrix-core tasks of one row tile with its u
+                             (u = 0: 2), no split                                */
   LSAMG_OPT_ONEPASS_ATA = 4, /* 1 (default): where the rows of G are short (a
                              finite-difference G), the FP64 A-apply G^T (G P) of
                              the multi-right-hand-side CG recomputes each row of G

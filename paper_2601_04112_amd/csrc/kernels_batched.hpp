@@ -546,6 +546,126 @@ __global__ void __launch_bounds__(kBlock) k_bmm(MmTasks tk, int ntask, GemvOp op
   }
 }
 
+template <int CT>
+__device__ __forceinline__ void vload(const double* __restrict__ p, double (&v)[CT]) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  if constexpr (CT == 4) {
+    const d4 t = *(const d4*)p;
+    v[0] = t[0]; v[1] = t[1]; v[2] = t[2]; v[3] = t[3];
+  } else if constexpr (CT == 2) {
+    const d2 t = *(const d2*)p;
+    v[0] = t[0]; v[1] = t[1];
+  } else {
+    v[0] = *p;
+  }
+}
+
+template <int CT>
+__device__ __forceinline__ void vstore(double* __restrict__ p, const double (&v)[CT]) {
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  if constexpr (CT == 4) {
+    d4 t;
+    t[0] = v[0]; t[1] = v[1]; t[2] = v[2]; t[3] = v[3];
+    *(d4*)p = t;
+  } else if constexpr (CT == 2) {
+    d2 t;
+    t[0] = v[0]; t[1] = v[1];
+    *(d2*)p = t;
+  } else {
+    *p = v[0];
+  }
+}
+
+// k_bmm in FP64 on the FP64 matrix cores (v_mfma_f64_16x16x4f64): the same
+// tasks (aggregate a, 16 RT output rows from j0, the whole loop; no split),
+// inputs formed per MODE, columns CT i .. CT i + CT-1 in lane i.  Result
+// register v of lane group g holds output row j0 + 16 r + g + 4 v (the FP64
+// form's result lanes).
+template <int MODE, bool ADD, int RT, int U, int NB>
+__global__ void __launch_bounds__(kBlock) k_bmmd(MmTasks tk, int ntask, GemvOp op,
+                                                 const int32_t* __restrict__ gidx,
+                                                 const int64_t* __restrict__ cptr,
+                                                 const int64_t* __restrict__ cpos,
+                                                 const double* __restrict__ tb,
+                                                 const double* __restrict__ M,
+                                                 const double* __restrict__ in,
+                                                 double* __restrict__ out) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  static_assert(NB % 16 == 0 && NB <= 64, "column tiles of 16");
+  constexpr int CT = NB / 16;
+  constexpr int WPB = kBlock / 64;
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, g = lane >> 4;
+  for (int t = __builtin_amdgcn_readfirstlane((int)xcd_block(blockIdx.x, gridDim.x) * WPB + (threadIdx.x >> 6)); t < ntask;
+       t += gridDim.x * WPB) {
+    const int a = tk.a[t], j0 = tk.j0[t], k0 = tk.k0[t], k1 = tk.k1[t];
+    const int nj = op.lj[a];
+    const int64_t ib = op.ibase[a];
+    const double* __restrict__ m = M + op.moff[a];
+    const int64_t ld = mrow(nj, op.pad);
+    f64x4 acc[RT][CT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int q = 0; q < CT; ++q) acc[r][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k = k0; k < k1; k += 4 * U) {
+      double av[U][RT], bv[U][CT];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = k + 4 * u + g;
+        const bool lv = l < k1;
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+          const int jj = j0 + 16 * r + i;
+          av[u][r] = (lv && jj < nj) ? m[(int64_t)l * ld + jj] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < CT; ++q) bv[u][q] = 0.0;
+        if (lv) {
+          const int64_t e = ib + l;
+          const int64_t row = MODE == IN_GATHER ? (int64_t)gidx[e] : e;
+          vload<CT>(in + row * NB + CT * i, bv[u]);
+          if (MODE == IN_TB) {
+            for (int64_t p = cptr[e]; p < cptr[e + 1]; ++p) {
+              double w[CT];
+              vload<CT>(tb + cpos[p] * NB + CT * i, w);
+#pragma unroll
+              for (int q = 0; q < CT; ++q) bv[u][q] += w[q];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int q = 0; q < CT; ++q)
+            acc[r][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u][r], bv[u][q], acc[r][q], 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int jj = j0 + 16 * r + g + 4 * v;
+        if (jj >= nj) continue;
+        double o[CT];
+#pragma unroll
+        for (int q = 0; q < CT; ++q) o[q] = acc[r][q][v];
+        double* d = out + (op.obase[a] + jj) * NB + CT * i;
+        if (ADD) {
+          double w[CT];
+          vload<CT>(d, w);
+#pragma unroll
+          for (int q = 0; q < CT; ++q) o[q] += w[q];
+        }
+        vstore<CT>(d, o);
+      }
+  }
+}
+
 // k_bmm on 64 columns with the input rows staged in LDS: a workgroup per
 // task (aggregate a, 64 output rows j0 .. j0+63, loop range [k0, k1), slot),
 // its four waves 16 rows each.  The loop runs in chunks of 32 input rows

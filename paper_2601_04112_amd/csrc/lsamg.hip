@@ -110,6 +110,7 @@ struct GemvPlan {
     dev::MmTasks tk{};
     float* part = nullptr;   // partial sums of a split loop (split > 1)
   } mm;
+  Mm mmd;                    // FP64 on the matrix cores (k_bmmd; rt 0: k_bgemm)
 };
 
 struct DLevel {
@@ -390,12 +391,12 @@ struct lsamg_handle {
   }
   bool mm_tuned = false;             // k_bmm tile shapes chosen for the batched buffers
   bool mm_tuned64 = false;           // and the 64-column forms (dense GEMM split, coarse residual)
-  bool dmmd_tuned = false;           // the FP64 dense level's form on 64 columns chosen
+  bool dmmd_tuned = false;           // the FP64 matrix-core forms chosen (fp64_tune)
   float* mm_part = nullptr;          // partial sums of split loops, sized for the buffers' width
   int64_t mm_part_cap = 0;
   void free_batched() {
     for (auto& D : L) {
-      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = GemvPlan::Mm{};
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm = P->mmd = GemvPlan::Mm{};
       D.dmm_split = D.dmmd_split = 0;
       D.dmm_M = nullptr;                // freed with the batched buffers below
       D.dmmd_M = nullptr;
@@ -1883,6 +1884,21 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
       return;
     }
   }
+  if constexpr (std::is_same<T, double>::value && NB >= 16) {
+    if (P.mmd.rt > 0) {
+      PROF(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", 1, " +
+                               std::to_string(P.mmd.u) + ", " + std::to_string(NB)),
+           bytes, s);
+      if (P.mmd.u == 8)
+        KLAUNCH(P.mmd.grid, dev::kBlock, 0, s, dev::k_bmmd<MODE, ADD, 1, 8, NB>, P.mmd.tk,
+                (int)P.mmd.ntask, P.op, gidx, cptr, cpos, tb, M, in, out);
+      else
+        KLAUNCH(P.mmd.grid, dev::kBlock, 0, s, dev::k_bmmd<MODE, ADD, 1, 2, NB>, P.mmd.tk,
+                (int)P.mmd.ntask, P.op, gidx, cptr, cpos, tb, M, in, out);
+      LAUNCH_OK();
+      return;
+    }
+  }
   PROF(kname("k_bgemm", std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
                             (ADD ? "true" : "false") + ", " + std::to_string(NB)),
        bytes, s);
@@ -2112,14 +2128,75 @@ void dense_mm_launch_d(const DLevel& L, int S, int kchunk, int KC, const double*
   }
 }
 
-// Autotuner of the FP64 dense level on 64 columns, run by the first FP64
-// batch of 64: the FMA k_bgemm against k_dense_mm64d for both chunk lengths
-// and loop splits 1..16 (or the split LSAMG_OPT_DENSE_SPLIT fixes), each
-// timed on the level's own buffers (one warm-up and three timed launches;
-// the FP64 matrix exceeds the last-level cache, so nothing is evicted
-// between them); the fastest is kept.  Makes the padded row-major FP64 copy
-// and the partial-sum buffer with the batched buffers.
-void dense_tune_d(lsamg_handle* h, hipStream_t s) {
+// Time run() (a fixed sequence of launches on s): one warm-up, then three
+// runs between two events; milliseconds for the three.
+template <typename F>
+float time_runs(hipStream_t s, F&& run) {
+  hipEvent_t e0, e1;
+  HIP_OK(hipEventCreate(&e0));
+  HIP_OK(hipEventCreate(&e1));
+  float t = 0.f;
+  try {
+    run();
+    HIP_OK(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r) run();
+    HIP_OK(hipEventRecord(e1, s));
+    HIP_OK(hipEventSynchronize(e1));
+    HIP_OK(hipEventElapsedTime(&t, e0, e1));
+  } catch (...) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return t;
+}
+
+// One FP64 aggregate-block operator on the matrix cores: the FMA k_bgemm
+// against k_bmmd (16-row tasks, 2 or 8 loop steps' loads together), timed on
+// the level's own matrices and buffers; the fastest is kept in P.mmd (task
+// lists live with the batched buffers).
+template <int MODE, bool ADD>
+void mmd_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
+              const int64_t* cpos, const double* tb, const double* M, const double* in,
+              double* out, hipStream_t s) {
+  P.mmd = GemvPlan::Mm{};
+  if (P.nagg == 0 || P.hlj.empty()) return;
+  if (h->mm_fixed > 0) {              // a fixed tile shape: k_bmmd with its loads in flight
+    P.mmd = mm_build(h, P, 1, 1, false);
+    P.mmd.u = (h->mm_fixed / 10) % 10 == 8 ? 8 : 2;
+    return;
+  }
+  auto run = [&] { bgemm<double, MODE, ADD, 64>(P, gidx, cptr, cpos, tb, M, in, out, s); };
+  float best = time_runs(s, run);
+  const GemvPlan::Mm mm = mm_build(h, P, 1, 1, false);
+  const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
+  int pick = 0;
+  for (int u : {2, 8}) {
+    if (u == 8 && llmax <= 32) continue;
+    P.mmd = mm;
+    P.mmd.u = u;
+    const float t = time_runs(s, run);
+    if (t < best) {
+      best = t;
+      pick = u;
+    }
+  }
+  P.mmd = mm;
+  P.mmd.u = pick;
+  if (pick == 0) P.mmd.rt = 0;
+}
+
+// FP64 forms on the matrix cores, chosen by the first FP64 batch of 64: each
+// level's aggregate-block operators (mmd_tune) and the dense level
+// (k_dense_mm64d for both chunk lengths and loop splits 1..16, or the split
+// LSAMG_OPT_DENSE_SPLIT fixes, against the FMA k_bgemm), each timed on the
+// level's own buffers (one warm-up and three timed launches; the FP64
+// dense matrix exceeds the last-level cache, so nothing is evicted between
+// them); the fastest is kept.  Makes the dense level's padded row-major FP64
+// copy and partial-sum buffer with the batched buffers.
+void fp64_tune(lsamg_handle* h, hipStream_t s) {
   if (h->dmmd_tuned || h->dry) return;
   struct Quiet {                       // tuning launches are not profiled
     Profiler* p;
@@ -2133,11 +2210,27 @@ void dense_tune_d(lsamg_handle* h, hipStream_t s) {
   h->batch_alloc = true;
   for (size_t l = 0; l < h->L.size(); ++l) {
     DLevel& L = h->L[l];
-    if (!(L.coarsest || L.tail)) continue;
+    auto& B = h->BL[l];
+    if (!(L.coarsest || L.tail)) {
+      DLevel& C = h->L[l + 1];
+      auto& BC = h->BL[l + 1];
+      mmd_tune<dev::IN_GATHER, false>(h, L.ras, L.oidx, nullptr, nullptr, nullptr, L.d.Zc, B.b,
+                                      B.x, s);
+      mmd_tune<dev::IN_DIRECT, false>(h, L.rst, nullptr, nullptr, nullptr, nullptr, L.d.Zh, B.r,
+                                      BC.b, s);
+      if (C.coarsest || C.tail)
+        mmd_tune<dev::IN_DIRECT, true>(h, L.pro, nullptr, nullptr, nullptr, nullptr, L.d.ZhT,
+                                       BC.x, B.x, s);
+      else
+        mmd_tune<dev::IN_TB, true>(h, L.pro, nullptr, C.cptr, C.cpos, BC.tb, L.d.ZhT, BC.x, B.x,
+                                   s);
+      mmd_tune<dev::IN_DIRECT, false>(h, L.rast, nullptr, nullptr, nullptr, nullptr, L.d.Zr, B.r,
+                                      B.tb, s);
+      continue;
+    }
     L.dmmd_split = 0;
     if (h->dense_split > 16) break;
     const int64_t n = L.n;
-    auto& B = h->BL[l];
     const double* in = B.b;
     double* out = B.x;
     if (!L.dmmd_M) {
@@ -2148,50 +2241,29 @@ void dense_tune_d(lsamg_handle* h, hipStream_t s) {
       LAUNCH_OK();
       L.dmmd_part = h->alloc<double>((size_t)(16 * n * 64));
     }
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    auto time3 = [&](auto&& run) {
-      run();                                   // warm-up
-      HIP_OK(hipEventRecord(e0, s));
-      for (int r = 0; r < 3; ++r) run();
-      HIP_OK(hipEventRecord(e1, s));
-      HIP_OK(hipEventSynchronize(e1));
-      float t = 0.f;
-      HIP_OK(hipEventElapsedTime(&t, e0, e1));
-      return t;
-    };
-    try {
-      float best = 1e30f;
-      if (h->dense_split == 0)
-        best = time3([&] {
-          bgemm<double, dev::IN_DIRECT, false, 64>(L.dense, nullptr, nullptr, nullptr, nullptr,
-                                                   L.d.Ainv, in, out, s);
-        });
-      std::vector<int> want;
-      if (h->dense_split > 0)
-        want.push_back(h->dense_split);
-      else
-        want = {1, 2, 3, 4, 6, 8, 12, 16};
-      for (int KC : {16, 32})
-        for (int w : want) {
-          int S = 1, kc = 0;
-          dense_split_shape(n, w, KC, &S, &kc);
-          const float ms = time3([&] { dense_mm_launch_d(L, S, kc, KC, in, out, s); });
-          if (ms < best) {
-            best = ms;
-            L.dmmd_split = S;
-            L.dmmd_kchunk = kc;
-            L.dmmd_kc = KC;
-          }
+    float best = 1e30f;
+    if (h->dense_split == 0)
+      best = time_runs(s, [&] {
+        bgemm<double, dev::IN_DIRECT, false, 64>(L.dense, nullptr, nullptr, nullptr, nullptr,
+                                                 L.d.Ainv, in, out, s);
+      });
+    std::vector<int> want;
+    if (h->dense_split > 0)
+      want.push_back(h->dense_split);
+    else
+      want = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int KC : {16, 32})
+      for (int w : want) {
+        int S = 1, kc = 0;
+        dense_split_shape(n, w, KC, &S, &kc);
+        const float ms = time_runs(s, [&] { dense_mm_launch_d(L, S, kc, KC, in, out, s); });
+        if (ms < best) {
+          best = ms;
+          L.dmmd_split = S;
+          L.dmmd_kchunk = kc;
+          L.dmmd_kc = KC;
         }
-    } catch (...) {
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      throw;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+      }
     break;
   }
   HIP_OK(hipStreamSynchronize(s));
@@ -2706,7 +2778,7 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
   auto t0 = std::chrono::steady_clock::now();
   ensure_batched(h, NB);
   if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
-  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) dense_tune_d(h, s);
+  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) fp64_tune(h, s);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -2833,7 +2905,7 @@ void bapply_vcycle(lsamg_handle* h, const double* X, double* Y, int nr, int64_t 
                    hipStream_t s) {
   ensure_batched(h, NB);
   if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
-  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) dense_tune_d(h, s);
+  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) fp64_tune(h, s);
   DLevel& L0 = h->L[0];
   auto& B0 = h->BL[0];
   const int64_t n = L0.n;
@@ -3062,7 +3134,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->use_mfma = value != 0;
     if (!h->use_mfma) {                 // back to k_bgemm; task lists stay until the buffers go
       for (auto& D : h->L) {
-        for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+        for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = P->mmd.rt = 0;
         D.dmm_split = D.dmmd_split = 0;
         D.bg_on = false;
       }
@@ -3081,7 +3153,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->mm_tuned = false;                // decided again with the tiles on the next batched solve
     h->mm_tuned64 = h->dmmd_tuned = false;
     for (auto& D : h->L) {
-      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = P->mmd.rt = 0;
       D.dmm_split = D.dmmd_split = 0;
     }
     h->drop_graphs(true);
@@ -3100,7 +3172,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
       return fail_with(LSAMG_EINVAL, "bad tile shape");
     h->mm_fixed = (int)value;
     for (auto& D : h->L) {
-      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = P->mmd.rt = 0;
       D.dmm_split = D.dmmd_split = 0;
     }
     h->mm_tuned = false;                // retuned (or fixed) on the next batched solve
@@ -3109,7 +3181,7 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
   } else if (opt == LSAMG_OPT_DENSE_SPLIT) {
     h->dense_split = (int)value;
     for (auto& D : h->L) {
-      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = 0;
+      for (GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.dense}) P->mm.rt = P->mmd.rt = 0;
       D.dmm_split = D.dmmd_split = 0;
     }
     h->mm_tuned = false;

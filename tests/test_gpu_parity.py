@@ -286,6 +286,42 @@ def test_batched_vcycle_every_tile_shape(which, request):
 
 
 @pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_batched_fp64_matrix_cores(which, request):
+    """The FP64 multi-right-hand-side V-cycle with its aggregate-block
+    operators on the FP64 matrix cores (k_bmmd, forced by a fixed tile shape,
+    both loads-in-flight counts) and as the autotuner picks gives the single-
+    vector FP64 V-cycle on every column to 1e-12, on 64 columns and then on
+    narrower batches with the same buffers; the forced form is the one that
+    runs."""
+    p, H, s = request.getfixturevalue(which)
+    X = np.stack([P.rhs_uniform(p.n, 1300 + j) for j in range(64)])
+    dX = dvec(X)
+    s.set_precision(L.FP64)
+    inf = s.info()
+    dense = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
+    try:
+        Y1 = [host(s.apply(L.OP_VCYCLE, dX[j])) for j in range(64)]
+        for tile in (121, 181, 401, 0):
+            s.set_option(L.OPT_MFMA_TILE, tile)
+            for nc in (64, 32, 16):
+                s.apply_vcycle_batch(dX[:nc])
+                s.profile(True, by_level=True)
+                Y = host(s.apply_vcycle_batch(dX[:nc]))
+                names = {k["name"] for k in s.profile_read()}
+                s.profile(False)
+                if tile:            # FMA only on the dense level
+                    fma = {k for k in names if k.startswith("k_bgemm")}
+                    assert any(k.startswith("k_bmmd") for k in names), (tile, nc, sorted(names))
+                    assert all(k.endswith(f"@L{dense}") for k in fma), (tile, nc, sorted(fma))
+                for j in range(nc):
+                    assert rel(Y[j], Y1[j]) <= 1e-12, (tile, nc, j, rel(Y[j], Y1[j]))
+    finally:
+        s.profile(False)
+        s.set_option(L.OPT_MFMA_TILE, 0)
+        s.set_precision(L.FP64)
+
+
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
 @pytest.mark.parametrize("prec", [L.MIXED, L.FP64])
 def test_batched_dense_level_every_split(which, prec, request):
     """The LDS-staged matrix-core GEMM of the dense level (k_dense_mm64 in
