@@ -189,7 +189,7 @@ def main():
                          "A = D1 + B^T D2^-1 B on a 128^3 grid")
     ap.add_argument("--N", type=int, default=0,
                     help="cells per side (default 512 for aniso2d, 128 for ls3d)")
-    ap.add_argument("--cpu-iters", type=int, default=2,
+    ap.add_argument("--cpu-iters", type=int, default=24,
                     help="PCG iterations of the oracle's timed sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64,
