@@ -1886,15 +1886,25 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
   }
   if constexpr (std::is_same<T, double>::value && NB >= 16) {
     if (P.mmd.rt > 0) {
-      PROF(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", 1, " +
-                               std::to_string(P.mmd.u) + ", " + std::to_string(NB)),
+      const GemvPlan::Mm& mm = P.mmd;
+      PROF(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
+                               std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
+                               std::to_string(NB)),
            bytes, s);
-      if (P.mmd.u == 8)
-        KLAUNCH(P.mmd.grid, dev::kBlock, 0, s, dev::k_bmmd<MODE, ADD, 1, 8, NB>, P.mmd.tk,
-                (int)P.mmd.ntask, P.op, gidx, cptr, cpos, tb, M, in, out);
+      auto launch = [&](auto kern) {
+        KLAUNCH(mm.grid, dev::kBlock, 0, s, kern, mm.tk, (int)mm.ntask, P.op, gidx, cptr, cpos,
+                tb, M, in, out);
+      };
+      if (mm.rt == 4)
+        launch(dev::k_bmmd<MODE, ADD, 4, 2, NB>);
+      else if (mm.rt == 2 && mm.u == 8)
+        launch(dev::k_bmmd<MODE, ADD, 2, 8, NB>);
+      else if (mm.rt == 2)
+        launch(dev::k_bmmd<MODE, ADD, 2, 2, NB>);
+      else if (mm.u == 8)
+        launch(dev::k_bmmd<MODE, ADD, 1, 8, NB>);
       else
-        KLAUNCH(P.mmd.grid, dev::kBlock, 0, s, dev::k_bmmd<MODE, ADD, 1, 2, NB>, P.mmd.tk,
-                (int)P.mmd.ntask, P.op, gidx, cptr, cpos, tb, M, in, out);
+        launch(dev::k_bmmd<MODE, ADD, 1, 2, NB>);
       LAUNCH_OK();
       return;
     }
@@ -2154,38 +2164,40 @@ float time_runs(hipStream_t s, F&& run) {
 }
 
 // One FP64 aggregate-block operator on the matrix cores: the FMA k_bgemm
-// against k_bmmd (16-row tasks, 2 or 8 loop steps' loads together), timed on
-// the level's own matrices and buffers; the fastest is kept in P.mmd (task
-// lists live with the batched buffers).
+// against k_bmmd (tasks of 1, 2 or 4 row tiles of 16; 2 or 8 loop steps'
+// loads together, 2 with 4 row tiles), timed on the level's own matrices and
+// buffers; the fastest is kept in P.mmd (task lists live with the batched
+// buffers).
 template <int MODE, bool ADD>
 void mmd_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
               const int64_t* cpos, const double* tb, const double* M, const double* in,
               double* out, hipStream_t s) {
   P.mmd = GemvPlan::Mm{};
   if (P.nagg == 0 || P.hlj.empty()) return;
-  if (h->mm_fixed > 0) {              // a fixed tile shape: k_bmmd with its loads in flight
-    P.mmd = mm_build(h, P, 1, 1, false);
-    P.mmd.u = (h->mm_fixed / 10) % 10 == 8 ? 8 : 2;
+  if (h->mm_fixed > 0) {              // a fixed tile shape: its row tiles and loads in flight
+    const int rt = h->mm_fixed / 100;
+    P.mmd = mm_build(h, P, rt, 1, false);
+    P.mmd.u = (h->mm_fixed / 10) % 10 == 8 && rt < 4 ? 8 : 2;
     return;
   }
   auto run = [&] { bgemm<double, MODE, ADD, 64>(P, gidx, cptr, cpos, tb, M, in, out, s); };
   float best = time_runs(s, run);
-  const GemvPlan::Mm mm = mm_build(h, P, 1, 1, false);
   const int llmax = *std::max_element(P.hll.begin(), P.hll.end());
-  int pick = 0;
-  for (int u : {2, 8}) {
-    if (u == 8 && llmax <= 32) continue;
-    P.mmd = mm;
-    P.mmd.u = u;
-    const float t = time_runs(s, run);
-    if (t < best) {
-      best = t;
-      pick = u;
+  GemvPlan::Mm pick{};                 // rt 0: k_bgemm
+  for (int rt : {1, 2, 4}) {
+    const GemvPlan::Mm mm = mm_build(h, P, rt, 1, false);
+    for (int u : {2, 8}) {
+      if (u == 8 && (llmax <= 32 || rt == 4)) continue;
+      P.mmd = mm;
+      P.mmd.u = u;
+      const float t = time_runs(s, run);
+      if (t < best) {
+        best = t;
+        pick = P.mmd;
+      }
     }
   }
-  P.mmd = mm;
-  P.mmd.u = pick;
-  if (pick == 0) P.mmd.rt = 0;
+  P.mmd = pick;
 }
 
 // FP64 forms on the matrix cores, chosen by the first FP64 batch of 64: each

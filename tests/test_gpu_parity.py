@@ -288,8 +288,9 @@ def test_batched_vcycle_every_tile_shape(which, request):
 @pytest.mark.parametrize("which", ["rot", "rot_tail"])
 def test_batched_fp64_matrix_cores(which, request):
     """The FP64 multi-right-hand-side V-cycle with its aggregate-block
-    operators on the FP64 matrix cores (k_bmmd, forced by a fixed tile shape,
-    both loads-in-flight counts) and as the autotuner picks gives the single-
+    operators on the FP64 matrix cores (k_bmmd, forced by a fixed tile shape:
+    1, 2 and 4 row tiles, both loads-in-flight counts) and as the autotuner
+    picks gives the single-
     vector FP64 V-cycle on every column to 1e-12, on 64 columns and then on
     narrower batches with the same buffers; the forced form is the one that
     runs."""
@@ -301,7 +302,7 @@ def test_batched_fp64_matrix_cores(which, request):
     dense = inf["tail_level"] if inf["tail_level"] >= 0 else inf["nlevels"] - 1
     try:
         Y1 = [host(s.apply(L.OP_VCYCLE, dX[j])) for j in range(64)]
-        for tile in (121, 181, 401, 0):
+        for tile in (121, 181, 221, 281, 401, 481, 0):
             s.set_option(L.OPT_MFMA_TILE, tile)
             for nc in (64, 32, 16):
                 s.apply_vcycle_batch(dX[:nc])
