@@ -112,11 +112,15 @@ def run_serving(args):
     t_warm = 0.0
     if args.prewarm:
         # steady state: one request per pool operator first, so every hierarchy
-        # is resident before the clock starts (their setup is reported apart)
+        # is resident before the clock starts (their setup is reported apart);
+        # it carries --prewarm-rhs columns, so the multi-right-hand-side
+        # buffers of the width the merged requests use are allocated and their
+        # matrix-core shapes tuned before the clock starts too
         tw = time.perf_counter()
         for k in range(args.pool):
             probs[k] = P.aniso2d(*pool[k])
-            srv.submit(k, probs[k].G, 2, probs[k].grid, P.rhs_uniform(probs[k].n, 7)[None, :],
+            bw = np.stack([P.rhs_uniform(probs[k].n, 7 + j) for j in range(args.prewarm_rhs)])
+            srv.submit(k, probs[k].G, 2, probs[k].grid, bw,
                        tol=1e-8, precision=L.MIXED, req_id=10 ** 6 + k, cmin=(2,))
         got = 0
         while got < args.pool:
@@ -173,7 +177,8 @@ def run_serving(args):
         "config": {"workload": f"{len(reqs)} Poisson requests at {args.qps}/s over a pool of "
                                f"{args.pool} aniso2d operators, N in {sizes}, theta~U[0,pi), "
                                f"log10 eps~U[-6,0], 1-8 rhs"
-                               + (", hierarchies resident before the clock starts"
+                               + (f", hierarchies resident and tuned ({args.prewarm_rhs}-column "
+                                  f"request each) before the clock starts"
                                   if args.prewarm else "")},
     }
     print(json.dumps(line))
@@ -203,6 +208,8 @@ def main():
     ap.add_argument("--budget-gb", type=float, default=160.0)
     ap.add_argument("--prewarm", action="store_true",
                     help="serving: make every pool operator resident before timing")
+    ap.add_argument("--prewarm-rhs", type=int, default=32,
+                    help="serving: right-hand sides of each operator's prewarm request")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the solves, negate a float32 buffer of this many MiB "
                          "into another (a plain streaming kernel of known bytes, the "
