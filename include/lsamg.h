@@ -79,7 +79,9 @@ typedef struct lsamg_params {
   int32_t ncmin;
   double tie_rtol;       /* relative width of an eigenvalue cluster (1e-8)   */
   double tie_atol;       /* absolute width of an eigenvalue cluster (1e-12)  */
-  double pinv_rtol;      /* pseudo-inverse cutoff in eq:gevp-S (1e-12)       */
+  double pinv_rtol;      /* pseudo-inverse cutoff in eq:gevp-S: directions of
+                            W^{1/2} G_{nz,Gamma} whose singular value is at
+                            most this times the largest count as null (1e-12)*/
   double thresh_margin;  /* strict side of the threshold test (1e-10)        */
   double stall_ratio;    /* stop coarsening if n_{l+1} > ratio * n_l (0.9)   */
   int32_t precision;     /* LSAMG_FP64 or LSAMG_MIXED (FP32 V-cycle)         */

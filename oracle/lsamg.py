@@ -28,7 +28,10 @@ the design notes of the repository):
 * eigenproblem: solved in the reversed, well-posed form
   ``S_omega u = mu A_omega_omega u`` with ``lambda = 1/mu`` (``mu = 0`` is
   ``lambda = infinity``); ``(A~_GammaGamma)^{-1}`` is the Moore-Penrose
-  pseudo-inverse, eigenvalues at or below ``pinv_rtol * max`` dropped;
+  pseudo-inverse, i.e. the Schur complement is the minimum energy over
+  ``u_Gamma``, computed as ``B_w^T (I - Q Q^T) B_w`` from the weighted rows
+  ``B = W^{1/2} G_{nz,Omega}`` (Q: range of ``B_Gamma``, singular values at
+  or below ``pinv_rtol`` times the largest dropped);
 * selection: ``k = #{lambda > thresh}`` capped at ``floor(|omega|/c_min)``
   (or a fixed count), at least one, and never splitting a cluster of equal
   eigenvalues (the cut moves down to the cluster start, or up to its end if
@@ -37,8 +40,9 @@ the design notes of the repository):
   the largest number of overlapping aggregates sharing an unknown;
 * eigenvectors are ``A_omega_omega``-orthonormal, ascending ``mu``, sign
   such that the largest-magnitude entry (first on ties) is positive;
-* PCG stops on the recurrence residual ``||r_k|| <= tol ||b||`` (2-norm,
-  x0 = 0).
+* PCG stops when the recurrence residual and the true residual both satisfy
+  ``||r|| <= tol ||b||`` (2-norm, x0 = 0); a recurrence residual that passes
+  while the true one does not is replaced by it and CG restarts.
 """
 from __future__ import annotations
 
@@ -65,12 +69,18 @@ class Params:
     cmin: tuple = (3, 4)            # per-level minimum coarsening ratio
     tie_rtol: float = 1e-8          # eigenvalue-cluster tolerance
     tie_atol: float = 1e-12
-    pinv_rtol: float = 1e-12        # pseudo-inverse cutoff
+    pinv_rtol: float = 1e-12        # rank cutoff of W^{1/2} G_{nz, Gamma}
     thresh_margin: float = 1e-10    # strict side of the threshold test
     stall_ratio: float = 0.9        # stop if n_{l+1} > stall_ratio * n_l
+    aggregation: str = "lattice"    # "lattice" blocks or "standard" (sec. 3.3)
+    agg_passes: tuple = (1,)        # n_agg of Algorithm 1 per level (last repeats)
 
     def cmin_at(self, level: int) -> int:
         c = tuple(self.cmin)
+        return int(c[min(level, len(c) - 1)])
+
+    def passes_at(self, level: int) -> int:
+        c = tuple(self.agg_passes)
         return int(c[min(level, len(c) - 1)])
 
 
@@ -174,6 +184,71 @@ def choose_block(coord, extent, b0: int, omega_max: int):
 
 
 # --------------------------------------------------------------------------
+# aggregation on matrix entries (section 3.3, Algorithm 1)
+# --------------------------------------------------------------------------
+def standard_aggregation(adj: sp.csr_matrix):
+    """Aggregates of the graph ``adj`` (structural off-diagonal pattern of a
+    matrix), by the greedy passes of standard aggregation (Vanek, Mandel,
+    Brezina) taken directly on matrix entries, nodes visited in index order:
+
+    1. a node whose neighbours are all unaggregated starts a new aggregate
+       holding it and its neighbours;
+    2. a node left over joins the aggregate (from pass 1) of its
+       lowest-numbered neighbour that pass 1 aggregated.
+
+    A node that pass 1 did not take had, when it was visited, a neighbour
+    already in an aggregate, so pass 2 places every remaining node and the
+    clean-up pass of the general method (for nodes whose strong connections
+    were all dropped) has nothing to do; a node without neighbours starts its
+    own aggregate in pass 1.  This is what the paper's extra assignment of
+    unaggregated nodes to a neighbouring aggregate guarantees.  Aggregate
+    ids are numbered in order of creation.  Returns ``(agg, n_agg)``.
+    """
+    adj = sp.csr_matrix(adj)
+    n = adj.shape[0]
+    ptr, col = adj.indptr, adj.indices
+    agg = -np.ones(n, dtype=np.int64)
+    n_agg = 0
+    for i in range(n):
+        nb = col[ptr[i]:ptr[i + 1]]
+        nb = nb[nb != i]
+        if agg[i] < 0 and np.all(agg[nb] < 0):
+            agg[i] = n_agg
+            agg[nb] = n_agg
+            n_agg += 1
+    first = agg.copy()
+    for i in range(n):
+        if agg[i] >= 0:
+            continue
+        nb = col[ptr[i]:ptr[i + 1]]
+        nb = np.sort(nb[(nb != i)])
+        done = nb[first[nb] >= 0]
+        agg[i] = first[done[0]]
+    return agg, n_agg
+
+
+def aggregate_standard(A_pattern: sp.csr_matrix, passes: int):
+    """``passes`` rounds of standard aggregation (section 3.3): the first on
+    the graph of ``A``, each further one on the graph of the aggregates
+    (``T^T A T`` with T the 0/1 aggregation matrix), composed, as the
+    paper's ``T_1 T_2``.  Returns ``(agg, n_agg)``."""
+    B = sp.csr_matrix(A_pattern, dtype=np.float64, copy=True)
+    B.data[:] = 1.0
+    n = B.shape[0]
+    agg = np.arange(n, dtype=np.int64)
+    n_agg = n
+    for _ in range(max(1, passes)):
+        a, na = standard_aggregation(B)
+        agg = a[agg]
+        n_agg = na
+        T = sp.csr_matrix((np.ones(len(a)), (np.arange(len(a)), a)),
+                          shape=(len(a), na))
+        B = (T.T @ B @ T).tocsr()
+        B.data[:] = 1.0
+    return agg, n_agg
+
+
+# --------------------------------------------------------------------------
 # overlap, partition of unity, multiplicity (sections 2.2, 3.1.1)
 # --------------------------------------------------------------------------
 def overlap(S: sp.csr_matrix, agg: np.ndarray, n_agg: int):
@@ -248,7 +323,9 @@ def local_splitting(G: sp.csr_matrix, nz: np.ndarray, Omega: np.ndarray,
 
 def schur_pinv(At: np.ndarray, nw: int, pinv_rtol: float) -> np.ndarray:
     """``S~_omega = A~_ww - A~_wG (A~_GG)^+ A~_Gw`` (eq:gevp-S), with the
-    Moore-Penrose pseudo-inverse of the SPSD block ``A~_GG``."""
+    Moore-Penrose pseudo-inverse of the SPSD block ``A~_GG`` (eigenvalues at
+    or below ``pinv_rtol`` times the largest dropped).  Kept as the plain
+    definition for the tests; the setup uses ``schur_ls``."""
     Aww = At[:nw, :nw]
     if At.shape[0] == nw:
         return Aww.copy()
@@ -258,6 +335,33 @@ def schur_pinv(At: np.ndarray, nw: int, pinv_rtol: float) -> np.ndarray:
     keep = lam > pinv_rtol * max(lam.max(), 0.0)
     Y = V[:, keep].T @ AwG.T
     return Aww - Y.T @ (Y / lam[keep][:, None])
+
+
+def schur_ls(B: np.ndarray, nw: int, rank_rtol: float) -> np.ndarray:
+    """The Schur complement of eq:gevp-S from the weighted rows
+    ``B = W^{1/2} G_{nz, Omega}`` (``A~ = B^T B``) without forming A~.
+
+    ``S~_omega = min_{u_Gamma} [u_w; u_G]^T A~ [u_w; u_G] = B_w^T (I - Q Q^T)
+    B_w`` with Q an orthonormal basis of range(B_Gamma); on a singular
+    ``A~_GammaGamma`` this is the Moore-Penrose (minimum-energy) reading.
+    Q and the rank come from the SVD of B_Gamma (singular values at or below
+    ``rank_rtol`` times the largest count as zero), so the conditioning of
+    B_Gamma enters once, not squared as in ``A~_GammaGamma``.
+    """
+    Bw = B[:, :nw]
+    if B.shape[1] == nw:
+        return Bw.T @ Bw
+    U, s, _ = np.linalg.svd(B[:, nw:], full_matrices=False)
+    r = int(np.sum(s > rank_rtol * s[0])) if s.size and s[0] > 0 else 0
+    Q = U[:, :r]
+    E = Bw - Q @ (Q.T @ Bw)
+    return E.T @ E
+
+
+def weighted_rows(G: sp.csr_matrix, nz: np.ndarray, Omega: np.ndarray,
+                  M: np.ndarray) -> np.ndarray:
+    """``W^{1/2} G_{nz, Omega}`` dense (section 3.1.1, ``W = diag(1/M)``)."""
+    return (sp.diags(1.0 / np.sqrt(M[nz])) @ G[nz][:, Omega]).toarray()
 
 
 def select_count(mu: np.ndarray, nw: int, p: Params, level: int,
@@ -348,8 +452,13 @@ def setup(G: sp.csr_matrix, ndim: int, grid: tuple, params: Params,
 
 
 def _build_level(L: Level, l: int, p: Params, basis_hook):
-    b, agg, n_agg, agg_coord, nblk = choose_block(L.coord, L.extent, p.block,
-                                                  p.omega_max)
+    if p.aggregation == "standard":
+        pat = (L.S.T @ L.S).tocsr()
+        agg, n_agg = aggregate_standard(pat, p.passes_at(l))
+        b, agg_coord, nblk = 0, np.zeros((n_agg, L.coord.shape[1]), dtype=np.int64), ()
+    else:
+        b, agg, n_agg, agg_coord, nblk = choose_block(L.coord, L.extent, p.block,
+                                                      p.omega_max)
     L.block, L.agg, L.n_agg, L.agg_coord, L.agg_extent = (b, agg, n_agg,
                                                            agg_coord, nblk)
     (L.omega, L.gamma, L.Omega, L.nz, L.M, _R, C) = overlap(L.S, agg, n_agg)
@@ -361,10 +470,9 @@ def _build_level(L: Level, l: int, p: Params, basis_hook):
     for i in range(n_agg):
         w, Om = L.omega[i], L.Omega[i]
         nw = len(w)
-        At = local_splitting(L.G, L.nz[i], Om, L.M)
         # G_{nz,w}^T G_{nz,w} = A(w, w): rows outside nz vanish on w
         Aww = L.A[w][:, w].toarray()
-        St = schur_pinv(At, nw, p.pinv_rtol)
+        St = schur_ls(weighted_rows(L.G, L.nz[i], Om, L.M), nw, p.pinv_rtol)
         mu, U = sla.eigh(St, Aww)                        # U^T Aww U = I
         k, hazard = select_count(mu, nw, p, l, L.thresh)
         if hazard:
@@ -455,9 +563,13 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
         fixed_iters: Optional[int] = None):
     """Preconditioned CG, x0 = 0, preconditioner = one V-cycle.
 
-    Stops when ``||r_k||_2 <= tol ||b||_2`` (recurrence residual) or, if
-    ``fixed_iters`` is given, after exactly that many iterations.
-    Returns ``(x, info)`` with iteration count and residual history.
+    Stops when ``||r_k||_2 <= tol ||b||_2`` for the recurrence residual and
+    the true residual ``b - A x_k`` recomputed at that point; when only the
+    recurrence residual passes, the true residual replaces it and CG restarts
+    from ``x_k`` (direction ``p = z``), so a reported convergence always holds
+    for ``b - A x``.  With ``fixed_iters`` it runs exactly that many
+    iterations.  Returns ``(x, info)`` with iteration count and residual
+    history (``restarts`` counts the replacements).
     """
     A0 = H.levels[0]
     x = np.zeros_like(b)
@@ -468,26 +580,37 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
     pdir = z.copy()
     rho = r @ z
     its = 0
+    restarts = 0
     limit = fixed_iters if fixed_iters is not None else maxit
-    while its < limit:
+    conv = nb == 0.0
+    while its < limit and not conv:
         q = apply_A(A0, pdir)
         alpha = rho / (pdir @ q)
         x += alpha * pdir
         r -= alpha * q
         its += 1
         hist.append(np.linalg.norm(r))
+        restart = False
         if fixed_iters is None and hist[-1] <= tol * nb:
-            break
+            rt = b - apply_A(A0, x)
+            if np.linalg.norm(rt) <= tol * nb:
+                conv = True
+                break
+            r = rt
+            hist[-1] = np.linalg.norm(r)
+            restart = True
+            restarts += 1
         z = vcycle(H, r)
         rho_new = r @ z
-        beta = rho_new / rho
+        if restart:
+            pdir = z.copy()
+        else:
+            pdir = z + (rho_new / rho) * pdir
         rho = rho_new
-        pdir = z + beta * pdir
-    true_res = np.linalg.norm(b - apply_A(A0, x)) / nb
-    conv = bool(hist[-1] <= tol * nb)
-    rhoavg = (hist[-1] / hist[0]) ** (1.0 / max(its, 1))
+    true_res = np.linalg.norm(b - apply_A(A0, x)) / nb if nb > 0 else 0.0
+    rhoavg = (hist[-1] / hist[0]) ** (1.0 / max(its, 1)) if nb > 0 else 0.0
     return x, dict(iters=its, hist=np.array(hist), true_rel_res=true_res,
-                   converged=conv, rho=rhoavg)
+                   converged=bool(conv), rho=rhoavg, restarts=restarts)
 
 
 def dense_preconditioner(H: Hierarchy) -> np.ndarray:
@@ -503,13 +626,17 @@ def dense_preconditioner(H: Hierarchy) -> np.ndarray:
 
 def stats(H: Hierarchy) -> dict:
     """Operator complexity sum nnz(A_l)/nnz(A_0), smoother complexity
-    sum |omega_i||Omega_i| / nnz(A_0), and per-level sizes."""
-    nnz0 = H.levels[0].A.nnz
-    oc = sum(L.A.nnz for L in H.levels) / nnz0
+    sum |omega_i||Omega_i| / nnz(A_0), and per-level sizes.  nnz counts the
+    structural entries of ``A_l = G_l^T G_l`` (the pattern of ``S_l^T S_l``
+    for the symbolic structure ``S_l`` of ``G_l``), not the entries that
+    happen to cancel to zero."""
+    nnzs = [int((L.S.T @ L.S).nnz) for L in H.levels]
+    nnz0 = nnzs[0]
+    oc = sum(nnzs) / nnz0
     sc = sum(sum(len(w) * len(O) for w, O in zip(L.omega, L.Omega))
              for L in H.levels if not L.coarsest) / nnz0
     return dict(levels=len(H.levels), n=[L.n for L in H.levels],
-                nnz_A=[L.A.nnz for L in H.levels],
+                nnz_A=nnzs,
                 n_agg=[L.n_agg for L in H.levels if not L.coarsest],
                 block=[L.block for L in H.levels if not L.coarsest],
                 n_color=[L.n_color for L in H.levels if not L.coarsest],

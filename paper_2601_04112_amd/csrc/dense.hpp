@@ -4,7 +4,8 @@
 // count.  Written from the textbook algorithms (Golub & Van Loan, "Matrix
 // Computations", 4th ed.): right-looking Cholesky (sec. 4.2), Householder
 // tridiagonalisation (sec. 8.3.1) followed by the implicit symmetric QR step
-// with Wilkinson shift (sec. 8.3.3), and Householder QR (sec. 5.2.2).
+// with Wilkinson shift (sec. 8.3.3), Householder QR (sec. 5.2.2) and
+// Householder QR with column pivoting (sec. 5.4.2).
 #pragma once
 
 #include <algorithm>
@@ -226,6 +227,70 @@ inline void qr_r(int r, int c, double* a) {
   }
   for (int j = 0; j < c; ++j)
     for (int i = j + 1; i < r; ++i) a[(size_t)j * r + i] = 0.0;
+}
+
+// Schur complement of a Gram matrix from its factor, without forming it:
+// for A = [Bw Bg]^T [Bw Bg] (Bw: rows x nw, Bg: rows x ng, column-major with
+// leading dimension rows, both overwritten), S = Bw^T (I - Q Q^T) Bw with Q an
+// orthonormal basis of range(Bg) -- the minimum over y of the energy of
+// [x; y], i.e. A_ww - A_wg A_gg^+ A_gw.  Q comes from Householder QR with
+// column pivoting of Bg; the factorisation stops (rank r) once the largest
+// remaining column norm is at most rtol times the first pivot's.  Each
+// reflector is applied to Bw as it is formed; S (nw x nw, column-major) is
+// then the Gram matrix of rows r.. of the transformed Bw.  Returns r.
+inline int schur_from_factor(int rows, int nw, int ng, double* Bw, double* Bg, double rtol,
+                             double* S) {
+  std::vector<double> v(std::max(rows, 1));
+  int r = 0;
+  double n0 = 0.0;
+  const int kmax = std::min(rows, ng);
+  for (int k = 0; k < kmax; ++k) {
+    int jm = k;
+    double best = -1.0;
+    for (int j = k; j < ng; ++j) {
+      const double* c = Bg + (size_t)j * rows;
+      double s = 0.0;
+      for (int i = k; i < rows; ++i) s += c[i] * c[i];
+      if (s > best) {
+        best = s;
+        jm = j;
+      }
+    }
+    best = std::sqrt(best);
+    if (k == 0) n0 = best;
+    if (!(best > rtol * n0) || best == 0.0) break;
+    if (jm != k)
+      std::swap_ranges(Bg + (size_t)k * rows, Bg + (size_t)(k + 1) * rows, Bg + (size_t)jm * rows);
+    const int m = rows - k;
+    double* col = Bg + (size_t)k * rows + k;
+    std::copy(col, col + m, v.begin());
+    double beta, alpha;
+    householder(m, v.data(), beta, alpha);
+    r = k + 1;
+    if (beta == 0.0) continue;
+    col[0] = alpha;
+    for (int i = 1; i < m; ++i) col[i] = 0.0;
+    auto reflect = [&](double* cj) {
+      double s = 0.0;
+      for (int i = 0; i < m; ++i) s += v[i] * cj[i];
+      s *= beta;
+      if (s == 0.0) return;
+      for (int i = 0; i < m; ++i) cj[i] -= s * v[i];
+    };
+    for (int j = k + 1; j < ng; ++j) reflect(Bg + (size_t)j * rows + k);
+    for (int j = 0; j < nw; ++j) reflect(Bw + (size_t)j * rows + k);
+  }
+  for (int j = 0; j < nw; ++j) {
+    const double* cj = Bw + (size_t)j * rows;
+    for (int i = j; i < nw; ++i) {
+      const double* ci = Bw + (size_t)i * rows;
+      double s = 0.0;
+      for (int t = r; t < rows; ++t) s += ci[t] * cj[t];
+      S[(size_t)j * nw + i] = s;
+      S[(size_t)i * nw + j] = s;
+    }
+  }
+  return r;
 }
 
 }  // namespace lsamg

@@ -404,14 +404,18 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     const int nO = (int)(L.optr[a + 1] - o0);
     const int ng = nO - nw;
     for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = j;
-    // A~_i (weighted, nO x nO) and A_ww = G_{nz,w}^T G_{nz,w}
-    std::vector<double> At((size_t)nO * nO, 0.0), Aww((size_t)nw * nw, 0.0);
+    // B = W^{1/2} G_{nz,Omega} (rows x nO, column-major; A~_i = B^T B) and
+    // A_ww = G_{nz,w}^T G_{nz,w}
+    int64_t rows = 0;
+    for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) rows += G.nrows[W.nz[e]];
+    std::vector<double> B((size_t)rows * nO, 0.0), Aww((size_t)nw * nw, 0.0);
     std::vector<int> lp;
+    int64_t r0 = 0;
     for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) {
       const int64_t g = W.nz[e];
       const int64_t s0 = G.sptr[g];
       const int ns = (int)(G.sptr[g + 1] - s0);
-      const double wg = 1.0 / (double)L.M[g];
+      const double sw = std::sqrt(1.0 / (double)L.M[g]);
       lp.resize(ns);
       for (int q = 0; q < ns; ++q) lp[q] = loc[G.supp[s0 + q]];
       const double* R = G.val.data() + G.vptr[g];
@@ -420,46 +424,20 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
         for (int qc = 0; qc < ns; ++qc) {
           const double vc = row[qc];
           if (vc == 0.0) continue;
-          double* col = At.data() + (size_t)lp[qc] * nO;
-          const bool cw = lp[qc] < nw;
+          B[(size_t)lp[qc] * rows + r0 + r] = sw * vc;
+          if (lp[qc] >= nw) continue;
           double* colw = Aww.data() + (size_t)lp[qc] * nw;
-          for (int qr = 0; qr < ns; ++qr) {
-            const double pr = row[qr] * vc;
-            col[lp[qr]] += wg * pr;
-            if (cw && lp[qr] < nw) colw[lp[qr]] += pr;
-          }
+          for (int qr = 0; qr < ns; ++qr)
+            if (lp[qr] < nw) colw[lp[qr]] += row[qr] * vc;
         }
       }
+      r0 += G.nrows[g];
     }
-    // S~ = A~_ww - A~_wG (A~_GG)^+ A~_Gw
+    // S~ = min over u_Gamma of the energy: B_w^T (I - Q Q^T) B_w, Q a basis
+    // of range(B_Gamma) (the pseudo-inverse reading of eq:gevp-S)
     std::vector<double> S((size_t)nw * nw);
-    for (int j = 0; j < nw; ++j)
-      for (int i = 0; i < nw; ++i) S[(size_t)j * nw + i] = At[(size_t)j * nO + i];
-    if (ng > 0) {
-      std::vector<double> Agg((size_t)ng * ng), lam(ng);
-      for (int j = 0; j < ng; ++j)
-        for (int i = 0; i < ng; ++i) Agg[(size_t)j * ng + i] = At[(size_t)(nw + j) * nO + nw + i];
-      if (!sym_eig(ng, Agg.data(), lam.data())) fail(LSAMG_ENOTSPD, "eigensolver did not converge");
-      const double lmax = std::max(lam[ng - 1], 0.0);
-      // Y = V_keep^T A~_Gw, then S -= Y^T diag(1/lam) Y
-      for (int c = 0; c < ng; ++c) {
-        if (!(lam[c] > p.pinv_rtol * lmax)) continue;
-        const double* v = Agg.data() + (size_t)c * ng;
-        std::vector<double> y(nw, 0.0);
-        for (int j = 0; j < nw; ++j) {
-          const double* col = At.data() + (size_t)j * nO + nw;   // A~_Gw column j
-          double s = 0.0;
-          for (int i = 0; i < ng; ++i) s += v[i] * col[i];
-          y[j] = s;
-        }
-        const double il = 1.0 / lam[c];
-        for (int j = 0; j < nw; ++j) {
-          const double f = y[j] * il;
-          double* sj = S.data() + (size_t)j * nw;
-          for (int i = 0; i < nw; ++i) sj[i] -= y[i] * f;
-        }
-      }
-    }
+    schur_from_factor((int)rows, nw, ng, B.data(), B.data() + (size_t)nw * rows, p.pinv_rtol,
+                      S.data());
     // S~ u = mu A_ww u  ->  C = L^{-1} S~ L^{-T}
     if (!chol_lower(nw, Aww.data())) fail(LSAMG_ENOTSPD, "A(omega,omega) is not SPD");
     std::vector<double> X(S);
