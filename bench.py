@@ -32,9 +32,15 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 METRIC = "solves/s to 1e-8 rel. residual (mixed vs FP64 V-cycle); p50/p99 latency"
 
 
-def cpu_baseline_cmd(N: int, iters: int):
+def cpu_baseline_cmd(N: int, reps: int):
+    """The oracle's solve phase in its assembled form (one CSR smoother per
+    level, its transpose for RAS-T, CSR A_l and P_l, the coarsest Cholesky
+    factor), timed on the host cores.  The child builds the hierarchy while
+    the GPU part runs, reports, then waits for a line on stdin before it
+    times one warm-up solve and `reps` solves to 1e-8, so the timed region
+    has the host to itself."""
     code = f"""
-import json, os, sys, time
+import json, os, platform, sys, time
 sys.path.insert(0, {ROOT!r})
 import numpy as np
 import oracle as O
@@ -43,11 +49,38 @@ prob = P.config2({N})
 t0 = time.time()
 H = O.setup(prob.G, 2, prob.grid, O.Params(cmin=(2,)))
 t_setup = time.time() - t0
-b = P.rhs_uniform(prob.n, P.CONFIG_RHS_SEED[2])
 t0 = time.time()
-x, info = O.pcg(H, b, tol=0.0, fixed_iters={iters})
-t = time.time() - t0
-print(json.dumps(dict(t_setup=t_setup, t_sample=t, iters={iters})))
+AV = O.AssembledVcycle(H)
+t_asm = time.time() - t0
+b = P.rhs_uniform(prob.n, P.CONFIG_RHS_SEED[2])
+print(json.dumps(dict(ready=True, t_setup=t_setup, t_assemble=t_asm)), flush=True)
+sys.stdin.readline()
+O.pcg(H, b, tol=1e-8, precond=AV)
+times, iters = [], []
+for _ in range({reps}):
+    t = time.perf_counter()
+    x, info = O.pcg(H, b, tol=1e-8, precond=AV)
+    times.append(time.perf_counter() - t)
+    iters.append(info["iters"])
+try:
+    from threadpoolctl import threadpool_info
+    blas = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+    blas_threads = max(d.get("num_threads", 1) for d in blas) if blas else 1
+    blas_name = blas[0].get("internal_api", "?") if blas else "?"
+except Exception:
+    blas_threads, blas_name = 1, "?"
+model = "?"
+try:
+    for ln in open("/proc/cpuinfo"):
+        if ln.startswith("model name"):
+            model = ln.split(":", 1)[1].strip()
+            break
+except OSError:
+    pass
+print(json.dumps(dict(t_setup=t_setup, t_assemble=t_asm, times=times, iters=iters,
+                      blas_threads=blas_threads, blas=blas_name, cpu_model=model,
+                      cpu_count=os.cpu_count(), affinity=len(os.sched_getaffinity(0)),
+                      true_rel_res=info["true_rel_res"])), flush=True)
 """
     return [sys.executable, "-c", code]
 
@@ -75,6 +108,29 @@ def measured_traffic(kernel: str):
                 and rec.get("source_sha256") == source_hash(rec["source_file"])):
             return rec["traffic_bytes_per_launch"]
     return None
+
+
+def method_bytes(inf, s: int):
+    """Bytes the method itself moves per PCG iteration, from the hierarchy's
+    sizes: per V-cycle level, both smoothers read the local-inverse rows
+    (2 s sum|omega||Omega|), two fused A-applies read G_l (nnz (s+4) + 4 m)
+    and two vectors each, P^T and P read P_l, plus about six vector passes;
+    the coarsest level reads its dense inverse once; each iteration adds a
+    fused FP64 A-apply and about ten FP64 vector passes.  Levels that the
+    library applies as one dense operator (the dense tail) are counted by
+    these, the method's own, steps.  s = bytes per V-cycle scalar."""
+    lv = inf["levels"]
+    per = []
+    for l, L in enumerate(lv):
+        if l == inf["nlevels"] - 1:
+            per.append(s * L["n"] ** 2)
+        else:
+            per.append(2 * s * L["smoother_entries"]
+                       + 2 * (L["g_nnz"] * (s + 4) + 4 * L["g_rows"] + 2 * s * L["n"])
+                       + 2 * s * L["p_entries"] + 6 * s * L["n"])
+    L0 = lv[0]
+    cg = L0["g_nnz"] * 12 + 4 * L0["g_rows"] + 16 * L0["n"] + 80 * L0["n"]
+    return sum(per) + cg, per, cg
 
 
 def percentile(v, q):
@@ -194,8 +250,8 @@ def main():
                          "A = D1 + B^T D2^-1 B on a 128^3 grid")
     ap.add_argument("--N", type=int, default=0,
                     help="cells per side (default 512 for aniso2d, 128 for ls3d)")
-    ap.add_argument("--cpu-iters", type=int, default=24,
-                    help="PCG iterations of the oracle's timed sample")
+    ap.add_argument("--cpu-reps", type=int, default=3,
+                    help="timed oracle solves of the CPU baseline (after one warm-up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64,
                     help="right-hand sides of the batched workload (0: skip)")
@@ -238,15 +294,14 @@ def main():
               "design notes). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    # CPU oracle baseline runs in a child process on the host cores while the
-    # GPU part runs (single-threaded BLAS: it uses one core)
+    # CPU oracle baseline: its setup runs in a child process while the GPU
+    # part runs; its timed solves run after the GPU part (BLAS on every core
+    # the host gives it)
     cpu_proc = None
     if not args.no_cpu_baseline:
-        env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1",
-                   MKL_NUM_THREADS="1")
-        cpu_proc = subprocess.Popen(cpu_baseline_cmd(args.N, args.cpu_iters),
-                                    stdout=subprocess.PIPE, stderr=subprocess.PIPE,
-                                    text=True, env=env)
+        cpu_proc = subprocess.Popen(cpu_baseline_cmd(args.N, args.cpu_reps),
+                                    stdin=subprocess.PIPE, stdout=subprocess.PIPE,
+                                    stderr=subprocess.PIPE, text=True)
 
     import torch
     import problems as P
@@ -309,6 +364,17 @@ def main():
     s.profile(False)
     dominant = allk[0]["name"]
     ktotal = sum(r["ms"] for r in allk)
+    # the same per kernel and level: each kernel's algorithmic bytes (the
+    # library's per-launch formula) over its time
+    s.profile(True, by_level=True)
+    s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
+    byl = sorted(s.profile_read(), key=lambda r: -r["ms"])
+    s.profile(False)
+    kernel_fracs = [dict(name=r["name"], us_per_launch=round(r["ms"] / r["launches"] * 1e3, 2),
+                         gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1),
+                         frac=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                         share=round(r["ms"] / ktotal, 3))
+                    for r in byl[:16] if r["launches"] and r["ms"] > 0]
 
     # timed region: the dominant kernel's launches carry HIP events (so the
     # V-cycle is launched kernel by kernel); the same solve replaying its
@@ -382,6 +448,15 @@ def main():
         print(f"batched fp64 {batched64['solves_per_s']:.2f} solves/s", file=sys.stderr,
               flush=True)
     dom = next((r for r in kp if r["name"] == dominant), None)
+    # whole-solve roofline: the method's bytes per iteration over the time
+    # per iteration of the timed solves
+    solve_roof = {}
+    for tag, res, sz in (("mixed", mixed, 4), ("fp64", fp64, 8)):
+        mb, per, cg = method_bytes(inf, sz)
+        gbs = mb / (res["ms_per_iteration"] * 1e-3) / 1e9
+        solve_roof[tag] = dict(bytes_per_iteration=int(mb), per_level_bytes=[int(v) for v in per],
+                               cg_bytes=int(cg), ms_per_iteration=round(res["ms_per_iteration"], 4),
+                               achieved=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4))
     roofline = None
     if dom and dom["launches"] > 0 and dom["ms"] > 0:
         avg_s = dom["ms"] / dom["launches"] * 1e-3
@@ -394,24 +469,46 @@ def main():
                         algorithmic_bytes_per_launch=int(bytes_per_launch),
                         launches=dom["launches"],
                         share_of_kernel_time=round(allk[0]["ms"] / ktotal, 3))
+        if dominant.startswith("k_sym_gemv") and inf["tail_level"] >= 0:
+            roofline["bytes_basis"] = (
+                f"dense-equivalent: the kernel applies the V-cycle of levels "
+                f">= {inf['tail_level']} as one packed symmetric matrix formed at "
+                f"setup; its bytes are that matrix's, not the method's steps for "
+                f"those levels (see solve)")
+    if roofline is not None:
+        roofline["solve"] = solve_roof
+        roofline["kernels"] = kernel_fracs
 
     cpu = None
     if cpu_proc is not None:
-        out, err = cpu_proc.communicate(timeout=1800)
+        print("cpu baseline: waiting for the oracle setup ...", file=sys.stderr, flush=True)
+        ready = cpu_proc.stdout.readline()
+        if ready.strip():
+            rd = json.loads(ready)
+            print(f"cpu baseline: oracle setup {rd['t_setup']:.0f} s, assembly "
+                  f"{rd['t_assemble']:.0f} s; timing {args.cpu_reps + 1} solves",
+                  file=sys.stderr, flush=True)
+        out, err = cpu_proc.communicate("go\n", timeout=1800)
         if cpu_proc.returncode == 0:
             r = json.loads(out.strip().splitlines()[-1])
-            # a solve = the initial V-cycle plus `iters` iterations each with one
-            # A-apply and one V-cycle; the sample ran cpu_iters of them
-            per_solve = r["t_sample"] * (fp64["iters"] + 1) / (r["iters"] + 1)
-            cpu = dict(value=round(1.0 / per_solve, 6), unit="solves/s", cores=1,
-                       kind="oracle",
-                       sample=(f"{r['iters']} PCG iterations ({r['iters'] + 1} V-cycles) of "
-                               f"the same solve, scaled to {fp64['iters']} iterations; "
-                               f"oracle setup {r['t_setup']:.0f} s untimed; 1 thread"),
-                       sample_seconds=round(r["t_sample"], 2))
+            tot = sum(r["times"])
+            cpu = dict(value=round(len(r["times"]) / tot, 6), unit="solves/s",
+                       cores=r["blas_threads"], kind="oracle",
+                       sample=(f"{len(r['times'])} whole solves to 1e-8 ({r['iters']} PCG "
+                               f"iterations each) after one warm-up, the same workload; "
+                               f"assembled form: each level's RAS smoother one CSR matrix, "
+                               f"RAS-T its transpose, CSR A_l and P_l, coarsest Cholesky; "
+                               f"scipy sparse products on one thread, dense solves on "
+                               f"{r['blas_threads']} {r['blas']} BLAS threads; "
+                               f"oracle setup {r['t_setup']:.0f} s + assembly "
+                               f"{r['t_assemble']:.0f} s untimed"),
+                       sample_seconds=round(tot, 2),
+                       p50_ms=round(percentile(r["times"], 0.5) * 1e3, 1),
+                       cpu_model=r["cpu_model"], cpu_count=r["cpu_count"],
+                       affinity=r["affinity"], true_rel_res=r["true_rel_res"])
         else:
-            cpu = dict(value=None, unit="solves/s", cores=1, kind="oracle",
-                       sample="failed: " + err.strip().splitlines()[-1][:200])
+            cpu = dict(value=None, unit="solves/s", cores=None, kind="oracle",
+                       sample="failed: " + (err.strip().splitlines() or ["?"])[-1][:200])
 
     smoother_entries = sum(l["smoother_entries"] for l in inf["levels"])
     line = {

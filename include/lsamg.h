@@ -100,11 +100,16 @@ typedef struct lsamg_params {
 /* Per-solve statistics (host memory, one entry per right-hand side). */
 typedef struct lsamg_stats {
   int32_t iters;         /* PCG iterations (applications of A)               */
-  int32_t converged;     /* 1 if ||r_k|| <= tol ||b||                        */
+  int32_t converged;     /* 1 if the recurrence residual and then the true
+                            residual b - A x both reached tol ||b||          */
   double rel_res;        /* ||r_k|| / ||b||, recurrence residual             */
   double true_rel_res;   /* ||b - A x|| / ||b||, recomputed in FP64          */
   double rho;            /* average convergence factor (||r_k||/||r_0||)^(1/k)*/
   double seconds;        /* wall time of the whole call                      */
+  int32_t restarts;      /* times the recurrence residual passed the test but
+                            the true residual did not: r was replaced by
+                            b - A x and CG restarted with p = z              */
+  int32_t reserved;
 } lsamg_stats;
 
 typedef struct lsamg_level_info {

@@ -18,7 +18,7 @@ convergence factors of the large configurations, which are parity unpinned
 (the paper's printed factors are for a different aggregation).
 """
 from .lsamg import (Params, Level, Hierarchy, setup, vcycle, pcg, ras, ras_t,
-                    apply_A, dense_preconditioner, stats)
+                    apply_A, dense_preconditioner, stats, AssembledVcycle)
 
 __all__ = ["Params", "Level", "Hierarchy", "setup", "vcycle", "pcg", "ras",
-           "ras_t", "apply_A", "dense_preconditioner", "stats"]
+           "ras_t", "apply_A", "dense_preconditioner", "stats", "AssembledVcycle"]

@@ -560,7 +560,8 @@ def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
 
 
 def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
-        fixed_iters: Optional[int] = None):
+        fixed_iters: Optional[int] = None,
+        precond: Optional[Callable] = None):
     """Preconditioned CG, x0 = 0, preconditioner = one V-cycle.
 
     Stops when ``||r_k||_2 <= tol ||b||_2`` for the recurrence residual and
@@ -568,15 +569,18 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
     recurrence residual passes, the true residual replaces it and CG restarts
     from ``x_k`` (direction ``p = z``), so a reported convergence always holds
     for ``b - A x``.  With ``fixed_iters`` it runs exactly that many
-    iterations.  Returns ``(x, info)`` with iteration count and residual
-    history (``restarts`` counts the replacements).
+    iterations.  ``precond(r)`` replaces the V-cycle by another form of the
+    same operator (``AssembledVcycle``).  Returns ``(x, info)`` with
+    iteration count and residual history (``restarts`` counts the
+    replacements).
     """
+    apply_b = precond if precond is not None else (lambda v: vcycle(H, v))
     A0 = H.levels[0]
     x = np.zeros_like(b)
     r = b.copy()
     nb = np.linalg.norm(b)
     hist = [np.linalg.norm(r)]
-    z = vcycle(H, r)
+    z = apply_b(r)
     pdir = z.copy()
     rho = r @ z
     its = 0
@@ -600,7 +604,7 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
             hist[-1] = np.linalg.norm(r)
             restart = True
             restarts += 1
-        z = vcycle(H, r)
+        z = apply_b(r)
         rho_new = r @ z
         if restart:
             pdir = z.copy()
@@ -611,6 +615,49 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
     rhoavg = (hist[-1] / hist[0]) ** (1.0 / max(its, 1)) if nb > 0 else 0.0
     return x, dict(iters=its, hist=np.array(hist), true_rel_res=true_res,
                    converged=bool(conv), rho=rhoavg, restarts=restarts)
+
+
+class AssembledVcycle:
+    """The same V-cycle with each level's operators assembled once as sparse
+    matrices, the plain form in which a CPU library would run the solve
+    phase: the RAS smoother ``S_l = sum_i R_i^T D_i A_i^{-1} R_i`` (eq:ras) as
+    one CSR matrix (its rows are the disjoint omega_i blocks of the local
+    inverses, ``sum_i |omega_i||Omega_i|`` entries), RAS-T (eq:ras-t) as its
+    transpose (``A_i^{-1}`` is symmetric and ``D_i`` diagonal), ``A_l`` and
+    ``P_l`` as CSR, and the coarsest level's Cholesky factor.  Applying it is
+    the V-cycle of ``vcycle`` with the local solves done through these
+    matrices instead of per-aggregate Cholesky solves."""
+
+    def __init__(self, H: Hierarchy):
+        self.H = H
+        self.S = []
+        self.ST = []
+        for L in H.levels:
+            if L.coarsest:
+                break
+            rr, cc, vv = [], [], []
+            for i in range(L.n_agg):
+                w, Om = L.omega[i], L.Omega[i]
+                Ainv = sla.cho_solve(L.chol[i], np.eye(len(Om)))
+                rr.append(np.repeat(w, len(Om)))
+                cc.append(np.tile(Om, len(w)))
+                vv.append(Ainv[:len(w), :].ravel())
+            S = sp.csr_matrix((np.concatenate(vv), (np.concatenate(rr), np.concatenate(cc))),
+                              shape=(L.n, L.n))
+            self.S.append(S)
+            self.ST.append(S.T.tocsr())
+
+    def apply(self, b: np.ndarray, level: int = 0) -> np.ndarray:
+        L = self.H.levels[level]
+        if L.coarsest:
+            return sla.cho_solve(L.chol_coarse, b)
+        x = self.S[level] @ b
+        r = b - L.A @ x
+        x = x + L.P @ self.apply(L.P.T @ r, level + 1)
+        r = b - L.A @ x
+        return x + self.ST[level] @ r
+
+    __call__ = apply
 
 
 def dense_preconditioner(H: Hierarchy) -> np.ndarray:

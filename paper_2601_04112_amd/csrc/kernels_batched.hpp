@@ -1662,6 +1662,54 @@ __global__ void __launch_bounds__(kBlock) k_bcg_dir(int64_t n, const double* __r
     P[e] = rz_old ? Z[e] + beta * P[e] : Z[e];   // first direction: P = Z (P may hold stale data)
 }
 
+// partials of ||B - Q||^2 per column (true residual with Q = A X)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bres_parts(int64_t n, const double* __restrict__ B,
+                                                       const double* __restrict__ Q,
+                                                       double* __restrict__ part) {
+  double v = 0;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
+       e += (int64_t)gridDim.x * kBlock) {
+    const double d = B[e] - Q[e];
+    v += d * d;
+  }
+  bwrite_parts<NB>(v, part);
+}
+
+// CG restart of the masked columns: R = B - Q (Q = A X), R32 = (float) R
+// (if given), and rho_old = 0 so that the next direction of such a column is
+// P = Z (beta = 0)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bcg_restart(int64_t n, const int* __restrict__ mask,
+                                                        const double* __restrict__ B,
+                                                        const double* __restrict__ Q,
+                                                        double* __restrict__ R,
+                                                        float* __restrict__ R32,
+                                                        double* __restrict__ rz_old) {
+  const int j = threadIdx.x % NB;
+  if (!mask[j]) return;
+  if (blockIdx.x == 0 && threadIdx.x < NB) rz_old[j] = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
+       e += (int64_t)gridDim.x * kBlock) {
+    const double r = B[e] - Q[e];
+    R[e] = r;
+    if (R32) R32[e] = (float)r;
+  }
+}
+
+// P = Z on the masked columns only (restart after the next direction of the
+// other columns was already formed)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bcg_dir_mask(int64_t n, const int* __restrict__ mask,
+                                                         const double* __restrict__ Z,
+                                                         double* __restrict__ P) {
+  const int j = threadIdx.x % NB;
+  if (!mask[j]) return;
+  for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
+       e += (int64_t)gridDim.x * kBlock)
+    P[e] = Z[e];
+}
+
 // Bi[i][j] = b[j*ld + perm[i]]  (user column-major -> internal interleaved)
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_bperm_in(int64_t n, int nrhs, int64_t ld,

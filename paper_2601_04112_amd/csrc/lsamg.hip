@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "launch_checks.hpp"
 #include "kernels.hpp"
 #include "kernels_batched.hpp"
 
@@ -109,6 +110,7 @@ struct GemvPlan {
     unsigned grid = 0;       // workgroups of the persistent launch
     dev::MmTasks tk{};
     float* part = nullptr;   // partial sums of a split loop (split > 1)
+    int64_t part_cap = 0;    // floats that part holds
   } mm;
   Mm mmd;                    // FP64 on the matrix cores (k_bmmd; rt 0: k_bgemm)
 };
@@ -142,6 +144,7 @@ struct DLevel {
   int64_t dmm_ld = 0;     // row stride of dmm_M
   double* dmmd_M = nullptr;    // the padded row-major copy of the FP64 operator (batched buffers)
   double* dmmd_part = nullptr; // its partial sums of split loops (batched buffers)
+  int64_t dmmd_part_cap = 0;   // doubles that dmmd_part holds
   int dmmd_split = 0;     // dense level, 64 columns, FP64: k_dense_mm64d loop ranges (0: bgemm)
   int dmmd_kchunk = 0, dmmd_kc = 0;
   int lanes_g = 1, lanes_gt = 1;
@@ -353,8 +356,8 @@ struct lsamg_handle {
          *Btmp = nullptr;
   // per-column scalars summed from those partials (k_bsum)
   double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr;
-  int* Bactive = nullptr;
-  int* Bactive_host = nullptr;       // pinned
+  int* Bactive = nullptr;            // 64 active flags, then 64 restart flags
+  int* Bactive_host = nullptr;       // pinned, the same two arrays
   double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
   // export buffers
   std::vector<int32_t> ex_agg, ex_k, ex_M;
@@ -401,6 +404,7 @@ struct lsamg_handle {
       D.dmm_M = nullptr;                // freed with the batched buffers below
       D.dmmd_M = nullptr;
       D.dmmd_part = nullptr;
+      D.dmmd_part_cap = 0;
       D.bg_on = false;                  // its staging goes with them too
     }
     mm_tuned = false;
@@ -1593,6 +1597,24 @@ void gv_tune(lsamg_handle* h, hipStream_t s) {
   h->gv_tuned[pi] = true;
 }
 
+// ||b - A x||_2 in FP64 (the true residual, left in h->z; q is overwritten)
+double true_residual(lsamg_handle* h, hipStream_t s) {
+  const int64_t n = h->L[0].n;
+  const unsigned gb = nblocks(n);
+  apply_A(h, h->x, h->q, s);
+  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_sub, n, h->bi, h->q, h->z);
+  LAUNCH_OK();
+  dot_parts(h, n, h->z, h->z, h->p_tmp, s);
+  parts_to_host(h, h->p_tmp, 0, s);
+  HIP_OK(hipStreamSynchronize(s));
+  return std::sqrt(host_sum(h, 0));
+}
+
+// Stop test: the recurrence residual ||r_k|| <= tol ||b|| and then the true
+// residual ||b - A x_k|| <= tol ||b||, both in FP64.  When only the first
+// holds, r is replaced by the true residual and CG restarts from x_k with
+// p = z (in FP32 V-cycle mode the two residuals part by the preconditioner's
+// rounding, so a reported convergence is always one of b - A x).
 int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, hipStream_t s,
             lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
@@ -1612,8 +1634,8 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
   if (!std::isfinite(nb2)) throw DevError{LSAMG_EBADINPUT, "non-finite entry in the right-hand side"};
   const double nb = std::sqrt(nb2);
   const bool mixed = h->precision == LSAMG_MIXED;
-  int its = 0;
-  double rn = nb, rprev = nb, fac = 0.5;
+  int its = 0, restarts = 0;
+  double rn = nb, rprev = nb, fac = 0.5, tr = -1.0;
   bool conv = (nb == 0.0);
   if (!conv && maxit > 0) {
     if (mixed) {
@@ -1646,31 +1668,41 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
       if (!std::isfinite(rn)) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
       fac = std::pow(rn / nb, 1.0 / its);
       rprev = rn;
+      bool restart = false;
       if (rn <= target) {
-        conv = true;
-        break;
+        tr = true_residual(h, s);
+        if (tr <= target) {
+          conv = true;
+          break;
+        }
+        // replace r by b - A x (left in z) and restart with p = z
+        KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_copy, n, h->z, h->r);
+        LAUNCH_OK();
+        if (mixed) {
+          KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<double, float>, n, h->r, L0.f.b);
+          LAUNCH_OK();
+        }
+        rn = rprev = tr;
+        tr = -1.0;
+        restart = true;
+        ++restarts;
       }
       if (its >= maxit) break;
-      if (near) cg_precondition(h, s, false, 1 - cur);
+      if (near || restart) cg_precondition(h, s, restart, 1 - cur);
       cur = 1 - cur;
     }
   }
-  // true residual in FP64
-  apply_A(h, h->x, h->q, s);
-  KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_sub, n, h->bi, h->q, h->z);
-  LAUNCH_OK();
-  dot_parts(h, n, h->z, h->z, h->p_tmp, s);
-  parts_to_host(h, h->p_tmp, 0, s);
+  if (tr < 0.0) tr = true_residual(h, s);
   KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_out, n, h->perm, h->x, x);
   LAUNCH_OK();
   HIP_OK(hipStreamSynchronize(s));
-  const double tr = std::sqrt(host_sum(h, 0));
   if (st) {
     st->iters = its;
     st->converged = conv ? 1 : 0;
     st->rel_res = nb > 0 ? rn / nb : 0.0;
     st->true_rel_res = nb > 0 ? tr / nb : 0.0;
     st->rho = (its > 0 && nb > 0) ? std::pow(rn / nb, 1.0 / its) : 0.0;
+    st->restarts = restarts;
     st->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return conv ? LSAMG_OK : LSAMG_ENOCONV;
@@ -1695,13 +1727,13 @@ void ensure_batched(lsamg_handle* h, int NB) {
     if (L.n >= ((int64_t)1 << 31) || L.nrows >= ((int64_t)1 << 31))
       throw DevError{LSAMG_EINVAL, "level too large for the multi-right-hand-side path"};
   h->bwidth = NB;
-  const int kBMax = NB;            // buffers sized for this width
+  const int W = NB;                // buffers sized for this width
   h->BL.assign(h->L.size(), lsamg_handle::BLev{});
   for (size_t l = 0; l < h->L.size(); ++l) {
     DLevel& L = h->L[l];
     auto& B = h->BL[l];
-    const size_t n = (size_t)L.n * kBMax, ny = (size_t)std::max<int64_t>(L.nrows, 1) * kBMax,
-                 nt = (size_t)std::max<int64_t>(L.ntb, 1) * kBMax;
+    const size_t n = (size_t)L.n * W, ny = (size_t)std::max<int64_t>(L.nrows, 1) * W,
+                 nt = (size_t)std::max<int64_t>(L.ntb, 1) * W;
     B.x = h->alloc<double>(n);
     B.b = h->alloc<double>(n);
     B.r = h->alloc<double>(n);
@@ -1712,28 +1744,28 @@ void ensure_batched(lsamg_handle* h, int NB) {
     B.fr = h->alloc<float>(n);
     B.fy = h->alloc<float>(ny);
     B.ftb = h->alloc<float>(nt);
-    if (L.bg_ok) B.fstg = h->alloc<float>((size_t)L.bg_nstg * kBMax);
+    if (L.bg_ok) B.fstg = h->alloc<float>((size_t)L.bg_nstg * W);
   }
-  const size_t n0 = (size_t)h->L[0].n * kBMax;
+  const size_t n0 = (size_t)h->L[0].n * W;
   h->BX = h->alloc<double>(n0);
   h->BR = h->alloc<double>(n0);
   h->BZ = h->alloc<double>(n0);
   h->BP = h->alloc<double>(n0);
   h->BQ = h->alloc<double>(n0);
   h->BBi = h->alloc<double>(n0);
-  h->Bpq = h->alloc<double>(kBNP * kBMax);
-  h->Brr = h->alloc<double>(kBNP * kBMax);
-  h->Brz[0] = h->alloc<double>(kBNP * kBMax);
-  h->Brz[1] = h->alloc<double>(kBNP * kBMax);
-  h->Btmp = h->alloc<double>(kBNP * kBMax);
-  h->Bpq_s = h->alloc<double>(kBMax);
-  h->Brr_s = h->alloc<double>(kBMax);
-  h->Brz_s[0] = h->alloc<double>(kBMax);
-  h->Brz_s[1] = h->alloc<double>(kBMax);
-  h->Btmp_s = h->alloc<double>(kBMax);
-  h->Bactive = h->alloc<int>(kBMax);
+  h->Bpq = h->alloc<double>(kBNP * W);
+  h->Brr = h->alloc<double>(kBNP * W);
+  h->Brz[0] = h->alloc<double>(kBNP * W);
+  h->Brz[1] = h->alloc<double>(kBNP * W);
+  h->Btmp = h->alloc<double>(kBNP * W);
+  h->Bpq_s = h->alloc<double>(W);
+  h->Brr_s = h->alloc<double>(W);
+  h->Brz_s[0] = h->alloc<double>(W);
+  h->Brz_s[1] = h->alloc<double>(W);
+  h->Btmp_s = h->alloc<double>(W);
+  h->Bactive = h->alloc<int>(2 * 64);   // active and restart flags of up to 64 columns
   if (!h->Bactive_host)
-    HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 64 * sizeof(int), hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 2 * 64 * sizeof(int), hipHostMallocDefault));
   if (!h->Bparts_host)
     HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * 64 * sizeof(double),
                          hipHostMallocDefault));
@@ -1827,6 +1859,10 @@ void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
                 const int64_t* cptr, const int64_t* cpos, const float* tb, const float* M,
                 const float* in, float* out, hipStream_t s, double bytes) {
   const bool split = mm.split > 1;
+  if (!split_fits(mm.split, P.out, NB, mm.part, mm.part_cap))
+    throw DevError{LSAMG_EINVAL, "matrix-core launch: the loop split's partial sums (" +
+                                     std::to_string(mm.split) + " x " + std::to_string(P.out) +
+                                     " x " + std::to_string(NB) + ") exceed their buffer"};
   bool done = false;
   if constexpr (NB == 64) {
     if (mm.lds) {
@@ -1968,6 +2004,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
     mm.u = c.u;
     mm.lds = c.lds;
     mm.part = part;
+    mm.part_cap = part_cap;
     float ms = 1e30f;
     try {
       bmm_launch<MODE, ADD, NB>(P, mm, gidx, cptr, cpos, tb, M, in, out, s, 0.0);
@@ -2006,6 +2043,7 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   P.mm.u = pick.u;
   P.mm.lds = pick.lds;
   P.mm.part = part;
+  P.mm.part_cap = part_cap;
   return best;
 }
 
@@ -2014,8 +2052,11 @@ float mm_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
 // of kchunk rows (S > 1: partial sums in part, then k_bmm_reduce in slot
 // order).
 void dense_mm_launch(const DLevel& L, int S, int kchunk, int KC, const float* in, float* out,
-                     float* part, hipStream_t s) {
+                     float* part, int64_t part_cap, hipStream_t s) {
   const int64_t n = L.n;
+  if (!split_fits(S, n, 64, part, part_cap))
+    throw DevError{LSAMG_EINVAL, "dense-level launch: " + std::to_string(S) +
+                                     " loop ranges exceed the partial-sum buffer"};
   {
     PROF("k_dense_mm64", sizeof(float) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))),
          s);
@@ -2078,7 +2119,7 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
         dense_split_shape(n, w, KC, &S, &kc);
         while (S > 1 && (int64_t)S * n * 64 > part_cap) dense_split_shape(n, S - 1, KC, &S, &kc);
         if (S > 1 && !part) dense_split_shape(n, 1, KC, &S, &kc);
-        dense_mm_launch(L, S, kc, KC, in, out, part, s);
+        dense_mm_launch(L, S, kc, KC, in, out, part, part_cap, s);
         float ms = 1e30f;
         for (int round = 0; round < 1; ++round) {   // three launches after the warm-up
           float tot = 0.f;
@@ -2086,7 +2127,7 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
             if (flush)
               KLAUNCH0(nblocks(flush_n), dev::kBlock, 0, s, dev::k_fill, flush_n, 0.0, flush);
             HIP_OK(hipEventRecord(e0, s));
-            dense_mm_launch(L, S, kc, KC, in, out, part, s);
+            dense_mm_launch(L, S, kc, KC, in, out, part, part_cap, s);
             HIP_OK(hipEventRecord(e1, s));
             HIP_OK(hipEventSynchronize(e1));
             float t = 0.f;
@@ -2118,6 +2159,9 @@ void dense_tune(lsamg_handle* h, DLevel& L, const float* M, const float* in, flo
 void dense_mm_launch_d(const DLevel& L, int S, int kchunk, int KC, const double* in, double* out,
                        hipStream_t s) {
   const int64_t n = L.n;
+  if (!split_fits(S, n, 64, L.dmmd_part, L.dmmd_part_cap))
+    throw DevError{LSAMG_EINVAL, "FP64 dense-level launch: " + std::to_string(S) +
+                                     " loop ranges exceed the partial-sum buffer"};
   {
     PROF("k_dense_mm64d",
          sizeof(double) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))), s);
@@ -2252,6 +2296,7 @@ void fp64_tune(lsamg_handle* h, hipStream_t s) {
                L.d.Ainv, L.dmmd_M);
       LAUNCH_OK();
       L.dmmd_part = h->alloc<double>((size_t)(16 * n * 64));
+      L.dmmd_part_cap = 16 * n * 64;
     }
     float best = 1e30f;
     if (h->dense_split == 0)
@@ -2420,7 +2465,8 @@ void bvcycle(lsamg_handle* h, size_t l, const T* B, T* X, hipStream_t s, bool fi
   if (L.coarsest || L.tail) {
     if constexpr (std::is_same<T, float>::value && NB == 64) {
       if (L.dmm_split > 0) {
-        dense_mm_launch(L, L.dmm_split, L.dmm_kchunk, L.dmm_kc, B, X, L.dense.mm.part, s);
+        dense_mm_launch(L, L.dmm_split, L.dmm_kchunk, L.dmm_kc, B, X, L.dense.mm.part,
+                        L.dense.mm.part_cap, s);
         return;
       }
     }
@@ -2721,8 +2767,13 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
   bsum<NB>(pq_part, pq, s);
 }
 
+// Z = B R (one batched V-cycle), rho partials into Brz[cur], and the next
+// direction P = Z + beta P (P = Z when first); with restart_mask given, only
+// the masked columns take P = Z and the others keep P (their direction was
+// already formed from the same Z)
 template <int NB>
-void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
+void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
+                      const int* restart_mask = nullptr) {
   DLevel& L0 = h->L[0];
   const int64_t n = L0.n;
   auto& B0 = h->BL[0];
@@ -2757,6 +2808,13 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   }
   LAUNCH_OK();
   bsum<NB>(h->Brz[cur], h->Brz_s[cur], s);
+  if (restart_mask) {
+    PROF(kname("k_bcg_dir_mask", std::to_string(NB)), 16 * n * NB, s);
+    KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir_mask<NB>, n, restart_mask,
+            (const double*)h->BZ, h->BP);
+    LAUNCH_OK();
+    return;
+  }
   PROF(kname("k_bcg_dir", std::to_string(NB)), 24 * n * NB, s);
   KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, (const double*)h->Brz_s[cur],
           first ? (const double*)nullptr : (const double*)h->Brz_s[1 - cur], (const double*)h->BZ,
@@ -2808,7 +2866,7 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
   bparts_to_host(h, h->Btmp_s, NB, 0, s);
   HIP_OK(hipStreamSynchronize(s));
   double nb2[kBMax], rr[kBMax], nbv[kBMax], rn[kBMax];
-  int its_col[kBMax], conv_col[kBMax];
+  int its_col[kBMax], conv_col[kBMax], restarts_col[kBMax] = {};
   bhost_sums(h, NB, 0, nb2);
   int nactive = 0;
   for (int j = 0; j < NB; ++j) {
@@ -2821,7 +2879,9 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
     h->Bactive_host[j] = (j < nr && nbv[j] > 0.0 && maxit > 0) ? 1 : 0;
     nactive += h->Bactive_host[j];
   }
-  HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, NB * sizeof(int), hipMemcpyHostToDevice, s));
+  for (int j = 0; j < kBMax; ++j) h->Bactive_host[kBMax + j] = 0;
+  HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, 2 * kBMax * sizeof(int), hipMemcpyHostToDevice,
+                        s));
   const bool mixed = h->precision == LSAMG_MIXED;
   int its = 0;
   double fac = 0.5;
@@ -2857,23 +2917,61 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
       bhost_sums(h, NB, slot, rr);
       nactive = 0;
       double worst = 0;
+      int ncand = 0;
       for (int j = 0; j < NB; ++j) {
         if (!h->Bactive_host[j]) continue;
         rn[j] = std::sqrt(rr[j]);
         if (!std::isfinite(rn[j])) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
         its_col[j] = its;
-        if (rn[j] <= tol * nbv[j]) {
-          conv_col[j] = 1;
-          h->Bactive_host[j] = 0;
-        } else {
-          ++nactive;
-          worst = std::max(worst, std::pow(rn[j] / nbv[j], 1.0 / its));
+        ncand += rn[j] <= tol * nbv[j];
+      }
+      // columns whose recurrence residual passes: their true residual
+      // b - A x decides (one batched A-apply for the whole block)
+      int* rmask = h->Bactive_host + kBMax;
+      for (int j = 0; j < kBMax; ++j) rmask[j] = 0;
+      int nrestart = 0;
+      if (ncand > 0) {
+        bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
+        KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, n, (const double*)h->BBi,
+                 (const double*)h->BQ, h->Btmp);
+        LAUNCH_OK();
+        bsum<NB>(h->Btmp, h->Btmp_s, s);
+        bparts_to_host(h, h->Btmp_s, NB, 0, s);
+        HIP_OK(hipStreamSynchronize(s));
+        double t2[kBMax];
+        bhost_sums(h, NB, 0, t2);
+        for (int j = 0; j < NB; ++j) {
+          if (!h->Bactive_host[j] || !(rn[j] <= tol * nbv[j])) continue;
+          const double tn = std::sqrt(t2[j]);
+          if (tn <= tol * nbv[j]) {
+            conv_col[j] = 1;
+            h->Bactive_host[j] = 0;
+          } else {
+            rmask[j] = 1;
+            rn[j] = tn;
+            ++restarts_col[j];
+            ++nrestart;
+          }
         }
+      }
+      for (int j = 0; j < NB; ++j) {
+        if (!h->Bactive_host[j]) continue;
+        ++nactive;
+        worst = std::max(worst, std::pow(rn[j] / nbv[j], 1.0 / its));
       }
       if (worst > 0) fac = worst;
       if (nactive == 0 || its >= maxit) break;
-      HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, NB * sizeof(int), hipMemcpyHostToDevice,
-                            s));
+      HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, 2 * kBMax * sizeof(int),
+                            hipMemcpyHostToDevice, s));
+      if (nrestart > 0) {
+        // R = B - A X on the restarted columns (A X is in BQ), rho_old = 0
+        KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_restart<NB>, n,
+                 (const int*)(h->Bactive + kBMax), (const double*)h->BBi, (const double*)h->BQ,
+                 h->BR, mixed ? B0.fb : (float*)nullptr, h->Brz_s[cur]);
+        LAUNCH_OK();
+        if (!near)                      // the other columns' next direction is formed
+          bcg_precondition<NB>(h, s, false, 1 - cur, h->Bactive + kBMax);
+      }
       if (near) bcg_precondition<NB>(h, s, false, 1 - cur);
       cur = 1 - cur;
     }
@@ -2904,6 +3002,7 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
       st[j].rel_res = nbv[j] > 0 ? rn[j] / nbv[j] : 0.0;
       st[j].true_rel_res = nbv[j] > 0 ? std::sqrt(tr2[j]) / nbv[j] : 0.0;
       st[j].rho = (its_col[j] > 0 && nbv[j] > 0) ? std::pow(rn[j] / nbv[j], 1.0 / its_col[j]) : 0.0;
+      st[j].restarts = restarts_col[j];
       st[j].seconds = secs;
     }
   }

@@ -55,7 +55,8 @@ class Params(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32),
                 ("rel_res", C.c_double), ("true_rel_res", C.c_double),
-                ("rho", C.c_double), ("seconds", C.c_double)]
+                ("rho", C.c_double), ("seconds", C.c_double),
+                ("restarts", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -3,17 +3,23 @@
 Tolerances (FP64 path): operators A, RAS, RAS-T agree to 1e-12 relative (the
 library applies explicit local-inverse rows, the oracle Cholesky solves; both
 backward stable on blocks with condition numbers below 1e3); the V-cycle and
-PCG iterates at equal iteration counts agree to 1e-10 relative.  Mixed path
-(FP32 V-cycle under FP64 CG): the true FP64 residual reaches the solve
-tolerance and iteration counts stay within 10% of the oracle's.
+PCG iterates at equal iteration counts agree to 1e-10 relative, single- and
+multi-right-hand-side, on every 2D case.  The Schur complement of eq:gevp-S
+is formed from the weighted rows of G on both sides (never from
+A~_GammaGamma), so even the cases with singular coarse A~_GammaGamma
+("illcond") keep FP64 rounding at its own level.
 
-Where a coarse-level A~_GammaGamma of eq:gevp-S keeps an eigenvalue far below
-its largest (ratio r), the Schur complement amplifies FP64 rounding by ~1/r
-in any implementation (the oracle and the library build A~ from differently
-rounded rows), so two correct FP64 codes agree only to the first-order
-forward-error bound u/r there (u = 2.2e-16).  The V-cycle tolerance is
-therefore max(1e-10, u/r) with r measured on the oracle hierarchy, and ten
-times that for PCG iterates; the "illcond" and 3D cases exercise r < 1e-11.
+The 3D case (anisotropy oblique to the grid, lognormal coefficient) is one
+where CG itself amplifies rounding: the oracle run on a right-hand side
+perturbed by one unit in the last place drifts from its own unperturbed
+iterate by ~1e-11 after 15 iterations and ~1e-9 after 25.  Its PCG iterates
+are compared at 1e-10 for as many iterations as the oracle's own drift stays
+below 1e-12, and at ten times the measured drift beyond that.
+
+Mixed path (FP32 V-cycle under FP64 CG): the library stops only when the
+true FP64 residual b - A x reaches the tolerance (the oracle's rule), so the
+residual computed with the oracle's A is asserted <= tol, and iteration
+counts stay within 10% of the oracle's.
 """
 import hashlib
 import json
@@ -123,7 +129,18 @@ U = 2.220446049250313e-16
 
 
 def vtol(H):
-    return max(1e-10, U / min_kept_gamma_ratio(H))
+    """FP64 parity bound of V-cycles and PCG iterates (see the module
+    docstring)."""
+    return 1e-10
+
+
+def oracle_drift(H, b, K, seed=1):
+    """Relative change of the oracle's K-iteration PCG iterate when b is
+    perturbed by one rounding unit per entry: CG's own sensitivity."""
+    b2 = b * (1 + U * np.random.default_rng(seed).standard_normal(len(b)))
+    x1, _ = O.pcg(H, b, fixed_iters=K)
+    x2, _ = O.pcg(H, b2, fixed_iters=K)
+    return rel(x2, x1)
 
 
 def test_apply_A(cfg1, rot):
@@ -164,20 +181,21 @@ def test_vcycle_mixed(which, request):
 
 @pytest.mark.parametrize("which", CASES)
 def test_pcg_fixed_iterations(which, request):
-    """Same iteration count as the oracle: iterates agree to 10 x vtol."""
+    """Same iteration count as the oracle: iterates agree to 1e-10."""
     p, H, s = request.getfixturevalue(which)
     s.set_precision(L.FP64)
     b = P.rhs_uniform(p.n, 0)
     xo, info = O.pcg(H, b, tol=1e-8)
     k = info["iters"]
+    assert info["restarts"] == 0
     x, st = s.solve(dvec(b), tol=0.0, maxit=k)
     assert st[0]["iters"] == k and st[0]["converged"] == 0
-    assert rel(host(x), xo) <= 10 * vtol(H)
+    assert rel(host(x), xo) <= vtol(H), rel(host(x), xo)
     # converged run: same stop iteration (+-1), true residual at tolerance
     x2, st2 = s.solve(dvec(b), tol=1e-8, maxit=500)
     assert abs(st2[0]["iters"] - k) <= 1 and st2[0]["converged"] == 1
     r = np.linalg.norm(b - H.levels[0].A @ host(x2)) / np.linalg.norm(b)
-    assert r <= 1.01e-8 and abs(r - st2[0]["true_rel_res"]) <= 1e-12
+    assert r <= 1e-8 and abs(r - st2[0]["true_rel_res"]) <= 1e-12
 
 
 @pytest.mark.parametrize("which", CASES)
@@ -191,7 +209,7 @@ def test_pcg_mixed(which, request):
     finally:
         s.set_precision(L.FP64)
     r = np.linalg.norm(b - H.levels[0].A @ host(x)) / np.linalg.norm(b)
-    assert st[0]["converged"] == 1 and r <= 1.05e-8
+    assert st[0]["converged"] == 1 and r <= 1e-8
     assert st[0]["iters"] <= math.ceil(1.10 * info["iters"])
 
 
@@ -213,9 +231,9 @@ def test_batched_equals_single(rot, nrhs):
     for j in range(nrhs):
         x1, st1 = s.solve(dvec(B[j]), tol=1e-8)
         assert abs(st[j]["iters"] - st1[0]["iters"]) <= 1
-        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1.01e-8
+        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1e-8
         r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
-        assert r <= 1.01e-8
+        assert r <= 1e-8
 
 
 @pytest.mark.parametrize("which", ["rot", "rot_tail"])
@@ -230,7 +248,7 @@ def test_batched_mixed(which, request):
         s.set_precision(L.FP64)
     for j in range(5):
         r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
-        assert st[j]["converged"] == 1 and r <= 1.05e-8
+        assert st[j]["converged"] == 1 and r <= 1e-8
         assert st[j]["iters"] <= math.ceil(1.10 * info["iters"]) + 1
 
 
@@ -410,7 +428,7 @@ def test_batched_two_pass_apply(rot):
         Xh = host(X)
         for j in (0, 31, 63):
             r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
-            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+            assert st[j]["converged"] == 1 and r <= 1e-8, (j, r)
     finally:
         s.set_option(L.OPT_ONEPASS_ATA, 1)
         s.set_precision(L.FP64)
@@ -457,7 +475,7 @@ def test_batched_tiled_ata(rot):
         Xh = host(Xm)
         for j in (0, 31, 63):
             r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
-            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+            assert st[j]["converged"] == 1 and r <= 1e-8, (j, r)
     finally:
         s.profile(False)
         s.set_option(L.OPT_ATA_TILES, 1)
@@ -487,7 +505,7 @@ def test_single_cg_tile(rot, prec):
             assert ("k_cg_dir" in names) == (not on), (on, sorted(names))
             out[on], its[on] = host(x), st[0]["iters"]
             r = np.linalg.norm(b - H.levels[0].A @ out[on]) / np.linalg.norm(b)
-            assert st[0]["converged"] == 1 and r <= 1.05e-8, (on, r)
+            assert st[0]["converged"] == 1 and r <= 1e-8, (on, r)
         assert its[1] == its[0]
         if prec == L.FP64:
             x8 = {}
@@ -537,7 +555,7 @@ def test_batched_group_pass(which, request):
         Xh = host(X)
         for j in (0, 32, 63):
             r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
-            assert st[j]["converged"] == 1 and r <= 1.05e-8, (j, r)
+            assert st[j]["converged"] == 1 and r <= 1e-8, (j, r)
     finally:
         s.profile(False)
         s.set_option(L.OPT_BGROUP, 0)
@@ -558,7 +576,7 @@ def test_more_than_one_batch(rot):
             Xh = host(X)
             for j in (0, 31, 63, 64, 69):
                 r = np.linalg.norm(B[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(B[j])
-                assert st[j]["converged"] == 1 and r <= 1.05e-8, (prec, j, r)
+                assert st[j]["converged"] == 1 and r <= 1e-8, (prec, j, r)
         s.set_precision(L.FP64)
         X, _ = s.solve(dB, tol=0.0, maxit=6)
         for j in (0, 63, 64, 69):
@@ -577,7 +595,7 @@ def test_batched_edge_columns(cfg1):
     assert st[1]["iters"] == 0 and st[1]["converged"] == 1 and np.all(host(X[1]) == 0)
     for j in (0, 2):
         r = np.linalg.norm(B[j] - H.levels[0].A @ host(X[j])) / np.linalg.norm(B[j])
-        assert r <= 1.01e-8
+        assert r <= 1e-8
     q = P.aniso2d(12, 0.2, 0.3)
     s1 = L.Solver(q.G, 2, q.grid, device=0)
     Bq = np.stack([P.rhs_uniform(q.n, 5 + j) for j in range(3)])
@@ -634,6 +652,11 @@ def test_full_coarse_space_is_direct(gpu_device):
 
 @pytest.mark.parametrize("tail", [0, 16384])
 def test_3d_small(gpu_device, tail):
+    """3D D1 + B^T D2^-1 B form: V-cycle to 1e-10; PCG iterates to 1e-10 for
+    the iterations over which the oracle's own drift under a one-ulp change
+    of b stays below 1e-12, and to ten times that drift at the oracle's stop
+    count; the converged solve reaches the tolerance on the true residual
+    with a stop count inside the range the perturbed oracle runs give."""
     p = P.ls3d(12)
     H, s = build(p, 3, O.Params(block=3, cmin=(2,), max_coarse=100),
                  block=3, cmin=(2,), max_coarse=100, dense_tail=tail)
@@ -642,9 +665,107 @@ def test_3d_small(gpu_device, tail):
     assert rel(host(s.apply(L.OP_VCYCLE, dvec(v))), O.vcycle(H, v)) <= vtol(H)
     b = P.rhs_uniform(p.n, 3)
     _, info = O.pcg(H, b, tol=1e-8)
+    K = info["iters"]
+    k_ok = max(k for k in range(1, K + 1, 3) if k == 1 or oracle_drift(H, b, k) <= 1e-12)
+    for k in (k_ok, K):
+        xo, _ = O.pcg(H, b, fixed_iters=k)
+        x, _ = s.solve(dvec(b), tol=0.0, maxit=k)
+        bound = vtol(H) if k == k_ok else max(vtol(H), 10 * oracle_drift(H, b, k))
+        assert rel(host(x), xo) <= bound, (k, rel(host(x), xo), bound)
+    stops = [K] + [O.pcg(H, b * (1 + U * np.random.default_rng(q).standard_normal(p.n)),
+                         tol=1e-8)[1]["iters"] for q in (1, 2, 3)]
     x, st = s.solve(dvec(b), tol=1e-8)
-    assert abs(st[0]["iters"] - info["iters"]) <= 1 and st[0]["true_rel_res"] <= 1.01e-8
+    assert min(stops) - 1 <= st[0]["iters"] <= max(stops) + 1, (st[0]["iters"], stops)
+    r = np.linalg.norm(b - H.levels[0].A @ host(x)) / np.linalg.norm(b)
+    assert st[0]["converged"] == 1 and r <= 1e-8
     s.close()
+
+
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_batched_vs_oracle(which, request):
+    """The multi-right-hand-side path against the oracle directly, element by
+    element: one FP64 V-cycle on 64 columns equals the oracle's V-cycle of
+    each column to 1e-10 (the FP32 one to 1e-4, as the single-vector FP32
+    V-cycle); FP64 PCG on 64 columns at a fixed iteration count equals the
+    oracle's PCG iterate of each sampled column to 1e-10; the mixed batch
+    reaches the tolerance on every column's true residual."""
+    p, H, s = request.getfixturevalue(which)
+    X = np.stack([P.rhs_uniform(p.n, 1500 + j) for j in range(64)])
+    dX = dvec(X)
+    try:
+        for prec, tol in ((L.FP64, 1e-10), (L.MIXED, 1e-4)):
+            s.set_precision(prec)
+            Y = host(s.apply_vcycle_batch(dX))
+            for j in range(64):
+                e = rel(Y[j], O.vcycle(H, X[j]))
+                assert e <= tol, (prec, j, e)
+        s.set_precision(L.FP64)
+        K = 10
+        Xs, st = s.solve(dX, tol=0.0, maxit=K)
+        Xh = host(Xs)
+        for j in (0, 13, 27, 40, 63):
+            xo, _ = O.pcg(H, X[j], fixed_iters=K)
+            assert st[j]["iters"] == K and rel(Xh[j], xo) <= 1e-10, (j, rel(Xh[j], xo))
+        s.set_precision(L.MIXED)
+        Xm, st = s.solve(dX, tol=1e-8)
+        Xh = host(Xm)
+        for j in range(64):
+            r = np.linalg.norm(X[j] - H.levels[0].A @ Xh[j]) / np.linalg.norm(X[j])
+            assert st[j]["converged"] == 1 and r <= 1e-8, (j, r)
+    finally:
+        s.set_precision(L.FP64)
+
+
+@pytest.mark.parametrize("prec", [L.FP64, L.MIXED])
+def test_true_residual_stop(rot, prec):
+    """Tolerances below what the true residual can reach: the recurrence
+    residual passes while b - A x does not, so the solver replaces r by the
+    true residual and restarts (as the oracle does); it reports convergence
+    only with its FP64 true residual at the tolerance (recomputed here with
+    the oracle's A, up to the rounding of that evaluation, which at 1e-14 is
+    no longer negligible), and otherwise stops at maxit without convergence
+    -- single vector and 8 columns."""
+    p, H, s = rot
+    b = P.rhs_uniform(p.n, 0)
+    B = np.stack([P.rhs_uniform(p.n, 40 + j) for j in range(8)])
+    nb = np.linalg.norm(b)
+    A = H.levels[0].A
+
+    def resid(bv, xv):
+        """||b - A x|| / ||b|| and the rounding noise of evaluating it (two
+        FP64 evaluations of A x: the assembled A and G^T (G x))"""
+        ax = A @ xv
+        noise = np.linalg.norm(ax - p.G.T @ (p.G @ xv)) / np.linalg.norm(bv)
+        return np.linalg.norm(bv - ax) / np.linalg.norm(bv), noise
+
+    s.set_precision(prec)
+    try:
+        restarts = 0
+        for tol in (1e-14, 1e-15):
+            _, info = O.pcg(H, b, tol=tol, maxit=60)
+            x, st = s.solve(dvec(b), tol=tol, maxit=60)
+            r, noise = resid(b, host(x))
+            restarts += st[0]["restarts"]
+            if st[0]["converged"]:
+                assert st[0]["true_rel_res"] <= tol and r <= tol + 5 * noise, (tol, r, noise)
+            else:
+                assert st[0]["iters"] == 60
+            if tol == 1e-15:             # out of reach for the oracle as well
+                assert not info["converged"] and not st[0]["converged"]
+                assert st[0]["restarts"] >= 1
+            X, stb = s.solve(dvec(B), tol=tol, maxit=60)
+            Xh = host(X)
+            for j in range(8):
+                rj, noise = resid(B[j], Xh[j])
+                restarts += stb[j]["restarts"]
+                if stb[j]["converged"]:
+                    assert stb[j]["true_rel_res"] <= tol and rj <= tol + 5 * noise, \
+                        (tol, j, rj, noise)
+                else:
+                    assert stb[j]["iters"] == 60
+        assert restarts >= 1
+    finally:
+        s.set_precision(L.FP64)
 
 
 def setup_hash(e) -> str:
@@ -658,10 +779,18 @@ def setup_hash(e) -> str:
 
 
 def test_config2_full_size(gpu_device):
-    """Rotated anisotropy, N=512 (261,121 unknowns), at the benchmarked size:
-    integer setup equal to the oracle's on every level, FP64 and mixed solves
-    against the stored oracle run (tests/golden/config2_oracle.json)."""
+    """Rotated anisotropy, N=512 (261,121 unknowns), at the benchmarked size,
+    against the stored oracle run (tests/golden/config2_oracle*): integer
+    setup equal on every level; the FP64 iterate after the oracle's
+    iteration count equal to the oracle's on every entry to 1e-10; 64
+    right-hand sides (seeds 100-163) through the FP64 multi-right-hand-side
+    path (the matrix-core block products and dense level that the benchmark
+    times) equal to the oracle's per-column PCG iterates at 4,096 sampled
+    entries and in norm, to 1e-10; converged FP64, mixed and batched mixed
+    solves reach the tolerance on the true residual."""
     fx = json.load(open(os.path.join(HERE, "golden", "config2_oracle.json")))
+    x_or = np.load(os.path.join(HERE, "golden", "config2_oracle_x.npy"))
+    bx = np.load(os.path.join(HERE, "golden", "config2_oracle_batch.npz"))
     p = P.config2()
     print(f"[case] config2 full size n={p.n}", flush=True)
     s = L.Solver(p.G, 2, p.grid, device=0, cmin=(2,))
@@ -678,25 +807,34 @@ def test_config2_full_size(gpu_device):
         assert setup_hash(e) == lv["hash"]
     b = P.rhs_uniform(p.n, P.CONFIG_RHS_SEED[2])
     K = fx["iters"]
-    idx = np.asarray(fx["sample_idx"])
     x, st = s.solve(dvec(b), tol=0.0, maxit=K)
-    xs = host(x)[idx]
-    assert np.linalg.norm(xs - fx["x_sample"]) <= 1e-9 * np.linalg.norm(fx["x_sample"])
-    assert abs(np.linalg.norm(host(x)) - fx["x_norm"]) <= 1e-9 * fx["x_norm"]
+    assert rel(host(x), x_or) <= 1e-10, rel(host(x), x_or)
     x, st = s.solve(dvec(b), tol=1e-8)
     assert st[0]["converged"] == 1 and abs(st[0]["iters"] - K) <= 1
-    assert st[0]["true_rel_res"] <= 1.01e-8
+    assert st[0]["true_rel_res"] <= 1e-8
     s.set_precision(L.MIXED)
     x, st = s.solve(dvec(b), tol=1e-8)
-    assert st[0]["converged"] == 1 and st[0]["true_rel_res"] <= 1.05e-8
+    assert st[0]["converged"] == 1 and st[0]["true_rel_res"] <= 1e-8
     assert st[0]["iters"] <= math.ceil(1.10 * K)
-    # 64 right-hand sides (seeds 100-163) in one batch, mixed precision
-    B = np.stack([P.rhs_uniform(p.n, 100 + j) for j in range(64)])
-    X, st = s.solve(dvec(B), tol=1e-8)
+    # 64 right-hand sides (seeds 100-163) in one batch
+    seeds = bx["seeds"].tolist()
+    B = np.stack([P.rhs_uniform(p.n, q) for q in seeds])
+    dB = dvec(B)
+    s.set_precision(L.FP64)
+    X, st = s.solve(dB, tol=0.0, maxit=int(bx["iters"]))
+    Xh = host(X)
+    idx = bx["idx"]
+    for j in range(len(seeds)):
+        nj = bx["x_norm"][j]
+        assert abs(np.linalg.norm(Xh[j]) - nj) <= 1e-10 * nj, j
+        e = np.linalg.norm(Xh[j][idx] - bx["x_sample"][j]) / np.linalg.norm(bx["x_sample"][j])
+        assert e <= 1e-10, (j, e)
+    s.set_precision(L.MIXED)
+    X, st = s.solve(dB, tol=1e-8)
     for j in range(64):
-        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1.05e-8
+        assert st[j]["converged"] == 1 and st[j]["true_rel_res"] <= 1e-8
         assert st[j]["iters"] <= math.ceil(1.10 * K) + 1
     for j in (0, 31, 63):
         r = np.linalg.norm(B[j] - p.G.T @ (p.G @ host(X[j]))) / np.linalg.norm(B[j])
-        assert r <= 1.05e-8
+        assert r <= 1e-8
     s.close()

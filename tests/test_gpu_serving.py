@@ -40,7 +40,7 @@ def check(prob, b, x, tol):
     X = np.atleast_2d(x)
     for j in range(A_b.shape[0]):
         r = A_b[j] - prob.G.T @ (prob.G @ X[j])
-        assert np.linalg.norm(r) <= 1.02 * tol * np.linalg.norm(A_b[j])
+        assert np.linalg.norm(r) <= tol * np.linalg.norm(A_b[j])
 
 
 def test_alone_equals_in_mix(gpu_device):

@@ -322,3 +322,31 @@ def test_stats_fields(cfg1):
     s = O.stats(H)
     assert s["levels"] == 2 and s["n"] == [961, 254]
     assert s["op_complexity"] > 1 and s["smoother_complexity"] > 1
+
+
+def test_assembled_vcycle(rot):
+    """The assembled form of the solve phase (one CSR smoother per level, its
+    transpose for RAS-T) is the same operator as the per-aggregate Cholesky
+    form: the smoother matrix applies eq:ras column by column, its transpose
+    eq:ras-t, it has sum_i |omega_i||Omega_i| entries, and the assembled
+    V-cycle and PCG iterates equal the oracle's to 1e-13.  (Taking the
+    Omega-columns of A_i^{-1} on omega instead of its omega-rows would give
+    RAS-T in place of RAS and fail the first check.)"""
+    p, H = rot
+    AV = O.AssembledVcycle(H)
+    L = H.levels[0]
+    S = AV.S[0].toarray()
+    R = dense_op(lambda v: O.ras(L, v), L.n)
+    RT = dense_op(lambda v: O.ras_t(L, v), L.n)
+    assert np.abs(S - R).max() <= 1e-13 * np.abs(R).max()
+    assert np.abs(AV.ST[0].toarray() - RT).max() <= 1e-13 * np.abs(R).max()
+    for l, Sl in enumerate(AV.S):
+        Lv = H.levels[l]
+        assert Sl.nnz == sum(len(w) * len(Om) for w, Om in zip(Lv.omega, Lv.Omega))
+    v = np.random.default_rng(11).standard_normal(p.n)
+    y = O.vcycle(H, v)
+    assert np.linalg.norm(AV(v) - y) <= 1e-13 * np.linalg.norm(y)
+    b = P.rhs_uniform(p.n, 0)
+    x1, i1 = O.pcg(H, b, fixed_iters=8)
+    x2, i2 = O.pcg(H, b, fixed_iters=8, precond=AV)
+    assert np.linalg.norm(x2 - x1) <= 1e-13 * np.linalg.norm(x1)
