@@ -232,6 +232,32 @@ int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs,
 int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y,
                    void* stream);
 
+/* Staging that lsamg_apply_op_noalloc holds on each GPU (32 MiB). */
+#define LSAMG_NOALLOC_SCRATCH_BYTES (32ll << 20)
+
+/* Allocation-free variant of lsamg_apply_op, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same operators, arguments and result as
+ * lsamg_apply_op, but the call
+ *   - allocates nothing: no hipMalloc/hipFree, no library routine that
+ *     allocates; its staging (the permuted input and the output before the
+ *     permutation, n doubles each, and for LSAMG_OP_A the m rows of G x) lives
+ *     in one static array of LSAMG_NOALLOC_SCRATCH_BYTES per GPU, which the
+ *     process keeps until it ends; level work vectors are the handle's own,
+ *     made at set-up;
+ *   - only enqueues its kernels on `stream` (no synchronisation, no HIP
+ *     graph, no kernel timing); y is valid once the stream reaches that
+ *     point.
+ * Every call on a GPU shares that GPU's staging array and the handle's
+ * level vectors: calls that overlap on one GPU (another stream, another
+ * thread, another handle on the same device) race and must be ordered by the
+ * caller.  Errors: EINVAL (null pointer, bad op, single-level hierarchy for
+ * RAS/RAS-T, or an operator whose staging exceeds the array: 8 (2n + m)
+ * bytes for LSAMG_OP_A, 16 n bytes otherwise; checked before any device
+ * work), ENODEV (no device copy), EHIP. */
+int lsamg_apply_op_noalloc(lsamg_handle* h, int32_t op, const double* x, double* y,
+                           void* stream);
+
 /* Select the V-cycle precision (LSAMG_FP64 or LSAMG_MIXED) for later calls. */
 int lsamg_set_precision(lsamg_handle* h, int32_t precision);
 

@@ -1057,5 +1057,10 @@ __global__ void __launch_bounds__(kBlock) k_fill(int64_t n, double v, double* __
   if (i < n) b[i] = v;
 }
 
+__global__ void __launch_bounds__(kBlock) k_fill_f32(int64_t n, float v, float* __restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) b[i] = v;
+}
+
 }  // namespace dev
 }  // namespace lsamg

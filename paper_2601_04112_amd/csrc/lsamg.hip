@@ -958,8 +958,36 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
 
 void build_tail(lsamg_handle* h, size_t lc);
 
+// Staging of the allocation-free entry point (lsamg_apply_op_noalloc): one
+// array per GPU for the whole process.  Host code never passes `scratch`
+// itself to a kernel (on the host it is only a stand-in symbol); it uses the
+// device address that hipGetSymbolAddress returns, resolved once per device
+// with that device current and kept in g_scratch_dev.
+constexpr int64_t kScratchDoubles = LSAMG_NOALLOC_SCRATCH_BYTES / sizeof(double);
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current).
+double* scratch_on(int device) {
+  if (device < 0 || device >= kMaxDevices)
+    throw DevError{LSAMG_EINVAL, "device index beyond the allocation-free staging table"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      throw DevError{LSAMG_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                     hipGetErrorString(e)};
+    g_scratch_dev[device] = (double*)ptr;
+  }
+  return g_scratch_dev[device];
+}
+
 void upload(lsamg_handle* h) {
   if (!h->dry) HIP_OK(hipSetDevice(h->device));
+  if (!h->dry) (void)scratch_on(h->device);   // resolve the staging address at set-up
   h->L.resize(h->H.levels.size());
   for (size_t l = 0; l < h->H.levels.size(); ++l) upload_level(h, h->H.levels[l], h->L[l], l == 0);
   const Level& L0 = h->H.levels[0];
@@ -3204,6 +3232,78 @@ int lsamg_apply_op(lsamg_handle* h, int32_t op, const double* x, double* y, void
     KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_out, n, h->perm, h->z, y);
     LAUNCH_OK();
     HIP_OK(hipStreamSynchronize(s));
+    return LSAMG_OK;
+  } catch (const DevError& e) {
+    return fail_with(e.code, e.msg);
+  }
+}
+
+int lsamg_apply_op_noalloc(lsamg_handle* h, int32_t op, const double* x, double* y,
+                           void* stream) {
+  if (!h || !x || !y) return fail_with(LSAMG_EINVAL, "null argument");
+  if (op < LSAMG_OP_A || op > LSAMG_OP_VCYCLE) return fail_with(LSAMG_EINVAL, "bad op");
+  if (h->H.levels.empty()) return fail_with(LSAMG_EINVAL, "empty hierarchy");
+  // staging in the per-GPU array: the permuted input and the output before
+  // the permutation (n each), plus the rows of G x for op A
+  const Level& H0 = h->H.levels[0];
+  const int64_t n = H0.n;
+  const int64_t rows = H0.G.total_rows();
+  const int64_t need = 2 * n + (op == LSAMG_OP_A ? rows : 0);
+  if (need > kScratchDoubles)
+    return fail_with(LSAMG_EINVAL,
+                     "lsamg_apply_op_noalloc: this operator needs " + std::to_string(need * 8) +
+                         " bytes of staging, more than the " +
+                         std::to_string((long long)LSAMG_NOALLOC_SCRATCH_BYTES) +
+                         " bytes the allocation-free entry point holds per GPU");
+  if (h->device < 0 || h->L.empty()) return fail_with(LSAMG_ENODEV, "handle has no device copy");
+  DLevel& L0 = h->L[0];
+  if ((op == LSAMG_OP_RAS || op == LSAMG_OP_RAST) && L0.coarsest)
+    return fail_with(LSAMG_EINVAL, "single-level hierarchy has no smoother");
+  if (L0.n != n || (op == LSAMG_OP_A && L0.nrows > rows))
+    return fail_with(LSAMG_EINVAL, "device hierarchy does not match the host one");
+  try {
+    DeviceGuard g(h->device);
+    hipStream_t s = (hipStream_t)stream;
+    double* base = scratch_on(h->device);
+    double* xi = base;                  // input in the internal numbering
+    double* zo = base + n;              // output before the permutation
+    double* gy = base + 2 * n;          // G x (op A)
+    const unsigned gb = nblocks(n);
+    KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_in, n, h->perm, x, xi);
+    LAUNCH_OK();
+    const bool mixed = h->precision == LSAMG_MIXED;
+    if (op == LSAMG_OP_A) {
+      spmv_csr<double>(L0.nrows, L0.lanes_g, L0.g_ptr, L0.g_col, L0.d.g_val, xi, gy, s, L0.nnz,
+                       L0.n);
+      spmv_csr<double>(L0.n, L0.lanes_gt, L0.gt_ptr, L0.gt_col, L0.d.gt_val, gy, zo, s, L0.nnz,
+                       L0.nrows);
+    } else if (op == LSAMG_OP_VCYCLE) {
+      precondition(h, xi, zo, s);       // kernels launched one by one, no graph
+    } else if (mixed) {
+      KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<double, float>, n, xi, L0.f.b);
+      LAUNCH_OK();
+      if (op == LSAMG_OP_RAS) {
+        ras<float>(L0, L0.f.b, L0.f.x, s);
+      } else {
+        KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_fill_f32, n, 0.0f, L0.f.x);
+        LAUNCH_OK();
+        ras_t_stage<float>(L0, L0.f.b, s);
+        gather_add<float>(L0, L0.f.x, s);
+      }
+      KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_convert<float, double>, n, L0.f.x, zo);
+      LAUNCH_OK();
+    } else {
+      if (op == LSAMG_OP_RAS) {
+        ras<double>(L0, xi, zo, s);
+      } else {
+        KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_fill, n, 0.0, zo);
+        LAUNCH_OK();
+        ras_t_stage<double>(L0, xi, s);
+        gather_add<double>(L0, zo, s);
+      }
+    }
+    KLAUNCH0(gb, dev::kBlock, 0, s, dev::k_perm_out, n, h->perm, zo, y);
+    LAUNCH_OK();
     return LSAMG_OK;
   } catch (const DevError& e) {
     return fail_with(e.code, e.msg);

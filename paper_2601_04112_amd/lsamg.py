@@ -130,6 +130,8 @@ _SIGS = {
                               C.POINTER(Stats)]),
     "lsamg_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
+    "lsamg_apply_op_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]),
     "lsamg_set_precision": (C.c_int, [C.c_void_p, C.c_int32]),
     "lsamg_set_option": (C.c_int, [C.c_void_p, C.c_int32, C.c_int64]),
     "lsamg_apply_vcycle_batch": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p,
@@ -156,13 +158,20 @@ _lib = None
 
 
 def load() -> C.CDLL:
-    """Load the built library (raises if it is missing: there is no fallback)."""
+    """Load the built library (raises if it is missing: there is no fallback).
+
+    torch is imported first: its ROCm build carries its own HIP and HSA
+    runtimes, which then also serve the library (whose libamdhip64.so.7 the
+    loader finds already present).  Loaded the other way round, the process
+    would hold two HIP/HSA runtimes, the library's could not open the GPU, and
+    device pointers from torch would be foreign to it."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run "
                           "python -m paper_2601_04112_amd.build")
+    import torch  # noqa: F401  (HIP runtime first, see above)
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)
@@ -286,6 +295,17 @@ class Solver:
         _check(load().lsamg_apply_op(self._h, op, C.c_void_p(x.data_ptr()),
                                      C.c_void_p(y.data_ptr()),
                                      self._stream(stream)))
+        return y
+
+    def apply_noalloc(self, op: int, x, out, stream=None):
+        """The allocation-free form of ``apply``: ``out`` must be given; the
+        call only enqueues its kernels on the stream (no synchronisation) and
+        allocates nothing (its staging is the library's per-GPU array)."""
+        x = self._dev_vec(x)
+        y = self._dev_vec(out)
+        _check(load().lsamg_apply_op_noalloc(self._h, op, C.c_void_p(x.data_ptr()),
+                                             C.c_void_p(y.data_ptr()),
+                                             self._stream(stream)))
         return y
 
     def apply_vcycle_batch(self, X, out=None, stream=None):
