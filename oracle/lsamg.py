@@ -347,7 +347,15 @@ def schur_ls(B: np.ndarray, nw: int, rank_rtol: float) -> np.ndarray:
     Q and the rank come from the SVD of B_Gamma (singular values at or below
     ``rank_rtol`` times the largest count as zero), so the conditioning of
     B_Gamma enters once, not squared as in ``A~_GammaGamma``.
+
+    The energy ``||B u||`` is unchanged when B is replaced by R from its QR
+    factorisation ``B = Q_B R`` (Q_B has orthonormal columns), so the same
+    formula is applied to R: at most |Omega_i| rows instead of every row of G
+    that touches the aggregate (on coarse levels, where G_l keeps all the
+    rows of G, tens of thousands).
     """
+    if B.shape[0] > B.shape[1]:
+        B = sla.qr(B, mode="r", check_finite=False)[0]
     Bw = B[:, :nw]
     if B.shape[1] == nw:
         return Bw.T @ Bw

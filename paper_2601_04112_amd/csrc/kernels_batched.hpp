@@ -1710,6 +1710,51 @@ __global__ void __launch_bounds__(kBlock) k_bcg_dir_mask(int64_t n, const int* _
     P[e] = Z[e];
 }
 
+// Load ncols user columns (column-major, leading dimension ld) into
+// columns j0 .. j0+ncols-1 of the interleaved blocks: B = R = b (internal
+// numbering), X = P = 0, R32 = (float) b (if given); other columns untouched
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bload(int64_t n, int j0, int ncols, int64_t ld,
+                                                  const int64_t* __restrict__ perm,
+                                                  const double* __restrict__ b,
+                                                  double* __restrict__ B, double* __restrict__ R,
+                                                  double* __restrict__ X, double* __restrict__ P,
+                                                  float* __restrict__ R32) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t i = e / ncols;
+  const int jj = (int)(e % ncols);
+  const double v = b[(int64_t)jj * ld + perm[i]];
+  const int64_t o = i * NB + j0 + jj;
+  B[o] = v;
+  R[o] = v;
+  X[o] = 0.0;
+  P[o] = 0.0;
+  if (R32) R32[o] = (float)v;
+}
+
+// Store columns j0 .. j0+ncols-1 of the interleaved X into user columns
+// (column-major, leading dimension ld, user numbering)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bstore(int64_t n, int j0, int ncols, int64_t ld,
+                                                   const int64_t* __restrict__ perm,
+                                                   const double* __restrict__ X,
+                                                   double* __restrict__ x) {
+  const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= n * ncols) return;
+  const int64_t i = e / ncols;
+  const int jj = (int)(e % ncols);
+  x[(int64_t)jj * ld + perm[i]] = X[i * NB + j0 + jj];
+}
+
+// rz[j] = 0 on the masked columns (their next direction is P = Z)
+template <int NB>
+__global__ void __launch_bounds__(kBlock) k_bzero_masked(const int* __restrict__ mask,
+                                                         double* __restrict__ rz) {
+  const int j = threadIdx.x;
+  if (j < NB && mask[j]) rz[j] = 0.0;
+}
+
 // Bi[i][j] = b[j*ld + perm[i]]  (user column-major -> internal interleaved)
 template <int NB>
 __global__ void __launch_bounds__(kBlock) k_bperm_in(int64_t n, int nrhs, int64_t ld,

@@ -356,8 +356,8 @@ struct lsamg_handle {
          *Btmp = nullptr;
   // per-column scalars summed from those partials (k_bsum)
   double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr;
-  int* Bactive = nullptr;            // 64 active flags, then 64 restart flags
-  int* Bactive_host = nullptr;       // pinned, the same two arrays
+  int* Bactive = nullptr;            // 64 active, 64 restart, 64 new-direction flags
+  int* Bactive_host = nullptr;       // pinned, the same three arrays
   double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
   // export buffers
   std::vector<int32_t> ex_agg, ex_k, ex_M;
@@ -1791,9 +1791,9 @@ void ensure_batched(lsamg_handle* h, int NB) {
   h->Brz_s[0] = h->alloc<double>(W);
   h->Brz_s[1] = h->alloc<double>(W);
   h->Btmp_s = h->alloc<double>(W);
-  h->Bactive = h->alloc<int>(2 * 64);   // active and restart flags of up to 64 columns
+  h->Bactive = h->alloc<int>(3 * 64);   // active, restart and new-direction flags, 64 columns
   if (!h->Bactive_host)
-    HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 2 * 64 * sizeof(int), hipHostMallocDefault));
+    HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 3 * 64 * sizeof(int), hipHostMallocDefault));
   if (!h->Bparts_host)
     HIP_OK(hipHostMalloc((void**)&h->Bparts_host, 3 * 64 * sizeof(double),
                          hipHostMallocDefault));
@@ -2868,171 +2868,283 @@ void bhost_sums(const lsamg_handle* h, int NB, int slot, double* out) {
   for (int j = 0; j < NB; ++j) out[j] = h->Bparts_host[(size_t)slot * 64 + j];
 }
 
-// PCG on nr <= NB right-hand sides at once: one FP64 CG per column (own
-// scalars and stop test), sharing every matrix read of the V-cycle and of A.
+// Host-side state of one column of the multi-right-hand-side PCG.
+struct BCol {
+  int active = 0;        // iterating
+  int its = 0, maxit = 0, restarts = 0, conv = 0, done = 0, bad = 0;
+  double tol = 0, nb = 0, rn = 0, tr = 0;   // tr: ||b - A x|| when done
+};
+
+// Multi-right-hand-side PCG on up to NB interleaved columns: one FP64 CG per
+// column (own scalars, stop test and iteration count) sharing every matrix
+// read of the V-cycle and of A.  Columns can be loaded whenever the engine
+// is between iterations and retire as soon as they finish, so a solve can
+// take new right-hand sides at any iteration boundary (the request server
+// does; pcg_batched loads all columns at once).
+//
+// Cycle: load columns -> norms() -> prepare() [Z = B R, next directions]
+// -> step() [q = A p, x, r update; stop tests on the recurrence residual,
+// then on the true residual] -> retire / load -> norms() -> prepare() ...
+// A column that enters (fresh) or whose recurrence residual passed while
+// its true residual did not (restart: r = b - A x) takes p = z as its next
+// direction.
+template <int NB>
+struct BatchCG {
+  lsamg_handle* h;
+  hipStream_t s;
+  bool mixed;
+  int cur = 0;               // Brz_s[cur]: rho of the current directions
+  bool pre_queued = false;   // the next preconditioner step is already queued
+  double fac = 0.5;          // slowest average reduction per iteration so far
+  BCol c[NB];
+  // flags of the device copy (h->Bactive): active, restart, new direction;
+  // copied to the pinned staging only inside prepare(), right before the
+  // upload (the step that follows synchronises past that copy)
+  int flg[192] = {};
+  int* act = flg;
+  int* rst = flg + 64;
+  int* ndir = flg + 128;
+
+  BatchCG(lsamg_handle* h_, hipStream_t s_) : h(h_), s(s_) {
+    ensure_batched(h, NB);
+    if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
+    if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) fp64_tune(h, s);
+    mixed = h->precision == LSAMG_MIXED;
+    const int64_t n0 = h->L[0].n * NB;
+    // every column starts from zeros, so unused columns stay finite
+    for (double* v : {h->BX, h->BR, h->BZ, h->BP, h->BQ, h->BBi}) {
+      KLAUNCH0(nblocks(n0), dev::kBlock, 0, s, dev::k_fill, n0, 0.0, v);
+      LAUNCH_OK();
+    }
+    for (double* v : {h->Brz_s[0], h->Brz_s[1]}) {
+      KLAUNCH0(1, dev::kBlock, 0, s, dev::k_fill, (int64_t)NB, 0.0, v);
+      LAUNCH_OK();
+    }
+    if (mixed) {
+      KLAUNCH0(nblocks(n0), dev::kBlock, 0, s, dev::k_fill_f32, n0, 0.0f, h->BL[0].fb);
+      LAUNCH_OK();
+    }
+  }
+
+  int64_t n() const { return h->L[0].n; }
+  int nactive() const {
+    int k = 0;
+    for (int j = 0; j < NB; ++j) k += c[j].active;
+    return k;
+  }
+
+  // columns j0 .. j0+ncols-1 from the user's device columns b (leading
+  // dimension ld); they become fresh (norms() then decides what runs)
+  void load(int j0, int ncols, const double* b, int64_t ld, double tol, int maxit) {
+    const int64_t nn = n() * ncols;
+    KLAUNCH0(nblocks(nn), dev::kBlock, 0, s, dev::k_bload<NB>, n(), j0, ncols, ld,
+             (const int64_t*)h->perm, b, h->BBi, h->BR, h->BX, h->BP,
+             mixed ? h->BL[0].fb : (float*)nullptr);
+    LAUNCH_OK();
+    for (int j = j0; j < j0 + ncols; ++j) {
+      c[j] = BCol{};
+      c[j].tol = tol;
+      c[j].maxit = maxit;
+      c[j].nb = -1.0;            // norm pending
+      ndir[j] = 1;
+    }
+  }
+
+  // ||b|| of the freshly loaded columns; a zero column is done at once
+  // (x = 0), a non-finite one is marked bad, maxit 0 leaves x = 0 unconverged
+  void norms() {
+    bool any = false;
+    for (int j = 0; j < NB; ++j) any = any || c[j].nb < 0;
+    if (!any) return;
+    KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n(), (const double*)h->BBi,
+             (const double*)h->BBi, h->Btmp);
+    LAUNCH_OK();
+    bsum<NB>(h->Btmp, h->Btmp_s, s);
+    bparts_to_host(h, h->Btmp_s, NB, 0, s);
+    HIP_OK(hipStreamSynchronize(s));
+    double nb2[NB];
+    bhost_sums(h, NB, 0, nb2);
+    for (int j = 0; j < NB; ++j) {
+      if (!(c[j].nb < 0)) continue;
+      BCol& q = c[j];
+      if (!std::isfinite(nb2[j])) {
+        q.bad = q.done = 1;
+        q.nb = 0;
+        continue;
+      }
+      q.nb = q.rn = q.tr = std::sqrt(nb2[j]);
+      if (q.nb == 0.0) {
+        q.conv = q.done = 1;
+      } else if (q.maxit <= 0) {
+        q.done = 1;
+      } else {
+        q.active = 1;
+      }
+    }
+  }
+
+  // Z = B R and the next directions (P = Z on fresh and restarted columns)
+  void prepare() {
+    int nnew = 0;
+    for (int j = 0; j < NB; ++j) {
+      act[j] = c[j].active;
+      if (!c[j].active) ndir[j] = rst[j] = 0;
+      nnew += ndir[j];
+    }
+    const int nact = nactive();
+    if (nact == 0) {
+      pre_queued = false;
+      return;
+    }
+    std::memcpy(h->Bactive_host, flg, sizeof(flg));
+    HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, sizeof(flg), hipMemcpyHostToDevice, s));
+    int nrst = 0;
+    for (int j = 0; j < NB; ++j) nrst += rst[j];
+    if (nrst > 0) {
+      // r = b - A x on the restarted columns (A x is in BQ from the true-residual
+      // test of the last step); rho_old = 0 there
+      KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_restart<NB>, n(), (const int*)(h->Bactive + 64),
+               (const double*)h->BBi, (const double*)h->BQ, h->BR,
+               mixed ? h->BL[0].fb : (float*)nullptr, h->Brz_s[cur]);
+      LAUNCH_OK();
+    }
+    if (pre_queued) {
+      // the other columns' next direction is formed; redo Z for the new ones
+      if (nnew > 0) bcg_precondition<NB>(h, s, false, 1 - cur, h->Bactive + 128);
+    } else {
+      if (nnew > 0) {
+        KLAUNCH0(1, dev::kBlock, 0, s, dev::k_bzero_masked<NB>, (const int*)(h->Bactive + 128),
+                 h->Brz_s[cur]);
+        LAUNCH_OK();
+      }
+      bcg_precondition<NB>(h, s, false, 1 - cur);
+    }
+    for (int j = 0; j < NB; ++j) ndir[j] = rst[j] = 0;
+    pre_queued = false;
+    cur = 1 - cur;
+  }
+
+  // one iteration of every active column; columns that finish in it get
+  // done = 1 (converged or at maxit, with their true residual) and leave the
+  // active set.  expect_more: the caller will load columns after this step,
+  // so the next preconditioner step waits for that instead of being queued
+  // early.  Returns the number of columns that finished.
+  int step(bool expect_more) {
+    if (nactive() == 0) return 0;
+    const int64_t nn = n();
+    bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, h->Bpq_s, s);
+    {
+      PROF(kname("k_bcg_update", std::to_string(NB)), (mixed ? 60 : 56) * nn * NB, s);
+      KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_update<NB>, nn, (const double*)h->Brz_s[cur],
+              (const double*)h->Bpq_s, (const int*)h->Bactive, (const double*)h->BP,
+              (const double*)h->BQ, h->BX, h->BR, mixed ? h->BL[0].fb : (float*)nullptr, h->Brr);
+      LAUNCH_OK();
+    }
+    bsum<NB>(h->Brr, h->Brr_s, s);
+    bparts_to_host(h, h->Brr_s, NB, 1, s);
+    HIP_OK(hipEventRecord(h->ev_rr[0], s));
+    // the most advanced column predicts whether this update converges one
+    bool near = expect_more;
+    for (int j = 0; j < NB; ++j) {
+      if (!c[j].active) continue;
+      ++c[j].its;
+      near = near || c[j].rn / c[j].nb * fac <= 2.0 * c[j].tol || c[j].its >= c[j].maxit;
+    }
+    if (!near) {
+      bcg_precondition<NB>(h, s, false, 1 - cur);
+      pre_queued = true;
+    }
+    HIP_OK(hipEventSynchronize(h->ev_rr[0]));
+    double rr[NB];
+    bhost_sums(h, NB, 1, rr);
+    int ntest = 0;
+    for (int j = 0; j < NB; ++j) {
+      if (!c[j].active) continue;
+      c[j].rn = std::sqrt(rr[j]);
+      if (!std::isfinite(c[j].rn)) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
+      ntest += c[j].rn <= c[j].tol * c[j].nb || c[j].its >= c[j].maxit;
+    }
+    int nfin = 0;
+    if (ntest > 0) {
+      // true residuals b - A x of the whole block (one batched A-apply)
+      bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
+      KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, nn, (const double*)h->BBi,
+               (const double*)h->BQ, h->Btmp);
+      LAUNCH_OK();
+      bsum<NB>(h->Btmp, h->Btmp_s, s);
+      bparts_to_host(h, h->Btmp_s, NB, 0, s);
+      HIP_OK(hipStreamSynchronize(s));
+      double t2[NB];
+      bhost_sums(h, NB, 0, t2);
+      for (int j = 0; j < NB; ++j) {
+        BCol& q = c[j];
+        if (!q.active) continue;
+        const bool pass = q.rn <= q.tol * q.nb;
+        if (!pass && q.its < q.maxit) continue;
+        q.tr = std::sqrt(t2[j]);
+        if (pass && q.tr <= q.tol * q.nb) {
+          q.conv = 1;
+        } else if (q.its < q.maxit) {      // replace r by b - A x, restart
+          rst[j] = ndir[j] = 1;
+          q.rn = q.tr;
+          ++q.restarts;
+          continue;
+        }
+        q.active = 0;
+        q.done = 1;
+        ++nfin;
+      }
+    }
+    double worst = 0;
+    for (int j = 0; j < NB; ++j)
+      if (c[j].active) worst = std::max(worst, std::pow(c[j].rn / c[j].nb, 1.0 / c[j].its));
+    if (worst > 0) fac = worst;
+    return nfin;
+  }
+
+  // columns j0 .. j0+ncols-1 of X to the user's device columns x
+  void store(int j0, int ncols, double* x, int64_t ld) {
+    const int64_t nn = n() * ncols;
+    KLAUNCH0(nblocks(nn), dev::kBlock, 0, s, dev::k_bstore<NB>, n(), j0, ncols, ld,
+             (const int64_t*)h->perm, (const double*)h->BX, x);
+    LAUNCH_OK();
+  }
+
+  void stats(int j, lsamg_stats* st, double secs) const {
+    const BCol& q = c[j];
+    st->iters = q.its;
+    st->converged = q.conv;
+    st->rel_res = q.nb > 0 ? q.rn / q.nb : 0.0;
+    st->true_rel_res = q.nb > 0 ? q.tr / q.nb : 0.0;
+    st->rho = (q.its > 0 && q.nb > 0) ? std::pow(q.rn / q.nb, 1.0 / q.its) : 0.0;
+    st->restarts = q.restarts;
+    st->reserved = 0;
+    st->seconds = secs;
+  }
+};
+
+// PCG on nr <= NB right-hand sides at once (all loaded before the first
+// iteration).
 template <int NB>
 int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
                 int maxit, hipStream_t s, lsamg_stats* st) {
   auto t0 = std::chrono::steady_clock::now();
-  ensure_batched(h, NB);
-  if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
-  if (h->precision == LSAMG_FP64 && h->use_mfma && NB == 64) fp64_tune(h, s);
-  DLevel& L0 = h->L[0];
-  auto& B0 = h->BL[0];
-  const int64_t n = L0.n;
-  const unsigned ge = nblocks(n * NB);
-  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_in<NB>, n, nr, ld, (const int64_t*)h->perm, b,
-           h->BBi);
-  LAUNCH_OK();
-  HIP_OK(hipMemsetAsync(h->BX, 0, (size_t)n * NB * sizeof(double), s));
-  HIP_OK(hipMemcpyAsync(h->BR, h->BBi, (size_t)n * NB * sizeof(double), hipMemcpyDeviceToDevice,
-                        s));
-  KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BBi,
-           (const double*)h->BBi, h->Btmp);
-  LAUNCH_OK();
-  bsum<NB>(h->Btmp, h->Btmp_s, s);
-  bparts_to_host(h, h->Btmp_s, NB, 0, s);
-  HIP_OK(hipStreamSynchronize(s));
-  double nb2[kBMax], rr[kBMax], nbv[kBMax], rn[kBMax];
-  int its_col[kBMax], conv_col[kBMax], restarts_col[kBMax] = {};
-  bhost_sums(h, NB, 0, nb2);
-  int nactive = 0;
-  for (int j = 0; j < NB; ++j) {
-    if (j < nr && !std::isfinite(nb2[j]))
-      throw DevError{LSAMG_EBADINPUT, "non-finite entry in a right-hand side"};
-    nbv[j] = std::sqrt(j < nr ? nb2[j] : 0.0);
-    rn[j] = nbv[j];
-    its_col[j] = 0;
-    conv_col[j] = (j < nr && nbv[j] == 0.0) ? 1 : 0;
-    h->Bactive_host[j] = (j < nr && nbv[j] > 0.0 && maxit > 0) ? 1 : 0;
-    nactive += h->Bactive_host[j];
+  BatchCG<NB> E(h, s);
+  E.load(0, nr, b, ld, tol, maxit);
+  E.norms();
+  for (int j = 0; j < nr; ++j)
+    if (E.c[j].bad) throw DevError{LSAMG_EBADINPUT, "non-finite entry in a right-hand side"};
+  while (E.nactive() > 0) {
+    E.prepare();
+    E.step(false);
   }
-  for (int j = 0; j < kBMax; ++j) h->Bactive_host[kBMax + j] = 0;
-  HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, 2 * kBMax * sizeof(int), hipMemcpyHostToDevice,
-                        s));
-  const bool mixed = h->precision == LSAMG_MIXED;
-  int its = 0;
-  double fac = 0.5;
-  if (nactive > 0) {
-    if (mixed) {
-      KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_convert<double, float>, n * NB,
-               (const double*)h->BR, B0.fb);
-      LAUNCH_OK();
-    }
-    int cur = 0;
-    bcg_precondition<NB>(h, s, true, cur);
-    while (its < maxit && nactive > 0) {
-      bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, h->Bpq_s, s);
-      {
-        PROF(kname("k_bcg_update", std::to_string(NB)), (mixed ? 60 : 56) * n * NB, s);
-        KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_update<NB>, n, (const double*)h->Brz_s[cur],
-                (const double*)h->Bpq_s, (const int*)h->Bactive, (const double*)h->BP,
-                (const double*)h->BQ, h->BX, h->BR, mixed ? B0.fb : (float*)nullptr, h->Brr);
-        LAUNCH_OK();
-      }
-      bsum<NB>(h->Brr, h->Brr_s, s);
-      const int slot = 1 + (its & 1);
-      bparts_to_host(h, h->Brr_s, NB, slot, s);
-      HIP_OK(hipEventRecord(h->ev_rr[its & 1], s));
-      ++its;
-      // the most advanced active column predicts whether this update converges
-      double best = 1e300;
-      for (int j = 0; j < NB; ++j)
-        if (h->Bactive_host[j]) best = std::min(best, rn[j] / nbv[j]);
-      const bool near = best * fac <= 2.0 * tol || its >= maxit;
-      if (!near) bcg_precondition<NB>(h, s, false, 1 - cur);
-      HIP_OK(hipEventSynchronize(h->ev_rr[(its - 1) & 1]));
-      bhost_sums(h, NB, slot, rr);
-      nactive = 0;
-      double worst = 0;
-      int ncand = 0;
-      for (int j = 0; j < NB; ++j) {
-        if (!h->Bactive_host[j]) continue;
-        rn[j] = std::sqrt(rr[j]);
-        if (!std::isfinite(rn[j])) throw DevError{LSAMG_ENOTSPD, "CG breakdown (non-finite residual)"};
-        its_col[j] = its;
-        ncand += rn[j] <= tol * nbv[j];
-      }
-      // columns whose recurrence residual passes: their true residual
-      // b - A x decides (one batched A-apply for the whole block)
-      int* rmask = h->Bactive_host + kBMax;
-      for (int j = 0; j < kBMax; ++j) rmask[j] = 0;
-      int nrestart = 0;
-      if (ncand > 0) {
-        bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
-        KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, n, (const double*)h->BBi,
-                 (const double*)h->BQ, h->Btmp);
-        LAUNCH_OK();
-        bsum<NB>(h->Btmp, h->Btmp_s, s);
-        bparts_to_host(h, h->Btmp_s, NB, 0, s);
-        HIP_OK(hipStreamSynchronize(s));
-        double t2[kBMax];
-        bhost_sums(h, NB, 0, t2);
-        for (int j = 0; j < NB; ++j) {
-          if (!h->Bactive_host[j] || !(rn[j] <= tol * nbv[j])) continue;
-          const double tn = std::sqrt(t2[j]);
-          if (tn <= tol * nbv[j]) {
-            conv_col[j] = 1;
-            h->Bactive_host[j] = 0;
-          } else {
-            rmask[j] = 1;
-            rn[j] = tn;
-            ++restarts_col[j];
-            ++nrestart;
-          }
-        }
-      }
-      for (int j = 0; j < NB; ++j) {
-        if (!h->Bactive_host[j]) continue;
-        ++nactive;
-        worst = std::max(worst, std::pow(rn[j] / nbv[j], 1.0 / its));
-      }
-      if (worst > 0) fac = worst;
-      if (nactive == 0 || its >= maxit) break;
-      HIP_OK(hipMemcpyAsync(h->Bactive, h->Bactive_host, 2 * kBMax * sizeof(int),
-                            hipMemcpyHostToDevice, s));
-      if (nrestart > 0) {
-        // R = B - A X on the restarted columns (A X is in BQ), rho_old = 0
-        KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_restart<NB>, n,
-                 (const int*)(h->Bactive + kBMax), (const double*)h->BBi, (const double*)h->BQ,
-                 h->BR, mixed ? B0.fb : (float*)nullptr, h->Brz_s[cur]);
-        LAUNCH_OK();
-        if (!near)                      // the other columns' next direction is formed
-          bcg_precondition<NB>(h, s, false, 1 - cur, h->Bactive + kBMax);
-      }
-      if (near) bcg_precondition<NB>(h, s, false, 1 - cur);
-      cur = 1 - cur;
-    }
-  }
-  // true residuals in FP64
-  bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
-  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_sub, n * NB, (const double*)h->BBi, (const double*)h->BQ,
-           h->BZ);
-  LAUNCH_OK();
-  KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BZ,
-           (const double*)h->BZ, h->Btmp);
-  LAUNCH_OK();
-  bsum<NB>(h->Btmp, h->Btmp_s, s);
-  bparts_to_host(h, h->Btmp_s, NB, 0, s);
-  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
-           (const double*)h->BX, x);
-  LAUNCH_OK();
+  E.store(0, nr, x, ld);
   HIP_OK(hipStreamSynchronize(s));
-  double tr2[kBMax];
-  bhost_sums(h, NB, 0, tr2);
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   bool all = true;
   for (int j = 0; j < nr; ++j) {
-    all = all && conv_col[j];
-    if (st) {
-      st[j].iters = its_col[j];
-      st[j].converged = conv_col[j];
-      st[j].rel_res = nbv[j] > 0 ? rn[j] / nbv[j] : 0.0;
-      st[j].true_rel_res = nbv[j] > 0 ? std::sqrt(tr2[j]) / nbv[j] : 0.0;
-      st[j].rho = (its_col[j] > 0 && nbv[j] > 0) ? std::pow(rn[j] / nbv[j], 1.0 / its_col[j]) : 0.0;
-      st[j].restarts = restarts_col[j];
-      st[j].seconds = secs;
-    }
+    all = all && E.c[j].conv;
+    if (st) E.stats(j, st + j, secs);
   }
   return all ? LSAMG_OK : LSAMG_ENOCONV;
 }
