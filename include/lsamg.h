@@ -196,12 +196,19 @@ typedef struct lsamg_done {
   double t_setup;          /* host setup + upload (0 on a hit)                   */
   double t_solve;          /* copy-in, solve, copy-out                           */
   double t_total;          /* submit to completion                               */
+  int32_t joined_at;       /* PCG iteration of the running solve at which the
+                              request's columns entered it (0: it started it)  */
+  int32_t reserved;
 } lsamg_done;
 
 typedef struct lsamg_server_stats {
   int64_t submitted, completed, hits, misses, evictions;
   size_t resident_bytes, peak_bytes, budget;
   int32_t queued, active;
+  int64_t joins;           /* requests that entered a solve already running      */
+  int64_t reserve_misses;  /* solves that added more device memory than their
+                              admission reserved (0 unless the bound is wrong)  */
+  int64_t iterations;      /* PCG iterations run so far, all solves together     */
 } lsamg_server_stats;
 
 typedef struct lsamg_server lsamg_server;
@@ -350,15 +357,22 @@ void lsamg_destroy(lsamg_handle* h);
 const char* lsamg_last_error(void);
 
 /* Continuous-batching request server on one GPU.  max_slots worker threads,
- * each with its own HIP stream, take queued requests: a request whose
- * hierarchy is resident and idle is solved at once, together with every other
- * queued request for the same operator and tolerance (one multi-right-hand-
- * side solve, at most 64 columns); a request for a new operator builds its
- * hierarchy on the host while the other slots keep the GPU busy, and is
- * admitted when its exact device footprint fits hbm_budget (idle
- * hierarchies are evicted least-recently-used first; a hierarchy larger than
- * the whole budget fails with ENOMEM).  Solves of different operators run
- * concurrently on their slots' streams.  Errors: EINVAL, ENODEV, ENOMEM. */
+ * each with its own HIP stream, run solves: a worker takes a queued request
+ * whose hierarchy is resident and idle (or new) and starts a multi-right-
+ * hand-side PCG on that operator, 8 to 64 columns wide, with the queued
+ * requests for it that fit.  At every PCG iteration boundary requests for the
+ * operator that arrived meanwhile enter free columns and start their own CG
+ * there (their own tolerance and iteration limit), and a request is reported
+ * as soon as its last column converges, freeing its columns; the solve ends
+ * when no column is active and no queued request for the operator fits.  A
+ * request for a new operator builds its hierarchy on the host while the
+ * other slots keep the GPU busy, and is admitted when its exact device
+ * footprint fits hbm_budget; each solve is then admitted with an upper bound
+ * of the device memory it can add (multi-right-hand-side buffers, autotuning,
+ * request staging), narrowed to fewer columns if needed.  Idle hierarchies
+ * are evicted least-recently-used first; memory that cannot fit fails the
+ * request with ENOMEM.  Solves of different operators run concurrently on
+ * their slots' streams.  Errors: EINVAL, ENODEV, ENOMEM. */
 int lsamg_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
                         lsamg_server** out);
 

@@ -3694,6 +3694,11 @@ struct SReq {
   std::vector<double> b;
   int64_t n = 0;
   double t_submit = 0;
+  // while solving
+  double t_taken = 0, t_setup = 0;
+  int hit = 0, joined_at = 0, batch_max = 0, cols_left = 0;
+  bool posted = false;
+  int col[64];                 // engine column of each right-hand side
 };
 
 struct SEntry {
@@ -3704,6 +3709,64 @@ struct SEntry {
   std::string msg;
   uint64_t last_use = 0;
 };
+
+// Device bytes a multi-right-hand-side solve of width NB may add to h: the
+// batched buffers (when not yet sized for NB, exactly as ensure_batched
+// makes them) and, while a width or precision is not tuned yet, an upper
+// bound of what the autotuners keep (split-loop partial sums, the dense
+// level's padded copies, task lists) plus their 512 MiB cache-flush buffer.
+size_t batched_reserve(const lsamg_handle* h, int NB) {
+  size_t b = 0;
+  auto add = [&](int64_t count, size_t sz) { b += (size_t)std::max<int64_t>(count, 1) * sz; };
+  const bool fresh = !(h->batched_ready && h->bwidth >= NB);
+  const int64_t W = fresh ? NB : h->bwidth;
+  if (fresh) {
+    for (const DLevel& L : h->L) {
+      const int64_t n = L.n * W, ny = std::max<int64_t>(L.nrows, 1) * W,
+                    nt = std::max<int64_t>(L.ntb, 1) * W;
+      for (int k = 0; k < 3; ++k) add(n, 8);
+      add(ny, 8);
+      add(nt, 8);
+      for (int k = 0; k < 3; ++k) add(n, 4);
+      add(ny, 4);
+      add(nt, 4);
+      if (L.bg_ok) add(L.bg_nstg * W, 4);
+    }
+    const int64_t n0 = h->L[0].n * W;
+    for (int k = 0; k < 6; ++k) add(n0, 8);
+    for (int k = 0; k < 5; ++k) add(kBNP * W, 8);
+    for (int k = 0; k < 5; ++k) add(W, 8);
+    add(192, 4);
+  }
+  // the autotuners run on the first FP32 solve of >= 16 columns (and again
+  // on the first of 64) and on the first FP64 solve of 64 columns; buffers
+  // made afresh drop what was tuned before
+  const bool mixed = h->precision == LSAMG_MIXED;
+  const bool tune = h->use_mfma &&
+                    (mixed ? NB >= 16 && (fresh || !h->mm_tuned || (NB == 64 && !h->mm_tuned64))
+                           : NB == 64 && (fresh || !h->dmmd_tuned));
+  if (tune) {
+    int64_t cap = 0;
+    for (size_t l = 0; l < h->L.size(); ++l) {
+      const DLevel& L = h->L[l];
+      if (L.coarsest || L.tail) {
+        cap = std::max<int64_t>(cap, 16 * L.n * W);
+        const int64_t ld = (L.n + 3) / 4 * 4;
+        add(L.n * ld, 4);                  // padded FP32 copy (k_dense_mm64)
+        add(L.n * ld, 8);                  // padded FP64 copy (k_dense_mm64d)
+        add(16 * L.n * 64, 8);             // its partial sums
+        add(5 * 16 * 2 * (L.n / 16 + 2), 4);
+        break;
+      }
+      if (l > 0) cap = std::max<int64_t>(cap, 4 * std::max(L.n, L.ntb) * W);
+      for (const GemvPlan* P : {&L.ras, &L.rast, &L.rst, &L.pro})
+        add(5 * 16 * 2 * (P->out / 16 + P->nagg + 1), 4);   // k_bmm and k_bmmd task lists
+    }
+    add(cap, 4);
+    b += (size_t)512 << 20;                // the tuners' flush buffer (freed after)
+  }
+  return b + b / 50 + ((size_t)1 << 20);
+}
 
 }  // namespace
 
@@ -3720,7 +3783,9 @@ struct lsamg_server {
   bool stop = false;
   size_t resident = 0, peak = 0;
   uint64_t tick = 0;
-  int64_t submitted = 0, completed = 0, hits = 0, misses = 0, evictions = 0;
+  int64_t submitted = 0, completed = 0, hits = 0, misses = 0, evictions = 0, joins = 0,
+          reserve_misses = 0;
+  std::atomic<int64_t> iterations{0};    // PCG iterations run by all solves
   int active = 0, waiting = 0;
 
   void account(size_t add, size_t sub) {
@@ -3729,20 +3794,20 @@ struct lsamg_server {
   }
 
   // post a completion (lock held)
-  void post(const SReq& q, int status, int hit, int batch, int its, double trr, double tq,
-            double tsetup, double tsolve) {
+  void post(const SReq& q, int status, int its, double trr, double t_solve) {
     lsamg_done d;
     std::memset(&d, 0, sizeof(d));
     d.id = q.r.id;
     d.status = status;
-    d.cache_hit = hit;
-    d.batch_rhs = batch;
+    d.cache_hit = q.hit;
+    d.batch_rhs = q.batch_max;
     d.iters_max = its;
     d.true_rel_res_max = trr;
-    d.t_queue = tq;
-    d.t_setup = tsetup;
-    d.t_solve = tsolve;
+    d.t_queue = q.t_taken - q.t_submit;
+    d.t_setup = q.t_setup;
+    d.t_solve = t_solve;
     d.t_total = now_s() - q.t_submit;
+    d.joined_at = q.joined_at;
     done.push_back(d);
     ++completed;
     cv_done.notify_all();
@@ -3764,16 +3829,173 @@ struct lsamg_server {
     return true;
   }
 
+  // make room for `need` more bytes (lock held): evict idle hierarchies,
+  // else wait for running solves to release memory.  False when it cannot
+  // fit: more than the budget, or every other slot is waiting as well.
+  bool make_room(std::unique_lock<std::mutex>& lk, size_t need) {
+    while (resident + need > budget) {
+      if (evict_one()) continue;
+      if (need > budget || waiting + 1 >= active) return false;
+      ++waiting;
+      cv_done.wait_for(lk, std::chrono::milliseconds(50));
+      --waiting;
+    }
+    return true;
+  }
+
   void worker();
+  template <int NB>
+  void session(std::unique_lock<std::mutex>& lk, uint64_t key, SReq first, hipStream_t st,
+               double*& stage, size_t& stage_cap);
 };
+
+// One multi-right-hand-side PCG of width NB on operator `key`, with the
+// lock held on entry and exit.  Requests for the operator that arrive while
+// it runs are loaded into free columns at the next iteration boundary and
+// start their own CG there; each request is reported as soon as its last
+// column finishes, and its columns take new requests.  The solve ends when
+// no column is active and no queued request for the operator fits.
+template <int NB>
+void lsamg_server::session(std::unique_lock<std::mutex>& lk, uint64_t key, SReq first,
+                           hipStream_t st, double*& stage, size_t& stage_cap) {
+  SEntry* e = &cache[key];
+  lsamg_handle* h = e->h;
+  const int64_t n = first.n;
+  std::vector<std::unique_ptr<SReq>> live;
+  SReq* owner[NB] = {};
+  int iter = 0;
+  auto free_cols = [&]() {
+    int k = 0;
+    for (int j = 0; j < NB; ++j) k += owner[j] == nullptr;
+    return k;
+  };
+  auto take = [&](SReq&& q) {          // lock held
+    live.push_back(std::make_unique<SReq>(std::move(q)));
+    SReq* p = live.back().get();
+    int c = 0;
+    for (int j = 0; j < NB && c < p->r.nrhs; ++j)
+      if (!owner[j]) {
+        owner[j] = p;
+        p->col[c++] = j;
+      }
+    p->cols_left = p->r.nrhs;
+    p->joined_at = iter;
+    p->t_taken = now_s();
+    return p;
+  };
+  // queued requests for this operator that fit the free columns (lock held)
+  auto admit = [&](std::vector<SReq*>& fresh) {
+    for (size_t i = 0; i < queue.size();) {
+      if (queue[i].r.op_key == key && queue[i].r.nrhs <= free_cols() && queue[i].n == n) {
+        SReq* p = take(std::move(queue[i]));
+        p->hit = 1;
+        if (iter > 0) ++joins;
+        fresh.push_back(p);
+        queue.erase(queue.begin() + i);
+      } else {
+        ++i;
+      }
+    }
+  };
+  std::vector<SReq*> fresh;
+  fresh.push_back(take(std::move(first)));
+  admit(fresh);
+  lk.unlock();
+  int rc = LSAMG_OK;
+  std::string msg;
+  try {
+    DeviceGuard g(device);
+    BatchCG<NB> E(h, st);
+    for (;;) {
+      // load the newly taken requests' columns through the staging buffer
+      for (SReq* p : fresh) {
+        const size_t need = (size_t)n * p->r.nrhs;
+        if (need > stage_cap) throw DevError{LSAMG_EINVAL, "staging smaller than a request"};
+        HIP_OK(hipMemcpyAsync(stage, p->b.data(), need * sizeof(double), hipMemcpyHostToDevice,
+                              st));
+        for (int c = 0; c < p->r.nrhs; ++c)
+          E.load(p->col[c], 1, stage + (size_t)c * n, n, p->r.tol, p->r.maxit);
+        // the next copy into the staging waits for these loads (same stream)
+      }
+      fresh.clear();
+      E.norms();
+      const int nact = E.nactive();
+      // collect finished columns; report requests whose columns are all done
+      std::vector<SReq*> finished;
+      for (auto& up : live) {
+        SReq* p = up.get();
+        if (p->cols_left == 0) continue;
+        int left = 0;
+        bool bad = false;
+        for (int c = 0; c < p->r.nrhs; ++c) {
+          const BCol& q = E.c[p->col[c]];
+          left += !q.done;
+          bad = bad || q.bad;
+        }
+        p->batch_max = std::max(p->batch_max, nact);
+        if (bad) {                       // a non-finite right-hand side: drop the request
+          for (int c = 0; c < p->r.nrhs; ++c) {
+            E.c[p->col[c]].active = 0;
+            E.c[p->col[c]].done = 1;
+          }
+          left = 0;
+        }
+        p->cols_left = left;
+        if (left == 0) finished.push_back(p);
+      }
+      for (SReq* p : finished) {
+        int its = 0, status = LSAMG_OK;
+        double trr = 0;
+        bool bad = false;
+        for (int c = 0; c < p->r.nrhs; ++c) {
+          const BCol& q = E.c[p->col[c]];
+          E.store(p->col[c], 1, stage + (size_t)c * n, n);
+          its = std::max(its, q.its);
+          trr = std::max(trr, q.nb > 0 ? q.tr / q.nb : 0.0);
+          if (!q.conv) status = LSAMG_ENOCONV;
+          bad = bad || q.bad;
+        }
+        if (bad) status = LSAMG_EBADINPUT;
+        HIP_OK(hipMemcpyAsync(p->r.x, stage, (size_t)n * p->r.nrhs * sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        const double ts = now_s() - p->t_taken;
+        lk.lock();
+        for (int c = 0; c < p->r.nrhs; ++c) owner[p->col[c]] = nullptr;
+        post(*p, status, its, trr, ts);
+        p->posted = true;
+        lk.unlock();
+      }
+      lk.lock();
+      admit(fresh);
+      const bool more = std::any_of(queue.begin(), queue.end(),
+                                    [&](const SReq& q) { return q.r.op_key == key; });
+      lk.unlock();
+      if (!fresh.empty()) continue;      // load them before the next iteration
+      if (E.nactive() == 0) break;
+      E.prepare();
+      E.step(more);
+      ++iter;
+      ++iterations;
+    }
+  } catch (const DevError& de) {
+    rc = de.code;
+    msg = de.msg;
+  }
+  lk.lock();
+  if (rc != LSAMG_OK) {                  // every request still in the solve fails with it
+    for (auto& up : live)
+      if (!up->posted) post(*up, rc, 0, 0, now_s() - up->t_taken);
+  }
+  (void)msg;
+}
 
 void lsamg_server::worker() {
   (void)hipSetDevice(device);
   hipStream_t st = nullptr;
   (void)hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  double *dB = nullptr, *dX = nullptr;
-  size_t cap = 0;
-  std::vector<lsamg_stats> stats;
+  double* stage = nullptr;               // n x 64 doubles of request columns in and out
+  size_t stage_cap = 0;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     // first queued request whose operator is resident and idle, or unknown
@@ -3800,16 +4022,14 @@ void lsamg_server::worker() {
     queue.erase(queue.begin() + pick);
     const uint64_t key = first.r.op_key;
     ++active;
-    const double t_taken = now_s();
-    double t_setup = 0;
+    first.t_taken = now_s();
     if (!miss && cache[key].failed) {
-      post(first, cache[key].err, 0, 0, 0, 0, t_taken - first.t_submit, 0, 0);
+      post(first, cache[key].err, 0, 0, 0);
       --active;
       cv_work.notify_all();
       continue;
     }
     SEntry* e = nullptr;
-    int hit = miss ? 0 : 1;
     if (miss) {
       ++misses;
       e = &cache[key];
@@ -3835,18 +4055,11 @@ void lsamg_server::worker() {
       e = &cache[key];
       // admission against the budget: evict idle hierarchies, else wait for
       // running solves to finish; a hierarchy larger than the budget fails
-      while (rc == LSAMG_OK && resident + need > budget) {
-        if (evict_one()) continue;
-        if (need > budget || waiting + 1 >= active) {
-          rc = LSAMG_ENOMEM;
-          msg = "hierarchy does not fit the device budget";
-          break;
-        }
-        ++waiting;
-        cv_done.wait_for(lk, std::chrono::milliseconds(50));
-        --waiting;
-        e = &cache[key];
+      if (rc == LSAMG_OK && !make_room(lk, need)) {
+        rc = LSAMG_ENOMEM;
+        msg = "hierarchy does not fit the device budget";
       }
+      e = &cache[key];
       if (rc == LSAMG_OK) {
         account(need, 0);                  // reserve before uploading
         lk.unlock();
@@ -3867,7 +4080,8 @@ void lsamg_server::worker() {
         e->busy = false;
         e->err = rc;
         e->msg = msg;
-        post(first, rc, 0, 0, 0, 0, t_taken - first.t_submit, now_s() - t_taken, 0);
+        first.t_setup = now_s() - first.t_taken;
+        post(first, rc, 0, 0, 0);
         --active;
         cv_work.notify_all();
         continue;
@@ -3875,100 +4089,92 @@ void lsamg_server::worker() {
       e->h = h;
       e->bytes = h->bytes;
       e->ready = true;
-      t_setup = now_s() - t_taken;
+      first.t_setup = now_s() - first.t_taken;
     } else {
       ++hits;
+      first.hit = 1;
       e = &cache[key];
       e->busy = true;
     }
-    // continuous batching: every queued request for this operator with the
-    // same tolerance and iteration limit joins the solve (<= 64 columns)
-    std::vector<SReq> group;
-    group.push_back(std::move(first));
-    int total = group[0].r.nrhs;
-    for (size_t i = 0; i < queue.size();) {
-      const lsamg_request& r = queue[i].r;
-      if (r.op_key == key && r.tol == group[0].r.tol && r.maxit == group[0].r.maxit &&
-          total + r.nrhs <= 64) {
-        total += r.nrhs;
-        group.push_back(std::move(queue[i]));
-        queue.erase(queue.begin() + i);
-      } else {
-        ++i;
+    // width of the solve: room for the columns queued for this operator now
+    // and as many again arriving while it runs
+    int cols = first.r.nrhs;
+    for (const SReq& q : queue)
+      if (q.r.op_key == key) cols += q.r.nrhs;
+    int NB = 8;
+    while (NB < 64 && NB < std::min(64, 2 * cols)) NB *= 2;
+    NB = std::max(NB, first.r.nrhs <= 8 ? 8 : first.r.nrhs <= 16 ? 16 : first.r.nrhs <= 32 ? 32 : 64);
+    // admission of the solve's own device memory (batched buffers, tuning,
+    // request staging), narrower widths first if the widest does not fit
+    lsamg_handle* h = e->h;
+    const size_t stage_need = (size_t)first.n * 64 * sizeof(double);
+    const size_t stage_grow = stage_need > stage_cap * sizeof(double) ? stage_need - stage_cap * sizeof(double) : 0;
+    size_t reserve = 0;
+    bool fits = false;
+    for (; NB >= 8; NB /= 2) {
+      if (NB < first.r.nrhs) break;
+      reserve = batched_reserve(h, NB) + stage_grow;
+      if (make_room(lk, reserve)) {
+        fits = true;
+        break;
       }
     }
-    lsamg_handle* h = e->h;
+    e = &cache[key];
+    if (!fits) {
+      e->busy = false;
+      e->last_use = ++tick;
+      post(first, LSAMG_ENOMEM, 0, 0, 0);
+      --active;
+      cv_work.notify_all();
+      continue;
+    }
+    account(reserve, 0);
     const size_t before = h->bytes;
-    lk.unlock();
-    const double t_solve0 = now_s();
-    const int64_t n = group[0].n;
-    int rc = LSAMG_OK;
-    std::string msg;
-    stats.assign(total, lsamg_stats{});
-    size_t grow = 0;
-    try {
-      DeviceGuard g(device);
-      const size_t need = (size_t)n * total;
-      if (need > cap) {
-        if (dB) (void)hipFree(dB);
-        if (dX) (void)hipFree(dX);
-        dB = dX = nullptr;
-        HIP_OK(hipMalloc(&dB, need * sizeof(double)));
-        HIP_OK(hipMalloc(&dX, need * sizeof(double)));
-        grow = 2 * (need - cap) * sizeof(double);
-        cap = need;
-      }
-      size_t off = 0;
-      for (auto& q : group) {
-        HIP_OK(hipMemcpyAsync(dB + off, q.b.data(), q.b.size() * sizeof(double),
-                              hipMemcpyHostToDevice, st));
-        off += q.b.size();
-      }
-      rc = lsamg_solve(h, dB, dX, total, n, group[0].r.tol, group[0].r.maxit, st, stats.data());
-      if (rc != LSAMG_OK) msg = lsamg_last_error();
-      if (rc == LSAMG_OK || rc == LSAMG_ENOCONV) {
-        off = 0;
-        for (auto& q : group) {
-          HIP_OK(hipMemcpyAsync(q.r.x, dX + off, q.b.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, st));
-          off += q.b.size();
+    if (stage_grow > 0) {
+      lk.unlock();
+      bool ok = true;
+      {
+        DeviceGuard g(device);
+        if (stage) (void)hipFree(stage);
+        stage = nullptr;
+        stage_cap = 0;
+        if (hipMalloc(&stage, stage_need) != hipSuccess) {
+          (void)hipGetLastError();
+          stage = nullptr;
+          ok = false;
         }
       }
-      HIP_OK(hipStreamSynchronize(st));
-    } catch (const DevError& de) {
-      rc = de.code;
-      msg = de.msg;
+      lk.lock();
+      if (!ok) {
+        account(0, reserve);
+        e = &cache[key];
+        e->busy = false;
+        post(first, LSAMG_ENOMEM, 0, 0, 0);
+        --active;
+        cv_work.notify_all();
+        continue;
+      }
+      stage_cap = (size_t)first.n * 64;
     }
-    const double t_solve = now_s() - t_solve0;
-    lk.lock();
+    switch (NB) {
+      case 8: session<8>(lk, key, std::move(first), st, stage, stage_cap); break;
+      case 16: session<16>(lk, key, std::move(first), st, stage, stage_cap); break;
+      case 32: session<32>(lk, key, std::move(first), st, stage, stage_cap); break;
+      default: session<64>(lk, key, std::move(first), st, stage, stage_cap); break;
+    }
+    // replace the reservation by what the solve really added
     e = &cache[key];
+    const size_t grown = h->bytes > before ? h->bytes - before : 0;
+    if (grown + stage_grow > reserve) ++reserve_misses;
+    account(h->bytes + stage_grow, before + reserve);
+    e->bytes = h->bytes;
     e->busy = false;
     e->last_use = ++tick;
-    account(h->bytes + grow, before);      // batched buffers the solve added
-    e->bytes = h->bytes;
-    int c0 = 0;
-    for (auto& q : group) {
-      int its = 0;
-      double trr = 0;
-      bool conv = true;
-      for (int j = 0; j < q.r.nrhs; ++j) {
-        its = std::max(its, stats[c0 + j].iters);
-        trr = std::max(trr, stats[c0 + j].true_rel_res);
-        conv = conv && stats[c0 + j].converged;
-      }
-      const int status = (rc == LSAMG_OK || rc == LSAMG_ENOCONV)
-                             ? (conv ? LSAMG_OK : LSAMG_ENOCONV)
-                             : rc;
-      post(q, status, hit, total, its, trr, t_taken - q.t_submit, t_setup, t_solve);
-      c0 += q.r.nrhs;
-    }
-    (void)msg;
     --active;
     cv_work.notify_all();
   }
   lk.unlock();
-  if (dB) (void)hipFree(dB);
-  if (dX) (void)hipFree(dX);
+  if (stage) (void)hipFree(stage);
   if (st) (void)hipStreamDestroy(st);
 }
 
@@ -4031,6 +4237,9 @@ int lsamg_server_stats_get(lsamg_server* s, lsamg_server_stats* out) {
   out->hits = s->hits;
   out->misses = s->misses;
   out->evictions = s->evictions;
+  out->joins = s->joins;
+  out->iterations = s->iterations.load();
+  out->reserve_misses = s->reserve_misses;
   out->resident_bytes = s->resident;
   out->peak_bytes = s->peak;
   out->budget = s->budget;

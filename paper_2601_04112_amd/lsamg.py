@@ -106,7 +106,8 @@ class Done(C.Structure):
                 ("batch_rhs", C.c_int32), ("iters_max", C.c_int32),
                 ("true_rel_res_max", C.c_double), ("t_queue", C.c_double),
                 ("t_setup", C.c_double), ("t_solve", C.c_double),
-                ("t_total", C.c_double)]
+                ("t_total", C.c_double), ("joined_at", C.c_int32),
+                ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -117,7 +118,9 @@ class ServerStats(C.Structure):
                 ("hits", C.c_int64), ("misses", C.c_int64),
                 ("evictions", C.c_int64), ("resident_bytes", C.c_size_t),
                 ("peak_bytes", C.c_size_t), ("budget", C.c_size_t),
-                ("queued", C.c_int32), ("active", C.c_int32)]
+                ("queued", C.c_int32), ("active", C.c_int32),
+                ("joins", C.c_int64), ("reserve_misses", C.c_int64),
+                ("iterations", C.c_int64)]
 
 
 # every symbol the header declares, with its ctypes signature
