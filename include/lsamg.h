@@ -79,9 +79,11 @@ typedef struct lsamg_params {
   int32_t ncmin;
   double tie_rtol;       /* relative width of an eigenvalue cluster (1e-8)   */
   double tie_atol;       /* absolute width of an eigenvalue cluster (1e-12)  */
-  double pinv_rtol;      /* pseudo-inverse cutoff in eq:gevp-S: directions of
-                            W^{1/2} G_{nz,Gamma} whose singular value is at
-                            most this times the largest count as null (1e-12)*/
+  double pinv_rtol;      /* pseudo-inverse cutoff in eq:gevp-S: singular
+                            values of W^{1/2} G_{nz,Gamma} at or below this
+                            times the largest count as null (1e-6, i.e.
+                            eigenvalues of A~_GammaGamma at or below 1e-12
+                            times the largest)                               */
   double thresh_margin;  /* strict side of the threshold test (1e-10)        */
   double stall_ratio;    /* stop coarsening if n_{l+1} > ratio * n_l (0.9)   */
   int32_t precision;     /* LSAMG_FP64 or LSAMG_MIXED (FP32 V-cycle)         */
@@ -95,7 +97,21 @@ typedef struct lsamg_params {
                             the GPU and applied as one dense matrix (n_l^2
                             entries per precision); 0: always recurse.
                             Default 16384.                                   */
+  int32_t aggregation;   /* LSAMG_AGG_LATTICE (0, default): lattice blocks of
+                            `block` points per axis; LSAMG_AGG_STANDARD (1):
+                            standard aggregation on the matrix entries of
+                            A_l = G_l^T G_l (sec. 3.3), nodes visited in index
+                            order, every unaggregated node joining the
+                            aggregate of its lowest-numbered aggregated
+                            neighbour; needs no lattice (ndim may be 0)      */
+  int32_t agg_passes[8]; /* standard aggregation: passes n_agg per level, the
+                            last one repeats (Algorithm 1; pass t aggregates
+                            the graph of pass t-1's aggregates, T_1 T_2 ...)  */
+  int32_t nagg_passes;   /* entries used in agg_passes (default 1: {1})      */
+  int32_t reserved_agg;
 } lsamg_params;
+
+enum { LSAMG_AGG_LATTICE = 0, LSAMG_AGG_STANDARD = 1 };
 
 /* Per-solve statistics (host memory, one entry per right-hand side). */
 typedef struct lsamg_stats {

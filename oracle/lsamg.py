@@ -31,7 +31,9 @@ the design notes of the repository):
   pseudo-inverse, i.e. the Schur complement is the minimum energy over
   ``u_Gamma``, computed as ``B_w^T (I - Q Q^T) B_w`` from the weighted rows
   ``B = W^{1/2} G_{nz,Omega}`` (Q: range of ``B_Gamma``, singular values at
-  or below ``pinv_rtol`` times the largest dropped);
+  or below ``pinv_rtol`` = 1e-6 times the largest counted as zero: the
+  eigenvalue cutoff 1e-12 of ``A~_GammaGamma = B_G^T B_G``, far enough above
+  rounding that two FP64 codes make the same rank decision);
 * selection: ``k = #{lambda > thresh}`` capped at ``floor(|omega|/c_min)``
   (or a fixed count), at least one, and never splitting a cluster of equal
   eigenvalues (the cut moves down to the cluster start, or up to its end if
@@ -69,7 +71,7 @@ class Params:
     cmin: tuple = (3, 4)            # per-level minimum coarsening ratio
     tie_rtol: float = 1e-8          # eigenvalue-cluster tolerance
     tie_atol: float = 1e-12
-    pinv_rtol: float = 1e-12        # rank cutoff of W^{1/2} G_{nz, Gamma}
+    pinv_rtol: float = 1e-6         # rank cutoff of W^{1/2} G_{nz, Gamma} (singular values)
     thresh_margin: float = 1e-10    # strict side of the threshold test
     stall_ratio: float = 0.9        # stop if n_{l+1} > stall_ratio * n_l
     aggregation: str = "lattice"    # "lattice" blocks or "standard" (sec. 3.3)
@@ -344,9 +346,12 @@ def schur_ls(B: np.ndarray, nw: int, rank_rtol: float) -> np.ndarray:
     ``S~_omega = min_{u_Gamma} [u_w; u_G]^T A~ [u_w; u_G] = B_w^T (I - Q Q^T)
     B_w`` with Q an orthonormal basis of range(B_Gamma); on a singular
     ``A~_GammaGamma`` this is the Moore-Penrose (minimum-energy) reading.
-    Q and the rank come from the SVD of B_Gamma (singular values at or below
-    ``rank_rtol`` times the largest count as zero), so the conditioning of
-    B_Gamma enters once, not squared as in ``A~_GammaGamma``.
+    Q and the numerical rank come from the SVD of B_Gamma (singular values
+    at or below ``rank_rtol`` times the largest count as zero), so the
+    conditioning of B_Gamma enters once, not squared as in
+    ``A~_GammaGamma``, and the truncated range does not depend on the basis
+    of the columns (an orthogonal change of an aggregate's eigenvector basis
+    on the finer level leaves it unchanged).
 
     The energy ``||B u||`` is unchanged when B is replaced by R from its QR
     factorisation ``B = Q_B R`` (Q_B has orthonormal columns), so the same
@@ -359,8 +364,8 @@ def schur_ls(B: np.ndarray, nw: int, rank_rtol: float) -> np.ndarray:
     Bw = B[:, :nw]
     if B.shape[1] == nw:
         return Bw.T @ Bw
-    U, s, _ = np.linalg.svd(B[:, nw:], full_matrices=False)
-    r = int(np.sum(s > rank_rtol * s[0])) if s.size and s[0] > 0 else 0
+    U, sv, _ = np.linalg.svd(B[:, nw:], full_matrices=False)
+    r = int(np.sum(sv > rank_rtol * sv[0])) if sv.size and sv[0] > 0 else 0
     Q = U[:, :r]
     E = Bw - Q @ (Q.T @ Bw)
     return E.T @ E

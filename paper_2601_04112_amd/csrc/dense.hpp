@@ -4,8 +4,9 @@
 // count.  Written from the textbook algorithms (Golub & Van Loan, "Matrix
 // Computations", 4th ed.): right-looking Cholesky (sec. 4.2), Householder
 // tridiagonalisation (sec. 8.3.1) followed by the implicit symmetric QR step
-// with Wilkinson shift (sec. 8.3.3), Householder QR (sec. 5.2.2) and
-// Householder QR with column pivoting (sec. 5.4.2).
+// with Wilkinson shift (sec. 8.3.3), Householder QR (sec. 5.2.2),
+// Householder QR with column pivoting (sec. 5.4.2) and the one-sided
+// (Hestenes) Jacobi SVD (sec. 8.6.3).
 #pragma once
 
 #include <algorithm>
@@ -227,6 +228,104 @@ inline void qr_r(int r, int c, double* a) {
   }
   for (int j = 0; j < c; ++j)
     for (int i = j + 1; i < r; ++i) a[(size_t)j * r + i] = 0.0;
+}
+
+// One-sided Jacobi SVD of the m x n matrix a (column-major): plane rotations
+// of column pairs, cyclic by rows of the pair table, until every pair is
+// orthogonal to m u relative to its norms.  On return the columns of a are
+// u_j sigma_j (mutually orthogonal) and sig[j] = sigma_j, in column order.
+inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
+  std::vector<double> nrm(n);
+  auto norm2 = [&](int j) {
+    const double* c = a + (size_t)j * m;
+    double s = 0.0;
+    for (int i = 0; i < m; ++i) s += c[i] * c[i];
+    return s;
+  };
+  for (int j = 0; j < n; ++j) nrm[j] = norm2(j);
+  const double tol = std::max(1e-15, 2.2e-16 * m);
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    bool rotated = false;
+    for (int p = 0; p + 1 < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double al = nrm[p], be = nrm[q];
+        if (al == 0.0 || be == 0.0) continue;
+        double* ap = a + (size_t)p * m;
+        double* aq = a + (size_t)q * m;
+        double g = 0.0;
+        for (int i = 0; i < m; ++i) g += ap[i] * aq[i];
+        if (std::abs(g) <= tol * std::sqrt(al * be)) continue;
+        rotated = true;
+        const double zeta = (be - al) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+        for (int i = 0; i < m; ++i) {
+          const double x = ap[i], y = aq[i];
+          ap[i] = c * x - s * y;
+          aq[i] = s * x + c * y;
+        }
+        nrm[p] = al - t * g;
+        nrm[q] = be + t * g;
+      }
+    for (int j = 0; j < n; ++j) nrm[j] = norm2(j);
+    if (!rotated) break;
+  }
+  for (int j = 0; j < n; ++j) sig[j] = std::sqrt(nrm[j]);
+}
+
+// The same Schur complement with the range of Bg truncated by its SVD
+// (singular values at or below rtol times the largest count as null), which
+// does not depend on the basis of Bg's columns.  B (rows x (nw + ng),
+// column-major, leading dimension rows, Bw first) is overwritten.  Rows
+// beyond nw + ng are first folded into the R factor of B's QR (the energy
+// ||B u|| is unchanged); the SVD of R's Gamma columns then comes from the
+// one-sided Jacobi method.  S is nw x nw, column-major.  Returns the rank.
+inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S) {
+  const int c = nw + ng;
+  int m = rows;
+  std::vector<double> R;
+  const double* M = B;
+  if (rows > c) {
+    qr_r(rows, c, B);
+    R.resize((size_t)c * c);
+    for (int j = 0; j < c; ++j)
+      std::copy(B + (size_t)j * rows, B + (size_t)j * rows + c, R.begin() + (size_t)j * c);
+    M = R.data();
+    m = c;
+  }
+  std::vector<double> E(M, M + (size_t)nw * m);            // Bw (or Rw)
+  int r = 0;
+  if (ng > 0) {
+    std::vector<double> U(M + (size_t)nw * m, M + (size_t)c * m), sig(ng);
+    jacobi_svd_cols(m, ng, U.data(), sig.data());
+    double smax = 0.0;
+    for (double v : sig) smax = std::max(smax, v);
+    for (int j = 0; j < ng; ++j) {
+      if (!(sig[j] > rtol * smax) || sig[j] == 0.0) continue;
+      ++r;
+      double* u = U.data() + (size_t)j * m;
+      const double inv = 1.0 / sig[j];
+      for (int i = 0; i < m; ++i) u[i] *= inv;
+      for (int w = 0; w < nw; ++w) {                      // E -= u (u^T E)
+        double* e = E.data() + (size_t)w * m;
+        double d = 0.0;
+        for (int i = 0; i < m; ++i) d += u[i] * e[i];
+        if (d == 0.0) continue;
+        for (int i = 0; i < m; ++i) e[i] -= d * u[i];
+      }
+    }
+  }
+  for (int j = 0; j < nw; ++j) {
+    const double* cj = E.data() + (size_t)j * m;
+    for (int i = j; i < nw; ++i) {
+      const double* ci = E.data() + (size_t)i * m;
+      double s = 0.0;
+      for (int t = 0; t < m; ++t) s += ci[t] * cj[t];
+      S[(size_t)j * nw + i] = s;
+      S[(size_t)i * nw + j] = s;
+    }
+  }
+  return r;
 }
 
 // Schur complement of a Gram matrix from its factor, without forming it:

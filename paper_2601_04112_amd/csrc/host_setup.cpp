@@ -138,6 +138,101 @@ AggResult aggregate_points(const std::vector<int32_t>& pc, const std::vector<int
   return res;
 }
 
+// Standard aggregation (sec. 3.3) of a graph given by its adjacency lists
+// (ptr/adj; self loops and repeats allowed, ignored), nodes visited in index
+// order: (1) a node whose neighbours are all unaggregated starts an
+// aggregate with them; (2) every node left over joins the aggregate (from
+// step 1) of its lowest-numbered neighbour that step 1 aggregated.  A node
+// step 1 skipped had an aggregated neighbour when visited, so step 2 places
+// every node; a node without neighbours is an aggregate of its own.
+// Aggregates are numbered in order of creation.
+std::vector<int64_t> standard_aggregation(int64_t n, const std::vector<int64_t>& ptr,
+                                          const std::vector<int64_t>& adj, int64_t& nagg) {
+  std::vector<int64_t> agg(n, -1);
+  nagg = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (agg[i] >= 0) continue;
+    bool free_nb = true;
+    for (int64_t e = ptr[i]; e < ptr[i + 1] && free_nb; ++e)
+      free_nb = adj[e] == i || agg[adj[e]] < 0;
+    if (!free_nb) continue;
+    agg[i] = nagg;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) agg[adj[e]] = nagg;
+    ++nagg;
+  }
+  const std::vector<int64_t> first = agg;
+  for (int64_t i = 0; i < n; ++i) {
+    if (first[i] >= 0) continue;
+    int64_t best = -1;
+    for (int64_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+      const int64_t j = adj[e];
+      if (j != i && first[j] >= 0 && (best < 0 || j < best)) best = j;
+    }
+    if (best < 0) fail(LSAMG_EINVAL, "standard aggregation left a node unassigned");
+    agg[i] = first[best];
+  }
+  return agg;
+}
+
+// Adjacency lists of n nodes from (u, v) edge pairs, both directions,
+// sorted and without repeats.
+void adjacency(int64_t n, const std::vector<std::pair<int64_t, int64_t>>& edges,
+               std::vector<int64_t>& ptr, std::vector<int64_t>& adj) {
+  ptr.assign(n + 1, 0);
+  for (auto& e : edges) {
+    ++ptr[e.first + 1];
+    ++ptr[e.second + 1];
+  }
+  for (int64_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+  adj.assign(ptr[n], 0);
+  std::vector<int64_t> fill(ptr.begin(), ptr.end() - 1);
+  for (auto& e : edges) {
+    adj[fill[e.first]++] = e.second;
+    adj[fill[e.second]++] = e.first;
+  }
+  std::vector<int64_t> nptr(n + 1, 0);
+  int64_t w = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    auto b = adj.begin() + ptr[i], en = adj.begin() + ptr[i + 1];
+    std::sort(b, en);
+    const int64_t k = std::unique(b, en) - b;
+    for (int64_t t = 0; t < k; ++t) adj[w + t] = adj[ptr[i] + t];
+    w += k;
+    nptr[i + 1] = w;
+  }
+  adj.resize(w);
+  ptr.swap(nptr);
+}
+
+// `passes` rounds of standard aggregation (Algorithm 1's n_agg): the first on
+// the given graph, each further one on the graph of the previous round's
+// aggregates (two aggregates adjacent when an edge joins them), composed:
+// the T_1 T_2 ... of sec. 3.3.  Returns the aggregate of every node.
+std::vector<int64_t> aggregate_standard(int64_t n, std::vector<int64_t> ptr,
+                                        std::vector<int64_t> adj, int passes, int64_t& nagg) {
+  std::vector<int64_t> agg(n);
+  std::iota(agg.begin(), agg.end(), 0);
+  int64_t cur = n;
+  for (int t = 0; t < std::max(1, passes); ++t) {
+    int64_t na = 0;
+    const std::vector<int64_t> a = standard_aggregation(cur, ptr, adj, na);
+    for (int64_t i = 0; i < n; ++i) agg[i] = a[agg[i]];
+    std::vector<std::pair<int64_t, int64_t>> edges;
+    for (int64_t u = 0; u < cur; ++u)
+      for (int64_t e = ptr[u]; e < ptr[u + 1]; ++e)
+        if (a[u] < a[adj[e]]) edges.emplace_back(a[u], a[adj[e]]);
+    adjacency(na, edges, ptr, adj);
+    cur = na;
+  }
+  nagg = cur;
+  return agg;
+}
+
+int agg_passes_at(const lsamg_params& p, int level) {
+  if (p.nagg_passes <= 0) return 1;
+  return std::max(1, p.agg_passes[std::min(level, std::min(p.nagg_passes, 8) - 1)]);
+}
+
 struct Csr {
   std::vector<int64_t> ptr;
   std::vector<int32_t> col;
@@ -436,8 +531,7 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     // S~ = min over u_Gamma of the energy: B_w^T (I - Q Q^T) B_w, Q a basis
     // of range(B_Gamma) (the pseudo-inverse reading of eq:gevp-S)
     std::vector<double> S((size_t)nw * nw);
-    schur_from_factor((int)rows, nw, ng, B.data(), B.data() + (size_t)nw * rows, p.pinv_rtol,
-                      S.data());
+    schur_svd((int)rows, nw, ng, B.data(), p.pinv_rtol, S.data());
     // S~ u = mu A_ww u  ->  C = L^{-1} S~ L^{-T}
     if (!chol_lower(nw, Aww.data())) fail(LSAMG_ENOTSPD, "A(omega,omega) is not SPD");
     std::vector<double> X(S);
@@ -510,7 +604,7 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
 // the set of parent aggregates each row touches, every group replaced by the
 // R factor of its QR factorisation.
 void next_level(Level& L, Work& W, Level& N, bool aggregate_next, const lsamg_params& p,
-                int nthreads) {
+                int level, int nthreads) {
   const int64_t na = L.nagg;
   const int ndim = L.ndim;
   std::vector<int32_t> pc((size_t)na * ndim);
@@ -526,7 +620,29 @@ void next_level(Level& L, Work& W, Level& N, bool aggregate_next, const lsamg_pa
   std::vector<int64_t> cagg(na, 0);
   N.ndim = ndim;
   for (int d = 0; d < 3; ++d) N.ext[d] = L.aext[d];
-  if (aggregate_next) {
+  if (aggregate_next && p.aggregation == LSAMG_AGG_STANDARD) {
+    // the graph of A_{l+1} joins every coarse unknown of parent a to every one
+    // of parent b when a row of G_l touches both (and those of a to each
+    // other), and the unknowns are numbered parent by parent: its standard
+    // aggregation keeps each parent's unknowns together and equals the
+    // standard aggregation of this parent graph, visited in parent order
+    std::vector<std::pair<int64_t, int64_t>> edges;
+    for (int64_t g = 0; g < L.G.ng(); ++g)
+      for (int64_t x = W.gtouch_ptr[g]; x < W.gtouch_ptr[g + 1]; ++x)
+        for (int64_t y = x + 1; y < W.gtouch_ptr[g + 1]; ++y)
+          if (W.gtouch[x] != W.gtouch[y])
+            edges.emplace_back(std::min(W.gtouch[x], W.gtouch[y]),
+                               std::max(W.gtouch[x], W.gtouch[y]));
+    std::sort(edges.begin(), edges.end());
+    edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+    std::vector<int64_t> ptr, adj;
+    adjacency(na, edges, ptr, adj);
+    int64_t nagg = 0;
+    cagg = aggregate_standard(na, std::move(ptr), std::move(adj), agg_passes_at(p, level + 1), nagg);
+    N.block = 0;
+    N.nagg = nagg;
+    for (int d = 0; d < 3; ++d) N.aext[d] = 1;
+  } else if (aggregate_next) {
     AggResult r = aggregate_points(pc, wk, ndim, N.ext, p.block, p.omega_max);
     cagg = r.id;
     N.block = r.b;
@@ -670,14 +786,20 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
   auto t0 = std::chrono::steady_clock::now();
   try {
     H.params = p;
-    const int ndim = p.ndim;
+    const bool standard = p.aggregation == LSAMG_AGG_STANDARD;
+    if (!standard && p.aggregation != LSAMG_AGG_LATTICE) fail(LSAMG_EINVAL, "bad aggregation");
+    // standard aggregation needs no lattice: the columns form a line
+    const int ndim = standard && p.ndim == 0 ? 1 : p.ndim;
     if (ndim < 1 || ndim > 3) fail(LSAMG_EINVAL, "ndim must be 1, 2 or 3");
+    int grid[3] = {1, 1, 1};
     int64_t np = 1;
     for (int d = 0; d < ndim; ++d) {
-      if (p.grid[d] <= 0) fail(LSAMG_EINVAL, "grid extents must be positive");
-      np *= p.grid[d];
+      grid[d] = standard && p.ndim == 0 ? (int)std::min<int64_t>(Gin.n, INT32_MAX) : p.grid[d];
+      if (grid[d] <= 0) fail(LSAMG_EINVAL, "grid extents must be positive");
+      np *= grid[d];
     }
     if (Gin.n != np) fail(LSAMG_EINVAL, "G has n columns != product of grid extents");
+    if (standard && (p.nagg_passes < 1 || p.nagg_passes > 8)) fail(LSAMG_EINVAL, "bad agg_passes");
     if (Gin.m <= 0 || Gin.n <= 0 || !Gin.rowptr || (Gin.nnz > 0 && (!Gin.col || !Gin.val)))
       fail(LSAMG_EINVAL, "bad G");
     if (p.block < 1 || p.omega_max < 1 || p.max_levels < 1) fail(LSAMG_EINVAL, "bad params");
@@ -691,8 +813,8 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     for (int64_t c = 0; c < n; ++c) {
       int64_t r = c;
       for (int d = 0; d < ndim; ++d) {
-        pc[(size_t)c * ndim + d] = (int32_t)(r % p.grid[d]);
-        r /= p.grid[d];
+        pc[(size_t)c * ndim + d] = (int32_t)(r % grid[d]);
+        r /= grid[d];
       }
     }
     H.levels.clear();
@@ -700,10 +822,34 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     Level& L0 = H.levels[0];
     L0.n = n;
     L0.ndim = ndim;
-    for (int d = 0; d < 3; ++d) L0.ext[d] = d < ndim ? p.grid[d] : 1;
+    for (int d = 0; d < 3; ++d) L0.ext[d] = d < ndim ? grid[d] : 1;
     const bool agg0 = (p.max_levels > 1) && (n > p.max_coarse);
     std::vector<int64_t> aid(n, 0);
-    if (agg0) {
+    if (agg0 && standard) {
+      // graph of A = G^T G: columns sharing a row of G (exact zeros dropped)
+      std::vector<std::pair<int64_t, int64_t>> edges;
+      std::vector<int64_t> cols;
+      for (int64_t r = 0; r < Gin.m; ++r) {
+        cols.clear();
+        for (int64_t e = Gin.rowptr[r]; e < Gin.rowptr[r + 1]; ++e) {
+          const int32_t c = Gin.col[e];
+          if (c < 0 || c >= n) fail(LSAMG_EINVAL, "column index out of range");
+          if (Gin.val[e] != 0.0) cols.push_back(c);
+        }
+        for (size_t x = 0; x < cols.size(); ++x)
+          for (size_t y = x + 1; y < cols.size(); ++y)
+            if (cols[x] != cols[y])
+              edges.emplace_back(std::min(cols[x], cols[y]), std::max(cols[x], cols[y]));
+      }
+      std::sort(edges.begin(), edges.end());
+      edges.erase(std::unique(edges.begin(), edges.end()), edges.end());
+      std::vector<int64_t> ptr, adj;
+      adjacency(n, edges, ptr, adj);
+      int64_t nagg = 0;
+      aid = aggregate_standard(n, std::move(ptr), std::move(adj), agg_passes_at(p, 0), nagg);
+      L0.block = 0;
+      L0.nagg = nagg;
+    } else if (agg0) {
       std::vector<int64_t> w(n, 1);
       AggResult r = aggregate_points(pc, w, ndim, L0.ext, p.block, p.omega_max);
       aid = r.id;
@@ -787,7 +933,7 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
       const bool stall = (double)nn > p.stall_ratio * (double)L.n;
       const bool agg_next = (l + 1 < p.max_levels - 1) && (nn > p.max_coarse) && !stall;
       Level N;
-      next_level(L, W, N, agg_next, p, nthreads);
+      next_level(L, W, N, agg_next, p, l, nthreads);
       H.levels.push_back(std::move(N));
       aggregated = agg_next;
       ++l;

@@ -3216,7 +3216,7 @@ void lsamg_params_default(lsamg_params* p) {
   p->ncmin = 1;
   p->tie_rtol = 1e-8;
   p->tie_atol = 1e-12;
-  p->pinv_rtol = 1e-12;
+  p->pinv_rtol = 1e-6;
   p->thresh_margin = 1e-10;
   p->stall_ratio = 0.9;
   p->precision = LSAMG_FP64;
@@ -3224,6 +3224,9 @@ void lsamg_params_default(lsamg_params* p) {
   p->nthreads = 0;
   p->verbose = 0;
   p->dense_tail = 16384;
+  p->aggregation = LSAMG_AGG_LATTICE;
+  p->agg_passes[0] = 1;
+  p->nagg_passes = 1;
 }
 
 const char* lsamg_last_error(void) { return g_last_error.c_str(); }

@@ -20,6 +20,7 @@ LSAMG_OK, LSAMG_EINVAL, LSAMG_EBADINPUT, LSAMG_ENOTSPD = 0, -1, -2, -3
 LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
 FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
+AGG_LATTICE, AGG_STANDARD = 0, 1
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
 OPT_ATA_TILES, OPT_BGROUP = 6, 7
 
@@ -49,7 +50,9 @@ class Params(C.Structure):
                 ("pinv_rtol", C.c_double), ("thresh_margin", C.c_double),
                 ("stall_ratio", C.c_double), ("precision", C.c_int32),
                 ("device", C.c_int32), ("nthreads", C.c_int32),
-                ("verbose", C.c_int32), ("dense_tail", C.c_int64)]
+                ("verbose", C.c_int32), ("dense_tail", C.c_int64),
+                ("aggregation", C.c_int32), ("agg_passes", C.c_int32 * 8),
+                ("nagg_passes", C.c_int32), ("reserved_agg", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -202,10 +205,11 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 omega_max: int = 400, n_eig_fixed: int = 0,
                 kappa: float = 50.0, cmin: Sequence[int] = (2,),
                 tie_rtol: float = 1e-8, tie_atol: float = 1e-12,
-                pinv_rtol: float = 1e-12, thresh_margin: float = 1e-10,
+                pinv_rtol: float = 1e-6, thresh_margin: float = 1e-10,
                 stall_ratio: float = 0.9, precision: int = FP64,
                 device: int = 0, nthreads: int = 0, verbose: bool = False,
-                dense_tail: int = 16384) -> Params:
+                dense_tail: int = 16384, aggregation: str = "lattice",
+                agg_passes: Sequence[int] = (1,)) -> Params:
     p = default_params()
     p.ndim = ndim
     for d in range(3):
@@ -221,6 +225,13 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
     p.precision, p.device, p.nthreads = precision, device, nthreads
     p.verbose = 1 if verbose else 0
     p.dense_tail = int(dense_tail)
+    if aggregation not in ("lattice", "standard"):
+        raise ValueError("aggregation must be 'lattice' or 'standard'")
+    p.aggregation = AGG_STANDARD if aggregation == "standard" else AGG_LATTICE
+    ap = list(agg_passes)[:8]
+    for i, c in enumerate(ap):
+        p.agg_passes[i] = int(c)
+    p.nagg_passes = len(ap)
     return p
 
 

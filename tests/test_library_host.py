@@ -170,3 +170,47 @@ def test_set_option_values():
            (L.OPT_BGROUP, 3), (99, 0)]
     for opt, v in bad:
         assert lib.lsamg_set_option(s._h, opt, v) == L.LSAMG_EINVAL, (opt, v)
+
+
+@pytest.mark.parametrize("passes", [(1,), (2,), (2, 1)])
+def test_integer_parity_standard_aggregation(passes):
+    """Standard aggregation on matrix entries (sec. 3.3), one pass, two passes
+    (T_1 T_2) and two passes on the finest level only: aggregates, Omega
+    lists, multiplicities and counts equal to the oracle's on every level."""
+    p = P.aniso2d(40, math.pi / 6, 1e-4)
+    H, inf = compare_setup(p, 2, O.Params(aggregation="standard", agg_passes=passes,
+                                          cmin=(2,), max_coarse=100),
+                           aggregation="standard", agg_passes=passes, cmin=(2,),
+                           max_coarse=100)
+    assert inf["nlevels"] >= 3
+
+
+def test_integer_parity_standard_3d():
+    p = P.ls3d(9)
+    compare_setup(p, 3, O.Params(aggregation="standard", agg_passes=(2,), cmin=(3, 4),
+                                 max_coarse=80),
+                  aggregation="standard", agg_passes=(2,), cmin=(3, 4), max_coarse=80)
+
+
+def test_standard_aggregation_without_lattice():
+    """A factor with no lattice behind its columns (identity rows plus random
+    difference rows between columns): the library takes ndim = 0 and still
+    builds the oracle's hierarchy."""
+    n = 700
+    rng = np.random.default_rng(8)
+    i = rng.integers(0, n, 2100)
+    j = (i + 1 + rng.integers(0, 30, 2100)) % n
+    rows = np.concatenate([np.arange(n), np.repeat(n + np.arange(len(i)), 2)])
+    cols = np.concatenate([np.arange(n), np.stack([i, j], 1).ravel()])
+    vals = np.concatenate([0.1 * np.ones(n), np.tile([1.0, -1.0], len(i))])
+    G = sp.csr_matrix((vals, (rows, cols)), shape=(n + len(i), n))
+    H = O.setup(G, 1, (n,), O.Params(aggregation="standard", cmin=(2,), max_coarse=60))
+    s = L.Solver(G, 0, (), device=-1, aggregation="standard", cmin=(2,), max_coarse=60)
+    inf = s.info()
+    assert inf["nlevels"] == len(H.levels) >= 3
+    for l, Lv in enumerate(H.levels[:-1]):
+        e = s.export_setup(l)
+        assert np.array_equal(e["agg"], Lv.agg) and np.array_equal(e["k"], Lv.k)
+        om = np.split(e["oidx"], e["optr"][1:-1])
+        assert all(np.array_equal(a, b) for a, b in zip(om, Lv.Omega))
+    s.close()
