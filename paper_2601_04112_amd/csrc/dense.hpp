@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <immintrin.h>
 #include <cstdint>
 #include <numeric>
 #include <vector>
@@ -230,19 +231,29 @@ inline void qr_r(int r, int c, double* a) {
     for (int i = j + 1; i < r; ++i) a[(size_t)j * r + i] = 0.0;
 }
 
+// Dot product of two contiguous vectors (fixed summation order: eight
+// interleaved partial sums, then the tail), with AVX2 fused multiply-adds.
+inline double dotv(int n, const double* a, const double* b) {
+  __m256d s0 = _mm256_setzero_pd(), s1 = _mm256_setzero_pd();
+  int i = 0;
+  for (; i + 8 <= n; i += 8) {
+    s0 = _mm256_fmadd_pd(_mm256_loadu_pd(a + i), _mm256_loadu_pd(b + i), s0);
+    s1 = _mm256_fmadd_pd(_mm256_loadu_pd(a + i + 4), _mm256_loadu_pd(b + i + 4), s1);
+  }
+  double t[4];
+  _mm256_storeu_pd(t, _mm256_add_pd(s0, s1));
+  double s = (t[0] + t[1]) + (t[2] + t[3]);
+  for (; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
 // One-sided Jacobi SVD of the m x n matrix a (column-major): plane rotations
 // of column pairs, cyclic by rows of the pair table, until every pair is
 // orthogonal to m u relative to its norms.  On return the columns of a are
 // u_j sigma_j (mutually orthogonal) and sig[j] = sigma_j, in column order.
 inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
   std::vector<double> nrm(n);
-  auto norm2 = [&](int j) {
-    const double* c = a + (size_t)j * m;
-    double s = 0.0;
-    for (int i = 0; i < m; ++i) s += c[i] * c[i];
-    return s;
-  };
-  for (int j = 0; j < n; ++j) nrm[j] = norm2(j);
+  for (int j = 0; j < n; ++j) nrm[j] = dotv(m, a + (size_t)j * m, a + (size_t)j * m);
   const double tol = std::max(1e-15, 2.2e-16 * m);
   for (int sweep = 0; sweep < 100; ++sweep) {
     bool rotated = false;
@@ -252,8 +263,7 @@ inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
         if (al == 0.0 || be == 0.0) continue;
         double* ap = a + (size_t)p * m;
         double* aq = a + (size_t)q * m;
-        double g = 0.0;
-        for (int i = 0; i < m; ++i) g += ap[i] * aq[i];
+        const double g = dotv(m, ap, aq);
         if (std::abs(g) <= tol * std::sqrt(al * be)) continue;
         rotated = true;
         const double zeta = (be - al) / (2.0 * g);
@@ -267,7 +277,7 @@ inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
         nrm[p] = al - t * g;
         nrm[q] = be + t * g;
       }
-    for (int j = 0; j < n; ++j) nrm[j] = norm2(j);
+    for (int j = 0; j < n; ++j) nrm[j] = dotv(m, a + (size_t)j * m, a + (size_t)j * m);
     if (!rotated) break;
   }
   for (int j = 0; j < n; ++j) sig[j] = std::sqrt(nrm[j]);
@@ -276,10 +286,16 @@ inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
 // The same Schur complement with the range of Bg truncated by its SVD
 // (singular values at or below rtol times the largest count as null), which
 // does not depend on the basis of Bg's columns.  B (rows x (nw + ng),
-// column-major, leading dimension rows, Bw first) is overwritten.  Rows
-// beyond nw + ng are first folded into the R factor of B's QR (the energy
-// ||B u|| is unchanged); the SVD of R's Gamma columns then comes from the
-// one-sided Jacobi method.  S is nw x nw, column-major.  Returns the rank.
+// column-major, leading dimension rows, Bw first) is overwritten; S is
+// nw x nw, column-major.  Returns the rank kept.
+//
+// Orthogonal reductions that leave ||B u|| and the singular values of Bg
+// unchanged come first: rows beyond nw + ng are folded into the R factor of
+// B's QR, then Householder QR with column pivoting brings Bg to an upper
+// trapezoidal T (k = min(rows, ng) rows, graded columns), with the same
+// reflectors applied to Bw.  The one-sided Jacobi method on T then gives the
+// singular values and, for those kept, the left singular vectors u_j, and
+// E = Bw - sum_j u_j u_j^T Bw (S = E^T E) in the reduced coordinates.
 inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S) {
   const int c = nw + ng;
   int m = rows;
@@ -296,33 +312,66 @@ inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S
   std::vector<double> E(M, M + (size_t)nw * m);            // Bw (or Rw)
   int r = 0;
   if (ng > 0) {
-    std::vector<double> U(M + (size_t)nw * m, M + (size_t)c * m), sig(ng);
-    jacobi_svd_cols(m, ng, U.data(), sig.data());
+    std::vector<double> X(M + (size_t)nw * m, M + (size_t)c * m), v(std::max(m, 1));
+    const int k = std::min(m, ng);
+    for (int s0 = 0; s0 < k; ++s0) {                        // pivoted Householder QR
+      int jm = s0;
+      double best = -1.0;
+      for (int j = s0; j < ng; ++j) {
+        const double* cc = X.data() + (size_t)j * m + s0;
+        const double sq = dotv(m - s0, cc, cc);
+        if (sq > best) {
+          best = sq;
+          jm = j;
+        }
+      }
+      if (best == 0.0) break;
+      if (jm != s0)
+        std::swap_ranges(X.begin() + (size_t)s0 * m, X.begin() + (size_t)(s0 + 1) * m,
+                         X.begin() + (size_t)jm * m);
+      const int mm = m - s0;
+      double* col = X.data() + (size_t)s0 * m + s0;
+      std::copy(col, col + mm, v.begin());
+      double beta, alpha;
+      householder(mm, v.data(), beta, alpha);
+      if (beta == 0.0) continue;
+      col[0] = alpha;
+      for (int i2 = 1; i2 < mm; ++i2) col[i2] = 0.0;
+      auto reflect = [&](double* cj) {
+        const double sd = beta * dotv(mm, v.data(), cj);
+        if (sd == 0.0) return;
+        for (int i2 = 0; i2 < mm; ++i2) cj[i2] -= sd * v[i2];
+      };
+      for (int j = s0 + 1; j < ng; ++j) reflect(X.data() + (size_t)j * m + s0);
+      for (int j = 0; j < nw; ++j) reflect(E.data() + (size_t)j * m + s0);
+    }
+    // T: rows 0..k-1 of X (the rest is zero), packed with leading dimension k
+    std::vector<double> T((size_t)k * ng), sig(ng);
+    for (int j = 0; j < ng; ++j)
+      std::copy(X.begin() + (size_t)j * m, X.begin() + (size_t)j * m + k, T.begin() + (size_t)j * k);
+    jacobi_svd_cols(k, ng, T.data(), sig.data());
     double smax = 0.0;
-    for (double v : sig) smax = std::max(smax, v);
+    for (double x : sig) smax = std::max(smax, x);
     for (int j = 0; j < ng; ++j) {
       if (!(sig[j] > rtol * smax) || sig[j] == 0.0) continue;
       ++r;
-      double* u = U.data() + (size_t)j * m;
+      double* u = T.data() + (size_t)j * k;
       const double inv = 1.0 / sig[j];
-      for (int i = 0; i < m; ++i) u[i] *= inv;
-      for (int w = 0; w < nw; ++w) {                      // E -= u (u^T E)
+      for (int i2 = 0; i2 < k; ++i2) u[i2] *= inv;
+      for (int w = 0; w < nw; ++w) {                        // E -= u (u^T E)
         double* e = E.data() + (size_t)w * m;
-        double d = 0.0;
-        for (int i = 0; i < m; ++i) d += u[i] * e[i];
+        const double d = dotv(k, u, e);
         if (d == 0.0) continue;
-        for (int i = 0; i < m; ++i) e[i] -= d * u[i];
+        for (int i2 = 0; i2 < k; ++i2) e[i2] -= d * u[i2];
       }
     }
   }
   for (int j = 0; j < nw; ++j) {
     const double* cj = E.data() + (size_t)j * m;
     for (int i = j; i < nw; ++i) {
-      const double* ci = E.data() + (size_t)i * m;
-      double s = 0.0;
-      for (int t = 0; t < m; ++t) s += ci[t] * cj[t];
-      S[(size_t)j * nw + i] = s;
-      S[(size_t)i * nw + j] = s;
+      const double sd = dotv(m, E.data() + (size_t)i * m, cj);
+      S[(size_t)j * nw + i] = sd;
+      S[(size_t)i * nw + j] = sd;
     }
   }
   return r;
