@@ -283,19 +283,136 @@ inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
   for (int j = 0; j < n; ++j) sig[j] = std::sqrt(nrm[j]);
 }
 
+// Plane rotation with [c s; -s c] [a; b] = [r; 0].
+inline void givens(double a, double b, double& c, double& s, double& r) {
+  if (b == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    r = a;
+  } else if (a == 0.0) {
+    c = 0.0;
+    s = 1.0;
+    r = b;
+  } else {
+    r = std::hypot(a, b);
+    c = a / r;
+    s = b / r;
+  }
+}
+
+// Singular values of the upper bidiagonal matrix (d, e) of order n by the
+// implicit-shift QR iteration of Golub and Kahan (Golub & Van Loan, sec.
+// 8.6.2: Wilkinson shift from the trailing 2 x 2 block of B^T B, a bulge
+// chased down by alternating right and left rotations, deflation at
+// negligible superdiagonal entries, and a zero diagonal entry removed by left
+// rotations along its row).  Every left rotation is applied to the rows of W
+// (n x nw, row-major), so W ends as U^T W0 with U the left singular vectors.
+// On return d holds the singular values with signs.  False if the iteration
+// does not converge.
+inline bool bidiag_svd(int n, double* d, double* e, double* W, int nw) {
+  const double eps = 2.220446049250313e-16;
+  double bnorm = 0.0;
+  for (int i = 0; i < n; ++i)
+    bnorm = std::max(bnorm, std::abs(d[i]) + (i + 1 < n ? std::abs(e[i]) : 0.0));
+  if (bnorm == 0.0) return true;
+  auto rot_rows = [&](int i, int j, double c, double s) {   // (Wi, Wj) <- G (Wi, Wj)
+    double* a = W + (size_t)i * nw;
+    double* b = W + (size_t)j * nw;
+    for (int t = 0; t < nw; ++t) {
+      const double x = a[t], y = b[t];
+      a[t] = c * x + s * y;
+      b[t] = -s * x + c * y;
+    }
+  };
+  int hi = n - 1;
+  long iter = 0;
+  const long maxit = 40L * n * n + 1000;
+  while (hi > 0) {
+    if (++iter > maxit) return false;
+    for (int i = 0; i < hi; ++i)
+      if (std::abs(e[i]) <= eps * (std::abs(d[i]) + std::abs(d[i + 1]))) e[i] = 0.0;
+    while (hi > 0 && e[hi - 1] == 0.0) --hi;
+    if (hi == 0) break;
+    int lo = hi - 1;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    // a negligible diagonal entry: zero its row's superdiagonal from the left
+    int zi = -1;
+    for (int i = lo; i < hi; ++i)
+      if (std::abs(d[i]) <= eps * bnorm) {
+        zi = i;
+        break;
+      }
+    if (zi >= 0) {
+      d[zi] = 0.0;
+      double x = e[zi];
+      e[zi] = 0.0;
+      for (int j = zi + 1; j <= hi && x != 0.0; ++j) {
+        double c, s, r;
+        givens(d[j], x, c, s, r);
+        d[j] = r;
+        rot_rows(j, zi, c, s);
+        if (j < hi) {
+          x = -s * e[j];
+          e[j] = c * e[j];
+        }
+      }
+      continue;
+    }
+    // Golub-Kahan step on rows/columns lo..hi
+    const double dm = d[hi - 1], dn = d[hi], em = e[hi - 1], el = hi - 1 > lo ? e[hi - 2] : 0.0;
+    const double t11 = dm * dm + el * el, t12 = dm * em, t22 = dn * dn + em * em;
+    const double dd = 0.5 * (t11 - t22);
+    double mu;
+    if (t12 == 0.0)
+      mu = t22;
+    else
+      mu = t22 - t12 * t12 / (dd + (dd >= 0.0 ? 1.0 : -1.0) * std::hypot(dd, t12));
+    double y = d[lo] * d[lo] - mu, z = d[lo] * e[lo];
+    for (int k = lo; k < hi; ++k) {
+      double c, s, r;
+      givens(y, z, c, s, r);                 // right rotation of columns k, k+1
+      if (k > lo) e[k - 1] = r;
+      const double dk = c * d[k] + s * e[k];
+      const double ek = -s * d[k] + c * e[k];
+      const double bulge = s * d[k + 1];
+      d[k + 1] *= c;
+      d[k] = dk;
+      e[k] = ek;
+      givens(d[k], bulge, c, s, r);          // left rotation of rows k, k+1
+      d[k] = r;
+      const double ek2 = c * e[k] + s * d[k + 1];
+      const double dk1 = -s * e[k] + c * d[k + 1];
+      e[k] = ek2;
+      d[k + 1] = dk1;
+      rot_rows(k, k + 1, c, s);
+      if (k + 1 < hi) {
+        z = s * e[k + 1];
+        e[k + 1] *= c;
+        y = e[k];
+      }
+    }
+  }
+  return true;
+}
+
 // The same Schur complement with the range of Bg truncated by its SVD
 // (singular values at or below rtol times the largest count as null), which
 // does not depend on the basis of Bg's columns.  B (rows x (nw + ng),
 // column-major, leading dimension rows, Bw first) is overwritten; S is
-// nw x nw, column-major.  Returns the rank kept.
+// nw x nw, column-major.  Returns the rank kept, or -1 if the SVD iteration
+// did not converge.
 //
-// Orthogonal reductions that leave ||B u|| and the singular values of Bg
-// unchanged come first: rows beyond nw + ng are folded into the R factor of
-// B's QR, then Householder QR with column pivoting brings Bg to an upper
-// trapezoidal T (k = min(rows, ng) rows, graded columns), with the same
-// reflectors applied to Bw.  The one-sided Jacobi method on T then gives the
-// singular values and, for those kept, the left singular vectors u_j, and
-// E = Bw - sum_j u_j u_j^T Bw (S = E^T E) in the reduced coordinates.
+// Only orthogonal transformations are used, so ||B u|| and the singular
+// values of Bg are those of the input: rows beyond nw + ng are folded into
+// the R factor of B's QR; with fewer rows than Gamma columns, Bg is replaced
+// by the triangle L of Bg = [L 0] Q (right transformations leave the left
+// singular vectors alone); Householder bidiagonalisation X = U_B [D; 0] V_B^T
+// (Golub & Van Loan, sec. 5.4.8) and the Golub-Kahan iteration then give
+// the singular values, with every left transformation applied to Bw as well.
+// Bw then holds U^T Bw: row j is u_j^T Bw, so S = sum over the dropped
+// singular directions (and the rows outside range(Bg)) of its rows' outer
+// products -- E^T E with E = (I - U_r U_r^T) Bw -- and U itself is never
+// formed.
 inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S) {
   const int c = nw + ng;
   int m = rows;
@@ -309,67 +426,103 @@ inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S
     M = R.data();
     m = c;
   }
-  std::vector<double> E(M, M + (size_t)nw * m);            // Bw (or Rw)
+  std::vector<double> E(M, M + (size_t)nw * m);            // Bw (column-major, m x nw)
+  std::vector<char> keep(m, 0);
   int r = 0;
   if (ng > 0) {
-    std::vector<double> X(M + (size_t)nw * m, M + (size_t)c * m), v(std::max(m, 1));
-    const int k = std::min(m, ng);
-    for (int s0 = 0; s0 < k; ++s0) {                        // pivoted Householder QR
-      int jm = s0;
-      double best = -1.0;
-      for (int j = s0; j < ng; ++j) {
-        const double* cc = X.data() + (size_t)j * m + s0;
-        const double sq = dotv(m - s0, cc, cc);
-        if (sq > best) {
-          best = sq;
-          jm = j;
-        }
-      }
-      if (best == 0.0) break;
-      if (jm != s0)
-        std::swap_ranges(X.begin() + (size_t)s0 * m, X.begin() + (size_t)(s0 + 1) * m,
-                         X.begin() + (size_t)jm * m);
-      const int mm = m - s0;
-      double* col = X.data() + (size_t)s0 * m + s0;
-      std::copy(col, col + mm, v.begin());
-      double beta, alpha;
-      householder(mm, v.data(), beta, alpha);
-      if (beta == 0.0) continue;
-      col[0] = alpha;
-      for (int i2 = 1; i2 < mm; ++i2) col[i2] = 0.0;
-      auto reflect = [&](double* cj) {
-        const double sd = beta * dotv(mm, v.data(), cj);
-        if (sd == 0.0) return;
-        for (int i2 = 0; i2 < mm; ++i2) cj[i2] -= sd * v[i2];
-      };
-      for (int j = s0 + 1; j < ng; ++j) reflect(X.data() + (size_t)j * m + s0);
-      for (int j = 0; j < nw; ++j) reflect(E.data() + (size_t)j * m + s0);
+    int n = ng;
+    std::vector<double> X;
+    if (m >= ng) {
+      X.assign(M + (size_t)nw * m, M + (size_t)c * m);       // m x n
+    } else {                                                // Bg^T = Q' R'  ->  L = R'^T
+      std::vector<double> Xt((size_t)ng * m);
+      for (int j = 0; j < ng; ++j)
+        for (int i2 = 0; i2 < m; ++i2) Xt[(size_t)i2 * ng + j] = M[(size_t)(nw + j) * m + i2];
+      qr_r(ng, m, Xt.data());
+      n = m;
+      X.assign((size_t)m * m, 0.0);
+      for (int j = 0; j < m; ++j)
+        for (int i2 = j; i2 < m; ++i2) X[(size_t)j * m + i2] = Xt[(size_t)i2 * ng + j];
     }
-    // T: rows 0..k-1 of X (the rest is zero), packed with leading dimension k
-    std::vector<double> T((size_t)k * ng), sig(ng);
-    for (int j = 0; j < ng; ++j)
-      std::copy(X.begin() + (size_t)j * m, X.begin() + (size_t)j * m + k, T.begin() + (size_t)j * k);
-    jacobi_svd_cols(k, ng, T.data(), sig.data());
-    double smax = 0.0;
-    for (double x : sig) smax = std::max(smax, x);
-    for (int j = 0; j < ng; ++j) {
-      if (!(sig[j] > rtol * smax) || sig[j] == 0.0) continue;
-      ++r;
-      double* u = T.data() + (size_t)j * k;
-      const double inv = 1.0 / sig[j];
-      for (int i2 = 0; i2 < k; ++i2) u[i2] *= inv;
-      for (int w = 0; w < nw; ++w) {                        // E -= u (u^T E)
-        double* e = E.data() + (size_t)w * m;
-        const double d = dotv(k, u, e);
-        if (d == 0.0) continue;
-        for (int i2 = 0; i2 < k; ++i2) e[i2] -= d * u[i2];
+    std::vector<double> d(n), e(std::max(n - 1, 1), 0.0), v(std::max(m, n)), w(m);
+    for (int j = 0; j < n; ++j) {
+      {                                                     // left reflector, column j
+        const int mm = m - j;
+        double* col = X.data() + (size_t)j * m + j;
+        std::copy(col, col + mm, v.begin());
+        double beta, alpha;
+        householder(mm, v.data(), beta, alpha);
+        if (beta != 0.0) {
+          col[0] = alpha;
+          for (int i2 = 1; i2 < mm; ++i2) col[i2] = 0.0;
+          auto reflect = [&](double* cj) {
+            const double sd = beta * dotv(mm, v.data(), cj);
+            if (sd == 0.0) return;
+            for (int i2 = 0; i2 < mm; ++i2) cj[i2] -= sd * v[i2];
+          };
+          for (int q = j + 1; q < n; ++q) reflect(X.data() + (size_t)q * m + j);
+          for (int q = 0; q < nw; ++q) reflect(E.data() + (size_t)q * m + j);
+        }
+        d[j] = X[(size_t)j * m + j];
       }
+      if (j + 1 < n) {                                      // right reflector, row j
+        const int len = n - j - 1;
+        for (int q = 0; q < len; ++q) v[q] = X[(size_t)(j + 1 + q) * m + j];
+        double beta, alpha;
+        householder(len, v.data(), beta, alpha);
+        if (beta != 0.0) {
+          // rows j+1.. of the trailing columns: Xs <- Xs (I - beta v v^T)
+          const int mr = m - j - 1;
+          std::fill(w.begin(), w.begin() + mr, 0.0);
+          for (int q = 0; q < len; ++q) {
+            const double vq = v[q];
+            if (vq == 0.0) continue;
+            const double* xq = X.data() + (size_t)(j + 1 + q) * m + j + 1;
+            for (int i2 = 0; i2 < mr; ++i2) w[i2] += vq * xq[i2];
+          }
+          for (int q = 0; q < len; ++q) {
+            const double f = beta * v[q];
+            if (f == 0.0) continue;
+            double* xq = X.data() + (size_t)(j + 1 + q) * m + j + 1;
+            for (int i2 = 0; i2 < mr; ++i2) xq[i2] -= f * w[i2];
+          }
+          X[(size_t)(j + 1) * m + j] = alpha;
+          for (int q = 1; q < len; ++q) X[(size_t)(j + 1 + q) * m + j] = 0.0;
+        }
+        e[j] = X[(size_t)(j + 1) * m + j];
+      }
+    }
+    // rows of U_B^T Bw (row-major) for the QR iteration's left rotations
+    std::vector<double> Wr((size_t)n * nw);
+    for (int q = 0; q < nw; ++q)
+      for (int i2 = 0; i2 < n; ++i2) Wr[(size_t)i2 * nw + q] = E[(size_t)q * m + i2];
+    if (!bidiag_svd(n, d.data(), e.data(), Wr.data(), nw)) return -1;
+    double smax = 0.0;
+    for (int j = 0; j < n; ++j) smax = std::max(smax, std::abs(d[j]));
+    for (int j = 0; j < n; ++j) {
+      const double sj = std::abs(d[j]);
+      if (sj > rtol * smax && sj != 0.0) {
+        keep[j] = 1;
+        ++r;
+      }
+      for (int q = 0; q < nw; ++q) E[(size_t)q * m + j] = Wr[(size_t)j * nw + q];
     }
   }
+  // S = sum over the rows of U^T Bw that are not kept
+  std::vector<double> Ed;
+  Ed.reserve((size_t)(m - r) * nw);
+  int md = 0;
+  for (int i2 = 0; i2 < m; ++i2) md += !keep[i2];
+  Ed.assign((size_t)md * nw, 0.0);
+  for (int q = 0; q < nw; ++q) {
+    int t = 0;
+    for (int i2 = 0; i2 < m; ++i2)
+      if (!keep[i2]) Ed[(size_t)q * md + t++] = E[(size_t)q * m + i2];
+  }
   for (int j = 0; j < nw; ++j) {
-    const double* cj = E.data() + (size_t)j * m;
+    const double* cj = Ed.data() + (size_t)j * md;
     for (int i = j; i < nw; ++i) {
-      const double sd = dotv(m, E.data() + (size_t)i * m, cj);
+      const double sd = dotv(md, Ed.data() + (size_t)i * md, cj);
       S[(size_t)j * nw + i] = sd;
       S[(size_t)i * nw + j] = sd;
     }

@@ -531,7 +531,8 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     // S~ = min over u_Gamma of the energy: B_w^T (I - Q Q^T) B_w, Q a basis
     // of range(B_Gamma) (the pseudo-inverse reading of eq:gevp-S)
     std::vector<double> S((size_t)nw * nw);
-    schur_svd((int)rows, nw, ng, B.data(), p.pinv_rtol, S.data());
+    if (schur_svd((int)rows, nw, ng, B.data(), p.pinv_rtol, S.data()) < 0)
+      fail(LSAMG_ENOTSPD, "singular value iteration did not converge");
     // S~ u = mu A_ww u  ->  C = L^{-1} S~ L^{-T}
     if (!chol_lower(nw, Aww.data())) fail(LSAMG_ENOTSPD, "A(omega,omega) is not SPD");
     std::vector<double> X(S);
