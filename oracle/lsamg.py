@@ -75,6 +75,8 @@ class Params:
     thresh_margin: float = 1e-10    # strict side of the threshold test
     stall_ratio: float = 0.9        # stop if n_{l+1} > stall_ratio * n_l
     aggregation: str = "lattice"    # "lattice" blocks or "standard" (sec. 3.3)
+    compress_rows: bool = False     # coarse G_l: each group of rows touching the same
+                                    # parent aggregates replaced by its QR R factor
     agg_passes: tuple = (1,)        # n_agg of Algorithm 1 per level (last repeats)
 
     def cmin_at(self, level: int) -> int:
@@ -452,7 +454,7 @@ def setup(G: sp.csr_matrix, ndim: int, grid: tuple, params: Params,
     l = 0
     while l < p.max_levels - 1 and lvl.n > p.max_coarse:
         _build_level(lvl, l, p, basis_hook)
-        nxt = _next_level(lvl)
+        nxt = _next_level(lvl, p.compress_rows)
         levels.append(nxt)
         l += 1
         stalled = nxt.n > p.stall_ratio * lvl.n
@@ -514,9 +516,17 @@ def _build_level(L: Level, l: int, p: Params, basis_hook):
                         shape=(L.n, int(off[-1])))
 
 
-def _next_level(L: Level) -> Level:
+def _next_level(L: Level, compress_rows: bool = False) -> Level:
     """``G_{l+1} = G_l P_l``, ``A_{l+1} = P_l^T A_l P_l`` (section 3.1.3);
-    coarse unknowns inherit their aggregate's lattice coordinate."""
+    coarse unknowns inherit their aggregate's lattice coordinate.
+
+    With ``compress_rows`` the rows of ``G_{l+1}`` that touch the same set of
+    parent aggregates (hence share one symbolic support, one multiplicity M
+    and one set of overlapping aggregates on the next level) are replaced by
+    the R factor of their QR factorisation: every sum of ``w g^T g`` over
+    them, so ``A_{l+1}``, each local ``A~_i`` and every Omega_i, is unchanged
+    in exact arithmetic, with at most |support| rows per group instead of the
+    fine rows (a CPU-time saving only)."""
     nc = L.P.shape[1]
     parent = np.repeat(np.arange(L.n_agg), L.k)
     E = sp.csr_matrix((np.ones(nc), (parent, np.arange(nc))),
@@ -525,6 +535,33 @@ def _next_level(L: Level) -> Level:
     S.data[:] = 1.0
     G = (L.G @ L.P).tocsr()
     A = (L.P.T @ L.A @ L.P).tocsr()
+    if compress_rows:
+        Rt = L._R.tocsr()
+        groups = {}
+        for j in range(Rt.shape[0]):
+            key = tuple(np.sort(Rt.indices[Rt.indptr[j]:Rt.indptr[j + 1]]))
+            groups.setdefault(key, []).append(j)
+        rr, cc, vv, sr, sc = [], [], [], [], []
+        row = 0
+        for key in sorted(groups):
+            idx = np.asarray(groups[key])
+            supp = S.indices[S.indptr[idx[0]]:S.indptr[idx[0] + 1]]
+            supp = np.sort(supp)
+            blk = G[idx][:, supp].toarray()
+            Rg = sla.qr(blk, mode="r", check_finite=False)[0]
+            k = min(len(idx), len(supp))
+            Rg = Rg[:k]
+            ii, jj = np.nonzero(Rg)
+            rr.append(row + ii)
+            cc.append(supp[jj])
+            vv.append(Rg[ii, jj])
+            sr.append(np.repeat(row + np.arange(k), len(supp)))
+            sc.append(np.tile(supp, k))
+            row += k
+        G = sp.csr_matrix((np.concatenate(vv), (np.concatenate(rr), np.concatenate(cc))),
+                          shape=(row, nc))
+        S = sp.csr_matrix((np.ones(sum(len(x) for x in sr)),
+                           (np.concatenate(sr), np.concatenate(sc))), shape=(row, nc))
     return Level(G=G, S=S, A=A, coord=L.agg_coord[parent],
                  extent=L.agg_extent)
 

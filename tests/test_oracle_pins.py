@@ -350,3 +350,32 @@ def test_assembled_vcycle(rot):
     x1, i1 = O.pcg(H, b, fixed_iters=8)
     x2, i2 = O.pcg(H, b, fixed_iters=8, precond=AV)
     assert np.linalg.norm(x2 - x1) <= 1e-13 * np.linalg.norm(x1)
+
+
+def test_row_compression_is_exact():
+    """Replacing each group of coarse rows of G_{l+1} = G_l P_l that touch the
+    same parent aggregates by the R factor of their QR leaves the hierarchy
+    unchanged: the same aggregates, Omega lists and counts on every level,
+    eigenvalues to 1e-12, A_1 = P_0^T A_0 P_0 to 1e-13 (deeper A_l depend on
+    the basis picked inside near-degenerate eigenvalue clusters, which
+    rounding may turn), and the V-cycle, which depends only on the spans, to
+    1e-12; the compressed factor has fewer rows."""
+    p = P.aniso2d(40, math.pi / 6, 1e-4)
+    prm = dict(cmin=(2,), max_coarse=60)
+    H1 = O.setup(p.G, 2, p.grid, O.Params(**prm))
+    H2 = O.setup(p.G, 2, p.grid, O.Params(compress_rows=True, **prm))
+    assert len(H1.levels) == len(H2.levels) >= 3
+    for l, (a, b) in enumerate(zip(H1.levels, H2.levels)):
+        if l <= 1:
+            assert abs(a.A - b.A).max() <= 1e-13 * abs(a.A).max()
+        if l > 0:
+            assert b.G.shape[0] < a.G.shape[0]
+        if a.coarsest:
+            continue
+        assert np.array_equal(a.agg, b.agg) and np.array_equal(a.k, b.k)
+        assert all(np.array_equal(x, y) for x, y in zip(a.Omega, b.Omega))
+        for x, y in zip(a.mu, b.mu):
+            assert np.abs(x - y).max() <= 1e-12
+    v = np.random.default_rng(5).standard_normal(p.n)
+    y1, y2 = O.vcycle(H1, v), O.vcycle(H2, v)
+    assert np.linalg.norm(y1 - y2) <= 1e-12 * np.linalg.norm(y1)
