@@ -494,7 +494,8 @@ def main():
             tot = sum(r["times"])
             cpu = dict(value=round(len(r["times"]) / tot, 6), unit="solves/s",
                        cores=r["blas_threads"], kind="oracle",
-                       sample=(f"{len(r['times'])} whole solves to 1e-8 ({r['iters']} PCG "
+                       sample=(f"{len(r['times'])} whole solves to 1e-8 "
+                               f"({'/'.join(str(i) for i in sorted(set(r['iters'])))} PCG "
                                f"iterations each) after one warm-up, the same workload; "
                                f"assembled form: each level's RAS smoother one CSR matrix, "
                                f"RAS-T its transpose, CSR A_l and P_l, coarsest Cholesky; "
