@@ -5,8 +5,8 @@
 // Computations", 4th ed.): right-looking Cholesky (sec. 4.2), Householder
 // tridiagonalisation (sec. 8.3.1) followed by the implicit symmetric QR step
 // with Wilkinson shift (sec. 8.3.3), Householder QR (sec. 5.2.2),
-// Householder QR with column pivoting (sec. 5.4.2) and the one-sided
-// (Hestenes) Jacobi SVD (sec. 8.6.3).
+// Householder bidiagonalisation (sec. 5.4.8) and the Golub-Kahan SVD step
+// (sec. 8.6.2).
 #pragma once
 
 #include <algorithm>
@@ -67,21 +67,42 @@ inline void trsm_lower_t(int n, const double* l, int r, double* b) {
 }
 
 // Householder vector of x (length m): on return x holds v with v[0] scaled
-// so that H = I - beta v v^T maps the input to alpha e_1.
+// so that H = I - beta v v^T maps the input to alpha e_1.  The vector is
+// first scaled by the power of two that brings its largest entry into
+// [1/2, 1) (2^1000 at most, which keeps the factor finite): exact, so the
+// result is unchanged wherever the plain formulas neither underflow nor
+// overflow, and v v^T (hence beta) stays finite for vectors far below the
+// rounding-noise level of a rank-deficient matrix (whose squares would
+// otherwise flush to zero or turn beta infinite).
 inline void householder(int m, double* x, double& beta, double& alpha) {
+  double amax = 0.0;
+  for (int i = 0; i < m; ++i) amax = std::max(amax, std::abs(x[i]));
+  if (amax == 0.0 || !std::isfinite(amax)) {
+    beta = 0.0;
+    alpha = x[0];
+    return;
+  }
+  int ex;
+  (void)std::frexp(amax, &ex);
+  ex = std::max(ex, -1000);
+  const double sc = std::ldexp(1.0, -ex);
+  for (int i = 0; i < m; ++i) x[i] *= sc;
   double sig = 0.0;
   for (int i = 1; i < m; ++i) sig += x[i] * x[i];
   const double x0 = x[0];
   if (sig == 0.0) {
     beta = 0.0;
-    alpha = x0;
+    alpha = std::ldexp(x0, ex);
+    x[0] = alpha;
+    for (int i = 1; i < m; ++i) x[i] = std::ldexp(x[i], ex);
     return;
   }
   const double nrm = std::sqrt(x0 * x0 + sig);
-  alpha = (x0 >= 0.0) ? -nrm : nrm;
-  x[0] = x0 - alpha;
+  const double a = (x0 >= 0.0) ? -nrm : nrm;
+  x[0] = x0 - a;
   const double vtv = x[0] * x[0] + sig;
   beta = 2.0 / vtv;
+  alpha = std::ldexp(a, ex);
 }
 
 // Symmetric eigen-decomposition a = V diag(w) V^T of the n x n matrix a
@@ -247,42 +268,6 @@ inline double dotv(int n, const double* a, const double* b) {
   return s;
 }
 
-// One-sided Jacobi SVD of the m x n matrix a (column-major): plane rotations
-// of column pairs, cyclic by rows of the pair table, until every pair is
-// orthogonal to m u relative to its norms.  On return the columns of a are
-// u_j sigma_j (mutually orthogonal) and sig[j] = sigma_j, in column order.
-inline void jacobi_svd_cols(int m, int n, double* a, double* sig) {
-  std::vector<double> nrm(n);
-  for (int j = 0; j < n; ++j) nrm[j] = dotv(m, a + (size_t)j * m, a + (size_t)j * m);
-  const double tol = std::max(1e-15, 2.2e-16 * m);
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    bool rotated = false;
-    for (int p = 0; p + 1 < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double al = nrm[p], be = nrm[q];
-        if (al == 0.0 || be == 0.0) continue;
-        double* ap = a + (size_t)p * m;
-        double* aq = a + (size_t)q * m;
-        const double g = dotv(m, ap, aq);
-        if (std::abs(g) <= tol * std::sqrt(al * be)) continue;
-        rotated = true;
-        const double zeta = (be - al) / (2.0 * g);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (std::abs(zeta) + std::sqrt(1.0 + zeta * zeta));
-        const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
-        for (int i = 0; i < m; ++i) {
-          const double x = ap[i], y = aq[i];
-          ap[i] = c * x - s * y;
-          aq[i] = s * x + c * y;
-        }
-        nrm[p] = al - t * g;
-        nrm[q] = be + t * g;
-      }
-    for (int j = 0; j < n; ++j) nrm[j] = dotv(m, a + (size_t)j * m, a + (size_t)j * m);
-    if (!rotated) break;
-  }
-  for (int j = 0; j < n; ++j) sig[j] = std::sqrt(nrm[j]);
-}
-
 // Plane rotation with [c s; -s c] [a; b] = [r; 0].
 inline void givens(double a, double b, double& c, double& s, double& r) {
   if (b == 0.0) {
@@ -312,8 +297,11 @@ inline void givens(double a, double b, double& c, double& s, double& r) {
 inline bool bidiag_svd(int n, double* d, double* e, double* W, int nw) {
   const double eps = 2.220446049250313e-16;
   double bnorm = 0.0;
-  for (int i = 0; i < n; ++i)
-    bnorm = std::max(bnorm, std::abs(d[i]) + (i + 1 < n ? std::abs(e[i]) : 0.0));
+  for (int i = 0; i < n; ++i) {
+    const double t = std::abs(d[i]) + (i + 1 < n ? std::abs(e[i]) : 0.0);
+    if (!std::isfinite(t)) return false;
+    bnorm = std::max(bnorm, t);
+  }
   if (bnorm == 0.0) return true;
   auto rot_rows = [&](int i, int j, double c, double s) {   // (Wi, Wj) <- G (Wi, Wj)
     double* a = W + (size_t)i * nw;
@@ -329,8 +317,14 @@ inline bool bidiag_svd(int n, double* d, double* e, double* W, int nw) {
   const long maxit = 40L * n * n + 1000;
   while (hi > 0) {
     if (++iter > maxit) return false;
+    // negligible superdiagonal: relative to its neighbours, or below the
+    // rounding level of the whole matrix (the singular values are needed to
+    // absolute accuracy eps ||B|| only; a relative test alone converges
+    // slowly on the clusters of tiny values of a rank-deficient matrix)
     for (int i = 0; i < hi; ++i)
-      if (std::abs(e[i]) <= eps * (std::abs(d[i]) + std::abs(d[i + 1]))) e[i] = 0.0;
+      if (std::abs(e[i]) <= eps * (std::abs(d[i]) + std::abs(d[i + 1])) ||
+          std::abs(e[i]) <= eps * bnorm)
+        e[i] = 0.0;
     while (hi > 0 && e[hi - 1] == 0.0) --hi;
     if (hi == 0) break;
     int lo = hi - 1;
@@ -525,70 +519,6 @@ inline int schur_svd(int rows, int nw, int ng, double* B, double rtol, double* S
       const double sd = dotv(md, Ed.data() + (size_t)i * md, cj);
       S[(size_t)j * nw + i] = sd;
       S[(size_t)i * nw + j] = sd;
-    }
-  }
-  return r;
-}
-
-// Schur complement of a Gram matrix from its factor, without forming it:
-// for A = [Bw Bg]^T [Bw Bg] (Bw: rows x nw, Bg: rows x ng, column-major with
-// leading dimension rows, both overwritten), S = Bw^T (I - Q Q^T) Bw with Q an
-// orthonormal basis of range(Bg) -- the minimum over y of the energy of
-// [x; y], i.e. A_ww - A_wg A_gg^+ A_gw.  Q comes from Householder QR with
-// column pivoting of Bg; the factorisation stops (rank r) once the largest
-// remaining column norm is at most rtol times the first pivot's.  Each
-// reflector is applied to Bw as it is formed; S (nw x nw, column-major) is
-// then the Gram matrix of rows r.. of the transformed Bw.  Returns r.
-inline int schur_from_factor(int rows, int nw, int ng, double* Bw, double* Bg, double rtol,
-                             double* S) {
-  std::vector<double> v(std::max(rows, 1));
-  int r = 0;
-  double n0 = 0.0;
-  const int kmax = std::min(rows, ng);
-  for (int k = 0; k < kmax; ++k) {
-    int jm = k;
-    double best = -1.0;
-    for (int j = k; j < ng; ++j) {
-      const double* c = Bg + (size_t)j * rows;
-      double s = 0.0;
-      for (int i = k; i < rows; ++i) s += c[i] * c[i];
-      if (s > best) {
-        best = s;
-        jm = j;
-      }
-    }
-    best = std::sqrt(best);
-    if (k == 0) n0 = best;
-    if (!(best > rtol * n0) || best == 0.0) break;
-    if (jm != k)
-      std::swap_ranges(Bg + (size_t)k * rows, Bg + (size_t)(k + 1) * rows, Bg + (size_t)jm * rows);
-    const int m = rows - k;
-    double* col = Bg + (size_t)k * rows + k;
-    std::copy(col, col + m, v.begin());
-    double beta, alpha;
-    householder(m, v.data(), beta, alpha);
-    r = k + 1;
-    if (beta == 0.0) continue;
-    col[0] = alpha;
-    for (int i = 1; i < m; ++i) col[i] = 0.0;
-    auto reflect = [&](double* cj) {
-      double s = 0.0;
-      for (int i = 0; i < m; ++i) s += v[i] * cj[i];
-      s *= beta;
-      if (s == 0.0) return;
-      for (int i = 0; i < m; ++i) cj[i] -= s * v[i];
-    };
-    for (int j = k + 1; j < ng; ++j) reflect(Bg + (size_t)j * rows + k);
-    for (int j = 0; j < nw; ++j) reflect(Bw + (size_t)j * rows + k);
-  }
-  for (int j = 0; j < nw; ++j) {
-    const double* cj = Bw + (size_t)j * rows;
-    for (int i = j; i < nw; ++i) {
-      const double* ci = Bw + (size_t)i * rows;
-      double s = 0.0;
-      for (int t = r; t < rows; ++t) s += ci[t] * cj[t];
-      S[(size_t)j * nw + i] = s;
-      S[(size_t)i * nw + j] = s;
     }
   }
   return r;
