@@ -177,6 +177,9 @@ typedef struct lsamg_kprof {
   int64_t launches;      /* launches timed since profiling was enabled       */
   double ms;             /* summed HIP-event durations of those launches     */
   double bytes;          /* summed algorithmic bytes of those launches       */
+  double flops;          /* summed algorithmic floating-point operations of
+                            those launches (matrix-core and dense products:
+                            2 x stored matrix entries x columns; else 0)     */
 } lsamg_kprof;
 
 typedef struct lsamg_handle lsamg_handle;
@@ -215,6 +218,7 @@ typedef struct lsamg_done {
   int32_t joined_at;       /* PCG iteration of the running solve at which the
                               request's columns entered it (0: it started it)  */
   int32_t reserved;
+  char msg[96];            /* error message of a failed request ("" on success) */
 } lsamg_done;
 
 typedef struct lsamg_server_stats {
@@ -333,12 +337,23 @@ enum {
                              expanded stencil); 2 or 3: the row form or the
                              expanded form in both precisions; 0: the untiled
                              forms                                              */
-  LSAMG_OPT_BGROUP = 7    /* 0 (default): on 64 columns in FP32, each coarse
+  LSAMG_OPT_BGROUP = 7,   /* 0 (default): on 64 columns in FP32, each coarse
                              level's residual runs as the row-group pass (R_g^T R_g
                              per group, staged) or as two CSR passes, whichever the
                              autotuner times faster; 1: the row-group pass where
                              built; 2: the CSR passes                           */
+  LSAMG_OPT_KRYLOV = 8    /* LSAMG_KRYLOV_CG (default): the outer iteration is
+                             preconditioned CG, beta = rho_new / rho_old;
+                             LSAMG_KRYLOV_FCG: flexible CG with one stored
+                             direction (Notay 2000), beta = -(z . A p) / (p . A p),
+                             which keeps consecutive directions A-orthogonal when
+                             the V-cycle is a slightly varying or unsymmetric
+                             operator (its FP32 form); the same in exact
+                             arithmetic with a fixed symmetric preconditioner.
+                             Applies to single and batched solves               */
 };
+
+enum { LSAMG_KRYLOV_CG = 0, LSAMG_KRYLOV_FCG = 1 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
  * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT and LSAMG_OPT_BGROUP.

@@ -611,7 +611,7 @@ def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
 
 def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
         fixed_iters: Optional[int] = None,
-        precond: Optional[Callable] = None):
+        precond: Optional[Callable] = None, flexible: bool = False):
     """Preconditioned CG, x0 = 0, preconditioner = one V-cycle.
 
     Stops when ``||r_k||_2 <= tol ||b||_2`` for the recurrence residual and
@@ -620,9 +620,14 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
     from ``x_k`` (direction ``p = z``), so a reported convergence always holds
     for ``b - A x``.  With ``fixed_iters`` it runs exactly that many
     iterations.  ``precond(r)`` replaces the V-cycle by another form of the
-    same operator (``AssembledVcycle``).  Returns ``(x, info)`` with
-    iteration count and residual history (``restarts`` counts the
-    replacements).
+    same operator (``AssembledVcycle``).  With ``flexible`` the direction is
+    made A-orthogonal to the previous one explicitly, ``beta = -(z_{k+1}^T
+    q_k) / (p_k^T q_k)`` with ``q_k = A p_k`` (flexible CG with one stored
+    direction, Notay 2000), which stays a CG method when the preconditioner
+    varies or is slightly unsymmetric (a V-cycle in lower precision); with
+    a fixed symmetric preconditioner it equals the standard ``beta`` in exact
+    arithmetic.  Returns ``(x, info)`` with iteration count and residual
+    history (``restarts`` counts the replacements).
     """
     apply_b = precond if precond is not None else (lambda v: vcycle(H, v))
     A0 = H.levels[0]
@@ -658,6 +663,8 @@ def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
         rho_new = r @ z
         if restart:
             pdir = z.copy()
+        elif flexible:
+            pdir = z - ((z @ q) / (pdir @ q)) * pdir
         else:
             pdir = z + (rho_new / rho) * pdir
         rho = rho_new

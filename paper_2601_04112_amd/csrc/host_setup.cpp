@@ -489,6 +489,14 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
   L.k.assign(na, 0);
   std::vector<std::vector<double>> mus(na), zh(na), zs(na);
   std::atomic<int64_t> hazards{0};
+  // per-phase thread time (verbose): local factor, Schur complement, local
+  // eigenproblem, local inverse rows
+  std::atomic<int64_t> ph_ns[4] = {{0}, {0}, {0}, {0}};
+  std::atomic<int64_t> max_nO{0}, max_rows{0};
+  auto tick = [] { return std::chrono::steady_clock::now(); };
+  auto add_ns = [&](int i, std::chrono::steady_clock::time_point t0) {
+    ph_ns[i] += std::chrono::duration_cast<std::chrono::nanoseconds>(tick() - t0).count();
+  };
   int nt = nthreads > 0 ? nthreads : default_threads();
   std::vector<std::vector<int32_t>> locs(nt);
   parallel_for(na, [&](int64_t a, int t) {
@@ -501,8 +509,13 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = j;
     // B = W^{1/2} G_{nz,Omega} (rows x nO, column-major; A~_i = B^T B) and
     // A_ww = G_{nz,w}^T G_{nz,w}
+    auto t_ph = tick();
     int64_t rows = 0;
     for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) rows += G.nrows[W.nz[e]];
+    for (int64_t cur = max_nO.load(); nO > cur && !max_nO.compare_exchange_weak(cur, nO);) {
+    }
+    for (int64_t cur = max_rows.load(); rows > cur && !max_rows.compare_exchange_weak(cur, rows);) {
+    }
     std::vector<double> B((size_t)rows * nO, 0.0), Aww((size_t)nw * nw, 0.0);
     std::vector<int> lp;
     int64_t r0 = 0;
@@ -531,8 +544,12 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     // S~ = min over u_Gamma of the energy: B_w^T (I - Q Q^T) B_w, Q a basis
     // of range(B_Gamma) (the pseudo-inverse reading of eq:gevp-S)
     std::vector<double> S((size_t)nw * nw);
+    add_ns(0, t_ph);
+    t_ph = tick();
     if (schur_svd((int)rows, nw, ng, B.data(), p.pinv_rtol, S.data()) < 0)
       fail(LSAMG_ENOTSPD, "singular value iteration did not converge");
+    add_ns(1, t_ph);
+    t_ph = tick();
     // S~ u = mu A_ww u  ->  C = L^{-1} S~ L^{-T}
     if (!chol_lower(nw, Aww.data())) fail(LSAMG_ENOTSPD, "A(omega,omega) is not SPD");
     std::vector<double> X(S);
@@ -565,6 +582,8 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     L.k[a] = k;
     mus[a] = std::move(mu);
     zh[a] = std::move(Zh);
+    add_ns(2, t_ph);
+    t_ph = tick();
     // smoother: A_i = A(Omega_i, Omega_i), Z_i = A_i^{-1}(omega_i, Omega_i)
     std::vector<double> Ai((size_t)nO * nO, 0.0);
     for (int r = 0; r < nO; ++r) {
@@ -581,8 +600,18 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     trsm_lower(nO, Ai.data(), nw, Zc.data());
     trsm_lower_t(nO, Ai.data(), nw, Zc.data());
     zs[a] = std::move(Zc);          // column j = row j of A_i^{-1} restricted to omega
+    add_ns(3, t_ph);
   }, nthreads);
   L.hazards = hazards.load();
+  if (p.verbose) {
+    std::fprintf(stderr,
+                 "lsamg setup: level %d: %lld aggregates, largest |Omega| %lld, most rows %lld; "
+                 "thread seconds: local factor %.1f, Schur complement %.1f, eigenproblem %.1f, "
+                 "local inverse %.1f\n",
+                 level, (long long)na, (long long)max_nO.load(), (long long)max_rows.load(),
+                 ph_ns[0] * 1e-9, ph_ns[1] * 1e-9, ph_ns[2] * 1e-9, ph_ns[3] * 1e-9);
+    std::fflush(stderr);
+  }
   L.muptr.assign(na + 1, 0);
   L.zoff.assign(na + 1, 0);
   L.poff.assign(na + 1, 0);

@@ -920,7 +920,9 @@ __global__ void __launch_bounds__(kBlock) k_cg_apq(int64_t n, const int64_t* __r
 }
 
 // alpha = rho / pq from the partials; x += alpha p; r -= alpha q;
-// r32 = (float) r (if given); partials of r . r
+// r32 = (float) r (if given); partials of r . r; pq_keep (if given) receives
+// a copy of the p . q partials (the flexible-CG denominator, which the next
+// A-apply would overwrite)
 __global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* __restrict__ rz_part,
                                                       const double* __restrict__ pq_part,
                                                       const double* __restrict__ p,
@@ -928,9 +930,12 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* _
                                                       double* __restrict__ x,
                                                       double* __restrict__ r,
                                                       float* __restrict__ r32,
-                                                      double* __restrict__ rr_part) {
+                                                      double* __restrict__ rr_part,
+                                                      double* __restrict__ pq_keep) {
   const int np = gridDim.x;
   const double alpha = sum_parts(rz_part, np) / sum_parts(pq_part, np);
+  if (pq_keep && blockIdx.x == 0)
+    for (int i = threadIdx.x; i < np; i += kBlock) pq_keep[i] = pq_part[i];
   double v = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
@@ -944,7 +949,8 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* _
 }
 
 // z = xv + staged RAS-T contributions (the finest level's V-cycle output in
-// the V-cycle precision T, widened to FP64); partials of r . z
+// the V-cycle precision T, widened to FP64); partials of r . z, and with q
+// given the partials of -(z . q) (the flexible-CG numerator, q = A p_old)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_cg_z(int64_t n, const T* __restrict__ xv,
                                                  const int64_t* __restrict__ cptr,
@@ -952,8 +958,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_z(int64_t n, const T* __restrict_
                                                  const T* __restrict__ tb,
                                                  const double* __restrict__ r,
                                                  double* __restrict__ z,
-                                                 double* __restrict__ rz_part) {
-  double v = 0;
+                                                 double* __restrict__ rz_part,
+                                                 const double* __restrict__ q,
+                                                 double* __restrict__ zq_part) {
+  double v = 0, w = 0;
   for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * kBlock) {
     T s = xv[i];
@@ -962,8 +970,10 @@ __global__ void __launch_bounds__(kBlock) k_cg_z(int64_t n, const T* __restrict_
     const double zi = (double)s;
     z[i] = zi;
     v += r[i] * zi;
+    if (q) w += zi * q[i];
   }
   write_part(v, rz_part);
+  if (q) write_part(-w, zq_part);
 }
 
 // p = z + beta p with beta = rho_new / rho_old (rho_old_part == nullptr: p = z)

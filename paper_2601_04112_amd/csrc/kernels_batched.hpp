@@ -1491,7 +1491,8 @@ __global__ void __launch_bounds__(kBlock) k_bcg_update(int64_t n, const double* 
   bwrite_parts<NB>(v, rr_part);
 }
 
-// Z = XV + staged RAS-T contributions (V-cycle precision T); partials of R . Z
+// Z = XV + staged RAS-T contributions (V-cycle precision T); partials of
+// R . Z, and with Q given the partials of -(Z . Q) (flexible CG, Q = A P_old)
 template <typename T, int NB>
 __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict__ XV,
                                                   const int64_t* __restrict__ cptr,
@@ -1499,9 +1500,11 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
                                                   const T* __restrict__ tb,
                                                   const double* __restrict__ R,
                                                   double* __restrict__ Z,
-                                                  double* __restrict__ rz_part) {
+                                                  double* __restrict__ rz_part,
+                                                  const double* __restrict__ Q,
+                                                  double* __restrict__ zq_part) {
   const int c = threadIdx.x % NB;
-  double v = 0;
+  double v = 0, w = 0;
   for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < n * NB;
        e += (int64_t)gridDim.x * kBlock) {
     const int64_t d = wave_row<NB>(e / NB);
@@ -1515,8 +1518,10 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
     const double zi = (double)s;
     Z[e] = zi;
     v += R[e] * zi;
+    if (Q) w += zi * Q[e];
   }
   bwrite_parts<NB>(v, rz_part);
+  if (Q) bwrite_parts<NB>(-w, zq_part);
 }
 
 // k_bcg_z on 64 columns with four columns per thread: a group of 16 lanes
@@ -1525,7 +1530,7 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z(int64_t n, const T* __restrict
 // round trip.  Z = (double)(XV + staged sum), the staged rows added in
 // position order as in k_bcg_z; partials of R . Z per column and workgroup
 // (column-major, as bwrite_parts) summed over the 16 unknown slots in a
-// fixed order.
+// fixed order.  With Q given, also the partials of -(Z . Q) (flexible CG).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restrict__ XV,
                                                     const int64_t* __restrict__ cptr,
@@ -1533,11 +1538,13 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restri
                                                     const T* __restrict__ tb,
                                                     const double* __restrict__ R,
                                                     double* __restrict__ Z,
-                                                    double* __restrict__ rz_part) {
+                                                    double* __restrict__ rz_part,
+                                                    const double* __restrict__ Q,
+                                                    double* __restrict__ zq_part) {
   constexpr int SL = kBlock / 16;          // unknown slots per workgroup
   __shared__ double sm[SL][64];
   const int slot = threadIdx.x >> 4, c4 = 4 * (threadIdx.x & 15);
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t d = (int64_t)xcd_block(blockIdx.x, gridDim.x) * SL + slot; d < n;
        d += (int64_t)gridDim.x * SL) {
     const int64_t o = d * 64 + c4;
@@ -1560,6 +1567,12 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restri
     *(d2*)(Z + o + 2) = z23;
 #pragma unroll
     for (int k = 0; k < 4; ++k) v[k] += r[k] * (double)s[k];
+    if (Q) {
+      double qv[4];
+      load4<double>(Q + o, qv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) w[k] += (double)s[k] * qv[k];
+    }
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) sm[slot][c4 + k] = v[k];
@@ -1568,6 +1581,16 @@ __global__ void __launch_bounds__(kBlock) k_bcg_z64(int64_t n, const T* __restri
     double t = 0;
     for (int q = 0; q < SL; ++q) t += sm[q][threadIdx.x];
     rz_part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+  }
+  if (!Q) return;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) sm[slot][c4 + k] = w[k];
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double t = 0;
+    for (int q = 0; q < SL; ++q) t += sm[q][threadIdx.x];
+    zq_part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = -t;
   }
 }
 

@@ -203,6 +203,7 @@ struct Profiler {
     std::string name;
     double bytes;
     hipEvent_t a, b;
+    double flops;
   };
   std::vector<Rec> recs;
   bool want(const std::string& nm) const { return on && (only.empty() || nm == only); }
@@ -223,13 +224,14 @@ struct ProfScope {
   Profiler* p = nullptr;
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope() = default;
-  ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t) {
+  ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t, double flops = 0.0) {
     if (!pp || !pp->want(name) || pp->used + 2 > pp->pool.size()) return;
     p = pp;
     a = pp->pool[pp->used++];
     b = pp->pool[pp->used++];
     pp->recs.push_back(Profiler::Rec{
-        pp->by_level && g_level >= 0 ? name + " @L" + std::to_string(g_level) : name, bytes, a, b});
+        pp->by_level && g_level >= 0 ? name + " @L" + std::to_string(g_level) : name, bytes, a, b,
+        flops});
   }
 };
 
@@ -289,6 +291,12 @@ const ProfScope kNoProf{};
   Profiler* pp_ = prof_active();      \
   ProfScope ps_(pp_, pp_ ? std::string(NAME) : std::string(), pp_ ? (double)(BYTES) : 0.0, S)
 
+// the same with the launch's algorithmic floating-point operations
+#define PROF_F(NAME, BYTES, FLOPS, S) \
+  Profiler* pp_ = prof_active();      \
+  ProfScope ps_(pp_, pp_ ? std::string(NAME) : std::string(), pp_ ? (double)(BYTES) : 0.0, S, \
+                pp_ ? (double)(FLOPS) : 0.0)
+
 template <typename T>
 const char* tname();
 template <>
@@ -315,6 +323,7 @@ struct lsamg_handle {
   bool gv_tuned[2] = {false, false}; // single-vector wide GEMV shapes tuned (double, float)
   // V-cycles replayed from HIP graphs, one per (precision, batch width)
   bool use_graphs = true;
+  int krylov = LSAMG_KRYLOV_CG;      // outer iteration: CG or flexible CG
   std::unordered_map<int, hipGraphExec_t> graphs;
   void drop_graphs(bool batched_only) {
     for (auto it = graphs.begin(); it != graphs.end();) {
@@ -334,11 +343,14 @@ struct lsamg_handle {
          *bi = nullptr, *part = nullptr, *sc = nullptr;
   // per-workgroup partial sums of the CG dot products (red_blocks(n) each)
   double *p_pq = nullptr, *p_rr = nullptr, *p_rz[2] = {nullptr, nullptr}, *p_tmp = nullptr;
+  // flexible CG: partials of -(z . q) and a copy of the last p . q partials
+  double *p_zq = nullptr, *p_pqo = nullptr;
   int red_np = 1;
   // k_cg_tile: the direction update p = z + beta p is applied by the next
   // A-apply, into p2 (then swapped with p); 0 none pending, 1 p = z, 2 p = z + beta p
   double* p2 = nullptr;
-  int dir_pending = 0, dir_cur = 0;
+  int dir_pending = 0;
+  const double *dir_num = nullptr, *dir_den = nullptr;   // partials of beta's terms
   double* sc_host = nullptr;         // pinned
   int nparts = 1024;
   hipEvent_t ev_rr[2] = {nullptr, nullptr};
@@ -353,9 +365,10 @@ struct lsamg_handle {
   std::vector<BLev> BL;
   double *BX = nullptr, *BR = nullptr, *BZ = nullptr, *BP = nullptr, *BQ = nullptr,
          *BBi = nullptr, *Bpq = nullptr, *Brr = nullptr, *Brz[2] = {nullptr, nullptr},
-         *Btmp = nullptr;
+         *Btmp = nullptr, *Bzq = nullptr;
   // per-column scalars summed from those partials (k_bsum)
-  double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr;
+  double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr,
+         *Bzq_s = nullptr;
   int* Bactive = nullptr;            // 64 active, 64 restart, 64 new-direction flags
   int* Bactive_host = nullptr;       // pinned, the same three arrays
   double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
@@ -1008,6 +1021,8 @@ void upload(lsamg_handle* h) {
   h->p_rz[0] = h->alloc<double>(h->red_np);
   h->p_rz[1] = h->alloc<double>(h->red_np);
   h->p_tmp = h->alloc<double>(h->red_np);
+  h->p_zq = h->alloc<double>(h->red_np);
+  h->p_pqo = h->alloc<double>(h->red_np);
   // dense tail: the first level below the finest that is small enough
   size_t lc = 0;
   if (h->H.params.dense_tail > 0)
@@ -1509,15 +1524,14 @@ void cg_apply(lsamg_handle* h, hipStream_t s) {
   if (!L.g_ptr || !L.gt_ptr) throw DevError{LSAMG_EINVAL, "finest-level G missing on the device"};
   const int64_t n = L.n;
   if (h->dir_pending) {                 // p = z (+ beta p) and q = A p in one pass
-    const int c = h->dir_cur;
-    const double* rz_old = h->dir_pending == 2 ? h->p_rz[1 - c] : nullptr;
+    const double* rz_old = h->dir_pending == 2 ? h->dir_den : nullptr;
     PROF(kname("k_cg_tile", std::to_string(L.ata_me) + ", " + std::to_string(L.ata_mf)),
          8.0 * (3 * n + (h->dir_pending == 2 ? n : 0)) + 12.0 * L.nnz + 8.0 * L.nrows + 16 * h->red_np,
          s);
     const size_t lds = (size_t)(L.at1.umax + L.at1_rmax) * sizeof(double);
     auto launch = [&](auto kern) {
       KLAUNCH(h->red_np, dev::kBlock, lds, s, kern, n, L.at1, (const double*)L.trv1,
-              (const double*)L.tdw1, (const double*)h->p_rz[c], rz_old, (const double*)h->z,
+              (const double*)L.tdw1, h->dir_num, rz_old, (const double*)h->z,
               (const double*)h->p, h->p2, h->q, h->p_pq);
     };
     const int me = L.ata_me, mf = L.ata_mf;
@@ -1555,33 +1569,39 @@ void cg_apply(lsamg_handle* h, hipStream_t s) {
 }
 
 // z = B r from the residual h->r (and its FP32 copy in mixed mode), the
-// partials of r . z into p_rz[cur], and p = z + beta p (beta from p_rz[cur]
-// over p_rz[1-cur]; p = z when first).
+// partials of r . z into p_rz[cur], and p = z + beta p (p = z when first):
+// beta = rho_new / rho_old from p_rz[cur] over p_rz[1-cur], or in flexible
+// CG beta = -(z . q) / (p . q) with q = A p of the direction just used.
 void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   DLevel& L0 = h->L[0];
   const int64_t n = L0.n;
   const unsigned g = h->red_np;
   const bool stage = !L0.coarsest;
+  const bool fcg = h->krylov == LSAMG_KRYLOV_FCG;
+  const double* qv = fcg && !first ? h->q : nullptr;
+  h->dir_num = fcg ? h->p_zq : h->p_rz[cur];
+  h->dir_den = fcg ? h->p_pqo : h->p_rz[1 - cur];
   if (h->precision == LSAMG_MIXED) {
     run_graph(h, 128 + 1, s, [&](hipStream_t gs) { vcycle<float>(h, 0, L0.f.b, L0.f.x, gs, false); });
-    PROF("k_cg_z<float>", 4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
+    PROF("k_cg_z<float>",
+         4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + (qv ? 24 : 16) * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<float>, n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
-                                                 L0.f.tb, h->r, h->z, h->p_rz[cur]);
+                                                 L0.f.tb, h->r, h->z, h->p_rz[cur], qv, h->p_zq);
   } else {
     run_graph(h, 1, s, [&](hipStream_t gs) { vcycle<double>(h, 0, h->r, L0.d.x, gs, false); });
-    PROF("k_cg_z<double>", 8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + 16 * n + 8 * g, s);
+    PROF("k_cg_z<double>",
+         8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + (qv ? 24 : 16) * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<double>, n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
-                                                  L0.d.tb, h->r, h->z, h->p_rz[cur]);
+                                                  L0.d.tb, h->r, h->z, h->p_rz[cur], qv, h->p_zq);
   }
   LAUNCH_OK();
   if (L0.at1_on) {                      // applied by the next cg_apply (k_cg_tile)
     h->dir_pending = first ? 1 : 2;
-    h->dir_cur = cur;
     return;
   }
   PROF("k_cg_dir", 24 * n + 16 * g, s);
-  KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_dir, n, h->p_rz[cur], first ? nullptr : h->p_rz[1 - cur],
-                                          h->z, h->p);
+  KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_dir, n, h->dir_num, first ? nullptr : h->dir_den, h->z,
+                                          h->p);
   LAUNCH_OK();
 }
 
@@ -1681,7 +1701,9 @@ int pcg_one(lsamg_handle* h, const double* b, double* x, double tol, int maxit, 
         PROF("k_cg_update", (mixed ? 60 : 56) * n + 24 * h->red_np, s);
         KLAUNCH(h->red_np, dev::kBlock, 0, s, dev::k_cg_update, n, h->p_rz[cur], h->p_pq, h->p, h->q,
                                                           h->x, h->r, mixed ? L0.f.b : nullptr,
-                                                          h->p_rr);
+                                                          h->p_rr,
+                                                          h->krylov == LSAMG_KRYLOV_FCG ? h->p_pqo
+                                                                                        : nullptr);
         LAUNCH_OK();
       }
       const int slot = 1 + (its & 1);
@@ -1786,11 +1808,13 @@ void ensure_batched(lsamg_handle* h, int NB) {
   h->Brz[0] = h->alloc<double>(kBNP * W);
   h->Brz[1] = h->alloc<double>(kBNP * W);
   h->Btmp = h->alloc<double>(kBNP * W);
+  h->Bzq = h->alloc<double>(kBNP * W);
   h->Bpq_s = h->alloc<double>(W);
   h->Brr_s = h->alloc<double>(W);
   h->Brz_s[0] = h->alloc<double>(W);
   h->Brz_s[1] = h->alloc<double>(W);
   h->Btmp_s = h->alloc<double>(W);
+  h->Bzq_s = h->alloc<double>(W);
   h->Bactive = h->alloc<int>(3 * 64);   // active, restart and new-direction flags, 64 columns
   if (!h->Bactive_host)
     HIP_OK(hipHostMalloc((void**)&h->Bactive_host, 3 * 64 * sizeof(int), hipHostMallocDefault));
@@ -1894,8 +1918,9 @@ void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
   bool done = false;
   if constexpr (NB == 64) {
     if (mm.lds) {
-      PROF(kname("k_bmm_lds", std::to_string(MODE) + ", " + (ADD ? "true" : "false")),
-           split ? bytes - sizeof(float) * (double)P.out * NB : bytes, s);
+      PROF_F(kname("k_bmm_lds", std::to_string(MODE) + ", " + (ADD ? "true" : "false")),
+             split ? bytes - sizeof(float) * (double)P.out * NB : bytes, 2.0 * (double)P.mat * NB,
+             s);
       KLAUNCH((unsigned)mm.ntask, dev::kBlock, 0, s, dev::k_bmm_lds<MODE, ADD>, mm.tk, P.op, gidx,
               cptr, cpos, tb, M, in, split ? mm.part : out, mm.part, (int64_t)P.out);
       LAUNCH_OK();
@@ -1903,10 +1928,11 @@ void bmm_launch(const GemvPlan& P, const GemvPlan::Mm& mm, const int32_t* gidx,
     }
   }
   if (!done) {
-    PROF(kname("k_bmm", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
-                            std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
-                            std::to_string(NB)),
-         split ? bytes - sizeof(float) * (double)P.out * NB : bytes, s);
+    PROF_F(kname("k_bmm", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
+                              std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
+                              std::to_string(NB)),
+           split ? bytes - sizeof(float) * (double)P.out * NB : bytes, 2.0 * (double)P.mat * NB,
+           s);
     auto launch = [&](auto kern) {
       KLAUNCH(mm.grid, dev::kBlock, 0, s, kern, mm.tk, (int)mm.ntask, P.op, gidx, cptr, cpos, tb, M,
               in, split ? mm.part : out, mm.part, (int64_t)P.out);
@@ -1951,10 +1977,10 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
   if constexpr (std::is_same<T, double>::value && NB >= 16) {
     if (P.mmd.rt > 0) {
       const GemvPlan::Mm& mm = P.mmd;
-      PROF(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
-                               std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
-                               std::to_string(NB)),
-           bytes, s);
+      PROF_F(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
+                                 std::to_string(mm.rt) + ", " + std::to_string(mm.u) + ", " +
+                                 std::to_string(NB)),
+             bytes, 2.0 * (double)P.mat * NB, s);
       auto launch = [&](auto kern) {
         KLAUNCH(mm.grid, dev::kBlock, 0, s, kern, mm.tk, (int)mm.ntask, P.op, gidx, cptr, cpos,
                 tb, M, in, out);
@@ -1973,9 +1999,9 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
       return;
     }
   }
-  PROF(kname("k_bgemm", std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
-                            (ADD ? "true" : "false") + ", " + std::to_string(NB)),
-       bytes, s);
+  PROF_F(kname("k_bgemm", std::string(tname<T>()) + ", " + std::to_string(MODE) + ", " +
+                              (ADD ? "true" : "false") + ", " + std::to_string(NB)),
+         bytes, 2.0 * (double)P.mat * NB, s);
   KLAUNCH((unsigned)P.ntask, dev::kBlock, 0, s, dev::k_bgemm<T, MODE, ADD, NB>, P.task_a,
           P.task_j0, P.op, gidx, cptr, cpos, tb, M, in, out);
   LAUNCH_OK();
@@ -2086,8 +2112,9 @@ void dense_mm_launch(const DLevel& L, int S, int kchunk, int KC, const float* in
     throw DevError{LSAMG_EINVAL, "dense-level launch: " + std::to_string(S) +
                                      " loop ranges exceed the partial-sum buffer"};
   {
-    PROF("k_dense_mm64", sizeof(float) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))),
-         s);
+    PROF_F("k_dense_mm64",
+           sizeof(float) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))),
+           2.0 * (double)n * n * 64, s);
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)S);
     if (KC == 64)
       KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64<64>, n, L.dmm_ld, kchunk,
@@ -2191,8 +2218,9 @@ void dense_mm_launch_d(const DLevel& L, int S, int kchunk, int KC, const double*
     throw DevError{LSAMG_EINVAL, "FP64 dense-level launch: " + std::to_string(S) +
                                      " loop ranges exceed the partial-sum buffer"};
   {
-    PROF("k_dense_mm64d",
-         sizeof(double) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))), s);
+    PROF_F("k_dense_mm64d",
+           sizeof(double) * ((double)n * n + (double)n * 64 * (1 + (S > 1 ? S : 1))),
+           2.0 * (double)n * n * 64, s);
     const dim3 grid((unsigned)((n + 63) / 64), (unsigned)S);
     if (KC == 32)
       KLAUNCH(grid, dev::kBlock, 0, s, dev::k_dense_mm64d<32>, n, L.dmm_ld, kchunk,
@@ -2806,36 +2834,43 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
   const int64_t n = L0.n;
   auto& B0 = h->BL[0];
   const bool stage = !L0.coarsest;
+  // flexible CG: beta_j = -(Z_j . Q_j) / (P_j . Q_j) with Q = A P of the
+  // directions just used (Bpq_s still holds P . Q from that A-apply)
+  const bool fcg = h->krylov == LSAMG_KRYLOV_FCG;
+  const double* Qv = fcg && !first ? (const double*)h->BQ : nullptr;
   if (h->precision == LSAMG_MIXED) {
     run_graph(h, 128 + NB, s,
               [&](hipStream_t gs) { bvcycle<float, NB>(h, 0, B0.fb, B0.fx, gs, false); });
     if (NB == 64) {
-      PROF("k_bcg_z64<float>", 20 * n * NB, s);
+      PROF("k_bcg_z64<float>", (Qv ? 28 : 20) * n * NB, s);
       KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z64<float>, n, (const float*)B0.fx,
               stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR,
-              h->BZ, h->Brz[cur]);
+              h->BZ, h->Brz[cur], Qv, h->Bzq);
     } else {
-      PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), 20 * n * NB, s);
+      PROF(kname("k_bcg_z", std::string("float, ") + std::to_string(NB)), (Qv ? 28 : 20) * n * NB,
+           s);
       KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
               stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
-              h->Brz[cur]);
+              h->Brz[cur], Qv, h->Bzq);
     }
   } else {
     run_graph(h, NB, s, [&](hipStream_t gs) { bvcycle<double, NB>(h, 0, h->BR, B0.x, gs, false); });
     if (NB == 64) {
-      PROF("k_bcg_z64<double>", 24 * n * NB, s);
+      PROF("k_bcg_z64<double>", (Qv ? 32 : 24) * n * NB, s);
       KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z64<double>, n, (const double*)B0.x,
               stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
-              h->BZ, h->Brz[cur]);
+              h->BZ, h->Brz[cur], Qv, h->Bzq);
     } else {
-      PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), 24 * n * NB, s);
+      PROF(kname("k_bcg_z", std::string("double, ") + std::to_string(NB)), (Qv ? 32 : 24) * n * NB,
+           s);
       KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
               stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
-              h->BZ, h->Brz[cur]);
+              h->BZ, h->Brz[cur], Qv, h->Bzq);
     }
   }
   LAUNCH_OK();
   bsum<NB>(h->Brz[cur], h->Brz_s[cur], s);
+  if (Qv) bsum<NB>(h->Bzq, h->Bzq_s, s);
   if (restart_mask) {
     PROF(kname("k_bcg_dir_mask", std::to_string(NB)), 16 * n * NB, s);
     KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir_mask<NB>, n, restart_mask,
@@ -2844,9 +2879,10 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
     return;
   }
   PROF(kname("k_bcg_dir", std::to_string(NB)), 24 * n * NB, s);
-  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, (const double*)h->Brz_s[cur],
-          first ? (const double*)nullptr : (const double*)h->Brz_s[1 - cur], (const double*)h->BZ,
-          h->BP);
+  const double* num = fcg ? h->Bzq_s : h->Brz_s[cur];
+  const double* den = fcg ? h->Bpq_s : h->Brz_s[1 - cur];
+  KLAUNCH(kBNP, dev::kBlock, 0, s, dev::k_bcg_dir<NB>, n, num, first ? (const double*)nullptr : den,
+          (const double*)h->BZ, h->BP);
   LAUNCH_OK();
 }
 
@@ -2916,7 +2952,7 @@ struct BatchCG {
       KLAUNCH0(nblocks(n0), dev::kBlock, 0, s, dev::k_fill, n0, 0.0, v);
       LAUNCH_OK();
     }
-    for (double* v : {h->Brz_s[0], h->Brz_s[1]}) {
+    for (double* v : {h->Brz_s[0], h->Brz_s[1], h->Bpq_s, h->Bzq_s}) {
       KLAUNCH0(1, dev::kBlock, 0, s, dev::k_fill, (int64_t)NB, 0.0, v);
       LAUNCH_OK();
     }
@@ -3001,10 +3037,10 @@ struct BatchCG {
     int nrst = 0;
     for (int j = 0; j < NB; ++j) nrst += rst[j];
     if (nrst > 0) {
-      // r = b - A x on the restarted columns (A x is in BQ from the true-residual
+      // r = b - A x on the restarted columns (A x is in BZ from the true-residual
       // test of the last step); rho_old = 0 there
       KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_restart<NB>, n(), (const int*)(h->Bactive + 64),
-               (const double*)h->BBi, (const double*)h->BQ, h->BR,
+               (const double*)h->BBi, (const double*)h->BZ, h->BR,
                mixed ? h->BL[0].fb : (float*)nullptr, h->Brz_s[cur]);
       LAUNCH_OK();
     }
@@ -3012,9 +3048,9 @@ struct BatchCG {
       // the other columns' next direction is formed; redo Z for the new ones
       if (nnew > 0) bcg_precondition<NB>(h, s, false, 1 - cur, h->Bactive + 128);
     } else {
-      if (nnew > 0) {
+      if (nnew > 0) {           // beta = 0 there: zero rho_old (CG) or p . q (flexible CG)
         KLAUNCH0(1, dev::kBlock, 0, s, dev::k_bzero_masked<NB>, (const int*)(h->Bactive + 128),
-                 h->Brz_s[cur]);
+                 h->krylov == LSAMG_KRYLOV_FCG ? h->Bpq_s : h->Brz_s[cur]);
         LAUNCH_OK();
       }
       bcg_precondition<NB>(h, s, false, 1 - cur);
@@ -3066,10 +3102,12 @@ struct BatchCG {
     }
     int nfin = 0;
     if (ntest > 0) {
-      // true residuals b - A x of the whole block (one batched A-apply)
-      bcg_apply<NB>(h, h->BX, h->BQ, h->Btmp, h->Btmp_s, s);
+      // true residuals b - A x of the whole block (one batched A-apply into
+      // BZ: Z is spent once the directions are formed, and BQ = A P stays
+      // for flexible CG's next beta)
+      bcg_apply<NB>(h, h->BX, h->BZ, h->Btmp, h->Btmp_s, s);
       KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, nn, (const double*)h->BBi,
-               (const double*)h->BQ, h->Btmp);
+               (const double*)h->BZ, h->Btmp);
       LAUNCH_OK();
       bsum<NB>(h->Btmp, h->Btmp_s, s);
       bparts_to_host(h, h->Btmp_s, NB, 0, s);
@@ -3172,12 +3210,12 @@ void bapply_vcycle(lsamg_handle* h, const double* X, double* Y, int nr, int64_t 
     bvcycle<float, NB>(h, 0, B0.fb, B0.fx, s, false);
     KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<float, NB>, n, (const float*)B0.fx,
              stage ? L0.cptr : nullptr, L0.cpos, (const float*)B0.ftb, (const double*)h->BR, h->BZ,
-             h->Btmp);
+             h->Btmp, (const double*)nullptr, (double*)nullptr);
   } else {
     bvcycle<double, NB>(h, 0, h->BR, B0.x, s, false);
     KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bcg_z<double, NB>, n, (const double*)B0.x,
              stage ? L0.cptr : nullptr, L0.cpos, (const double*)B0.tb, (const double*)h->BR,
-             h->BZ, h->Btmp);
+             h->BZ, h->Btmp, (const double*)nullptr, (double*)nullptr);
   }
   LAUNCH_OK();
   KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
@@ -3470,6 +3508,8 @@ int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
     h->drop_graphs(true);               // captured batched V-cycles name the old kernels
   } else if (opt == LSAMG_OPT_GRAPH) {
     h->use_graphs = value != 0;
+  } else if (opt == LSAMG_OPT_KRYLOV) {
+    h->krylov = (int)value;
   } else if (opt == LSAMG_OPT_ONEPASS_ATA) {
     for (auto& D : h->L) D.fuse_ata = value != 0 && D.fuse_ok;
     h->drop_graphs(true);
@@ -3561,6 +3601,7 @@ int lsamg_profile_read(lsamg_handle* h, lsamg_kprof* out, int32_t cap, int32_t* 
       acc[i].launches += 1;
       acc[i].ms += ms;
       acc[i].bytes += r.bytes;
+      acc[i].flops += r.flops;
     }
     P.recs.clear();
     P.used = 0;
@@ -3737,8 +3778,8 @@ size_t batched_reserve(const lsamg_handle* h, int NB) {
     }
     const int64_t n0 = h->L[0].n * W;
     for (int k = 0; k < 6; ++k) add(n0, 8);
-    for (int k = 0; k < 5; ++k) add(kBNP * W, 8);
-    for (int k = 0; k < 5; ++k) add(W, 8);
+    for (int k = 0; k < 6; ++k) add(kBNP * W, 8);
+    for (int k = 0; k < 6; ++k) add(W, 8);
     add(192, 4);
   }
   // the autotuners run on the first FP32 solve of >= 16 columns (and again
@@ -3797,9 +3838,11 @@ struct lsamg_server {
   }
 
   // post a completion (lock held)
-  void post(const SReq& q, int status, int its, double trr, double t_solve) {
+  void post(const SReq& q, int status, int its, double trr, double t_solve,
+            const std::string& msg = std::string()) {
     lsamg_done d;
     std::memset(&d, 0, sizeof(d));
+    std::snprintf(d.msg, sizeof(d.msg), "%s", msg.c_str());
     d.id = q.r.id;
     d.status = status;
     d.cache_hit = q.hit;
@@ -3988,9 +4031,8 @@ void lsamg_server::session(std::unique_lock<std::mutex>& lk, uint64_t key, SReq 
   lk.lock();
   if (rc != LSAMG_OK) {                  // every request still in the solve fails with it
     for (auto& up : live)
-      if (!up->posted) post(*up, rc, 0, 0, now_s() - up->t_taken);
+      if (!up->posted) post(*up, rc, 0, 0, now_s() - up->t_taken, msg);
   }
-  (void)msg;
 }
 
 void lsamg_server::worker() {
@@ -4027,7 +4069,7 @@ void lsamg_server::worker() {
     ++active;
     first.t_taken = now_s();
     if (!miss && cache[key].failed) {
-      post(first, cache[key].err, 0, 0, 0);
+      post(first, cache[key].err, 0, 0, 0, cache[key].msg);
       --active;
       cv_work.notify_all();
       continue;
@@ -4084,7 +4126,7 @@ void lsamg_server::worker() {
         e->err = rc;
         e->msg = msg;
         first.t_setup = now_s() - first.t_taken;
-        post(first, rc, 0, 0, 0);
+        post(first, rc, 0, 0, 0, msg);
         --active;
         cv_work.notify_all();
         continue;
@@ -4126,7 +4168,7 @@ void lsamg_server::worker() {
     if (!fits) {
       e->busy = false;
       e->last_use = ++tick;
-      post(first, LSAMG_ENOMEM, 0, 0, 0);
+      post(first, LSAMG_ENOMEM, 0, 0, 0, "the solve's device memory does not fit the budget");
       --active;
       cv_work.notify_all();
       continue;
@@ -4152,7 +4194,7 @@ void lsamg_server::worker() {
         account(0, reserve);
         e = &cache[key];
         e->busy = false;
-        post(first, LSAMG_ENOMEM, 0, 0, 0);
+        post(first, LSAMG_ENOMEM, 0, 0, 0, "staging allocation failed");
         --active;
         cv_work.notify_all();
         continue;

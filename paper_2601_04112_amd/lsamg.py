@@ -22,7 +22,8 @@ FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
 AGG_LATTICE, AGG_STANDARD = 0, 1
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
-OPT_ATA_TILES, OPT_BGROUP = 6, 7
+OPT_ATA_TILES, OPT_BGROUP, OPT_KRYLOV = 6, 7, 8
+KRYLOV_CG, KRYLOV_FCG = 0, 1
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
                -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
@@ -94,7 +95,7 @@ class SetupView(C.Structure):
 
 class KProf(C.Structure):
     _fields_ = [("name", C.c_char * 80), ("launches", C.c_int64),
-                ("ms", C.c_double), ("bytes", C.c_double)]
+                ("ms", C.c_double), ("bytes", C.c_double), ("flops", C.c_double)]
 
 
 class Request(C.Structure):
@@ -110,7 +111,7 @@ class Done(C.Structure):
                 ("true_rel_res_max", C.c_double), ("t_queue", C.c_double),
                 ("t_setup", C.c_double), ("t_solve", C.c_double),
                 ("t_total", C.c_double), ("joined_at", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("msg", C.c_char * 96)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -343,7 +344,8 @@ class Solver:
         (0 off, 1 per precision, 2 row form, 3 expanded form), OPT_MFMA_TILE
         (0: autotune, else 100*rt + 10*u + split) or OPT_DENSE_SPLIT (0: autotune,
         1..16: LDS-staged dense GEMM with that many loop ranges, 17: never) or OPT_BGROUP
-        (0: autotune, 1: row-group pass, 2: CSR passes)."""
+        (0: autotune, 1: row-group pass, 2: CSR passes) or OPT_KRYLOV (KRYLOV_CG or
+        KRYLOV_FCG: flexible CG)."""
         _check(load().lsamg_set_option(self._h, opt, int(value)))
 
     # -- kernel timing ----------------------------------------------------
@@ -360,7 +362,8 @@ class Solver:
         cnt = C.c_int32()
         _check(load().lsamg_profile_read(self._h, buf, 256, C.byref(cnt)))
         return [dict(name=buf[i].name.decode(), launches=buf[i].launches,
-                     ms=buf[i].ms, bytes=buf[i].bytes) for i in range(cnt.value)]
+                     ms=buf[i].ms, bytes=buf[i].bytes, flops=buf[i].flops)
+                for i in range(cnt.value)]
 
     # -- introspection ----------------------------------------------------
     def info(self) -> dict:
@@ -465,6 +468,7 @@ class Server:
         out = []
         for i in range(cnt.value):
             d = buf[i].as_dict()
+            d["msg"] = d["msg"].decode(errors="replace")
             bb, x, _ = self._live.pop(d["id"])
             d["x"] = x
             out.append(d)

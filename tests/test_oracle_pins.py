@@ -379,3 +379,19 @@ def test_row_compression_is_exact():
     v = np.random.default_rng(5).standard_normal(p.n)
     y1, y2 = O.vcycle(H1, v), O.vcycle(H2, v)
     assert np.linalg.norm(y1 - y2) <= 1e-12 * np.linalg.norm(y1)
+
+
+def test_flexible_cg_equals_cg_with_symmetric_preconditioner(rot):
+    """With the (symmetric, fixed) V-cycle, flexible CG's A-orthogonalised
+    direction beta = -(z_{k+1}.q_k)/(p_k.q_k) equals the standard
+    beta = rho_{k+1}/rho_k in exact arithmetic, so both give the same iterates
+    (to 1e-10 after 12 iterations) and reach 1e-8 at the same count; a sign
+    error in either beta would part them after the first iteration."""
+    p, H = rot
+    b = P.rhs_uniform(p.n, 3)
+    x1, i1 = O.pcg(H, b, fixed_iters=12)
+    x2, i2 = O.pcg(H, b, fixed_iters=12, flexible=True)
+    assert np.linalg.norm(x2 - x1) <= 1e-10 * np.linalg.norm(x1)
+    _, c1 = O.pcg(H, b, tol=1e-8)
+    _, c2 = O.pcg(H, b, tol=1e-8, flexible=True)
+    assert c1["converged"] and c2["converged"] and abs(c1["iters"] - c2["iters"]) <= 1
