@@ -393,9 +393,13 @@ const char* lsamg_last_error(void);
  * hand-side PCG on that operator, 8 to 64 columns wide, with the queued
  * requests for it that fit.  At every PCG iteration boundary requests for the
  * operator that arrived meanwhile enter free columns and start their own CG
- * there (their own tolerance and iteration limit), and a request is reported
- * as soon as its last column converges, freeing its columns; the solve ends
- * when no column is active and no queued request for the operator fits.  A
+ * there (their own tolerance and iteration limit), first come first served
+ * (a request waiting for columns is not overtaken by a narrower later one),
+ * and a request is reported as soon as its last column converges, freeing
+ * its columns; the solve ends when no column is active and no queued request
+ * for the operator fits.  When the columns waiting for the operator amount
+ * to a full batch of the running width, that solve takes no more requests
+ * and drains, so the next one starts wider (up to 64 columns).  A
  * request for a new operator builds its hierarchy on the host while the
  * other slots keep the GPU busy, and is admitted when its exact device
  * footprint fits hbm_budget; each solve is then admitted with an upper bound

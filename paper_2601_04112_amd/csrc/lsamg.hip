@@ -3900,7 +3900,8 @@ struct lsamg_server {
 // it runs are loaded into free columns at the next iteration boundary and
 // start their own CG there; each request is reported as soon as its last
 // column finishes, and its columns take new requests.  The solve ends when
-// no column is active and no queued request for the operator fits.
+// no column is active and no queued request for the operator fits (or it
+// drains for a wider solve, see admit).
 template <int NB>
 void lsamg_server::session(std::unique_lock<std::mutex>& lk, uint64_t key, SReq first,
                            hipStream_t st, double*& stage, size_t& stage_cap) {
@@ -3929,19 +3930,31 @@ void lsamg_server::session(std::unique_lock<std::mutex>& lk, uint64_t key, SReq 
     p->t_taken = now_s();
     return p;
   };
-  // queued requests for this operator that fit the free columns (lock held)
+  // queued requests for this operator, first come first served, while they
+  // fit the free columns (a request that does not fit stops the scan, so
+  // narrower later ones cannot starve it).  When the columns still waiting
+  // amount to a full batch of this width, the solve stops taking requests
+  // and drains: the next solve on the operator starts at the width the
+  // queue then asks for (lock held)
+  bool draining = false;
   auto admit = [&](std::vector<SReq*>& fresh) {
+    if (draining) return;
+    int waiting = 0;
     for (size_t i = 0; i < queue.size();) {
-      if (queue[i].r.op_key == key && queue[i].r.nrhs <= free_cols() && queue[i].n == n) {
+      if (queue[i].r.op_key != key || queue[i].n != n) {
+        ++i;
+      } else if (waiting == 0 && queue[i].r.nrhs <= free_cols()) {
         SReq* p = take(std::move(queue[i]));
         p->hit = 1;
         if (iter > 0) ++joins;
         fresh.push_back(p);
         queue.erase(queue.begin() + i);
       } else {
+        waiting += queue[i].r.nrhs;
         ++i;
       }
     }
+    if (NB < 64 && waiting >= NB) draining = true;
   };
   std::vector<SReq*> fresh;
   fresh.push_back(take(std::move(first)));

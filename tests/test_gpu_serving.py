@@ -136,6 +136,63 @@ def test_join_running_solve(gpu_device):
     assert st["joins"] >= 3 and st["misses"] == 1
 
 
+def _start_long(srv, p, nr=2):
+    """a request that cannot converge (tol 1e-15) and keeps its solve running
+    for 200 iterations; returns its id once that solve is iterating"""
+    import time
+    b = np.stack([P.rhs_uniform(p.n, 70 + j) for j in range(nr)])
+    rid = srv.submit(0, p.G, 2, p.grid, b, tol=1e-15, maxit=200, cmin=(2,), max_coarse=200)
+    t0 = time.time()
+    while srv.stats()["iterations"] < 5:
+        assert time.time() - t0 < 60
+        time.sleep(0.002)
+    return rid
+
+
+def test_admission_first_come_first_served(gpu_device):
+    """Requests enter a running solve in arrival order: with 6 of its 8
+    columns free, a 5-column request joins, a 4-column one then waits for
+    columns, and a 1-column request behind it (which would fit the last free
+    column at once) must not overtake it."""
+    p = op(0)
+    srv = L.Server(hbm_budget=8 << 30, max_slots=1)
+    r_long = _start_long(srv, p)
+    bs = [np.stack([P.rhs_uniform(p.n, 80 + 10 * i + j) for j in range(nr)])
+          for i, nr in enumerate((5, 4, 1))]
+    ids = [srv.submit(0, p.G, 2, p.grid, b, tol=1e-8, cmin=(2,), max_coarse=200) for b in bs]
+    res = drain(srv, 4)
+    srv.close()
+    assert res[r_long]["status"] == L.LSAMG_ENOCONV
+    for rid, b in zip(ids, bs):
+        assert res[rid]["status"] == 0
+        check(p, b, res[rid]["x"], 1e-8)
+    a, b4, c1 = (res[r] for r in ids)
+    assert a["joined_at"] > 0 and b4["joined_at"] > a["joined_at"]
+    assert c1["joined_at"] >= b4["joined_at"], (b4["joined_at"], c1["joined_at"])
+
+
+def test_waiting_batch_widens_the_next_solve(gpu_device):
+    """When the columns waiting for an operator fill a whole batch of the
+    running width, that solve takes no more requests: of three 4-column
+    requests arriving at an 8-column solve with 6 free columns, the first
+    joins it, and the other two start together in the next solve (joined at
+    its first iteration) instead of trickling into the narrow one."""
+    p = op(0)
+    srv = L.Server(hbm_budget=8 << 30, max_slots=1)
+    r_long = _start_long(srv, p)
+    bs = [np.stack([P.rhs_uniform(p.n, 120 + 10 * i + j) for j in range(4)]) for i in range(3)]
+    ids = [srv.submit(0, p.G, 2, p.grid, b, tol=1e-8, cmin=(2,), max_coarse=200) for b in bs]
+    res = drain(srv, 4)
+    srv.close()
+    assert res[r_long]["status"] == L.LSAMG_ENOCONV and res[r_long]["iters_max"] == 200
+    for rid, b in zip(ids, bs):
+        assert res[rid]["status"] == 0 and res[rid]["cache_hit"] == 1
+        check(p, b, res[rid]["x"], 1e-8)
+    assert res[ids[0]]["joined_at"] > 0
+    assert res[ids[1]]["joined_at"] == 0 and res[ids[2]]["joined_at"] == 0
+    assert res[ids[1]]["batch_rhs"] == 8 and res[ids[2]]["batch_rhs"] == 8
+
+
 def test_budget_admission_and_eviction(gpu_device):
     probs = [op(k) for k in range(3)]
     # size the budget for about one hierarchy
