@@ -143,11 +143,14 @@ def percentile(v, q):
 
 
 def run_serving(args):
-    """Request stream: Poisson arrivals at args.qps, operators drawn from a
-    seeded pool of args.pool distinct 2D problems (N in {64,...,1024}, theta
-    ~ U[0, pi), log10 eps ~ U[-6, 0]), 1-8 right-hand sides each, FP32
-    V-cycle under FP64 CG to 1e-8.  Hierarchies stay resident (HBM budget
-    args.budget_gb) and requests for a busy or resident operator are merged."""
+    """Request stream: Poisson arrivals at each rate of args.qps, operators
+    drawn from a seeded pool of args.pool distinct 2D problems (N in
+    {64,...,1024}, theta ~ U[0, pi), log10 eps ~ U[-6, 0]), 1-8 right-hand
+    sides each, FP32 V-cycle under FP64 CG to 1e-8.  Hierarchies stay
+    resident (HBM budget args.budget_gb); a request for an operator whose
+    solve is running joins it at the next PCG iteration boundary.  With
+    several rates the same server (and its resident hierarchies) serves one
+    stream per rate, one after another."""
     import numpy as np
     import problems as P
     from paper_2601_04112_amd import lsamg as L
@@ -158,19 +161,15 @@ def run_serving(args):
     for k in range(args.pool):
         N = int(rng.choice(sizes))
         pool.append((N, float(rng.uniform(0, math.pi)), float(10 ** rng.uniform(-6, 0))))
-    reqs = []
-    t = 0.0
-    for i in range(args.requests):
-        t += float(rng.exponential(1.0 / args.qps))
-        reqs.append((t, int(rng.integers(args.pool)), int(rng.integers(1, 9)), 10000 + 8 * i))
     probs = {}
     srv = L.Server(hbm_budget=int(args.budget_gb * (1 << 30)), max_slots=args.slots)
     t_warm = 0.0
+    warm = []
     if args.prewarm:
         # steady state: one request per pool operator first, so every hierarchy
         # is resident before the clock starts (their setup is reported apart);
         # it carries --prewarm-rhs columns, so the multi-right-hand-side
-        # buffers of the width the merged requests use are allocated and their
+        # buffers of the widths the solves use are allocated and their
         # matrix-core shapes tuned before the clock starts too
         tw = time.perf_counter()
         for k in range(args.pool):
@@ -179,58 +178,93 @@ def run_serving(args):
             srv.submit(k, probs[k].G, 2, probs[k].grid, bw,
                        tol=1e-8, precision=L.MIXED, req_id=10 ** 6 + k, cmin=(2,))
         got = 0
+        warm = []
         while got < args.pool:
-            got += len(srv.poll(wait_ms=1000))
-            print(f"[serve] prewarm {got}/{args.pool}", file=sys.stderr, flush=True)
+            ds = srv.poll(wait_ms=1000)
+            got += len(ds)
+            for d in ds:
+                k = d["id"] - 10 ** 6
+                warm.append(dict(N=pool[k][0], setup_s=round(d["t_setup"], 1), status=d["status"]))
+                print(f"[serve] prewarm {got}/{args.pool}: N={pool[k][0]} setup "
+                      f"{d['t_setup']:.1f} s status {d['status']} {d['msg']}",
+                      file=sys.stderr, flush=True)
         t_warm = time.perf_counter() - tw
-    done = {}
-    t0 = time.perf_counter()
-    t_report = t0
-    i = 0
-    while len(done) < len(reqs):
-        now = time.perf_counter() - t0
-        while i < len(reqs) and reqs[i][0] <= now:
-            _, k, nr, seed = reqs[i]
-            if k not in probs:
-                probs[k] = P.aniso2d(*pool[k])
-            p = probs[k]
-            b = np.stack([P.rhs_uniform(p.n, seed + j) for j in range(nr)])
-            srv.submit(k, p.G, 2, p.grid, b, tol=1e-8, precision=L.MIXED, req_id=i,
-                       cmin=(2,))
-            i += 1
-        wait = 5 if i >= len(reqs) else max(0, int((reqs[i][0] - now) * 1e3))
-        for d in srv.poll(wait_ms=min(wait, 20)):
-            d.pop("x")
-            done[d["id"]] = d
-        if time.perf_counter() - t_report > 5.0:
-            t_report = time.perf_counter()
-            print(f"[serve] t={t_report - t0:.0f}s submitted {i}/{len(reqs)} "
-                  f"done {len(done)}", file=sys.stderr, flush=True)
-    makespan = time.perf_counter() - t0
+    sweep = []
+    next_id = 0
+    for qps in [float(q) for q in str(args.qps).split(",")]:
+        rq = np.random.default_rng(int(5 + 1000 * qps))
+        reqs = []
+        t = 0.0
+        for i in range(args.requests):
+            t += float(rq.exponential(1.0 / qps))
+            reqs.append((t, int(rq.integers(args.pool)), int(rq.integers(1, 9)), 10000 + 8 * i))
+        st0 = srv.stats()
+        done = {}
+        t0 = time.perf_counter()
+        t_report = t0
+        i = 0
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i][0] <= now:
+                _, k, nr, seed = reqs[i]
+                if k not in probs:
+                    probs[k] = P.aniso2d(*pool[k])
+                p = probs[k]
+                b = np.stack([P.rhs_uniform(p.n, seed + j) for j in range(nr)])
+                srv.submit(k, p.G, 2, p.grid, b, tol=1e-8, precision=L.MIXED,
+                           req_id=next_id + i, cmin=(2,))
+                i += 1
+            wait = 5 if i >= len(reqs) else max(0, int((reqs[i][0] - now) * 1e3))
+            for d in srv.poll(wait_ms=min(wait, 20)):
+                d.pop("x")
+                done[d["id"]] = d
+            if time.perf_counter() - t_report > 5.0:
+                t_report = time.perf_counter()
+                print(f"[serve] qps {qps:g} t={t_report - t0:.0f}s submitted {i}/{len(reqs)} "
+                      f"done {len(done)}", file=sys.stderr, flush=True)
+        makespan = time.perf_counter() - t0
+        next_id += len(reqs)
+        st = srv.stats()
+        lat = [d["t_total"] * 1e3 for d in done.values()]
+        hit_lat = [d["t_total"] * 1e3 for d in done.values() if d["cache_hit"]]
+        solve_lat = [(d["t_queue"] + d["t_solve"]) * 1e3 for d in done.values()]
+        nrhs_total = sum(r[2] for r in reqs)
+        ok = sum(1 for d in done.values() if d["status"] == 0)
+        status_counts = {}
+        errors = {}
+        for d in done.values():
+            status_counts[str(d["status"])] = status_counts.get(str(d["status"]), 0) + 1
+            if d["status"] != 0 and d["msg"]:
+                errors[d["msg"]] = errors.get(d["msg"], 0) + 1
+        sweep.append({
+            "qps": qps, "value": round(nrhs_total / makespan, 2), "unit": "solves/s",
+            "requests": len(reqs), "rhs_total": nrhs_total, "makespan_s": round(makespan, 2),
+            "ok": ok, "status_counts": status_counts, "errors": errors,
+            "p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
+            "p50_ms_hit": round(percentile(hit_lat, 0.5), 2) if hit_lat else None,
+            "p99_ms_hit": round(percentile(hit_lat, 0.99), 2) if hit_lat else None,
+            "p50_ms_excl_setup": round(percentile(solve_lat, 0.5), 2),
+            "p99_ms_excl_setup": round(percentile(solve_lat, 0.99), 2),
+            "joined_running_solve": sum(1 for d in done.values() if d["joined_at"] > 0),
+            "max_true_rel_res": max(d["true_rel_res_max"] for d in done.values()),
+            "max_batch_rhs": max(d["batch_rhs"] for d in done.values()),
+            "misses": st["misses"] - st0["misses"], "evictions": st["evictions"] - st0["evictions"],
+            "pcg_iterations": st["iterations"] - st0["iterations"],
+            "setup_s_total": round(sum(d["t_setup"] for d in done.values()), 1)})
+        print(f"[serve] qps {qps:g}: {sweep[-1]['value']} solves/s, p50 {sweep[-1]['p50_ms']} ms, "
+              f"p99 {sweep[-1]['p99_ms']} ms", file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
-    lat = [d["t_total"] * 1e3 for d in done.values()]
-    hit_lat = [d["t_total"] * 1e3 for d in done.values() if d["cache_hit"]]
-    solve_lat = [(d["t_queue"] + d["t_solve"]) * 1e3 for d in done.values()]
-    nrhs_total = sum(r[2] for r in reqs)
-    ok = sum(1 for d in done.values() if d["status"] == 0)
+    head = sweep[0]
     line = {
         "metric": "serving: solves/s and p50/p99 latency, 1e-8 rel. residual",
-        "value": round(nrhs_total / makespan, 2), "unit": "solves/s",
-        "requests": len(reqs), "rhs_total": nrhs_total, "qps": args.qps,
-        "makespan_s": round(makespan, 2), "ok": ok,
-        "p50_ms": round(percentile(lat, 0.5), 2), "p99_ms": round(percentile(lat, 0.99), 2),
-        "p50_ms_hit": round(percentile(hit_lat, 0.5), 2) if hit_lat else None,
-        "p99_ms_hit": round(percentile(hit_lat, 0.99), 2) if hit_lat else None,
-        "p50_ms_excl_setup": round(percentile(solve_lat, 0.5), 2),
-        "p99_ms_excl_setup": round(percentile(solve_lat, 0.99), 2),
-        "max_true_rel_res": max(d["true_rel_res_max"] for d in done.values()),
-        "max_batch_rhs": max(d["batch_rhs"] for d in done.values()),
-        "setup_s_total": round(sum(d["t_setup"] for d in done.values()), 1),
+        "value": head["value"], "unit": "solves/s", "qps": head["qps"],
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "sweep": sweep,
         "server": st, "pool": args.pool, "slots": args.slots,
         "prewarm_s": round(t_warm, 1) if args.prewarm else None,
+        "prewarm": warm if args.prewarm else None,
         "dtype": "f32 V-cycle / f64 CG", "data": "synthetic",
-        "config": {"workload": f"{len(reqs)} Poisson requests at {args.qps}/s over a pool of "
+        "config": {"workload": f"{args.requests} Poisson requests per rate over a pool of "
                                f"{args.pool} aniso2d operators, N in {sizes}, theta~U[0,pi), "
                                f"log10 eps~U[-6,0], 1-8 rhs"
                                + (f", hierarchies resident and tuned ({args.prewarm_rhs}-column "
@@ -257,19 +291,23 @@ def main():
                     help="right-hand sides of the batched workload (0: skip)")
     ap.add_argument("--serve", action="store_true",
                     help="run the request-stream serving benchmark instead")
-    ap.add_argument("--qps", type=float, default=50.0)
+    ap.add_argument("--qps", default="50",
+                    help="serving: request rate(s) per second, comma-separated for a sweep")
     ap.add_argument("--requests", type=int, default=1024)
     ap.add_argument("--pool", type=int, default=16)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gb", type=float, default=160.0)
     ap.add_argument("--prewarm", action="store_true",
                     help="serving: make every pool operator resident before timing")
-    ap.add_argument("--prewarm-rhs", type=int, default=32,
+    ap.add_argument("--prewarm-rhs", type=int, default=64,
                     help="serving: right-hand sides of each operator's prewarm request")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the solves, negate a float32 buffer of this many MiB "
                          "into another (a plain streaming kernel of known bytes, the "
                          "reference for hardware byte counters)")
+    ap.add_argument("--cmin", default="2",
+                    help="aniso2d: minimum coarsening ratio per level (LS_{a,b,...} of "
+                         "sec. 3.4), comma-separated, the last repeats")
     ap.add_argument("--maxit", type=int, default=0,
                     help="PCG iteration cap (default 1000; 200 for ls3d)")
     args = ap.parse_args()
@@ -297,6 +335,9 @@ def main():
     # CPU oracle baseline: its setup runs in a child process while the GPU
     # part runs; its timed solves run after the GPU part (BLAS on every core
     # the host gives it)
+    cmin = tuple(int(c) for c in str(args.cmin).split(","))
+    if cmin != (2,):
+        args.no_cpu_baseline = True         # the oracle baseline runs the default schedule
     cpu_proc = None
     if not args.no_cpu_baseline:
         cpu_proc = subprocess.Popen(cpu_baseline_cmd(args.N, args.cpu_reps),
@@ -316,7 +357,7 @@ def main():
         seed = P.CONFIG_RHS_SEED[3]
     else:
         prob = P.config2(args.N)
-        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=(2,))
+        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin)
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
@@ -421,6 +462,20 @@ def main():
                 mfma = dict(kernel=r["name"], n=nt, nrhs=args.batch, avg_launch_us=round(us, 2),
                             achieved=round(tf, 2), peak=peak, unit="TFLOP/s",
                             frac=round(tf / peak, 4))
+        # matrix-core rate of the aggregate-block products on levels 1-2
+        # (RAS, P^T, P, RAS-T as per-aggregate GEMMs of 64 columns)
+        mfma_levels = []
+        for r in bkl:
+            nm = r["name"]
+            if (r["flops"] > 0 and r["launches"] and (" @L1" in nm or " @L2" in nm)
+                    and nm.split("<")[0] in ("k_bmm", "k_bmm_lds", "k_bmmd", "k_bgemm")):
+                us = r["ms"] / r["launches"] * 1e3
+                tf = r["flops"] / (r["ms"] * 1e-3) / 1e12
+                mfma_levels.append(dict(kernel=nm, avg_launch_us=round(us, 2),
+                                        gflop_per_launch=round(r["flops"] / r["launches"] / 1e9, 3),
+                                        achieved=round(tf, 2), peak=peak, unit="TFLOP/s",
+                                        frac=round(tf / peak, 4),
+                                        gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1)))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for _ in range(steps):
@@ -433,7 +488,7 @@ def main():
                     iters_min=min(its), iters_max=max(its),
                     all_converged=all(r["converged"] for r in bst),
                     max_true_rel_res=max(r["true_rel_res"] for r in bst),
-                    mfma_dense=mfma,
+                    mfma_dense=mfma, mfma_levels_1_2=mfma_levels,
                     top_kernels=[dict(name=r["name"], ms_per_batch=round(r["ms"], 3),
                                       launches=r["launches"],
                                       gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1))
@@ -533,7 +588,7 @@ def main():
                          f"c_min=3,4, coarsest<2000" if three_d else
                          f"aniso2d N={args.N} theta=pi/6 eps=1e-4 (n={prob.n}, "
                          f"m={prob.m}), rhs uniform[-1,1] seed {seed}, tol 1e-8, "
-                         f"4x4 aggregates, c_min=2, coarsest<2000"),
+                         f"4x4 aggregates, c_min={args.cmin}, coarsest<2000"),
             "levels": inf["nlevels"],
             "n_per_level": [l["n"] for l in inf["levels"]],
             "op_complexity": round(inf["op_complexity"], 3),
