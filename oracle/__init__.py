@@ -18,7 +18,9 @@ convergence factors of the large configurations, which are parity unpinned
 (the paper's printed factors are for a different aggregation).
 """
 from .lsamg import (Params, Level, Hierarchy, setup, vcycle, pcg, ras, ras_t,
-                    apply_A, dense_preconditioner, stats, AssembledVcycle)
+                    apply_A, dense_preconditioner, stats, AssembledVcycle,
+                    additive_schwarz, acycle)
 
 __all__ = ["Params", "Level", "Hierarchy", "setup", "vcycle", "pcg", "ras",
-           "ras_t", "apply_A", "dense_preconditioner", "stats", "AssembledVcycle"]
+           "ras_t", "apply_A", "dense_preconditioner", "stats", "AssembledVcycle",
+           "additive_schwarz", "acycle"]

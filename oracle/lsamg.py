@@ -609,6 +609,29 @@ def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
     return x + ras_t(L, r)
 
 
+def additive_schwarz(L: Level, r: np.ndarray) -> np.ndarray:
+    """``sum_i R_i^T A_i^{-1} R_i r``: eq:ras without the partition of unity,
+    the smoother M_1^{-1} of the additive two-level method (sec. 3.1.1)."""
+    out = np.zeros_like(r)
+    for i in range(L.n_agg):
+        Om = L.Omega[i]
+        out[Om] += sla.cho_solve(L.chol[i], r[Om])
+    return out
+
+
+def acycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
+    """The additive method of sec. 3.1.1, ``(P (P^T A P)^{-1} P^T + M_1^{-1})
+    b`` with M_1^{-1} the additive Schwarz smoother, made multilevel by
+    applying the same form to the coarse operator P^T A P = G_{l+1}^T
+    G_{l+1} instead of inverting it (exact at the coarsest level).  Every
+    term is symmetric positive semi-definite, so the cycle is a symmetric
+    preconditioner for CG."""
+    L = H.levels[level]
+    if L.coarsest:
+        return sla.cho_solve(L.chol_coarse, b)
+    return additive_schwarz(L, b) + L.P @ acycle(H, L.P.T @ b, level + 1)
+
+
 def pcg(H: Hierarchy, b: np.ndarray, tol: float = 1e-8, maxit: int = 500,
         fixed_iters: Optional[int] = None,
         precond: Optional[Callable] = None, flexible: bool = False):

@@ -298,6 +298,46 @@ def test_additive_two_level_upper_bound():
     ev = np.linalg.eigvals(M2 @ A).real
     assert ev.max() <= L.n_color + 1 + 1e-8
     assert ev.min() > 0
+    # the oracle's additive cycle on two levels is this M_2 (exact coarse
+    # solve), and its smoother this additive Schwarz sum
+    v = P.rhs_uniform(n, 6)
+    assert np.linalg.norm(O.additive_schwarz(L, v) - AS @ v) <= 1e-12 * np.linalg.norm(AS @ v)
+    assert np.linalg.norm(O.acycle(H, v) - M2 @ v) <= 1e-11 * np.linalg.norm(M2 @ v)
+
+
+def test_additive_cycle_multilevel(rot):
+    """The multilevel additive cycle is the recursion B_l = M_{1,l}^{-1} +
+    P_l B_{l+1} P_l^T with B_L = A_L^{-1}, written out here with dense
+    matrices (inverted local blocks, explicit P_l) from the finest level
+    down; it is symmetric and positive definite, its spectrum against A is
+    bounded above by the two-level bound's k_c + 1 summed over the levels
+    (each term is an A-bounded projection sum), and PCG with it reaches
+    1e-8 on the true residual.  A dropped coarse term, a transposed P or the
+    RAS partition of unity in the smoother fails one of these."""
+    p, H = rot
+    Bd = np.linalg.inv(H.levels[-1].A.toarray())
+    bound = 1.0
+    for L in reversed(H.levels[:-1]):
+        A = L.A.toarray()
+        AS = np.zeros_like(A)
+        for i in range(L.n_agg):
+            Om = L.Omega[i]
+            AS[np.ix_(Om, Om)] += np.linalg.inv(A[np.ix_(Om, Om)])
+        Pd = L.P.toarray()
+        Bd = AS + Pd @ Bd @ Pd.T
+        bound += L.n_color
+    v = P.rhs_uniform(p.n, 7)
+    y = O.acycle(H, v)
+    assert np.linalg.norm(y - Bd @ v) <= 1e-11 * np.linalg.norm(Bd @ v)
+    w = P.rhs_uniform(p.n, 8)
+    assert abs(w @ O.acycle(H, v) - v @ O.acycle(H, w)) <= 1e-12 * np.linalg.norm(v) * np.linalg.norm(y) * 10
+    A0 = H.levels[0].A.toarray()
+    ev = np.linalg.eigvals(Bd @ A0).real
+    assert ev.min() > 0 and ev.max() <= bound + 1e-8
+    b = P.rhs_uniform(p.n, 9)
+    x, info = O.pcg(H, b, tol=1e-8, precond=lambda r: O.acycle(H, r))
+    assert info["converged"]
+    assert np.linalg.norm(b - A0 @ x) <= 1e-8 * np.linalg.norm(b)
 
 
 # P14 -- any basis of span(Zhat_i) gives the same preconditioner
