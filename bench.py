@@ -308,6 +308,9 @@ def main():
     ap.add_argument("--cmin", default="2",
                     help="aniso2d: minimum coarsening ratio per level (LS_{a,b,...} of "
                          "sec. 3.4), comma-separated, the last repeats")
+    ap.add_argument("--cycle", choices=("v", "additive"), default="v",
+                    help="aniso2d: the multiplicative V-cycle or the additive cycle of "
+                         "sec. 3.1.1 (single right-hand sides only)")
     ap.add_argument("--maxit", type=int, default=0,
                     help="PCG iteration cap (default 1000; 200 for ls3d)")
     args = ap.parse_args()
@@ -336,8 +339,10 @@ def main():
     # part runs; its timed solves run after the GPU part (BLAS on every core
     # the host gives it)
     cmin = tuple(int(c) for c in str(args.cmin).split(","))
-    if cmin != (2,):
-        args.no_cpu_baseline = True         # the oracle baseline runs the default schedule
+    if cmin != (2,) or args.cycle != "v":
+        args.no_cpu_baseline = True         # the oracle baseline runs the default method
+    if args.cycle != "v":
+        args.batch = 0                      # the additive cycle solves columns one by one
     cpu_proc = None
     if not args.no_cpu_baseline:
         cpu_proc = subprocess.Popen(cpu_baseline_cmd(args.N, args.cpu_reps),
@@ -357,7 +362,7 @@ def main():
         seed = P.CONFIG_RHS_SEED[3]
     else:
         prob = P.config2(args.N)
-        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin)
+        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle)
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
@@ -507,6 +512,9 @@ def main():
     # per iteration of the timed solves
     solve_roof = {}
     for tag, res, sz in (("mixed", mixed, 4), ("fp64", fp64, 8)):
+        if args.workload == "aniso2d" and args.cycle != "v":
+            solve_roof[tag] = None          # the per-level formula is the V-cycle's
+            continue
         mb, per, cg = method_bytes(inf, sz)
         gbs = mb / (res["ms_per_iteration"] * 1e-3) / 1e9
         solve_roof[tag] = dict(bytes_per_iteration=int(mb), per_level_bytes=[int(v) for v in per],
@@ -588,7 +596,7 @@ def main():
                          f"c_min=3,4, coarsest<2000" if three_d else
                          f"aniso2d N={args.N} theta=pi/6 eps=1e-4 (n={prob.n}, "
                          f"m={prob.m}), rhs uniform[-1,1] seed {seed}, tol 1e-8, "
-                         f"4x4 aggregates, c_min={args.cmin}, coarsest<2000"),
+                         f"4x4 aggregates, c_min={args.cmin}, {args.cycle}-cycle, coarsest<2000"),
             "levels": inf["nlevels"],
             "n_per_level": [l["n"] for l in inf["levels"]],
             "op_complexity": round(inf["op_complexity"], 3),

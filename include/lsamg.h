@@ -108,10 +108,21 @@ typedef struct lsamg_params {
                             last one repeats (Algorithm 1; pass t aggregates
                             the graph of pass t-1's aggregates, T_1 T_2 ...)  */
   int32_t nagg_passes;   /* entries used in agg_passes (default 1: {1})      */
-  int32_t reserved_agg;
+  int32_t cycle;         /* LSAMG_CYCLE_V (0, default): the multiplicative
+                            V-cycle (RAS pre-smoother, coarse-grid correction,
+                            RAS-T post-smoother, sec. 3.1.1); LSAMG_CYCLE_ADDITIVE
+                            (1): the additive method of sec. 3.1.1, the
+                            additive Schwarz smoother sum_i R_i^T A_i^{-1} R_i
+                            (eq:ras without the partition of unity) plus
+                            P (coarse cycle) P^T on every level, exact at the
+                            coarsest; setup then also stores the full local
+                            inverses A_i^{-1} (|Omega_i|^2 entries each), there
+                            is no dense tail, and several right-hand sides are
+                            solved one after another                         */
 } lsamg_params;
 
 enum { LSAMG_AGG_LATTICE = 0, LSAMG_AGG_STANDARD = 1 };
+enum { LSAMG_CYCLE_V = 0, LSAMG_CYCLE_ADDITIVE = 1 };
 
 /* Per-solve statistics (host memory, one entry per right-hand side). */
 typedef struct lsamg_stats {

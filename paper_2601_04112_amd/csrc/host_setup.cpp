@@ -487,7 +487,8 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
   const Groups& G = L.G;
   const int64_t na = L.nagg, n = L.n;
   L.k.assign(na, 0);
-  std::vector<std::vector<double>> mus(na), zh(na), zs(na);
+  std::vector<std::vector<double>> mus(na), zh(na), zs(na), za(na);
+  const bool additive = p.cycle == LSAMG_CYCLE_ADDITIVE;
   std::atomic<int64_t> hazards{0};
   // per-phase thread time (verbose): local factor, Schur complement, local
   // eigenproblem, local inverse rows
@@ -600,6 +601,13 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     trsm_lower(nO, Ai.data(), nw, Zc.data());
     trsm_lower_t(nO, Ai.data(), nw, Zc.data());
     zs[a] = std::move(Zc);          // column j = row j of A_i^{-1} restricted to omega
+    if (additive) {                 // the whole A_i^{-1} (additive Schwarz smoother)
+      std::vector<double> Za((size_t)nO * nO, 0.0);
+      for (int j = 0; j < nO; ++j) Za[(size_t)j * nO + j] = 1.0;
+      trsm_lower(nO, Ai.data(), nO, Za.data());
+      trsm_lower_t(nO, Ai.data(), nO, Za.data());
+      za[a] = std::move(Za);
+    }
     add_ns(3, t_ph);
   }, nthreads);
   L.hazards = hazards.load();
@@ -623,10 +631,16 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
   L.mu.resize(L.muptr[na]);
   L.Z.resize(L.zoff[na]);
   L.Zhat.resize(L.poff[na]);
+  if (additive) {
+    L.aoff.assign(na + 1, 0);
+    for (int64_t a = 0; a < na; ++a) L.aoff[a + 1] = L.aoff[a] + (int64_t)za[a].size();
+    L.Ainv_loc.resize(L.aoff[na]);
+  }
   parallel_for(na, [&](int64_t a, int) {
     std::copy(mus[a].begin(), mus[a].end(), L.mu.begin() + L.muptr[a]);
     std::copy(zs[a].begin(), zs[a].end(), L.Z.begin() + L.zoff[a]);
     std::copy(zh[a].begin(), zh[a].end(), L.Zhat.begin() + L.poff[a]);
+    if (additive) std::copy(za[a].begin(), za[a].end(), L.Ainv_loc.begin() + L.aoff[a]);
   }, nthreads);
 }
 
@@ -830,6 +844,7 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     }
     if (Gin.n != np) fail(LSAMG_EINVAL, "G has n columns != product of grid extents");
     if (standard && (p.nagg_passes < 1 || p.nagg_passes > 8)) fail(LSAMG_EINVAL, "bad agg_passes");
+    if (p.cycle != LSAMG_CYCLE_V && p.cycle != LSAMG_CYCLE_ADDITIVE) fail(LSAMG_EINVAL, "bad cycle");
     if (Gin.m <= 0 || Gin.n <= 0 || !Gin.rowptr || (Gin.nnz > 0 && (!Gin.col || !Gin.val)))
       fail(LSAMG_EINVAL, "bad G");
     if (p.block < 1 || p.omega_max < 1 || p.max_levels < 1) fail(LSAMG_EINVAL, "bad params");

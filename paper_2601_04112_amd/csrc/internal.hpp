@@ -59,6 +59,10 @@ struct Level {
   std::vector<int64_t> poff;       // [nagg+1] offsets into Zhat
   std::vector<double> Zhat;        // |omega_i| x k_i row-major
   std::vector<int64_t> cstart;     // [nagg+1] coarse unknowns of aggregate i
+  // additive cycle only: the whole A_i^{-1} per aggregate (|Omega_i|^2,
+  // symmetric, column-major), at aoff[i]
+  std::vector<int64_t> aoff;
+  std::vector<double> Ainv_loc;
   int64_t hazards = 0;
   // coarsest
   std::vector<double> Ainv;        // n x n dense inverse

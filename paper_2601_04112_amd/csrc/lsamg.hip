@@ -63,6 +63,7 @@ struct DPrec {            // arrays that exist in both V-cycle precisions
   T* Zh = nullptr;        // Zhat_i row-major (restriction P^T)
   T* ZhT = nullptr;       // Zhat_i column-major (prolongation P)
   T* Ainv = nullptr;      // coarsest inverse, or the dense tail operator
+  T* As = nullptr;        // additive cycle: A_i^{-1} per aggregate, padded rows
   T* Spk = nullptr;       // the same operator as packed lower 64x64 tiles (k_sym_gemv)
   T* spart = nullptr;     // k_sym_gemv slots, nT * nT * 64
   T* x = nullptr;         // V-cycle output at this level
@@ -117,6 +118,7 @@ struct GemvPlan {
 
 struct DLevel {
   GemvPlan ras, rast, rst, pro;
+  GemvPlan as;            // additive cycle: A_i^{-1} b(Omega_i) into the staging
   GemvPlan dense;         // coarsest level: A_L^{-1} as one block (batched path)
   int64_t n = 0, nagg = 0, nrows = 0, nnz = 0, ntb = 0;
   bool coarsest = false;
@@ -864,6 +866,24 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
       }
     }
   }
+  // additive cycle: the whole A_i^{-1} (symmetric), rows padded as above
+  std::vector<int64_t> offa(HL.nagg);
+  std::vector<double> As;
+  const bool additive = !HL.aoff.empty();
+  if (additive) {
+    int64_t tota = 0;
+    for (int64_t a = 0; a < HL.nagg; ++a) {
+      offa[a] = tota;
+      tota += (HL.optr[a + 1] - HL.optr[a]) * pad4(HL.optr[a + 1] - HL.optr[a]);
+    }
+    As.assign(tota, 0.0);
+    for (int64_t a = 0; a < HL.nagg; ++a) {
+      const int64_t nO = HL.optr[a + 1] - HL.optr[a];
+      const double* z = HL.Ainv_loc.data() + HL.aoff[a];
+      for (int64_t l = 0; l < nO; ++l)
+        for (int64_t j = 0; j < nO; ++j) As[offa[a] + l * pad4(nO) + j] = z[l * nO + j];
+    }
+  }
   // cover lists for the RAS-T gather: for unknown j, staging positions
   // optr[i] + (index of j in Omega_i), ascending i
   std::vector<int64_t> cp(D.n + 1, 0);
@@ -960,6 +980,11 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   plan(D.rast, nO, nw, d_nO, d_nw, d_offr, d_w0, d_o0, D.n, false);
   plan(D.rst, kk, nw, d_k, d_nw, d_offh, d_w0, d_c0, D.n, false);
   plan(D.pro, nw, kk, d_nw, d_k, d_offt, d_c0, d_w0, ncoarse, false);
+  if (additive) {
+    D.d.As = h->upload_f<double>(As);
+    D.f.As = h->upload_f<float>(As);
+    plan(D.as, nO, nO, d_nO, d_nO, h->upload(offa), d_o0, d_o0, D.n, true);
+  }
   if (finest) {      // inputs of P^T and RAS-T are residual rows omega_a formed on the fly
     int64_t em = 0;
     for (int64_t a = 0; a < HL.nagg; ++a) em = std::max(em, tp[HL.astart[a + 1]] - tp[HL.astart[a]]);
@@ -1025,7 +1050,7 @@ void upload(lsamg_handle* h) {
   h->p_pqo = h->alloc<double>(h->red_np);
   // dense tail: the first level below the finest that is small enough
   size_t lc = 0;
-  if (h->H.params.dense_tail > 0)
+  if (h->H.params.dense_tail > 0 && h->H.params.cycle == LSAMG_CYCLE_V)
     for (size_t l = 1; l < h->L.size() && !h->L[l].coarsest; ++l)
       if (h->L[l].n <= h->H.params.dense_tail) {
         lc = l;
@@ -1371,15 +1396,12 @@ void gemv_resid(DLevel& L, const GemvPlan& Pl, const T* M, const T* b, T* out, h
   }
 }
 
-// x = B b on level l from a zero initial guess.  With finalize = false the
-// RAS-T contributions of this level are left staged in tb: the caller (the
-// finer level's prolongation) adds them when it reads x.
+// x = S b with the dense symmetric operator of level L (the coarsest
+// inverse, or the dense tail)
 template <typename T>
-void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool finalize) {
-  LevelTag tag_((int)l);
-  DLevel& L = h->L[l];
+void dense_apply(DLevel& L, const T* b, T* x, hipStream_t s) {
   DPrec<T>& P = prec<T>(L);
-  if (L.coarsest || L.tail) {
+  {
     {
       // algorithmic: the stored half of the symmetric operator, x and y once
       PROF(kname("k_sym_gemv", tname<T>()), sizeof(T) * (L.n * (L.n + 1) / 2 + 2 * L.n), s);
@@ -1392,6 +1414,19 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
     KLAUNCH((unsigned)L.nT * (dev::kTile / 16), dev::kBlock, 0, s, dev::k_sym_reduce<T>, L.n, L.nT,
             (const T*)P.spart, x);
     LAUNCH_OK();
+  }
+}
+
+// x = B b on level l from a zero initial guess.  With finalize = false the
+// RAS-T contributions of this level are left staged in tb: the caller (the
+// finer level's prolongation) adds them when it reads x.
+template <typename T>
+void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool finalize) {
+  LevelTag tag_((int)l);
+  DLevel& L = h->L[l];
+  DPrec<T>& P = prec<T>(L);
+  if (L.coarsest || L.tail) {
+    dense_apply<T>(L, b, x, s);
     return;
   }
   DLevel& C = h->L[l + 1];
@@ -1413,6 +1448,50 @@ void vcycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool fin
   resid_first<T>(L, x, s);
   gemv_resid<T, false>(L, L.rast, P.Zr, b, P.tb, s);                         // eq:ras-t
   if (finalize) gather_add<T>(L, x, s);
+}
+
+// x = B b on level l by the additive method of sec. 3.1.1 made multilevel:
+// the additive Schwarz smoother sum_i R_i^T A_i^{-1} R_i b (eq:ras without
+// the partition of unity; its local results staged in tb, as RAS-T's are)
+// plus P applied to the same cycle of P^T b on the next level, exact on the
+// coarsest.  No residual is formed.  finalize as in vcycle.
+template <typename T>
+void acycle(lsamg_handle* h, size_t l, const T* b, T* x, hipStream_t s, bool finalize) {
+  LevelTag tag_((int)l);
+  DLevel& L = h->L[l];
+  DPrec<T>& P = prec<T>(L);
+  if (L.coarsest || L.tail) {
+    dense_apply<T>(L, b, x, s);
+    return;
+  }
+  if (!P.As) throw DevError{LSAMG_EINVAL, "the hierarchy was set up for the V-cycle"};
+  DLevel& C = h->L[l + 1];
+  DPrec<T>& PC = prec<T>(C);
+  dev::InSpec<T> sg = no_spec<T>();
+  sg.idx = L.oidx;
+  gemv<T, dev::IN_GATHER, false>(L.as, sg, P.As, b, P.tb, s);                // A_i^{-1} b(Omega_i)
+  gemv<T, dev::IN_DIRECT, false>(L.rst, no_spec<T>(), P.Zh, b, PC.b, s);     // P^T b
+  acycle<T>(h, l + 1, PC.b, PC.x, s, false);
+  if (C.coarsest || C.tail) {
+    gemv<T, dev::IN_DIRECT, false>(L.pro, no_spec<T>(), P.ZhT, PC.x, x, s);  // x = P e
+  } else {
+    dev::InSpec<T> sp = no_spec<T>();
+    sp.ptr = C.cptr;
+    sp.pos = C.cpos;
+    sp.v1 = PC.tb;
+    gemv<T, dev::IN_TB, false>(L.pro, sp, P.ZhT, PC.x, x, s,
+                               (int64_t)(sizeof(T) + 8) * C.ntb + 8 * (C.n + 1));
+  }
+  if (finalize) gather_add<T>(L, x, s);
+}
+
+// the handle's cycle (V or additive) on level 0
+template <typename T>
+void cycle(lsamg_handle* h, const T* b, T* x, hipStream_t s, bool finalize) {
+  if (h->H.params.cycle == LSAMG_CYCLE_ADDITIVE)
+    acycle<T>(h, 0, b, x, s, finalize);
+  else
+    vcycle<T>(h, 0, b, x, s, finalize);
 }
 
 // Run fn (which launches a fixed sequence of kernels on a stream: one
@@ -1458,14 +1537,14 @@ void precondition(lsamg_handle* h, const double* r, double* z, hipStream_t s) {
       KLAUNCH(nblocks(L0.n), dev::kBlock, 0, s, dev::k_convert<double, float>, L0.n, r, L0.f.b);
       LAUNCH_OK();
     }
-    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, true);
+    cycle<float>(h, L0.f.b, L0.f.x, s, true);
     {
       PROF("k_convert<float, double>", 12 * L0.n, s);
       KLAUNCH(nblocks(L0.n), dev::kBlock, 0, s, dev::k_convert<float, double>, L0.n, L0.f.x, z);
       LAUNCH_OK();
     }
   } else {
-    vcycle<double>(h, 0, r, z, s, true);
+    cycle<double>(h, r, z, s, true);
   }
 }
 
@@ -1582,13 +1661,13 @@ void cg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur) {
   h->dir_num = fcg ? h->p_zq : h->p_rz[cur];
   h->dir_den = fcg ? h->p_pqo : h->p_rz[1 - cur];
   if (h->precision == LSAMG_MIXED) {
-    run_graph(h, 128 + 1, s, [&](hipStream_t gs) { vcycle<float>(h, 0, L0.f.b, L0.f.x, gs, false); });
+    run_graph(h, 128 + 1, s, [&](hipStream_t gs) { cycle<float>(h, L0.f.b, L0.f.x, gs, false); });
     PROF("k_cg_z<float>",
          4 * n + (stage ? 12 * L0.ntb + 8 * (n + 1) : 0) + (qv ? 24 : 16) * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<float>, n, L0.f.x, stage ? L0.cptr : nullptr, L0.cpos,
                                                  L0.f.tb, h->r, h->z, h->p_rz[cur], qv, h->p_zq);
   } else {
-    run_graph(h, 1, s, [&](hipStream_t gs) { vcycle<double>(h, 0, h->r, L0.d.x, gs, false); });
+    run_graph(h, 1, s, [&](hipStream_t gs) { cycle<double>(h, h->r, L0.d.x, gs, false); });
     PROF("k_cg_z<double>",
          8 * n + (stage ? 16 * L0.ntb + 8 * (n + 1) : 0) + (qv ? 24 : 16) * n + 8 * g, s);
     KLAUNCH(g, dev::kBlock, 0, s, dev::k_cg_z<double>, n, L0.d.x, stage ? L0.cptr : nullptr, L0.cpos,
@@ -1619,7 +1698,7 @@ void gv_tune(lsamg_handle* h, hipStream_t s) {
   if (h->gv_tuned[pi] || h->L.empty()) return;
   int64_t mx = 1;
   for (auto& D : h->L)
-    for (const GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro}) mx = std::max(mx, P->out);
+    for (const GemvPlan* P : {&D.ras, &D.rast, &D.rst, &D.pro, &D.as}) mx = std::max(mx, P->out);
   struct Ctx {
     GvTune t;
     Profiler* saved = g_prof;
@@ -1638,9 +1717,9 @@ void gv_tune(lsamg_handle* h, hipStream_t s) {
   g_gvtune = &c.t;
   DLevel& L0 = h->L[0];
   if (mixed)
-    vcycle<float>(h, 0, L0.f.b, L0.f.x, s, false);
+    cycle<float>(h, L0.f.b, L0.f.x, s, false);
   else
-    vcycle<double>(h, 0, h->r, L0.d.x, s, false);
+    cycle<double>(h, h->r, L0.d.x, s, false);
   HIP_OK(hipStreamSynchronize(s));
   h->gv_tuned[pi] = true;
 }
@@ -3319,7 +3398,7 @@ int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64
     ProfGuard pg(&h->prof);
     hipStream_t s = (hipStream_t)stream;
     int rc = LSAMG_OK;
-    if (nrhs == 1 || h->batch_mode == 0) {
+    if (nrhs == 1 || h->batch_mode == 0 || h->H.params.cycle == LSAMG_CYCLE_ADDITIVE) {
       for (int32_t c = 0; c < nrhs; ++c) {
         int r1 = pcg_one(h, b + (size_t)c * ld, x + (size_t)c * ld, tol, maxit, s,
                          stats ? stats + c : nullptr);
@@ -3468,6 +3547,8 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
   if (!h || !X || !Y || nrhs < 1 || nrhs > kBMax) return fail_with(LSAMG_EINVAL, "bad argument");
   if (h->device < 0 || h->L.empty()) return fail_with(LSAMG_ENODEV, "handle has no device copy");
   if (ld < h->L[0].n) return fail_with(LSAMG_EINVAL, "ld < n");
+  if (h->H.params.cycle != LSAMG_CYCLE_V)
+    return fail_with(LSAMG_EINVAL, "the multi-column cycle is the V-cycle");
   try {
     DeviceGuard g(h->device);
     ProfGuard pg(&h->prof);
@@ -4259,6 +4340,8 @@ int lsamg_server_submit(lsamg_server* s, const lsamg_request* req) {
   if (!s || !req || !req->G || !req->params || !req->b || !req->x || req->nrhs < 1 ||
       req->nrhs > 64 || req->maxit < 0 || !(req->tol >= 0.0) || req->G->n <= 0)
     return fail_with(LSAMG_EINVAL, "bad request");
+  if (req->params->cycle != LSAMG_CYCLE_V)
+    return fail_with(LSAMG_EINVAL, "the server solves with the V-cycle");
   SReq q;
   q.r = *req;
   q.n = req->G->n;

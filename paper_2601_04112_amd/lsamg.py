@@ -21,6 +21,7 @@ LSAMG_ENOMEM, LSAMG_EHIP, LSAMG_ENOCONV, LSAMG_ENODEV = -4, -5, -6, -7
 FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
 AGG_LATTICE, AGG_STANDARD = 0, 1
+CYCLE_V, CYCLE_ADDITIVE = 0, 1
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
 OPT_ATA_TILES, OPT_BGROUP, OPT_KRYLOV = 6, 7, 8
 KRYLOV_CG, KRYLOV_FCG = 0, 1
@@ -53,7 +54,7 @@ class Params(C.Structure):
                 ("device", C.c_int32), ("nthreads", C.c_int32),
                 ("verbose", C.c_int32), ("dense_tail", C.c_int64),
                 ("aggregation", C.c_int32), ("agg_passes", C.c_int32 * 8),
-                ("nagg_passes", C.c_int32), ("reserved_agg", C.c_int32)]
+                ("nagg_passes", C.c_int32), ("cycle", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -210,7 +211,7 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 stall_ratio: float = 0.9, precision: int = FP64,
                 device: int = 0, nthreads: int = 0, verbose: bool = False,
                 dense_tail: int = 16384, aggregation: str = "lattice",
-                agg_passes: Sequence[int] = (1,)) -> Params:
+                agg_passes: Sequence[int] = (1,), cycle: str = "v") -> Params:
     p = default_params()
     p.ndim = ndim
     for d in range(3):
@@ -233,6 +234,9 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
     for i, c in enumerate(ap):
         p.agg_passes[i] = int(c)
     p.nagg_passes = len(ap)
+    if cycle not in ("v", "additive"):
+        raise ValueError("cycle must be 'v' or 'additive'")
+    p.cycle = CYCLE_ADDITIVE if cycle == "additive" else CYCLE_V
     return p
 
 

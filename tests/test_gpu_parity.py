@@ -909,3 +909,55 @@ def test_flexible_cg(which, request):
     finally:
         s.set_option(L.OPT_KRYLOV, L.KRYLOV_CG)
         s.set_precision(L.FP64)
+
+
+@pytest.fixture(scope="module")
+def rot_add(gpu_device):
+    """As rot, set up for the additive cycle (whole local inverses)."""
+    p = P.aniso2d(64, math.pi / 6, 1e-4)
+    H, s = build(p, 2, O.Params(cmin=(2,), max_coarse=150), cmin=(2,), max_coarse=150,
+                 dense_tail=2000, cycle="additive")
+    assert len(H.levels) >= 3 and s.info()["tail_level"] == -1   # no dense tail
+    yield p, H, s
+    s.close()
+
+
+def test_additive_cycle(rot_add):
+    """The additive multilevel cycle (sec. 3.1.1): one FP64 cycle equals the
+    oracle's acycle to 1e-10 (FP32 to 1e-4); PCG with it at the oracle's
+    stop count equals the oracle's iterate to 1e-10 and the converged solve
+    stops within one iteration of it on a true residual at tolerance; the
+    mixed solve converges within 1.1x the oracle's count; several right-hand
+    sides are solved column by column (bitwise the single solves), and the
+    multi-column V-cycle entry refuses the handle."""
+    p, H, s = rot_add
+    pre = lambda r: O.acycle(H, r)
+    v = np.random.default_rng(21).standard_normal(p.n)
+    try:
+        s.set_precision(L.FP64)
+        assert rel(host(s.apply(L.OP_VCYCLE, dvec(v))), O.acycle(H, v)) <= vtol(H)
+        b = P.rhs_uniform(p.n, 0)
+        xo, info = O.pcg(H, b, tol=1e-8, precond=pre)
+        K = info["iters"]
+        assert info["converged"] and info["restarts"] == 0
+        x, st = s.solve(dvec(b), tol=0.0, maxit=K)
+        assert st[0]["iters"] == K and rel(host(x), xo) <= vtol(H), rel(host(x), xo)
+        x2, st2 = s.solve(dvec(b), tol=1e-8, maxit=1000)
+        A = H.levels[0].A
+        r = np.linalg.norm(b - A @ host(x2)) / np.linalg.norm(b)
+        assert st2[0]["converged"] == 1 and abs(st2[0]["iters"] - K) <= 1 and r <= 1e-8
+        X = np.stack([P.rhs_uniform(p.n, 30 + j) for j in range(3)])
+        Xs, stb = s.solve(dvec(X), tol=1e-8, maxit=1000)
+        for j in range(3):
+            xj, _ = s.solve(dvec(X[j]), tol=1e-8, maxit=1000)
+            assert np.array_equal(host(Xs)[j], host(xj)) and stb[j]["converged"] == 1
+        with pytest.raises(L.LsamgError):
+            s.apply_vcycle_batch(dvec(X))
+        s.set_precision(L.MIXED)
+        assert rel(host(s.apply(L.OP_VCYCLE, dvec(v))), O.acycle(H, v)) <= 1e-4
+        xm, stm = s.solve(dvec(b), tol=1e-8, maxit=1000)
+        r = np.linalg.norm(b - A @ host(xm)) / np.linalg.norm(b)
+        assert stm[0]["converged"] == 1 and r <= 1e-8
+        assert stm[0]["iters"] <= math.ceil(1.10 * K)
+    finally:
+        s.set_precision(L.FP64)
