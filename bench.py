@@ -308,6 +308,8 @@ def main():
     ap.add_argument("--cmin", default="2",
                     help="aniso2d: minimum coarsening ratio per level (LS_{a,b,...} of "
                          "sec. 3.4), comma-separated, the last repeats")
+    ap.add_argument("--omega-max", type=int, default=800,
+                    help="aniso2d: coarse aggregates of at most this many unknowns")
     ap.add_argument("--cycle", choices=("v", "additive"), default="v",
                     help="aniso2d: the multiplicative V-cycle or the additive cycle of "
                          "sec. 3.1.1 (single right-hand sides only)")
@@ -339,7 +341,7 @@ def main():
     # part runs; its timed solves run after the GPU part (BLAS on every core
     # the host gives it)
     cmin = tuple(int(c) for c in str(args.cmin).split(","))
-    if cmin != (2,) or args.cycle != "v":
+    if cmin != (2,) or args.cycle != "v" or args.omega_max != 800:
         args.no_cpu_baseline = True         # the oracle baseline runs the default method
     if args.cycle != "v":
         args.batch = 0                      # the additive cycle solves columns one by one
@@ -362,7 +364,8 @@ def main():
         seed = P.CONFIG_RHS_SEED[3]
     else:
         prob = P.config2(args.N)
-        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle)
+        s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle,
+                     omega_max=args.omega_max)
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
@@ -596,7 +599,8 @@ def main():
                          f"c_min=3,4, coarsest<2000" if three_d else
                          f"aniso2d N={args.N} theta=pi/6 eps=1e-4 (n={prob.n}, "
                          f"m={prob.m}), rhs uniform[-1,1] seed {seed}, tol 1e-8, "
-                         f"4x4 aggregates, c_min={args.cmin}, {args.cycle}-cycle, coarsest<2000"),
+                         f"4x4 aggregates, c_min={args.cmin}, omega_max={args.omega_max}, "
+                         f"{args.cycle}-cycle, coarsest<2000"),
             "levels": inf["nlevels"],
             "n_per_level": [l["n"] for l in inf["levels"]],
             "op_complexity": round(inf["op_complexity"], 3),

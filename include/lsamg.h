@@ -70,7 +70,7 @@ typedef struct lsamg_params {
   int32_t grid[3];       /* lattice extent per axis, x fastest               */
   int32_t block;         /* lattice block width per axis (4 in 2D, 3 in 3D)  */
   int32_t omega_max;     /* coarse levels shrink the block until every
-                            aggregate has at most this many unknowns (400)   */
+                            aggregate has at most this many unknowns (800)   */
   int32_t n_eig_fixed;   /* > 0: fixed eigenvector count per aggregate;
                             0: threshold rule of sec. 3.4                    */
   double kappa;          /* target condition number (50, sec. 3.4)           */
@@ -367,7 +367,8 @@ enum {
 enum { LSAMG_KRYLOV_CG = 0, LSAMG_KRYLOV_FCG = 1 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
- * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT and LSAMG_OPT_BGROUP.
+ * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT, LSAMG_OPT_BGROUP and
+ * LSAMG_OPT_ATA_TILES.
  * EINVAL on an unknown option or value. */
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
 

@@ -65,7 +65,7 @@ class Params:
     max_levels: int = 10            # L_max
     max_coarse: int = 2000          # n_coarse
     block: int = 4                  # lattice block per axis on level 0
-    omega_max: int = 400            # largest aggregate on coarse levels
+    omega_max: int = 800            # largest aggregate on coarse levels
     n_eig_fixed: int = 0            # > 0: fixed count per aggregate
     kappa: float = 50.0             # target condition number (section 3.4)
     cmin: tuple = (3, 4)            # per-level minimum coarsening ratio

@@ -335,6 +335,95 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow_m(int64_t nagg, GemvOp o
   *dst = ADD ? *dst + acc : acc;
 }
 
+// Narrow form with 16-byte loads (every lj_a <= 64): one wavefront per
+// aggregate, four aggregates per workgroup.  With V = 16 / sizeof(T)
+// outputs per vector, the lanes of a wavefront are Q = ceil(lj/V) output
+// vectors by LG = 64/Q row groups; lane (g, q) loads rows l = g, g+LG, ...
+// of output vector q (rows are padded to multiples of 4 entries and blocks
+// start 16-byte aligned), U rows in flight, so one load instruction moves a
+// contiguous stretch of the aggregate's block.  The LG partial vectors of
+// each q are then added in row-group order through LDS.
+// LDS per wavefront: (round4(lmax + emax) + 64 V) * sizeof(T).
+template <typename T, int MODE, bool ADD>
+__global__ void __launch_bounds__(kBlock) k_gemv_narrow4(int64_t nagg, GemvOp op, int lmax,
+                                                         int emax, InSpec<T> spec,
+                                                         const T* __restrict__ M,
+                                                         const T* __restrict__ in,
+                                                         T* __restrict__ out) {
+  constexpr int V = 16 / sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(V)));
+  constexpr int U = 4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem_raw[];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t a = xcd_block(blockIdx.x, gridDim.x) * (kBlock / 64) + wave;
+  const bool valid = a < nagg;
+  const int stride = ((lmax + emax + 3) & ~3) + 64 * V;
+  T* sv = reinterpret_cast<T*>(smem_raw) + (size_t)wave * stride;
+  T* pr = sv + lmax;
+  vec* red = reinterpret_cast<vec*>(sv + ((lmax + emax + 3) & ~3));
+  int nj = 0, nl = 0, Q = 1, LG = 64, g = 0, q = 0;
+  int64_t ib = 0, ld = 0;
+  const T* m = M;
+  vec mv[U];
+  const vec zero = {};
+  if (valid) {
+    nj = op.lj[a];
+    nl = op.ll[a];
+    Q = (nj + V - 1) / V;
+    LG = 64 / Q;
+    g = lane / Q;
+    q = lane % Q;
+    ld = mrow(nj, 1);
+    m = M + op.moff[a] + V * q;
+    // the first U rows of the lane do not depend on the staged input
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = g + u * LG;
+      mv[u] = (g < LG && l < nl) ? __builtin_nontemporal_load((const vec*)(m + (int64_t)l * ld))
+                                 : zero;
+    }
+    ib = op.ibase[a];
+    if (MODE == IN_RESG)
+      stage_products<T, MODE>(pr, ib, nl, spec, lane, 64);
+    else
+      stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, lane, 64);
+  }
+  if (MODE == IN_RESG) {
+    __syncthreads();
+    if (valid) stage_inputs<T, MODE>(sv, pr, in, ib, nl, spec, lane, 64);
+  }
+  __syncthreads();
+  vec acc = zero;
+  if (valid && g < LG) {
+    vec av[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int l = g + u * LG;
+      av[u] = l < nl ? mv[u] * sv[l] : zero;
+    }
+    int l = g + U * LG;
+    for (; l + (U - 1) * LG < nl; l += U * LG) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        mv[u] = __builtin_nontemporal_load((const vec*)(m + (int64_t)(l + u * LG) * ld));
+#pragma unroll
+      for (int u = 0; u < U; ++u) av[u] += mv[u] * sv[l + u * LG];
+    }
+    for (; l < nl; l += LG) av[0] += __builtin_nontemporal_load((const vec*)(m + (int64_t)l * ld)) * sv[l];
+    acc = (av[0] + av[1]) + (av[2] + av[3]);
+  }
+  red[lane] = acc;
+  __syncthreads();
+  if (valid && g == 0 && q < Q) {
+    vec t = red[q];
+    for (int gg = 1; gg < LG; ++gg) t += red[gg * Q + q];
+    T* dst = out + op.obase[a] + V * q;
+#pragma unroll
+    for (int k = 0; k < V; ++k)
+      if (V * q + k < nj) dst[k] = ADD ? dst[k] + t[k] : t[k];
+  }
+}
+
 // Wide form: one workgroup of NW wavefronts per task (aggregate a, 64-wide
 // slice j0 of its outputs); the waves split the loop over l and their
 // partial sums are added in wave order through LDS.
@@ -933,14 +1022,24 @@ __global__ void __launch_bounds__(kBlock) k_cg_update(int64_t n, const double* _
                                                       double* __restrict__ rr_part,
                                                       double* __restrict__ pq_keep) {
   const int np = gridDim.x;
+  // the first element's operands do not depend on alpha: loaded before the
+  // partial sums are reduced, so the two latencies overlap
+  const int64_t i0 = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  double p0 = 0, q0 = 0, x0 = 0, r0 = 0;
+  if (i0 < n) {
+    p0 = p[i0];
+    q0 = q[i0];
+    x0 = x[i0];
+    r0 = r[i0];
+  }
   const double alpha = sum_parts(rz_part, np) / sum_parts(pq_part, np);
   if (pq_keep && blockIdx.x == 0)
     for (int i = threadIdx.x; i < np; i += kBlock) pq_keep[i] = pq_part[i];
   double v = 0;
-  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * kBlock) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
+  for (int64_t i = i0; i < n; i += (int64_t)gridDim.x * kBlock) {
+    const bool pre = i == i0;
+    x[i] = (pre ? x0 : x[i]) + alpha * (pre ? p0 : p[i]);
+    const double ri = (pre ? r0 : r[i]) - alpha * (pre ? q0 : q[i]);
     r[i] = ri;
     if (r32) r32[i] = (float)ri;
     v += ri * ri;

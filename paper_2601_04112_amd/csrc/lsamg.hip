@@ -88,7 +88,8 @@ struct GemvPlan {
   mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
   mutable int form_t = 0;         // FP32 wide form: 0 one output per lane, 1 four (k_gemv_wide4)
   mutable int narrow_t[2] = {1, 1};  // G > 0: the form timed fastest: 0 wide, 1 narrow
-                                     // (a wavefront per aggregate), 2 an aggregate per lane group
+                                     // (a wavefront per aggregate), 2 an aggregate per
+                                     // lane group, 3 16-byte loads (k_gemv_narrow4)
   int64_t ntask4 = 0;             // tasks (aggregate, 256-wide output slice) of k_gemv_wide4
   int32_t* task4_a = nullptr;
   int32_t* task4_j0 = nullptr;
@@ -1200,6 +1201,17 @@ void gemv_narrow_m_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* 
   }
 }
 
+// narrow form with 16-byte loads, a wavefront per aggregate
+template <typename T, int MODE, bool ADD>
+void gemv_narrow4_launch(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in,
+                         T* out, hipStream_t s, const ProfScope& ps_) {
+  const unsigned g = (unsigned)((P.nagg + 3) / 4);
+  const int emax = MODE == dev::IN_RESG ? P.emax : 0;
+  const size_t lds = (size_t)4 * (((P.lmax + emax + 3) & ~3) + 64 * (16 / sizeof(T))) * sizeof(T);
+  KLAUNCH(g, dev::kBlock, lds, s, dev::k_gemv_narrow4<T, MODE, ADD>, P.nagg, P.op, P.lmax, emax,
+          sp, M, in, out);
+}
+
 template <typename T, int MODE, bool ADD>
 void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, T* out,
           hipStream_t s, int64_t extra_bytes = 0) {
@@ -1212,13 +1224,15 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
   if (P.nw_t[pi] == 0 && g_gvtune && !g_rec && (try_wide || P.G < 64)) {
     float best = 1e30f;
     int pick = P.NW, pick_form = 0, pick_narrow = 0;
-    for (int nf = 1; nf <= 2 && P.G > 0; ++nf) {
+    for (int nf = 1; nf <= 3 && P.G > 0; ++nf) {
       if (nf == 2 && P.G >= 64) continue;
       auto run = [&]() {
         if (nf == 1)
           gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
-        else
+        else if (nf == 2)
           gemv_narrow_m_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
+        else
+          gemv_narrow4_launch<T, MODE, ADD>(P, sp, M, in, (T*)g_gvtune->scratch, s, kNoProf);
       };
       run();
       for (int round = 0; round < 2; ++round) {
@@ -1267,13 +1281,17 @@ void gemv(const GemvPlan& P, const dev::InSpec<T>& sp, const T* M, const T* in, 
   const int NWsel = P.nw_t[pi] ? P.nw_t[pi] : P.NW;
   const int form = pi == 1 ? P.form_t : 0;
   // the names are those of the kernel symbols (k_gemv_wide4 has no type parameter)
-  PROF(kname(narrow ? (nform == 2 ? "k_gemv_narrow_m" : "k_gemv_narrow")
+  PROF(kname(narrow ? (nform == 2 ? "k_gemv_narrow_m" : nform == 3 ? "k_gemv_narrow4" : "k_gemv_narrow")
                     : (form == 1 ? "k_gemv_wide4" : "k_gemv_wide"),
-             (form == 1 ? std::string() : std::string(tname<T>()) + ", ") + std::to_string(MODE) +
-                 ", " + (ADD ? "true" : "false") + ", " + std::to_string(narrow ? P.G : NWsel)),
+             (form == 1 && !narrow ? std::string() : std::string(tname<T>()) + ", ") +
+                 std::to_string(MODE) + ", " + (ADD ? "true" : "false") +
+                 (nform == 3 ? std::string()
+                             : ", " + std::to_string(narrow ? P.G : NWsel))),
        sizeof(T) * (P.mat + P.in_u + P.out * (ADD ? 2 : 1)) + 4 * P.idx + 32 * P.nagg + extra_bytes,
        s);
-  if (nform == 2) {
+  if (nform == 3) {
+    gemv_narrow4_launch<T, MODE, ADD>(P, sp, M, in, out, s, ps_);
+  } else if (nform == 2) {
     gemv_narrow_m_launch<T, MODE, ADD>(P, sp, M, in, out, s, ps_);
   } else if (narrow) {
     gemv_narrow_launch<T, MODE, ADD>(P, sp, M, in, out, s, ps_);
@@ -3326,7 +3344,7 @@ void lsamg_params_default(lsamg_params* p) {
   p->max_levels = 10;
   p->max_coarse = 2000;
   p->block = 4;
-  p->omega_max = 400;
+  p->omega_max = 800;
   p->n_eig_fixed = 0;
   p->kappa = 50.0;
   p->cmin[0] = 2;

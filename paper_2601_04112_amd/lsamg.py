@@ -204,7 +204,7 @@ def default_params() -> Params:
 
 def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 max_levels: int = 10, max_coarse: int = 2000,
-                omega_max: int = 400, n_eig_fixed: int = 0,
+                omega_max: int = 800, n_eig_fixed: int = 0,
                 kappa: float = 50.0, cmin: Sequence[int] = (2,),
                 tie_rtol: float = 1e-8, tie_atol: float = 1e-12,
                 pinv_rtol: float = 1e-6, thresh_margin: float = 1e-10,

@@ -15,6 +15,11 @@ stored values to check the library at full size without re-running the
   each run for ``BATCH_ITERS`` PCG iterations by the oracle: every column's
   2-norm, and the entries at ``BATCH_SAMPLES`` fixed indices of every column.
 
+The oracle hierarchy is built with exact row compression of the coarse
+G_l (each group of rows touching the same parents replaced by its QR R
+factor), as the library stores them; the integer setup is the same as the
+plain form's.
+
 Usage: python tests/golden/make_config2_fixture.py [N]
 """
 import hashlib
@@ -58,7 +63,7 @@ def main(N: int = 512):
     global _H
     prob = P.config2(N)
     t0 = time.time()
-    H = O.setup(prob.G, 2, prob.grid, O.Params(cmin=(2,)))
+    H = O.setup(prob.G, 2, prob.grid, O.Params(cmin=(2,), compress_rows=True))
     t_setup = time.time() - t0
     _H = H
     levels = []
