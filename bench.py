@@ -385,7 +385,7 @@ def main():
         for _ in range(warmup):
             s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
         if only is not None:
-            s.profile(True, only)
+            s.profile(True, only, by_level=" @L" in only)
         torch.cuda.synchronize()
         lat = []
         t_start = time.perf_counter()
@@ -404,21 +404,19 @@ def main():
                     converged=bool(st[0]["converged"]),
                     ms_per_iteration=elapsed * 1e3 / steps / max(1, st[0]["iters"])), kp
 
-    # untimed pass over every kernel: find the dominant kernel of the mixed path
+    # untimed pass over every kernel and level: the dominant kernel of the
+    # mixed path is the one operator (kernel at one level) with the most time;
+    # each kernel's algorithmic bytes (the library's per-launch formula) over
+    # its time
     s.set_precision(L.MIXED)
     s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
-    s.profile(True)
-    s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
-    allk = sorted(s.profile_read(), key=lambda r: -r["ms"])
-    s.profile(False)
-    dominant = allk[0]["name"]
-    ktotal = sum(r["ms"] for r in allk)
-    # the same per kernel and level: each kernel's algorithmic bytes (the
-    # library's per-launch formula) over its time
     s.profile(True, by_level=True)
     s.solve(b, tol=1e-8, out=x, maxit=args.maxit)
     byl = sorted(s.profile_read(), key=lambda r: -r["ms"])
     s.profile(False)
+    allk = byl
+    dominant = byl[0]["name"]
+    ktotal = sum(r["ms"] for r in byl)
     kernel_fracs = [dict(name=r["name"], us_per_launch=round(r["ms"] / r["launches"] * 1e3, 2),
                          gbs=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9, 1),
                          frac=round(r["bytes"] / (r["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),

@@ -209,7 +209,10 @@ struct Profiler {
     double flops;
   };
   std::vector<Rec> recs;
-  bool want(const std::string& nm) const { return on && (only.empty() || nm == only); }
+  // only: a kernel name, or with by_level a name with its " @L<level>"
+  bool want(const std::string& nm, const std::string& full) const {
+    return on && (only.empty() || nm == only || full == only);
+  }
 };
 
 thread_local Profiler* g_prof = nullptr;
@@ -228,13 +231,14 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope() = default;
   ProfScope(Profiler* pp, const std::string& name, double bytes, hipStream_t, double flops = 0.0) {
-    if (!pp || !pp->want(name) || pp->used + 2 > pp->pool.size()) return;
+    if (!pp) return;
+    const std::string full =
+        pp->by_level && g_level >= 0 ? name + " @L" + std::to_string(g_level) : name;
+    if (!pp->want(name, full) || pp->used + 2 > pp->pool.size()) return;
     p = pp;
     a = pp->pool[pp->used++];
     b = pp->pool[pp->used++];
-    pp->recs.push_back(Profiler::Rec{
-        pp->by_level && g_level >= 0 ? name + " @L" + std::to_string(g_level) : name, bytes, a, b,
-        flops});
+    pp->recs.push_back(Profiler::Rec{full, bytes, a, b, flops});
   }
 };
 
