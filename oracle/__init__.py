@@ -19,8 +19,8 @@ convergence factors of the large configurations, which are parity unpinned
 """
 from .lsamg import (Params, Level, Hierarchy, setup, vcycle, pcg, ras, ras_t,
                     apply_A, dense_preconditioner, stats, AssembledVcycle,
-                    additive_schwarz, acycle)
+                    additive_schwarz, acycle, block_pcg)
 
 __all__ = ["Params", "Level", "Hierarchy", "setup", "vcycle", "pcg", "ras",
            "ras_t", "apply_A", "dense_preconditioner", "stats", "AssembledVcycle",
-           "additive_schwarz", "acycle"]
+           "additive_schwarz", "acycle", "block_pcg"]

@@ -609,6 +609,68 @@ def vcycle(H: Hierarchy, b: np.ndarray, level: int = 0) -> np.ndarray:
     return x + ras_t(L, r)
 
 
+def block_pcg(H: Hierarchy, B: np.ndarray, tol: float = 1e-8, maxit: int = 500,
+              fixed_iters: Optional[int] = None, precond: Optional[Callable] = None,
+              pinv_rtol: float = 1e-12):
+    """Block preconditioned CG (O'Leary 1980) on the columns of B (n x s),
+    X0 = 0, in the form whose block of search directions is made
+    A-orthogonal to the previous block explicitly:
+
+        Q = A P,  G = P^T Q,  C = G^+ (P^T R),  X += P C,  R -= Q C,
+        Z = M R,  D = -G^+ (Q^T Z),  P = Z + P D,
+
+    starting from P = Z = M B.  G^+ is the pseudo-inverse of the symmetric
+    s x s matrix G (eigenvalues at or below pinv_rtol times the largest count
+    as zero), so directions that have become linearly dependent (columns
+    that converged, or equal right-hand sides) drop out instead of breaking
+    the iteration.  Every column's iterate minimises the A-norm of its error
+    over the sum of all columns' Krylov spaces.  Stops when every nonzero
+    column has ||r_j|| <= tol ||b_j|| and then its true residual too
+    (otherwise R is replaced by B - A X and P by M R, as in ``pcg``); with
+    ``fixed_iters`` runs exactly that many iterations.  Returns ``(X, info)``
+    with the iteration count, restarts and per-column relative residuals."""
+    apply_b = precond if precond is not None else (lambda v: vcycle(H, v))
+    M = lambda V: np.stack([apply_b(V[:, j]) for j in range(V.shape[1])], axis=1)
+    A0 = H.levels[0]
+    X = np.zeros_like(B)
+    R = B.copy()
+    nb = np.linalg.norm(B, axis=0)
+    live = nb > 0
+    Z = M(R)
+    Pd = Z.copy()
+    its = restarts = 0
+    limit = fixed_iters if fixed_iters is not None else maxit
+    conv = not live.any()
+    while its < limit and not conv:
+        Q = apply_A(A0, Pd)
+        G = Pd.T @ Q
+        w, V = np.linalg.eigh(0.5 * (G + G.T))
+        keep = w > pinv_rtol * max(w.max(), 0.0)
+        Gp = (V[:, keep] / w[keep]) @ V[:, keep].T
+        C = Gp @ (Pd.T @ R)
+        X = X + Pd @ C
+        R = R - Q @ C
+        its += 1
+        if fixed_iters is None:
+            rn = np.linalg.norm(R, axis=0)
+            if np.all(rn[live] <= tol * nb[live]):
+                Rt = B - apply_A(A0, X)
+                if np.all(np.linalg.norm(Rt, axis=0)[live] <= tol * nb[live]):
+                    conv = True
+                    break
+                R = Rt
+                restarts += 1
+                Z = M(R)
+                Pd = Z.copy()
+                continue
+        Z = M(R)
+        Pd = Z - Pd @ (Gp @ (Q.T @ Z))
+    nbs = np.where(live, nb, 1.0)
+    true_res = np.linalg.norm(B - apply_A(A0, X), axis=0) / nbs
+    return X, dict(iters=its, converged=bool(conv), restarts=restarts,
+                   rel_res=np.linalg.norm(R, axis=0) / nbs, true_rel_res=true_res)
+
+
 def additive_schwarz(L: Level, r: np.ndarray) -> np.ndarray:
     """``sum_i R_i^T A_i^{-1} R_i r``: eq:ras without the partition of unity,
     the smoother M_1^{-1} of the additive two-level method (sec. 3.1.1)."""

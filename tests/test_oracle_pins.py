@@ -435,3 +435,43 @@ def test_flexible_cg_equals_cg_with_symmetric_preconditioner(rot):
     _, c1 = O.pcg(H, b, tol=1e-8)
     _, c2 = O.pcg(H, b, tol=1e-8, flexible=True)
     assert c1["converged"] and c2["converged"] and abs(c1["iters"] - c2["iters"]) <= 1
+
+
+def test_block_pcg(rot):
+    """Block PCG (O'Leary) pins: (1) on one column it is CG (same iterate
+    after 12 iterations to 1e-10); (2) after k iterations every column's
+    A-norm error is at most that of its own CG after k iterations, since its
+    iterate minimises the error over the sum of all columns' Krylov spaces,
+    which contains its own (strictly smaller on every column here); (3) a
+    repeated right-hand side makes the block Gram matrix singular: the
+    pseudo-inverse drops the dependent direction and both copies equal the
+    solve without the repeat; (4) all columns converge on their true
+    residuals within the CG count.  A sign error in D, directions not
+    A-orthogonalised against the previous block (P = Z), or a plain inverse
+    of the singular Gram matrix fails one of these.  (P^T R and Z^T R are
+    equal here in exact arithmetic, since the previous block is orthogonal
+    to the new residual, so either may form C.)"""
+    p, H = rot
+    A = H.levels[0].A.toarray()
+    b = P.rhs_uniform(p.n, 11)
+    x1, _ = O.pcg(H, b, fixed_iters=12)
+    xb, _ = O.block_pcg(H, b[:, None], fixed_iters=12)
+    assert np.linalg.norm(xb[:, 0] - x1) <= 1e-10 * np.linalg.norm(x1)
+    B = np.stack([P.rhs_uniform(p.n, 20 + j) for j in range(6)], axis=1)
+    xs = np.linalg.solve(A, B)
+    k = 4
+    Xb, _ = O.block_pcg(H, B, fixed_iters=k)
+    for j in range(6):
+        xc, _ = O.pcg(H, B[:, j], fixed_iters=k)
+        eb, ec = Xb[:, j] - xs[:, j], xc - xs[:, j]
+        assert eb @ A @ eb < (ec @ A @ ec) * (1 - 1e-6), j
+    B2 = np.concatenate([B[:, :3], B[:, :1], B[:, 3:]], axis=1)
+    X2, _ = O.block_pcg(H, B2, fixed_iters=6)
+    X1, _ = O.block_pcg(H, B, fixed_iters=6)
+    assert np.linalg.norm(X2[:, 0] - X2[:, 3]) <= 1e-12 * np.linalg.norm(X2[:, 0])
+    keep = [0, 1, 2, 4, 5, 6]
+    assert np.linalg.norm(X2[:, keep] - X1) <= 1e-9 * np.linalg.norm(X1)
+    Xc, info = O.block_pcg(H, B, tol=1e-8)
+    _, ic = O.pcg(H, B[:, 0], tol=1e-8)
+    assert info["converged"] and info["true_rel_res"].max() <= 1e-8
+    assert info["iters"] <= ic["iters"]
