@@ -308,6 +308,9 @@ def main():
     ap.add_argument("--cmin", default="2",
                     help="aniso2d: minimum coarsening ratio per level (LS_{a,b,...} of "
                          "sec. 3.4), comma-separated, the last repeats")
+    ap.add_argument("--batch-krylov", choices=("cg", "fcg", "block"), default="cg",
+                    help="outer iteration of the batched legs: per-column CG, flexible "
+                         "CG, or block CG over the batch")
     ap.add_argument("--omega-max", type=int, default=800,
                     help="aniso2d: coarse aggregates of at most this many unknowns")
     ap.add_argument("--cycle", choices=("v", "additive"), default="v",
@@ -442,6 +445,8 @@ def main():
                          dtype=torch.float64, device="cuda:0")
         XB = torch.empty_like(B)
         s.set_precision(prec)
+        s.set_option(L.OPT_KRYLOV, {"cg": L.KRYLOV_CG, "fcg": L.KRYLOV_FCG,
+                                    "block": L.KRYLOV_BLOCK}[args.batch_krylov])
         s.solve(B, tol=1e-8, out=XB)     # first batched solve: autotunes the MFMA tiles
         s.profile(True, by_level=True)
         s.solve(B, tol=1e-8, out=XB)
@@ -489,7 +494,9 @@ def main():
         torch.cuda.synchronize()
         el = time.perf_counter() - t1
         its = [r["iters"] for r in bst]
-        return dict(nrhs=args.batch, solves_per_s=round(args.batch * steps / el, 2),
+        s.set_option(L.OPT_KRYLOV, L.KRYLOV_CG)
+        return dict(nrhs=args.batch, krylov=args.batch_krylov,
+                    solves_per_s=round(args.batch * steps / el, 2),
                     ms_per_batch=round(el * 1e3 / steps, 3), steps=steps,
                     iters_min=min(its), iters_max=max(its),
                     all_converged=all(r["converged"] for r in bst),

@@ -361,14 +361,23 @@ enum {
                              the V-cycle is a slightly varying or unsymmetric
                              operator (its FP32 form); the same in exact
                              arithmetic with a fixed symmetric preconditioner.
-                             Applies to single and batched solves               */
+                             Applies to single and batched solves.
+                             LSAMG_KRYLOV_BLOCK: several right-hand sides run as
+                             block CG (O'Leary 1980) in batches of up to 64
+                             columns: one iterate per column minimising its
+                             error over all columns' Krylov spaces, directions
+                             A-orthogonalised per block through the 64 x 64
+                             Gram matrix P^T A P (pseudo-inverse: dependent
+                             directions drop out); all columns of a batch
+                             iterate until every one has converged.  A single
+                             right-hand side runs as CG                      */
 };
 
-enum { LSAMG_KRYLOV_CG = 0, LSAMG_KRYLOV_FCG = 1 };
+enum { LSAMG_KRYLOV_CG = 0, LSAMG_KRYLOV_FCG = 1, LSAMG_KRYLOV_BLOCK = 2 };
 
 /* Set a solve-path option (LSAMG_OPT_*) for later calls.  Values are 0 or 1
- * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT, LSAMG_OPT_BGROUP and
- * LSAMG_OPT_ATA_TILES.
+ * except for LSAMG_OPT_MFMA_TILE, LSAMG_OPT_DENSE_SPLIT, LSAMG_OPT_BGROUP,
+ * LSAMG_OPT_ATA_TILES and LSAMG_OPT_KRYLOV.
  * EINVAL on an unknown option or value. */
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value);
 

@@ -998,4 +998,36 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
   return LSAMG_OK;
 }
 
+// C = G^+ F by the symmetric eigen-decomposition G = V diag(w) V^T:
+// C = V diag(1/w_k, kept) V^T F
+int gram_pinv_apply(int s, const double* G, const double* F, double* C, double rtol) {
+  std::vector<double> V((size_t)s * s), w(s);
+  for (int i = 0; i < s; ++i)          // column-major symmetric copy, (G + G^T) / 2
+    for (int j = 0; j < s; ++j) V[(size_t)j * s + i] = 0.5 * (G[(size_t)i * s + j] + G[(size_t)j * s + i]);
+  if (!sym_eig(s, V.data(), w.data())) return -1;
+  const double wmax = s > 0 ? std::max(w[s - 1], 0.0) : 0.0;
+  std::vector<double> VtF((size_t)s * s, 0.0);   // (V^T F) scaled by 1/w, row k
+  int rank = 0;
+  for (int k = 0; k < s; ++k) {
+    if (!(w[k] > rtol * wmax) || w[k] <= 0.0) continue;
+    ++rank;
+    const double* vk = V.data() + (size_t)k * s;  // eigenvector k (column k)
+    double* row = VtF.data() + (size_t)k * s;
+    for (int i = 0; i < s; ++i) {
+      const double vi = vk[i];
+      if (vi == 0.0) continue;
+      const double* fi = F + (size_t)i * s;
+      for (int j = 0; j < s; ++j) row[j] += vi * fi[j];
+    }
+    for (int j = 0; j < s; ++j) row[j] /= w[k];
+  }
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < s; ++k) v += V[(size_t)k * s + i] * VtF[(size_t)k * s + j];
+      C[(size_t)i * s + j] = v;
+    }
+  return rank;
+}
+
 }  // namespace lsamg

@@ -87,4 +87,10 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int)>& body,
                   int nthreads = 0);
 int default_threads();
 
+// C = G^+ F for the symmetric s x s matrix G and the s x s matrix F (both
+// row-major; C row-major): the pseudo-inverse drops the eigenvalues of G at
+// or below rtol times the largest.  Returns the rank kept, or -1 if the
+// eigen-decomposition does not converge.  (Block CG's small dense step.)
+int gram_pinv_apply(int s, const double* G, const double* F, double* C, double rtol);
+
 }  // namespace lsamg

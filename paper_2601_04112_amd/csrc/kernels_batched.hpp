@@ -1804,5 +1804,152 @@ __global__ void __launch_bounds__(kBlock) k_bperm_out(int64_t n, int nrhs, int64
   if (j < nrhs) x[(int64_t)j * ld + perm[i]] = X[e];
 }
 
+// ---------------------------------------------------------------------------
+// Block CG on 64 interleaved columns (row i of a block: 64 contiguous FP64
+// values).  The workgroups take contiguous ranges of rows, staged through
+// LDS kBgRows at a time with coalesced loads; a thread owns a 4 x 4 block of
+// the 64 x 64 result (rows 4 (t / 16) .., columns 4 (t % 16) ..).
+// ---------------------------------------------------------------------------
+constexpr int kBgRows = 16;
+
+// part[blk][a * 64 + b] = sum over the workgroup's rows i of A[i][a] B[i][b]
+__global__ void __launch_bounds__(kBlock) k_bgram64(int64_t n, const double* __restrict__ A,
+                                                    const double* __restrict__ B,
+                                                    double* __restrict__ part) {
+  __shared__ double sA[kBgRows][64], sB[kBgRows][64];
+  const int t = threadIdx.x, a0 = 4 * (t >> 4), b0 = 4 * (t & 15);
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
+  double acc[4][4] = {};
+  for (int64_t rb = r0; rb < r1; rb += kBgRows) {
+    const int nr = (int)(r1 - rb < kBgRows ? r1 - rb : kBgRows);
+    for (int e = t; e < kBgRows * 64; e += kBlock) {
+      const int r = e >> 6, c = e & 63;
+      sA[r][c] = r < nr ? A[(rb + r) * 64 + c] : 0.0;
+      sB[r][c] = r < nr ? B[(rb + r) * 64 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int r = 0; r < nr; ++r) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        av[k] = sA[r][a0 + k];
+        bv[k] = sB[r][b0 + k];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] += av[i] * bv[j];
+    }
+    __syncthreads();
+  }
+  double* o = part + (int64_t)blockIdx.x * 4096;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) o[(a0 + i) * 64 + b0 + j] = acc[i][j];
+}
+
+// out[e] = sum over the np workgroup partials of entry e (ascending order)
+__global__ void __launch_bounds__(kBlock) k_bgram_sum(int np, const double* __restrict__ part,
+                                                      double* __restrict__ out) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= 4096) return;
+  double v = 0.0;
+  for (int b = 0; b < np; ++b) v += part[(int64_t)b * 4096 + e];
+  out[e] = v;
+}
+
+// X += P C and R -= Q C row by row (C: 64 x 64 row-major), R32 = (float) R
+// if given, and the per-column partials of ||R||^2 (column-major over the
+// workgroups, as bwrite_parts).  Thread t: row t / 16 of the staged rows,
+// columns 4 (t % 16) ...
+__global__ void __launch_bounds__(kBlock) k_bupd64(int64_t n, const double* __restrict__ P,
+                                                   const double* __restrict__ Q,
+                                                   const double* __restrict__ C,
+                                                   double* __restrict__ X, double* __restrict__ R,
+                                                   float* __restrict__ R32,
+                                                   double* __restrict__ rr_part) {
+  __shared__ double sC[64][64];
+  __shared__ double sP[kBgRows][64], sQ[kBgRows][64];
+  __shared__ double sRR[kBgRows][64];
+  const int t = threadIdx.x, r = t >> 4, c0 = 4 * (t & 15);
+  for (int e = t; e < 4096; e += kBlock) sC[e >> 6][e & 63] = C[e];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
+  double rr[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t rb = r0; rb < r1; rb += kBgRows) {
+    const int nr = (int)(r1 - rb < kBgRows ? r1 - rb : kBgRows);
+    for (int e = t; e < kBgRows * 64; e += kBlock) {
+      const int rr_ = e >> 6, c = e & 63;
+      sP[rr_][c] = rr_ < nr ? P[(rb + rr_) * 64 + c] : 0.0;
+      sQ[rr_][c] = rr_ < nr ? Q[(rb + rr_) * 64 + c] : 0.0;
+    }
+    __syncthreads();
+    if (r < nr) {
+      double dx[4] = {0.0, 0.0, 0.0, 0.0}, dr[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < 64; ++k) {
+        const double pk = sP[r][k], qk = sQ[r][k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          dx[j] += pk * sC[k][c0 + j];
+          dr[j] += qk * sC[k][c0 + j];
+        }
+      }
+      const int64_t o = (rb + r) * 64 + c0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        X[o + j] += dx[j];
+        const double rn = R[o + j] - dr[j];
+        R[o + j] = rn;
+        if (R32) R32[o + j] = (float)rn;
+        rr[j] += rn * rn;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) sRR[r][c0 + j] = rr[j];
+  __syncthreads();
+  if (t < 64) {
+    double v = 0.0;
+    for (int q = 0; q < kBgRows; ++q) v += sRR[q][t];
+    rr_part[(int64_t)t * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// P = Z + P D row by row (D: 64 x 64 row-major); each workgroup stages the
+// old rows of its range before writing them
+__global__ void __launch_bounds__(kBlock) k_bdir64(int64_t n, const double* __restrict__ Z,
+                                                   const double* __restrict__ D,
+                                                   double* __restrict__ P) {
+  __shared__ double sD[64][64];
+  __shared__ double sP[kBgRows][64];
+  const int t = threadIdx.x, r = t >> 4, c0 = 4 * (t & 15);
+  for (int e = t; e < 4096; e += kBlock) sD[e >> 6][e & 63] = D[e];
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per, r1 = r0 + per < n ? r0 + per : n;
+  for (int64_t rb = r0; rb < r1; rb += kBgRows) {
+    const int nr = (int)(r1 - rb < kBgRows ? r1 - rb : kBgRows);
+    for (int e = t; e < kBgRows * 64; e += kBlock) {
+      const int rr_ = e >> 6, c = e & 63;
+      sP[rr_][c] = rr_ < nr ? P[(rb + rr_) * 64 + c] : 0.0;
+    }
+    __syncthreads();
+    if (r < nr) {
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < 64; ++k) {
+        const double pk = sP[r][k];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) d[j] += pk * sD[k][c0 + j];
+      }
+      const int64_t o = (rb + r) * 64 + c0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) P[o + j] = Z[o + j] + d[j];
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace dev
 }  // namespace lsamg

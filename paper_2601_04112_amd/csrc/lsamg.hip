@@ -376,6 +376,10 @@ struct lsamg_handle {
   // per-column scalars summed from those partials (k_bsum)
   double *Bpq_s = nullptr, *Brr_s = nullptr, *Brz_s[2] = {nullptr, nullptr}, *Btmp_s = nullptr,
          *Bzq_s = nullptr;
+  // block CG (64 columns): Gram partials per workgroup, the summed 64 x 64
+  // matrices (G = P^T Q, F = P^T R or E = Q^T Z) and the step matrices C, D
+  double *Bg_part = nullptr, *Bg_G = nullptr, *Bg_F = nullptr, *Bg_C = nullptr;
+  double* Bg_host = nullptr;         // pinned: G, F and C (3 x 4096)
   int* Bactive = nullptr;            // 64 active, 64 restart, 64 new-direction flags
   int* Bactive_host = nullptr;       // pinned, the same three arrays
   double* Bparts_host = nullptr;     // pinned, 3 slots of kBNP * 64
@@ -432,6 +436,7 @@ struct lsamg_handle {
     dmmd_tuned = false;
     mm_part = nullptr;                 // freed with the batched buffers below
     mm_part_cap = 0;
+    Bg_part = Bg_G = Bg_F = Bg_C = nullptr;
     drop_graphs(true);
     for (void* ptr : ballocs) (void)hipFree(ptr);
     ballocs.clear();
@@ -461,6 +466,8 @@ struct lsamg_handle {
     Bactive_host = nullptr;
     if (Bparts_host) (void)hipHostFree(Bparts_host);
     Bparts_host = nullptr;
+    if (Bg_host) (void)hipHostFree(Bg_host);
+    Bg_host = nullptr;
     bytes = 0;
   }
 };
@@ -2924,21 +2931,14 @@ void bcg_apply(lsamg_handle* h, const double* Pv, double* Qv, double* pq_part, d
   bsum<NB>(pq_part, pq, s);
 }
 
-// Z = B R (one batched V-cycle), rho partials into Brz[cur], and the next
-// direction P = Z + beta P (P = Z when first); with restart_mask given, only
-// the masked columns take P = Z and the others keep P (their direction was
-// already formed from the same Z)
+// Z = B R (one batched V-cycle) and the rho partials of R . Z into Brz[cur];
+// with Qv given also the partials of -(Z . Qv) into Bzq
 template <int NB>
-void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
-                      const int* restart_mask = nullptr) {
+void bcg_z(lsamg_handle* h, hipStream_t s, int cur, const double* Qv) {
   DLevel& L0 = h->L[0];
   const int64_t n = L0.n;
   auto& B0 = h->BL[0];
   const bool stage = !L0.coarsest;
-  // flexible CG: beta_j = -(Z_j . Q_j) / (P_j . Q_j) with Q = A P of the
-  // directions just used (Bpq_s still holds P . Q from that A-apply)
-  const bool fcg = h->krylov == LSAMG_KRYLOV_FCG;
-  const double* Qv = fcg && !first ? (const double*)h->BQ : nullptr;
   if (h->precision == LSAMG_MIXED) {
     run_graph(h, 128 + NB, s,
               [&](hipStream_t gs) { bvcycle<float, NB>(h, 0, B0.fb, B0.fx, gs, false); });
@@ -2970,6 +2970,21 @@ void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
     }
   }
   LAUNCH_OK();
+}
+
+// Z = B R, rho per column into Brz_s[cur], and the next direction P = Z +
+// beta P (P = Z when first); with restart_mask given, only the masked
+// columns take P = Z and the others keep P (their direction was already
+// formed from the same Z)
+template <int NB>
+void bcg_precondition(lsamg_handle* h, hipStream_t s, bool first, int cur,
+                      const int* restart_mask = nullptr) {
+  const int64_t n = h->L[0].n;
+  // flexible CG: beta_j = -(Z_j . Q_j) / (P_j . Q_j) with Q = A P of the
+  // directions just used (Bpq_s still holds P . Q from that A-apply)
+  const bool fcg = h->krylov == LSAMG_KRYLOV_FCG;
+  const double* Qv = fcg && !first ? (const double*)h->BQ : nullptr;
+  bcg_z<NB>(h, s, cur, Qv);
   bsum<NB>(h->Brz[cur], h->Brz_s[cur], s);
   if (Qv) bsum<NB>(h->Bzq, h->Bzq_s, s);
   if (restart_mask) {
@@ -3288,6 +3303,206 @@ int pcg_batched(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld,
   return all ? LSAMG_OK : LSAMG_ENOCONV;
 }
 
+// Block PCG (O'Leary) on nr <= 64 columns: the A-orthogonalised form
+//   Q = A P, G = P^T Q, C = G^+ P^T R, X += P C, R -= Q C,
+//   Z = B R, D = -G^+ Q^T Z, P = Z + P D,
+// from P = Z = B R0; the 64 x 64 Gram matrices are summed on the device and
+// their pseudo-inverse step (eigenvalues at or below 1e-12 of the largest
+// dropped, so dependent directions leave the block) runs on the host.  All
+// columns iterate together; the stop test and the true-residual restart are
+// those of pcg_batched, taken when every nonzero column passes.  Unused
+// columns of the 64 are zero and drop out of the Gram matrices.
+constexpr int kBgBlocks = 512;         // workgroups of the Gram and update kernels
+
+int pcg_block(lsamg_handle* h, const double* b, double* x, int nr, int64_t ld, double tol,
+              int maxit, hipStream_t s, lsamg_stats* st) {
+  constexpr int NB = 64;
+  auto t0 = std::chrono::steady_clock::now();
+  ensure_batched(h, NB);
+  if (h->precision == LSAMG_MIXED && h->use_mfma) mm_tune_all<NB>(h, s);
+  if (h->precision == LSAMG_FP64 && h->use_mfma) fp64_tune(h, s);
+  if (!h->Bg_part) {
+    h->batch_alloc = true;
+    struct Reset {
+      lsamg_handle* h;
+      ~Reset() { h->batch_alloc = false; }
+    } reset{h};
+    h->Bg_part = h->alloc<double>((size_t)kBgBlocks * 4096);
+    h->Bg_G = h->alloc<double>(4096);
+    h->Bg_F = h->alloc<double>(4096);
+    h->Bg_C = h->alloc<double>(4096);
+  }
+  if (!h->Bg_host)
+    HIP_OK(hipHostMalloc((void**)&h->Bg_host, 3 * 4096 * sizeof(double), hipHostMallocDefault));
+  double* Gh = h->Bg_host;
+  double* Fh = Gh + 4096;
+  double* Ch = Fh + 4096;
+  const int64_t n = h->L[0].n, nn = n * NB;
+  const unsigned ge = nblocks(nn);
+  const bool mixed = h->precision == LSAMG_MIXED;
+  float* R32 = mixed ? h->BL[0].fb : nullptr;
+  auto gram = [&](const double* A, const double* B, double* out) {
+    {
+      PROF("k_bgram64", 16.0 * nn + 8.0 * kBgBlocks * 4096, s);
+      KLAUNCH(kBgBlocks, dev::kBlock, 0, s, dev::k_bgram64, n, A, B, h->Bg_part);
+      LAUNCH_OK();
+    }
+    KLAUNCH0(16, dev::kBlock, 0, s, dev::k_bgram_sum, kBgBlocks, (const double*)h->Bg_part, out);
+    LAUNCH_OK();
+  };
+  auto fetch = [&](const double* dsrc, double* hdst) {
+    HIP_OK(hipMemcpyAsync(hdst, dsrc, 4096 * sizeof(double), hipMemcpyDeviceToHost, s));
+  };
+  auto step_matrix = [&](const double* F, double sign) {   // Ch = sign G^+ F, uploaded
+    if (gram_pinv_apply(NB, Gh, F, Ch, 1e-12) < 0)
+      throw DevError{LSAMG_ENOTSPD, "block CG: Gram eigen-decomposition did not converge"};
+    if (sign < 0)
+      for (int e = 0; e < 4096; ++e) Ch[e] = -Ch[e];
+    HIP_OK(hipMemcpyAsync(h->Bg_C, Ch, 4096 * sizeof(double), hipMemcpyHostToDevice, s));
+  };
+  // B (internal numbering, zero beyond nr), X = 0, R = B
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_in<NB>, n, nr, ld, (const int64_t*)h->perm, b,
+           h->BBi);
+  LAUNCH_OK();
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_fill, nn, 0.0, h->BX);
+  LAUNCH_OK();
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_copy, nn, (const double*)h->BBi, h->BR);
+  LAUNCH_OK();
+  if (mixed) {
+    KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_convert<double, float>, nn, (const double*)h->BR, R32);
+    LAUNCH_OK();
+  }
+  auto col_sums = [&](double* out) {   // per-column sums of h->Btmp partials (kBNP each)
+    bsum<NB>(h->Btmp, h->Btmp_s, s);
+    bparts_to_host(h, h->Btmp_s, NB, 0, s);
+    HIP_OK(hipStreamSynchronize(s));
+    bhost_sums(h, NB, 0, out);
+  };
+  double nb2[NB], nb[NB];
+  KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bdot<NB>, n, (const double*)h->BBi,
+           (const double*)h->BBi, h->Btmp);
+  LAUNCH_OK();
+  col_sums(nb2);
+  bool any = false;
+  for (int j = 0; j < NB; ++j) {
+    if (!std::isfinite(nb2[j])) throw DevError{LSAMG_EBADINPUT, "non-finite entry in a right-hand side"};
+    nb[j] = std::sqrt(nb2[j]);
+    any = any || (j < nr && nb[j] > 0.0);
+  }
+  auto precondition_into_p = [&]() {   // Z = B R, P = Z
+    bcg_z<NB>(h, s, 0, nullptr);
+    KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_copy, nn, (const double*)h->BZ, h->BP);
+    LAUNCH_OK();
+  };
+  int its = 0, restarts = 0;
+  bool conv = !any;
+  double rn[NB], tr[NB];
+  for (int j = 0; j < NB; ++j) rn[j] = tr[j] = nb[j];
+  if (!conv && maxit > 0) precondition_into_p();
+  while (!conv && its < maxit) {
+    bcg_apply<NB>(h, h->BP, h->BQ, h->Bpq, h->Bpq_s, s);            // Q = A P
+    gram(h->BP, h->BQ, h->Bg_G);
+    gram(h->BP, h->BR, h->Bg_F);
+    fetch(h->Bg_G, Gh);
+    fetch(h->Bg_F, Fh);
+    HIP_OK(hipStreamSynchronize(s));
+    step_matrix(Fh, 1.0);                                             // C = G^+ P^T R
+    {
+      PROF("k_bupd64", 8.0 * nn * (mixed ? 6.5 : 6.0) + 8.0 * 4096, s);
+      KLAUNCH(kBgBlocks, dev::kBlock, 0, s, dev::k_bupd64, n, (const double*)h->BP,
+              (const double*)h->BQ, (const double*)h->Bg_C, h->BX, h->BR, R32, h->Btmp);
+      LAUNCH_OK();
+    }
+    ++its;
+    {                                   // the update wrote kBgBlocks partials per column
+      PROF("k_bsum", 8.0 * (kBgBlocks + 1) * NB, s);
+      KLAUNCH(NB, dev::kBlock, 0, s, dev::k_bsum<NB>, kBgBlocks, (const double*)h->Btmp,
+              h->Btmp_s);
+      LAUNCH_OK();
+    }
+    bparts_to_host(h, h->Btmp_s, NB, 0, s);
+    HIP_OK(hipStreamSynchronize(s));
+    double rr[NB];
+    bhost_sums(h, NB, 0, rr);
+    bool pass = true;
+    for (int j = 0; j < nr; ++j) {
+      rn[j] = std::sqrt(rr[j]);
+      if (!std::isfinite(rn[j])) throw DevError{LSAMG_ENOTSPD, "block CG breakdown (non-finite residual)"};
+      pass = pass && (nb[j] == 0.0 || rn[j] <= tol * nb[j]);
+    }
+    if (pass) {
+      // true residuals b - A x (A x into BZ)
+      bcg_apply<NB>(h, h->BX, h->BZ, h->Btmp, h->Btmp_s, s);
+      KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, n, (const double*)h->BBi,
+               (const double*)h->BZ, h->Btmp);
+      LAUNCH_OK();
+      double t2[NB];
+      col_sums(t2);
+      bool tpass = true;
+      for (int j = 0; j < nr; ++j) {
+        tr[j] = std::sqrt(t2[j]);
+        tpass = tpass && (nb[j] == 0.0 || tr[j] <= tol * nb[j]);
+      }
+      if (tpass) {
+        conv = true;
+        break;
+      }
+      if (its >= maxit) break;
+      // restart from the true residual: R = B - A X, P = Z = B R
+      KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_sub, nn, (const double*)h->BBi, (const double*)h->BZ,
+               h->BR);
+      LAUNCH_OK();
+      if (mixed) {
+        KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_convert<double, float>, nn, (const double*)h->BR, R32);
+        LAUNCH_OK();
+      }
+      ++restarts;
+      precondition_into_p();
+      continue;
+    }
+    if (its >= maxit) break;
+    bcg_z<NB>(h, s, 0, nullptr);                                      // Z = B R
+    gram(h->BQ, h->BZ, h->Bg_F);                                      // E = Q^T Z
+    fetch(h->Bg_F, Fh);
+    HIP_OK(hipStreamSynchronize(s));
+    step_matrix(Fh, -1.0);                                            // D = -G^+ E
+    {
+      PROF("k_bdir64", 8.0 * nn * 3 + 8.0 * 4096, s);
+      KLAUNCH(kBgBlocks, dev::kBlock, 0, s, dev::k_bdir64, n, (const double*)h->BZ,
+              (const double*)h->Bg_C, h->BP);
+      LAUNCH_OK();
+    }
+  }
+  if (!conv) {                           // true residuals of the final iterate
+    bcg_apply<NB>(h, h->BX, h->BZ, h->Btmp, h->Btmp_s, s);
+    KLAUNCH0(kBNP, dev::kBlock, 0, s, dev::k_bres_parts<NB>, n, (const double*)h->BBi,
+             (const double*)h->BZ, h->Btmp);
+    LAUNCH_OK();
+    double t2[NB];
+    col_sums(t2);
+    for (int j = 0; j < nr; ++j) tr[j] = std::sqrt(t2[j]);
+  }
+  KLAUNCH0(ge, dev::kBlock, 0, s, dev::k_bperm_out<NB>, n, nr, ld, (const int64_t*)h->perm,
+           (const double*)h->BX, x);
+  LAUNCH_OK();
+  HIP_OK(hipStreamSynchronize(s));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool all = true;
+  for (int j = 0; j < nr; ++j) {
+    const bool cj = nb[j] == 0.0 || tr[j] <= tol * nb[j];
+    all = all && cj;
+    if (!st) continue;
+    st[j].iters = its;
+    st[j].converged = cj ? 1 : 0;
+    st[j].rel_res = nb[j] > 0 ? rn[j] / nb[j] : 0.0;
+    st[j].true_rel_res = nb[j] > 0 ? tr[j] / nb[j] : 0.0;
+    st[j].rho = (its > 0 && nb[j] > 0) ? std::pow(rn[j] / nb[j], 1.0 / its) : 0.0;
+    st[j].restarts = restarts;
+    st[j].seconds = secs;
+  }
+  return all ? LSAMG_OK : LSAMG_ENOCONV;
+}
+
 // Y = B X for nr <= NB columns through the multi-right-hand-side V-cycle
 // (the preconditioner step of pcg_batched), user numbering in and out.
 template <int NB>
@@ -3429,8 +3644,11 @@ int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64
     } else {
       for (int32_t c0 = 0; c0 < nrhs; c0 += kBMax) {
         const int nr = std::min<int32_t>(kBMax, nrhs - c0);
-        int r1 = solve_batched(h, b + (size_t)c0 * ld, x + (size_t)c0 * ld, nr, ld, tol, maxit, s,
-                               stats ? stats + c0 : nullptr);
+        int r1 = h->krylov == LSAMG_KRYLOV_BLOCK
+                     ? pcg_block(h, b + (size_t)c0 * ld, x + (size_t)c0 * ld, nr, ld, tol, maxit, s,
+                                 stats ? stats + c0 : nullptr)
+                     : solve_batched(h, b + (size_t)c0 * ld, x + (size_t)c0 * ld, nr, ld, tol,
+                                     maxit, s, stats ? stats + c0 : nullptr);
         if (r1 != LSAMG_OK) rc = r1;
       }
     }
@@ -3592,8 +3810,9 @@ int lsamg_apply_vcycle_batch(lsamg_handle* h, const double* X, double* Y, int32_
 int lsamg_set_option(lsamg_handle* h, int32_t opt, int64_t value) {
   if (!h || value < 0 || (opt == LSAMG_OPT_DENSE_SPLIT && value > 17) ||
       (opt == LSAMG_OPT_BGROUP && value > 2) || (opt == LSAMG_OPT_ATA_TILES && value > 3) ||
+      (opt == LSAMG_OPT_KRYLOV && value > 2) ||
       (opt != LSAMG_OPT_MFMA_TILE && opt != LSAMG_OPT_DENSE_SPLIT && opt != LSAMG_OPT_BGROUP &&
-       opt != LSAMG_OPT_ATA_TILES && value > 1))
+       opt != LSAMG_OPT_ATA_TILES && opt != LSAMG_OPT_KRYLOV && value > 1))
     return fail_with(LSAMG_EINVAL, "bad argument");
   if (opt == LSAMG_OPT_BATCHED) {
     h->batch_mode = (int)value;

@@ -24,7 +24,7 @@ AGG_LATTICE, AGG_STANDARD = 0, 1
 CYCLE_V, CYCLE_ADDITIVE = 0, 1
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
 OPT_ATA_TILES, OPT_BGROUP, OPT_KRYLOV = 6, 7, 8
-KRYLOV_CG, KRYLOV_FCG = 0, 1
+KRYLOV_CG, KRYLOV_FCG, KRYLOV_BLOCK = 0, 1, 2
 
 ERROR_NAMES = {0: "OK", -1: "EINVAL", -2: "EBADINPUT", -3: "ENOTSPD",
                -4: "ENOMEM", -5: "EHIP", -6: "ENOCONV", -7: "ENODEV"}
@@ -348,8 +348,8 @@ class Solver:
         (0 off, 1 per precision, 2 row form, 3 expanded form), OPT_MFMA_TILE
         (0: autotune, else 100*rt + 10*u + split) or OPT_DENSE_SPLIT (0: autotune,
         1..16: LDS-staged dense GEMM with that many loop ranges, 17: never) or OPT_BGROUP
-        (0: autotune, 1: row-group pass, 2: CSR passes) or OPT_KRYLOV (KRYLOV_CG or
-        KRYLOV_FCG: flexible CG)."""
+        (0: autotune, 1: row-group pass, 2: CSR passes) or OPT_KRYLOV (KRYLOV_CG,
+        KRYLOV_FCG: flexible CG, or KRYLOV_BLOCK: block CG on batches of columns)."""
         _check(load().lsamg_set_option(self._h, opt, int(value)))
 
     # -- kernel timing ----------------------------------------------------

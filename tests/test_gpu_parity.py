@@ -961,3 +961,42 @@ def test_additive_cycle(rot_add):
         assert stm[0]["iters"] <= math.ceil(1.10 * K)
     finally:
         s.set_precision(L.FP64)
+
+
+@pytest.mark.parametrize("which", ["rot", "rot_tail"])
+def test_block_cg(which, request):
+    """Block CG (LSAMG_KRYLOV_BLOCK) on 20 columns (44 zero columns of the
+    64-column block drop out through the pseudo-inverse): the FP64 iterate
+    after 4 iterations equals the oracle's block PCG to 1e-10; the converged
+    solve reaches the tolerance on every column's true residual within the
+    oracle's block iteration count + 1 (FP64) and within the CG count
+    (mixed); a zero right-hand side stays zero."""
+    p, H, s = request.getfixturevalue(which)
+    X = np.stack([P.rhs_uniform(p.n, 700 + j) for j in range(20)])
+    X[5] = 0.0
+    A = H.levels[0].A
+    Xo4, _ = O.block_pcg(H, X.T, fixed_iters=4)
+    Xo, info = O.block_pcg(H, X.T, tol=1e-8)
+    _, ic = O.pcg(H, X[0], tol=1e-8)
+    s.set_option(L.OPT_KRYLOV, L.KRYLOV_BLOCK)
+    try:
+        s.set_precision(L.FP64)
+        Xg, st = s.solve(dvec(X), tol=0.0, maxit=4)
+        Xh = host(Xg)
+        assert all(st[j]["iters"] == 4 for j in range(20))
+        e = rel(Xh.T, Xo4)
+        assert e <= vtol(H), e
+        for prec, cap in ((L.FP64, info["iters"] + 1), (L.MIXED, ic["iters"])):
+            s.set_precision(prec)
+            Xg, st = s.solve(dvec(X), tol=1e-8, maxit=200)
+            Xh = host(Xg)
+            assert np.all(Xh[5] == 0.0)
+            for j in range(20):
+                if j == 5:
+                    continue
+                r = np.linalg.norm(X[j] - A @ Xh[j]) / np.linalg.norm(X[j])
+                assert st[j]["converged"] == 1 and r <= 1e-8, (prec, j, r)
+                assert st[j]["iters"] <= cap, (prec, st[j]["iters"], cap)
+    finally:
+        s.set_option(L.OPT_KRYLOV, L.KRYLOV_CG)
+        s.set_precision(L.FP64)
