@@ -87,6 +87,9 @@ struct GemvPlan {
   int NW = 4;          // wide form: wavefronts per workgroup (default from the task count)
   mutable int nw_t[2] = {0, 0};   // wide form, autotuned per precision (double, float); 0: NW
   mutable int form_t = 0;         // FP32 wide form: 0 one output per lane, 1 four (k_gemv_wide4)
+  // residual consumers of the finest level (narrow forms), per precision:
+  // 0 untimed, 1 r = b - G^T y in its own pass, 2 formed while staging inputs
+  mutable int rsep_t[2] = {0, 0};
   mutable int narrow_t[2] = {1, 1};  // G > 0: the form timed fastest: 0 wide, 1 narrow
                                      // (a wavefront per aggregate), 2 an aggregate per
                                      // lane group, 3 16-byte loads (k_gemv_narrow4)
@@ -1415,13 +1418,41 @@ void gemv_resid(DLevel& L, const GemvPlan& Pl, const T* M, const T* b, T* out, h
     resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, P.r, s, L.nnz, L.nrows);
     gemv<T, dev::IN_DIRECT, ADD>(Pl, sp, M, P.r, out, s);
   } else {
+    // the narrow forms can form r(omega_i) while staging their inputs, or
+    // read r from its own pass: the first solve of each precision times both
+    const int pi = sizeof(T) == sizeof(float) ? 1 : 0;
     sp.idx = L.gt_col;
     sp.ptr = L.gt_ptr;
     sp.v1 = P.gt_val;
     sp.v2 = P.y;
-    gemv<T, dev::IN_RESG, ADD>(Pl, sp, M, b, out, s,
-                               (int64_t)(sizeof(T) + 4) * L.nnz + 8 * (L.n + 1) +
-                                   sizeof(T) * L.nrows);
+    auto on_the_fly = [&]() {
+      gemv<T, dev::IN_RESG, ADD>(Pl, sp, M, b, out, s,
+                                 (int64_t)(sizeof(T) + 4) * L.nnz + 8 * (L.n + 1) +
+                                     sizeof(T) * L.nrows);
+    };
+    auto separate = [&]() {
+      resid_csr<T>(L.n, L.lanes_gt, L.gt_ptr, L.gt_col, P.gt_val, P.y, b, P.r, s, L.nnz, L.nrows);
+      gemv<T, dev::IN_DIRECT, ADD>(Pl, no_spec<T>(), M, P.r, out, s);
+    };
+    if (Pl.rsep_t[pi] == 0 && g_gvtune && !g_rec) {
+      on_the_fly();                     // fixes the GEMV form first
+      float best[2] = {1e30f, 1e30f};
+      for (int f = 0; f < 2; ++f)
+        for (int round = 0; round < 2; ++round) {
+          HIP_OK(hipEventRecord(g_gvtune->e0, s));
+          for (int r = 0; r < 3; ++r) f == 0 ? on_the_fly() : separate();
+          HIP_OK(hipEventRecord(g_gvtune->e1, s));
+          HIP_OK(hipEventSynchronize(g_gvtune->e1));
+          float t = 0.f;
+          HIP_OK(hipEventElapsedTime(&t, g_gvtune->e0, g_gvtune->e1));
+          best[f] = std::min(best[f], t);
+        }
+      Pl.rsep_t[pi] = best[1] < best[0] ? 1 : 2;
+    }
+    if (Pl.rsep_t[pi] == 1)
+      separate();
+    else
+      on_the_fly();
   }
 }
 
