@@ -135,13 +135,17 @@ struct GemvOp {
   const int32_t* ll;     // [nagg] input length (loop dimension)
   const int64_t* ibase;  // [nagg] input base (index-list base for IN_GATHER)
   const int64_t* obase;  // [nagg] output base
-  int pad;               // != 0: rows of M_a padded to a multiple of 4 entries
+  int pad;               // rows of M_a: 0 unpadded, 1 padded to a multiple of 4
+                         // entries, else to a multiple of pad (a multiple of 4)
 };
 
-// Row stride of M_a: lj, or lj rounded up to a multiple of 4 (padded
-// layout: every row starts 16-byte aligned for FP32, and the padding is zero).
+// Row stride of M_a: lj, or lj rounded up to a multiple of 4 or of pad
+// (padded layout: every row starts 16-byte aligned, or on a 128-byte line
+// for pad 32 in FP32, and the padding is zero).
 __device__ __forceinline__ int64_t mrow(int nj, int pad) {
-  return pad ? (int64_t)((nj + 3) & ~3) : (int64_t)nj;
+  if (pad == 0) return nj;
+  if (pad == 1) return (int64_t)((nj + 3) & ~3);
+  return (int64_t)((nj + pad - 1) / pad) * pad;
 }
 
 // Where the input vector entries come from (MODE):
@@ -373,7 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_gemv_narrow4(int64_t nagg, GemvOp op
     LG = 64 / Q;
     g = lane / Q;
     q = lane % Q;
-    ld = mrow(nj, 1);
+    ld = mrow(nj, op.pad);
     m = M + op.moff[a] + V * q;
     // the first U rows of the lane do not depend on the staged input
 #pragma unroll
@@ -523,7 +527,7 @@ __global__ void __launch_bounds__(NW * 64) k_gemv_wide4(const int32_t* __restric
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = j0 + 4 * lane;
   const bool jv = j < nj;
-  const int64_t ld = mrow(nj, 1);
+  const int64_t ld = mrow(nj, op.pad);
   const float* m = M + op.moff[a] + (jv ? j : 0);
   constexpr int U = 8;
   const f32x4 zero = {0.f, 0.f, 0.f, 0.f};

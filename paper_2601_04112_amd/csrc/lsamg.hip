@@ -846,23 +846,38 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     D.max_k = std::max<int>(D.max_k, HL.k[a]);
   }
   // device layouts of Z_i (row-major for RAS-T, column-major for RAS) and of
-  // Zhat_i (row-major for P^T, column-major for P): every row padded to a
-  // multiple of 4 entries with zeros and every block starting at a multiple
-  // of 4 entries, so each row starts 16-byte aligned (FP32)
-  auto pad4 = [](int64_t v) { return (v + 3) & ~(int64_t)3; };
+  // Zhat_i (row-major for P^T, column-major for P): every row padded with
+  // zeros to a multiple of 4 entries, and every block starting at a multiple
+  // of 4 entries, so each row starts 16-byte aligned; an operator with rows
+  // longer than 256 entries (the wide forms split them into several output
+  // slices) pads its rows to 32 entries instead, so each row starts on a
+  // 128-byte line and neighbouring slices share no line
+  int64_t max_nw = 1, max_nO = 1, max_k = 1;
+  for (int64_t a = 0; a < HL.nagg; ++a) {
+    max_nw = std::max<int64_t>(max_nw, HL.astart[a + 1] - HL.astart[a]);
+    max_nO = std::max<int64_t>(max_nO, HL.optr[a + 1] - HL.optr[a]);
+    max_k = std::max<int64_t>(max_k, HL.k[a]);
+  }
+  const int64_t pr_ = max_nO > 256 ? 32 : 4, pc_ = max_nw > 256 ? 32 : 4,
+                ph_ = max_k > 256 ? 32 : 4;
+  auto padto = [](int64_t v, int64_t q) { return (v + q - 1) / q * q; };
+  auto padr = [&](int64_t v) { return padto(v, pr_); };   // rows of Omega_i entries
+  auto padc = [&](int64_t v) { return padto(v, pc_); };   // rows of omega_i entries
+  auto padh = [&](int64_t v) { return padto(v, ph_); };   // rows of k_i entries
+  auto opad = [](int64_t q) { return q == 4 ? 1 : (int)q; };
   std::vector<int64_t> offr(HL.nagg), offc(HL.nagg), offh(HL.nagg), offt(HL.nagg);
   int64_t totr = 0, totc = 0, toth = 0, tott = 0;
   for (int64_t a = 0; a < HL.nagg; ++a) {
     const int64_t nw = HL.astart[a + 1] - HL.astart[a], nO = HL.optr[a + 1] - HL.optr[a],
                   k = HL.k[a];
     offr[a] = totr;
-    totr += nw * pad4(nO);
+    totr += nw * padr(nO);
     offc[a] = totc;
-    totc += nO * pad4(nw);
+    totc += nO * padc(nw);
     offh[a] = toth;
-    toth += nw * pad4(k);
+    toth += nw * padh(k);
     offt[a] = tott;
-    tott += k * pad4(nw);
+    tott += k * padc(nw);
   }
   std::vector<double> Zr(totr, 0.0), Zc(totc, 0.0), Zh(toth, 0.0), ZhT(tott, 0.0);
   for (int64_t a = 0; a < HL.nagg; ++a) {
@@ -872,12 +887,12 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     const double* zh = HL.Zhat.data() + HL.poff[a];    // host: |omega| x k row-major
     for (int64_t p = 0; p < nw; ++p) {
       for (int64_t c = 0; c < nO; ++c) {
-        Zr[offr[a] + p * pad4(nO) + c] = z[p * nO + c];
-        Zc[offc[a] + c * pad4(nw) + p] = z[p * nO + c];
+        Zr[offr[a] + p * padr(nO) + c] = z[p * nO + c];
+        Zc[offc[a] + c * padc(nw) + p] = z[p * nO + c];
       }
       for (int64_t t = 0; t < k; ++t) {
-        Zh[offh[a] + p * pad4(k) + t] = zh[p * k + t];
-        ZhT[offt[a] + t * pad4(nw) + p] = zh[p * k + t];
+        Zh[offh[a] + p * padh(k) + t] = zh[p * k + t];
+        ZhT[offt[a] + t * padc(nw) + p] = zh[p * k + t];
       }
     }
   }
@@ -889,14 +904,14 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     int64_t tota = 0;
     for (int64_t a = 0; a < HL.nagg; ++a) {
       offa[a] = tota;
-      tota += (HL.optr[a + 1] - HL.optr[a]) * pad4(HL.optr[a + 1] - HL.optr[a]);
+      tota += (HL.optr[a + 1] - HL.optr[a]) * padr(HL.optr[a + 1] - HL.optr[a]);
     }
     As.assign(tota, 0.0);
     for (int64_t a = 0; a < HL.nagg; ++a) {
       const int64_t nO = HL.optr[a + 1] - HL.optr[a];
       const double* z = HL.Ainv_loc.data() + HL.aoff[a];
       for (int64_t l = 0; l < nO; ++l)
-        for (int64_t j = 0; j < nO; ++j) As[offa[a] + l * pad4(nO) + j] = z[l * nO + j];
+        for (int64_t j = 0; j < nO; ++j) As[offa[a] + l * padr(nO) + j] = z[l * nO + j];
     }
   }
   // cover lists for the RAS-T gather: for unknown j, staging positions
@@ -944,8 +959,8 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
   int64_t* d_c0 = h->upload(c0);
   auto plan = [&](GemvPlan& P, const std::vector<int32_t>& lj, const std::vector<int32_t>& ll,
                   int32_t* dlj, int32_t* dll, int64_t* moff, int64_t* ib, int64_t* ob,
-                  int64_t in_unique, bool gathered) {
-    P.op = dev::GemvOp{moff, dlj, dll, ib, ob, 1};
+                  int64_t in_unique, bool gathered, int pad) {
+    P.op = dev::GemvOp{moff, dlj, dll, ib, ob, pad};
     P.nagg = HL.nagg;
     P.hlj = lj;
     P.hll = ll;
@@ -991,14 +1006,14 @@ void upload_level(lsamg_handle* h, const Level& HL, DLevel& D, bool finest) {
     while (P.NW < 16 && P.ntask * P.NW < 4096) P.NW <<= 1;
   };
   const int64_t ncoarse = HL.cstart[HL.nagg];
-  plan(D.ras, nw, nO, d_nw, d_nO, d_offc, d_o0, d_w0, D.n, true);
-  plan(D.rast, nO, nw, d_nO, d_nw, d_offr, d_w0, d_o0, D.n, false);
-  plan(D.rst, kk, nw, d_k, d_nw, d_offh, d_w0, d_c0, D.n, false);
-  plan(D.pro, nw, kk, d_nw, d_k, d_offt, d_c0, d_w0, ncoarse, false);
+  plan(D.ras, nw, nO, d_nw, d_nO, d_offc, d_o0, d_w0, D.n, true, opad(pc_));
+  plan(D.rast, nO, nw, d_nO, d_nw, d_offr, d_w0, d_o0, D.n, false, opad(pr_));
+  plan(D.rst, kk, nw, d_k, d_nw, d_offh, d_w0, d_c0, D.n, false, opad(ph_));
+  plan(D.pro, nw, kk, d_nw, d_k, d_offt, d_c0, d_w0, ncoarse, false, opad(pc_));
   if (additive) {
     D.d.As = h->upload_f<double>(As);
     D.f.As = h->upload_f<float>(As);
-    plan(D.as, nO, nO, d_nO, d_nO, h->upload(offa), d_o0, d_o0, D.n, true);
+    plan(D.as, nO, nO, d_nO, d_nO, h->upload(offa), d_o0, d_o0, D.n, true, opad(pr_));
   }
   if (finest) {      // inputs of P^T and RAS-T are residual rows omega_a formed on the fly
     int64_t em = 0;
