@@ -479,7 +479,7 @@ def main():
         for r in bkl:
             nm = r["name"]
             if (r["flops"] > 0 and r["launches"] and (" @L1" in nm or " @L2" in nm)
-                    and nm.split("<")[0] in ("k_bmm", "k_bmm_lds", "k_bmmd", "k_bgemm")):
+                    and nm.split("<")[0] in ("k_bmm", "k_bmm_lds", "k_bmmd", "k_bmmd_lds", "k_bgemm")):
                 us = r["ms"] / r["launches"] * 1e3
                 tf = r["flops"] / (r["ms"] * 1e-3) / 1e12
                 mfma_levels.append(dict(kernel=nm, avg_launch_us=round(us, 2),

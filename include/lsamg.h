@@ -323,8 +323,9 @@ enum {
                              aggregate-block operators of a batch run on the
                              FP64 matrix cores or on FMA, whichever the
                              autotuner times faster; a fixed shape makes them all
-                             FP64 matrix-core tasks with its rt and u (u = 0, and
-                             u with rt = 4: 2), no split                         */
+                             FP64 matrix-core tasks with its rt and u (u with
+                             rt = 4: 2; u = 0: the LDS-staged form on 64-row
+                             tasks), no split                                    */
   LSAMG_OPT_ONEPASS_ATA = 4, /* 1 (default): where the rows of G are short (a
                              finite-difference G), the FP64 A-apply G^T (G P) of
                              the multi-right-hand-side CG recomputes each row of G

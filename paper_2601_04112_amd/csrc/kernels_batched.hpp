@@ -666,6 +666,99 @@ __global__ void __launch_bounds__(kBlock) k_bmmd(MmTasks tk, int ntask, GemvOp o
   }
 }
 
+// k_bmmd on 64 columns with the input rows staged in LDS: a workgroup per
+// task (aggregate a, 64 output rows j0 .. j0+63, the whole loop), its four
+// waves 16 rows each.  The loop runs in chunks of 32 input rows (formed per
+// MODE as in k_bmmd), staged once per workgroup instead of once per wave
+// and double-buffered, the next chunk's loads issued before the current
+// chunk's MFMAs.  Operands and result lanes as k_bmmd with CT = 4: lane
+// (i, g) of wave w feeds A[i][g] = M[k + g][j0 + 16 w + i] and B[g][i] =
+// column 4 i + q of input row k + g for column tile q; result register v of
+// lane group g holds output row j0 + 16 w + g + 4 v, columns 4 i .. 4 i + 3.
+template <int MODE, bool ADD>
+__global__ void __launch_bounds__(kBlock) k_bmmd_lds(MmTasks tk, GemvOp op,
+                                                     const int32_t* __restrict__ gidx,
+                                                     const int64_t* __restrict__ cptr,
+                                                     const int64_t* __restrict__ cpos,
+                                                     const double* __restrict__ tb,
+                                                     const double* __restrict__ M,
+                                                     const double* __restrict__ in,
+                                                     double* __restrict__ out) {
+  typedef double f64x4 __attribute__((ext_vector_type(4)));
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  constexpr int KC = 32, SB = 64 + 2, KS = KC / 4;
+  __shared__ __attribute__((aligned(16))) double sB[2][KC * SB];
+  const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+  const int a = tk.a[t], j0 = tk.j0[t], k0 = tk.k0[t], k1 = tk.k1[t];
+  const int nj = op.lj[a];
+  const int64_t ib = op.ibase[a];
+  const double* __restrict__ m = M + op.moff[a];
+  const int64_t ld = mrow(nj, op.pad);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i = lane & 15, g = lane >> 4;
+  const int jr = j0 + 16 * w + i;            // this lane's output row (A operand row)
+  const bool jv = jr < nj;
+  const int sr = threadIdx.x >> 3, sc = 8 * (threadIdx.x & 7);   // staging: row sr, 8 columns
+  const f64x4 zero = {0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[4] = {zero, zero, zero, zero};
+  f64x2 bst[4];
+  double am[KS];
+  auto load_chunk = [&](int kb) {
+    const int l = kb + sr;
+    const f64x2 z2 = {0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) bst[c] = z2;
+    if (l < k1) {
+      const int64_t e = ib + l;
+      const int64_t row = MODE == IN_GATHER ? (int64_t)gidx[e] : e;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) bst[c] = *(const f64x2*)(in + row * 64 + sc + 2 * c);
+      if (MODE == IN_TB) {
+        for (int64_t p = cptr[e]; p < cptr[e + 1]; ++p)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) bst[c] += *(const f64x2*)(tb + cpos[p] * 64 + sc + 2 * c);
+      }
+    }
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const int lk = kb + 4 * st + g;
+      am[st] = (jv && lk < k1) ? m[(int64_t)lk * ld + jr] : 0.0;
+    }
+  };
+  int buf = 0;
+  if (k0 < k1) load_chunk(k0);
+  for (int kb = k0; kb < k1; kb += KC) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) *(f64x2*)(sB[buf] + sr * SB + sc + 2 * c) = bst[c];
+    double av[KS];
+#pragma unroll
+    for (int st = 0; st < KS; ++st) av[st] = am[st];
+    __syncthreads();
+    if (kb + KC < k1) load_chunk(kb + KC);    // in flight during this chunk's MFMAs
+#pragma unroll
+    for (int st = 0; st < KS; ++st) {
+      const double* bp = sB[buf] + (4 * st + g) * SB + 4 * i;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bp[q], acc[q], 0, 0, 0);
+    }
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int jj = j0 + 16 * w + g + 4 * v;
+    if (jj >= nj) continue;
+    double* d = out + (op.obase[a] + jj) * 64 + 4 * i;
+    f64x2 o0 = {acc[0][v], acc[1][v]}, o1 = {acc[2][v], acc[3][v]};
+    if (ADD) {
+      o0 += *(const f64x2*)d;
+      o1 += *(const f64x2*)(d + 2);
+    }
+    *(f64x2*)d = o0;
+    *(f64x2*)(d + 2) = o1;
+  }
+}
+
 // k_bmm on 64 columns with the input rows staged in LDS: a workgroup per
 // task (aggregate a, 64 output rows j0 .. j0+63, loop range [k0, k1), slot),
 // its four waves 16 rows each.  The loop runs in chunks of 32 input rows

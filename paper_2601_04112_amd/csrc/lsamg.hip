@@ -2129,6 +2129,15 @@ void bgemm(const GemvPlan& P, const int32_t* gidx, const int64_t* cptr, const in
     }
   }
   if constexpr (std::is_same<T, double>::value && NB >= 16) {
+    if (NB == 64 && P.mmd.rt > 0 && P.mmd.lds) {
+      const GemvPlan::Mm& mm = P.mmd;
+      PROF_F(kname("k_bmmd_lds", std::to_string(MODE) + ", " + (ADD ? "true" : "false")), bytes,
+             2.0 * (double)P.mat * NB, s);
+      KLAUNCH((unsigned)mm.ntask, dev::kBlock, 0, s, dev::k_bmmd_lds<MODE, ADD>, mm.tk, P.op, gidx,
+              cptr, cpos, tb, M, in, out);
+      LAUNCH_OK();
+      return;
+    }
     if (P.mmd.rt > 0) {
       const GemvPlan::Mm& mm = P.mmd;
       PROF_F(kname("k_bmmd", std::to_string(MODE) + ", " + (ADD ? "true" : "false") + ", " +
@@ -2419,9 +2428,9 @@ float time_runs(hipStream_t s, F&& run) {
 
 // One FP64 aggregate-block operator on the matrix cores: the FMA k_bgemm
 // against k_bmmd (tasks of 1, 2 or 4 row tiles of 16; 2 or 8 loop steps'
-// loads together, 2 with 4 row tiles), timed on the level's own matrices and
-// buffers; the fastest is kept in P.mmd (task lists live with the batched
-// buffers).
+// loads together, 2 with 4 row tiles) and the LDS-staged k_bmmd_lds (64-row
+// tasks), timed on the level's own matrices and buffers; the fastest is kept
+// in P.mmd (task lists live with the batched buffers).
 template <int MODE, bool ADD>
 void mmd_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* cptr,
               const int64_t* cpos, const double* tb, const double* M, const double* in,
@@ -2429,9 +2438,11 @@ void mmd_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
   P.mmd = GemvPlan::Mm{};
   if (P.nagg == 0 || P.hlj.empty()) return;
   if (h->mm_fixed > 0) {              // a fixed tile shape: its row tiles and loads in flight
-    const int rt = h->mm_fixed / 100;
-    P.mmd = mm_build(h, P, rt, 1, false);
-    P.mmd.u = (h->mm_fixed / 10) % 10 == 8 && rt < 4 ? 8 : 2;
+    const int rt = h->mm_fixed / 100, u = (h->mm_fixed / 10) % 10;
+    const bool lds = u == 0;           // u = 0: the LDS-staged form, 64-row tasks
+    P.mmd = mm_build(h, P, lds ? 4 : rt, 1, false);
+    P.mmd.u = u == 8 && rt < 4 ? 8 : 2;
+    P.mmd.lds = lds;
     return;
   }
   auto run = [&] { bgemm<double, MODE, ADD, 64>(P, gidx, cptr, cpos, tb, M, in, out, s); };
@@ -2444,6 +2455,15 @@ void mmd_tune(lsamg_handle* h, GemvPlan& P, const int32_t* gidx, const int64_t* 
       if (u == 8 && (llmax <= 32 || rt == 4)) continue;
       P.mmd = mm;
       P.mmd.u = u;
+      const float t = time_runs(s, run);
+      if (t < best) {
+        best = t;
+        pick = P.mmd;
+      }
+    }
+    if (rt == 4) {                     // the same tasks, staged through LDS
+      P.mmd = mm;
+      P.mmd.lds = true;
       const float t = time_runs(s, run);
       if (t < best) {
         best = t;

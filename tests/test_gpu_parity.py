@@ -323,8 +323,8 @@ def test_batched_vcycle_every_tile_shape(which, request):
 def test_batched_fp64_matrix_cores(which, request):
     """The FP64 multi-right-hand-side V-cycle with its aggregate-block
     operators on the FP64 matrix cores (k_bmmd, forced by a fixed tile shape:
-    1, 2 and 4 row tiles, both loads-in-flight counts) and as the autotuner
-    picks gives the single-
+    1, 2 and 4 row tiles, both loads-in-flight counts; k_bmmd_lds, the
+    LDS-staged form on 64 columns) and as the autotuner picks gives the single-
     vector FP64 V-cycle on every column to 1e-12, on 64 columns and then on
     narrower batches with the same buffers; the forced form is the one that
     runs."""
@@ -348,6 +348,8 @@ def test_batched_fp64_matrix_cores(which, request):
                     fma = {k for k in names if k.startswith("k_bgemm")}
                     assert any(k.startswith("k_bmmd") for k in names), (tile, nc, sorted(names))
                     assert all(k.endswith(f"@L{dense}") for k in fma), (tile, nc, sorted(fma))
+                    lds = any(k.startswith("k_bmmd_lds") for k in names)
+                    assert lds == (tile == 401 and nc == 64), (tile, nc, sorted(names))
                 for j in range(nc):
                     assert rel(Y[j], Y1[j]) <= 1e-12, (tile, nc, j, rel(Y[j], Y1[j]))
     finally:
