@@ -119,6 +119,18 @@ typedef struct lsamg_params {
                             inverses A_i^{-1} (|Omega_i|^2 entries each), there
                             is no dense tail, and several right-hand sides are
                             solved one after another                         */
+  int32_t setup_device;  /* 0 (default): the local dense problems of every
+                            level (Algorithm 1: the pseudo-inverse Schur
+                            complement of eq:gevp-S, the reduced local
+                            eigenproblem, the local inverses A_i^{-1}) run on
+                            the host's cores; 1: they run on the HIP device
+                            `device` as batched FP64 factorisations (batched
+                            SVD, Cholesky and symmetric eigensolvers of rocSOLVER,
+                            batched GEMM and triangular solves of rocBLAS, both
+                            loaded when first needed), aggregates of similar
+                            size padded into one batch; the integer steps and
+                            G_{l+1} = G_l P_l stay on the host.  Needs
+                            device >= 0 (else LSAMG_EINVAL)                    */
 } lsamg_params;
 
 enum { LSAMG_AGG_LATTICE = 0, LSAMG_AGG_STANDARD = 1 };

@@ -1,7 +1,8 @@
 """Build ``liblsamg.so`` in-tree for gfx950.
 
-The host setup (``host_setup.cpp``) is compiled with g++; the HIP sources
-with hipcc for ``--offload-arch=gfx950``; both are linked into one shared
+The host setup (``host_setup.cpp``) is compiled with g++; the HIP sources (the
+kernels and C-ABI, and the device setup) with hipcc for
+``--offload-arch=gfx950``; both are linked into one shared
 library next to this file.  Run ``python -m paper_2601_04112_amd.build``.
 """
 from __future__ import annotations
@@ -19,7 +20,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SRCS = ["host_setup.cpp"]
-HIP_SRCS = ["lsamg.hip"]
+HIP_SRCS = ["lsamg.hip", "setup_device.hip"]
 
 CXXFLAGS = ["-O3", "-fPIC", "-std=c++17", "-pthread", "-mavx2", "-mfma",
             "-Wall", "-Wno-unused-function"]
@@ -55,7 +56,7 @@ def build(verbose: bool = False) -> str:
                 print(r.stdout + r.stderr, file=sys.stderr)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
-         + ["-pthread"])
+         + ["-pthread", "-ldl"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -8,6 +8,9 @@
 // reduced eigenproblem eq:gevp-S solved as S~ u = mu A_ww u; selection of
 // sec. 3.4; smoother rows Z_i = A_i^{-1}(omega_i, Omega_i); interpolation
 // eq:mg-p; G_{l+1} = G_l P_l (sec. 3.1.3) with exact row compression.
+// With setup_device set, the dense local problems (Schur complement,
+// eigenproblem, local and coarsest inverses) go to the HIP device in
+// batches (setup_device.hip); everything else stays here.
 #include <algorithm>
 #include <cstdio>
 #include <array>
@@ -482,9 +485,98 @@ int select_count(const double* mu, int nw, const lsamg_params& p, int level, dou
   return k;
 }
 
+// Rows of B = W^{1/2} G_{nz_i} for aggregate a: every row of the groups in nz_i.
+int64_t local_rows(const Level& L, const Work& W, int64_t a) {
+  int64_t rows = 0;
+  for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) rows += L.G.nrows[W.nz[e]];
+  return rows;
+}
+
+// The local blocks of aggregate a (sec. 3.1.1, eq:gevp-S), written into
+// zero-initialised column-major buffers: Bw and Bg (leading dimension ldb)
+// the omega_i and Gamma_i columns of B = W^{1/2} G_{nz_i} (W = 1/M per
+// group; rows of nz_i's groups in order, so A~_i = B^T B), Aww (leading
+// dimension ldw) = G_{nz,omega}^T G_{nz,omega}, and, if Ai is not null, Ai
+// (leading dimension ldo) = A(Omega_i, Omega_i).  loc holds n entries, all
+// -1 on entry and again on return.
+void local_blocks(const Level& L, const Work& W, int64_t a, std::vector<int32_t>& loc, double* Bw,
+                  double* Bg, int64_t ldb, double* Aww, int ldw, double* Ai, int ldo) {
+  const Groups& G = L.G;
+  const int nw = (int)(L.astart[a + 1] - L.astart[a]);
+  const int64_t o0 = L.optr[a];
+  const int nO = (int)(L.optr[a + 1] - o0);
+  for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = j;
+  std::vector<int> lp;
+  int64_t r0 = 0;
+  for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) {
+    const int64_t g = W.nz[e];
+    const int64_t s0 = G.sptr[g];
+    const int ns = (int)(G.sptr[g + 1] - s0);
+    const double sw = std::sqrt(1.0 / (double)L.M[g]);
+    lp.resize(ns);
+    for (int q = 0; q < ns; ++q) lp[q] = loc[G.supp[s0 + q]];
+    const double* R = G.val.data() + G.vptr[g];
+    for (int r = 0; r < G.nrows[g]; ++r) {
+      const double* row = R + (size_t)r * ns;
+      for (int qc = 0; qc < ns; ++qc) {
+        const double vc = row[qc];
+        if (vc == 0.0) continue;
+        const int c = lp[qc];
+        if (c >= nw) {
+          Bg[(size_t)(c - nw) * ldb + r0 + r] = sw * vc;
+          continue;
+        }
+        Bw[(size_t)c * ldb + r0 + r] = sw * vc;
+        double* colw = Aww + (size_t)c * ldw;
+        for (int qr = 0; qr < ns; ++qr)
+          if (lp[qr] < nw) colw[lp[qr]] += row[qr] * vc;
+      }
+    }
+    r0 += G.nrows[g];
+  }
+  if (Ai) {
+    for (int r = 0; r < nO; ++r) {
+      const int32_t d = L.oidx[o0 + r];
+      for (int64_t e = W.A.ptr[d]; e < W.A.ptr[d + 1]; ++e) {
+        const int c = loc[W.A.col[e]];
+        if (c >= 0) Ai[(size_t)c * ldo + r] = W.A.val[e];
+      }
+    }
+  }
+  for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = -1;
+}
+
+// Concatenate the per-aggregate results into the level's arrays.
+void store_local(Level& L, std::vector<std::vector<double>>& mus,
+                 std::vector<std::vector<double>>& zs, std::vector<std::vector<double>>& zh,
+                 std::vector<std::vector<double>>& za, bool additive, int nthreads) {
+  const int64_t na = L.nagg;
+  L.muptr.assign(na + 1, 0);
+  L.zoff.assign(na + 1, 0);
+  L.poff.assign(na + 1, 0);
+  for (int64_t a = 0; a < na; ++a) {
+    L.muptr[a + 1] = L.muptr[a] + (int64_t)mus[a].size();
+    L.zoff[a + 1] = L.zoff[a] + (int64_t)zs[a].size();
+    L.poff[a + 1] = L.poff[a] + (int64_t)zh[a].size();
+  }
+  L.mu.resize(L.muptr[na]);
+  L.Z.resize(L.zoff[na]);
+  L.Zhat.resize(L.poff[na]);
+  if (additive) {
+    L.aoff.assign(na + 1, 0);
+    for (int64_t a = 0; a < na; ++a) L.aoff[a + 1] = L.aoff[a] + (int64_t)za[a].size();
+    L.Ainv_loc.resize(L.aoff[na]);
+  }
+  parallel_for(na, [&](int64_t a, int) {
+    std::copy(mus[a].begin(), mus[a].end(), L.mu.begin() + L.muptr[a]);
+    std::copy(zs[a].begin(), zs[a].end(), L.Z.begin() + L.zoff[a]);
+    std::copy(zh[a].begin(), zh[a].end(), L.Zhat.begin() + L.poff[a]);
+    if (additive) std::copy(za[a].begin(), za[a].end(), L.Ainv_loc.begin() + L.aoff[a]);
+  }, nthreads);
+}
+
 // Local eigenproblems (eq:gevp-S) and smoother rows, one aggregate at a time.
 void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, int nthreads) {
-  const Groups& G = L.G;
   const int64_t na = L.nagg, n = L.n;
   L.k.assign(na, 0);
   std::vector<std::vector<double>> mus(na), zh(na), zs(na), za(na);
@@ -507,41 +599,18 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     const int64_t o0 = L.optr[a];
     const int nO = (int)(L.optr[a + 1] - o0);
     const int ng = nO - nw;
-    for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = j;
-    // B = W^{1/2} G_{nz,Omega} (rows x nO, column-major; A~_i = B^T B) and
-    // A_ww = G_{nz,w}^T G_{nz,w}
+    // B = W^{1/2} G_{nz,Omega} (rows x nO, column-major; A~_i = B^T B),
+    // A_ww = G_{nz,w}^T G_{nz,w} and A_i = A(Omega_i, Omega_i)
     auto t_ph = tick();
-    int64_t rows = 0;
-    for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) rows += G.nrows[W.nz[e]];
+    const int64_t rows = local_rows(L, W, a);
     for (int64_t cur = max_nO.load(); nO > cur && !max_nO.compare_exchange_weak(cur, nO);) {
     }
     for (int64_t cur = max_rows.load(); rows > cur && !max_rows.compare_exchange_weak(cur, rows);) {
     }
     std::vector<double> B((size_t)rows * nO, 0.0), Aww((size_t)nw * nw, 0.0);
-    std::vector<int> lp;
-    int64_t r0 = 0;
-    for (int64_t e = W.nz_ptr[a]; e < W.nz_ptr[a + 1]; ++e) {
-      const int64_t g = W.nz[e];
-      const int64_t s0 = G.sptr[g];
-      const int ns = (int)(G.sptr[g + 1] - s0);
-      const double sw = std::sqrt(1.0 / (double)L.M[g]);
-      lp.resize(ns);
-      for (int q = 0; q < ns; ++q) lp[q] = loc[G.supp[s0 + q]];
-      const double* R = G.val.data() + G.vptr[g];
-      for (int r = 0; r < G.nrows[g]; ++r) {
-        const double* row = R + (size_t)r * ns;
-        for (int qc = 0; qc < ns; ++qc) {
-          const double vc = row[qc];
-          if (vc == 0.0) continue;
-          B[(size_t)lp[qc] * rows + r0 + r] = sw * vc;
-          if (lp[qc] >= nw) continue;
-          double* colw = Aww.data() + (size_t)lp[qc] * nw;
-          for (int qr = 0; qr < ns; ++qr)
-            if (lp[qr] < nw) colw[lp[qr]] += row[qr] * vc;
-        }
-      }
-      r0 += G.nrows[g];
-    }
+    std::vector<double> Ai((size_t)nO * nO, 0.0);
+    local_blocks(L, W, a, loc, B.data(), B.data() + (size_t)nw * rows, rows, Aww.data(), nw,
+                 Ai.data(), nO);
     // S~ = min over u_Gamma of the energy: B_w^T (I - Q Q^T) B_w, Q a basis
     // of range(B_Gamma) (the pseudo-inverse reading of eq:gevp-S)
     std::vector<double> S((size_t)nw * nw);
@@ -585,16 +654,7 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
     zh[a] = std::move(Zh);
     add_ns(2, t_ph);
     t_ph = tick();
-    // smoother: A_i = A(Omega_i, Omega_i), Z_i = A_i^{-1}(omega_i, Omega_i)
-    std::vector<double> Ai((size_t)nO * nO, 0.0);
-    for (int r = 0; r < nO; ++r) {
-      const int32_t d = L.oidx[o0 + r];
-      for (int64_t e = W.A.ptr[d]; e < W.A.ptr[d + 1]; ++e) {
-        const int c = loc[W.A.col[e]];
-        if (c >= 0) Ai[(size_t)c * nO + r] = W.A.val[e];
-      }
-    }
-    for (int j = 0; j < nO; ++j) loc[L.oidx[o0 + j]] = -1;
+    // smoother: Z_i = A_i^{-1}(omega_i, Omega_i)
     if (!chol_lower(nO, Ai.data())) fail(LSAMG_ENOTSPD, "local block A(Omega,Omega) is not SPD");
     std::vector<double> Zc((size_t)nO * nw, 0.0);
     for (int j = 0; j < nw; ++j) Zc[(size_t)j * nO + j] = 1.0;
@@ -620,28 +680,140 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
                  ph_ns[0] * 1e-9, ph_ns[1] * 1e-9, ph_ns[2] * 1e-9, ph_ns[3] * 1e-9);
     std::fflush(stderr);
   }
-  L.muptr.assign(na + 1, 0);
-  L.zoff.assign(na + 1, 0);
-  L.poff.assign(na + 1, 0);
+  store_local(L, mus, zs, zh, za, additive, nthreads);
+}
+
+// The same local problems with their dense work on the HIP device
+// (device_local_problems): aggregates sorted by |Omega_i| and cut into
+// batches of similar size (each block padded to its batch's largest), the
+// blocks assembled on the host threads, factorised in one batched pass per
+// batch, and the eigenvector counts (sec. 3.4) and signs taken on the host
+// as in the host path.
+void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int level,
+                                  int nthreads) {
+  const int64_t na = L.nagg, n = L.n;
+  L.k.assign(na, 0);
+  const bool additive = p.cycle == LSAMG_CYCLE_ADDITIVE;
+  std::vector<std::vector<double>> mus(na), zh(na), zs(na), za(na);
+  std::vector<int32_t> nwv(na), nov(na);
+  std::vector<int64_t> rowv(na);
   for (int64_t a = 0; a < na; ++a) {
-    L.muptr[a + 1] = L.muptr[a] + (int64_t)mus[a].size();
-    L.zoff[a + 1] = L.zoff[a] + (int64_t)zs[a].size();
-    L.poff[a + 1] = L.poff[a] + (int64_t)zh[a].size();
+    nwv[a] = (int32_t)(L.astart[a + 1] - L.astart[a]);
+    nov[a] = (int32_t)(L.optr[a + 1] - L.optr[a]);
+    rowv[a] = local_rows(L, W, a);
   }
-  L.mu.resize(L.muptr[na]);
-  L.Z.resize(L.zoff[na]);
-  L.Zhat.resize(L.poff[na]);
-  if (additive) {
-    L.aoff.assign(na + 1, 0);
-    for (int64_t a = 0; a < na; ++a) L.aoff[a + 1] = L.aoff[a] + (int64_t)za[a].size();
-    L.Ainv_loc.resize(L.aoff[na]);
+  std::vector<int64_t> order(na);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return nov[x] != nov[y] ? nov[x] < nov[y] : rowv[x] < rowv[y];
+  });
+  const int nt = nthreads > 0 ? nthreads : default_threads();
+  std::vector<std::vector<int32_t>> locs(nt);
+  std::atomic<int64_t> hazards{0};
+  double t_asm = 0, t_dev = 0, t_post = 0;
+  double ph[7] = {0, 0, 0, 0, 0, 0, 0};
+  int nbatch = 0;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto secs = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+  // a batch grows while its padded blocks stay within 2^30 doubles (8 GiB),
+  // and, once it holds 64 aggregates (enough to fill the device), while its
+  // largest |Omega| stays within 1.25 x + 16 of its smallest
+  const double cap = (double)(1 << 30);
+  for (int64_t i = 0; i < na;) {
+    int64_t R = rowv[order[i]], Wd = nwv[order[i]], Od = nov[order[i]];
+    int64_t Gd = Od - Wd;
+    int64_t j = i + 1;
+    auto per = [](int64_t r, int64_t w, int64_t g, int64_t o) {
+      return (double)(2 * r * (w + g) + 3 * w * w + 2 * o * o + 2 * o * w);
+    };
+    for (; j < na; ++j) {
+      const int64_t a = order[j];
+      if (j - i >= 64 && nov[a] > 1.25 * nov[order[i]] + 16) break;
+      const int64_t r2 = std::max(R, rowv[a]), w2 = std::max<int64_t>(Wd, nwv[a]);
+      const int64_t g2 = std::max<int64_t>(Gd, nov[a] - nwv[a]), o2 = std::max<int64_t>(Od, nov[a]);
+      if ((double)(j - i + 1) * per(r2, w2, g2, o2) > cap) break;
+      R = r2, Wd = w2, Gd = g2, Od = o2;
+    }
+    const int nb = (int)(j - i);
+    auto t0 = now();
+    std::vector<int32_t> bnw(nb), rank(nb);
+    std::vector<double> Bw((size_t)nb * R * Wd, 0.0), Bg((size_t)nb * R * Gd, 0.0);
+    std::vector<double> Aww((size_t)nb * Wd * Wd, 0.0), Ai((size_t)nb * Od * Od, 0.0);
+    parallel_for(nb, [&](int64_t b, int t) {
+      if (locs[t].empty()) locs[t].assign(n, -1);
+      const int64_t a = order[i + b];
+      bnw[b] = nwv[a];
+      double* aww = Aww.data() + (size_t)b * Wd * Wd;
+      double* ai = Ai.data() + (size_t)b * Od * Od;
+      local_blocks(L, W, a, locs[t], Bw.data() + (size_t)b * R * Wd, Bg.data() + (size_t)b * R * Gd,
+                   R, aww, (int)Wd, ai, (int)Od);
+      for (int64_t q = nwv[a]; q < Wd; ++q) aww[(size_t)q * Wd + q] = 1.0;
+      for (int64_t q = nov[a]; q < Od; ++q) ai[(size_t)q * Od + q] = 1.0;
+    }, nthreads);
+    t_asm += secs(t0);
+    t0 = now();
+    std::vector<double> mu((size_t)nb * Wd), U((size_t)nb * Wd * Wd), Z((size_t)nb * Od * Wd);
+    std::vector<double> Ainv(additive ? (size_t)nb * Od * Od : 0);
+    std::string msg;
+    const int rc = device_local_problems(p.device, nb, (int)R, (int)Wd, (int)Gd, (int)Od,
+                                         p.pinv_rtol, bnw.data(), Bw.data(), Bg.data(), Aww.data(),
+                                         Ai.data(), mu.data(), U.data(), Z.data(),
+                                         additive ? Ainv.data() : nullptr, rank.data(),
+                                         p.verbose ? ph : nullptr, msg);
+    if (rc != LSAMG_OK) fail(rc, msg);
+    t_dev += secs(t0);
+    t0 = now();
+    parallel_for(nb, [&](int64_t b, int) {
+      const int64_t a = order[i + b];
+      const int nw = nwv[a], nO = nov[a];
+      const double* m = mu.data() + (size_t)b * Wd;
+      bool hz = false;
+      const int k = select_count(m, nw, p, level, L.thresh, hz);
+      if (hz) hazards++;
+      std::vector<double> Zh((size_t)nw * k);
+      const double* ub = U.data() + (size_t)b * Wd * Wd;
+      for (int t2 = 0; t2 < k; ++t2) {
+        const double* u = ub + (size_t)t2 * Wd;
+        int jm = 0;
+        for (int q = 1; q < nw; ++q)
+          if (std::fabs(u[q]) > std::fabs(u[jm])) jm = q;
+        const double sg = u[jm] < 0.0 ? -1.0 : 1.0;
+        for (int q = 0; q < nw; ++q) Zh[(size_t)q * k + t2] = sg * u[q];
+      }
+      L.k[a] = k;
+      mus[a].assign(m, m + nw);
+      zh[a] = std::move(Zh);
+      std::vector<double> Zc((size_t)nO * nw);
+      const double* zb = Z.data() + (size_t)b * Od * Wd;
+      for (int q = 0; q < nw; ++q)
+        std::copy(zb + (size_t)q * Od, zb + (size_t)q * Od + nO, Zc.begin() + (size_t)q * nO);
+      zs[a] = std::move(Zc);
+      if (additive) {
+        std::vector<double> Za((size_t)nO * nO);
+        const double* ab = Ainv.data() + (size_t)b * Od * Od;
+        for (int q = 0; q < nO; ++q)
+          std::copy(ab + (size_t)q * Od, ab + (size_t)q * Od + nO, Za.begin() + (size_t)q * nO);
+        za[a] = std::move(Za);
+      }
+    }, nthreads);
+    t_post += secs(t0);
+    ++nbatch;
+    i = j;
   }
-  parallel_for(na, [&](int64_t a, int) {
-    std::copy(mus[a].begin(), mus[a].end(), L.mu.begin() + L.muptr[a]);
-    std::copy(zs[a].begin(), zs[a].end(), L.Z.begin() + L.zoff[a]);
-    std::copy(zh[a].begin(), zh[a].end(), L.Zhat.begin() + L.poff[a]);
-    if (additive) std::copy(za[a].begin(), za[a].end(), L.Ainv_loc.begin() + L.aoff[a]);
-  }, nthreads);
+  L.hazards = hazards.load();
+  if (p.verbose) {
+    std::fprintf(stderr,
+                 "lsamg setup: level %d: %lld aggregates in %d device batches; seconds: blocks "
+                 "%.2f, device %.2f (uploads %.2f, SVD %.2f, Schur products %.2f, Cholesky "
+                 "and solves %.2f, eigensolver %.2f, local inverses %.2f, downloads %.2f), "
+                 "counts and copies %.2f\n",
+                 level, (long long)na, nbatch, t_asm, t_dev, ph[0], ph[1], ph[2], ph[3], ph[4],
+                 ph[5], ph[6], t_post);
+    std::fflush(stderr);
+  }
+  store_local(L, mus, zs, zh, za, additive, nthreads);
 }
 
 // Next level: numbering (aggregated or not), and G_{l+1} = G_l P_l grouped by
@@ -808,12 +980,20 @@ void next_level(Level& L, Work& W, Level& N, bool aggregate_next, const lsamg_pa
   }
 }
 
-void coarsest_inverse(Level& L, Work& W, int nthreads) {
+// Dense inverse of the coarsest A_L (on the HIP device `device` if >= 0).
+void coarsest_inverse(Level& L, Work& W, int nthreads, int device) {
   const int64_t n = L.n;
   if (n > 40000) fail(LSAMG_EINVAL, "coarsest level too large for a dense solve");
   std::vector<double> A((size_t)n * n, 0.0);
   for (int64_t r = 0; r < n; ++r)
     for (int64_t e = W.A.ptr[r]; e < W.A.ptr[r + 1]; ++e) A[(size_t)W.A.col[e] * n + r] = W.A.val[e];
+  if (device >= 0) {
+    L.Ainv.assign((size_t)n * n, 0.0);
+    std::string msg;
+    const int rc = device_spd_inverse(device, (int)n, A.data(), L.Ainv.data(), msg);
+    if (rc != LSAMG_OK) fail(rc, msg);
+    return;
+  }
   if (!chol_lower((int)n, A.data())) fail(LSAMG_ENOTSPD, "coarsest matrix is not SPD");
   L.Ainv.assign((size_t)n * n, 0.0);
   parallel_for(n, [&](int64_t j, int) {
@@ -845,6 +1025,9 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     if (Gin.n != np) fail(LSAMG_EINVAL, "G has n columns != product of grid extents");
     if (standard && (p.nagg_passes < 1 || p.nagg_passes > 8)) fail(LSAMG_EINVAL, "bad agg_passes");
     if (p.cycle != LSAMG_CYCLE_V && p.cycle != LSAMG_CYCLE_ADDITIVE) fail(LSAMG_EINVAL, "bad cycle");
+    if (p.setup_device != 0 && p.setup_device != 1) fail(LSAMG_EINVAL, "bad setup_device");
+    if (p.setup_device && p.device < 0)
+      fail(LSAMG_EINVAL, "setup on the device needs a HIP device (device >= 0)");
     if (Gin.m <= 0 || Gin.n <= 0 || !Gin.rowptr || (Gin.nnz > 0 && (!Gin.col || !Gin.val)))
       fail(LSAMG_EINVAL, "bad G");
     if (p.block < 1 || p.omega_max < 1 || p.max_levels < 1) fail(LSAMG_EINVAL, "bad params");
@@ -965,13 +1148,16 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
       L.a_nnz = W.A.ptr[L.n];
       if (!aggregated) {
         L.coarsest = true;
-        coarsest_inverse(L, W, nthreads);
+        coarsest_inverse(L, W, nthreads, p.setup_device ? p.device : -1);
         progress(l, "coarsest inverse done");
         break;
       }
       overlap_and_colour(L, W, p, nthreads);
       progress(l, "overlap and colouring done");
-      spectral_and_smoother(L, W, p, l, nthreads);
+      if (p.setup_device)
+        spectral_and_smoother_device(L, W, p, l, nthreads);
+      else
+        spectral_and_smoother(L, W, p, l, nthreads);
       progress(l, "local eigenproblems and smoother done");
       int64_t nn = 0;
       for (int32_t kk : L.k) nn += kk;

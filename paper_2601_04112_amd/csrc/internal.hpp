@@ -87,6 +87,31 @@ void parallel_for(int64_t n, const std::function<void(int64_t, int)>& body,
                   int nthreads = 0);
 int default_threads();
 
+// The dense local problems of nb aggregates on the HIP device `device`
+// (setup on the device, csrc/setup_device.hip), every block padded to the
+// batch's sizes: R rows of W^{1/2} G_{nz_i}, W unknowns of omega_i, Gm of
+// Gamma_i, O of Omega_i.  Inputs (host, column-major, packed per aggregate):
+// Bw (R x W) and Bg (R x Gm), the columns of W^{1/2} G_{nz_i} on omega_i and
+// on Gamma_i (zero in padded rows and columns); Aww (W x W) = A_ww of
+// eq:gevp-S and Ai (O x O) = A(Omega_i, Omega_i), both identity on their
+// padded diagonal; nw[b] the true |omega_i|.  Outputs (host): mu (W per
+// aggregate) the eigenvalues of S~ u = mu A_ww u ascending, the true ones
+// first; U (W x W) their A_ww-orthonormal eigenvectors; Z (O x W) the
+// columns A_i^{-1} e_j, j < W; Ainv (O x O, if not null) the whole A_i^{-1};
+// rank[b] the singular values of B_Gamma kept in the pseudo-inverse (those
+// above rtol times the largest).  phase (7 entries, may be null): seconds
+// added per phase (uploads, SVD, Schur products, Cholesky and triangular
+// solves, eigensolver, local inverses, downloads), with a synchronisation
+// after each.  Returns an LSAMG_* code, msg on error.
+int device_local_problems(int device, int nb, int R, int W, int Gm, int O, double rtol,
+                          const int32_t* nw, const double* Bw, const double* Bg, const double* Aww,
+                          const double* Ai, double* mu, double* U, double* Z, double* Ainv,
+                          int32_t* rank, double* phase, std::string& msg);
+
+// Ainv = A^{-1} for the SPD n x n matrix A (column-major, host) on the HIP
+// device `device` (Cholesky factor, then solves against the identity).
+int device_spd_inverse(int device, int n, const double* A, double* Ainv, std::string& msg);
+
 // C = G^+ F for the symmetric s x s matrix G and the s x s matrix F (both
 // row-major; C row-major): the pseudo-inverse drops the eigenvalues of G at
 // or below rtol times the largest.  Returns the rank kept, or -1 if the

@@ -54,7 +54,8 @@ class Params(C.Structure):
                 ("device", C.c_int32), ("nthreads", C.c_int32),
                 ("verbose", C.c_int32), ("dense_tail", C.c_int64),
                 ("aggregation", C.c_int32), ("agg_passes", C.c_int32 * 8),
-                ("nagg_passes", C.c_int32), ("cycle", C.c_int32)]
+                ("nagg_passes", C.c_int32), ("cycle", C.c_int32),
+                ("setup_device", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -211,7 +212,8 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 stall_ratio: float = 0.9, precision: int = FP64,
                 device: int = 0, nthreads: int = 0, verbose: bool = False,
                 dense_tail: int = 16384, aggregation: str = "lattice",
-                agg_passes: Sequence[int] = (1,), cycle: str = "v") -> Params:
+                agg_passes: Sequence[int] = (1,), cycle: str = "v",
+                setup_device: bool = False) -> Params:
     p = default_params()
     p.ndim = ndim
     for d in range(3):
@@ -237,6 +239,7 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
     if cycle not in ("v", "additive"):
         raise ValueError("cycle must be 'v' or 'additive'")
     p.cycle = CYCLE_ADDITIVE if cycle == "additive" else CYCLE_V
+    p.setup_device = 1 if setup_device else 0
     return p
 
 

@@ -137,6 +137,17 @@ def test_error_bad_params():
         L.Solver(p.G, 2, p.grid, device=-1, block=0)
 
 
+def test_setup_on_device_needs_a_device():
+    """setup_device asks for the local dense problems on the HIP device: a
+    host-only handle (device < 0) cannot have it, and it is refused before
+    any work instead of falling back to the host."""
+    p = P.aniso2d(8, 0.0, 1.0)
+    with pytest.raises(L.LsamgError) as e:
+        L.Solver(p.G, 2, p.grid, device=-1, setup_device=True)
+    assert e.value.code == L.LSAMG_EINVAL
+    assert "device" in str(e.value)
+
+
 def test_solve_without_device_is_refused():
     p = P.aniso2d(8, 0.0, 1.0)
     s = L.Solver(p.G, 2, p.grid, device=-1)
