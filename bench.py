@@ -176,7 +176,8 @@ def run_serving(args):
             probs[k] = P.aniso2d(*pool[k])
             bw = np.stack([P.rhs_uniform(probs[k].n, 7 + j) for j in range(args.prewarm_rhs)])
             srv.submit(k, probs[k].G, 2, probs[k].grid, bw,
-                       tol=1e-8, precision=L.MIXED, req_id=10 ** 6 + k, cmin=(2,))
+                       tol=1e-8, precision=L.MIXED, req_id=10 ** 6 + k, cmin=(2,),
+                       setup_device=args.setup == "device")
         got = 0
         warm = []
         while got < args.pool:
@@ -212,7 +213,7 @@ def run_serving(args):
                 p = probs[k]
                 b = np.stack([P.rhs_uniform(p.n, seed + j) for j in range(nr)])
                 srv.submit(k, p.G, 2, p.grid, b, tol=1e-8, precision=L.MIXED,
-                           req_id=next_id + i, cmin=(2,))
+                           req_id=next_id + i, cmin=(2,), setup_device=args.setup == "device")
                 i += 1
             wait = 5 if i >= len(reqs) else max(0, int((reqs[i][0] - now) * 1e3))
             for d in srv.poll(wait_ms=min(wait, 20)):
@@ -316,6 +317,9 @@ def main():
     ap.add_argument("--cycle", choices=("v", "additive"), default="v",
                     help="aniso2d: the multiplicative V-cycle or the additive cycle of "
                          "sec. 3.1.1 (single right-hand sides only)")
+    ap.add_argument("--setup", choices=("device", "host"), default="device",
+                    help="where the setup's dense local problems run (untimed): "
+                         "batched on the GPU, or on the host's cores")
     ap.add_argument("--maxit", type=int, default=0,
                     help="PCG iteration cap (default 1000; 200 for ls3d)")
     args = ap.parse_args()
@@ -363,12 +367,13 @@ def main():
         prob = P.config3(args.N)
         print(f"ls3d N={args.N}: n={prob.n}, m={prob.m}, nnz={prob.G.nnz}; setup ...",
               file=sys.stderr, flush=True)
-        s = L.Solver(prob.G, 3, prob.grid, device=0, block=3, cmin=(3, 4), verbose=True)
+        s = L.Solver(prob.G, 3, prob.grid, device=0, block=3, cmin=(3, 4), verbose=True,
+                     setup_device=args.setup == "device")
         seed = P.CONFIG_RHS_SEED[3]
     else:
         prob = P.config2(args.N)
         s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle,
-                     omega_max=args.omega_max)
+                     omega_max=args.omega_max, setup_device=args.setup == "device")
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
@@ -612,6 +617,7 @@ def main():
             "smoother_complexity": round(inf["smoother_complexity"], 3),
             "smoother_entries": smoother_entries,
             "setup_s": round(t_setup, 2),
+            "setup": args.setup,
             "dense_tail_level": inf["tail_level"],
             "device_gb": round(inf["device_bytes"] / 1e9, 2),
             "parallelism": "single GPU",

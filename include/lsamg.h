@@ -210,7 +210,10 @@ typedef struct lsamg_handle lsamg_handle;
 /* ---- serving ---------------------------------------------------------- */
 
 /* One solve request.  Requests with equal op_key share one hierarchy: the
- * first builds it (host setup + upload), later ones find it resident. */
+ * first builds it (setup, then upload once admitted), later ones find it
+ * resident.  With params->setup_device the setup's dense local problems run
+ * on the server's device, 12 GiB of the HBM budget held for them while it
+ * runs (LSAMG_ENOMEM when that cannot be freed). */
 typedef struct lsamg_request {
   uint64_t id;             /* caller's id, returned in lsamg_done                */
   uint64_t op_key;         /* operator identity                                  */
@@ -235,7 +238,7 @@ typedef struct lsamg_done {
   int32_t iters_max;       /* most PCG iterations over the request's columns     */
   double true_rel_res_max; /* largest ||b - A x|| / ||b|| over its columns       */
   double t_queue;          /* seconds from submit until taken by a worker        */
-  double t_setup;          /* host setup + upload (0 on a hit)                   */
+  double t_setup;          /* setup + upload (0 on a hit)                        */
   double t_solve;          /* copy-in, solve, copy-out                           */
   double t_total;          /* submit to completion                               */
   int32_t joined_at;       /* PCG iteration of the running solve at which the

@@ -3621,6 +3621,49 @@ int fail_with(int code, const std::string& msg) {
 
 }  // namespace
 
+namespace {
+
+// lsamg_setup; with upload_now false the handle stays host-only (device -1)
+// even when p->device names the device that a device setup runs on
+int setup_impl(const lsamg_csr* G, const lsamg_params* p, bool upload_now, lsamg_handle** out) {
+  if (!G || !p || !out) return fail_with(LSAMG_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->precision != LSAMG_FP64 && p->precision != LSAMG_MIXED)
+    return fail_with(LSAMG_EINVAL, "bad precision");
+  lsamg_handle* h = new (std::nothrow) lsamg_handle();
+  if (!h) return fail_with(LSAMG_ENOMEM, "handle allocation failed");
+  std::string msg;
+  int rc = build_hierarchy(*G, *p, h->H, msg);
+  if (rc != LSAMG_OK) {
+    delete h;
+    return fail_with(rc, msg);
+  }
+  h->precision = p->precision;
+  h->device = upload_now ? p->device : -1;
+  if (upload_now) {
+    try {
+      int ndev = 0;
+      if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= p->device)
+        throw DevError{LSAMG_ENODEV, "no such HIP device"};
+      DeviceGuard g(p->device);
+      upload(h);
+      HIP_OK(hipDeviceSynchronize());
+    } catch (const DevError& e) {
+      h->free_all();
+      delete h;
+      return fail_with(e.code, e.msg);
+    } catch (const std::bad_alloc&) {
+      h->free_all();
+      delete h;
+      return fail_with(LSAMG_ENOMEM, "host allocation failed during upload");
+    }
+  }
+  *out = h;
+  return LSAMG_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void lsamg_params_default(lsamg_params* p) {
@@ -3652,40 +3695,7 @@ void lsamg_params_default(lsamg_params* p) {
 const char* lsamg_last_error(void) { return g_last_error.c_str(); }
 
 int lsamg_setup(const lsamg_csr* G, const lsamg_params* p, lsamg_handle** out) {
-  if (!G || !p || !out) return fail_with(LSAMG_EINVAL, "null argument");
-  *out = nullptr;
-  if (p->precision != LSAMG_FP64 && p->precision != LSAMG_MIXED)
-    return fail_with(LSAMG_EINVAL, "bad precision");
-  lsamg_handle* h = new (std::nothrow) lsamg_handle();
-  if (!h) return fail_with(LSAMG_ENOMEM, "handle allocation failed");
-  std::string msg;
-  int rc = build_hierarchy(*G, *p, h->H, msg);
-  if (rc != LSAMG_OK) {
-    delete h;
-    return fail_with(rc, msg);
-  }
-  h->precision = p->precision;
-  h->device = p->device;
-  if (p->device >= 0) {
-    try {
-      int ndev = 0;
-      if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= p->device)
-        throw DevError{LSAMG_ENODEV, "no such HIP device"};
-      DeviceGuard g(p->device);
-      upload(h);
-      HIP_OK(hipDeviceSynchronize());
-    } catch (const DevError& e) {
-      h->free_all();
-      delete h;
-      return fail_with(e.code, e.msg);
-    } catch (const std::bad_alloc&) {
-      h->free_all();
-      delete h;
-      return fail_with(LSAMG_ENOMEM, "host allocation failed during upload");
-    }
-  }
-  *out = h;
-  return LSAMG_OK;
+  return setup_impl(G, p, p && p->device >= 0, out);
 }
 
 int lsamg_solve(lsamg_handle* h, const double* b, double* x, int32_t nrhs, int64_t ld, double tol,
@@ -4202,6 +4212,11 @@ size_t batched_reserve(const lsamg_handle* h, int NB) {
 
 }  // namespace
 
+// HBM a device setup may hold while it runs (its batches' blocks, at most
+// 2^30 doubles, plus the factorisations' workspace), admitted by the server
+// for the duration of a setup on the device
+constexpr size_t kSetupTransient = (size_t)12 << 30;
+
 struct lsamg_server {
   int device = 0;
   size_t budget = 0;
@@ -4480,12 +4495,23 @@ void lsamg_server::worker() {
       ++misses;
       e = &cache[key];
       e->busy = true;
+      // a setup on the device holds transient buffers (batches of at most
+      // 8 GiB of blocks, plus the factorisations' workspace): admitted
+      // against the budget for its duration
+      const bool on_dev = first.r.params->setup_device != 0;
+      const bool room = !on_dev || make_room(lk, kSetupTransient);
+      if (on_dev && room) account(kSetupTransient, 0);
       lk.unlock();
       lsamg_params p = *first.r.params;
-      p.device = -1;                       // host setup now, upload after admission
+      p.device = on_dev ? device : -1;     // upload only after admission
       lsamg_handle* h = nullptr;
-      int rc = lsamg_setup(first.r.G, &p, &h);
-      std::string msg = rc == LSAMG_OK ? "" : lsamg_last_error();
+      int rc = room ? setup_impl(first.r.G, &p, false, &h) : LSAMG_ENOMEM;
+      std::string msg = rc == LSAMG_OK ? "" : room ? lsamg_last_error()
+                                                  : "no room in the device budget for the setup";
+      if (on_dev && room) {
+        std::lock_guard<std::mutex> g(mu);
+        account(0, kSetupTransient);
+      }
       size_t need = 0;
       if (rc == LSAMG_OK) {
         h->device = device;

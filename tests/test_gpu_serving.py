@@ -4,7 +4,7 @@ A result must be the same alone and in a mix of concurrent requests, within
 the solve tolerance: both solutions reach ||b - A x|| <= tol ||b|| (checked
 here in FP64 with A = G^T G) and differ by at most what two such solutions
 can differ by.  Admission against the device budget, eviction, a failing
-setup and an oversize hierarchy are covered as well.
+setup, an oversize hierarchy and setups on the device are covered as well.
 """
 import math
 
@@ -244,3 +244,53 @@ def test_hierarchy_larger_than_budget(gpu_device):
     res = drain(srv, 1)
     srv.close()
     assert res[rid]["status"] == L.LSAMG_ENOMEM
+
+
+def test_device_setup_in_server(gpu_device):
+    """Requests asking for the setup on the device: the server runs it on its
+    device with 12 GiB of the budget held meanwhile; the solutions reach the
+    tolerance and equal those of a host setup within it; a singular operator
+    fails alone (its device Cholesky reports it); a budget below the setup's
+    transient need fails the request with LSAMG_ENOMEM."""
+    probs = [op(0), op(1)]
+    bad = P.aniso2d(32, 0.0, 1.0)
+    Gb = bad.G.tolil()
+    Gb[:, 7] = 0.0
+    import scipy.sparse as sp
+    Gb = sp.csr_matrix(Gb)
+    srv = L.Server(hbm_budget=32 << 30, max_slots=2)
+    ids = {}
+    for i in range(6):
+        k = i % 2
+        b = np.stack([P.rhs_uniform(probs[k].n, 500 + 4 * i + j) for j in range(2)])
+        ids[srv.submit(k, probs[k].G, 2, probs[k].grid, b, tol=1e-8, cmin=(2,),
+                       max_coarse=200, setup_device=True)] = (k, b)
+    r_bad = srv.submit(9, Gb, 2, bad.grid, np.ones(bad.n), tol=1e-8, max_coarse=100,
+                       setup_device=True)
+    res = drain(srv, 7)
+    st = srv.stats()
+    srv.close()
+    assert res[r_bad]["status"] == L.LSAMG_ENOTSPD
+    for rid, (k, b) in ids.items():
+        assert res[rid]["status"] == 0, res[rid]["msg"]
+        check(probs[k], b, res[rid]["x"], 1e-8)
+    assert st["peak_bytes"] <= 32 << 30
+    # the same requests with a host setup: solutions within the tolerance
+    srv = L.Server(hbm_budget=8 << 30, max_slots=2)
+    host_ids = {}
+    for rid, (k, b) in ids.items():
+        host_ids[srv.submit(k, probs[k].G, 2, probs[k].grid, b, tol=1e-8, cmin=(2,),
+                            max_coarse=200)] = rid
+    hres = drain(srv, len(ids))
+    srv.close()
+    for hid, rid in host_ids.items():
+        xd, xh = np.atleast_2d(res[rid]["x"]), np.atleast_2d(hres[hid]["x"])
+        for j in range(xd.shape[0]):
+            assert np.linalg.norm(xd[j] - xh[j]) <= 1e-6 * np.linalg.norm(xh[j])
+    # a budget below the setup's transient need
+    srv = L.Server(hbm_budget=8 << 30, max_slots=1)
+    rid = srv.submit(0, probs[0].G, 2, probs[0].grid, np.ones(probs[0].n), tol=1e-8, cmin=(2,),
+                     max_coarse=200, setup_device=True)
+    r = drain(srv, 1)[rid]
+    srv.close()
+    assert r["status"] == L.LSAMG_ENOMEM
