@@ -212,7 +212,7 @@ typedef struct lsamg_handle lsamg_handle;
 /* One solve request.  Requests with equal op_key share one hierarchy: the
  * first builds it (setup, then upload once admitted), later ones find it
  * resident.  With params->setup_device the setup's dense local problems run
- * on the server's device, 12 GiB of the HBM budget held for them while it
+ * on the server's device, 24 GiB of the HBM budget held for them while it
  * runs (LSAMG_ENOMEM when that cannot be freed). */
 typedef struct lsamg_request {
   uint64_t id;             /* caller's id, returned in lsamg_done                */

@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <mutex>
 #include <numeric>
 #include <stdexcept>
@@ -592,7 +593,25 @@ void spectral_and_smoother(Level& L, Work& W, const lsamg_params& p, int level, 
   };
   int nt = nthreads > 0 ? nthreads : default_threads();
   std::vector<std::vector<int32_t>> locs(nt);
+  // verbose: a line per tenth of the level's aggregates finished
+  std::atomic<int64_t> finished{0};
+  const int64_t tenth = std::max<int64_t>(1, na / 10);
+  const auto t_level = tick();
   parallel_for(na, [&](int64_t a, int t) {
+    struct Done {
+      std::atomic<int64_t>& f;
+      int64_t na, tenth;
+      bool verbose;
+      int level;
+      std::chrono::steady_clock::time_point t0;
+      ~Done() {
+        const int64_t d = ++f;
+        if (verbose && na >= 20 && d % tenth == 0)
+          std::fprintf(stderr, "lsamg setup: level %d: %lld of %lld aggregates, %.1f s\n", level,
+                       (long long)d, (long long)na,
+                       std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      }
+    } done{finished, na, tenth, p.verbose != 0, level, t_level};
     if (locs[t].empty()) locs[t].assign(n, -1);
     auto& loc = locs[t];
     const int nw = (int)(L.astart[a + 1] - L.astart[a]);
@@ -717,10 +736,10 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
   auto secs = [](std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
-  // a batch grows while its padded blocks stay within 2^30 doubles (8 GiB),
+  // a batch grows while its padded blocks stay within 2^31 doubles (16 GiB),
   // and, once it holds 64 aggregates (enough to fill the device), while its
   // largest |Omega| stays within 1.25 x + 16 of its smallest
-  const double cap = (double)(1 << 30);
+  const double cap = (double)(1LL << 31);
   for (int64_t i = 0; i < na;) {
     int64_t R = rowv[order[i]], Wd = nwv[order[i]], Od = nov[order[i]];
     int64_t Gd = Od - Wd;
@@ -739,28 +758,36 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
     const int nb = (int)(j - i);
     auto t0 = now();
     std::vector<int32_t> bnw(nb), rank(nb);
-    std::vector<double> Bw((size_t)nb * R * Wd, 0.0), Bg((size_t)nb * R * Gd, 0.0);
-    std::vector<double> Aww((size_t)nb * Wd * Wd, 0.0), Ai((size_t)nb * Od * Od, 0.0);
+    // batch buffers left uninitialised here: each aggregate's thread clears
+    // its own blocks, and the device writes every output entry
+    auto buf = [](size_t c) { return std::unique_ptr<double[]>(new double[std::max<size_t>(c, 1)]); };
+    auto Bw = buf((size_t)nb * R * Wd), Bg = buf((size_t)nb * R * Gd);
+    auto Aww = buf((size_t)nb * Wd * Wd), Ai = buf((size_t)nb * Od * Od);
     parallel_for(nb, [&](int64_t b, int t) {
       if (locs[t].empty()) locs[t].assign(n, -1);
       const int64_t a = order[i + b];
       bnw[b] = nwv[a];
-      double* aww = Aww.data() + (size_t)b * Wd * Wd;
-      double* ai = Ai.data() + (size_t)b * Od * Od;
-      local_blocks(L, W, a, locs[t], Bw.data() + (size_t)b * R * Wd, Bg.data() + (size_t)b * R * Gd,
-                   R, aww, (int)Wd, ai, (int)Od);
+      double* bw = Bw.get() + (size_t)b * R * Wd;
+      double* bg = Bg.get() + (size_t)b * R * Gd;
+      double* aww = Aww.get() + (size_t)b * Wd * Wd;
+      double* ai = Ai.get() + (size_t)b * Od * Od;
+      std::fill_n(bw, (size_t)R * Wd, 0.0);
+      std::fill_n(bg, (size_t)R * Gd, 0.0);
+      std::fill_n(aww, (size_t)Wd * Wd, 0.0);
+      std::fill_n(ai, (size_t)Od * Od, 0.0);
+      local_blocks(L, W, a, locs[t], bw, bg, R, aww, (int)Wd, ai, (int)Od);
       for (int64_t q = nwv[a]; q < Wd; ++q) aww[(size_t)q * Wd + q] = 1.0;
       for (int64_t q = nov[a]; q < Od; ++q) ai[(size_t)q * Od + q] = 1.0;
     }, nthreads);
     t_asm += secs(t0);
     t0 = now();
-    std::vector<double> mu((size_t)nb * Wd), U((size_t)nb * Wd * Wd), Z((size_t)nb * Od * Wd);
-    std::vector<double> Ainv(additive ? (size_t)nb * Od * Od : 0);
+    auto mu = buf((size_t)nb * Wd), U = buf((size_t)nb * Wd * Wd), Z = buf((size_t)nb * Od * Wd);
+    auto Ainv = buf(additive ? (size_t)nb * Od * Od : 0);
     std::string msg;
     const int rc = device_local_problems(p.device, nb, (int)R, (int)Wd, (int)Gd, (int)Od,
-                                         p.pinv_rtol, bnw.data(), Bw.data(), Bg.data(), Aww.data(),
-                                         Ai.data(), mu.data(), U.data(), Z.data(),
-                                         additive ? Ainv.data() : nullptr, rank.data(),
+                                         p.pinv_rtol, bnw.data(), Bw.get(), Bg.get(), Aww.get(),
+                                         Ai.get(), mu.get(), U.get(), Z.get(),
+                                         additive ? Ainv.get() : nullptr, rank.data(),
                                          p.verbose ? ph : nullptr, msg);
     if (rc != LSAMG_OK) fail(rc, msg);
     t_dev += secs(t0);
@@ -768,12 +795,12 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
     parallel_for(nb, [&](int64_t b, int) {
       const int64_t a = order[i + b];
       const int nw = nwv[a], nO = nov[a];
-      const double* m = mu.data() + (size_t)b * Wd;
+      const double* m = mu.get() + (size_t)b * Wd;
       bool hz = false;
       const int k = select_count(m, nw, p, level, L.thresh, hz);
       if (hz) hazards++;
       std::vector<double> Zh((size_t)nw * k);
-      const double* ub = U.data() + (size_t)b * Wd * Wd;
+      const double* ub = U.get() + (size_t)b * Wd * Wd;
       for (int t2 = 0; t2 < k; ++t2) {
         const double* u = ub + (size_t)t2 * Wd;
         int jm = 0;
@@ -786,13 +813,13 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
       mus[a].assign(m, m + nw);
       zh[a] = std::move(Zh);
       std::vector<double> Zc((size_t)nO * nw);
-      const double* zb = Z.data() + (size_t)b * Od * Wd;
+      const double* zb = Z.get() + (size_t)b * Od * Wd;
       for (int q = 0; q < nw; ++q)
         std::copy(zb + (size_t)q * Od, zb + (size_t)q * Od + nO, Zc.begin() + (size_t)q * nO);
       zs[a] = std::move(Zc);
       if (additive) {
         std::vector<double> Za((size_t)nO * nO);
-        const double* ab = Ainv.data() + (size_t)b * Od * Od;
+        const double* ab = Ainv.get() + (size_t)b * Od * Od;
         for (int q = 0; q < nO; ++q)
           std::copy(ab + (size_t)q * Od, ab + (size_t)q * Od + nO, Za.begin() + (size_t)q * nO);
         za[a] = std::move(Za);

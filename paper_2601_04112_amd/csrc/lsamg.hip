@@ -4213,9 +4213,9 @@ size_t batched_reserve(const lsamg_handle* h, int NB) {
 }  // namespace
 
 // HBM a device setup may hold while it runs (its batches' blocks, at most
-// 2^30 doubles, plus the factorisations' workspace), admitted by the server
+// 2^31 doubles, plus the factorisations' workspace), admitted by the server
 // for the duration of a setup on the device
-constexpr size_t kSetupTransient = (size_t)12 << 30;
+constexpr size_t kSetupTransient = (size_t)24 << 30;
 
 struct lsamg_server {
   int device = 0;

@@ -248,7 +248,7 @@ def test_hierarchy_larger_than_budget(gpu_device):
 
 def test_device_setup_in_server(gpu_device):
     """Requests asking for the setup on the device: the server runs it on its
-    device with 12 GiB of the budget held meanwhile; the solutions reach the
+    device with 24 GiB of the budget held meanwhile; the solutions reach the
     tolerance and equal those of a host setup within it; a singular operator
     fails alone (its device Cholesky reports it); a budget below the setup's
     transient need fails the request with LSAMG_ENOMEM."""
@@ -258,7 +258,7 @@ def test_device_setup_in_server(gpu_device):
     Gb[:, 7] = 0.0
     import scipy.sparse as sp
     Gb = sp.csr_matrix(Gb)
-    srv = L.Server(hbm_budget=32 << 30, max_slots=2)
+    srv = L.Server(hbm_budget=40 << 30, max_slots=2)
     ids = {}
     for i in range(6):
         k = i % 2
@@ -274,7 +274,7 @@ def test_device_setup_in_server(gpu_device):
     for rid, (k, b) in ids.items():
         assert res[rid]["status"] == 0, res[rid]["msg"]
         check(probs[k], b, res[rid]["x"], 1e-8)
-    assert st["peak_bytes"] <= 32 << 30
+    assert st["peak_bytes"] <= 40 << 30
     # the same requests with a host setup: solutions within the tolerance
     srv = L.Server(hbm_budget=8 << 30, max_slots=2)
     host_ids = {}
