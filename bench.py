@@ -320,6 +320,8 @@ def main():
     ap.add_argument("--setup", choices=("device", "host"), default="device",
                     help="where the setup's dense local problems run (untimed): "
                          "batched on the GPU, or on the host's cores")
+    ap.add_argument("--verbose-setup", action="store_true",
+                    help="per-level setup lines on stderr (always on for ls3d)")
     ap.add_argument("--maxit", type=int, default=0,
                     help="PCG iteration cap (default 1000; 200 for ls3d)")
     args = ap.parse_args()
@@ -373,7 +375,8 @@ def main():
     else:
         prob = P.config2(args.N)
         s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle,
-                     omega_max=args.omega_max, setup_device=args.setup == "device")
+                     omega_max=args.omega_max, setup_device=args.setup == "device",
+                     verbose=args.verbose_setup)
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
     print(f"setup {t_setup:.1f} s", file=sys.stderr, flush=True)
