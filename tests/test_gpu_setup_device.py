@@ -140,3 +140,39 @@ def test_device_setup_config2_full_size(gpu_device):
         assert st[0]["iters"] <= math.ceil(1.10 * K)
     finally:
         s.close()
+
+
+def test_device_setup_3d_small(gpu_device):
+    """The 3D D1 + B^T D2^-1 B form (anisotropy oblique to the grid,
+    lognormal coefficient) with the setup on the device: integer setup equal
+    to the oracle's, local eigenvalues to 1e-10, the V-cycle to 1e-10, and
+    the converged solve at the tolerance on the true residual within one
+    iteration of the host-setup library's stop count (its PCG iterates are
+    compared with the oracle's, under CG's own amplification on this
+    operator, in the host-setup 3D parity test)."""
+    p = P.ls3d(12)
+    print(f"[case] device setup 3D n={p.n}", flush=True)
+    prm = dict(block=3, cmin=(2,), max_coarse=100)
+    H = O.setup(p.G, 3, p.grid, O.Params(**prm))
+    s = L.Solver(p.G, 3, p.grid, device=0, setup_device=True, dense_tail=0, **prm)
+    sh = L.Solver(p.G, 3, p.grid, device=0, dense_tail=0, **prm)
+    try:
+        for l, Lv in enumerate(H.levels):
+            if Lv.coarsest:
+                break
+            e = s.export_setup(l)
+            assert np.array_equal(e["agg"], Lv.agg) and np.array_equal(e["k"], Lv.k), l
+            mu = np.split(e["mu"], e["muptr"][1:-1])
+            for i, (a, b) in enumerate(zip(mu, Lv.mu)):
+                assert np.abs(a - b).max() <= 1e-10 * max(1.0, np.abs(b).max()), (l, i)
+        v = np.random.default_rng(9).standard_normal(p.n)
+        assert rel(host(s.apply(L.OP_VCYCLE, dvec(v))), O.vcycle(H, v)) <= 1e-10
+        b = P.rhs_uniform(p.n, 3)
+        x, st = s.solve(dvec(b), tol=1e-8)
+        _, sth = sh.solve(dvec(b), tol=1e-8)
+        r = np.linalg.norm(b - H.levels[0].A @ host(x)) / np.linalg.norm(b)
+        assert st[0]["converged"] == 1 and r <= 1e-8
+        assert abs(st[0]["iters"] - sth[0]["iters"]) <= 1
+    finally:
+        s.close()
+        sh.close()
