@@ -761,18 +761,17 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
     // batch buffers left uninitialised here: each aggregate's thread clears
     // its own blocks, and the device writes every output entry
     auto buf = [](size_t c) { return std::unique_ptr<double[]>(new double[std::max<size_t>(c, 1)]); };
-    auto Bw = buf((size_t)nb * R * Wd), Bg = buf((size_t)nb * R * Gd);
+    auto Bb = buf((size_t)nb * R * (Gd + Wd));          // per aggregate [B_Gamma B_w]
     auto Aww = buf((size_t)nb * Wd * Wd), Ai = buf((size_t)nb * Od * Od);
     parallel_for(nb, [&](int64_t b, int t) {
       if (locs[t].empty()) locs[t].assign(n, -1);
       const int64_t a = order[i + b];
       bnw[b] = nwv[a];
-      double* bw = Bw.get() + (size_t)b * R * Wd;
-      double* bg = Bg.get() + (size_t)b * R * Gd;
+      double* bg = Bb.get() + (size_t)b * R * (Gd + Wd);
+      double* bw = bg + (size_t)R * Gd;
       double* aww = Aww.get() + (size_t)b * Wd * Wd;
       double* ai = Ai.get() + (size_t)b * Od * Od;
-      std::fill_n(bw, (size_t)R * Wd, 0.0);
-      std::fill_n(bg, (size_t)R * Gd, 0.0);
+      std::fill_n(bg, (size_t)R * (Gd + Wd), 0.0);
       std::fill_n(aww, (size_t)Wd * Wd, 0.0);
       std::fill_n(ai, (size_t)Od * Od, 0.0);
       local_blocks(L, W, a, locs[t], bw, bg, R, aww, (int)Wd, ai, (int)Od);
@@ -785,8 +784,8 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
     auto Ainv = buf(additive ? (size_t)nb * Od * Od : 0);
     std::string msg;
     const int rc = device_local_problems(p.device, nb, (int)R, (int)Wd, (int)Gd, (int)Od,
-                                         p.pinv_rtol, bnw.data(), Bw.get(), Bg.get(), Aww.get(),
-                                         Ai.get(), mu.get(), U.get(), Z.get(),
+                                         p.pinv_rtol, bnw.data(), Bb.get(), Aww.get(), Ai.get(),
+                                         mu.get(), U.get(), Z.get(),
                                          additive ? Ainv.get() : nullptr, rank.data(),
                                          p.verbose ? ph : nullptr, msg);
     if (rc != LSAMG_OK) fail(rc, msg);

@@ -91,8 +91,8 @@ int default_threads();
 // (setup on the device, csrc/setup_device.hip), every block padded to the
 // batch's sizes: R rows of W^{1/2} G_{nz_i}, W unknowns of omega_i, Gm of
 // Gamma_i, O of Omega_i.  Inputs (host, column-major, packed per aggregate):
-// Bw (R x W) and Bg (R x Gm), the columns of W^{1/2} G_{nz_i} on omega_i and
-// on Gamma_i (zero in padded rows and columns); Aww (W x W) = A_ww of
+// B (R x (Gm + W)) = W^{1/2} G_{nz_i} with its Gamma_i columns first, then
+// its omega_i columns (zero in padded rows and columns); Aww (W x W) = A_ww of
 // eq:gevp-S and Ai (O x O) = A(Omega_i, Omega_i), both identity on their
 // padded diagonal; nw[b] the true |omega_i|.  Outputs (host): mu (W per
 // aggregate) the eigenvalues of S~ u = mu A_ww u ascending, the true ones
@@ -104,9 +104,9 @@ int default_threads();
 // solves, eigensolver, local inverses, downloads), with a synchronisation
 // after each.  Returns an LSAMG_* code, msg on error.
 int device_local_problems(int device, int nb, int R, int W, int Gm, int O, double rtol,
-                          const int32_t* nw, const double* Bw, const double* Bg, const double* Aww,
-                          const double* Ai, double* mu, double* U, double* Z, double* Ainv,
-                          int32_t* rank, double* phase, std::string& msg);
+                          const int32_t* nw, const double* B, const double* Aww, const double* Ai,
+                          double* mu, double* U, double* Z, double* Ainv, int32_t* rank,
+                          double* phase, std::string& msg);
 
 // Ainv = A^{-1} for the SPD n x n matrix A (column-major, host) on the HIP
 // device `device` (Cholesky factor, then solves against the identity).

@@ -3,11 +3,15 @@
 //
 // Per aggregate i (sec. 3.1.1, eq:gevp, eq:gevp-S):
 //   1. the pseudo-inverse Schur complement S~ = B_w^T (I - Q Q^T) B_w, with
-//      B = W^{1/2} G_{nz_i} split into its omega_i columns B_w and its Gamma_i
-//      columns B_Gamma, and Q the left singular vectors of B_Gamma whose
-//      singular values exceed rtol times the largest (batched SVD; the
-//      dropped vectors are zeroed, then C = Q^T B_w, E = B_w - Q C and
-//      S~ = E^T E as batched GEMMs);
+//      B = W^{1/2} G_{nz_i} split into its Gamma_i columns B_Gamma and its
+//      omega_i columns B_w, and Q the left singular vectors of B_Gamma whose
+//      singular values exceed rtol times the largest.  Blocks with at least
+//      as many rows as columns are first reduced by a batched Householder QR
+//      of [B_Gamma B_w] to its R factor [R11 R12; 0 R22] (the SVD is then
+//      that of R11, and the R22 part is added as R22^T R22), as the host
+//      setup does; otherwise the SVD is that of B_Gamma.  The dropped
+//      vectors are zeroed, then C = Q^T B_w, E = B_w - Q C and S~ = E^T E
+//      are batched GEMMs;
 //   2. the reduced eigenproblem S~ u = mu A_ww u through the Cholesky factor
 //      A_ww = L L^T: C = L^{-1} S~ L^{-T} (batched triangular solves),
 //      symmetrised, then the batched eigensolver (Jacobi for blocks of up
@@ -74,6 +78,7 @@ struct RocApi {
   decltype(&rocblas_dgemm_strided_batched) gemm = nullptr;
   decltype(&rocblas_dtrsm_strided_batched) trsm = nullptr;
   decltype(&rocsolver_dgesvd_strided_batched) gesvd = nullptr;
+  decltype(&rocsolver_dgeqrf_strided_batched) geqrf = nullptr;
   decltype(&rocsolver_dpotrf_strided_batched) potrf = nullptr;
   decltype(&rocsolver_dpotrs_strided_batched) potrs = nullptr;
   decltype(&rocsolver_dsyevj_strided_batched) syevj = nullptr;
@@ -121,6 +126,7 @@ const RocApi& roc_api() {
     get(hb, "rocblas_dgemm_strided_batched", api.gemm);
     get(hb, "rocblas_dtrsm_strided_batched", api.trsm);
     get(hs, "rocsolver_dgesvd_strided_batched", api.gesvd);
+    get(hs, "rocsolver_dgeqrf_strided_batched", api.geqrf);
     get(hs, "rocsolver_dpotrf_strided_batched", api.potrf);
     get(hs, "rocsolver_dpotrs_strided_batched", api.potrs);
     get(hs, "rocsolver_dsyevj_strided_batched", api.syevj);
@@ -162,6 +168,28 @@ __global__ void __launch_bounds__(256) k_keep_mask(int R, int mn, double rtol,
   }
   __syncthreads();
   if (t == 0) rank[b] = cnt;
+}
+
+// From the Householder QR of B (R x (Gm + W) per aggregate, R factor in the
+// upper triangle): R11 (Gm x Gm) and R22 (W x W, rows and columns Gm ..
+// Gm + W - 1), upper triangular with zeros below the diagonal.  One
+// workgroup per aggregate.
+__global__ void __launch_bounds__(256) k_upper_blocks(int R, int Gm, int W,
+                                                      const double* __restrict__ B,
+                                                      double* __restrict__ R11,
+                                                      double* __restrict__ R22) {
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double* a = B + (size_t)b * R * (Gm + W);
+  double* r11 = R11 + (size_t)b * Gm * Gm;
+  double* r22 = R22 + (size_t)b * W * W;
+  for (int64_t e = t; e < (int64_t)Gm * Gm; e += 256) {
+    const int i = (int)(e % Gm), j = (int)(e / Gm);
+    r11[e] = i <= j ? a[(size_t)j * R + i] : 0.0;
+  }
+  for (int64_t e = t; e < (int64_t)W * W; e += 256) {
+    const int i = (int)(e % W), j = (int)(e / W);
+    r22[e] = i <= j ? a[(size_t)(Gm + j) * R + Gm + i] : 0.0;
+  }
 }
 
 // Symmetrise the true nw[b] x nw[b] block of C (W x W per aggregate) as
@@ -270,12 +298,12 @@ struct Ctx {
 }  // namespace
 
 int device_local_problems(int device, int nb, int R, int W, int Gm, int O, double rtol,
-                          const int32_t* nw, const double* Bw, const double* Bg, const double* Aww,
-                          const double* Ai, double* mu, double* U, double* Z, double* Ainv,
-                          int32_t* rank, double* phase, std::string& msg) {
+                          const int32_t* nw, const double* B, const double* Aww, const double* Ai,
+                          double* mu, double* U, double* Z, double* Ainv, int32_t* rank,
+                          double* phase, std::string& msg) {
   if (nb <= 0) return LSAMG_OK;
-  if (R < 0 || W <= 0 || Gm < 0 || O < W || !nw || !Bw || !Aww || !Ai || !mu || !U || !Z ||
-      !rank || (Gm > 0 && !Bg)) {
+  if (R < 0 || W <= 0 || Gm < 0 || O < W || !nw || !B || !Aww || !Ai || !mu || !U || !Z ||
+      !rank) {
     msg = "device setup: bad batch sizes or pointers";
     return LSAMG_EINVAL;
   }
@@ -288,9 +316,9 @@ int device_local_problems(int device, int nb, int R, int W, int Gm, int O, doubl
     Ctx c(device, api);
     const size_t nbz = (size_t)nb;
     const double one = 1.0, zero = 0.0, mone = -1.0;
-    // phase seconds (when asked): 0 uploads, 1 SVD, 2 Schur products,
-    // 3 Cholesky and triangular solves, 4 eigensolver, 5 local inverses,
-    // 6 downloads
+    // phase seconds (when asked): 0 uploads, 1 SVD (and the QR before it),
+    // 2 Schur products, 3 Cholesky and triangular solves, 4 eigensolver,
+    // 5 local inverses, 6 downloads
     auto t_last = std::chrono::steady_clock::now();
     auto mark = [&](int i) {
       if (!phase) return;
@@ -299,40 +327,77 @@ int device_local_problems(int device, int nb, int R, int W, int Gm, int O, doubl
       phase[i] += std::chrono::duration<double>(t - t_last).count();
       t_last = t;
     };
+    const int nc = Gm + W;                      // columns of B: Gamma first, then omega
+    const rocblas_stride sB = (rocblas_stride)R * nc;
     int32_t* dnw = c.upload(nw, nbz);
-    double* dBw = c.upload(Bw, nbz * R * W);
+    double* dB = c.upload(B, nbz * R * nc);
+    double* dBw = dB + (size_t)R * Gm;          // omega columns (leading dimension R)
     rocblas_int* info = c.alloc<rocblas_int>(nbz);
     int32_t* drank = c.alloc<int32_t>(nbz);
     SD_HIP(hipMemsetAsync(drank, 0, nbz * sizeof(int32_t), c.s));
-    // 1. S~ = B_w^T (I - Q Q^T) B_w
-    const int mn = std::min(R, Gm);
     double* dAww = c.upload(Aww, nbz * W * W);
     double* dAi = c.upload(Ai, nbz * O * O);
-    double* dBg = mn > 0 ? c.upload(Bg, nbz * R * Gm) : nullptr;
     mark(0);
-    if (mn > 0) {
-      double* dS = c.alloc<double>(nbz * mn);
-      double* dU = c.alloc<double>(nbz * R * mn);
-      double* dE = c.alloc<double>(nbz * std::max(mn - 1, 1));
-      SD_ROC(api.gesvd(c.hb, rocblas_svect_singular, rocblas_svect_none, R, Gm, dBg, R,
-                       (rocblas_stride)R * Gm, dS, mn, dU, R, (rocblas_stride)R * mn, nullptr, 1, 1,
-                       dE, std::max(mn - 1, 1), rocblas_outofplace, info, nb));
+    // 1. S~ = B_w^T (I - Q Q^T) B_w
+    double* dSm = c.alloc<double>(nbz * W * W);
+    if (Gm > 0 && R >= nc) {
+      // tall blocks: B = [B_Gamma B_w] = Q [R11 R12; 0 R22] (Householder QR),
+      // R11 = W Sigma Y^T; with W_k the kept left vectors,
+      // S~ = (R12 - W_k W_k^T R12)^T (R12 - W_k W_k^T R12) + R22^T R22
+      double* dtau = c.alloc<double>(nbz * nc);
+      SD_ROC(api.geqrf(c.hb, R, nc, dB, R, sB, dtau, nc, nb));
+      double* dR11 = c.alloc<double>(nbz * Gm * Gm);
+      double* dR22 = c.alloc<double>(nbz * W * W);
+      hipLaunchKernelGGL(k_upper_blocks, dim3(nb), dim3(256), 0, c.s, R, Gm, W, (const double*)dB,
+                         dR11, dR22);
+      SD_HIP(hipGetLastError());
+      double* dS = c.alloc<double>(nbz * Gm);
+      double* dU = c.alloc<double>(nbz * Gm * Gm);
+      double* dE = c.alloc<double>(nbz * std::max(Gm - 1, 1));
+      SD_ROC(api.gesvd(c.hb, rocblas_svect_singular, rocblas_svect_none, Gm, Gm, dR11, Gm,
+                       (rocblas_stride)Gm * Gm, dS, Gm, dU, Gm, (rocblas_stride)Gm * Gm, nullptr, 1,
+                       1, dE, std::max(Gm - 1, 1), rocblas_outofplace, info, nb));
       c.check_info(info, nb, LSAMG_ENOTSPD, "singular value iteration did not converge");
       mark(1);
-      hipLaunchKernelGGL(k_keep_mask, dim3(nb), dim3(256), 0, c.s, R, mn, rtol, dS, dU, drank);
+      hipLaunchKernelGGL(k_keep_mask, dim3(nb), dim3(256), 0, c.s, Gm, Gm, rtol, dS, dU, drank);
       SD_HIP(hipGetLastError());
-      double* dC = c.alloc<double>(nbz * mn * W);
-      SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, mn, W, R, &one, dU,
-                      R, (rocblas_stride)R * mn, dBw, R, (rocblas_stride)R * W, &zero, dC, mn,
-                      (rocblas_stride)mn * W, nb));
-      SD_ROC(api.gemm(c.hb, rocblas_operation_none, rocblas_operation_none, R, W, mn, &mone, dU, R,
-                      (rocblas_stride)R * mn, dC, mn, (rocblas_stride)mn * W, &one, dBw, R,
-                      (rocblas_stride)R * W, nb));
+      double* dC = c.alloc<double>(nbz * Gm * W);
+      SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, Gm, W, Gm, &one, dU,
+                      Gm, (rocblas_stride)Gm * Gm, dBw, R, sB, &zero, dC, Gm,
+                      (rocblas_stride)Gm * W, nb));
+      SD_ROC(api.gemm(c.hb, rocblas_operation_none, rocblas_operation_none, Gm, W, Gm, &mone, dU, Gm,
+                      (rocblas_stride)Gm * Gm, dC, Gm, (rocblas_stride)Gm * W, &one, dBw, R, sB,
+                      nb));
+      SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, W, W, Gm, &one, dBw,
+                      R, sB, dBw, R, sB, &zero, dSm, W, (rocblas_stride)W * W, nb));
+      SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, W, W, W, &one, dR22,
+                      W, (rocblas_stride)W * W, dR22, W, (rocblas_stride)W * W, &one, dSm, W,
+                      (rocblas_stride)W * W, nb));
+    } else {
+      // S~ from the left singular vectors of B_Gamma itself
+      const int mn = std::min(R, Gm);
+      if (mn > 0) {
+        double* dS = c.alloc<double>(nbz * mn);
+        double* dU = c.alloc<double>(nbz * R * mn);
+        double* dE = c.alloc<double>(nbz * std::max(mn - 1, 1));
+        SD_ROC(api.gesvd(c.hb, rocblas_svect_singular, rocblas_svect_none, R, Gm, dB, R, sB, dS, mn,
+                         dU, R, (rocblas_stride)R * mn, nullptr, 1, 1, dE, std::max(mn - 1, 1),
+                         rocblas_outofplace, info, nb));
+        c.check_info(info, nb, LSAMG_ENOTSPD, "singular value iteration did not converge");
+        mark(1);
+        hipLaunchKernelGGL(k_keep_mask, dim3(nb), dim3(256), 0, c.s, R, mn, rtol, dS, dU, drank);
+        SD_HIP(hipGetLastError());
+        double* dC = c.alloc<double>(nbz * mn * W);
+        SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, mn, W, R, &one,
+                        dU, R, (rocblas_stride)R * mn, dBw, R, sB, &zero, dC, mn,
+                        (rocblas_stride)mn * W, nb));
+        SD_ROC(api.gemm(c.hb, rocblas_operation_none, rocblas_operation_none, R, W, mn, &mone, dU, R,
+                        (rocblas_stride)R * mn, dC, mn, (rocblas_stride)mn * W, &one, dBw, R, sB,
+                        nb));
+      }
+      SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, W, W, R, &one, dBw,
+                      R, sB, dBw, R, sB, &zero, dSm, W, (rocblas_stride)W * W, nb));
     }
-    double* dSm = c.alloc<double>(nbz * W * W);
-    SD_ROC(api.gemm(c.hb, rocblas_operation_transpose, rocblas_operation_none, W, W, R, &one, dBw, R,
-                    (rocblas_stride)R * W, dBw, R, (rocblas_stride)R * W, &zero, dSm, W,
-                    (rocblas_stride)W * W, nb));
     mark(2);
     // 2. S~ u = mu A_ww u
     SD_ROC(api.potrf(c.hb, rocblas_fill_lower, W, dAww, W, (rocblas_stride)W * W, info, nb));
