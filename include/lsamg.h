@@ -124,7 +124,7 @@ typedef struct lsamg_params {
                             complement of eq:gevp-S, the reduced local
                             eigenproblem, the local inverses A_i^{-1}) run on
                             the host's cores; 1: they run on the HIP device
-                            `device` as batched FP64 factorisations (batched
+                            `device` as batched FP64 factorisations (batched QR,
                             SVD, Cholesky and symmetric eigensolvers of rocSOLVER,
                             batched GEMM and triangular solves of rocBLAS, both
                             loaded when first needed), aggregates of similar
