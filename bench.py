@@ -177,7 +177,7 @@ def run_serving(args):
             bw = np.stack([P.rhs_uniform(probs[k].n, 7 + j) for j in range(args.prewarm_rhs)])
             srv.submit(k, probs[k].G, 2, probs[k].grid, bw,
                        tol=1e-8, precision=L.MIXED, req_id=10 ** 6 + k, cmin=(2,),
-                       setup_device=args.setup == "device")
+                       setup_device=args.setup)
         got = 0
         warm = []
         while got < args.pool:
@@ -213,7 +213,7 @@ def run_serving(args):
                 p = probs[k]
                 b = np.stack([P.rhs_uniform(p.n, seed + j) for j in range(nr)])
                 srv.submit(k, p.G, 2, p.grid, b, tol=1e-8, precision=L.MIXED,
-                           req_id=next_id + i, cmin=(2,), setup_device=args.setup == "device")
+                           req_id=next_id + i, cmin=(2,), setup_device=args.setup)
                 i += 1
             wait = 5 if i >= len(reqs) else max(0, int((reqs[i][0] - now) * 1e3))
             for d in srv.poll(wait_ms=min(wait, 20)):
@@ -317,9 +317,10 @@ def main():
     ap.add_argument("--cycle", choices=("v", "additive"), default="v",
                     help="aniso2d: the multiplicative V-cycle or the additive cycle of "
                          "sec. 3.1.1 (single right-hand sides only)")
-    ap.add_argument("--setup", choices=("device", "host"), default="device",
+    ap.add_argument("--setup", choices=("auto", "device", "host"), default="auto",
                     help="where the setup's dense local problems run (untimed): "
-                         "batched on the GPU, or on the host's cores")
+                         "batched on the GPU, on the host's cores, or (auto) on "
+                         "the GPU from 100,000 unknowns on")
     ap.add_argument("--verbose-setup", action="store_true",
                     help="per-level setup lines on stderr (always on for ls3d)")
     ap.add_argument("--maxit", type=int, default=0,
@@ -370,12 +371,12 @@ def main():
         print(f"ls3d N={args.N}: n={prob.n}, m={prob.m}, nnz={prob.G.nnz}; setup ...",
               file=sys.stderr, flush=True)
         s = L.Solver(prob.G, 3, prob.grid, device=0, block=3, cmin=(3, 4), verbose=True,
-                     setup_device=args.setup == "device")
+                     setup_device=args.setup)
         seed = P.CONFIG_RHS_SEED[3]
     else:
         prob = P.config2(args.N)
         s = L.Solver(prob.G, 2, prob.grid, device=0, cmin=cmin, cycle=args.cycle,
-                     omega_max=args.omega_max, setup_device=args.setup == "device",
+                     omega_max=args.omega_max, setup_device=args.setup,
                      verbose=args.verbose_setup)
         seed = P.CONFIG_RHS_SEED[2]
     t_setup = time.time() - t0
@@ -620,7 +621,8 @@ def main():
             "smoother_complexity": round(inf["smoother_complexity"], 3),
             "smoother_entries": smoother_entries,
             "setup_s": round(t_setup, 2),
-            "setup": args.setup,
+            "setup": ("device" if args.setup == "device"
+                      or (args.setup == "auto" and prob.n >= 100000) else "host"),
             "dense_tail_level": inf["tail_level"],
             "device_gb": round(inf["device_bytes"] / 1e9, 2),
             "parallelism": "single GPU",

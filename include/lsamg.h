@@ -119,19 +119,29 @@ typedef struct lsamg_params {
                             inverses A_i^{-1} (|Omega_i|^2 entries each), there
                             is no dense tail, and several right-hand sides are
                             solved one after another                         */
-  int32_t setup_device;  /* 0 (default): the local dense problems of every
-                            level (Algorithm 1: the pseudo-inverse Schur
-                            complement of eq:gevp-S, the reduced local
-                            eigenproblem, the local inverses A_i^{-1}) run on
-                            the host's cores; 1: they run on the HIP device
-                            `device` as batched FP64 factorisations (batched QR,
+  int32_t setup_device;  /* where the local dense problems of every level
+                            (Algorithm 1: the pseudo-inverse Schur complement
+                            of eq:gevp-S, the reduced local eigenproblem, the
+                            local inverses A_i^{-1}) run.
+                            LSAMG_SETUP_HOST (0): on the host's cores;
+                            LSAMG_SETUP_DEVICE (1): on the HIP device `device`
+                            as batched FP64 factorisations (batched QR,
                             SVD, Cholesky and symmetric eigensolvers of rocSOLVER,
                             batched GEMM and triangular solves of rocBLAS, both
                             loaded when first needed), aggregates of similar
                             size padded into one batch; the integer steps and
                             G_{l+1} = G_l P_l stay on the host.  Needs
-                            device >= 0 (else LSAMG_EINVAL)                    */
+                            device >= 0 (else LSAMG_EINVAL);
+                            LSAMG_SETUP_AUTO (2, default): on the device when
+                            device >= 0 and G has at least 100,000 columns
+                            (where the batches fill the GPU), else on the host */
 } lsamg_params;
+
+enum {
+  LSAMG_SETUP_HOST = 0,
+  LSAMG_SETUP_DEVICE = 1,
+  LSAMG_SETUP_AUTO = 2
+};
 
 enum { LSAMG_AGG_LATTICE = 0, LSAMG_AGG_STANDARD = 1 };
 enum { LSAMG_CYCLE_V = 0, LSAMG_CYCLE_ADDITIVE = 1 };
@@ -211,9 +221,11 @@ typedef struct lsamg_handle lsamg_handle;
 
 /* One solve request.  Requests with equal op_key share one hierarchy: the
  * first builds it (setup, then upload once admitted), later ones find it
- * resident.  With params->setup_device the setup's dense local problems run
- * on the server's device, 24 GiB of the HBM budget held for them while it
- * runs (LSAMG_ENOMEM when that cannot be freed). */
+ * resident.  When params->setup_device puts the setup's dense local
+ * problems on the device, they run on the server's device with 24 GiB of the
+ * HBM budget held for them meanwhile; when that cannot be freed, an
+ * LSAMG_SETUP_DEVICE request fails with LSAMG_ENOMEM and an LSAMG_SETUP_AUTO
+ * one runs its setup on the host. */
 typedef struct lsamg_request {
   uint64_t id;             /* caller's id, returned in lsamg_done                */
   uint64_t op_key;         /* operator identity                                  */

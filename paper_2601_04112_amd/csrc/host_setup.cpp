@@ -8,9 +8,10 @@
 // reduced eigenproblem eq:gevp-S solved as S~ u = mu A_ww u; selection of
 // sec. 3.4; smoother rows Z_i = A_i^{-1}(omega_i, Omega_i); interpolation
 // eq:mg-p; G_{l+1} = G_l P_l (sec. 3.1.3) with exact row compression.
-// With setup_device set, the dense local problems (Schur complement,
-// eigenproblem, local and coarsest inverses) go to the HIP device in
-// batches (setup_device.hip); everything else stays here.
+// When setup_device puts them there (setup_on_device), the dense local
+// problems (Schur complement, eigenproblem, local and coarsest inverses) go
+// to the HIP device in batches (setup_device.hip); everything else stays
+// here.
 #include <algorithm>
 #include <cstdio>
 #include <array>
@@ -1032,6 +1033,11 @@ void coarsest_inverse(Level& L, Work& W, int nthreads, int device) {
 
 }  // namespace
 
+bool setup_on_device(const lsamg_params& p, int64_t n) {
+  if (p.device < 0 || p.setup_device == LSAMG_SETUP_HOST) return false;
+  return p.setup_device == LSAMG_SETUP_DEVICE || n >= kAutoDeviceSetupN;
+}
+
 int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, std::string& msg) {
   auto t0 = std::chrono::steady_clock::now();
   try {
@@ -1051,9 +1057,11 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
     if (Gin.n != np) fail(LSAMG_EINVAL, "G has n columns != product of grid extents");
     if (standard && (p.nagg_passes < 1 || p.nagg_passes > 8)) fail(LSAMG_EINVAL, "bad agg_passes");
     if (p.cycle != LSAMG_CYCLE_V && p.cycle != LSAMG_CYCLE_ADDITIVE) fail(LSAMG_EINVAL, "bad cycle");
-    if (p.setup_device != 0 && p.setup_device != 1) fail(LSAMG_EINVAL, "bad setup_device");
-    if (p.setup_device && p.device < 0)
+    if (p.setup_device < LSAMG_SETUP_HOST || p.setup_device > LSAMG_SETUP_AUTO)
+      fail(LSAMG_EINVAL, "bad setup_device");
+    if (p.setup_device == LSAMG_SETUP_DEVICE && p.device < 0)
       fail(LSAMG_EINVAL, "setup on the device needs a HIP device (device >= 0)");
+    const bool on_dev = setup_on_device(p, Gin.n);
     if (Gin.m <= 0 || Gin.n <= 0 || !Gin.rowptr || (Gin.nnz > 0 && (!Gin.col || !Gin.val)))
       fail(LSAMG_EINVAL, "bad G");
     if (p.block < 1 || p.omega_max < 1 || p.max_levels < 1) fail(LSAMG_EINVAL, "bad params");
@@ -1174,13 +1182,13 @@ int build_hierarchy(const lsamg_csr& Gin, const lsamg_params& p, Hierarchy& H, s
       L.a_nnz = W.A.ptr[L.n];
       if (!aggregated) {
         L.coarsest = true;
-        coarsest_inverse(L, W, nthreads, p.setup_device ? p.device : -1);
+        coarsest_inverse(L, W, nthreads, on_dev ? p.device : -1);
         progress(l, "coarsest inverse done");
         break;
       }
       overlap_and_colour(L, W, p, nthreads);
       progress(l, "overlap and colouring done");
-      if (p.setup_device)
+      if (on_dev)
         spectral_and_smoother_device(L, W, p, l, nthreads);
       else
         spectral_and_smoother(L, W, p, l, nthreads);

@@ -108,6 +108,12 @@ int device_local_problems(int device, int nb, int R, int W, int Gm, int O, doubl
                           double* mu, double* U, double* Z, double* Ainv, int32_t* rank,
                           double* phase, std::string& msg);
 
+// Whether the setup of a G with n columns runs its dense local problems on
+// the device (setup_device, device): always for LSAMG_SETUP_DEVICE, from
+// kAutoDeviceSetupN columns on for LSAMG_SETUP_AUTO, never without a device.
+constexpr int64_t kAutoDeviceSetupN = 100000;
+bool setup_on_device(const lsamg_params& p, int64_t n);
+
 // Ainv = A^{-1} for the SPD n x n matrix A (column-major, host) on the HIP
 // device `device` (Cholesky factor, then solves against the identity).
 int device_spd_inverse(int device, int n, const double* A, double* Ainv, std::string& msg);

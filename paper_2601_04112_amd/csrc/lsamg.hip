@@ -3690,6 +3690,7 @@ void lsamg_params_default(lsamg_params* p) {
   p->aggregation = LSAMG_AGG_LATTICE;
   p->agg_passes[0] = 1;
   p->nagg_passes = 1;
+  p->setup_device = LSAMG_SETUP_AUTO;
 }
 
 const char* lsamg_last_error(void) { return g_last_error.c_str(); }
@@ -4498,17 +4499,23 @@ void lsamg_server::worker() {
       // a setup on the device holds transient buffers (batches of at most
       // 8 GiB of blocks, plus the factorisations' workspace): admitted
       // against the budget for its duration
-      const bool on_dev = first.r.params->setup_device != 0;
-      const bool room = !on_dev || make_room(lk, kSetupTransient);
-      if (on_dev && room) account(kSetupTransient, 0);
-      lk.unlock();
       lsamg_params p = *first.r.params;
+      p.device = device;
+      bool on_dev = setup_on_device(p, first.r.G->n);
+      bool room = !on_dev || make_room(lk, kSetupTransient);
+      if (on_dev && !room && p.setup_device == LSAMG_SETUP_AUTO) {
+        on_dev = false;                    // no room: the host does the setup
+        room = true;
+      }
+      if (on_dev) account(kSetupTransient, 0);
+      lk.unlock();
+      p.setup_device = on_dev ? LSAMG_SETUP_DEVICE : LSAMG_SETUP_HOST;
       p.device = on_dev ? device : -1;     // upload only after admission
       lsamg_handle* h = nullptr;
       int rc = room ? setup_impl(first.r.G, &p, false, &h) : LSAMG_ENOMEM;
       std::string msg = rc == LSAMG_OK ? "" : room ? lsamg_last_error()
                                                   : "no room in the device budget for the setup";
-      if (on_dev && room) {
+      if (on_dev) {
         std::lock_guard<std::mutex> g(mu);
         account(0, kSetupTransient);
       }

@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 OP_A, OP_RAS, OP_RAST, OP_VCYCLE = 0, 1, 2, 3
 AGG_LATTICE, AGG_STANDARD = 0, 1
 CYCLE_V, CYCLE_ADDITIVE = 0, 1
+SETUP_HOST, SETUP_DEVICE, SETUP_AUTO = 0, 1, 2
 OPT_BATCHED, OPT_MFMA, OPT_GRAPH, OPT_MFMA_TILE, OPT_ONEPASS_ATA, OPT_DENSE_SPLIT = 0, 1, 2, 3, 4, 5
 OPT_ATA_TILES, OPT_BGROUP, OPT_KRYLOV = 6, 7, 8
 KRYLOV_CG, KRYLOV_FCG, KRYLOV_BLOCK = 0, 1, 2
@@ -213,7 +214,7 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
                 device: int = 0, nthreads: int = 0, verbose: bool = False,
                 dense_tail: int = 16384, aggregation: str = "lattice",
                 agg_passes: Sequence[int] = (1,), cycle: str = "v",
-                setup_device: bool = False) -> Params:
+                setup_device="auto") -> Params:
     p = default_params()
     p.ndim = ndim
     for d in range(3):
@@ -239,7 +240,16 @@ def make_params(ndim: int, grid: Sequence[int], *, block: int = 4,
     if cycle not in ("v", "additive"):
         raise ValueError("cycle must be 'v' or 'additive'")
     p.cycle = CYCLE_ADDITIVE if cycle == "additive" else CYCLE_V
-    p.setup_device = 1 if setup_device else 0
+    # True / "device": the setup's dense local problems on the GPU; False /
+    # "host": on the host; "auto": on the GPU from 100,000 unknowns on
+    if setup_device in ("auto", None):
+        p.setup_device = SETUP_AUTO
+    elif setup_device in (True, "device", 1):
+        p.setup_device = SETUP_DEVICE
+    elif setup_device in (False, "host", 0):
+        p.setup_device = SETUP_HOST
+    else:
+        raise ValueError("setup_device must be 'auto', 'device' or 'host'")
     return p
 
 

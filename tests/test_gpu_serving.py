@@ -287,10 +287,17 @@ def test_device_setup_in_server(gpu_device):
         xd, xh = np.atleast_2d(res[rid]["x"]), np.atleast_2d(hres[hid]["x"])
         for j in range(xd.shape[0]):
             assert np.linalg.norm(xd[j] - xh[j]) <= 1e-6 * np.linalg.norm(xh[j])
-    # a budget below the setup's transient need
+    # a budget below the setup's transient need: a request that asks for the
+    # device fails, one in the automatic mode (an operator of over 100,000
+    # unknowns, which would go to the device) is set up on the host
+    big = P.aniso2d(320, 0.4, 1e-3)
     srv = L.Server(hbm_budget=8 << 30, max_slots=1)
     rid = srv.submit(0, probs[0].G, 2, probs[0].grid, np.ones(probs[0].n), tol=1e-8, cmin=(2,),
                      max_coarse=200, setup_device=True)
-    r = drain(srv, 1)[rid]
+    bb = P.rhs_uniform(big.n, 77)
+    rid2 = srv.submit(1, big.G, 2, big.grid, bb, tol=1e-8, cmin=(2,), setup_device="auto")
+    r = drain(srv, 2)
     srv.close()
-    assert r["status"] == L.LSAMG_ENOMEM
+    assert r[rid]["status"] == L.LSAMG_ENOMEM
+    assert big.n >= 100000 and r[rid2]["status"] == 0, r[rid2]["msg"]
+    check(big, bb, r[rid2]["x"], 1e-8)

@@ -148,6 +148,26 @@ def test_setup_on_device_needs_a_device():
     assert "device" in str(e.value)
 
 
+def test_setup_device_values():
+    """setup_device: 'auto' (the default) and 'host' build host-only handles
+    without a device; an unknown value is refused by the binding, and an
+    out-of-range one by the library."""
+    p = P.aniso2d(8, 0.0, 1.0)
+    for v in ("auto", "host", False):
+        s = L.Solver(p.G, 2, p.grid, device=-1, setup_device=v)
+        assert s.info()["nlevels"] >= 1
+        s.close()
+    with pytest.raises(ValueError):
+        L.make_params(2, p.grid, setup_device="gpu")
+    prm = L.make_params(2, p.grid, device=-1)
+    assert prm.setup_device == L.SETUP_AUTO
+    prm.setup_device = 7
+    csr = L._HostCsr(p.G)
+    h = ctypes.c_void_p()
+    rc = L.load().lsamg_setup(ctypes.byref(csr.csr), ctypes.byref(prm), ctypes.byref(h))
+    assert rc == L.LSAMG_EINVAL and not h.value
+
+
 def test_solve_without_device_is_refused():
     p = P.aniso2d(8, 0.0, 1.0)
     s = L.Solver(p.G, 2, p.grid, device=-1)
