@@ -732,6 +732,7 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
   std::atomic<int64_t> hazards{0};
   double t_asm = 0, t_dev = 0, t_post = 0;
   double ph[7] = {0, 0, 0, 0, 0, 0, 0};
+  int64_t full_rank = 0, with_gamma = 0;      // B_Gamma blocks, and those of full column rank
   int nbatch = 0;
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto secs = [](std::chrono::steady_clock::time_point t0) {
@@ -790,6 +791,11 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
                                          additive ? Ainv.get() : nullptr, rank.data(),
                                          p.verbose ? ph : nullptr, msg);
     if (rc != LSAMG_OK) fail(rc, msg);
+    for (int b = 0; b < nb; ++b) {
+      const int64_t a = order[i + b];
+      full_rank += rank[b] == nov[a] - nwv[a];
+      with_gamma += nov[a] > nwv[a];
+    }
     t_dev += secs(t0);
     t0 = now();
     parallel_for(nb, [&](int64_t b, int) {
@@ -835,9 +841,9 @@ void spectral_and_smoother_device(Level& L, Work& W, const lsamg_params& p, int 
                  "lsamg setup: level %d: %lld aggregates in %d device batches; seconds: blocks "
                  "%.2f, device %.2f (uploads %.2f, SVD %.2f, Schur products %.2f, Cholesky "
                  "and solves %.2f, eigensolver %.2f, local inverses %.2f, downloads %.2f), "
-                 "counts and copies %.2f\n",
+                 "counts and copies %.2f; Gamma blocks of full column rank: %lld of %lld\n",
                  level, (long long)na, nbatch, t_asm, t_dev, ph[0], ph[1], ph[2], ph[3], ph[4],
-                 ph[5], ph[6], t_post);
+                 ph[5], ph[6], t_post, (long long)full_rank, (long long)with_gamma);
     std::fflush(stderr);
   }
   store_local(L, mus, zs, zh, za, additive, nthreads);
