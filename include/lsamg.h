@@ -225,7 +225,10 @@ typedef struct lsamg_handle lsamg_handle;
  * problems on the device, they run on the server's device with 24 GiB of the
  * HBM budget held for them meanwhile; when that cannot be freed, an
  * LSAMG_SETUP_DEVICE request fails with LSAMG_ENOMEM and an LSAMG_SETUP_AUTO
- * one runs its setup on the host. */
+ * one runs its setup on the host.  The device setup's libraries (rocBLAS,
+ * rocSOLVER) are opened when the server is created, before its workers
+ * launch anything; outside the server they are opened by the first setup on
+ * the device, which should not overlap kernel launches of other threads. */
 typedef struct lsamg_request {
   uint64_t id;             /* caller's id, returned in lsamg_done                */
   uint64_t op_key;         /* operator identity                                  */

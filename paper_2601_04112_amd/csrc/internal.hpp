@@ -114,6 +114,12 @@ int device_local_problems(int device, int nb, int R, int W, int Gm, int O, doubl
 constexpr int64_t kAutoDeviceSetupN = 100000;
 bool setup_on_device(const lsamg_params& p, int64_t n);
 
+// Opens rocBLAS and rocSOLVER (whose loading registers their device code
+// with the HIP runtime) and makes and releases one rocBLAS handle on
+// `device`: done before other threads launch kernels, so that loading never
+// overlaps their launches.  Returns an LSAMG_* code, msg on error.
+int device_setup_preload(int device, std::string& msg);
+
 // Ainv = A^{-1} for the SPD n x n matrix A (column-major, host) on the HIP
 // device `device` (Cholesky factor, then solves against the identity).
 int device_spd_inverse(int device, int n, const double* A, double* Ainv, std::string& msg);

@@ -4666,6 +4666,14 @@ int lsamg_server_create(int32_t device, size_t hbm_budget, int32_t max_slots,
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
     return fail_with(LSAMG_ENODEV, "no such HIP device");
+  // the device setup's libraries are opened now, before any worker launches
+  // kernels: opening them later, in one worker, while another launches, has
+  // made those launches fail ("invalid device function").  Without them a
+  // setup on the device fails with its own message, and host setups work.
+  {
+    std::string pmsg;
+    (void)device_setup_preload(device, pmsg);
+  }
   lsamg_server* s = new (std::nothrow) lsamg_server();
   if (!s) return fail_with(LSAMG_ENOMEM, "server allocation failed");
   s->device = device;

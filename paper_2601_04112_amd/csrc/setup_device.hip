@@ -457,6 +457,21 @@ int device_local_problems(int device, int nb, int R, int W, int Gm, int O, doubl
   return LSAMG_OK;
 }
 
+int device_setup_preload(int device, std::string& msg) {
+  const RocApi& api = roc_api();
+  if (!api.ok) {
+    msg = api.err;
+    return LSAMG_EINVAL;
+  }
+  try {
+    Ctx c(device, api);                 // a rocBLAS handle made and released
+  } catch (const SetupDevError& e) {
+    msg = e.msg;
+    return e.code;
+  }
+  return LSAMG_OK;
+}
+
 int device_spd_inverse(int device, int n, const double* A, double* Ainv, std::string& msg) {
   if (n <= 0) return LSAMG_OK;
   if (!A || !Ainv) {
